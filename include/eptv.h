@@ -1,0 +1,187 @@
+/*
+ * eptv.h -- C ABI of the MI355X (gfx950) EPTV fan-beam reconstruction library
+ * (libeptv.so).
+ *
+ * The method is the edge-preserving total-variation (EPTV) reconstruction of
+ * Tian, Jia, Yuan, Pan, Jiang, "GPU-based Low Dose CT Reconstruction via
+ * Edge-preserving Total Variation Regularization":
+ *
+ *   minimise  mu/2 ||P f - y||^2 + sum_e w_e TV_e(f)   subject to f >= 0
+ *
+ * (Sec. 2.1, Eq. 2 and Eq. 4-5), solved by alternating a CGLS data step (P1,
+ * App. I) and a gradient-descent EPTV step with Armijo line search (P2,
+ * Sec. 2.2 Eq. 8-10 and App. II Eq. A2-A3), followed by positivity.
+ *
+ * Conventions shared by every call
+ *   image     float32 [ny][nx], x fastest.  Pixel (i, j) is the square of side
+ *             pixel_mm centred at ((i + 1/2 - nx/2) d, (j + 1/2 - ny/2) d);
+ *             pixels are half-open, so a ray lying exactly on a grid line
+ *             belongs to the pixel above / to the right of it.
+ *   sinogram  float32 [n_views][n_bins], bin fastest.  View v has angle
+ *             theta_v (default 2 pi v / n_views); its source sits at
+ *             -sad_mm (cos theta_v, sin theta_v); bin b is the ray leaving the
+ *             source along theta_v + beta_b, beta_b = (b - (n_bins-1)/2 +
+ *             bin_offset) dbeta_rad (equiangular arc detector, Sec. 3).
+ *   edges     x-edge magnitudes/weights [ny][nx+1]: entry [j][i+1] is the
+ *             half-edge (i+1/2, j), i = -1..nx-1; y-edges [ny+1][nx]: entry
+ *             [j+1][i] is (i, j+1/2), j = -1..ny-1.  Values outside the image
+ *             are zero (the zero boundary condition of App. II).
+ *   memory    every array argument is a device pointer on the current HIP
+ *             device, owned by the caller, contiguous, 4-byte aligned (ws:
+ *             256-byte aligned).  Structs and stats arrays are host memory.
+ *   streams   `stream` is a hipStream_t (NULL = the default stream).  Every
+ *             call only enqueues work on it and returns, except where a call
+ *             says it synchronises.
+ *   errors    every call returns an eptv_status; no call throws or aborts.
+ *             Argument checks happen before anything is enqueued.
+ */
+#ifndef EPTV_H
+#define EPTV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    EPTV_OK = 0,
+    EPTV_ERR_ARG = 1,       /* null pointer, non-positive size, bad parameter */
+    EPTV_ERR_GEOMETRY = 2,  /* source inside the image circle, dbeta <= 0 ... */
+    EPTV_ERR_WORKSPACE = 3, /* workspace missing or smaller than required */
+    EPTV_ERR_HIP = 4,       /* a HIP runtime call failed */
+    EPTV_ERR_NONFINITE = 5  /* reserved */
+} eptv_status;
+
+/* Scanner geometry (Sec. 3; App. III Eq. A6).  view_angles_rad is a host array
+ * of n_views angles, or NULL for equally spaced views over a full turn.  The
+ * source must lie outside the circle through the image corners. */
+typedef struct {
+    int nx, ny;
+    double pixel_mm;
+    int n_views;
+    const double* view_angles_rad;
+    int n_bins;
+    double dbeta_rad;
+    double bin_offset;
+    double sad_mm, sdd_mm;
+} eptv_geometry;
+
+/* Solver parameters.  The paper fixes none of the counts or step constants;
+ * each field names the passage it parameterises. */
+typedef struct {
+    int outer_iters;     /* K, outer iterations of the EPTV algorithm (Sec. 2.2) */
+    int cgls_iters;      /* M, CGLS steps per P1 (App. I); 0 = gradient form of Eq. 8 */
+    int tv_iters;        /* gradient-descent steps per P2 (Sec. 2.2) */
+    int zero_init;       /* 1: f^(0) = 0 as in the algorithm; 0: f is a warm start */
+    double mu;           /* data weight of Eq. 2 (used by the gradient form of P1) */
+    double lambda;       /* splitting weight of Eq. 7-9 */
+    double edge_quantile;/* sigma = this quantile of the half-edge magnitudes (Sec. 2.1) */
+    double sigma_fixed;  /* < 0: adaptive sigma; otherwise used as is (+inf = plain TV) */
+    double sigma_floor;  /* lower bound on the adaptive sigma */
+    double tv_eps;       /* eps added under the root of Eq. A3 (mm^-1) */
+    double armijo_c;     /* sufficient-decrease constant of the Armijo rule */
+    double armijo_shrink;/* backtracking factor */
+    double armijo_t0;    /* first trial step; <= 0 means 1/lambda */
+    int armijo_max_backtracks;
+    int p2_start;        /* 0: P2 starts at v (P1's output); 1: at f^(k) */
+    int positivity;      /* 1: step 3 of the algorithm (f = max(f, 0)) */
+} eptv_params;
+
+/* Optional per-iteration records, host arrays filled when a call that takes
+ * stats returns (that call synchronises its stream).  Any pointer may be NULL. */
+typedef struct {
+    float* sigma;        /* [K]   sigma used by each P2 */
+    int32_t* armijo_k;   /* [K*T] accepted backtrack index per GD step, -1 = none */
+    int32_t* cgls_steps; /* [K]   CGLS steps actually run (breakdown stops early) */
+    double* cgls_resid;  /* [K]   ||y - P v||^2 at the end of each CGLS P1 */
+    double* rmse;        /* [K]   root-mean-square difference to f_ref, if given */
+} eptv_stats;
+
+typedef struct eptv_plan_s* eptv_plan;
+
+/* Precompute the per-ray and per-view tables of a geometry on the current
+ * device.  Allocates device memory; the plan owns it until eptv_plan_destroy.
+ * A plan is immutable after creation and may be shared by several streams. */
+int eptv_plan_create(const eptv_geometry* geom, eptv_plan* out);
+int eptv_plan_destroy(eptv_plan plan);
+
+/* Number of (ray, pixel) pairs with a positive intersection length, counted
+ * on the host in double precision: the nonzeros of P (Sec. 2.1, Eq. 1). */
+int eptv_plan_nnz(eptv_plan plan, long long* nnz);
+
+/* Workspace bytes for the calls below (device memory the caller allocates and
+ * passes as ws / ws_bytes; a smaller ws_bytes is EPTV_ERR_WORKSPACE).
+ * params == NULL gives the size needed by eptv_project / eptv_backproject /
+ * eptv_tv_gradient / eptv_select_sigma and by eptv_tv_step with up to 4096
+ * steps; eptv_reconstruct needs the size for its params (the per-iteration
+ * records grow with outer_iters * tv_iters).  Calls that run concurrently need
+ * separate workspaces; the contents need no initialisation. */
+int eptv_workspace_bytes(eptv_plan plan, const eptv_params* params, size_t* bytes);
+
+/* q = alpha P x + beta q (Sec. 2.1 Eq. 1): p_ij is the exact length of ray i
+ * inside pixel j.  x [ny][nx], q [n_views][n_bins]; beta == 0 never reads q.
+ * ws: workspace of eptv_workspace_bytes(plan, NULL). */
+int eptv_project(eptv_plan plan, const float* x, float* q, float alpha, float beta,
+                 void* ws, size_t ws_bytes, void* stream);
+
+/* eptv_project for callers that keep the image in both layouts: xT is the
+ * same image stored transposed, [nx][ny] (y fastest).  Rays closer to the x
+ * axis read xT, the others read x, so every wave reads contiguous memory.
+ * Needs no workspace; launches the projector kernel only. */
+int eptv_project_dual(eptv_plan plan, const float* x, const float* xT, float* q, float alpha, float beta,
+                      void* stream);
+
+/* z = alpha P^T r + beta z with P^T the exact transpose of eptv_project's P
+ * (Sec. 2.2, below Eq. 6), computed pixel by pixel (Sec. 2.3) without atomics.
+ * r [n_views][n_bins], z [ny][nx]; beta == 0 never reads z. */
+int eptv_backproject(eptv_plan plan, const float* r, float* z, float alpha, float beta,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* The P2 descent direction g = lambda (f - v) + (A2 variation of the EPTV
+ * term) (Eq. 9-10, App. II Eq. A2) with the half-edge magnitudes and weights
+ * w = exp(-TV^2 / sigma^2) of Eq. A3 / Eq. 5 taken at f.  sigma may be +inf
+ * (w = 1).  wx [ny][nx+1] and wy [ny+1][nx] receive the weights (may be NULL). */
+int eptv_tv_gradient(eptv_plan plan, const float* f, const float* v, float lambda, float sigma,
+                     float tv_eps, float* g, float* wx, float* wy, void* ws, size_t ws_bytes,
+                     void* stream);
+
+/* sigma = max(order statistic of rank ceil(q n) - 1 (0-based, ascending) of
+ * the n = ny(nx+1) + (ny+1)nx half-edge magnitudes of f, sigma_floor)
+ * (Sec. 2.1: sigma set from the gradient-magnitude histogram).  Exact
+ * selection on the float32 magnitudes.  Writes one float to the device
+ * pointer sigma_out. */
+int eptv_select_sigma(eptv_plan plan, const float* f, double q, float tv_eps, float sigma_floor,
+                      float* sigma_out, void* ws, size_t ws_bytes, void* stream);
+
+/* n_steps gradient-descent steps of P2 (Eq. 8) from f towards v, in place:
+ * the weights are recomputed at each step and held fixed inside an Armijo
+ * backtracking search t = t0 shrink^k, k = 0..max_backtracks, for the first
+ * t with Q(f - t g) <= Q(f) - c t ||g||^2, Q(h) = lambda/2 ||h - v||^2 +
+ * sum_e w_e TV_e(h); without such t the step is skipped.  sigma < 0 selects
+ * sigma from f as eptv_select_sigma does (params->edge_quantile,
+ * params->sigma_floor).  No positivity.  stats->sigma[0] and
+ * stats->armijo_k[0..n_steps-1] are filled when given (synchronises). */
+int eptv_tv_step(eptv_plan plan, const eptv_params* params, float* f, const float* v, float sigma,
+                 int n_steps, void* ws, size_t ws_bytes, eptv_stats* stats, void* stream);
+
+/* The EPTV algorithm (Sec. 2.2): from f^(0) = 0 (or the warm start in f),
+ * params->outer_iters times: P1 by CGLS started at f^(k) (App. I), sigma
+ * from the P2 start image, P2 by eptv_tv_step's descent, positivity; f holds
+ * f^(K) on return.  y [n_views][n_bins] are the log-transformed data.
+ * f_ref (may be NULL) is an image the per-iteration RMSE is measured
+ * against.  One outer iteration is captured once as a HIP graph and replayed
+ * (set EPTV_NO_GRAPH=1 in the environment to launch kernels directly). */
+int eptv_reconstruct(eptv_plan plan, const eptv_params* params, const float* y, float* f,
+                     const float* f_ref, void* ws, size_t ws_bytes, eptv_stats* stats, void* stream);
+
+const char* eptv_status_string(int status);
+
+/* Last HIP error text seen by the library on this thread ("" if none). */
+const char* eptv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

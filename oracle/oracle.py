@@ -64,11 +64,11 @@ class Params:
     tv_iters: int = 5
     zero_init: int = 1
     mu: float = 1.0
-    lam: float = 100.0
+    lam: float = 1000.0
     edge_quantile: float = 0.90
     sigma_fixed: float = -1.0
     sigma_floor: float = 1e-12
-    tv_eps: float = 1e-6
+    tv_eps: float = 1e-4
     armijo_c: float = 1e-4
     armijo_shrink: float = 0.5
     armijo_t0: float = 0.0

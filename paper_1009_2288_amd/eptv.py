@@ -1,0 +1,305 @@
+"""Python binding of ``libeptv.so`` (the C ABI declared in ``include/eptv.h``).
+
+Argument marshalling only: tensors are checked (float32, contiguous, on the
+plan's GPU, right shape) and their device pointers passed to the library; every
+step of the computation runs in the library's HIP kernels.  PyTorch provides
+device memory and streams.  There is no fallback: if the library is not built
+or no GPU is present the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from dataclasses import dataclass, asdict
+from typing import Optional
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libeptv.so")
+
+EPTV_OK, EPTV_ERR_ARG, EPTV_ERR_GEOMETRY, EPTV_ERR_WORKSPACE, EPTV_ERR_HIP, EPTV_ERR_NONFINITE = range(6)
+
+SYMBOLS = ["eptv_plan_create", "eptv_plan_destroy", "eptv_plan_nnz", "eptv_workspace_bytes", "eptv_project",
+           "eptv_project_dual", "eptv_backproject", "eptv_tv_gradient", "eptv_select_sigma", "eptv_tv_step", "eptv_reconstruct",
+           "eptv_status_string", "eptv_last_error"]
+
+
+class EptvError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = f"{where}: {_lib().eptv_status_string(status).decode()}"
+        extra = _lib().eptv_last_error().decode()
+        if status == EPTV_ERR_HIP and extra:
+            msg += f" ({extra})"
+        super().__init__(msg)
+
+
+class _Geometry(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("pixel_mm", C.c_double), ("n_views", C.c_int),
+                ("view_angles_rad", C.POINTER(C.c_double)), ("n_bins", C.c_int), ("dbeta_rad", C.c_double),
+                ("bin_offset", C.c_double), ("sad_mm", C.c_double), ("sdd_mm", C.c_double)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("outer_iters", C.c_int), ("cgls_iters", C.c_int), ("tv_iters", C.c_int), ("zero_init", C.c_int),
+                ("mu", C.c_double), ("lambda_", C.c_double), ("edge_quantile", C.c_double),
+                ("sigma_fixed", C.c_double), ("sigma_floor", C.c_double), ("tv_eps", C.c_double),
+                ("armijo_c", C.c_double), ("armijo_shrink", C.c_double), ("armijo_t0", C.c_double),
+                ("armijo_max_backtracks", C.c_int), ("p2_start", C.c_int), ("positivity", C.c_int)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("sigma", C.POINTER(C.c_float)), ("armijo_k", C.POINTER(C.c_int32)),
+                ("cgls_steps", C.POINTER(C.c_int32)), ("cgls_resid", C.POINTER(C.c_double)),
+                ("rmse", C.POINTER(C.c_double))]
+
+
+@dataclass
+class Params:
+    """Solver parameters (the fields of ``eptv_params``)."""
+
+    outer_iters: int = 100
+    cgls_iters: int = 3
+    tv_iters: int = 5
+    zero_init: int = 1
+    mu: float = 1.0
+    lam: float = 1000.0
+    edge_quantile: float = 0.90
+    sigma_fixed: float = -1.0
+    sigma_floor: float = 1e-12
+    tv_eps: float = 1e-4
+    armijo_c: float = 1e-4
+    armijo_shrink: float = 0.5
+    armijo_t0: float = 0.0
+    armijo_max_backtracks: int = 20
+    p2_start: int = 0
+    positivity: int = 1
+
+    def _c(self) -> _Params:
+        d = asdict(self)
+        d["lambda_"] = d.pop("lam")
+        return _Params(**d)
+
+
+_L = None
+
+
+def _lib() -> C.CDLL:
+    global _L
+    if _L is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1009_2288_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, sz = C.c_void_p, C.c_size_t
+        L.eptv_plan_create.argtypes = [C.POINTER(_Geometry), C.POINTER(vp)]
+        L.eptv_plan_destroy.argtypes = [vp]
+        L.eptv_plan_nnz.argtypes = [vp, C.POINTER(C.c_longlong)]
+        L.eptv_workspace_bytes.argtypes = [vp, C.POINTER(_Params), C.POINTER(sz)]
+        L.eptv_project.argtypes = [vp, vp, vp, C.c_float, C.c_float, vp, sz, vp]
+        L.eptv_project_dual.argtypes = [vp, vp, vp, vp, C.c_float, C.c_float, vp]
+        L.eptv_backproject.argtypes = [vp, vp, vp, C.c_float, C.c_float, vp, sz, vp]
+        L.eptv_tv_gradient.argtypes = [vp, vp, vp, C.c_float, C.c_float, C.c_float, vp, vp, vp, vp, sz, vp]
+        L.eptv_select_sigma.argtypes = [vp, vp, C.c_double, C.c_float, C.c_float, vp, vp, sz, vp]
+        L.eptv_tv_step.argtypes = [vp, C.POINTER(_Params), vp, vp, C.c_float, C.c_int, vp, sz, C.POINTER(_Stats), vp]
+        L.eptv_reconstruct.argtypes = [vp, C.POINTER(_Params), vp, vp, vp, vp, sz, C.POINTER(_Stats), vp]
+        L.eptv_status_string.argtypes = [C.c_int]
+        L.eptv_status_string.restype = C.c_char_p
+        L.eptv_last_error.restype = C.c_char_p
+        _L = L
+    return _L
+
+
+def library() -> C.CDLL:
+    """The loaded ``libeptv.so`` (raises if it is not built)."""
+    return _lib()
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != EPTV_OK:
+        raise EptvError(rc, where)
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+class Plan:
+    """Geometry tables of one scanner geometry on one GPU (``eptv_plan``)."""
+
+    def __init__(self, geom, device: Optional[torch.device] = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libeptv needs a ROCm GPU; none is visible")
+        self.device = torch.device(device if device is not None else "cuda", )
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.nx, self.ny = int(geom.nx), int(geom.ny)
+        self.n_views, self.n_bins = int(geom.n_views), int(geom.n_bins)
+        ang = getattr(geom, "view_angles_rad", None)
+        self._ang = None
+        ptr = None
+        if ang is not None:
+            import numpy as np
+            self._ang = np.ascontiguousarray(np.asarray(ang, dtype=np.float64))
+            ptr = self._ang.ctypes.data_as(C.POINTER(C.c_double))
+        g = _Geometry(self.nx, self.ny, float(geom.pixel_mm), self.n_views, ptr, self.n_bins,
+                      float(geom.dbeta_rad), float(getattr(geom, "bin_offset", 0.0)), float(geom.sad_mm),
+                      float(geom.sdd_mm))
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(_lib().eptv_plan_create(C.byref(g), C.byref(h)), "eptv_plan_create")
+        self._h = h
+        self._ws = None
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _L is not None:
+            _L.eptv_plan_destroy(h)
+            self._h = None
+
+    # ------------------------------------------------------------- helpers
+    @property
+    def nnz(self) -> int:
+        n = C.c_longlong()
+        _check(_lib().eptv_plan_nnz(self._h, C.byref(n)), "eptv_plan_nnz")
+        return int(n.value)
+
+    def workspace_bytes(self, params: Optional[Params] = None) -> int:
+        n = C.c_size_t()
+        cp = params._c() if params is not None else None
+        _check(_lib().eptv_workspace_bytes(self._h, C.byref(cp) if cp is not None else None, C.byref(n)),
+               "eptv_workspace_bytes")
+        return int(n.value)
+
+    def workspace(self, params: Optional[Params] = None) -> torch.Tensor:
+        need = self.workspace_bytes(params)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def _img(self, t: torch.Tensor, name: str) -> torch.Tensor:
+        return self._t(t, (self.ny, self.nx), name)
+
+    def _sino(self, t: torch.Tensor, name: str) -> torch.Tensor:
+        return self._t(t, (self.n_views, self.n_bins), name)
+
+    def _t(self, t: torch.Tensor, shape, name: str) -> torch.Tensor:
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or t.device != self.device:
+            raise TypeError(f"{name} must be a float32 tensor on {self.device}")
+        if tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous with shape {tuple(shape)}, got {tuple(t.shape)}")
+        return t
+
+    def new_image(self) -> torch.Tensor:
+        return torch.empty((self.ny, self.nx), dtype=torch.float32, device=self.device)
+
+    def new_sinogram(self) -> torch.Tensor:
+        return torch.empty((self.n_views, self.n_bins), dtype=torch.float32, device=self.device)
+
+    # ------------------------------------------------------------- the calls
+    def project(self, x: torch.Tensor, out: Optional[torch.Tensor] = None, alpha: float = 1.0, beta: float = 0.0,
+                stream=None) -> torch.Tensor:
+        """out = alpha P x + beta out."""
+        x = self._img(x, "x")
+        out = self._sino(out if out is not None else self.new_sinogram(), "out")
+        ws = self.workspace()
+        _check(_lib().eptv_project(self._h, x.data_ptr(), out.data_ptr(), alpha, beta, ws.data_ptr(), ws.numel(),
+                                   _stream(stream)), "eptv_project")
+        return out
+
+    def project_dual(self, x: torch.Tensor, xT: torch.Tensor, out: Optional[torch.Tensor] = None,
+                     alpha: float = 1.0, beta: float = 0.0, stream=None) -> torch.Tensor:
+        """out = alpha P x + beta out, with xT the same image transposed ([nx][ny])."""
+        x = self._img(x, "x")
+        xT = self._t(xT, (self.nx, self.ny), "xT")
+        out = self._sino(out if out is not None else self.new_sinogram(), "out")
+        _check(_lib().eptv_project_dual(self._h, x.data_ptr(), xT.data_ptr(), out.data_ptr(), alpha, beta,
+                                        _stream(stream)), "eptv_project_dual")
+        return out
+
+    def backproject(self, r: torch.Tensor, out: Optional[torch.Tensor] = None, alpha: float = 1.0,
+                    beta: float = 0.0, stream=None) -> torch.Tensor:
+        """out = alpha P^T r + beta out."""
+        r = self._sino(r, "r")
+        out = self._img(out if out is not None else self.new_image(), "out")
+        ws = self.workspace()
+        _check(_lib().eptv_backproject(self._h, r.data_ptr(), out.data_ptr(), alpha, beta, ws.data_ptr(),
+                                       ws.numel(), _stream(stream)), "eptv_backproject")
+        return out
+
+    def tv_gradient(self, f: torch.Tensor, v: torch.Tensor, lam: float, sigma: float, tv_eps: float,
+                    with_weights: bool = True, stream=None):
+        """(g, wx, wy): the P2 direction and the half-edge weights at f."""
+        f, v = self._img(f, "f"), self._img(v, "v")
+        g = self.new_image()
+        wx = torch.empty((self.ny, self.nx + 1), dtype=torch.float32, device=self.device) if with_weights else None
+        wy = torch.empty((self.ny + 1, self.nx), dtype=torch.float32, device=self.device) if with_weights else None
+        ws = self.workspace()
+        _check(_lib().eptv_tv_gradient(self._h, f.data_ptr(), v.data_ptr(), lam, sigma, tv_eps, g.data_ptr(),
+                                       wx.data_ptr() if wx is not None else None,
+                                       wy.data_ptr() if wy is not None else None, ws.data_ptr(), ws.numel(),
+                                       _stream(stream)), "eptv_tv_gradient")
+        return g, wx, wy
+
+    def select_sigma(self, f: torch.Tensor, q: float, tv_eps: float, sigma_floor: float = 1e-12,
+                     stream=None) -> torch.Tensor:
+        """Device scalar (1-element tensor) holding sigma."""
+        f = self._img(f, "f")
+        out = torch.empty(1, dtype=torch.float32, device=self.device)
+        ws = self.workspace()
+        _check(_lib().eptv_select_sigma(self._h, f.data_ptr(), q, tv_eps, sigma_floor, out.data_ptr(),
+                                        ws.data_ptr(), ws.numel(), _stream(stream)), "eptv_select_sigma")
+        return out
+
+    def tv_step(self, f: torch.Tensor, v: torch.Tensor, params: Params, n_steps: int, sigma: float = -1.0,
+                stats: bool = True, stream=None):
+        """In-place P2 descent steps on f; returns (armijo_k per step, sigma) when stats."""
+        import numpy as np
+        f, v = self._img(f, "f"), self._img(v, "v")
+        ws = self.workspace()
+        ks = np.zeros(max(n_steps, 1), np.int32)
+        sg = np.zeros(1, np.float32)
+        st = _Stats(sg.ctypes.data_as(C.POINTER(C.c_float)), ks.ctypes.data_as(C.POINTER(C.c_int32)), None, None,
+                    None)
+        cp = params._c()
+        _check(_lib().eptv_tv_step(self._h, C.byref(cp), f.data_ptr(), v.data_ptr(), sigma, n_steps, ws.data_ptr(),
+                                   ws.numel(), C.byref(st) if stats else None, _stream(stream)), "eptv_tv_step")
+        return (ks[:n_steps].copy(), float(sg[0])) if stats else None
+
+    def reconstruct(self, y: torch.Tensor, params: Params, f: Optional[torch.Tensor] = None,
+                    f_ref: Optional[torch.Tensor] = None, stats: bool = True, stream=None):
+        """Run params.outer_iters EPTV iterations; returns (f, stats dict or None)."""
+        import numpy as np
+        y = self._sino(y, "y")
+        if f is None:
+            f = torch.zeros((self.ny, self.nx), dtype=torch.float32, device=self.device)
+        f = self._img(f, "f")
+        if f_ref is not None:
+            f_ref = self._img(f_ref, "f_ref")
+        ws = self.workspace(params)
+        K, T = params.outer_iters, params.tv_iters
+        rec = None
+        stp = None
+        if stats:
+            rec = {"sigma": np.zeros(max(K, 1), np.float32), "armijo_k": np.zeros(max(K * T, 1), np.int32),
+                   "cgls_steps": np.zeros(max(K, 1), np.int32), "cgls_resid": np.zeros(max(K, 1)),
+                   "rmse": np.zeros(max(K, 1))}
+            st = _Stats(rec["sigma"].ctypes.data_as(C.POINTER(C.c_float)),
+                        rec["armijo_k"].ctypes.data_as(C.POINTER(C.c_int32)),
+                        rec["cgls_steps"].ctypes.data_as(C.POINTER(C.c_int32)),
+                        rec["cgls_resid"].ctypes.data_as(C.POINTER(C.c_double)),
+                        rec["rmse"].ctypes.data_as(C.POINTER(C.c_double)))
+            stp = C.byref(st)
+        cp = params._c()
+        _check(_lib().eptv_reconstruct(self._h, C.byref(cp), y.data_ptr(), f.data_ptr(),
+                                       f_ref.data_ptr() if f_ref is not None else None, ws.data_ptr(), ws.numel(),
+                                       stp, _stream(stream)), "eptv_reconstruct")
+        if rec is not None:
+            rec = {k: v[:K].copy() for k, v in rec.items() if k != "armijo_k"} | {
+                "armijo_k": rec["armijo_k"][:K * T].reshape(K, T).copy()}
+            if f_ref is None:
+                rec.pop("rmse")
+        return f, rec

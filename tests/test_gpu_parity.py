@@ -1,0 +1,334 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Both sides receive identical float32-representable inputs (the oracle widens
+them to float64).  Per-call bar: relative L2 <= 1e-5 for P, P^T, the P2
+direction and the edge weights, and for sigma; after a fixed number of outer
+iterations: relative L2 <= 1e-4 on the image.  Inputs are seeded synthetic
+phantoms and random arrays of the two workload shapes plus ragged shapes.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1009_2288_amd import synth
+from paper_1009_2288_amd.synth import Geometry, fan_dbeta
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(autouse=True)
+def announce(request):
+    sys.__stderr__.write(f"\n[gpu-case] {request.node.nodeid}\n")
+    sys.__stderr__.flush()
+    yield
+
+
+@pytest.fixture(scope="module")
+def E():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm GPU")
+    from paper_1009_2288_amd import eptv
+    eptv.library()
+    return eptv
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def ragged_geom():
+    return Geometry(77, 53, 1.1, 13, 101, fan_dbeta(77, 53, 1.1, 150.0, 101) * 1.05, 150.0, 300.0, 0.3)
+
+
+def odd_geom():
+    # odd bin count (a ray through the isocentre), odd image, views not a multiple of 4
+    return Geometry(65, 65, 1.0, 7, 129, fan_dbeta(65, 65, 1.0, 120.0, 129), 120.0, 240.0)
+
+
+GEOMS = {
+    "small": synth.geometry_small,
+    "paper": synth.geometry_paper,
+    "ragged": ragged_geom,
+    "odd": odd_geom,
+}
+
+_mat_cache = {}
+
+
+def matrix(oracle, name):
+    if name not in _mat_cache:
+        _mat_cache[name] = oracle.Matrix(GEOMS[name]())
+    return _mat_cache[name]
+
+
+_plan_cache = {}
+
+
+def plan(E, name):
+    if name not in _plan_cache:
+        _plan_cache[name] = E.Plan(GEOMS[name]())
+    return _plan_cache[name]
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+# ------------------------------------------------------------------ P and P^T
+
+@pytest.mark.parametrize("name", list(GEOMS))
+def test_project_parity(E, oracle, name):
+    g = GEOMS[name]()
+    M, P = matrix(oracle, name), plan(E, name)
+    for seed, img in ((0, synth.random_image(g.nx, g.ny, 1)),
+                      (1, synth.raster(synth.phantom_small(3) if g.nx <= 128 else synth.phantom_paper(3), g.nx, g.ny,
+                                       g.pixel_mm).astype(np.float32))):
+        q = P.project(dev(img)).cpu().numpy()
+        assert rel(q, M.project(img)) <= 1e-5, (name, seed)
+    # the same kernel fed both layouts by the caller gives the same bits
+    img = synth.random_image(g.nx, g.ny, 1)
+    qa = P.project(dev(img))
+    qb = P.project_dual(dev(img), dev(img.T.copy()))
+    assert torch.equal(qa, qb)
+    # q = alpha P x + beta q
+    x = synth.random_image(g.nx, g.ny, 5)
+    q0 = synth.random_sinogram(g.n_views, g.n_bins, 6)
+    out = dev(q0)
+    P.project(dev(x), out, alpha=-0.5, beta=2.0)
+    assert rel(out.cpu().numpy(), -0.5 * M.project(x) + 2.0 * q0) <= 1e-5
+
+
+@pytest.mark.parametrize("name", list(GEOMS))
+def test_backproject_parity(E, oracle, name):
+    g = GEOMS[name]()
+    M, P = matrix(oracle, name), plan(E, name)
+    r = synth.random_sinogram(g.n_views, g.n_bins, 2)
+    z = P.backproject(dev(r)).cpu().numpy()
+    assert rel(z, M.backproject(r)) <= 1e-5
+    r2 = M.project(synth.random_image(g.nx, g.ny, 3)).astype(np.float32)
+    z2 = P.backproject(dev(r2)).cpu().numpy()
+    assert rel(z2, M.backproject(r2)) <= 1e-5
+    z0 = synth.random_image(g.nx, g.ny, 4)
+    out = dev(z0)
+    P.backproject(dev(r), out, alpha=0.25, beta=-1.0)
+    assert rel(out.cpu().numpy(), 0.25 * M.backproject(r) - z0) <= 1e-5
+
+
+@pytest.mark.parametrize("name", list(GEOMS))
+def test_float32_adjoint(E, name):
+    """<P x, r> = <x, P^T r> for the float32 operators: they are exact transposes,
+    so the two sides differ only by float32 summation."""
+    g = GEOMS[name]()
+    P = plan(E, name)
+    rng = np.random.default_rng(7)
+    x = rng.normal(size=(g.ny, g.nx)).astype(np.float32)
+    r = rng.normal(size=(g.n_views, g.n_bins)).astype(np.float32)
+    px = P.project(dev(x)).cpu().numpy().astype(np.float64)
+    ptr = P.backproject(dev(r)).cpu().numpy().astype(np.float64)
+    a, b = np.vdot(px, r), np.vdot(x, ptr)
+    scale = np.linalg.norm(px) * np.linalg.norm(r)
+    assert abs(a - b) <= 1e-6 * scale
+
+
+@pytest.mark.parametrize("name", list(GEOMS))
+def test_nnz_matches_oracle(E, oracle, name):
+    M, P = matrix(oracle, name), plan(E, name)
+    assert abs(P.nnz - M.nnz) <= 1e-4 * M.nnz
+
+
+def test_ray_on_grid_line(E, oracle):
+    """theta = 0 exactly, odd bin count, even image: the central ray lies on a grid
+    line and goes wholly to the row above it on both sides."""
+    g = Geometry(16, 16, 1.0, 1, 9, fan_dbeta(16, 16, 1.0, 60.0, 9), 60.0, 120.0, 0.0, np.array([0.0]))
+    M, P = oracle.Matrix(g), E.Plan(g)
+    x = synth.random_image(16, 16, 11)
+    assert rel(P.project(dev(x)).cpu().numpy(), M.project(x)) <= 1e-6
+    r = synth.random_sinogram(1, 9, 12)
+    assert rel(P.backproject(dev(r)).cpu().numpy(), M.backproject(r)) <= 1e-6
+
+
+# ------------------------------------------------------------------ TV terms and sigma
+
+@pytest.mark.parametrize("name", ["small", "paper", "ragged"])
+def test_tv_gradient_and_weights_parity(E, oracle, name):
+    g = GEOMS[name]()
+    P = plan(E, name)
+    f = synth.random_image(g.nx, g.ny, 21, 0.0, 0.03)
+    v = synth.random_image(g.nx, g.ny, 22, 0.0, 0.03)
+    for sigma in (0.004, 0.02, float("inf")):
+        gg, wx, wy = P.tv_gradient(dev(f), dev(v), 1000.0, sigma, 1e-6)
+        go, wxo, wyo = oracle.tv_gradient(f, v, 1000.0, sigma, 1e-6)
+        assert rel(gg.cpu().numpy(), go) <= 1e-5, sigma
+        assert rel(wx.cpu().numpy(), wxo) <= 1e-5
+        assert rel(wy.cpu().numpy(), wyo) <= 1e-5
+
+
+@pytest.mark.parametrize("name", ["small", "paper", "ragged"])
+def test_select_sigma_parity(E, oracle, name):
+    g = GEOMS[name]()
+    P = plan(E, name)
+    f = synth.raster(synth.phantom_small(4), g.nx, g.ny, g.pixel_mm).astype(np.float32)
+    f += synth.random_image(g.nx, g.ny, 23, -0.002, 0.002)
+    for q in (0.9, 0.95, 0.05, 1.0, 1e-9):
+        s = float(P.select_sigma(dev(f), q, 1e-6).cpu()[0])
+        so = oracle.select_sigma(f, 1e-6, q, 1e-12)
+        assert abs(s - so) <= 1e-5 * so, q
+
+
+def test_select_sigma_exact_on_rectangle(E):
+    """A 3 x 5 rectangle (height 1/64, exact in float32, eps = 0) has a known
+    multiset of half-edge magnitudes; every order statistic is exact."""
+    g = Geometry(16, 16, 1.0, 4, 32, fan_dbeta(16, 16, 1.0, 60.0, 32), 60.0, 120.0)
+    P = E.Plan(g)
+    h = 1.0 / 64
+    f = np.zeros((16, 16), np.float32)
+    f[4:9, 3:6] = h
+    r2 = math.sqrt(2.0)
+    vals = [h] * (2 * 1 + 2 * 3) + [3 * h / (2 * r2)] * 8 + [h / r2] * (4 * 2 + 4 * 4) + [h / (2 * r2)] * 8
+    allv = np.sort(np.array(vals + [0.0] * (2 * 16 * 17 - len(vals))))
+    for q in (0.95, 0.97, 0.99, 1.0):
+        s = float(P.select_sigma(dev(f), q, 0.0, 1e-30).cpu()[0])
+        want = allv[math.ceil(q * allv.size) - 1]
+        assert abs(s - want) <= 2e-7 * want, q
+
+
+def test_tv_step_parity(E, oracle):
+    g = GEOMS["small"]()
+    P = plan(E, "small")
+    c = synth.make_case("small", 0)
+    v = c.phantom.astype(np.float32) + synth.random_image(g.nx, g.ny, 31, -0.003, 0.003)
+    for sigma in (-1.0, 0.005, float("inf")):
+        prm = E.Params(lam=1000.0)
+        f = dev(v)
+        ks, sg = P.tv_step(f, dev(v), prm, 6, sigma)
+        op = oracle.Params(lam=1000.0)
+        fo, ko, mo, so = oracle.tv_step(v, v, op, 6, sigma)
+        assert list(ks) == list(ko), (sigma, ks, ko, mo)
+        assert rel(f.cpu().numpy(), fo) <= 1e-5
+        if sigma < 0:
+            assert abs(sg - so) <= 1e-5 * so
+
+
+# ------------------------------------------------------------------ the whole iteration
+
+def oracle_params(oracle, K, **kw):
+    return oracle.Params(outer_iters=K, lam=kw.pop("lam", 1000.0), **kw)
+
+
+def run_pair(E, oracle, name, case, K, **kw):
+    P = plan(E, name)
+    M = matrix(oracle, name)
+    y = case.y.astype(np.float32)
+    fo, so = M.reconstruct(y, oracle_params(oracle, K, **kw), f_ref=case.phantom)
+    prm = E.Params(outer_iters=K, lam=kw.pop("lam", 1000.0), **kw)
+    f, sg = P.reconstruct(dev(y), prm, f_ref=dev(case.phantom))
+    return f.cpu().numpy(), sg, fo, so
+
+
+def well_separated(so, tol=1e-5):
+    """The oracle's own Armijo decisions are far from ties (relative margin >
+    tol), so float32 arithmetic cannot flip them; parity of the whole
+    trajectory is then expected to the 1e-4 bar."""
+    return float(so["armijo_margin"].min()) > tol
+
+
+def test_reconstruct_small_case(E, oracle):
+    """128^2 / 30 views / 256 bins, 50 outer iterations (M = 3, T = 5)."""
+    c = synth.make_case("small", 0)
+    f, sg, fo, so = run_pair(E, oracle, "small", c, 50)
+    assert well_separated(so)
+    assert np.array_equal(sg["cgls_steps"], so["cgls_steps"])
+    np.testing.assert_allclose(sg["sigma"], so["sigma"], rtol=1e-4)
+    assert (sg["armijo_k"] == so["armijo_k"]).mean() >= 0.99, (sg["armijo_k"], so["armijo_k"])
+    assert rel(f, fo) <= 1e-4
+    np.testing.assert_allclose(sg["rmse"], so["rmse"], rtol=1e-4)
+    np.testing.assert_allclose(sg["cgls_resid"], so["cgls_resid"], rtol=1e-4)
+
+
+def test_reconstruct_paper_case_20_iterations(E, oracle):
+    """512^2 / 40 views / 736 bins at the full size, 20 outer iterations."""
+    c = synth.make_case("paper", 0)
+    f, sg, fo, so = run_pair(E, oracle, "paper", c, 20)
+    assert well_separated(so)
+    assert np.array_equal(sg["armijo_k"], so["armijo_k"])
+    assert rel(f, fo) <= 1e-4
+    np.testing.assert_allclose(sg["sigma"], so["sigma"], rtol=1e-4)
+
+
+@pytest.mark.parametrize("kw", [dict(cgls_iters=0, mu=1.0, lam=2000.0, p2_start=1),
+                                dict(tv_iters=0), dict(sigma_fixed=float("inf")),
+                                dict(cgls_iters=1, tv_iters=2, edge_quantile=0.5, positivity=0)])
+def test_reconstruct_variants_ragged(E, oracle, kw):
+    g = GEOMS["ragged"]()
+    ell = synth.phantom_small(7)
+    for e in ell:
+        e.cx *= 0.35
+        e.cy *= 0.35
+        e.a *= 0.35
+        e.b *= 0.35
+    p = synth.line_integrals(ell, g)
+    y = synth.noisy_sinogram(p, 2e4, 99)
+    case = synth.Case("ragged", g, ell, synth.raster(ell, g.nx, g.ny, g.pixel_mm), p, y, 2e4, 7)
+    f, sg, fo, so = run_pair(E, oracle, "ragged", case, 8, **dict(kw))
+    assert rel(f, fo) <= 1e-4, kw
+
+
+def test_reconstruct_is_deterministic_and_graph_equals_direct(E, monkeypatch):
+    c = synth.make_case("small", 1)
+    P = plan(E, "small")
+    prm = E.Params(outer_iters=6)
+    y = dev(c.y)
+    f1, _ = P.reconstruct(y, prm, stats=False)
+    f2, _ = P.reconstruct(y, prm, stats=False)
+    monkeypatch.setenv("EPTV_NO_GRAPH", "1")
+    f3, _ = P.reconstruct(y, prm, stats=False)
+    torch.cuda.synchronize()
+    assert torch.equal(f1, f2) and torch.equal(f1, f3)
+
+
+def test_warm_start_split_equals_straight_run(E):
+    """Resume: K1 iterations then K2 more from the result equals K1 + K2 in one call."""
+    c = synth.make_case("small", 2)
+    P = plan(E, "small")
+    y = dev(c.y)
+    fa, _ = P.reconstruct(y, E.Params(outer_iters=7), stats=False)
+    fb, _ = P.reconstruct(y, E.Params(outer_iters=4), stats=False)
+    fb, _ = P.reconstruct(y, E.Params(outer_iters=3, zero_init=0), f=fb, stats=False)
+    torch.cuda.synchronize()
+    assert torch.equal(fa, fb)
+
+
+def test_workspace_and_argument_errors(E):
+    P = plan(E, "small")
+    lib = E.library()
+    x = torch.zeros((128, 128), device="cuda")
+    q = torch.zeros((30, 256), device="cuda")
+    ws = P.workspace()
+    need = P.workspace_bytes()
+    assert lib.eptv_project(P._h, x.data_ptr(), q.data_ptr(), 1.0, 0.0, ws.data_ptr(), need - 1, None) == 3
+    assert lib.eptv_project(P._h, x.data_ptr(), q.data_ptr(), 1.0, 0.0, None, need, None) == 3
+    assert lib.eptv_project(P._h, x.data_ptr(), q.data_ptr(), 1.0, 0.0, ws.data_ptr() + 8, need, None) == 3
+    with pytest.raises(E.EptvError):
+        P.reconstruct(torch.zeros((30, 256), device="cuda"), E.Params(outer_iters=2, cgls_iters=65))
+    with pytest.raises(ValueError):
+        P.project(torch.zeros((64, 128), device="cuda"))
+    with pytest.raises(TypeError):
+        P.project(torch.zeros((128, 128), device="cuda", dtype=torch.float64))
+
+
+def test_zero_iterations_and_empty_steps(E):
+    P = plan(E, "small")
+    c = synth.make_case("small", 0)
+    f0 = dev(c.phantom)
+    f, st = P.reconstruct(dev(c.y), E.Params(outer_iters=0, zero_init=0), f=f0.clone())
+    assert torch.equal(f, f0)
+    f1 = f0.clone()
+    ks, _ = P.tv_step(f1, f0, E.Params(), 0, 0.01)
+    assert len(ks) == 0 and torch.equal(f1, f0)
