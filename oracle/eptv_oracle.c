@@ -21,6 +21,8 @@
 #define ORC_PAR_MIN 16384
 
 struct orc_matrix {
+    orc_geometry g;    /* a copy, view angles included, for the Eq. 11 operator */
+    double* angles;
     int nx, ny;
     int n_rows, n_cols;
     long long nnz;
@@ -137,6 +139,10 @@ int orc_matrix_build(const orc_geometry* g, orc_matrix** out)
         return 1;
     const int nrow = g->n_views * g->n_bins, cap = g->nx + g->ny + 4;
     orc_matrix* m = (orc_matrix*)calloc(1, sizeof(orc_matrix));
+    m->g = *g;
+    m->angles = (double*)malloc(sizeof(double) * (size_t)g->n_views);
+    for (int v = 0; v < g->n_views; ++v) m->angles[v] = view_angle(g, v);
+    m->g.view_angles_rad = m->angles;
     m->nx = g->nx;
     m->ny = g->ny;
     m->n_rows = nrow;
@@ -186,6 +192,7 @@ int orc_matrix_build(const orc_geometry* g, orc_matrix** out)
 void orc_matrix_free(orc_matrix* m)
 {
     if (!m) return;
+    free(m->angles);
     free(m->rowptr);
     free(m->col);
     free(m->val);
@@ -225,6 +232,42 @@ void orc_backproject(const orc_matrix* m, const double* r, double* z)
         double s = 0.0;
         for (long long e = m->colptr[c]; e < m->colptr[c + 1]; ++e) s += m->cval[e] * r[m->row[e]];
         z[c] = s;
+    }
+}
+
+/* Eq. 11 (derived in App. III): the pixel-driven backprojector of the paper's
+ * on-the-fly strategy.  For pixel centre p and view theta, with the source at
+ * S = -SAD (cos theta, sin theta):
+ *   l     = |p - S|, the source-to-pixel distance;
+ *   beta* = the angle of p - S measured from the central ray (counter-clockwise
+ *           positive, the sense in which the bin angles grow);
+ *   y(beta*) = linear interpolation between the two bins whose centre angles
+ *           bracket beta*, a bin beyond the detector reading zero;
+ * and [P^T y](p) = (d^2 / dbeta) * sum over views of y(beta*) / l.  It is a
+ * smooth approximation of the transpose above, not its exact transpose. */
+void orc_backproject_interp(const orc_geometry* g, const double* y, double* z)
+{
+    const double d = g->pixel_mm, scale = d * d / g->dbeta_rad;
+    const int nx = g->nx, ny = g->ny, B = g->n_bins;
+#pragma omp parallel for schedule(static) if (nx * ny > ORC_PAR_MIN)
+    for (int c = 0; c < nx * ny; ++c) {
+        const double px = (c % nx + 0.5 - 0.5 * nx) * d, py = (c / nx + 0.5 - 0.5 * ny) * d;
+        double acc = 0.0;
+        for (int v = 0; v < g->n_views; ++v) {
+            const double th = view_angle(g, v);
+            const double ex = cos(th), ey = sin(th);
+            const double rx = px + g->sad_mm * ex, ry = py + g->sad_mm * ey; /* p - S */
+            const double l = sqrt(rx * rx + ry * ry);
+            const double bstar = atan2(ex * ry - ey * rx, ex * rx + ey * ry);
+            /* fractional bin index: bin b is centred on beta_b of bin_angle() */
+            const double t = bstar / g->dbeta_rad + 0.5 * (B - 1) - g->bin_offset;
+            const double b0 = floor(t), a = t - b0;
+            const int k = (int)b0;
+            const double y0 = (k >= 0 && k < B) ? y[(size_t)v * B + k] : 0.0;
+            const double y1 = (k + 1 >= 0 && k + 1 < B) ? y[(size_t)v * B + k + 1] : 0.0;
+            acc += ((1.0 - a) * y0 + a * y1) / l;
+        }
+        z[c] = scale * acc;
     }
 }
 
@@ -438,7 +481,15 @@ static double dot(size_t n, const double* a, const double* b)
     return s;
 }
 
-int orc_cgls(const orc_matrix* m, const double* y, double* u, int iters, double* resid)
+static void backproject_with(const orc_matrix* m, int interp, const double* r, double* z)
+{
+    if (interp)
+        orc_backproject_interp(&m->g, r, z);
+    else
+        orc_backproject(m, r, z);
+}
+
+int orc_cgls_with(const orc_matrix* m, int interp_bp, const double* y, double* u, int iters, double* resid)
 {
     size_t nr = (size_t)m->n_rows, nc = (size_t)m->n_cols;
     double* r = (double*)malloc(sizeof(double) * nr);
@@ -447,7 +498,7 @@ int orc_cgls(const orc_matrix* m, const double* y, double* u, int iters, double*
     double* z = (double*)malloc(sizeof(double) * nc);
     orc_project(m, u, q);
     for (size_t i = 0; i < nr; ++i) r[i] = y[i] - q[i];
-    orc_backproject(m, r, z);
+    backproject_with(m, interp_bp, r, z);
     memcpy(s, z, sizeof(double) * nc);
     double gam = dot(nc, z, z), gam0 = gam;
     int steps = 0;
@@ -459,7 +510,7 @@ int orc_cgls(const orc_matrix* m, const double* y, double* u, int iters, double*
         double a = gam / del;
         for (size_t i = 0; i < nc; ++i) u[i] += a * s[i];
         for (size_t i = 0; i < nr; ++i) r[i] -= a * q[i];
-        orc_backproject(m, r, z);
+        backproject_with(m, interp_bp, r, z);
         double gnew = dot(nc, z, z);
         double b = gnew / gam;
         for (size_t i = 0; i < nc; ++i) s[i] = z[i] + b * s[i];
@@ -474,10 +525,17 @@ int orc_cgls(const orc_matrix* m, const double* y, double* u, int iters, double*
     return steps;
 }
 
+int orc_cgls(const orc_matrix* m, const double* y, double* u, int iters, double* resid)
+{
+    return orc_cgls_with(m, 0, y, u, iters, resid);
+}
+
 /* ------------------------------------------------------------------ outer loop
  * The EPTV algorithm of Sec. 2.2: from f^(0) = 0, repeat
  *   1. v = argmin ||P f - y||^2 by CGLS started at f^(k)   (or, with zero CGLS
  *      steps, the gradient form of Eq. 8: v = f - mu/lambda P^T (P f - y));
+ *      P^T is the transpose, or with interp_bp the Eq. 11 operator in its
+ *      place, as the paper's on-the-fly code does (Sec. 2.3);
  *   2. P2 by gradient descent from v (or f^(k)), sigma chosen once from the
  *      P2 start image, weights updated at every descent step;
  *   3. negative pixels set to zero. */
@@ -498,11 +556,11 @@ int orc_reconstruct(const orc_matrix* m, const orc_params* p, const double* y, d
         double resid = 0.0;
         int steps = 0;
         if (p->cgls_iters > 0) {
-            steps = orc_cgls(m, y, v, p->cgls_iters, &resid);
+            steps = orc_cgls_with(m, p->interp_bp, y, v, p->cgls_iters, &resid);
         } else {
             orc_project(m, f, q);
             for (size_t i = 0; i < nr; ++i) q[i] -= y[i];
-            orc_backproject(m, q, w);
+            backproject_with(m, p->interp_bp, q, w);
             for (size_t i = 0; i < nc; ++i) v[i] = f[i] - (p->mu / p->lambda) * w[i];
             orc_project(m, v, q);
             for (size_t i = 0; i < nr; ++i) resid += (y[i] - q[i]) * (y[i] - q[i]);

@@ -12,7 +12,8 @@
  *   - P: the fan-beam system matrix whose entry p_ij is the length of ray i
  *     inside pixel j (Sec. 2.1, Eq. 1), traced with Siddon's parametric method
  *     and stored explicitly (the paper's look-up-table strategy, Sec. 2.3);
- *   - P^T: the transpose of that matrix (Sec. 2.2, below Eq. 6);
+ *   - P^T: the transpose of that matrix (Sec. 2.2, below Eq. 6), and the
+ *     paper's pixel-driven interpolating backprojector (Eq. 11, App. III);
  *   - the half-edge TV magnitudes and edge weights (Eq. 5; App. II Eq. A3),
  *     the EPTV variation by the symmetric difference scheme (App. II Eq. A2)
  *     and the P2 descent direction (Eq. 9);
@@ -59,6 +60,9 @@ int orc_trace_ray(const orc_geometry* g, int v, int b, int cap, int* pix, double
 void orc_project(const orc_matrix* m, const double* x, double* q);     /* q = P x   */
 void orc_backproject(const orc_matrix* m, const double* r, double* z); /* z = P^T r */
 
+/* z = the Eq. 11 pixel-driven interpolating backprojection of y (App. III). */
+void orc_backproject_interp(const orc_geometry* g, const double* y, double* z);
+
 /* Half-edge TV magnitudes of App. II Eq. A3 (+eps^2 under the root). */
 void orc_tv_edges(int nx, int ny, const double* f, double eps, double* tvx, double* tvy);
 /* J_h(f) = sum over all half-edges of w_e * TV_e, w_e = exp(-TV_e^2/sigma^2) (Eq. 4-5). */
@@ -87,6 +91,7 @@ typedef struct {
     int p2_start;             /* 0: P2 starts at v, 1: at f^(k) */
     int positivity;
     int track_energy;         /* fill energy[] with E(f^(k+1)) */
+    int interp_bp;            /* 1: P1 uses the Eq. 11 backprojector for P^T */
 } orc_params;
 
 typedef struct {              /* every pointer may be NULL */
@@ -101,6 +106,8 @@ typedef struct {              /* every pointer may be NULL */
 
 /* CGLS on min ||P u - y||^2 from the given u (App. I). Returns steps run. */
 int orc_cgls(const orc_matrix* m, const double* y, double* u, int iters, double* resid);
+/* The same with the Eq. 11 backprojector in place of P^T when interp_bp. */
+int orc_cgls_with(const orc_matrix* m, int interp_bp, const double* y, double* u, int iters, double* resid);
 
 /* n GD steps of P2 from f (in/out) towards v; sigma < 0 selects it from f. */
 int orc_tv_step(int nx, int ny, const orc_params* p, double* f, const double* v,

@@ -45,7 +45,7 @@ class _Params(C.Structure):
                 ("sigma_floor", C.c_double), ("tv_eps", C.c_double), ("armijo_c", C.c_double),
                 ("armijo_shrink", C.c_double), ("armijo_t0", C.c_double),
                 ("armijo_max_backtracks", C.c_int), ("p2_start", C.c_int),
-                ("positivity", C.c_int), ("track_energy", C.c_int)]
+                ("positivity", C.c_int), ("track_energy", C.c_int), ("interp_bp", C.c_int)]
 
 
 class _Stats(C.Structure):
@@ -76,6 +76,7 @@ class Params:
     p2_start: int = 0
     positivity: int = 1
     track_energy: int = 0
+    interp_bp: int = 0
 
     def _c(self) -> _Params:
         d = asdict(self)
@@ -101,6 +102,7 @@ def lib() -> C.CDLL:
         L.orc_trace_ray.argtypes = [C.POINTER(_Geom), C.c_int, C.c_int, C.c_int, ip, dp]
         L.orc_project.argtypes = [C.c_void_p, dp, dp]
         L.orc_backproject.argtypes = [C.c_void_p, dp, dp]
+        L.orc_backproject_interp.argtypes = [C.POINTER(_Geom), dp, dp]
         L.orc_tv_edges.argtypes = [C.c_int, C.c_int, dp, C.c_double, dp, dp]
         L.orc_tv_energy.argtypes = [C.c_int, C.c_int, dp, C.c_double, C.c_double]
         L.orc_tv_energy.restype = C.c_double
@@ -111,6 +113,7 @@ def lib() -> C.CDLL:
         L.orc_select_sigma.argtypes = [C.c_int, C.c_int, dp, C.c_double, C.c_double, C.c_double]
         L.orc_select_sigma.restype = C.c_double
         L.orc_cgls.argtypes = [C.c_void_p, dp, dp, C.c_int, dp]
+        L.orc_cgls_with.argtypes = [C.c_void_p, C.c_int, dp, dp, C.c_int, dp]
         L.orc_tv_step.argtypes = [C.c_int, C.c_int, C.POINTER(_Params), dp, dp, C.c_double, C.c_int,
                                   ip, dp, dp]
         L.orc_reconstruct.argtypes = [C.c_void_p, C.POINTER(_Params), dp, dp, dp, C.POINTER(_Stats)]
@@ -146,6 +149,17 @@ def _geom(g) -> tuple[_Geom, Optional[np.ndarray]]:
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def backproject_interp(g, r) -> np.ndarray:
+    """Eq. 11 (App. III): pixel-driven backprojection with linear interpolation in beta."""
+    r = _f64(r).reshape(-1)
+    assert r.size == int(g.n_views) * int(g.n_bins)
+    cg, keep = _geom(g)
+    z = np.zeros(int(g.nx) * int(g.ny))
+    lib().orc_backproject_interp(C.byref(cg), _d(r), _d(z))
+    del keep
+    return z.reshape(int(g.ny), int(g.nx))
 
 
 class Matrix:
@@ -194,10 +208,15 @@ class Matrix:
         lib().orc_backproject(self._h, _d(r), _d(z))
         return z.reshape(self.ny, self.nx)
 
-    def cgls(self, y, u0, iters: int):
+    def backproject_interp(self, r) -> np.ndarray:
+        """The Eq. 11 backprojector of the same geometry."""
+        return backproject_interp(self.g, r)
+
+    def cgls(self, y, u0, iters: int, interp_bp: int = 0):
         u = _f64(u0).reshape(-1).copy()
         res = np.zeros(1)
-        steps = lib().orc_cgls(self._h, _d(_f64(y).reshape(-1)), _d(u), int(iters), _d(res))
+        steps = lib().orc_cgls_with(self._h, int(interp_bp), _d(_f64(y).reshape(-1)), _d(u), int(iters),
+                                    _d(res))
         return u.reshape(self.ny, self.nx), int(steps), float(res[0])
 
     def reconstruct(self, y, params: Params, f0=None, f_ref=None) -> tuple[np.ndarray, dict]:

@@ -169,6 +169,112 @@ def test_rotation_by_quarter_turn(oracle):
     np.testing.assert_allclose(M.project(fr), np.roll(M.project(f), 2, axis=0), rtol=1e-11, atol=1e-11)
 
 
+# ------------------------------------------------------------------ Eq. 11 backprojector (App. III)
+
+@pytest.mark.parametrize("offset,bins", [(0.0, (4,)), (0.5, (3, 4)), (-0.5, (4, 5))])
+def test_eq11_centre_pixel_closed_form(oracle, offset, bins):
+    """The centre pixel of an odd grid sits on the isocentre: every view sees it
+    on the central ray (beta* = 0) at distance SAD, so Eq. 11 reads the bin
+    whose centre is at beta = 0 (or the mean of the two around it when the
+    detector is shifted by half a bin) and divides by SAD."""
+    g = geom(5, 5, 7, 9, pixel=0.7, angles=np.random.default_rng(11).uniform(0, 2 * np.pi, 7), offset=offset)
+    y = np.random.default_rng(12).uniform(size=(g.n_views, g.n_bins))
+    z = oracle.backproject_interp(g, y)
+    expect = g.pixel_mm ** 2 / (g.dbeta_rad * g.sad_mm) * sum(y[:, b].sum() for b in bins) / len(bins)
+    assert abs(z[2, 2] - expect) <= 1e-12 * expect
+
+
+def test_eq11_strip_lies_on_the_traced_ray(oracle):
+    """For a sinogram with a single non-zero bin, the pixels that Eq. 11 gives at
+    least half their full weight d^2 / (dbeta l) have centres within half a bin
+    of that ray, so the ray crosses each of them: they must be a subset of the
+    ray's Siddon support (itself pinned by brute force above) and cover a good
+    part of it."""
+    g = geom(32, 32, 4, 160, angles=[0.3, 1.9, 3.4, 5.0])
+    M = oracle.Matrix(g)
+    half_diag = 0.5 * g.pixel_mm * math.hypot(g.nx, g.ny)
+    assert (g.sad_mm + half_diag) * 0.5 * g.dbeta_rad < 0.5 * g.pixel_mm  # strip narrower than a pixel
+    px = (np.arange(g.nx) + 0.5 - 0.5 * g.nx) * g.pixel_mm
+    py = (np.arange(g.ny) + 0.5 - 0.5 * g.ny) * g.pixel_mm
+    for v, b in [(0, 80), (1, 60), (2, 95), (3, 71)]:
+        th = g.angles()[v]
+        dist = np.hypot(px[None, :] + g.sad_mm * np.cos(th), py[:, None] + g.sad_mm * np.sin(th))
+        y = np.zeros((g.n_views, g.n_bins))
+        y[v, b] = 1.0
+        strip = oracle.backproject_interp(g, y) * dist * g.dbeta_rad / g.pixel_mm ** 2 >= 0.5
+        support = M.backproject(y) > 0.0
+        assert strip.any() and not (strip & ~support).any()
+        assert strip.sum() >= 0.15 * support.sum()
+
+
+def test_eq11_adjoint_condition_on_smooth_data(oracle):
+    """App. III: the operator is built to satisfy <f, P^T y> = <P f, y> (Eq. A3),
+    which the paper reports holds to better than 1 %.  On smooth inputs (a
+    rasterised phantom and the exact line integrals of another) the defect is
+    second order in the sampling and far smaller."""
+    from paper_1009_2288_amd import synth
+    c = synth.make_case("small", 0)
+    M = oracle.Matrix(c.geom)
+    other = synth.Ellipse(10.0, -5.0, 30.0, 18.0, 0.4, 0.02)
+    y = synth.line_integrals([other], c.geom)
+    a = float(np.vdot(M.project(c.phantom), y))
+    b = float(np.vdot(c.phantom, M.backproject_interp(y)))
+    assert abs(a - b) <= 2e-4 * abs(a)
+
+
+def test_eq11_scale_matches_transpose_of_constant(oracle):
+    """Per view the chords of the rays through a pixel sum to its area over the
+    ray spacing l * dbeta, the constant Eq. 11 carries: on a constant sinogram
+    the two operators agree when averaged over 8x8 blocks."""
+    from paper_1009_2288_amd import synth
+    g = synth.geometry_small()
+    M = oracle.Matrix(g)
+    one = np.ones((g.n_views, g.n_bins))
+    k = 8
+    blk = lambda z: z.reshape(g.ny // k, k, g.nx // k, k).mean(axis=(1, 3))
+    r = blk(M.backproject(one)) / blk(oracle.backproject_interp(g, one))
+    c = r[4:12, 4:12]
+    assert np.abs(c - 1.0).max() <= 1e-2
+
+
+def test_eq11_zero_beyond_the_detector(oracle):
+    """A pixel seen outside the fan reads nothing (zero beyond the last bin),
+    and no view reads a neighbouring view's bins: with a narrow fan, a
+    sinogram whose only non-zero bins are the edge bins of the other view gives
+    the same image as that view alone."""
+    g = geom(9, 9, 1, 5, angles=[0.0], fan_scale=0.2)
+    z = oracle.backproject_interp(g, np.ones((1, 5)))
+    assert z[4, 4] > 0 and z[0, 4] == 0.0 and z[8, 4] == 0.0
+    angles = [0.0, 2.0]
+    g2 = geom(9, 9, 2, 5, angles=angles, fan_scale=0.2)
+    for keep in (0, 1):
+        g1 = geom(9, 9, 1, 5, angles=[angles[keep]], fan_scale=0.2)
+        y = np.zeros((2, 5))
+        y[keep, 0] = y[keep, 4] = 1.0
+        z2 = oracle.backproject_interp(g2, y)
+        assert np.array_equal(z2, oracle.backproject_interp(g1, y[keep:keep + 1]))
+        assert z2.max() > 0
+
+
+def test_eq11_in_p1_wiring(oracle):
+    """With interp_bp the P1 step uses Eq. 11 in place of P^T: one gradient-form
+    step is f - mu/lambda B(P f - y), one CGLS step is u + a s with s = B r,
+    a = |s|^2 / |P s|^2 (App. I with B for P^T), B the Eq. 11 operator."""
+    g = geom(12, 10, 9, 40)
+    M = oracle.Matrix(g)
+    rng = np.random.default_rng(21)
+    f0 = rng.uniform(size=(g.ny, g.nx))
+    y = M.project(rng.uniform(size=(g.ny, g.nx)))
+    base = dict(outer_iters=1, tv_iters=0, zero_init=0, positivity=0, interp_bp=1, sigma_fixed=1.0)
+    mu, lam = 1.0, 50.0
+    f, _ = M.reconstruct(y, oracle.Params(cgls_iters=0, mu=mu, lam=lam, **base), f0=f0)
+    np.testing.assert_allclose(f, f0 - mu / lam * M.backproject_interp(M.project(f0) - y), rtol=1e-12, atol=1e-12)
+    f, _ = M.reconstruct(y, oracle.Params(cgls_iters=1, **base), f0=f0)
+    s = M.backproject_interp(y - M.project(f0))
+    a = np.vdot(s, s) / np.vdot(M.project(s), M.project(s))
+    np.testing.assert_allclose(f, f0 + a * s, rtol=1e-12, atol=1e-12)
+
+
 def test_nnz_small_case(oracle):
     """Every ray of the 128^2 case crosses the image; each meets between max(n)
     and nx+ny-1 pixels."""
