@@ -397,6 +397,61 @@ void orc_tv_gradient(int nx, int ny, const double* f, const double* v, double la
     free(wy);
 }
 
+/* Vector-Jacobian product of the descent direction g(f) of Eq. 9 / Eq. A2
+ * with respect to f, out = (dg/df)^T u, for differentiating through P2 steps
+ * (sigma and the step sizes held constant).  Write g = lambda (f - v) +
+ * sum_e F_e (e_B - e_A) over half-edges e from pixel A to pixel B, with
+ * F_e = w(TV) d / TV, d = f_B - f_A, TV = sqrt(d^2 + t1^2/2 + t2^2/2 + eps^2),
+ * t1, t2 the differences of the pair means of Eq. A3 and w = exp(-TV^2/s^2).
+ * Then dF/dd = w/TV - c d, dF/dt1 = -c t1/2, dF/dt2 = -c t2/2 with
+ * c = w d (1/TV + 2 TV/s^2) / TV^2, and each edge adds (u_B - u_A) times the
+ * derivative of F_e to every pixel F_e depends on.  Ghost pixels (outside
+ * the image) carry no entry. */
+static void vjp_add(double* out, int nx, int ny, int i, int j, double c)
+{
+    if (i >= 0 && i < nx && j >= 0 && j < ny) out[(size_t)j * nx + i] += c;
+}
+
+static void vjp_edge(int nx, int ny, const double* f, const double* u, double sigma, double eps, int ax, int ay,
+                     int bx, int by, int px_, int py_, double* out)
+{
+    /* A = (ax, ay), B = (bx, by); (px_, py_) is the unit step across the edge
+     * direction (the "up" pair of an x-edge, the "right" pair of a y-edge). */
+    const double fa = px(f, nx, ny, ax, ay), fb = px(f, nx, ny, bx, by);
+    const double d = fb - fa, m0 = 0.5 * (fa + fb);
+    const double mu = 0.5 * (px(f, nx, ny, ax + px_, ay + py_) + px(f, nx, ny, bx + px_, by + py_));
+    const double md = 0.5 * (px(f, nx, ny, ax - px_, ay - py_) + px(f, nx, ny, bx - px_, by - py_));
+    const double t1 = mu - m0, t2 = m0 - md;
+    const double tv = sqrt(d * d + 0.5 * t1 * t1 + 0.5 * t2 * t2 + eps * eps);
+    const double r = tv / sigma, w = exp(-r * r);
+    const double c = w * d * (1.0 / tv + 2.0 * tv / (sigma * sigma)) / (tv * tv);
+    const double ub = px(u, nx, ny, bx, by), ua = px(u, nx, ny, ax, ay), ue = ub - ua;
+    const double dd = ue * (w / tv - c * d), d1 = ue * (-0.5 * c * t1), d2 = ue * (-0.5 * c * t2);
+    /* d = fB - fA */
+    vjp_add(out, nx, ny, bx, by, dd);
+    vjp_add(out, nx, ny, ax, ay, -dd);
+    /* t1 = (f(A+p) + f(B+p))/2 - (fA + fB)/2 */
+    vjp_add(out, nx, ny, ax + px_, ay + py_, 0.5 * d1);
+    vjp_add(out, nx, ny, bx + px_, by + py_, 0.5 * d1);
+    vjp_add(out, nx, ny, ax, ay, -0.5 * d1);
+    vjp_add(out, nx, ny, bx, by, -0.5 * d1);
+    /* t2 = (fA + fB)/2 - (f(A-p) + f(B-p))/2 */
+    vjp_add(out, nx, ny, ax, ay, 0.5 * d2);
+    vjp_add(out, nx, ny, bx, by, 0.5 * d2);
+    vjp_add(out, nx, ny, ax - px_, ay - py_, -0.5 * d2);
+    vjp_add(out, nx, ny, bx - px_, by - py_, -0.5 * d2);
+}
+
+void orc_tv_gradient_vjp(int nx, int ny, const double* f, double lambda, double sigma, double eps,
+                         const double* u, double* out)
+{
+    for (size_t p = 0; p < (size_t)nx * ny; ++p) out[p] = lambda * u[p];
+    for (int j = 0; j < ny; ++j)
+        for (int i = -1; i < nx; ++i) vjp_edge(nx, ny, f, u, sigma, eps, i, j, i + 1, j, 0, 1, out);
+    for (int j = -1; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) vjp_edge(nx, ny, f, u, sigma, eps, i, j, i, j + 1, 1, 0, out);
+}
+
 /* Sec. 2.1: sigma from the distribution of gradient magnitudes, a fixed share
  * of them lying above it.  Order statistic of rank ceil(q n) - 1 (0-based,
  * ascending) over all n half-edge magnitudes, by a full sort. */

@@ -70,6 +70,9 @@ double orc_tv_energy(int nx, int ny, const double* f, double sigma, double eps);
 /* g = lambda (f - v) + A2 variation (Eq. 9, App. II Eq. A2), weights from f. */
 void orc_tv_gradient(int nx, int ny, const double* f, const double* v, double lambda,
                      double sigma, double eps, double* g, double* wx, double* wy);
+/* out = (dg/df)^T u for the g above, sigma held fixed (may be +inf). */
+void orc_tv_gradient_vjp(int nx, int ny, const double* f, double lambda, double sigma, double eps,
+                         const double* u, double* out);
 /* Q(h) = lambda/2 ||h - v||^2 + sum_e w_e TV_e(h) with caller-frozen weights. */
 double orc_surrogate(int nx, int ny, const double* h, const double* v, double lambda,
                      const double* wx, const double* wy, double eps);

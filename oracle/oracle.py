@@ -108,6 +108,7 @@ def lib() -> C.CDLL:
         L.orc_tv_energy.restype = C.c_double
         L.orc_tv_gradient.argtypes = [C.c_int, C.c_int, dp, dp, C.c_double, C.c_double, C.c_double,
                                       dp, dp, dp]
+        L.orc_tv_gradient_vjp.argtypes = [C.c_int, C.c_int, dp, C.c_double, C.c_double, C.c_double, dp, dp]
         L.orc_surrogate.argtypes = [C.c_int, C.c_int, dp, dp, C.c_double, dp, dp, C.c_double]
         L.orc_surrogate.restype = C.c_double
         L.orc_select_sigma.argtypes = [C.c_int, C.c_int, dp, C.c_double, C.c_double, C.c_double]
@@ -273,6 +274,15 @@ def tv_gradient(f, v, lam: float, sigma: float, eps: float):
     wy = np.zeros((ny + 1, nx))
     lib().orc_tv_gradient(nx, ny, _d(f), _d(v), float(lam), float(sigma), float(eps), _d(g), _d(wx), _d(wy))
     return g, wx, wy
+
+
+def tv_gradient_vjp(f, u, lam: float, sigma: float, eps: float) -> np.ndarray:
+    """(dg/df)^T u for the P2 direction g of Eq. 9 (sigma fixed)."""
+    f, u = _f64(f), _f64(u)
+    ny, nx = f.shape
+    out = np.zeros((ny, nx))
+    lib().orc_tv_gradient_vjp(nx, ny, _d(f), float(lam), float(sigma), float(eps), _d(u), _d(out))
+    return out
 
 
 def surrogate(h, v, lam: float, wx, wy, eps: float) -> float:

@@ -392,6 +392,42 @@ def test_tv_gradient_divergence_sums_to_zero(oracle):
     assert abs(g.sum()) < 1e-12 * np.abs(g).sum()
 
 
+@pytest.mark.parametrize("sigma", [0.3, np.inf])
+def test_tv_vjp_matches_finite_difference_jacobian(oracle, sigma):
+    """(dg/df)^T against the Jacobian of the direction g built column by column
+    from central differences of g itself (independent of the VJP's formulas)."""
+    nx, ny, lam, eps, h = 5, 4, 0.7, 0.05, 1e-6
+    rng = np.random.default_rng(31)
+    f = rng.normal(size=(ny, nx))
+    v = rng.normal(size=(ny, nx))
+    n = nx * ny
+    J = np.zeros((n, n))
+    for k in range(n):
+        e = np.zeros(n)
+        e[k] = h
+        gp = oracle.tv_gradient(f + e.reshape(ny, nx), v, lam, sigma, eps)[0]
+        gm = oracle.tv_gradient(f - e.reshape(ny, nx), v, lam, sigma, eps)[0]
+        J[:, k] = (gp - gm).ravel() / (2 * h)
+    for k in range(3):
+        u = rng.normal(size=(ny, nx))
+        got = oracle.tv_gradient_vjp(f, u, lam, sigma, eps).ravel()
+        np.testing.assert_allclose(got, J.T @ u.ravel(), rtol=1e-6, atol=1e-6 * np.abs(J).max())
+
+
+def test_tv_vjp_large_eps_is_dirichlet_laplacian(oracle):
+    """With sigma = inf and eps far above every difference, F = d / eps and the
+    Jacobian tends to lambda I + L / eps, L the 5-point negative Laplacian with
+    zero values outside the image."""
+    nx, ny, lam, eps = 7, 6, 0.3, 1e5
+    rng = np.random.default_rng(32)
+    f = rng.uniform(size=(ny, nx))
+    u = rng.normal(size=(ny, nx))
+    up = np.pad(u, 1)
+    lap = 4 * u - up[1:-1, 2:] - up[1:-1, :-2] - up[2:, 1:-1] - up[:-2, 1:-1]
+    got = oracle.tv_gradient_vjp(f, u, lam, np.inf, eps)
+    np.testing.assert_allclose(got, lam * u + lap / eps, rtol=1e-8, atol=1e-12)
+
+
 def test_sigma_matches_numpy_inverted_cdf(oracle):
     rng = np.random.default_rng(9)
     f = rng.uniform(0, 0.03, size=(23, 19))
