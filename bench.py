@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK = 157.3e12  # MI355X published FP32 vector peak, FLOP/s
+HBM_PEAK = 8.0e12            # MI355X published HBM3E bandwidth, B/s
 
 
 def log(msg):
@@ -61,6 +62,41 @@ def cpu_baseline(case, iters):
             "seconds": dt}
 
 
+def time_to_rmse(E, synth, P, base, torch, np, seeds):
+    """Seconds of plain GPU EPTV until the RMSE to the phantom reaches the FP64
+    oracle's RMSE after 100 iterations (tests/golden/rmse_targets_paper.json),
+    the device-side RMSE record included in the timed run; median over seeds."""
+    with open(os.path.join(ROOT, "tests", "golden", "rmse_targets_paper.json")) as fh:
+        targets = json.load(fh)
+    per = []
+    s = torch.cuda.current_stream()
+    for seed in seeds:
+        c = synth.make_case("paper", seed)
+        y = torch.from_numpy(c.y.astype(np.float32)).cuda()
+        ref = torch.from_numpy(c.phantom.astype(np.float32)).cuda()
+        target = targets["seeds"][str(seed)]["rmse_final"]
+        _, st = P.reconstruct(y, E.Params(outer_iters=100, zero_init=1, **base), f_ref=ref)
+        hit = np.nonzero(st["rmse"] <= target)[0]
+        if hit.size == 0:
+            per.append({"seed": seed, "target": target, "iterations": None, "seconds": None})
+            continue
+        n = int(hit[0]) + 1
+        f = torch.zeros_like(ref)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(s)
+        P.reconstruct(y, E.Params(outer_iters=n, zero_init=1, **base), f=f, f_ref=ref, stats=False)
+        e1.record(s)
+        torch.cuda.synchronize()
+        per.append({"seed": seed, "target": target, "iterations": n, "seconds": e0.elapsed_time(e1) / 1e3,
+                    "rmse": float(st["rmse"][n - 1])})
+    secs = [p["seconds"] for p in per if p["seconds"] is not None]
+    return {"target": "FP64 oracle RMSE to the phantom after 100 iterations, same seed",
+            "plain_seconds_median": float(np.median(secs)) if len(secs) == len(per) else None,
+            "plain_iterations_median": float(np.median([p["iterations"] for p in per if p["iterations"]])),
+            "per_seed": per}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +105,9 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=200)
     ap.add_argument("--cpu-iters", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rmse-seeds", type=int, default=10, help="seeds for the time-to-RMSE leg (0 to skip)")
+    ap.add_argument("--operator", choices=["fly", "stored"], default="fly",
+                    help="P and P^T on the fly, or from the stored float32 matrix")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
@@ -90,7 +129,10 @@ def main():
     y = torch.from_numpy(case.y.astype(np.float32)).cuda()
     ref = torch.from_numpy(case.phantom.astype(np.float32)).cuda()
     f = torch.zeros((g.ny, g.nx), dtype=torch.float32, device="cuda")
-    base = dict(cgls_iters=3, tv_iters=5, lam=1000.0, edge_quantile=0.9, tv_eps=1e-4)
+    stored = args.operator == "stored"
+    if stored:
+        log(f"bench: storing the system matrix ({P.store_matrix() / 2**20:.0f} MiB)")
+    base = dict(cgls_iters=3, tv_iters=5, lam=1000.0, edge_quantile=0.9, tv_eps=1e-4, stored_matrix=int(stored))
 
     log(f"bench: warmup {args.warmup} iterations")
     P.reconstruct(y, eptv.Params(outer_iters=args.warmup, zero_init=1, **base), f=f, stats=False)
@@ -118,18 +160,41 @@ def main():
     q = P.new_sinogram()
     z = P.new_image()
     r = y.clone()
-    t_proj = kernel_avg_ms(lambda: P.project_dual(x, xT, q), args.kernel_reps, torch)
-    t_bp = kernel_avg_ms(lambda: P.backproject(r, z), args.kernel_reps, torch)
+    ops = {"project_dual": lambda: P.project_dual(x, xT, q), "backproject": lambda: P.backproject(r, z),
+           "backproject_interp": lambda: P.backproject_interp(r, z)}
+    if stored:
+        ops.update({"project_stored": lambda: P.project_stored(x, q),
+                    "backproject_stored": lambda: P.backproject_stored(r, z)})
+    op_ms = {k: kernel_avg_ms(fn, args.kernel_reps, torch) for k, fn in ops.items()}
+    t_proj = op_ms["project_stored" if stored else "project_dual"]
+    t_bp = op_ms["backproject_stored" if stored else "backproject"]
     per_it = {"project": 4 * t_proj, "backproject": 3 * t_bp}
     dom = max(per_it, key=per_it.get)
     t_dom = t_proj if dom == "project" else t_bp
-    flops = 2.0 * nnz
-    achieved = flops / (t_dom * 1e-3)
-    roof = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
-            "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK, "traffic": None,
-            "avg_ms": t_dom, "algorithmic_flops_per_launch": flops, "nnz": nnz,
-            "project_avg_ms": t_proj, "backproject_avg_ms": t_bp}
-    log(f"bench: project {t_proj * 1e3:.1f} us, backproject {t_bp * 1e3:.1f} us, nnz {nnz}")
+    if stored:
+        # one CSR (or CSC) pass: 4-byte value and 4-byte index per nonzero,
+        # 8-byte offsets per row (column), the input vector once, the output once
+        n_img, n_sino = g.nx * g.ny, g.n_views * g.n_bins
+        rows, n_in, n_out = (n_sino, n_img, n_sino) if dom == "project" else (n_img, n_sino, n_img)
+        nbytes = 8.0 * nnz + 8.0 * (rows + 1) + 4.0 * (n_in + n_out)
+        achieved = nbytes / (t_dom * 1e-3)
+        roof = {"bound": "hbm", "kernel": dom + "_stored", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": None, "avg_ms": t_dom,
+                "algorithmic_bytes_per_launch": nbytes, "nnz": nnz}
+    else:
+        flops = 2.0 * nnz
+        achieved = flops / (t_dom * 1e-3)
+        roof = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK, "traffic": None,
+                "avg_ms": t_dom, "algorithmic_flops_per_launch": flops, "nnz": nnz}
+    roof["operators_avg_ms"] = op_ms
+    log("bench: " + ", ".join(f"{k} {v * 1e3:.1f} us" for k, v in op_ms.items()) + f", nnz {nnz}")
+
+    ttr = None
+    if args.rmse_seeds > 0:
+        log(f"bench: time to the oracle's RMSE, seeds 0-{args.rmse_seeds - 1}")
+        ttr = time_to_rmse(eptv, synth, P, base, torch, np, range(args.rmse_seeds))
+        log(f"bench: plain EPTV reaches the oracle RMSE in {ttr['plain_seconds_median']} s (median)")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -154,8 +219,9 @@ def main():
                                "thorax-like ellipse phantom with low-contrast inserts, Poisson I0 5e4; "
                                "per iteration 3 CGLS steps, adaptive sigma (q 0.9), 5 Armijo GD steps, positivity",
                    "image": [g.ny, g.nx], "views": g.n_views, "bins": g.n_bins, "cgls_iters": 3, "tv_iters": 5,
-                   "graph": os.environ.get("EPTV_NO_GRAPH", "0") in ("", "0")},
+                   "graph": os.environ.get("EPTV_NO_GRAPH", "0") in ("", "0"), "operator": args.operator},
         "rmse_vs_phantom": rmse,
+        "time_to_rmse": ttr,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

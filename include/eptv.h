@@ -56,7 +56,12 @@ typedef enum {
 
 /* Scanner geometry (Sec. 3; App. III Eq. A6).  view_angles_rad is a host array
  * of n_views angles, or NULL for equally spaced views over a full turn.  The
- * source must lie outside the circle through the image corners. */
+ * source must lie outside the circle through the image corners, and the fan
+ * (bin angles (b - (n_bins-1)/2 + bin_offset) dbeta_rad, one bin beyond each
+ * end included) must stay within +-pi/2 of the central ray; otherwise
+ * EPTV_ERR_GEOMETRY.  Pixel (i, j) is centred at
+ * ((i + 1/2 - nx/2) pixel_mm, (j + 1/2 - ny/2) pixel_mm), the source of view
+ * theta at -sad_mm (cos theta, sin theta), ray b along theta + beta_b. */
 typedef struct {
     int nx, ny;
     double pixel_mm;
@@ -87,6 +92,11 @@ typedef struct {
     int armijo_max_backtracks;
     int p2_start;        /* 0: P2 starts at v (P1's output); 1: at f^(k) */
     int positivity;      /* 1: step 3 of the algorithm (f = max(f, 0)) */
+    int stored_matrix;   /* 1: P and P^T from the matrix kept by eptv_plan_store_matrix
+                            (the look-up-table strategy of Sec. 2.3); 0: on the fly */
+    int interp_bp;       /* 1: P1 uses the Eq. 11 interpolating backprojector in place
+                            of P^T (the paper's on-the-fly code, Sec. 2.3); 0: the
+                            exact transpose */
 } eptv_params;
 
 /* Optional per-iteration records, host arrays filled when a call that takes
@@ -110,6 +120,25 @@ int eptv_plan_destroy(eptv_plan plan);
 /* Number of (ray, pixel) pairs with a positive intersection length, counted
  * on the host in double precision: the nonzeros of P (Sec. 2.1, Eq. 1). */
 int eptv_plan_nnz(eptv_plan plan, long long* nnz);
+
+/* The float32 system matrix of a geometry as the kernels evaluate it, in CSR
+ * form by ray (row v*n_bins + b; columns j*nx + i; entries in the order the
+ * ray sweeps the image), computed on the host: no GPU is needed.  Pass NULL
+ * arrays to get *nnz only; otherwise rowptr holds n_views*n_bins + 1 entries
+ * and col/val hold *nnz. */
+int eptv_geometry_matrix(const eptv_geometry* geom, long long* nnz, long long* rowptr, int* col, float* val);
+
+/* Store that matrix on the plan's device, by ray (CSR, for P) and by pixel
+ * (CSC, for P^T): 16 bytes per nonzero plus the offsets (215 MB at 512^2 /
+ * 40 views x 736 bins).  Owned by the plan; built once, later calls only
+ * report the size.  Synchronous. */
+int eptv_plan_store_matrix(eptv_plan plan, size_t* device_bytes);
+
+/* q = alpha P x + beta q and z = alpha P^T r + beta z from the stored matrix
+ * (EPTV_ERR_ARG if it is not stored).  Same matrix as eptv_project /
+ * eptv_backproject bit for bit; only the summation order differs. */
+int eptv_project_stored(eptv_plan plan, const float* x, float* q, float alpha, float beta, void* stream);
+int eptv_backproject_stored(eptv_plan plan, const float* r, float* z, float alpha, float beta, void* stream);
 
 /* Workspace bytes for the calls below (device memory the caller allocates and
  * passes as ws / ws_bytes; a smaller ws_bytes is EPTV_ERR_WORKSPACE).
@@ -139,6 +168,15 @@ int eptv_project_dual(eptv_plan plan, const float* x, const float* xT, float* q,
 int eptv_backproject(eptv_plan plan, const float* r, float* z, float alpha, float beta,
                      void* ws, size_t ws_bytes, void* stream);
 
+/* z = alpha B r + beta z with B the pixel-driven interpolating backprojector
+ * of Eq. 11 (App. III): per pixel and view, r is interpolated linearly in the
+ * bin direction at the angle beta* of the ray through the pixel centre (bins
+ * beyond the detector read zero), divided by the source-to-pixel distance l,
+ * summed over views and scaled by pixel_mm^2 / dbeta_rad.  A smooth
+ * approximation of P^T, not its exact transpose.  r [n_views][n_bins],
+ * z [ny][nx]; beta == 0 never reads z.  Needs no workspace. */
+int eptv_backproject_interp(eptv_plan plan, const float* r, float* z, float alpha, float beta, void* stream);
+
 /* The P2 descent direction g = lambda (f - v) + (A2 variation of the EPTV
  * term) (Eq. 9-10, App. II Eq. A2) with the half-edge magnitudes and weights
  * w = exp(-TV^2 / sigma^2) of Eq. A3 / Eq. 5 taken at f.  sigma may be +inf
@@ -146,6 +184,16 @@ int eptv_backproject(eptv_plan plan, const float* r, float* z, float alpha, floa
 int eptv_tv_gradient(eptv_plan plan, const float* f, const float* v, float lambda, float sigma,
                      float tv_eps, float* g, float* wx, float* wy, void* ws, size_t ws_bytes,
                      void* stream);
+
+/* out = (dg/df)^T u: the vector-Jacobian product of eptv_tv_gradient's g with
+ * respect to f, sigma held fixed (Eq. 9 with the A2 variation; the weights of
+ * Eq. 5 / A3 are differentiated along with the magnitudes).  For gradients
+ * through unrolled descent steps; the product with respect to v is -lambda u.
+ * tv_eps must be > 0 (the magnitudes are then differentiable everywhere).
+ * f, u, out [ny][nx]; out must not alias f or u.  ws: workspace of
+ * eptv_workspace_bytes(plan, NULL). */
+int eptv_tv_gradient_vjp(eptv_plan plan, const float* f, const float* u, float lambda, float sigma, float tv_eps,
+                         float* out, void* ws, size_t ws_bytes, void* stream);
 
 /* sigma = max(order statistic of rank ceil(q n) - 1 (0-based, ascending) of
  * the n = ny(nx+1) + (ny+1)nx half-edge magnitudes of f, sigma_floor)

@@ -19,68 +19,99 @@ namespace eptv {
 // continuous row coordinate e(k) = e0 + k*slope and leaves at e(k+1) (row
 // units: 0 at the image bottom edge, 1 per pixel, |slope| <= 1).  A ray closer
 // to the y axis is swept row by row with the roles of rows and columns
-// exchanged.  e is held in 32.32 fixed point, E(k) = E0 + k*S, so stepping
-// along the ray is exact integer arithmetic and a crossing of a row boundary is
-// located to ~1e-10 pixel however shallow the ray.  The length of the ray
-// inside cell (k, m) of its sweep, with lo/hi the smaller/larger of E(k),
-// E(k+1), m0 = floor(lo), m1 = floor(hi) (m1 <= m0 + 1), is
-//     S == 0:            wfull                   if m == m0
-//     m0 == m1:          (hi - lo) * w32         if m == m0
-//     m1 == m0 + 1:      (2^32 - frac(lo)) * w32 if m == m0,  frac(hi) * w32 if m == m1
-// and 0 elsewhere, where w32 = 2^-32 d/|sin| (d/|cos| for row sweeps) is the
-// length per fixed-point unit of row crossed and wfull = d/|cos| (d/|sin|) the
-// length across a whole column (row).  Both the projector and the
-// backprojector evaluate exactly this expression with the same integer and
-// float operations, so their float32 matrices are transposes of each other.
-struct RayTable {
-    longlong2* d_fx = nullptr;  // [V*B] (E0, S)
-    float2* d_w = nullptr;      // [V*B] (w32, +-wfull); wfull < 0 marks a row sweep
-    int2* d_range = nullptr;    // [V*B] sweep range [k_lo, k_hi) that can meet the image
-    float2* d_view = nullptr;   // [V] (cos theta, sin theta)
+// exchanged.  Coordinates are 32.32 fixed point, so stepping along the ray is
+// exact integer arithmetic and a crossing of a row boundary is located to
+// ~1e-10 pixel however shallow the ray.  For cell k of the sweep,
+//     lo(k) = lo0 + k*step  = min(E(k), E(k+1)),   hi(k) = lo(k) + span,
+// span = |step|; the ray's length inside cross cell m of that sweep cell is
+// given by cell_weights() below.  The projector and the backprojector both
+// evaluate exactly that function, so their float32 matrices are transposes of
+// each other bit for bit.
+struct alignas(16) RayFx {
+    long long lo0;   // lo(0)
+    long long step;  // E(k+1) - E(k)
+    long long span;  // |step| (0: the ray is parallel to the sweep axis)
+    float w32;       // 2^-32 d/|sin| (d/|cos| for row sweeps): length per fixed-point unit crossed
+    float wfull;     // d/|cos| (d/|sin|): length across a whole cell; < 0 marks a row sweep
 };
 
-// Ray length in cross cell m of the sweep cell whose boundaries are at E(k) = ea
-// and E(k+1) = eb (32.32 fixed point), given S = eb - ea.
-__device__ __forceinline__ float chord_fx(long long ea, long long eb, long long S, int m, float w32, float wfull)
+struct RayTable {
+    RayFx* d_ray = nullptr;    // [V*B]
+    int2* d_range = nullptr;   // [V*B] sweep range [k_lo, k_hi) that can meet the image
+    float2* d_view = nullptr;  // [V] (cos theta, sin theta)
+    double2* d_view_d = nullptr; // [V] (cos theta, sin theta) in double
+    double* d_tau = nullptr;   // [B+2] tan of the bin angles, bins -1 .. B
+    int* d_list_off = nullptr; // [tiles+1] backprojector ray lists: offsets
+    int* d_list = nullptr;     // ray ids v*B + b that can meet each 16x16 tile
+};
+
+// Lengths of a ray inside the (at most two) cross cells m0 and m0+1 of one
+// sweep cell with lower/upper fixed-point bounds lo and lo + span:
+//     span == 0:                 c0 = wfull,                         c1 = 0
+//     floor(lo) == floor(hi):    c0 = (hi - lo) * w32,               c1 = 0
+//     otherwise (floor(hi) = m0+1): c0 = (2^32 - frac(lo)) * w32,    c1 = frac(hi) * w32
+// with every fixed-point length converted to float exactly once, so each entry
+// carries a relative error of about 1e-7 however shallow the ray.
+struct CellW {
+    int m0;
+    float c0, c1;
+};
+
+__host__ __device__ __forceinline__ CellW cell_weights(long long lo, long long span, float w32, float wfull)
 {
-    const long long lo = S >= 0 ? ea : eb, hi = S >= 0 ? eb : ea;
+    const long long hi = lo + span;
     const int m0 = (int)(lo >> 32), m1 = (int)(hi >> 32);
-    if (S == 0) return m == m0 ? wfull : 0.0f;
     const unsigned flo = (unsigned)lo, fhi = (unsigned)hi;
-    if (m == m0) return (m1 == m0 ? (float)(fhi - flo) : 4294967296.0f - (float)flo) * w32;
-    if (m == m1) return (float)fhi * w32;
-    return 0.0f;
+    const bool same = m0 == m1;
+    CellW w;
+    w.m0 = m0;
+    // 2^32 - frac(lo) formed in integers (exact) before the one rounding to float
+    const float rest = flo ? (float)(0u - flo) : 4294967296.0f;
+    w.c0 = span == 0 ? wfull : (same ? (float)(fhi - flo) : rest) * w32;
+    w.c1 = same ? 0.0f : (float)fhi * w32;
+    return w;
 }
 
 // ---------------------------------------------------------------- device state
 constexpr int kMaxCgls = 64;
-constexpr int kSelectBins = 2048;       // 11-bit radix digits
-constexpr int kArmijoCand = 16;         // Armijo candidates evaluated per pass
+constexpr int kSelectBins = 2048;  // 11-bit radix digits
+constexpr int kArmijoFirst = 8;    // Armijo candidates k = 0..7 in the first pass
+constexpr int kArmijoMore = 16;    // candidates per later pass
+constexpr int kArmijoSlots = 16;   // partial slots per block
 
+// Scalars that stay on the device.  Each entry is written by one kernel and
+// read only by later kernels on the stream (never by the writer's own grid).
 struct DevState {
-    // P1 (CGLS)
-    double gamma[kMaxCgls + 1];  // ||P^T r||^2 before step m
-    double delta[kMaxCgls];      // ||P s||^2 at step m
+    // P1 (CGLS): per-step entries, written by the step's vector kernels
+    double gamma[kMaxCgls + 1];  // ||P^T r_m||^2
     double gamma0;
     float a[kMaxCgls], b[kMaxCgls];
-    int cg_active;
+    int active[kMaxCgls];        // CGLS still running after step m
     int cg_steps;
-    double resid;
     // sigma selection
     uint32_t prefix;
     uint32_t rank;
-    uint32_t rank0;
     float sigma;
     float inv_sigma2;
-    // P2 (Armijo)
+    // P2 (Armijo): the current step's energies and decision
     double q0, gg;
     int decided;
     int k;
     float t;
     // bookkeeping
     int iter;
-    double rmse_acc;
-    int pad[8];
+};
+
+// The float32 system matrix stored on the device (optional, see spmv.hip).
+struct StoredMatrix {
+    long long nnz = 0;
+    int* d_rowptr = nullptr;  // [V*B + 1] CSR by ray
+    int* d_col = nullptr;     // [nnz] pixel index
+    float* d_val = nullptr;   // [nnz] length
+    int* d_colptr = nullptr;  // [nx*ny + 1] CSC by pixel
+    int* d_row = nullptr;     // [nnz] ray index
+    float* d_cval = nullptr;  // [nnz] length
+    size_t bytes = 0;
 };
 
 struct Plan {
@@ -90,6 +121,7 @@ struct Plan {
     long long nnz = 0;
     int device = 0;
     RayTable rays;
+    StoredMatrix mat;
     hipStream_t cap_stream = nullptr;
     // cached graph of one outer iteration
     hipGraphExec_t gexec = nullptr;
@@ -103,14 +135,23 @@ struct Workspace {
     float* s;       // CGLS direction
     float* sT;      // its transposed copy
     float* z;       // backprojection P^T r
-    float* g;       // P2 direction
+    float* g;       // P2 direction (ping)
+    float* g2;      // P2 direction (pong)
+    float* f1;      // P2 iterate (ping)
+    float* f2;      // P2 iterate (pong)
     float* wx;      // x-edge weights [ny][nx+1]
     float* wy;      // y-edge weights [ny+1][nx]
     float* r;       // CGLS residual [V][B]
     float* q;       // P s [V][B]
     uint32_t* keys; // edge magnitude bit patterns [n_edges]
+    float* edge3;   // three values per half-edge [3][n_edges] (direction VJP)
     uint32_t* hist; // [3][kSelectBins]
-    double* part;   // per-block partial sums
+    double* part_proj;  // ||P s||^2 per projector block
+    double* part_bp;    // ||P^T r||^2 per backprojector block
+    double* part_grad;  // (Q, ||g||^2) per gradient block
+    double* part_arm;   // kArmijoSlots candidate energies per Armijo block
+    double* part_res;   // ||r||^2 per sinogram block of the last CGLS axpy
+    double* part_rmse;  // (f - f_ref)^2 per block
     DevState* st;
     float* st_sigma;     // [K]
     int32_t* st_k;       // [K*T]
@@ -127,8 +168,11 @@ size_t workspace_layout(const Plan& p, int K, int T, char* base, Workspace* w);
 size_t n_edges(const Plan& p);
 int project_blocks(const Plan& p);
 int image_tile_blocks(const Plan& p);
+void bp_tile_lists(const Plan& p, std::vector<int>& off, std::vector<int>& list);
+int sino_blocks(const Plan& p);
 int armijo_blocks(const Plan& p);
 int select_blocks(const Plan& p);
+constexpr int kRmseBlocks = 256;
 
 hipError_t launch_transpose(const float* src, float* dst, int nx, int ny, hipStream_t s);
 hipError_t launch_fill(float* dst, size_t n, float value, hipStream_t s);
@@ -136,21 +180,27 @@ hipError_t launch_project(const Plan& p, const float* x, const float* xT, float 
                           const float* c, float* q, double* partial, hipStream_t s);
 hipError_t launch_backproject(const Plan& p, const float* r, float alpha, float beta, const float* c,
                               float* z, float* zT, double* partial, hipStream_t s);
+hipError_t launch_backproject_interp(const Plan& p, const float* r, float alpha, float beta, const float* c,
+                                     float* z, float* zT, double* partial, hipStream_t s);
 
-// CGLS glue
+hipError_t launch_project_stored(const Plan& p, const float* x, float alpha, float beta, const float* c, float* q,
+                                 double* partial, hipStream_t s);
+hipError_t launch_backproject_stored(const Plan& p, const float* r, float alpha, float beta, const float* c, float* z,
+                                     float* zT, double* partial, hipStream_t s);
+
+// CGLS (App. I): the vector kernels sum the partials of the operator call
+// before them, so no separate scalar kernel is launched.
 hipError_t launch_state_init(DevState* st, uint32_t* hist, uint32_t rank, float sigma_fixed,
                              int zero_iter, hipStream_t s);
-hipError_t launch_cgls_gamma(DevState* st, const double* part, int nparts, int m, hipStream_t s);
-hipError_t launch_cgls_delta(DevState* st, const double* part, int nparts, int m, hipStream_t s);
-hipError_t launch_cgls_axpy(const Plan& p, DevState* st, int m, const float* u_in, float* u,
-                            const float* sdir, float* r, const float* q, double* part_r2, hipStream_t s);
-hipError_t launch_cgls_resid(DevState* st, const double* part, int nparts, hipStream_t s);
-hipError_t launch_cgls_supdate(const Plan& p, DevState* st, int m, const float* z, float* sdir,
-                               float* sdirT, hipStream_t s);
+hipError_t launch_cgls_axpy(const Plan& p, DevState* st, int m, const double* part_bp,
+                            const double* part_proj, const float* u_in, float* u, const float* sdir,
+                            float* r, const float* q, double* part_res, hipStream_t s);
+hipError_t launch_cgls_supdate(const Plan& p, DevState* st, int m, const double* part_bp, const float* z,
+                               float* sdir, float* sdirT, hipStream_t s);
 hipError_t launch_gd_p1(const Plan& p, const float* f, const float* z, float step, float* u,
                         hipStream_t s);
 
-// sigma
+// sigma: three histogram passes, each closed by a one-block kernel
 hipError_t launch_edges_hist(const Plan& p, const float* f, float eps2, uint32_t* keys,
                              uint32_t* hist0, hipStream_t s);
 hipError_t launch_select_hist(const Plan& p, int pass, const uint32_t* keys, const DevState* st,
@@ -159,27 +209,30 @@ hipError_t launch_select_finalize(DevState* st, int pass, uint32_t* hist, float 
                                   hipStream_t s);
 hipError_t launch_sigma_out(const DevState* st, float* out, hipStream_t s);
 
-// P2
-hipError_t launch_tv_grad(const Plan& p, const float* f, const float* v, float lambda,
-                          const DevState* st, float sigma_direct, float eps2, float* g, float* wx,
-                          float* wy, double* part, hipStream_t s);
-hipError_t launch_grad_finalize(DevState* st, const double* part, int nparts, hipStream_t s);
+// P2: direction (optionally applying the previous step first), Armijo
+// candidates, the decision, the final update
+hipError_t launch_tv_vjp(const Plan& p, const float* f, const float* u, float lambda, float sigma, float eps2,
+                         float* e3, float* out, hipStream_t s);
+hipError_t launch_tv_grad(const Plan& p, const float* f, const float* g_prev, const DevState* st_prev,
+                          float* f_out, const float* v, float lambda, const DevState* st,
+                          float sigma_direct, float eps2, float* g, float* wx, float* wy, double* part,
+                          hipStream_t s);
 hipError_t launch_armijo(const Plan& p, int pass, const float* f, const float* g, const float* v,
                          const float* wx, const float* wy, float lambda, float eps2, float t0,
                          float shrink, const DevState* st, double* part, hipStream_t s);
-hipError_t launch_armijo_finalize(DevState* st, const double* part, int nparts, int pass,
-                                  int max_bt, double c, double t0, double shrink, hipStream_t s);
+hipError_t launch_armijo_finalize(const Plan& p, DevState* st, const double* part_grad,
+                                  const double* part_arm, int pass, int max_bt, double c_arm, float t0,
+                                  float shrink, int32_t* st_k, int step, int T, hipStream_t s);
 hipError_t launch_p2_update(const Plan& p, const DevState* st, const float* fcur, const float* g,
-                            float* fout, float* foutT, int clamp, int32_t* st_k, int step,
-                            int T, hipStream_t s);
+                            float* fout, float* foutT, int clamp, hipStream_t s);
 hipError_t launch_copy_clamp(const Plan& p, const float* src, float* dst, float* dstT, int clamp,
                              hipStream_t s);
 
 // bookkeeping
 hipError_t launch_rmse_part(const Plan& p, const float* f, const float* ref, double* part,
                             hipStream_t s);
-hipError_t launch_iter_end(DevState* st, const double* rmse_part, double npix, int with_rmse,
-                           float* st_sigma, int32_t* st_steps, double* st_resid, double* st_rmse,
-                           hipStream_t s);
+hipError_t launch_iter_end(const Plan& p, DevState* st, const double* part_res, int with_resid,
+                           const double* part_rmse, int with_rmse, float* st_sigma, int32_t* st_steps,
+                           double* st_resid, double* st_rmse, hipStream_t s);
 
 }  // namespace eptv

@@ -11,6 +11,9 @@
 #include <string>
 
 #include "eptv_internal.h"
+#include "geometry.h"
+
+#include <vector>
 
 struct eptv_plan_s {
     eptv::Plan p;
@@ -33,85 +36,47 @@ static int hip_fail(hipError_t e, const char* what)
         if (e_ != hipSuccess) return hip_fail(e_, #call); \
     } while (0)
 
-// ------------------------------------------------------------------ geometry
-// Ray (v, b) leaves the source s_v = -SAD (cos theta_v, sin theta_v) along
-// theta_v + beta_b (Sec. 3 scanner; App. III Eq. A6).  Its sweep form is
-// computed in double precision and stored in 32.32 fixed point (see RayTable).
-struct HostRay {
-    long long E0, S;
-    float w32, wfull;
-    bool rows;
-    int k_lo, k_hi;
+// The float32 system matrix of a plan, by ray (CSR): row v*B + b lists the
+// pixels the ray meets with their lengths, in sweep order.
+struct HostCsr {
+    std::vector<long long> rowptr;
+    std::vector<int> col;
+    std::vector<float> val;
 };
 
-static long long to_fixed(double e) { return std::llround(std::ldexp(e, 32)); }
-
-static HostRay make_ray(const Plan& p, double theta, double beta)
+static void build_csr(const Plan& p, HostCsr& m)
 {
-    const double d = p.pixel;
-    const double c = std::cos(theta + beta), s = std::sin(theta + beta);
-    const double sx = -p.sad * std::cos(theta), sy = -p.sad * std::sin(theta);
-    const double x0 = -0.5 * p.nx * d, y0 = -0.5 * p.ny * d;
-    HostRay R;
-    double e0, slope;
-    int ncross, nsweep;
-    if (std::fabs(c) >= std::fabs(s)) {  // swept column by column
-        e0 = (sy + (x0 - sx) * s / c - y0) / d;
-        slope = s / c;
-        R.w32 = s != 0.0 ? (float)std::ldexp(d / std::fabs(s), -32) : 0.0f;
-        R.wfull = (float)(d / std::fabs(c));
-        R.rows = false;
-        ncross = p.ny;
-        nsweep = p.nx;
-    } else {  // swept row by row
-        e0 = (sx + (y0 - sy) * c / s - x0) / d;
-        slope = c / s;
-        R.w32 = c != 0.0 ? (float)std::ldexp(d / std::fabs(c), -32) : 0.0f;
-        R.wfull = (float)(d / std::fabs(s));
-        R.rows = true;
-        ncross = p.nx;
-        nsweep = p.ny;
-    }
-    R.E0 = to_fixed(e0);
-    R.S = to_fixed(slope);
-    // Sweep cells whose entry/exit coordinates can touch [0, ncross), widened
-    // far beyond the fixed-point rounding of e.
-    const double delta = std::ldexp(1.0, -18) * (p.nx + p.ny + 2);
-    if (R.S == 0) {
-        const double e = std::ldexp((double)R.E0, -32);
-        const bool in = e >= -delta && e < ncross + delta;
-        R.k_lo = 0;
-        R.k_hi = in ? nsweep : 0;
-    } else {
-        double ka = (-delta - e0) / slope, kb = (ncross + delta - e0) / slope;
-        double lo = std::floor(std::min(ka, kb)) - 1.0, hi = std::ceil(std::max(ka, kb)) + 1.0;
-        lo = std::min(std::max(lo, 0.0), (double)nsweep);
-        hi = std::min(std::max(hi, 0.0), (double)nsweep);
-        R.k_lo = (int)lo;
-        R.k_hi = std::max((int)hi, R.k_lo);
-    }
-    return R;
+    const int nrow = p.V * p.B;
+    m.rowptr.assign((size_t)nrow + 1, 0);
+    m.col.clear();
+    m.val.clear();
+    for (int v = 0; v < p.V; ++v)
+        for (int b = 0; b < p.B; ++b) {
+            const double beta = ((double)b - 0.5 * (p.B - 1) + p.bin_offset) * p.dbeta;
+            const HostRay R = make_ray(p, p.angles[v], beta);
+            for_each_entry(R, p, [&](long long pix, float c) {
+                m.col.push_back((int)pix);
+                m.val.push_back(c);
+            });
+            m.rowptr[(size_t)v * p.B + b + 1] = (long long)m.col.size();
+        }
 }
 
-// Nonzeros of the float32 matrix, from the same fixed-point cell bounds the
-// kernels use.
-static long long count_nnz(const HostRay& R, const Plan& p)
+static Plan host_plan(const eptv_geometry* g)
 {
-    const int ncross = R.rows ? p.nx : p.ny;
-    long long n = 0;
-    for (int k = R.k_lo; k < R.k_hi; ++k) {
-        const long long ea = R.E0 + (long long)k * R.S, eb = ea + R.S;
-        const long long lo = std::min(ea, eb), hi = std::max(ea, eb);
-        const int m0 = (int)(lo >> 32), m1 = (int)(hi >> 32);
-        const bool in0 = m0 >= 0 && m0 < ncross, in1 = m1 >= 0 && m1 < ncross;
-        if (R.S == 0 || m0 == m1) {
-            n += in0 && (R.S == 0 || hi > lo);
-        } else {
-            n += in0;
-            n += in1 && (unsigned)hi != 0u;
-        }
-    }
-    return n;
+    Plan p;
+    p.nx = g->nx;
+    p.ny = g->ny;
+    p.V = g->n_views;
+    p.B = g->n_bins;
+    p.pixel = g->pixel_mm;
+    p.dbeta = g->dbeta_rad;
+    p.bin_offset = g->bin_offset;
+    p.sad = g->sad_mm;
+    p.sdd = g->sdd_mm;
+    p.angles.resize(p.V);
+    for (int v = 0; v < p.V; ++v) p.angles[v] = g->view_angles_rad ? g->view_angles_rad[v] : 2.0 * M_PI * v / p.V;
+    return p;
 }
 
 static int validate_geometry(const eptv_geometry* g)
@@ -126,7 +91,8 @@ static int validate_geometry(const eptv_geometry* g)
     if (!(g->sad_mm > half_diag * (1.0 + 1e-6)) || !std::isfinite(g->sad_mm)) return EPTV_ERR_GEOMETRY;
     if (!(g->sdd_mm >= g->sad_mm)) return EPTV_ERR_GEOMETRY;
     const double edge = (0.5 * (g->n_bins - 1) + std::fabs(g->bin_offset)) * g->dbeta_rad;
-    if (!(edge < 0.5 * M_PI)) return EPTV_ERR_GEOMETRY;  // every ray must point into the half-plane ahead
+    // every ray, and the angle one bin beyond each detector end, points into the half-plane ahead
+    if (!(edge + g->dbeta_rad < 0.5 * M_PI)) return EPTV_ERR_GEOMETRY;
     if (g->view_angles_rad)
         for (int v = 0; v < g->n_views; ++v)
             if (!std::isfinite(g->view_angles_rad[v])) return EPTV_ERR_GEOMETRY;
@@ -135,18 +101,6 @@ static int validate_geometry(const eptv_geometry* g)
 
 // ------------------------------------------------------------------ workspace
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
-
-static int partial_count(const Plan& p)
-{
-    const int img = image_tile_blocks(p);
-    int n = project_blocks(p);
-    n = std::max(n, img);
-    n = std::max(n, 2 * img);
-    n = std::max(n, kArmijoCand * armijo_blocks(p));
-    n = std::max(n, (int)(((size_t)p.V * p.B + 1023) / 1024));
-    n = std::max(n, 256);
-    return n;
-}
 
 size_t workspace_layout(const Plan& p, int K, int T, char* base, Workspace* w)
 {
@@ -166,13 +120,22 @@ size_t workspace_layout(const Plan& p, int K, int T, char* base, Workspace* w)
     W.sT = (float*)take(ni * 4);
     W.z = (float*)take(ni * 4);
     W.g = (float*)take(ni * 4);
+    W.g2 = (float*)take(ni * 4);
+    W.f1 = (float*)take(ni * 4);
+    W.f2 = (float*)take(ni * 4);
     W.wx = (float*)take((size_t)p.ny * (p.nx + 1) * 4);
     W.wy = (float*)take((size_t)(p.ny + 1) * p.nx * 4);
     W.r = (float*)take(ns * 4);
     W.q = (float*)take(ns * 4);
     W.keys = (uint32_t*)take(n_edges(p) * 4);
+    W.edge3 = (float*)take(3 * n_edges(p) * 4);
     W.hist = (uint32_t*)take(3 * kSelectBins * 4);
-    W.part = (double*)take((size_t)partial_count(p) * 8);
+    W.part_proj = (double*)take((size_t)project_blocks(p) * 8);
+    W.part_bp = (double*)take((size_t)image_tile_blocks(p) * 8);
+    W.part_grad = (double*)take((size_t)armijo_blocks(p) * 2 * 8);
+    W.part_arm = (double*)take((size_t)armijo_blocks(p) * kArmijoSlots * 8);
+    W.part_res = (double*)take((size_t)sino_blocks(p) * 8);
+    W.part_rmse = (double*)take((size_t)kRmseBlocks * 8);
     W.st = (DevState*)take(sizeof(DevState));
     W.st_sigma = (float*)take(kcap * 4);
     W.st_k = (int32_t*)take(ktcap * 4);
@@ -195,6 +158,8 @@ static int check_params(const eptv_params* q)
                             q->armijo_max_backtracks > 4096 || !(q->armijo_c >= 0)))
         return EPTV_ERR_ARG;
     if ((long long)q->outer_iters * q->tv_iters > (1LL << 28)) return EPTV_ERR_ARG;
+    if ((q->stored_matrix != 0 && q->stored_matrix != 1) || (q->interp_bp != 0 && q->interp_bp != 1))
+        return EPTV_ERR_ARG;
     return EPTV_OK;
 }
 
@@ -235,29 +200,45 @@ static hipError_t enqueue_select(const Plan& p, Workspace& W, const float* img, 
     return hipSuccess;
 }
 
-// One P2 descent step from fcur into fout (Sec. 2.2; Armijo line search).
-static hipError_t enqueue_gd_step(const Plan& p, Workspace& W, const eptv_params& q, const float* fcur,
-                                  const float* v, float* fout, float* foutT, int clamp, int step, int T,
-                                  int32_t* st_k, hipStream_t s)
+static int armijo_passes(int max_bt)
+{
+    const int rest = std::max(0, max_bt + 1 - kArmijoFirst);
+    return 1 + (rest + kArmijoMore - 1) / kArmijoMore;
+}
+
+// n_steps P2 descent steps (Sec. 2.2; Armijo line search) from `start`
+// towards v; the result goes to `fout` (and its transpose to foutT when
+// given), truncated at zero when `clamp`.  Step t > 0 applies step t-1 inside
+// its gradient kernel, so only the last step has an update kernel of its own.
+static hipError_t enqueue_p2(const Plan& p, Workspace& W, const eptv_params& q, const float* start, const float* v,
+                             int n_steps, float* fout, float* foutT, int clamp, int32_t* st_k, hipStream_t s)
 {
     hipError_t e;
     const float eps2 = (float)(q.tv_eps * q.tv_eps);
-    const int nb = armijo_blocks(p);
-    if ((e = launch_tv_grad(p, fcur, v, (float)q.lambda, W.st, 0.0f, eps2, W.g, W.wx, W.wy, W.part, s)) !=
-        hipSuccess)
-        return e;
-    if ((e = launch_grad_finalize(W.st, W.part, nb, s)) != hipSuccess) return e;
-    const int npass = (q.armijo_max_backtracks + kArmijoCand) / kArmijoCand;
-    const float t0 = t0_of(q);
-    for (int pass = 0; pass < npass; ++pass) {
-        if ((e = launch_armijo(p, pass, fcur, W.g, v, W.wx, W.wy, (float)q.lambda, eps2, t0, (float)q.armijo_shrink,
-                               W.st, W.part, s)) != hipSuccess)
+    const float t0 = t0_of(q), shrink = (float)q.armijo_shrink;
+    const int npass = armijo_passes(q.armijo_max_backtracks);
+    const float* fcur = start;
+    float* gbuf[2] = {W.g, W.g2};
+    float* fbuf[2] = {W.f1, W.f2};
+    for (int t = 0; t < n_steps; ++t) {
+        float* g = gbuf[t & 1];
+        const float* gprev = t > 0 ? gbuf[(t - 1) & 1] : nullptr;
+        float* fnext = t > 0 ? fbuf[t & 1] : nullptr;
+        if ((e = launch_tv_grad(p, fcur, gprev, W.st, fnext, v, (float)q.lambda, W.st, 0.0f, eps2, g, W.wx, W.wy,
+                                W.part_grad, s)) != hipSuccess)
             return e;
-        if ((e = launch_armijo_finalize(W.st, W.part, nb, pass, q.armijo_max_backtracks, q.armijo_c, t0,
-                                        q.armijo_shrink, s)) != hipSuccess)
-            return e;
+        if (t > 0) fcur = fnext;
+        for (int pass = 0; pass < npass; ++pass) {
+            if ((e = launch_armijo(p, pass, fcur, g, v, W.wx, W.wy, (float)q.lambda, eps2, t0, shrink, W.st,
+                                   W.part_arm, s)) != hipSuccess)
+                return e;
+            if ((e = launch_armijo_finalize(p, W.st, W.part_grad, W.part_arm, pass, q.armijo_max_backtracks,
+                                            q.armijo_c, t0, shrink, st_k, t, n_steps, s)) != hipSuccess)
+                return e;
+        }
     }
-    return launch_p2_update(p, W.st, fcur, W.g, fout, foutT, clamp, st_k, step, T, s);
+    if (n_steps == 0) return launch_copy_clamp(p, start, fout, foutT, clamp, s);
+    return launch_p2_update(p, W.st, fcur, gbuf[(n_steps - 1) & 1], fout, foutT, clamp, s);
 }
 
 // One outer iteration of the EPTV algorithm (Sec. 2.2), entirely on `s`.
@@ -273,32 +254,36 @@ static hipError_t enqueue_iteration(const Ctx& c, hipStream_t s)
                                0, s)) != hipSuccess)
         return e;
     // Step 1: P1.  r = y - P f
-    if ((e = launch_project(p, c.f, W.fT, -1.0f, 1.0f, c.y, W.r, nullptr, s)) != hipSuccess) return e;
+    // P and P^T: on the fly, or from the stored matrix (the paper's two strategies, Sec. 2.3)
+    auto proj = [&](const float* x, const float* xT, float al, float be, const float* cc, float* out, double* part) {
+        return q.stored_matrix ? launch_project_stored(p, x, al, be, cc, out, part, s)
+                               : launch_project(p, x, xT, al, be, cc, out, part, s);
+    };
+    // P^T: the exact transpose (on the fly or stored), or the Eq. 11 operator
+    auto bproj = [&](const float* rr, float al, float be, const float* cc, float* zz, float* zzT, double* part) {
+        if (q.interp_bp) return launch_backproject_interp(p, rr, al, be, cc, zz, zzT, part, s);
+        return q.stored_matrix ? launch_backproject_stored(p, rr, al, be, cc, zz, zzT, part, s)
+                               : launch_backproject(p, rr, al, be, cc, zz, zzT, part, s);
+    };
+    if ((e = proj(c.f, W.fT, -1.0f, 1.0f, c.y, W.r, nullptr)) != hipSuccess) return e;
     if (M > 0) {
-        const int nbp = image_tile_blocks(p), npj = project_blocks(p);
-        // s = P^T r, gamma_0
-        if ((e = launch_backproject(p, W.r, 1.0f, 0.0f, nullptr, W.s, W.sT, W.part, s)) != hipSuccess) return e;
-        if ((e = launch_cgls_gamma(W.st, W.part, nbp, 0, s)) != hipSuccess) return e;
+        // s = P^T r (gamma_0 partials)
+        if ((e = bproj(W.r, 1.0f, 0.0f, nullptr, W.s, W.sT, W.part_bp)) != hipSuccess) return e;
         for (int m = 0; m < M; ++m) {
             const bool last = m == M - 1;
-            if ((e = launch_project(p, W.s, W.sT, 1.0f, 0.0f, nullptr, W.q, W.part, s)) != hipSuccess) return e;
-            if ((e = launch_cgls_delta(W.st, W.part, npj, m, s)) != hipSuccess) return e;
-            if ((e = launch_cgls_axpy(p, W.st, m, m == 0 ? c.f : W.u, W.u, W.s, W.r, W.q, last ? W.part : nullptr,
-                                      s)) != hipSuccess)
+            // q = P s (delta_m partials); u += a_m s, r -= a_m q
+            if ((e = proj(W.s, W.sT, 1.0f, 0.0f, nullptr, W.q, W.part_proj)) != hipSuccess) return e;
+            if ((e = launch_cgls_axpy(p, W.st, m, W.part_bp, W.part_proj, m == 0 ? c.f : W.u, W.u, W.s, W.r, W.q,
+                                      last ? W.part_res : nullptr, s)) != hipSuccess)
                 return e;
-            if (last) {
-                const int nsb = (int)(((size_t)p.V * p.B + 1023) / 1024);
-                if ((e = launch_cgls_resid(W.st, W.part, nsb, s)) != hipSuccess) return e;
-                break;  // P^T r of the final residual is not needed
-            }
-            if ((e = launch_backproject(p, W.r, 1.0f, 0.0f, nullptr, W.z, nullptr, W.part, s)) != hipSuccess)
-                return e;
-            if ((e = launch_cgls_gamma(W.st, W.part, nbp, m + 1, s)) != hipSuccess) return e;
-            if ((e = launch_cgls_supdate(p, W.st, m, W.z, W.s, W.sT, s)) != hipSuccess) return e;
+            if (last) break;  // P^T r of the final residual is not needed
+            // z = P^T r (gamma_{m+1} partials); s = z + b_m s
+            if ((e = bproj(W.r, 1.0f, 0.0f, nullptr, W.z, nullptr, W.part_bp)) != hipSuccess) return e;
+            if ((e = launch_cgls_supdate(p, W.st, m, W.part_bp, W.z, W.s, W.sT, s)) != hipSuccess) return e;
         }
     } else {
         // gradient form of Eq. 8: v = f - mu/lambda P^T (P f - y)
-        if ((e = launch_backproject(p, W.r, 1.0f, 0.0f, nullptr, W.z, nullptr, nullptr, s)) != hipSuccess) return e;
+        if ((e = bproj(W.r, 1.0f, 0.0f, nullptr, W.z, nullptr, nullptr)) != hipSuccess) return e;
         if ((e = launch_gd_p1(p, c.f, W.z, (float)(q.mu / q.lambda), W.u, s)) != hipSuccess) return e;
     }
     // Step 2: P2 from v (or f^(k)), sigma chosen once from the start image.
@@ -307,20 +292,12 @@ static hipError_t enqueue_iteration(const Ctx& c, hipStream_t s)
         if ((e = enqueue_select(p, W, start, (float)(q.tv_eps * q.tv_eps), (float)q.sigma_floor, s)) != hipSuccess)
             return e;
     }
-    if (T == 0) {
-        if ((e = launch_copy_clamp(p, start, c.f, W.fT, q.positivity, s)) != hipSuccess) return e;
-    }
-    for (int t = 0; t < T; ++t) {
-        const bool last = t == T - 1;
-        // Step 3 (positivity) is fused into the last descent update.
-        if ((e = enqueue_gd_step(p, W, q, t == 0 ? start : c.f, W.u, c.f, last ? W.fT : nullptr,
-                                 last && q.positivity, t, T, W.st_k, s)) != hipSuccess)
-            return e;
-    }
+    // Step 3 (positivity) is fused into the last descent update.
+    if ((e = enqueue_p2(p, W, q, start, W.u, T, c.f, W.fT, q.positivity, W.st_k, s)) != hipSuccess) return e;
     if (c.f_ref) {
-        if ((e = launch_rmse_part(p, c.f, c.f_ref, W.part, s)) != hipSuccess) return e;
+        if ((e = launch_rmse_part(p, c.f, c.f_ref, W.part_rmse, s)) != hipSuccess) return e;
     }
-    return launch_iter_end(W.st, W.part, (double)p.nx * p.ny, c.f_ref != nullptr, W.st_sigma, W.st_steps,
+    return launch_iter_end(p, W.st, W.part_res, M > 0, W.part_rmse, c.f_ref != nullptr, W.st_sigma, W.st_steps,
                            W.st_resid, W.st_rmse, s);
 }
 
@@ -361,21 +338,9 @@ int eptv_plan_create(const eptv_geometry* geom, eptv_plan* out)
     eptv_plan h = new (std::nothrow) eptv_plan_s();
     if (!h) return EPTV_ERR_ARG;
     Plan& p = h->p;
-    p.nx = geom->nx;
-    p.ny = geom->ny;
-    p.V = geom->n_views;
-    p.B = geom->n_bins;
-    p.pixel = geom->pixel_mm;
-    p.dbeta = geom->dbeta_rad;
-    p.bin_offset = geom->bin_offset;
-    p.sad = geom->sad_mm;
-    p.sdd = geom->sdd_mm;
-    p.angles.resize(p.V);
-    for (int v = 0; v < p.V; ++v)
-        p.angles[v] = geom->view_angles_rad ? geom->view_angles_rad[v] : 2.0 * M_PI * v / p.V;
+    p = host_plan(geom);
 
-    std::vector<longlong2> fx((size_t)p.V * p.B);
-    std::vector<float2> wt((size_t)p.V * p.B);
+    std::vector<RayFx> ray((size_t)p.V * p.B);
     std::vector<int2> range((size_t)p.V * p.B);
     std::vector<float2> view(p.V);
     long long nnz = 0;
@@ -385,24 +350,40 @@ int eptv_plan_create(const eptv_geometry* geom, eptv_plan* out)
             const double beta = ((double)b - 0.5 * (p.B - 1) + p.bin_offset) * p.dbeta;
             const HostRay R = make_ray(p, p.angles[v], beta);
             const size_t id = (size_t)v * p.B + b;
-            fx[id].x = R.E0;
-            fx[id].y = R.S;
-            wt[id] = make_float2(R.w32, R.rows ? -R.wfull : R.wfull);
+            ray[id] = R.fx();
             range[id] = make_int2(R.k_lo, R.k_hi);
-            nnz += count_nnz(R, p);
+            for_each_entry(R, p, [&](long long, float) { ++nnz; });
         }
     }
     p.nnz = nnz;
+    std::vector<int> list_off, list;
+    bp_tile_lists(p, list_off, list);
+    std::vector<double2> view_d(p.V);
+    for (int v = 0; v < p.V; ++v) view_d[v] = make_double2(std::cos(p.angles[v]), std::sin(p.angles[v]));
+    std::vector<double> tau(p.B + 2);
+    for (int b = -1; b <= p.B; ++b) {
+        const double beta = ((double)b - 0.5 * (p.B - 1) + p.bin_offset) * p.dbeta;
+        tau[b + 1] = std::tan(beta);  // |beta| < pi/2 by the geometry check
+    }
     hipError_t e = hipGetDevice(&p.device);
-    if (e == hipSuccess) e = hipMalloc(&p.rays.d_fx, fx.size() * sizeof(longlong2));
-    if (e == hipSuccess) e = hipMalloc(&p.rays.d_w, wt.size() * sizeof(float2));
+    if (e == hipSuccess) e = hipMalloc(&p.rays.d_ray, ray.size() * sizeof(RayFx));
     if (e == hipSuccess) e = hipMalloc(&p.rays.d_range, range.size() * sizeof(int2));
     if (e == hipSuccess) e = hipMalloc(&p.rays.d_view, view.size() * sizeof(float2));
-    if (e == hipSuccess) e = hipMemcpy(p.rays.d_fx, fx.data(), fx.size() * sizeof(longlong2), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(p.rays.d_w, wt.data(), wt.size() * sizeof(float2), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p.rays.d_ray, ray.data(), ray.size() * sizeof(RayFx), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(p.rays.d_range, range.data(), range.size() * sizeof(int2), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(p.rays.d_view, view.data(), view.size() * sizeof(float2), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&p.rays.d_view_d, view_d.size() * sizeof(double2));
+    if (e == hipSuccess)
+        e = hipMemcpy(p.rays.d_view_d, view_d.data(), view_d.size() * sizeof(double2), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&p.rays.d_tau, tau.size() * sizeof(double));
+    if (e == hipSuccess) e = hipMemcpy(p.rays.d_tau, tau.data(), tau.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&p.rays.d_list_off, list_off.size() * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&p.rays.d_list, std::max<size_t>(list.size(), 1) * sizeof(int));
+    if (e == hipSuccess)
+        e = hipMemcpy(p.rays.d_list_off, list_off.data(), list_off.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !list.empty())
+        e = hipMemcpy(p.rays.d_list, list.data(), list.size() * sizeof(int), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&p.cap_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         rc = hip_fail(e, "eptv_plan_create");
@@ -419,10 +400,19 @@ int eptv_plan_destroy(eptv_plan h)
     Plan& p = h->p;
     if (p.gexec) hipGraphExecDestroy(p.gexec);
     if (p.cap_stream) hipStreamDestroy(p.cap_stream);
-    if (p.rays.d_fx) hipFree(p.rays.d_fx);
-    if (p.rays.d_w) hipFree(p.rays.d_w);
+    if (p.rays.d_ray) hipFree(p.rays.d_ray);
+    if (p.mat.d_rowptr) hipFree(p.mat.d_rowptr);
+    if (p.mat.d_col) hipFree(p.mat.d_col);
+    if (p.mat.d_val) hipFree(p.mat.d_val);
+    if (p.mat.d_colptr) hipFree(p.mat.d_colptr);
+    if (p.mat.d_row) hipFree(p.mat.d_row);
+    if (p.mat.d_cval) hipFree(p.mat.d_cval);
     if (p.rays.d_range) hipFree(p.rays.d_range);
     if (p.rays.d_view) hipFree(p.rays.d_view);
+    if (p.rays.d_view_d) hipFree(p.rays.d_view_d);
+    if (p.rays.d_tau) hipFree(p.rays.d_tau);
+    if (p.rays.d_list_off) hipFree(p.rays.d_list_off);
+    if (p.rays.d_list) hipFree(p.rays.d_list);
     delete h;
     return EPTV_OK;
 }
@@ -431,6 +421,85 @@ int eptv_plan_nnz(eptv_plan h, long long* nnz)
 {
     if (!h || !nnz) return EPTV_ERR_ARG;
     *nnz = h->p.nnz;
+    return EPTV_OK;
+}
+
+int eptv_geometry_matrix(const eptv_geometry* geom, long long* nnz, long long* rowptr, int* col, float* val)
+{
+    if (!nnz) return EPTV_ERR_ARG;
+    const int rc = validate_geometry(geom);
+    if (rc != EPTV_OK) return rc;
+    const Plan p = host_plan(geom);
+    HostCsr m;
+    build_csr(p, m);
+    *nnz = (long long)m.col.size();
+    if (rowptr) std::memcpy(rowptr, m.rowptr.data(), m.rowptr.size() * sizeof(long long));
+    if (col) std::memcpy(col, m.col.data(), m.col.size() * sizeof(int));
+    if (val) std::memcpy(val, m.val.data(), m.val.size() * sizeof(float));
+    return EPTV_OK;
+}
+
+int eptv_plan_store_matrix(eptv_plan h, size_t* device_bytes)
+{
+    if (!h) return EPTV_ERR_ARG;
+    Plan& p = h->p;
+    if (!p.mat.d_rowptr) {
+        HostCsr m;
+        build_csr(p, m);
+        const long long nnz = (long long)m.col.size();
+        if (nnz >= (1LL << 31) || (long long)p.nx * p.ny >= (1LL << 31)) return EPTV_ERR_ARG;
+        const int nrow = p.V * p.B, npix = p.nx * p.ny;
+        std::vector<int> rowptr(m.rowptr.begin(), m.rowptr.end());
+        // the same entries grouped by pixel, rays ascending
+        std::vector<int> colptr((size_t)npix + 1, 0), rowi((size_t)nnz);
+        std::vector<float> cval((size_t)nnz);
+        for (long long e = 0; e < nnz; ++e) colptr[(size_t)m.col[e] + 1]++;
+        for (int c = 0; c < npix; ++c) colptr[(size_t)c + 1] += colptr[c];
+        std::vector<int> fill(colptr.begin(), colptr.end() - 1);
+        for (int r = 0; r < nrow; ++r)
+            for (long long e = m.rowptr[r]; e < m.rowptr[r + 1]; ++e) {
+                const int at = fill[m.col[e]]++;
+                rowi[at] = r;
+                cval[at] = m.val[e];
+            }
+        StoredMatrix& S = p.mat;
+        hipError_t e = hipMalloc(&S.d_rowptr, rowptr.size() * 4);
+        if (e == hipSuccess) e = hipMalloc(&S.d_col, (size_t)nnz * 4);
+        if (e == hipSuccess) e = hipMalloc(&S.d_val, (size_t)nnz * 4);
+        if (e == hipSuccess) e = hipMalloc(&S.d_colptr, colptr.size() * 4);
+        if (e == hipSuccess) e = hipMalloc(&S.d_row, (size_t)nnz * 4);
+        if (e == hipSuccess) e = hipMalloc(&S.d_cval, (size_t)nnz * 4);
+        if (e == hipSuccess) e = hipMemcpy(S.d_rowptr, rowptr.data(), rowptr.size() * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(S.d_col, m.col.data(), (size_t)nnz * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(S.d_val, m.val.data(), (size_t)nnz * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(S.d_colptr, colptr.data(), colptr.size() * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(S.d_row, rowi.data(), (size_t)nnz * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(S.d_cval, cval.data(), (size_t)nnz * 4, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            for (void* ptr : {(void*)S.d_rowptr, (void*)S.d_col, (void*)S.d_val, (void*)S.d_colptr, (void*)S.d_row,
+                              (void*)S.d_cval})
+                if (ptr) hipFree(ptr);
+            S = StoredMatrix();
+            return hip_fail(e, "eptv_plan_store_matrix");
+        }
+        S.nnz = nnz;
+        S.bytes = (rowptr.size() + colptr.size()) * 4 + (size_t)nnz * 16;
+    }
+    if (device_bytes) *device_bytes = p.mat.bytes;
+    return EPTV_OK;
+}
+
+int eptv_project_stored(eptv_plan h, const float* x, float* q, float alpha, float beta, void* stream)
+{
+    if (!h || !x || !q || !h->p.mat.d_rowptr) return EPTV_ERR_ARG;
+    EPTV_HIP(launch_project_stored(h->p, x, alpha, beta, q, q, nullptr, (hipStream_t)stream));
+    return EPTV_OK;
+}
+
+int eptv_backproject_stored(eptv_plan h, const float* r, float* z, float alpha, float beta, void* stream)
+{
+    if (!h || !r || !z || !h->p.mat.d_rowptr) return EPTV_ERR_ARG;
+    EPTV_HIP(launch_backproject_stored(h->p, r, alpha, beta, z, z, nullptr, nullptr, (hipStream_t)stream));
     return EPTV_OK;
 }
 
@@ -486,6 +555,13 @@ int eptv_backproject(eptv_plan h, const float* r, float* z, float alpha, float b
     return EPTV_OK;
 }
 
+int eptv_backproject_interp(eptv_plan h, const float* r, float* z, float alpha, float beta, void* stream)
+{
+    if (!h || !r || !z) return EPTV_ERR_ARG;
+    EPTV_HIP(launch_backproject_interp(h->p, r, alpha, beta, z, z, nullptr, nullptr, (hipStream_t)stream));
+    return EPTV_OK;
+}
+
 int eptv_tv_gradient(eptv_plan h, const float* f, const float* v, float lambda, float sigma, float tv_eps, float* g,
                      float* wx, float* wy, void* ws, size_t ws_bytes, void* stream)
 {
@@ -494,8 +570,20 @@ int eptv_tv_gradient(eptv_plan h, const float* f, const float* v, float lambda, 
     Workspace W;
     int rc = bind_ws(h->p, 1, 0, ws, ws_bytes, &W);
     if (rc != EPTV_OK) return rc;
-    EPTV_HIP(launch_tv_grad(h->p, f, v, lambda, nullptr, sigma, tv_eps * tv_eps, g, wx, wy, nullptr,
-                            (hipStream_t)stream));
+    EPTV_HIP(launch_tv_grad(h->p, f, nullptr, nullptr, nullptr, v, lambda, nullptr, sigma, tv_eps * tv_eps, g, wx, wy,
+                            nullptr, (hipStream_t)stream));
+    return EPTV_OK;
+}
+
+int eptv_tv_gradient_vjp(eptv_plan h, const float* f, const float* u, float lambda, float sigma, float tv_eps,
+                         float* out, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!h || !f || !u || !out) return EPTV_ERR_ARG;
+    if (!(sigma > 0) || !(tv_eps > 0) || !std::isfinite(tv_eps) || !std::isfinite(lambda)) return EPTV_ERR_ARG;
+    Workspace W;
+    int rc = bind_ws(h->p, 1, 0, ws, ws_bytes, &W);
+    if (rc != EPTV_OK) return rc;
+    EPTV_HIP(launch_tv_vjp(h->p, f, u, lambda, sigma, tv_eps * tv_eps, W.edge3, out, (hipStream_t)stream));
     return EPTV_OK;
 }
 
@@ -529,8 +617,7 @@ int eptv_tv_step(eptv_plan h, const eptv_params* q, float* f, const float* v, fl
     const Plan& p = h->p;
     EPTV_HIP(launch_state_init(W.st, W.hist, select_rank(p, q->edge_quantile), sigma < 0 ? -1.0f : sigma, 1, s));
     if (sigma < 0) EPTV_HIP(enqueue_select(p, W, f, (float)(q->tv_eps * q->tv_eps), (float)q->sigma_floor, s));
-    for (int t = 0; t < n_steps; ++t)
-        EPTV_HIP(enqueue_gd_step(p, W, *q, f, v, f, nullptr, 0, t, n_steps, W.st_k, s));
+    EPTV_HIP(enqueue_p2(p, W, *q, f, v, n_steps, f, nullptr, 0, W.st_k, s));
     if (stats) {
         if (stats->sigma) EPTV_HIP(hipMemcpyAsync(stats->sigma, &W.st->sigma, 4, hipMemcpyDeviceToHost, s));
         if (stats->armijo_k && n_steps > 0)
@@ -547,6 +634,7 @@ int eptv_reconstruct(eptv_plan h, const eptv_params* q, const float* y, float* f
     int rc = check_params(q);
     if (rc != EPTV_OK) return rc;
     Plan& p = h->p;
+    if (q->stored_matrix && !p.mat.d_rowptr) return EPTV_ERR_ARG;
     Workspace W;
     rc = bind_ws(p, q->outer_iters, q->tv_iters, ws, ws_bytes, &W);
     if (rc != EPTV_OK) return rc;

@@ -5,7 +5,8 @@
 // consecutive detector bins of one view, so the output row q[v][b..b+63] is
 // written with one coalesced store.  Each ray is swept along its dominant axis
 // (see RayTable); the sweep is split into NSEG segments handled by the waves of
-// a block and summed in LDS in a fixed order.  Rays swept column by column read
+// a block and summed in LDS in a fixed order, and each wave evaluates four
+// sweep cells at a time without branches so their loads are in flight together.  Rays swept column by column read
 // the transposed image, so the 64 lanes of a wave, which sit in neighbouring
 // rows of one column, touch contiguous memory in both sweep directions.
 //
@@ -21,9 +22,34 @@
 namespace eptv {
 
 // ------------------------------------------------------------------ projector
+#ifndef EPTV_PROJ_SEG
+#define EPTV_PROJ_SEG 16
+#endif
+constexpr int kProjSeg = EPTV_PROJ_SEG;  // sweep segments (waves) per block of 64 rays
+constexpr int kProjUnroll = 4;           // sweep cells whose loads are issued together
+
+// Contribution of one sweep cell: the (at most two) pixels the ray crosses in
+// it, with out-of-image cells weighted 0 and their loads pointed at cell 0.
+struct CellTap {
+    int i0, i1;
+    float a0, a1;
+};
+
+__device__ __forceinline__ CellTap cell_tap(long long lo, const RayFx& R, float wfull, int ncross)
+{
+    const CellW w = cell_weights(lo, R.span, R.w32, wfull);
+    const bool in0 = (unsigned)w.m0 < (unsigned)ncross;
+    const bool in1 = (unsigned)(w.m0 + 1) < (unsigned)ncross;
+    CellTap t;
+    t.i0 = in0 ? w.m0 : 0;
+    t.i1 = in1 ? w.m0 + 1 : 0;
+    t.a0 = in0 ? w.c0 : 0.0f;
+    t.a1 = in1 ? w.c1 : 0.0f;
+    return t;
+}
+
 template <int NSEG>
-__global__ __launch_bounds__(64 * NSEG) void k_project(const longlong2* __restrict__ fx,
-                                                       const float2* __restrict__ wt,
+__global__ __launch_bounds__(64 * NSEG) void k_project(const RayFx* __restrict__ rays,
                                                        const int2* __restrict__ range,
                                                        const float* __restrict__ x,
                                                        const float* __restrict__ xT, int nx, int ny,
@@ -34,41 +60,50 @@ __global__ __launch_bounds__(64 * NSEG) void k_project(const longlong2* __restri
     __shared__ double lds[1];
     const int lane = threadIdx.x & 63, seg = threadIdx.x >> 6;
     const int b = blockIdx.x * 64 + lane, v = blockIdx.y;
-    float acc = 0.0f;
+    float acc = 0.0f, acc1 = 0.0f;
     if (b < B) {
         const int id = v * B + b;
-        const longlong2 FX = fx[id];
-        const float2 W = wt[id];
+        const RayFx R = rays[id];
         const int2 K = range[id];
-        const bool rows = W.y < 0.0f;  // swept row by row: cells are columns of x
-        const float wfull = fabsf(W.y), w32 = W.x;
-        const long long S = FX.y;
+        const bool rows = R.wfull < 0.0f;  // swept row by row: cells are rows of x
+        const float wfull = fabsf(R.wfull);
         const float* img = rows ? x : xT;
         const int ncross = rows ? nx : ny;
         const int len = K.y - K.x;
         const int k0 = K.x + (int)(((long long)len * seg) / NSEG);
         const int k1 = K.x + (int)(((long long)len * (seg + 1)) / NSEG);
-        long long E = FX.x + (long long)k0 * S;
-        for (int k = k0; k < k1; ++k) {
-            const long long En = E + S;
-            const long long lo = S >= 0 ? E : En, hi = S >= 0 ? En : E;
-            const int m0 = (int)(lo >> 32), m1 = (int)(hi >> 32);
-            const float* line = img + (size_t)k * ncross;
-            if (S == 0) {
-                if (m0 >= 0 && m0 < ncross) acc = fmaf(wfull, line[m0], acc);
-            } else {
-                const unsigned flo = (unsigned)lo, fhi = (unsigned)hi;
-                if (m0 == m1) {
-                    if (m0 >= 0 && m0 < ncross) acc = fmaf((float)(fhi - flo) * w32, line[m0], acc);
-                } else {
-                    if (m0 >= 0 && m0 < ncross) acc = fmaf((4294967296.0f - (float)flo) * w32, line[m0], acc);
-                    if (fhi != 0u && m1 >= 0 && m1 < ncross) acc = fmaf((float)fhi * w32, line[m1], acc);
-                }
+        long long lo = R.lo0 + (long long)k0 * R.step;
+        const float* line = img + (size_t)k0 * ncross;
+        int k = k0;
+        for (; k + kProjUnroll <= k1; k += kProjUnroll) {
+            CellTap t[kProjUnroll];
+#pragma unroll
+            for (int u = 0; u < kProjUnroll; ++u) {
+                t[u] = cell_tap(lo, R, wfull, ncross);
+                lo += R.step;
             }
-            E = En;
+            float p0[kProjUnroll], p1[kProjUnroll];
+#pragma unroll
+            for (int u = 0; u < kProjUnroll; ++u) {
+                p0[u] = line[u * ncross + t[u].i0];
+                p1[u] = line[u * ncross + t[u].i1];
+            }
+#pragma unroll
+            for (int u = 0; u < kProjUnroll; ++u) {
+                acc = fmaf(t[u].a0, p0[u], acc);
+                acc1 = fmaf(t[u].a1, p1[u], acc1);
+            }
+            line += (size_t)kProjUnroll * ncross;
+        }
+        for (; k < k1; ++k) {
+            const CellTap t = cell_tap(lo, R, wfull, ncross);
+            acc = fmaf(t.a0, line[t.i0], acc);
+            acc1 = fmaf(t.a1, line[t.i1], acc1);
+            lo += R.step;
+            line += ncross;
         }
     }
-    red[seg][lane] = acc;
+    red[seg][lane] = acc + acc1;
     __syncthreads();
     if (seg == 0) {
         float out = 0.0f;
@@ -92,38 +127,219 @@ __global__ __launch_bounds__(64 * NSEG) void k_project(const longlong2* __restri
     }
 }
 
-constexpr int kProjSeg = 8;
-
 int project_blocks(const Plan& p) { return ((p.B + 63) / 64) * p.V; }
 
 hipError_t launch_project(const Plan& p, const float* x, const float* xT, float alpha, float beta,
                           const float* c, float* q, double* partial, hipStream_t s)
 {
     dim3 grid((p.B + 63) / 64, p.V);
-    hipLaunchKernelGGL(k_project<kProjSeg>, grid, dim3(64 * kProjSeg), 0, s, p.rays.d_fx, p.rays.d_w,
-                       p.rays.d_range, x, xT, p.nx, p.ny, p.B, alpha, beta, c, q, partial);
+    hipLaunchKernelGGL(k_project<kProjSeg>, grid, dim3(64 * kProjSeg), 0, s, p.rays.d_ray, p.rays.d_range, x, xT,
+                       p.nx, p.ny, p.B, alpha, beta, c, q, partial);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ backprojector
-struct BpConst {
-    float pixel;      // d
-    float sad;
-    float inv_dbeta;
-    float bin_c;      // (B-1)/2 - bin_offset: bin coordinate of beta = 0
-    float rad;        // d / sqrt(2): radius of the circle around a pixel
-    float margin;     // extra bins on each side (rounding of the bin search)
-};
-
 constexpr int kTile = 16;
 
-__global__ __launch_bounds__(256) void k_backproject(const longlong2* __restrict__ fx,
-                                                     const float2* __restrict__ wt,
-                                                     const float2* __restrict__ view,
+// lo0 + ks * step for 0 <= ks < 2^15 and |step| <= 2^32: the low word of step
+// in one 32x32->64 multiply-add, its high word (-1, 0 or 1) in a 24-bit one.
+__device__ __forceinline__ long long cell_lo(const RayFx& R, int ks)
+{
+    const unsigned long long prod =
+        (unsigned long long)(unsigned)ks * (unsigned)(unsigned long long)R.step + (unsigned long long)R.lo0;
+    const int hi = (int)(prod >> 32) + __mul24(ks, (int)(R.step >> 32));
+    return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)prod);
+}
+
+// P^T r, exact transpose of k_project, computed tile by tile without write
+// conflicts (the concern of Sec. 2.3) and without per-pixel arctangents.
+// A block owns a 16x16 pixel tile.  The host lists, per tile, every ray that
+// can meet it (views ascending, bins ascending); the block stages them in LDS
+// in chunks and walks each through the tile's 16 sweep lines: thread
+// (line, group) evaluates the ray's one or two cells on its sweep line with
+// the projector's own fixed-point arithmetic (cell_weights) and adds c * r to
+// the group's private accumulator tile.  The 16 lanes of a group take the
+// same ray at the same time, and a ray's sweep lines own distinct pixels, so
+// no two lanes ever update one accumulator entry; the per-pixel order (rays
+// in list order, then the 16 groups in order) is fixed, so results are
+// deterministic.
+constexpr int kBpGroups = 16;
+constexpr int kBpChunk = 256;
+
+struct BpEntry {
+    RayFx ray;
+    int2 range;
+    float r;
+    float pad;
+};
+
+__global__ __launch_bounds__(256) void k_backproject(const RayFx* __restrict__ rays,
+                                                     const int2* __restrict__ range,
+                                                     const int* __restrict__ list_off,
+                                                     const int* __restrict__ list,
                                                      const float* __restrict__ r, int nx, int ny,
-                                                     int V, int B, BpConst k, float alpha,
-                                                     float beta, const float* c, float* z,
+                                                     float alpha, float beta, const float* c, float* z,
                                                      float* zT, double* partial)
+{
+    __shared__ BpEntry ent[kBpChunk];
+    __shared__ float acc[kBpGroups][kTile][kTile + 1];
+    __shared__ float tile[kTile][kTile + 1];
+    __shared__ double lds[4];
+    const int tx = threadIdx.x & (kTile - 1), ty = threadIdx.x / kTile;
+    const int line = tx, grp = ty;  // the same split read as (sweep line, group)
+    const int i0 = blockIdx.x * kTile, j0 = blockIdx.y * kTile;
+    for (int g = 0; g < kBpGroups; ++g) acc[g][ty][tx] = 0.0f;
+    const int t = blockIdx.y * gridDim.x + blockIdx.x;
+    const int beg = list_off[t], end = list_off[t + 1];
+    for (int base = beg; base < end; base += kBpChunk) {
+        const int n = min(kBpChunk, end - base);
+        __syncthreads();
+        if ((int)threadIdx.x < n) {
+            const int id = list[base + threadIdx.x];
+            BpEntry e;
+            e.ray = rays[id];
+            e.range = range[id];
+            e.r = r[id];
+            e.pad = 0.0f;
+            ent[threadIdx.x] = e;
+        }
+        __syncthreads();
+        for (int k = grp; k < n; k += kBpGroups) {
+            const BpEntry& e = ent[k];
+            const bool rows = e.ray.wfull < 0.0f;  // swept row by row
+            const int ks = (rows ? j0 : i0) + line;
+            if (ks < e.range.x || ks >= e.range.y) continue;
+            const CellW w = cell_weights(cell_lo(e.ray, ks), e.ray.span, e.ray.w32, fabsf(e.ray.wfull));
+            const int m = w.m0 - (rows ? i0 : j0);
+            if ((unsigned)m < (unsigned)kTile) {
+                float& a = rows ? acc[grp][line][m] : acc[grp][m][line];
+                a = fmaf(w.c0, e.r, a);
+            }
+            if ((unsigned)(m + 1) < (unsigned)kTile) {
+                float& a = rows ? acc[grp][line][m + 1] : acc[grp][m + 1][line];
+                a = fmaf(w.c1, e.r, a);
+            }
+        }
+    }
+    __syncthreads();
+    const int i = i0 + tx, j = j0 + ty;
+    const bool in = i < nx && j < ny;
+    float sum = 0.0f;
+#pragma unroll
+    for (int g = 0; g < kBpGroups; ++g) sum += acc[g][ty][tx];
+    float out = 0.0f;
+    if (in) {
+        const size_t id = (size_t)j * nx + i;
+        out = alpha * sum;
+        if (beta != 0.0f) out = fmaf(beta, c[id], out);
+        z[id] = out;
+    }
+    if (zT) {
+        tile[ty][tx] = out;
+        __syncthreads();
+        const int it = i0 + ty, jt = j0 + tx;
+        if (it < nx && jt < ny) zT[(size_t)it * ny + jt] = tile[tx][ty];
+    }
+    if (partial) {
+        const double s2 = block_sum<256>((double)out * (double)out, lds);
+        if (threadIdx.x == 0) partial[t] = s2;
+    }
+}
+
+int image_tile_blocks(const Plan& p) { return ((p.nx + kTile - 1) / kTile) * ((p.ny + kTile - 1) / kTile); }
+
+// Per tile, every ray that can meet one of its pixels, as global ray ids
+// (views ascending, bins ascending within a view).  The pixel centres span a
+// rectangle, so their angles seen from the source lie between those of its
+// corners; a ray through a pixel passes within d/sqrt(2) of its centre, i.e.
+// within asin(rad / l) of the centre's angle, largest at the rectangle point
+// nearest the source; half a bin more covers rounding.
+void bp_tile_lists(const Plan& p, std::vector<int>& off, std::vector<int>& list)
+{
+    const int gx = (p.nx + kTile - 1) / kTile, gy = (p.ny + kTile - 1) / kTile;
+    const double rad = p.pixel * std::sqrt(0.5) * (1.0 + 1e-6), bin_c = 0.5 * (p.B - 1) - p.bin_offset;
+    off.assign((size_t)gx * gy + 1, 0);
+    list.clear();
+    for (int ty = 0; ty < gy; ++ty)
+        for (int tx = 0; tx < gx; ++tx) {
+            const int i0 = tx * kTile, i1 = std::min(i0 + kTile, p.nx) - 1;
+            const int j0 = ty * kTile, j1 = std::min(j0 + kTile, p.ny) - 1;
+            const double x0 = (i0 + 0.5 - 0.5 * p.nx) * p.pixel, x1 = (i1 + 0.5 - 0.5 * p.nx) * p.pixel;
+            const double y0 = (j0 + 0.5 - 0.5 * p.ny) * p.pixel, y1 = (j1 + 0.5 - 0.5 * p.ny) * p.pixel;
+            for (int v = 0; v < p.V; ++v) {
+                const double cs = std::cos(p.angles[v]), sn = std::sin(p.angles[v]);
+                const double sx = -p.sad * cs, sy = -p.sad * sn;
+                double lo = 1e300, hi = -1e300;
+                for (int cnr = 0; cnr < 4; ++cnr) {
+                    const double px = (cnr & 1) ? x1 : x0, py = (cnr & 2) ? y1 : y0;
+                    const double along = px * cs + py * sn + p.sad, across = py * cs - px * sn;
+                    const double b = std::atan2(across, along) / p.dbeta + bin_c;
+                    lo = std::min(lo, b);
+                    hi = std::max(hi, b);
+                }
+                const double nxp = std::min(std::max(sx, x0), x1) - sx, nyp = std::min(std::max(sy, y0), y1) - sy;
+                const double lmin = std::sqrt(nxp * nxp + nyp * nyp);
+                const double hw = std::asin(std::min(1.0, rad / lmin)) / p.dbeta + 0.5;
+                const long long b0 = std::max(0LL, (long long)std::floor(lo - hw));
+                const long long b1 = std::min((long long)p.B - 1, (long long)std::ceil(hi + hw));
+                for (long long b = b0; b <= b1; ++b) list.push_back(v * p.B + (int)b);
+            }
+            off[(size_t)ty * gx + tx + 1] = (int)list.size();
+        }
+}
+
+hipError_t launch_backproject(const Plan& p, const float* r, float alpha, float beta, const float* c,
+                              float* z, float* zT, double* partial, hipStream_t s)
+{
+    dim3 grid((p.nx + kTile - 1) / kTile, (p.ny + kTile - 1) / kTile);
+    hipLaunchKernelGGL(k_backproject, grid, dim3(256), 0, s, p.rays.d_ray, p.rays.d_range, p.rays.d_list_off,
+                       p.rays.d_list, r, p.nx, p.ny, alpha, beta, c, z, zT, partial);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ Eq. 11 backprojector
+// The paper's pixel-driven backprojector (Eq. 11, derived in App. III): per
+// view, the pixel centre's angle beta* seen from the source picks a fractional
+// bin, the sinogram is interpolated linearly there (bins beyond the detector
+// read zero) and weighted by 1/l, l the source-to-pixel distance; the sum over
+// views is scaled by d^2 / dbeta.  Only approximately the transpose of the
+// projector.
+//
+// The interpolation weight moves by 1/dbeta per radian of beta*, so beta* must
+// be right to far better than a float32 arctangent.  The bin angles are
+// equally spaced and the same for every view, so with tau_b = tan(beta_b)
+// (double, per bin) and rho = across/along = tan(beta*):
+//   beta* - beta_b = atan((across - tau_b along) / (along + tau_b across)),
+// a small angle (about one bin), whose arctangent is x - x^3/3 to 1e-15.
+// The numerator is formed in double from double coordinates; a float32
+// polynomial arctangent (error < 1.3e-7 rad) only guesses the bin, corrected
+// by one if the fraction leaves [0, 1).
+__device__ __forceinline__ float guess_atan(float t)
+{
+    // odd polynomial of degree 15 fitted to atan on [0, 1], reflected above 1
+    const float a = fabsf(t);
+    const bool big = a > 1.0f;
+    const float u = big ? __builtin_amdgcn_rcpf(a) : a;
+    const float u2 = u * u;
+    float p = -4.054555384e-03f;
+    p = fmaf(p, u2, 2.186291682e-02f);
+    p = fmaf(p, u2, -5.591227011e-02f);
+    p = fmaf(p, u2, 9.642193375e-02f);
+    p = fmaf(p, u2, -1.390862809e-01f);
+    p = fmaf(p, u2, 1.994656538e-01f);
+    p = fmaf(p, u2, -3.332986076e-01f);
+    p = fmaf(p, u2, 9.999993356e-01f);
+    p *= u;
+    p = big ? 1.5707963268f - p : p;
+    return copysignf(p, t);
+}
+
+__global__ __launch_bounds__(256) void k_backproject_interp(const double2* __restrict__ view,
+                                                            const double* __restrict__ tau,
+                                                            const float* __restrict__ r, int nx, int ny, int V,
+                                                            int B, double pixel, double sad, float inv_dbeta,
+                                                            float bin_c, float scale, float beta, const float* c,
+                                                            float* z, float* zT, double* partial)
 {
     __shared__ float tile[kTile][kTile + 1];
     __shared__ double lds[4];
@@ -132,38 +348,37 @@ __global__ __launch_bounds__(256) void k_backproject(const longlong2* __restrict
     const bool in = i < nx && j < ny;
     float acc = 0.0f;
     if (in) {
-        const float cx = ((float)i + 0.5f - 0.5f * (float)nx) * k.pixel;
-        const float cy = ((float)j + 0.5f - 0.5f * (float)ny) * k.pixel;
-        const float rad2 = k.rad * k.rad;
+        const double cx = ((double)i + 0.5 - 0.5 * nx) * pixel;
+        const double cy = ((double)j + 0.5 - 0.5 * ny) * pixel;
         for (int v = 0; v < V; ++v) {
-            const float2 cs = view[v];
-            // position of the pixel centre in the frame of the view's central ray
-            const float along = fmaf(cx, cs.x, fmaf(cy, cs.y, k.sad));
-            const float across = fmaf(cy, cs.x, -cx * cs.y);
-            const float bc = fmaf(atan2f(across, along), k.inv_dbeta, k.bin_c);
-            // the pixel lies inside a circle of radius d/sqrt(2): its rays are
-            // within asin(rad/l) <= rad / sqrt(l^2 - rad^2) of the centre's.
-            const float hw = fmaf(k.rad * rsqrtf(along * along + across * across - rad2),
-                                  k.inv_dbeta, k.margin);
-            const int b0 = max((int)ceilf(bc - hw), 0);
-            const int b1 = min((int)floorf(bc + hw), B - 1);
-            const longlong2* fv = fx + (size_t)v * B;
-            const float2* wv = wt + (size_t)v * B;
-            const float* rr = r + (size_t)v * B;
-            for (int b = b0; b <= b1; ++b) {
-                const longlong2 FX = fv[b];
-                const float2 W = wv[b];
-                const bool rows = W.y < 0.0f;
-                const int ks = rows ? j : i, m = rows ? i : j;
-                const long long ea = FX.x + (long long)ks * FX.y;
-                acc = fmaf(chord_fx(ea, ea + FX.y, FX.y, m, W.x, fabsf(W.y)), rr[b], acc);
+            const double2 cs = view[v];
+            // pixel centre in the frame of the view's central ray
+            const double along = fma(cx, cs.x, fma(cy, cs.y, sad));
+            const double across = fma(cy, cs.x, -cx * cs.y);
+            const float alf = (float)along, acf = (float)across;
+            int b0 = (int)floorf(fmaf(guess_atan(acf * __builtin_amdgcn_rcpf(alf)), inv_dbeta, bin_c));
+            if (b0 < -1 || b0 > B - 1) continue;  // both bins beyond the detector
+            const double tb = tau[b0 + 1];
+            const float x = (float)fma(-tb, along, across) / (float)fma(tb, across, along);
+            float a = (x - x * x * x * (1.0f / 3.0f)) * inv_dbeta;
+            if (a < 0.0f) {
+                --b0;
+                a += 1.0f;
+            } else if (a >= 1.0f) {
+                ++b0;
+                a -= 1.0f;
             }
+            const float* rr = r + (size_t)v * B;
+            const float y0 = (b0 >= 0 && b0 < B) ? rr[b0] : 0.0f;
+            const float y1 = (b0 + 1 >= 0 && b0 + 1 < B) ? rr[b0 + 1] : 0.0f;
+            const float inv_l = __builtin_amdgcn_rsqf(fmaf(alf, alf, acf * acf));
+            acc = fmaf(fmaf(a, y1 - y0, y0), inv_l, acc);
         }
     }
     float out = 0.0f;
     if (in) {
         const size_t id = (size_t)j * nx + i;
-        out = alpha * acc;
+        out = scale * acc;
         if (beta != 0.0f) out = fmaf(beta, c[id], out);
         z[id] = out;
     }
@@ -179,26 +394,14 @@ __global__ __launch_bounds__(256) void k_backproject(const longlong2* __restrict
     }
 }
 
-int image_tile_blocks(const Plan& p) { return ((p.nx + kTile - 1) / kTile) * ((p.ny + kTile - 1) / kTile); }
-
-hipError_t launch_backproject(const Plan& p, const float* r, float alpha, float beta, const float* c,
-                              float* z, float* zT, double* partial, hipStream_t s)
+hipError_t launch_backproject_interp(const Plan& p, const float* r, float alpha, float beta, const float* c,
+                                     float* z, float* zT, double* partial, hipStream_t s)
 {
-    const double half_diag = 0.5 * p.pixel * std::sqrt((double)p.nx * p.nx + (double)p.ny * p.ny);
-    const double dot_min = p.sad - half_diag;
-    // rounding of the stored ray coordinates (far below 2^-22 (nx+ny) row units)
-    // seen from the nearest pixel, plus a fixed 0.01 bin for the bin search itself.
-    const double err = std::ldexp(1.0, -22) * (p.nx + p.ny) * p.pixel / (dot_min * p.dbeta);
-    BpConst k;
-    k.pixel = (float)p.pixel;
-    k.sad = (float)p.sad;
-    k.inv_dbeta = (float)(1.0 / p.dbeta);
-    k.bin_c = (float)(0.5 * (p.B - 1) - p.bin_offset);
-    k.rad = (float)(p.pixel * std::sqrt(0.5) * (1.0 + 1e-6));
-    k.margin = (float)(0.01 + 4.0 * err);
+    const float scale = (float)((double)alpha * p.pixel * p.pixel / p.dbeta);
     dim3 grid((p.nx + kTile - 1) / kTile, (p.ny + kTile - 1) / kTile);
-    hipLaunchKernelGGL(k_backproject, grid, dim3(256), 0, s, p.rays.d_fx, p.rays.d_w, p.rays.d_view, r, p.nx,
-                       p.ny, p.V, p.B, k, alpha, beta, c, z, zT, partial);
+    hipLaunchKernelGGL(k_backproject_interp, grid, dim3(256), 0, s, p.rays.d_view_d, p.rays.d_tau, r, p.nx, p.ny,
+                       p.V, p.B, p.pixel, p.sad, (float)(1.0 / p.dbeta), (float)(0.5 * (p.B - 1) - p.bin_offset),
+                       scale, beta, c, z, zT, partial);
     return hipGetLastError();
 }
 

@@ -1,4 +1,7 @@
-// reduce.h -- deterministic block reductions (fixed butterfly + fixed wave order).
+// reduce.h -- deterministic reductions (fixed butterfly, fixed block order).
+// A grid-wide sum is two-stage: each block of the producing kernel writes one
+// float64 partial, and a later kernel on the same stream sums the partials in
+// a fixed order (kernel boundaries make them visible without fences).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -28,12 +31,14 @@ __device__ __forceinline__ double block_sum(double v, double* lds)
     return r;
 }
 
-// Sum of part[0..n) in a fixed order by one block of 256 threads (valid in all threads).
-__device__ __forceinline__ double block_sum_array(const double* part, int n, int stride, double* lds)
+// Sum of part[i * stride], i < n, written by an earlier kernel, by a block of
+// NT threads in a fixed order (valid in all threads).  `lds` holds NT/64 doubles.
+template <int NT>
+__device__ __forceinline__ double block_sum_partials(const double* part, int n, int stride, double* lds)
 {
     double v = 0.0;
-    for (int i = threadIdx.x; i < n; i += 256) v += part[(size_t)i * stride];
-    return block_sum<256>(v, lds);
+    for (int i = threadIdx.x; i < n; i += NT) v += part[(size_t)i * stride];
+    return block_sum<NT>(v, lds);
 }
 
 }  // namespace eptv

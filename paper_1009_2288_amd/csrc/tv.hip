@@ -66,9 +66,14 @@ __device__ __forceinline__ float tv_down(const Nbhd& N, float e2)
 
 size_t n_edges(const Plan& p) { return (size_t)p.ny * (p.nx + 1) + (size_t)(p.ny + 1) * p.nx; }
 
-// ------------------------------------------------------------------ sigma: magnitudes + first digit
+// ------------------------------------------------------------------ sigma (radix select)
+// sigma is the order statistic of rank `rank` of all half-edge magnitudes.
+// Magnitudes are non-negative floats, so their bit patterns order like the
+// values; the selection takes three digits (bits 31..21, 20..10, 9..0), each
+// by a histogram of the keys that match the digits found so far, closed by a
+// one-block kernel that finds the digit whose bucket holds the rank.
+
 // Edge index: x-edge (i+1/2, j) -> j*(nx+1) + i+1; y-edge (i, j+1/2) -> ny*(nx+1) + (j+1)*nx + i.
-// Magnitudes are non-negative floats, so their bit patterns order like the values.
 __global__ __launch_bounds__(256) void k_edges_hist(const float* __restrict__ f, int nx, int ny, float eps2,
                                                     uint32_t* keys, uint32_t* hist0)
 {
@@ -110,7 +115,6 @@ hipError_t launch_edges_hist(const Plan& p, const float* f, float eps2, uint32_t
     return hipGetLastError();
 }
 
-// ------------------------------------------------------------------ sigma: later digits
 // pass 1: digit = bits 20..10 among keys whose bits 31..21 equal the prefix;
 // pass 2: digit = bits 9..0 among keys whose bits 31..10 equal the prefix.
 __global__ __launch_bounds__(256) void k_select_hist(const uint32_t* __restrict__ keys, size_t n, int pass,
@@ -138,17 +142,16 @@ int select_blocks(const Plan& p)
     return (int)std::max<size_t>(1, std::min<size_t>((n + 2047) / 2048, 512));
 }
 
-hipError_t launch_select_hist(const Plan& p, int pass, const uint32_t* keys, const DevState* st,
-                              uint32_t* hist, hipStream_t s)
+hipError_t launch_select_hist(const Plan& p, int pass, const uint32_t* keys, const DevState* st, uint32_t* hist,
+                              hipStream_t s)
 {
-    hipLaunchKernelGGL(k_select_hist, dim3(select_blocks(p)), dim3(256), 0, s, keys, n_edges(p), pass, st,
-                       hist);
+    hipLaunchKernelGGL(k_select_hist, dim3(select_blocks(p)), dim3(256), 0, s, keys, n_edges(p), pass, st, hist);
     return hipGetLastError();
 }
 
-// Find the digit whose bucket holds the wanted rank, fold it into the prefix,
-// and clear the histogram for the next use.  After the last digit the prefix
-// is the bit pattern of the selected magnitude.
+// The digit whose bucket holds the rank (an inclusive scan over 256 groups of
+// buckets), folded into the prefix; the histogram is cleared for its next use.
+// After the last digit the prefix is the bit pattern of the selected magnitude.
 __global__ __launch_bounds__(256) void k_select_finalize(DevState* st, int pass, uint32_t* hist, float floor_)
 {
     __shared__ uint32_t sums[256];
@@ -159,14 +162,23 @@ __global__ __launch_bounds__(256) void k_select_finalize(DevState* st, int pass,
     uint32_t local = 0;
     for (int e = 0; e < per; ++e) local += hist[t * per + e];
     sums[t] = local;
+    if (t == 0) {  // only kept if the rank exceeded the count, which cannot happen
+        found_digit = (uint32_t)(nb - 1);
+        found_before = 0u;
+    }
     __syncthreads();
-    if (t == 0) {
-        const uint32_t rank = st->rank;
-        uint32_t before = 0;
-        int blk = 0;
-        while (blk < 255 && before + sums[blk] <= rank) before += sums[blk++];
-        int d = blk * per;
-        while (d < blk * per + per - 1 && before + hist[d] <= rank) before += hist[d++];
+    for (int o = 1; o < 256; o <<= 1) {
+        const uint32_t add = t >= o ? sums[t - o] : 0u;
+        __syncthreads();
+        sums[t] += add;
+        __syncthreads();
+    }
+    const uint32_t rank = st->rank;
+    const uint32_t before_group = t ? sums[t - 1] : 0u;
+    if (before_group <= rank && rank < sums[t]) {
+        uint32_t before = before_group;
+        int d = t * per;
+        while (d < t * per + per - 1 && before + hist[d] <= rank) before += hist[d++];
         found_digit = (uint32_t)d;
         found_before = before;
     }
@@ -175,10 +187,9 @@ __global__ __launch_bounds__(256) void k_select_finalize(DevState* st, int pass,
     if (t == 0) {
         const int shift = pass == 0 ? 21 : (pass == 1 ? 10 : 0);
         st->prefix |= found_digit << shift;
-        st->rank -= found_before;
+        st->rank = rank - found_before;
         if (pass == 2) {
-            float sg = __uint_as_float(st->prefix);
-            sg = fmaxf(sg, floor_);
+            const float sg = fmaxf(__uint_as_float(st->prefix), floor_);
             st->sigma = sg;
             st->inv_sigma2 = 1.0f / (sg * sg);
         }
@@ -205,10 +216,20 @@ hipError_t launch_sigma_out(const DevState* st, float* out, hipStream_t s)
 // ------------------------------------------------------------------ direction g (Eq. 9, A2)
 __device__ __forceinline__ float weight(float tv, float inv_s2) { return expf(-(tv * tv) * inv_s2); }
 
-__global__ __launch_bounds__(256) void k_tv_grad(const float* __restrict__ f, const float* __restrict__ v, int nx,
-                                                 int ny, float lambda, const DevState* st, float inv_s2_direct,
-                                                 float eps2, float* __restrict__ g, float* wx, float* wy,
-                                                 double* part)
+// The step f - t g of the previous descent step (none when it was rejected),
+// evaluated with the same float operation as the final update kernel.
+__device__ __forceinline__ float stepped(float f, float g, int k, float t) { return k >= 0 ? fmaf(-t, g, f) : f; }
+
+// g = lambda (f - v) + A2 at the current iterate, with the weights at it.
+// When g_prev is given the current iterate is first formed from the previous
+// one, f - t g_prev (the previous step's decision in st_prev), and stored to
+// f_out.  Per-block partials: (Q(f) = sum of w TV over owned edges +
+// lambda/2 (f - v)^2, ||g||^2).
+__global__ __launch_bounds__(256) void k_tv_grad(const float* __restrict__ f, const float* __restrict__ g_prev,
+                                                 const DevState* st_prev, float* __restrict__ f_out,
+                                                 const float* __restrict__ v, int nx, int ny, float lambda,
+                                                 const DevState* st, float inv_s2_direct, float eps2,
+                                                 float* __restrict__ g, float* wx, float* wy, double* part)
 {
     __shared__ double lds[4];
     const float inv_s2 = st ? st->inv_sigma2 : inv_s2_direct;
@@ -217,6 +238,18 @@ __global__ __launch_bounds__(256) void k_tv_grad(const float* __restrict__ f, co
     if (i < nx && j < ny) {
         Nbhd N;
         load_nbhd(f, nx, ny, i, j, N);
+        if (g_prev) {
+            Nbhd G;
+            load_nbhd(g_prev, nx, ny, i, j, G);
+            const int kp = st_prev->k;
+            const float tp = st_prev->t;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) N.n[a][b] = stepped(N.n[a][b], G.n[a][b], kp, tp);
+            // outside pixels stay zero: f and g are both zero there
+            f_out[(size_t)j * nx + i] = N.n[1][1];
+        }
         const float c = N.n[1][1];
         const float tR = tv_right(N, eps2), tL = tv_left(N, eps2), tU = tv_up(N, eps2), tD = tv_down(N, eps2);
         const float wR = weight(tR, inv_s2), wL = weight(tL, inv_s2), wU = weight(tU, inv_s2),
@@ -255,35 +288,15 @@ __global__ __launch_bounds__(256) void k_tv_grad(const float* __restrict__ f, co
     }
 }
 
-hipError_t launch_tv_grad(const Plan& p, const float* f, const float* v, float lambda, const DevState* st,
-                          float sigma_direct, float eps2, float* g, float* wx, float* wy, double* part,
-                          hipStream_t s)
+hipError_t launch_tv_grad(const Plan& p, const float* f, const float* g_prev, const DevState* st_prev, float* f_out,
+                          const float* v, float lambda, const DevState* st, float sigma_direct, float eps2, float* g,
+                          float* wx, float* wy, double* part, hipStream_t s)
 {
     const float inv_s2 = (sigma_direct > 0.0f && std::isfinite(sigma_direct)) ? 1.0f / (sigma_direct * sigma_direct)
                                                                              : 0.0f;
     dim3 grid((p.nx + kT - 1) / kT, (p.ny + kT - 1) / kT);
-    hipLaunchKernelGGL(k_tv_grad, grid, dim3(256), 0, s, f, v, p.nx, p.ny, lambda, st, inv_s2, eps2, g, wx, wy,
-                       part);
-    return hipGetLastError();
-}
-
-__global__ __launch_bounds__(256) void k_grad_finalize(DevState* st, const double* part, int n)
-{
-    __shared__ double lds[4];
-    const double q = block_sum_array(part, n, 2, lds);
-    const double gg = block_sum_array(part + 1, n, 2, lds);
-    if (threadIdx.x == 0) {
-        st->q0 = q;
-        st->gg = gg;
-        st->decided = 0;
-        st->k = -1;
-        st->t = 0.0f;
-    }
-}
-
-hipError_t launch_grad_finalize(DevState* st, const double* part, int nparts, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_grad_finalize, dim3(1), dim3(256), 0, s, st, part, nparts);
+    hipLaunchKernelGGL(k_tv_grad, grid, dim3(256), 0, s, f, g_prev, st_prev, f_out, v, p.nx, p.ny, lambda, st, inv_s2,
+                       eps2, g, wx, wy, part);
     return hipGetLastError();
 }
 
@@ -297,35 +310,35 @@ __device__ __forceinline__ float cand_t(float t0, float shrink, int k)
     return t;
 }
 
-// Q(f - t_k g) for kArmijoCand candidates k = pass*kArmijoCand + c, with the
-// weights frozen at f: partial sums per block, [block][candidate].
+// Candidate range of pass p: [0, 8) first, then 16 at a time.
+__host__ __device__ __forceinline__ int pass_first(int pass) { return pass == 0 ? 0 : kArmijoFirst + kArmijoMore * (pass - 1); }
+
+// Q(f - t_k g) for the NC candidates of one pass, with the weights frozen at
+// f: per-block partial sums, [block][kArmijoSlots].
+template <int NC>
 __global__ __launch_bounds__(256) void k_armijo(const float* __restrict__ f, const float* __restrict__ g,
                                                 const float* __restrict__ v, const float* __restrict__ wx,
                                                 const float* __restrict__ wy, int nx, int ny, float lambda,
                                                 float eps2, float t0, float shrink, int pass, const DevState* st,
                                                 double* part)
 {
-    __shared__ double lds[4];
-    if (st->decided) return;  // uniform: an earlier pass already chose a step
+    __shared__ double red[4][NC];
+    if (pass > 0 && st->decided) return;  // uniform: an earlier pass already chose a step
     const int i = blockIdx.x * kT + (threadIdx.x & (kT - 1)), j = blockIdx.y * kT + threadIdx.x / kT;
-    const bool in = i < nx && j < ny;
-    Nbhd F, G;
-    float wR = 0.f, wU = 0.f, wL = 0.f, wD = 0.f, vv = 0.f;
-    if (in) {
+    double e[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) e[c] = 0.0;
+    if (i < nx && j < ny) {
+        Nbhd F, G;
         load_nbhd(f, nx, ny, i, j, F);
         load_nbhd(g, nx, ny, i, j, G);
         const size_t xo = (size_t)j * (nx + 1);
-        wR = wx[xo + i + 1];
-        wU = wy[(size_t)(j + 1) * nx + i];
-        if (i == 0) wL = wx[xo];
-        if (j == 0) wD = wy[i];
-        vv = v[(size_t)j * nx + i];
-    }
-    const int b = blockIdx.y * gridDim.x + blockIdx.x;
-    float t = cand_t(t0, shrink, pass * kArmijoCand);
-    for (int c = 0; c < kArmijoCand; ++c) {
-        double e = 0.0;
-        if (in) {
+        const float wR = wx[xo + i + 1], wU = wy[(size_t)(j + 1) * nx + i];
+        const float wL = i == 0 ? wx[xo] : 0.0f, wD = j == 0 ? wy[i] : 0.0f;
+        const float vv = v[(size_t)j * nx + i];
+        float t = cand_t(t0, shrink, pass_first(pass));
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
             Nbhd H;
 #pragma unroll
             for (int a = 0; a < 3; ++a)
@@ -335,68 +348,130 @@ __global__ __launch_bounds__(256) void k_armijo(const float* __restrict__ f, con
             if (i == 0) s += wL * tv_left(H, eps2);
             if (j == 0) s += wD * tv_down(H, eps2);
             const float d = H.n[1][1] - vv;
-            e = (double)s + 0.5 * (double)lambda * (double)d * (double)d;
+            e[c] = (double)s + 0.5 * (double)lambda * (double)d * (double)d;
+            t *= shrink;
         }
-        const double tot = block_sum<256>(e, lds);
-        if (threadIdx.x == 0) part[(size_t)b * kArmijoCand + c] = tot;
-        t *= shrink;
+    }
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const double sc = wave_sum(e[c]);
+        if (l == 0) red[w][c] = sc;
+    }
+    __syncthreads();
+    if (threadIdx.x < NC) {
+        const int c = threadIdx.x;
+        part[(size_t)(blockIdx.y * gridDim.x + blockIdx.x) * kArmijoSlots + c] =
+            red[0][c] + red[1][c] + red[2][c] + red[3][c];
     }
 }
 
 int armijo_blocks(const Plan& p) { return ((p.nx + kT - 1) / kT) * ((p.ny + kT - 1) / kT); }
 
-hipError_t launch_armijo(const Plan& p, int pass, const float* f, const float* g, const float* v,
-                         const float* wx, const float* wy, float lambda, float eps2, float t0, float shrink,
-                         const DevState* st, double* part, hipStream_t s)
+hipError_t launch_armijo(const Plan& p, int pass, const float* f, const float* g, const float* v, const float* wx,
+                         const float* wy, float lambda, float eps2, float t0, float shrink, const DevState* st,
+                         double* part, hipStream_t s)
 {
     dim3 grid((p.nx + kT - 1) / kT, (p.ny + kT - 1) / kT);
-    hipLaunchKernelGGL(k_armijo, grid, dim3(256), 0, s, f, g, v, wx, wy, p.nx, p.ny, lambda, eps2, t0, shrink,
-                       pass, st, part);
+    if (pass == 0)
+        hipLaunchKernelGGL(k_armijo<kArmijoFirst>, grid, dim3(256), 0, s, f, g, v, wx, wy, p.nx, p.ny, lambda, eps2,
+                           t0, shrink, pass, st, part);
+    else
+        hipLaunchKernelGGL(k_armijo<kArmijoMore>, grid, dim3(256), 0, s, f, g, v, wx, wy, p.nx, p.ny, lambda, eps2,
+                           t0, shrink, pass, st, part);
     return hipGetLastError();
 }
 
-// First candidate with Q_k <= Q0 - c t_k ||g||^2; after the last allowed
-// candidate without one, the step is skipped (k = -1, t = 0).
-__global__ __launch_bounds__(256) void k_armijo_finalize(DevState* st, const double* part, int n, int pass,
-                                                         int max_bt, double c, float t0, float shrink)
+// The decision of one pass: the first candidate with Q_k <= Q0 - c t_k ||g||^2.
+// Pass 0 also closes Q0 and ||g||^2 from the gradient kernel's partials.
+// After the last allowed candidate without acceptance the step is skipped
+// (k = -1, t = 0).  The accepted index is recorded for the iteration.
+// One block of 1024 threads: thread t loads the partial rows of blocks t,
+// t + 1024, ... (all loads in flight together; the partials come from every
+// XCD, so each load is a far one), then every slot is summed by a fixed
+// butterfly within each wave and over the 16 waves in order.
+constexpr int kFinThreads = 1024;
+constexpr int kFinVals = kArmijoSlots + 2;
+
+__global__ __launch_bounds__(kFinThreads) void k_armijo_finalize(DevState* st, const double* part_grad,
+                                                                 const double* part_arm, int nb, int pass,
+                                                                 int max_bt, double c_arm, float t0, float shrink,
+                                                                 int32_t* st_k, int step, int T)
 {
-    __shared__ double lds[4];
-    if (st->decided) return;
-    const double q0 = st->q0, gg = st->gg;
-    for (int cc = 0; cc < kArmijoCand; ++cc) {
-        const int k = pass * kArmijoCand + cc;
-        if (k > max_bt) break;
-        const double qk = block_sum_array(part + cc, n, kArmijoCand, lds);
-        const float t = cand_t(t0, shrink, k);
-        if (qk <= q0 - c * (double)t * gg) {
-            if (threadIdx.x == 0) {
-                st->decided = 1;
-                st->k = k;
-                st->t = t;
-            }
-            return;
+    __shared__ double red[kFinThreads / 64][kFinVals];
+    __shared__ double tot[kFinVals];
+    if (pass > 0 && st->decided) return;
+    double v[kFinVals];
+#pragma unroll
+    for (int c = 0; c < kFinVals; ++c) v[c] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kFinThreads) {
+        const double2* row = reinterpret_cast<const double2*>(part_arm + (size_t)b * kArmijoSlots);
+#pragma unroll
+        for (int c = 0; c < kArmijoSlots / 2; ++c) {
+            const double2 x = row[c];
+            v[2 * c] += x.x;
+            v[2 * c + 1] += x.y;
+        }
+        if (pass == 0) {
+            const double2 gq = reinterpret_cast<const double2*>(part_grad)[b];
+            v[kArmijoSlots] += gq.x;
+            v[kArmijoSlots + 1] += gq.y;
         }
     }
-    if ((pass + 1) * kArmijoCand > max_bt && threadIdx.x == 0) {
-        st->decided = 1;
-        st->k = -1;
-        st->t = 0.0f;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int c = 0; c < kFinVals; ++c) {
+        const double r = wave_sum(v[c]);
+        if (lane == 0) red[w][c] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x < kFinVals) {
+        double s = 0.0;
+        for (int q = 0; q < kFinThreads / 64; ++q) s += red[q][threadIdx.x];
+        tot[threadIdx.x] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (pass == 0) {
+            st->q0 = tot[kArmijoSlots];
+            st->gg = tot[kArmijoSlots + 1];
+        }
+        const double q0 = pass == 0 ? tot[kArmijoSlots] : st->q0;
+        const double g2 = pass == 0 ? tot[kArmijoSlots + 1] : st->gg;
+        const int first = pass_first(pass), nc = pass == 0 ? kArmijoFirst : kArmijoMore;
+        int kk = -1;
+        float tk = 0.0f;
+        for (int cc = 0; cc < nc; ++cc) {
+            const int k = first + cc;
+            if (k > max_bt) break;
+            const float t = cand_t(t0, shrink, k);
+            if (tot[cc] <= q0 - c_arm * (double)t * g2) {
+                kk = k;
+                tk = t;
+                break;
+            }
+        }
+        const bool last_pass = first + nc > max_bt;
+        st->decided = kk >= 0 || last_pass;
+        st->k = kk;
+        st->t = tk;
+        if ((kk >= 0 || last_pass) && st_k) st_k[(size_t)st->iter * T + step] = kk;
     }
 }
 
-hipError_t launch_armijo_finalize(DevState* st, const double* part, int nparts, int pass, int max_bt, double c,
-                                  double t0, double shrink, hipStream_t s)
+hipError_t launch_armijo_finalize(const Plan& p, DevState* st, const double* part_grad, const double* part_arm,
+                                  int pass, int max_bt, double c_arm, float t0, float shrink, int32_t* st_k, int step,
+                                  int T, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_armijo_finalize, dim3(1), dim3(256), 0, s, st, part, nparts, pass, max_bt, c, (float)t0,
-                       (float)shrink);
+    hipLaunchKernelGGL(k_armijo_finalize, dim3(1), dim3(kFinThreads), 0, s, st, part_grad, part_arm,
+                       armijo_blocks(p), pass, max_bt, c_arm, t0, shrink, st_k, step, T);
     return hipGetLastError();
 }
 
 // f_out = f - t g (unchanged when no step was accepted), optional truncation at
 // zero (step 3 of the algorithm) and optional transposed copy for the projector.
 __global__ __launch_bounds__(256) void k_p2_update(const DevState* st, const float* fcur, const float* __restrict__ g,
-                                                   float* fout, float* foutT, int clamp, int nx, int ny,
-                                                   int32_t* st_k, int step, int T)
+                                                   float* fout, float* foutT, int clamp, int nx, int ny)
 {
     __shared__ float tl[32][33];
     const int k = st->k;
@@ -408,14 +483,12 @@ __global__ __launch_bounds__(256) void k_p2_update(const DevState* st, const flo
         float val = 0.0f;
         if (i < nx && j < ny) {
             const size_t id = (size_t)j * nx + i;
-            val = fcur[id];
-            if (k >= 0) val = fmaf(-t, g[id], val);
+            val = stepped(fcur[id], g[id], k, t);
             if (clamp) val = fmaxf(val, 0.0f);
             fout[id] = val;
         }
         tl[r][tx] = val;
     }
-    if (st_k && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) st_k[(size_t)st->iter * T + step] = k;
     if (foutT) {
         __syncthreads();
         for (int r = ty; r < 32; r += 8) {
@@ -426,11 +499,10 @@ __global__ __launch_bounds__(256) void k_p2_update(const DevState* st, const flo
 }
 
 hipError_t launch_p2_update(const Plan& p, const DevState* st, const float* fcur, const float* g, float* fout,
-                            float* foutT, int clamp, int32_t* st_k, int step, int T, hipStream_t s)
+                            float* foutT, int clamp, hipStream_t s)
 {
     dim3 grid((p.nx + 31) / 32, (p.ny + 31) / 32);
-    hipLaunchKernelGGL(k_p2_update, grid, dim3(256), 0, s, st, fcur, g, fout, foutT, clamp, p.nx, p.ny, st_k, step,
-                       T);
+    hipLaunchKernelGGL(k_p2_update, grid, dim3(256), 0, s, st, fcur, g, fout, foutT, clamp, p.nx, p.ny);
     return hipGetLastError();
 }
 
@@ -464,6 +536,105 @@ hipError_t launch_copy_clamp(const Plan& p, const float* src, float* dst, float*
 {
     dim3 grid((p.nx + 31) / 32, (p.ny + 31) / 32);
     hipLaunchKernelGGL(k_copy_clamp, grid, dim3(256), 0, s, src, dst, dstT, clamp, p.nx, p.ny);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ VJP of the direction
+// (dg/df)^T u with sigma fixed, for differentiating through descent steps.
+// With g = lambda (f - v) + sum_e F_e (e_B - e_A) over half-edges from pixel A
+// to pixel B, F_e = w d / TV (d = f_B - f_A, t1 and t2 the pair-mean
+// differences of Eq. A3, w = exp(-TV^2/sigma^2)):
+//   dF/dd = w/TV - c d, dF/dt1 = -c t1/2, dF/dt2 = -c t2/2,
+//   c = w d (1/TV + 2 TV/sigma^2) / TV^2.
+// Pass 1 stores per edge, scaled by u_B - u_A: DD = dF/dd and the half
+// derivatives H1 = dF/dt1 / 2, H2 = dF/dt2 / 2 (edge order as for the keys).
+// Pass 2 gathers per pixel: as A of an edge -DD - H1 + H2, as B +DD - H1 + H2,
+// as a member of the pair beyond the edge (A+p, B+p) +H1, of the pair before
+// it (A-p, B-p) -H2.
+__device__ __forceinline__ void vjp_coef(float a, float b, float au, float bu, float ad, float bd, float ua,
+                                         float ub, float inv_s2, float eps2, float* e3, size_t ne, size_t e)
+{
+    const float d = b - a;
+    const float m0 = 0.5f * (a + b), t1 = 0.5f * (au + bu) - m0, t2 = m0 - 0.5f * (ad + bd);
+    const float tv = sqrtf(d * d + 0.5f * (t1 * t1) + 0.5f * (t2 * t2) + eps2);
+    const float itv = 1.0f / tv;
+    const float w = expf(-(tv * tv) * inv_s2);
+    const float c = w * d * (itv + 2.0f * tv * inv_s2) * (itv * itv);
+    const float ue = ub - ua;
+    e3[e] = ue * (w * itv - c * d);
+    e3[ne + e] = -0.25f * ue * c * t1;
+    e3[2 * ne + e] = -0.25f * ue * c * t2;
+}
+
+__global__ __launch_bounds__(256) void k_vjp_edges(const float* __restrict__ f, const float* __restrict__ u, int nx,
+                                                   int ny, float inv_s2, float eps2, float* e3)
+{
+    const int i = blockIdx.x * kT + (threadIdx.x & (kT - 1)), j = blockIdx.y * kT + threadIdx.x / kT;
+    if (i >= nx || j >= ny) return;
+    Nbhd N;
+    load_nbhd(f, nx, ny, i, j, N);
+    const size_t ne = (size_t)ny * (nx + 1) + (size_t)(ny + 1) * nx;
+    const size_t xo = (size_t)j * (nx + 1), yo = (size_t)ny * (nx + 1);
+    const float uc = u[(size_t)j * nx + i];
+    const float ur = pix(u, nx, ny, i + 1, j), uu = pix(u, nx, ny, i, j + 1);
+    // right edge (i+1/2, j): A = (i, j), B = (i+1, j), p = (0, 1)
+    vjp_coef(N.n[1][1], N.n[2][1], N.n[1][2], N.n[2][2], N.n[1][0], N.n[2][0], uc, ur, inv_s2, eps2, e3, ne,
+             xo + i + 1);
+    // up edge (i, j+1/2): A = (i, j), B = (i, j+1), p = (1, 0)
+    vjp_coef(N.n[1][1], N.n[1][2], N.n[2][1], N.n[2][2], N.n[0][1], N.n[0][2], uc, uu, inv_s2, eps2, e3, ne,
+             yo + (size_t)(j + 1) * nx + i);
+    if (i == 0)  // left border edge: A is outside the image
+        vjp_coef(N.n[0][1], N.n[1][1], N.n[0][2], N.n[1][2], N.n[0][0], N.n[1][0], 0.0f, uc, inv_s2, eps2, e3, ne,
+                 xo);
+    if (j == 0)  // bottom border edge
+        vjp_coef(N.n[1][0], N.n[1][1], N.n[2][0], N.n[2][1], N.n[0][0], N.n[0][1], 0.0f, uc, inv_s2, eps2, e3, ne,
+                 yo + i);
+}
+
+__global__ __launch_bounds__(256) void k_vjp_gather(const float* __restrict__ e3, const float* __restrict__ u,
+                                                    int nx, int ny, float lambda, float* out)
+{
+    const int i = blockIdx.x * kT + (threadIdx.x & (kT - 1)), j = blockIdx.y * kT + threadIdx.x / kT;
+    if (i >= nx || j >= ny) return;
+    const size_t ne = (size_t)ny * (nx + 1) + (size_t)(ny + 1) * nx, yo = (size_t)ny * (nx + 1);
+    const float* DD = e3;
+    const float* H1 = e3 + ne;
+    const float* H2 = e3 + 2 * ne;
+    // x-edge between (a, b) and (a+1, b), a in [-1, nx-1], b in [0, ny-1]
+    auto xe = [&](int a, int b) -> long long {
+        return (b >= 0 && b < ny) ? (long long)b * (nx + 1) + a + 1 : -1;
+    };
+    // y-edge between (a, b) and (a, b+1), a in [0, nx-1], b in [-1, ny-1]
+    auto ye = [&](int a, int b) -> long long {
+        return (a >= 0 && a < nx) ? (long long)(yo + (size_t)(b + 1) * nx + a) : -1;
+    };
+    auto h1 = [&](long long e) { return e >= 0 ? H1[e] : 0.0f; };
+    auto h2 = [&](long long e) { return e >= 0 ? H2[e] : 0.0f; };
+    float acc = lambda * u[(size_t)j * nx + i];
+    {
+        const long long ea = xe(i, j), eb = xe(i - 1, j);  // this pixel is A of ea, B of eb
+        acc += -DD[ea] - H1[ea] + H2[ea];
+        acc += DD[eb] - H1[eb] + H2[eb];
+        acc += h1(xe(i, j - 1)) + h1(xe(i - 1, j - 1));
+        acc -= h2(xe(i, j + 1)) + h2(xe(i - 1, j + 1));
+    }
+    {
+        const long long ea = ye(i, j), eb = ye(i, j - 1);
+        acc += -DD[ea] - H1[ea] + H2[ea];
+        acc += DD[eb] - H1[eb] + H2[eb];
+        acc += h1(ye(i - 1, j)) + h1(ye(i - 1, j - 1));
+        acc -= h2(ye(i + 1, j)) + h2(ye(i + 1, j - 1));
+    }
+    out[(size_t)j * nx + i] = acc;
+}
+
+hipError_t launch_tv_vjp(const Plan& p, const float* f, const float* u, float lambda, float sigma, float eps2,
+                         float* e3, float* out, hipStream_t s)
+{
+    dim3 grid((p.nx + kT - 1) / kT, (p.ny + kT - 1) / kT);
+    const float inv_s2 = std::isinf(sigma) ? 0.0f : 1.0f / (sigma * sigma);
+    hipLaunchKernelGGL(k_vjp_edges, grid, dim3(256), 0, s, f, u, p.nx, p.ny, inv_s2, eps2, e3);
+    hipLaunchKernelGGL(k_vjp_gather, grid, dim3(256), 0, s, e3, u, p.nx, p.ny, lambda, out);
     return hipGetLastError();
 }
 

@@ -23,7 +23,9 @@ EPTV_OK, EPTV_ERR_ARG, EPTV_ERR_GEOMETRY, EPTV_ERR_WORKSPACE, EPTV_ERR_HIP, EPTV
 
 SYMBOLS = ["eptv_plan_create", "eptv_plan_destroy", "eptv_plan_nnz", "eptv_workspace_bytes", "eptv_project",
            "eptv_project_dual", "eptv_backproject", "eptv_tv_gradient", "eptv_select_sigma", "eptv_tv_step", "eptv_reconstruct",
-           "eptv_status_string", "eptv_last_error"]
+           "eptv_status_string", "eptv_last_error", "eptv_geometry_matrix", "eptv_plan_store_matrix",
+           "eptv_project_stored", "eptv_backproject_stored", "eptv_backproject_interp",
+           "eptv_tv_gradient_vjp"]
 
 
 class EptvError(RuntimeError):
@@ -47,7 +49,8 @@ class _Params(C.Structure):
                 ("mu", C.c_double), ("lambda_", C.c_double), ("edge_quantile", C.c_double),
                 ("sigma_fixed", C.c_double), ("sigma_floor", C.c_double), ("tv_eps", C.c_double),
                 ("armijo_c", C.c_double), ("armijo_shrink", C.c_double), ("armijo_t0", C.c_double),
-                ("armijo_max_backtracks", C.c_int), ("p2_start", C.c_int), ("positivity", C.c_int)]
+                ("armijo_max_backtracks", C.c_int), ("p2_start", C.c_int), ("positivity", C.c_int),
+                ("stored_matrix", C.c_int), ("interp_bp", C.c_int)]
 
 
 class _Stats(C.Structure):
@@ -76,6 +79,8 @@ class Params:
     armijo_max_backtracks: int = 20
     p2_start: int = 0
     positivity: int = 1
+    stored_matrix: int = 0
+    interp_bp: int = 0
 
     def _c(self) -> _Params:
         d = asdict(self)
@@ -101,9 +106,15 @@ def _lib() -> C.CDLL:
         L.eptv_project_dual.argtypes = [vp, vp, vp, vp, C.c_float, C.c_float, vp]
         L.eptv_backproject.argtypes = [vp, vp, vp, C.c_float, C.c_float, vp, sz, vp]
         L.eptv_tv_gradient.argtypes = [vp, vp, vp, C.c_float, C.c_float, C.c_float, vp, vp, vp, vp, sz, vp]
+        L.eptv_tv_gradient_vjp.argtypes = [vp, vp, vp, C.c_float, C.c_float, C.c_float, vp, vp, sz, vp]
         L.eptv_select_sigma.argtypes = [vp, vp, C.c_double, C.c_float, C.c_float, vp, vp, sz, vp]
         L.eptv_tv_step.argtypes = [vp, C.POINTER(_Params), vp, vp, C.c_float, C.c_int, vp, sz, C.POINTER(_Stats), vp]
         L.eptv_reconstruct.argtypes = [vp, C.POINTER(_Params), vp, vp, vp, vp, sz, C.POINTER(_Stats), vp]
+        L.eptv_geometry_matrix.argtypes = [C.POINTER(_Geometry), C.POINTER(C.c_longlong), vp, vp, vp]
+        L.eptv_plan_store_matrix.argtypes = [vp, C.POINTER(sz)]
+        L.eptv_project_stored.argtypes = [vp, vp, vp, C.c_float, C.c_float, vp]
+        L.eptv_backproject_stored.argtypes = [vp, vp, vp, C.c_float, C.c_float, vp]
+        L.eptv_backproject_interp.argtypes = [vp, vp, vp, C.c_float, C.c_float, vp]
         L.eptv_status_string.argtypes = [C.c_int]
         L.eptv_status_string.restype = C.c_char_p
         L.eptv_last_error.restype = C.c_char_p
@@ -127,6 +138,37 @@ def _stream(stream) -> int:
     return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
 
 
+def _geometry(geom):
+    """(ctypes struct, keep-alive array) for a geometry object."""
+    import numpy as np
+    ang = getattr(geom, "view_angles_rad", None)
+    keep = None
+    ptr = None
+    if ang is not None:
+        keep = np.ascontiguousarray(np.asarray(ang, dtype=np.float64))
+        ptr = keep.ctypes.data_as(C.POINTER(C.c_double))
+    g = _Geometry(int(geom.nx), int(geom.ny), float(geom.pixel_mm), int(geom.n_views), ptr, int(geom.n_bins),
+                  float(geom.dbeta_rad), float(getattr(geom, "bin_offset", 0.0)), float(geom.sad_mm),
+                  float(geom.sdd_mm))
+    return g, keep
+
+
+def geometry_matrix(geom):
+    """The float32 system matrix the kernels evaluate, as host CSR arrays
+    (rowptr int64, col int32, val float32), computed on the host (no GPU)."""
+    import numpy as np
+    g, keep = _geometry(geom)
+    n = C.c_longlong()
+    _check(_lib().eptv_geometry_matrix(C.byref(g), C.byref(n), None, None, None), "eptv_geometry_matrix")
+    rp = np.zeros(int(geom.n_views) * int(geom.n_bins) + 1, np.int64)
+    col = np.zeros(n.value, np.int32)
+    val = np.zeros(n.value, np.float32)
+    _check(_lib().eptv_geometry_matrix(C.byref(g), C.byref(n), rp.ctypes.data, col.ctypes.data, val.ctypes.data),
+           "eptv_geometry_matrix")
+    del keep
+    return rp, col, val
+
+
 class Plan:
     """Geometry tables of one scanner geometry on one GPU (``eptv_plan``)."""
 
@@ -138,16 +180,7 @@ class Plan:
             self.device = torch.device("cuda", torch.cuda.current_device())
         self.nx, self.ny = int(geom.nx), int(geom.ny)
         self.n_views, self.n_bins = int(geom.n_views), int(geom.n_bins)
-        ang = getattr(geom, "view_angles_rad", None)
-        self._ang = None
-        ptr = None
-        if ang is not None:
-            import numpy as np
-            self._ang = np.ascontiguousarray(np.asarray(ang, dtype=np.float64))
-            ptr = self._ang.ctypes.data_as(C.POINTER(C.c_double))
-        g = _Geometry(self.nx, self.ny, float(geom.pixel_mm), self.n_views, ptr, self.n_bins,
-                      float(geom.dbeta_rad), float(getattr(geom, "bin_offset", 0.0)), float(geom.sad_mm),
-                      float(geom.sdd_mm))
+        g, self._ang = _geometry(geom)
         h = C.c_void_p()
         with torch.cuda.device(self.device):
             _check(_lib().eptv_plan_create(C.byref(g), C.byref(h)), "eptv_plan_create")
@@ -220,6 +253,38 @@ class Plan:
                                         _stream(stream)), "eptv_project_dual")
         return out
 
+    def store_matrix(self) -> int:
+        """Keep the float32 system matrix on the device (CSR + CSC); returns its bytes."""
+        n = C.c_size_t()
+        with torch.cuda.device(self.device):
+            _check(_lib().eptv_plan_store_matrix(self._h, C.byref(n)), "eptv_plan_store_matrix")
+        return int(n.value)
+
+    def project_stored(self, x: torch.Tensor, out: Optional[torch.Tensor] = None, alpha: float = 1.0,
+                       beta: float = 0.0, stream=None) -> torch.Tensor:
+        x = self._img(x, "x")
+        out = self._sino(out if out is not None else self.new_sinogram(), "out")
+        _check(_lib().eptv_project_stored(self._h, x.data_ptr(), out.data_ptr(), alpha, beta, _stream(stream)),
+               "eptv_project_stored")
+        return out
+
+    def backproject_stored(self, r: torch.Tensor, out: Optional[torch.Tensor] = None, alpha: float = 1.0,
+                           beta: float = 0.0, stream=None) -> torch.Tensor:
+        r = self._sino(r, "r")
+        out = self._img(out if out is not None else self.new_image(), "out")
+        _check(_lib().eptv_backproject_stored(self._h, r.data_ptr(), out.data_ptr(), alpha, beta, _stream(stream)),
+               "eptv_backproject_stored")
+        return out
+
+    def backproject_interp(self, r: torch.Tensor, out: Optional[torch.Tensor] = None, alpha: float = 1.0,
+                           beta: float = 0.0, stream=None) -> torch.Tensor:
+        """out = alpha B r + beta out, B the Eq. 11 interpolating backprojector."""
+        r = self._sino(r, "r")
+        out = self._img(out if out is not None else self.new_image(), "out")
+        _check(_lib().eptv_backproject_interp(self._h, r.data_ptr(), out.data_ptr(), alpha, beta, _stream(stream)),
+               "eptv_backproject_interp")
+        return out
+
     def backproject(self, r: torch.Tensor, out: Optional[torch.Tensor] = None, alpha: float = 1.0,
                     beta: float = 0.0, stream=None) -> torch.Tensor:
         """out = alpha P^T r + beta out."""
@@ -243,6 +308,16 @@ class Plan:
                                        wy.data_ptr() if wy is not None else None, ws.data_ptr(), ws.numel(),
                                        _stream(stream)), "eptv_tv_gradient")
         return g, wx, wy
+
+    def tv_gradient_vjp(self, f: torch.Tensor, u: torch.Tensor, lam: float, sigma: float, tv_eps: float,
+                        out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """(dg/df)^T u for the P2 direction g at f (sigma fixed)."""
+        f, u = self._img(f, "f"), self._img(u, "u")
+        out = self._img(out if out is not None else self.new_image(), "out")
+        ws = self.workspace()
+        _check(_lib().eptv_tv_gradient_vjp(self._h, f.data_ptr(), u.data_ptr(), lam, sigma, tv_eps, out.data_ptr(),
+                                           ws.data_ptr(), ws.numel(), _stream(stream)), "eptv_tv_gradient_vjp")
+        return out
 
     def select_sigma(self, f: torch.Tensor, q: float, tv_eps: float, sigma_floor: float = 1e-12,
                      stream=None) -> torch.Tensor:

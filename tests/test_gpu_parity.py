@@ -226,7 +226,8 @@ def run_pair(E, oracle, name, case, K, **kw):
     P = plan(E, name)
     M = matrix(oracle, name)
     y = case.y.astype(np.float32)
-    fo, so = M.reconstruct(y, oracle_params(oracle, K, **kw), f_ref=case.phantom)
+    okw = {k: v for k, v in kw.items() if k != "stored_matrix"}
+    fo, so = M.reconstruct(y, oracle_params(oracle, K, **okw), f_ref=case.phantom)
     prm = E.Params(outer_iters=K, lam=kw.pop("lam", 1000.0), **kw)
     f, sg = P.reconstruct(dev(y), prm, f_ref=dev(case.phantom))
     return f.cpu().numpy(), sg, fo, so
@@ -332,3 +333,66 @@ def test_zero_iterations_and_empty_steps(E):
     f1 = f0.clone()
     ks, _ = P.tv_step(f1, f0, E.Params(), 0, 0.01)
     assert len(ks) == 0 and torch.equal(f1, f0)
+
+
+# ------------------------------------------------------------------ the stored matrix (Sec. 2.3 look-up tables)
+
+@pytest.mark.parametrize("name", ["small", "paper", "ragged", "odd"])
+def test_stored_matrix_parity(E, oracle, name):
+    g = GEOMS[name]()
+    M, P = matrix(oracle, name), plan(E, name)
+    nbytes = P.store_matrix()
+    assert nbytes >= 16 * P.nnz
+    x = synth.random_image(g.nx, g.ny, 41)
+    r = synth.random_sinogram(g.n_views, g.n_bins, 42)
+    qs = P.project_stored(dev(x)).cpu().numpy()
+    zs = P.backproject_stored(dev(r)).cpu().numpy()
+    assert rel(qs, M.project(x)) <= 1e-5
+    assert rel(zs, M.backproject(r)) <= 1e-5
+    # the same float32 matrix as the on-the-fly kernels: only summation order differs
+    assert rel(qs, P.project(dev(x)).cpu().numpy()) <= 1e-6
+    assert rel(zs, P.backproject(dev(r)).cpu().numpy()) <= 1e-6
+    out = dev(q0 := synth.random_sinogram(g.n_views, g.n_bins, 43))
+    P.project_stored(dev(x), out, alpha=2.0, beta=-1.0)
+    assert rel(out.cpu().numpy(), 2.0 * M.project(x) - q0) <= 1e-5
+
+
+def test_reconstruct_stored_matrix(E, oracle):
+    c = synth.make_case("small", 0)
+    P = plan(E, "small")
+    P.store_matrix()
+    f, sg, fo, so = run_pair(E, oracle, "small", c, 50, stored_matrix=1)
+    assert well_separated(so)
+    assert np.array_equal(sg["armijo_k"], so["armijo_k"])
+    assert rel(f, fo) <= 1e-4
+
+
+# ------------------------------------------------------------------ Eq. 11 backprojector (App. III)
+
+@pytest.mark.parametrize("name", ["small", "paper", "ragged", "odd"])
+def test_backproject_interp_parity(E, oracle, name):
+    g = GEOMS[name]()
+    P = plan(E, name)
+    for seed, r in ((51, synth.random_sinogram(g.n_views, g.n_bins, 51)),
+                    (52, synth.make_case("small", 0).p if name == "small" else None)):
+        if r is None:
+            continue
+        z = P.backproject_interp(dev(r)).cpu().numpy()
+        assert rel(z, oracle.backproject_interp(g, r)) <= 1e-5, seed
+    c0 = synth.random_image(g.nx, g.ny, 53)
+    out = dev(c0)
+    P.backproject_interp(dev(r := synth.random_sinogram(g.n_views, g.n_bins, 54)), out, alpha=0.5, beta=2.0)
+    assert rel(out.cpu().numpy(), 0.5 * oracle.backproject_interp(g, r) + 2.0 * c0) <= 1e-5
+
+
+@pytest.mark.parametrize("K,kw", [(30, dict()), (5, dict(cgls_iters=0, mu=1.0, lam=2000.0, p2_start=1))])
+def test_reconstruct_interp_bp(E, oracle, K, kw):
+    """P1 with the Eq. 11 operator in place of P^T.  The gradient form of P1
+    with it is far less stable: the oracle's own image moves by 1.4e-6 after
+    10 iterations and 4e-5 after 20 for a 6e-8 relative change of y (1e-8
+    after 5), so it is compared over 5 iterations."""
+    c = synth.make_case("small", 0)
+    f, sg, fo, so = run_pair(E, oracle, "small", c, K, interp_bp=1, **kw)
+    assert well_separated(so)
+    assert np.array_equal(sg["armijo_k"], so["armijo_k"])
+    assert rel(f, fo) <= 1e-4
