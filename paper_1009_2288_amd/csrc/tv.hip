@@ -73,6 +73,20 @@ size_t n_edges(const Plan& p) { return (size_t)p.ny * (p.nx + 1) + (size_t)(p.ny
 // by a histogram of the keys that match the digits found so far, closed by a
 // one-block kernel that finds the digit whose bucket holds the rank.
 
+// LDS histogram increment.  Flat image regions give many identical
+// magnitudes (sqrt(eps^2)), so the lanes of a wave that share the first
+// active lane's bin add their count with one atomic; the others add one each.
+__device__ __forceinline__ void hist_add(uint32_t* h, uint32_t bin)
+{
+    const uint32_t lead = __builtin_amdgcn_readfirstlane(bin);
+    const unsigned long long same = __ballot(bin == lead);
+    if (bin == lead) {
+        if ((int)(threadIdx.x & 63) == __ffsll((long long)same) - 1) atomicAdd(&h[lead], (uint32_t)__popcll(same));
+    } else {
+        atomicAdd(&h[bin], 1u);
+    }
+}
+
 // Edge index: x-edge (i+1/2, j) -> j*(nx+1) + i+1; y-edge (i, j+1/2) -> ny*(nx+1) + (j+1)*nx + i.
 __global__ __launch_bounds__(256) void k_edges_hist(const float* __restrict__ f, int nx, int ny, float eps2,
                                                     uint32_t* keys, uint32_t* hist0)
@@ -87,19 +101,19 @@ __global__ __launch_bounds__(256) void k_edges_hist(const float* __restrict__ f,
         const size_t xo = (size_t)j * (nx + 1), yo = (size_t)ny * (nx + 1);
         uint32_t k = __float_as_uint(tv_right(N, eps2));
         keys[xo + i + 1] = k;
-        atomicAdd(&h[k >> 21], 1u);
+        hist_add(h, k >> 21);
         k = __float_as_uint(tv_up(N, eps2));
         keys[yo + (size_t)(j + 1) * nx + i] = k;
-        atomicAdd(&h[k >> 21], 1u);
+        hist_add(h, k >> 21);
         if (i == 0) {
             k = __float_as_uint(tv_left(N, eps2));
             keys[xo] = k;
-            atomicAdd(&h[k >> 21], 1u);
+            hist_add(h, k >> 21);
         }
         if (j == 0) {
             k = __float_as_uint(tv_down(N, eps2));
             keys[yo + i] = k;
-            atomicAdd(&h[k >> 21], 1u);
+            hist_add(h, k >> 21);
         }
     }
     __syncthreads();
@@ -129,7 +143,7 @@ __global__ __launch_bounds__(256) void k_select_hist(const uint32_t* __restrict_
     const uint32_t want = st->prefix >> hshift;
     for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
         const uint32_t k = keys[e];
-        if ((k >> hshift) == want) atomicAdd(&h[(k >> dshift) & dmask], 1u);
+        if ((k >> hshift) == want) hist_add(h, (k >> dshift) & dmask);
     }
     __syncthreads();
     for (int b = threadIdx.x; b < kSelectBins; b += 256)
@@ -280,10 +294,10 @@ __global__ __launch_bounds__(256) void k_tv_grad(const float* __restrict__ f, co
     if (part) {
         const double qs = block_sum<256>(q, lds);
         const double gs = block_sum<256>(gg, lds);
-        if (threadIdx.x == 0) {
-            const int b = blockIdx.y * gridDim.x + blockIdx.x;
-            part[2 * b] = qs;
-            part[2 * b + 1] = gs;
+        if (threadIdx.x == 0) {  // slot-major: [Q | ||g||^2][block]
+            const int b = blockIdx.y * gridDim.x + blockIdx.x, nb = gridDim.x * gridDim.y;
+            part[b] = qs;
+            part[nb + b] = gs;
         }
     }
 }
@@ -314,7 +328,7 @@ __device__ __forceinline__ float cand_t(float t0, float shrink, int k)
 __host__ __device__ __forceinline__ int pass_first(int pass) { return pass == 0 ? 0 : kArmijoFirst + kArmijoMore * (pass - 1); }
 
 // Q(f - t_k g) for the NC candidates of one pass, with the weights frozen at
-// f: per-block partial sums, [block][kArmijoSlots].
+// f: per-block partial sums, slot-major [kArmijoSlots][block].
 template <int NC>
 __global__ __launch_bounds__(256) void k_armijo(const float* __restrict__ f, const float* __restrict__ g,
                                                 const float* __restrict__ v, const float* __restrict__ wx,
@@ -361,7 +375,7 @@ __global__ __launch_bounds__(256) void k_armijo(const float* __restrict__ f, con
     __syncthreads();
     if (threadIdx.x < NC) {
         const int c = threadIdx.x;
-        part[(size_t)(blockIdx.y * gridDim.x + blockIdx.x) * kArmijoSlots + c] =
+        part[(size_t)c * (gridDim.x * gridDim.y) + blockIdx.y * gridDim.x + blockIdx.x] =
             red[0][c] + red[1][c] + red[2][c] + red[3][c];
     }
 }
@@ -386,10 +400,11 @@ hipError_t launch_armijo(const Plan& p, int pass, const float* f, const float* g
 // Pass 0 also closes Q0 and ||g||^2 from the gradient kernel's partials.
 // After the last allowed candidate without acceptance the step is skipped
 // (k = -1, t = 0).  The accepted index is recorded for the iteration.
-// One block of 1024 threads: thread t loads the partial rows of blocks t,
-// t + 1024, ... (all loads in flight together; the partials come from every
-// XCD, so each load is a far one), then every slot is summed by a fixed
-// butterfly within each wave and over the 16 waves in order.
+// One block of 1024 threads: thread t loads the partials of blocks t,
+// t + 1024, ... of every slot (slot-major, so each wave load is contiguous;
+// all loads are in flight together, and they are far ones: the partials were
+// written on every XCD), then every slot is summed by a fixed butterfly within
+// each wave and over the 16 waves in order.
 constexpr int kFinThreads = 1024;
 constexpr int kFinVals = kArmijoSlots + 2;
 
@@ -404,18 +419,14 @@ __global__ __launch_bounds__(kFinThreads) void k_armijo_finalize(DevState* st, c
     double v[kFinVals];
 #pragma unroll
     for (int c = 0; c < kFinVals; ++c) v[c] = 0.0;
+    const int nc = pass == 0 ? kArmijoFirst : kArmijoMore;
     for (int b = threadIdx.x; b < nb; b += kFinThreads) {
-        const double2* row = reinterpret_cast<const double2*>(part_arm + (size_t)b * kArmijoSlots);
 #pragma unroll
-        for (int c = 0; c < kArmijoSlots / 2; ++c) {
-            const double2 x = row[c];
-            v[2 * c] += x.x;
-            v[2 * c + 1] += x.y;
-        }
+        for (int c = 0; c < kArmijoSlots; ++c)
+            if (c < nc) v[c] += part_arm[(size_t)c * nb + b];
         if (pass == 0) {
-            const double2 gq = reinterpret_cast<const double2*>(part_grad)[b];
-            v[kArmijoSlots] += gq.x;
-            v[kArmijoSlots + 1] += gq.y;
+            v[kArmijoSlots] += part_grad[b];
+            v[kArmijoSlots + 1] += part_grad[nb + b];
         }
     }
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -438,7 +449,7 @@ __global__ __launch_bounds__(kFinThreads) void k_armijo_finalize(DevState* st, c
         }
         const double q0 = pass == 0 ? tot[kArmijoSlots] : st->q0;
         const double g2 = pass == 0 ? tot[kArmijoSlots + 1] : st->gg;
-        const int first = pass_first(pass), nc = pass == 0 ? kArmijoFirst : kArmijoMore;
+        const int first = pass_first(pass);
         int kk = -1;
         float tk = 0.0f;
         for (int cc = 0; cc < nc; ++cc) {
