@@ -97,6 +97,35 @@ def time_to_rmse(E, synth, P, base, torch, np, seeds):
             "per_seed": per}
 
 
+def batch_leg(E, synth, torch, np, n_slices, iters, warmup):
+    """The batched workload: n_slices slices of 256^2 / 384^2 / 512^2, 20-60
+    views, 368-736 bins, I0 1e4-1e5 (seed 0), every phase one launch over all
+    slices, one captured graph per outer iteration, launch shapes from the
+    tuner."""
+    cases = synth.batch_cases(n_slices, 0, with_phantom=False)
+    B = E.Batch([c.geom for c in cases])
+    tuned = B.tune(reps=5)
+    ys = [torch.from_numpy(c.y.astype(np.float32)).cuda() for c in cases]
+    prm = dict(cgls_iters=3, tv_iters=5, lam=1000.0, edge_quantile=0.9, tv_eps=1e-4)
+    fs, _ = B.reconstruct(ys, E.Params(outer_iters=warmup, zero_init=1, **prm), stats=False)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    B.reconstruct(ys, E.Params(outer_iters=iters, zero_init=0, **prm), fs=fs, stats=False)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / iters
+    work = sum(c.geom.nx * c.geom.ny * c.geom.n_views for c in cases) / (512 * 512 * 40)
+    return {"slices": n_slices, "iterations": iters, "ms_per_batch_iteration": ms,
+            "slice_iterations_per_s": n_slices * 1e3 / ms,
+            "work_in_512x512x40_slices": work,
+            "equivalent_512x512x40_iterations_per_s": work * 1e3 / ms,
+            "launch": tuned,
+            "workload": "64 seeded slices, side uniform in {256, 384, 512} (1 mm), views 20-60, bins 368-736, "
+                        "I0 log-uniform 1e4-1e5; per iteration 3 CGLS steps, adaptive sigma, 5 Armijo steps"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +135,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rmse-seeds", type=int, default=10, help="seeds for the time-to-RMSE leg (0 to skip)")
+    ap.add_argument("--batch-slices", type=int, default=64, help="slices of the batched leg (0 to skip)")
+    ap.add_argument("--batch-iters", type=int, default=20)
     ap.add_argument("--operator", choices=["fly", "stored"], default="fly",
                     help="P and P^T on the fly, or from the stored float32 matrix")
     args = ap.parse_args()
@@ -196,6 +227,13 @@ def main():
         ttr = time_to_rmse(eptv, synth, P, base, torch, np, range(args.rmse_seeds))
         log(f"bench: plain EPTV reaches the oracle RMSE in {ttr['plain_seconds_median']} s (median)")
 
+    bat = None
+    if args.batch_slices > 0:
+        log(f"bench: batched leg, {args.batch_slices} slices")
+        bat = batch_leg(eptv, synth, torch, np, args.batch_slices, args.batch_iters, 3)
+        log(f"bench: batch {bat['ms_per_batch_iteration']:.3f} ms per iteration of all slices, "
+            f"{bat['equivalent_512x512x40_iterations_per_s']:.1f} equivalent 512^2/40 it/s, launch {bat['launch']}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"bench: CPU oracle baseline, {args.cpu_iters} iterations")
@@ -222,6 +260,7 @@ def main():
                    "graph": os.environ.get("EPTV_NO_GRAPH", "0") in ("", "0"), "operator": args.operator},
         "rmse_vs_phantom": rmse,
         "time_to_rmse": ttr,
+        "batch": bat,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -224,6 +224,47 @@ int eptv_tv_step(eptv_plan plan, const eptv_params* params, float* f, const floa
 int eptv_reconstruct(eptv_plan plan, const eptv_params* params, const float* y, float* f,
                      const float* f_ref, void* ws, size_t ws_bytes, eptv_stats* stats, void* stream);
 
+/* ------------------------------------------------------------------ batches
+ * Many slices, each with its own geometry (image size, views, bins), iterated
+ * together: every phase of the EPTV iteration (Sec. 2.2) is one launch for
+ * the whole batch, a persistent grid walking a list of (slice, block) items,
+ * and one outer iteration of all slices is one captured graph.  Each slice's
+ * arithmetic is that of eptv_reconstruct on its own plan; with the
+ * projector's launch shape at 16 segments (the one-slice default) the images
+ * are identical bit for bit.  The stored-matrix and Eq. 11 variants are
+ * one-slice only (EPTV_ERR_ARG here). */
+typedef struct eptv_batch_s* eptv_batch;
+
+/* One plan per geometry (geoms[0 .. n_slices-1]); owns them. */
+int eptv_batch_create(const eptv_geometry* geoms, int n_slices, eptv_batch* out);
+int eptv_batch_destroy(eptv_batch batch);
+int eptv_batch_size(eptv_batch batch, int* n_slices);
+/* The plan of one slice (owned by the batch), for one-slice calls. */
+int eptv_batch_plan(eptv_batch batch, int slice, eptv_plan* plan);
+/* Workspace bytes for eptv_batch_reconstruct with these params. */
+int eptv_batch_workspace_bytes(eptv_batch batch, const eptv_params* params, size_t* bytes);
+
+/* Launch shapes: projector sweep segments per block (4, 8 or 16) and
+ * persistent blocks per compute unit for the projector and for the
+ * tile-shaped phases (1..64).  eptv_batch_tune chooses them by timing. */
+int eptv_batch_set_launch(eptv_batch batch, int proj_seg, int proj_blocks_per_cu, int tile_blocks_per_cu);
+int eptv_batch_get_launch(eptv_batch batch, int* proj_seg, int* proj_grid, int* tile_grid);
+/* The launch-shape tuner: times the batched projector (sweep segments 4/8/16
+ * x 1/2/4 blocks per CU) and backprojector (2/4/8/16 blocks per CU) on
+ * scratch data, reps launches each, and keeps the fastest; reports their
+ * average times (may be NULL).  Allocates and frees scratch device memory;
+ * synchronises the stream. */
+int eptv_batch_tune(eptv_batch batch, int reps, void* stream, float* proj_ms, float* backproj_ms);
+
+/* params.outer_iters EPTV iterations on every slice: y[i] (device
+ * [V_i][B_i]), f[i] (device [ny_i][nx_i], warm start unless zero_init,
+ * result), f_ref (NULL, or an array of reference images for the RMSE
+ * record); host arrays of n_slices device pointers.  stats: NULL or an array
+ * of n_slices records (synchronises the stream).  ws: 256-byte aligned
+ * device workspace of eptv_batch_workspace_bytes. */
+int eptv_batch_reconstruct(eptv_batch batch, const eptv_params* params, const float* const* y, float* const* f,
+                           const float* const* f_ref, void* ws, size_t ws_bytes, eptv_stats* stats, void* stream);
+
 const char* eptv_status_string(int status);
 
 /* Last HIP error text seen by the library on this thread ("" if none). */

@@ -13,26 +13,19 @@
 //            b_m = gamma_{m+1} / gamma_m, s = P^T r_{m+1} + b_m s.
 // Breakdown (delta_m = 0, or gamma_m <= 1e-30 gamma_0) freezes the iterate for
 // the remaining steps.
+#include "batch.h"
 #include "eptv_internal.h"
 #include "reduce.h"
 
 namespace eptv {
 
+__device__ __forceinline__ void reset_iteration_state(DevState* st, uint32_t* hist, float sigma_fixed);
+
 __global__ void k_state_init(DevState* st, uint32_t* hist, uint32_t rank, float sigma_fixed, int zero_iter)
 {
-    const int t = threadIdx.x;
-    for (int i = t; i < 3 * kSelectBins; i += blockDim.x) hist[i] = 0u;
-    if (t == 0) {
-        st->cg_steps = 0;
-        st->prefix = 0u;
-        st->rank = rank;
-        st->sigma = sigma_fixed;
-        st->inv_sigma2 = sigma_fixed >= 0.0f ? 1.0f / (sigma_fixed * sigma_fixed) : 0.0f;
-        st->decided = 0;
-        st->k = -1;
-        st->t = 0.0f;
-        if (zero_iter) st->iter = 0;
-    }
+    if (threadIdx.x == 0) st->rank0 = rank;
+    reset_iteration_state(st, hist, sigma_fixed);
+    if (threadIdx.x == 0 && zero_iter) st->iter = 0;
 }
 
 hipError_t launch_state_init(DevState* st, uint32_t* hist, uint32_t rank, float sigma_fixed, int zero_iter,
@@ -52,20 +45,18 @@ int sino_blocks(const Plan& p) { return (int)(((size_t)p.V * p.B + 1023) / 1024)
 constexpr int kAxpyBlock = 256;
 constexpr int kAxpyPer = 4;
 
-__global__ __launch_bounds__(kAxpyBlock) void k_cgls_axpy(DevState* st, int m, const double* part_bp, int n_bp,
-                                                          const double* part_proj, int n_proj, size_t n_img,
-                                                          size_t n_sino, int img_blocks, const float* u_in,
-                                                          float* u, const float* sdir, float* r, const float* q,
-                                                          double* part_res)
+__device__ __forceinline__ void cgls_axpy_block(DevState* st, int m, const double* part_bp, int n_bp,
+                                                const double* part_proj, int n_proj, size_t n_img, size_t n_sino,
+                                                int img_blocks, const float* u_in, float* u, const float* sdir,
+                                                float* r, const float* q, double* part_res, int blk, double* lds)
 {
-    __shared__ double lds[4];
     const double g = m == 0 ? block_sum_partials<kAxpyBlock>(part_bp, n_bp, 1, lds) : st->gamma[m];
     const double d = block_sum_partials<kAxpyBlock>(part_proj, n_proj, 1, lds);
     const double g0 = m == 0 ? g : st->gamma0;
     const int was = m == 0 ? 1 : st->active[m - 1];
     const int active = was && (g > 1e-30 * g0) && (d > 0.0);
     const float a = active ? (float)(g / d) : 0.0f;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blk == 0 && threadIdx.x == 0) {
         if (m == 0) {
             st->gamma[0] = g;
             st->gamma0 = g;
@@ -74,15 +65,15 @@ __global__ __launch_bounds__(kAxpyBlock) void k_cgls_axpy(DevState* st, int m, c
         st->active[m] = active;
         if (active) st->cg_steps = m + 1;
     }
-    if ((int)blockIdx.x < img_blocks) {
-        const size_t base = (size_t)blockIdx.x * kAxpyBlock * kAxpyPer + threadIdx.x;
+    if (blk < img_blocks) {
+        const size_t base = (size_t)blk * kAxpyBlock * kAxpyPer + threadIdx.x;
 #pragma unroll
         for (int e = 0; e < kAxpyPer; ++e) {
             const size_t i = base + (size_t)e * kAxpyBlock;
             if (i < n_img) u[i] = fmaf(a, sdir[i], u_in[i]);
         }
     } else {
-        const size_t base = (size_t)(blockIdx.x - img_blocks) * kAxpyBlock * kAxpyPer + threadIdx.x;
+        const size_t base = (size_t)(blk - img_blocks) * kAxpyBlock * kAxpyPer + threadIdx.x;
         double r2 = 0.0;
 #pragma unroll
         for (int e = 0; e < kAxpyPer; ++e) {
@@ -95,12 +86,23 @@ __global__ __launch_bounds__(kAxpyBlock) void k_cgls_axpy(DevState* st, int m, c
         }
         if (part_res) {
             r2 = block_sum<kAxpyBlock>(r2, lds);
-            if (threadIdx.x == 0) part_res[blockIdx.x - img_blocks] = r2;
+            if (threadIdx.x == 0) part_res[blk - img_blocks] = r2;
         }
     }
 }
 
-static int axpy_blocks(size_t n) { return (int)((n + kAxpyBlock * kAxpyPer - 1) / (kAxpyBlock * kAxpyPer)); }
+__global__ __launch_bounds__(kAxpyBlock) void k_cgls_axpy(DevState* st, int m, const double* part_bp, int n_bp,
+                                                          const double* part_proj, int n_proj, size_t n_img,
+                                                          size_t n_sino, int img_blocks, const float* u_in,
+                                                          float* u, const float* sdir, float* r, const float* q,
+                                                          double* part_res)
+{
+    __shared__ double lds[4];
+    cgls_axpy_block(st, m, part_bp, n_bp, part_proj, n_proj, n_img, n_sino, img_blocks, u_in, u, sdir, r, q,
+                    part_res, blockIdx.x, lds);
+}
+
+int axpy_blocks(size_t n) { return (int)((n + kAxpyBlock * kAxpyPer - 1) / (kAxpyBlock * kAxpyPer)); }
 
 hipError_t launch_cgls_axpy(const Plan& p, DevState* st, int m, const double* part_bp, const double* part_proj,
                             const float* u_in, float* u, const float* sdir, float* r, const float* q,
@@ -116,19 +118,17 @@ hipError_t launch_cgls_axpy(const Plan& p, DevState* st, int m, const double* pa
 // s = z + b_m s, written row-major and transposed (the projector reads both);
 // b_m = gamma_{m+1} / gamma_m with gamma_{m+1} summed from the backprojector's
 // partials and recorded for step m+1.
-__global__ __launch_bounds__(256) void k_cgls_supdate(DevState* st, int m, const double* part_bp, int n_bp,
-                                                      const float* __restrict__ z, float* sdir, float* sdirT, int nx,
-                                                      int ny)
+__device__ __forceinline__ void cgls_supdate_block(DevState* st, int m, const double* part_bp, int n_bp,
+                                                   const float* __restrict__ z, float* sdir, float* sdirT, int nx,
+                                                   int ny, int tbx, int tby, float (*t)[33], double* lds)
 {
-    __shared__ float t[32][33];
-    __shared__ double lds[4];
     const double gn = block_sum_partials<256>(part_bp, n_bp, 1, lds);
     const float bm = st->active[m] ? (float)(gn / st->gamma[m]) : 0.0f;
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    if (tbx == 0 && tby == 0 && threadIdx.x == 0) {
         st->gamma[m + 1] = gn;
         st->b[m] = bm;
     }
-    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const int bx = tbx * 32, by = tby * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     for (int k = ty; k < 32; k += 8) {
         const int i = bx + tx, j = by + k;
@@ -147,6 +147,15 @@ __global__ __launch_bounds__(256) void k_cgls_supdate(DevState* st, int m, const
     }
 }
 
+__global__ __launch_bounds__(256) void k_cgls_supdate(DevState* st, int m, const double* part_bp, int n_bp,
+                                                      const float* __restrict__ z, float* sdir, float* sdirT, int nx,
+                                                      int ny)
+{
+    __shared__ float t[32][33];
+    __shared__ double lds[4];
+    cgls_supdate_block(st, m, part_bp, n_bp, z, sdir, sdirT, nx, ny, blockIdx.x, blockIdx.y, t, lds);
+}
+
 hipError_t launch_cgls_supdate(const Plan& p, DevState* st, int m, const double* part_bp, const float* z,
                                float* sdir, float* sdirT, hipStream_t s)
 {
@@ -157,10 +166,15 @@ hipError_t launch_cgls_supdate(const Plan& p, DevState* st, int m, const double*
 }
 
 // Gradient form of P1 (Eq. 8): v = f - mu/lambda P^T (P f - y) = f + step * P^T r.
-__global__ void k_gd_p1(const float* f, const float* z, float step, float* u, size_t n)
+__device__ __forceinline__ void gd_p1_block(const float* f, const float* z, float step, float* u, size_t n, int blk,
+                                            int nblk)
 {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        u[i] = fmaf(step, z[i], f[i]);
+    for (size_t i = (size_t)blk * 256 + threadIdx.x; i < n; i += (size_t)nblk * 256) u[i] = fmaf(step, z[i], f[i]);
+}
+
+__global__ __launch_bounds__(256) void k_gd_p1(const float* f, const float* z, float step, float* u, size_t n)
+{
+    gd_p1_block(f, z, step, u, n, blockIdx.x, gridDim.x);
 }
 
 hipError_t launch_gd_p1(const Plan& p, const float* f, const float* z, float step, float* u, hipStream_t s)
@@ -172,16 +186,22 @@ hipError_t launch_gd_p1(const Plan& p, const float* f, const float* z, float ste
 }
 
 // ------------------------------------------------------------------ bookkeeping
-__global__ __launch_bounds__(256) void k_rmse_part(const float* f, const float* ref, size_t n, double* part)
+__device__ __forceinline__ void rmse_part_block(const float* f, const float* ref, size_t n, double* part, int blk,
+                                                int nblk, double* lds)
 {
-    __shared__ double lds[4];
     double acc = 0.0;
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    for (size_t i = (size_t)blk * 256 + threadIdx.x; i < n; i += (size_t)nblk * 256) {
         const double d = (double)f[i] - (double)ref[i];
         acc += d * d;
     }
     acc = block_sum<256>(acc, lds);
-    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+    if (threadIdx.x == 0) part[blk] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_rmse_part(const float* f, const float* ref, size_t n, double* part)
+{
+    __shared__ double lds[4];
+    rmse_part_block(f, ref, n, part, blockIdx.x, gridDim.x, lds);
 }
 
 hipError_t launch_rmse_part(const Plan& p, const float* f, const float* ref, double* part, hipStream_t s)
@@ -190,13 +210,28 @@ hipError_t launch_rmse_part(const Plan& p, const float* f, const float* ref, dou
     return hipGetLastError();
 }
 
-// Per-iteration records, then the iteration counter.
-__global__ __launch_bounds__(256) void k_iter_end(DevState* st, const double* part_res, int n_res, int with_resid,
-                                                  const double* part_rmse, int with_rmse, double npix,
-                                                  float* st_sigma, int32_t* st_steps, double* st_resid,
-                                                  double* st_rmse)
+// Per-iteration records, the iteration counter, and the reset of the
+// per-iteration state for the next iteration (histograms, CGLS step count,
+// selection prefix, sigma, step decision), so no kernel of its own is needed.
+__device__ __forceinline__ void reset_iteration_state(DevState* st, uint32_t* hist, float sigma_fixed)
 {
-    __shared__ double lds[4];
+    for (int i = threadIdx.x; i < 3 * kSelectBins; i += blockDim.x) hist[i] = 0u;
+    if (threadIdx.x == 0) {
+        st->cg_steps = 0;
+        st->prefix = 0u;
+        st->rank = st->rank0;
+        st->sigma = sigma_fixed;
+        st->inv_sigma2 = sigma_fixed >= 0.0f ? 1.0f / (sigma_fixed * sigma_fixed) : 0.0f;
+        st->k = -1;
+        st->t = 0.0f;
+    }
+}
+
+__device__ __forceinline__ void iter_end_block(DevState* st, const double* part_res, int n_res, int with_resid,
+                                               const double* part_rmse, int with_rmse, double npix, float* st_sigma,
+                                               int32_t* st_steps, double* st_resid, double* st_rmse, uint32_t* hist,
+                                               float sigma_fixed, double* lds)
+{
     const double res = with_resid ? block_sum_partials<256>(part_res, n_res, 1, lds) : 0.0;
     const double e = with_rmse ? block_sum_partials<256>(part_rmse, kRmseBlocks, 1, lds) : 0.0;
     if (threadIdx.x == 0) {
@@ -207,14 +242,153 @@ __global__ __launch_bounds__(256) void k_iter_end(DevState* st, const double* pa
         if (with_rmse && st_rmse) st_rmse[it] = sqrt(e / npix);
         st->iter = it + 1;
     }
+    __syncthreads();
+    reset_iteration_state(st, hist, sigma_fixed);
+}
+
+__global__ __launch_bounds__(256) void k_iter_end(DevState* st, const double* part_res, int n_res, int with_resid,
+                                                  const double* part_rmse, int with_rmse, double npix,
+                                                  float* st_sigma, int32_t* st_steps, double* st_resid,
+                                                  double* st_rmse, uint32_t* hist, float sigma_fixed)
+{
+    __shared__ double lds[4];
+    iter_end_block(st, part_res, n_res, with_resid, part_rmse, with_rmse, npix, st_sigma, st_steps, st_resid, st_rmse,
+                   hist, sigma_fixed, lds);
 }
 
 hipError_t launch_iter_end(const Plan& p, DevState* st, const double* part_res, int with_resid,
                            const double* part_rmse, int with_rmse, float* st_sigma, int32_t* st_steps,
-                           double* st_resid, double* st_rmse, hipStream_t s)
+                           double* st_resid, double* st_rmse, uint32_t* hist, float sigma_fixed, hipStream_t s)
 {
     hipLaunchKernelGGL(k_iter_end, dim3(1), dim3(256), 0, s, st, part_res, sino_blocks(p), with_resid, part_rmse,
-                       with_rmse, (double)p.nx * p.ny, st_sigma, st_steps, st_resid, st_rmse);
+                       with_rmse, (double)p.nx * p.ny, st_sigma, st_steps, st_resid, st_rmse, hist, sigma_fixed);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ batched kernels (see batch.h)
+__global__ __launch_bounds__(kAxpyBlock) void kb_cgls_axpy(const SliceDev* __restrict__ sl,
+                                                           const int2* __restrict__ items, int n_items, int m,
+                                                           int u_ins, int with_res)
+{
+    __shared__ double lds[4];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 w = items[it];
+        const SliceDev& d = sl[w.x];
+        __syncthreads();
+        cgls_axpy_block(d.st, m, d.part[kPartBp], d.t16x * d.t16y, d.part[kPartProj], d.proj_gx * d.V,
+                        (size_t)d.nx * d.ny, (size_t)d.V * d.B, d.axpy_img, d.buf[u_ins], d.buf[kBufU],
+                        d.buf[kBufS], d.buf[kBufR], d.buf[kBufQ], with_res ? d.part[kPartRes] : nullptr, w.y, lds);
+    }
+}
+
+hipError_t blaunch_cgls_axpy(const BatchDev& b, int m, int u_in, bool with_res, hipStream_t s)
+{
+    const int n = b.n_items[kShAxpy];
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(kb_cgls_axpy, dim3(b.grid[kShAxpy]), dim3(kAxpyBlock), 0, s, b.slices, b.items[kShAxpy], n, m,
+                       u_in, (int)with_res);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void kb_cgls_supdate(const SliceDev* __restrict__ sl, const int2* __restrict__ items,
+                                                       int n_items, int m)
+{
+    __shared__ float t[32][33];
+    __shared__ double lds[4];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 w = items[it];
+        const SliceDev& d = sl[w.x];
+        __syncthreads();
+        cgls_supdate_block(d.st, m, d.part[kPartBp], d.t16x * d.t16y, d.buf[kBufZ], d.buf[kBufS], d.buf[kBufST], d.nx,
+                           d.ny, w.y % d.t32x, w.y / d.t32x, t, lds);
+    }
+}
+
+hipError_t blaunch_cgls_supdate(const BatchDev& b, int m, hipStream_t s)
+{
+    const int n = b.n_items[kShT32];
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(kb_cgls_supdate, dim3(b.grid[kShT32]), dim3(256), 0, s, b.slices, b.items[kShT32], n, m);
+    return hipGetLastError();
+}
+
+// gradient form of P1 over 32x32 tiles: u = f + step z
+__global__ __launch_bounds__(256) void kb_gd_p1(const SliceDev* __restrict__ sl, const int2* __restrict__ items,
+                                                int n_items, float step)
+{
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 w = items[it];
+        const SliceDev& d = sl[w.x];
+        const int bx = (w.y % d.t32x) * 32, by = (w.y / d.t32x) * 32;
+        const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+        for (int k = ty; k < 32; k += 8) {
+            const int i = bx + tx, j = by + k;
+            if (i < d.nx && j < d.ny) {
+                const size_t id = (size_t)j * d.nx + i;
+                d.buf[kBufU][id] = fmaf(step, d.buf[kBufZ][id], d.buf[kBufF][id]);
+            }
+        }
+    }
+}
+
+hipError_t blaunch_gd_p1(const BatchDev& b, float step, hipStream_t s)
+{
+    const int n = b.n_items[kShT32];
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(kb_gd_p1, dim3(b.grid[kShT32]), dim3(256), 0, s, b.slices, b.items[kShT32], n, step);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void kb_rmse_part(const SliceDev* __restrict__ sl, const int2* __restrict__ items,
+                                                    int n_items, int fs)
+{
+    __shared__ double lds[4];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 w = items[it];
+        const SliceDev& d = sl[w.x];
+        if (!d.buf[kBufFRef]) continue;  // uniform per item
+        __syncthreads();
+        rmse_part_block(d.buf[fs], d.buf[kBufFRef], (size_t)d.nx * d.ny, d.part[kPartRmse], w.y, kRmseBlocks, lds);
+    }
+}
+
+hipError_t blaunch_rmse_part(const BatchDev& b, int f, hipStream_t s)
+{
+    const int n = b.n_items[kShRmse];
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(kb_rmse_part, dim3(b.grid[kShRmse]), dim3(256), 0, s, b.slices, b.items[kShRmse], n, f);
+    return hipGetLastError();
+}
+
+// one block per slice
+__global__ __launch_bounds__(256) void kb_iter_end(const SliceDev* __restrict__ sl, int with_resid, int with_rmse,
+                                                   float sigma_fixed)
+{
+    __shared__ double lds[4];
+    const SliceDev& d = sl[blockIdx.x];
+    const int rm = with_rmse && d.buf[kBufFRef] != nullptr;
+    iter_end_block(d.st, d.part[kPartRes], d.axpy_sino, with_resid, d.part[kPartRmse], rm, (double)d.nx * d.ny,
+                   d.st_sigma, d.st_steps, d.st_resid, d.st_rmse, d.hist, sigma_fixed, lds);
+}
+
+hipError_t blaunch_iter_end(const BatchDev& b, bool with_resid, bool with_rmse, float sigma_fixed, hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_iter_end, dim3(b.n), dim3(256), 0, s, b.slices, (int)with_resid, (int)with_rmse,
+                       sigma_fixed);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void kb_state_init(const SliceDev* __restrict__ sl, float sigma_fixed, int zero_iter)
+{
+    const SliceDev& d = sl[blockIdx.x];
+    if (threadIdx.x == 0) d.st->rank0 = d.rank;
+    reset_iteration_state(d.st, d.hist, sigma_fixed);
+    if (threadIdx.x == 0 && zero_iter) d.st->iter = 0;
+}
+
+hipError_t blaunch_state_init(const BatchDev& b, float sigma_fixed, int zero_iter, hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_state_init, dim3(b.n), dim3(256), 0, s, b.slices, sigma_fixed, zero_iter);
     return hipGetLastError();
 }
 

@@ -75,9 +75,8 @@ __host__ __device__ __forceinline__ CellW cell_weights(long long lo, long long s
 // ---------------------------------------------------------------- device state
 constexpr int kMaxCgls = 64;
 constexpr int kSelectBins = 2048;  // 11-bit radix digits
-constexpr int kArmijoFirst = 8;    // Armijo candidates k = 0..7 in the first pass
-constexpr int kArmijoMore = 16;    // candidates per later pass
-constexpr int kArmijoSlots = 16;   // partial slots per block
+constexpr int kArmijoFirst = 8;    // Armijo candidates k = 0..7, evaluated by the whole grid
+constexpr int kArmijoMore = 16;    // candidates per round of the rare longer search
 
 // Scalars that stay on the device.  Each entry is written by one kernel and
 // read only by later kernels on the stream (never by the writer's own grid).
@@ -90,12 +89,12 @@ struct DevState {
     int cg_steps;
     // sigma selection
     uint32_t prefix;
-    uint32_t rank;
+    uint32_t rank;               // rank still to find below the digits chosen so far
+    uint32_t rank0;              // the order statistic's rank (set once per run)
     float sigma;
     float inv_sigma2;
     // P2 (Armijo): the current step's energies and decision
     double q0, gg;
-    int decided;
     int k;
     float t;
     // bookkeeping
@@ -149,7 +148,7 @@ struct Workspace {
     double* part_proj;  // ||P s||^2 per projector block
     double* part_bp;    // ||P^T r||^2 per backprojector block
     double* part_grad;  // (Q, ||g||^2) per gradient block
-    double* part_arm;   // kArmijoSlots candidate energies per Armijo block
+    double* part_arm;   // kArmijoFirst candidate energies per Armijo block (slot-major)
     double* part_res;   // ||r||^2 per sinogram block of the last CGLS axpy
     double* part_rmse;  // (f - f_ref)^2 per block
     DevState* st;
@@ -217,12 +216,13 @@ hipError_t launch_tv_grad(const Plan& p, const float* f, const float* g_prev, co
                           float* f_out, const float* v, float lambda, const DevState* st,
                           float sigma_direct, float eps2, float* g, float* wx, float* wy, double* part,
                           hipStream_t s);
-hipError_t launch_armijo(const Plan& p, int pass, const float* f, const float* g, const float* v,
-                         const float* wx, const float* wy, float lambda, float eps2, float t0,
-                         float shrink, const DevState* st, double* part, hipStream_t s);
-hipError_t launch_armijo_finalize(const Plan& p, DevState* st, const double* part_grad,
-                                  const double* part_arm, int pass, int max_bt, double c_arm, float t0,
-                                  float shrink, int32_t* st_k, int step, int T, hipStream_t s);
+hipError_t launch_armijo(const Plan& p, const float* f, const float* g, const float* v, const float* wx,
+                         const float* wy, float lambda, float eps2, float t0, float shrink, double* part,
+                         hipStream_t s);
+hipError_t launch_armijo_decide(const Plan& p, DevState* st, const double* part_grad, const double* part_arm,
+                                int max_bt, double c_arm, float t0, float shrink, int32_t* st_k, int step, int T,
+                                const float* f, const float* g, const float* v, const float* wx, const float* wy,
+                                float lambda, float eps2, hipStream_t s);
 hipError_t launch_p2_update(const Plan& p, const DevState* st, const float* fcur, const float* g,
                             float* fout, float* foutT, int clamp, hipStream_t s);
 hipError_t launch_copy_clamp(const Plan& p, const float* src, float* dst, float* dstT, int clamp,
@@ -233,6 +233,6 @@ hipError_t launch_rmse_part(const Plan& p, const float* f, const float* ref, dou
                             hipStream_t s);
 hipError_t launch_iter_end(const Plan& p, DevState* st, const double* part_res, int with_resid,
                            const double* part_rmse, int with_rmse, float* st_sigma, int32_t* st_steps,
-                           double* st_resid, double* st_rmse, hipStream_t s);
+                           double* st_resid, double* st_rmse, uint32_t* hist, float sigma_fixed, hipStream_t s);
 
 }  // namespace eptv

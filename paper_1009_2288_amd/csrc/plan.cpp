@@ -12,29 +12,21 @@
 
 #include "eptv_internal.h"
 #include "geometry.h"
+#include "host_internal.h"
 
 #include <vector>
-
-struct eptv_plan_s {
-    eptv::Plan p;
-    std::mutex graph_mu;
-};
 
 namespace eptv {
 
 static thread_local std::string g_last_error;
 
-static int hip_fail(hipError_t e, const char* what)
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+int hip_fail(hipError_t e, const char* what)
 {
     g_last_error = std::string(what) + ": " + hipGetErrorString(e);
     return EPTV_ERR_HIP;
 }
-
-#define EPTV_HIP(call)                                   \
-    do {                                                 \
-        hipError_t e_ = (call);                          \
-        if (e_ != hipSuccess) return hip_fail(e_, #call); \
-    } while (0)
 
 // The float32 system matrix of a plan, by ray (CSR): row v*B + b lists the
 // pixels the ray meets with their lengths, in sweep order.
@@ -79,7 +71,7 @@ static Plan host_plan(const eptv_geometry* g)
     return p;
 }
 
-static int validate_geometry(const eptv_geometry* g)
+int validate_geometry(const eptv_geometry* g)
 {
     if (!g) return EPTV_ERR_ARG;
     if (g->nx <= 0 || g->ny <= 0 || g->n_views <= 0 || g->n_bins <= 0) return EPTV_ERR_ARG;
@@ -133,7 +125,7 @@ size_t workspace_layout(const Plan& p, int K, int T, char* base, Workspace* w)
     W.part_proj = (double*)take((size_t)project_blocks(p) * 8);
     W.part_bp = (double*)take((size_t)image_tile_blocks(p) * 8);
     W.part_grad = (double*)take((size_t)armijo_blocks(p) * 2 * 8);
-    W.part_arm = (double*)take((size_t)armijo_blocks(p) * kArmijoSlots * 8);
+    W.part_arm = (double*)take((size_t)armijo_blocks(p) * kArmijoFirst * 8);
     W.part_res = (double*)take((size_t)sino_blocks(p) * 8);
     W.part_rmse = (double*)take((size_t)kRmseBlocks * 8);
     W.st = (DevState*)take(sizeof(DevState));
@@ -146,7 +138,7 @@ size_t workspace_layout(const Plan& p, int K, int T, char* base, Workspace* w)
     return off;
 }
 
-static int check_params(const eptv_params* q)
+int check_params(const eptv_params* q)
 {
     if (!q) return EPTV_ERR_ARG;
     if (q->outer_iters < 0 || q->cgls_iters < 0 || q->cgls_iters > kMaxCgls || q->tv_iters < 0) return EPTV_ERR_ARG;
@@ -163,7 +155,7 @@ static int check_params(const eptv_params* q)
     return EPTV_OK;
 }
 
-static uint32_t select_rank(const Plan& p, double q)
+uint32_t select_rank(const Plan& p, double q)
 {
     const double n = (double)n_edges(p);
     long long k = (long long)std::ceil(q * n) - 1;
@@ -180,7 +172,7 @@ struct Ctx {
     const float* f_ref;
 };
 
-static float t0_of(const eptv_params& q)
+float t0_of(const eptv_params& q)
 {
     return (float)(q.armijo_t0 > 0 ? q.armijo_t0 : 1.0 / q.lambda);
 }
@@ -200,23 +192,20 @@ static hipError_t enqueue_select(const Plan& p, Workspace& W, const float* img, 
     return hipSuccess;
 }
 
-static int armijo_passes(int max_bt)
-{
-    const int rest = std::max(0, max_bt + 1 - kArmijoFirst);
-    return 1 + (rest + kArmijoMore - 1) / kArmijoMore;
-}
+// sigma the per-iteration state starts from: fixed, or -1 (chosen by the selection)
+float sigma_init(const eptv_params& q) { return q.sigma_fixed < 0 ? -1.0f : (float)q.sigma_fixed; }
 
 // n_steps P2 descent steps (Sec. 2.2; Armijo line search) from `start`
 // towards v; the result goes to `fout` (and its transpose to foutT when
 // given), truncated at zero when `clamp`.  Step t > 0 applies step t-1 inside
 // its gradient kernel, so only the last step has an update kernel of its own.
+
 static hipError_t enqueue_p2(const Plan& p, Workspace& W, const eptv_params& q, const float* start, const float* v,
                              int n_steps, float* fout, float* foutT, int clamp, int32_t* st_k, hipStream_t s)
 {
     hipError_t e;
     const float eps2 = (float)(q.tv_eps * q.tv_eps);
     const float t0 = t0_of(q), shrink = (float)q.armijo_shrink;
-    const int npass = armijo_passes(q.armijo_max_backtracks);
     const float* fcur = start;
     float* gbuf[2] = {W.g, W.g2};
     float* fbuf[2] = {W.f1, W.f2};
@@ -228,14 +217,13 @@ static hipError_t enqueue_p2(const Plan& p, Workspace& W, const eptv_params& q, 
                                 W.part_grad, s)) != hipSuccess)
             return e;
         if (t > 0) fcur = fnext;
-        for (int pass = 0; pass < npass; ++pass) {
-            if ((e = launch_armijo(p, pass, fcur, g, v, W.wx, W.wy, (float)q.lambda, eps2, t0, shrink, W.st,
-                                   W.part_arm, s)) != hipSuccess)
-                return e;
-            if ((e = launch_armijo_finalize(p, W.st, W.part_grad, W.part_arm, pass, q.armijo_max_backtracks,
-                                            q.armijo_c, t0, shrink, st_k, t, n_steps, s)) != hipSuccess)
-                return e;
-        }
+        if ((e = launch_armijo(p, fcur, g, v, W.wx, W.wy, (float)q.lambda, eps2, t0, shrink, W.part_arm, s)) !=
+            hipSuccess)
+            return e;
+        if ((e = launch_armijo_decide(p, W.st, W.part_grad, W.part_arm, q.armijo_max_backtracks, q.armijo_c, t0,
+                                      shrink, st_k, t, n_steps, fcur, g, v, W.wx, W.wy, (float)q.lambda, eps2, s)) !=
+            hipSuccess)
+            return e;
     }
     if (n_steps == 0) return launch_copy_clamp(p, start, fout, foutT, clamp, s);
     return launch_p2_update(p, W.st, fcur, gbuf[(n_steps - 1) & 1], fout, foutT, clamp, s);
@@ -250,9 +238,7 @@ static hipError_t enqueue_iteration(const Ctx& c, hipStream_t s)
     const int M = q.cgls_iters, T = q.tv_iters;
     const bool adaptive = q.sigma_fixed < 0;
     hipError_t e;
-    if ((e = launch_state_init(W.st, W.hist, select_rank(p, q.edge_quantile), adaptive ? -1.0f : (float)q.sigma_fixed,
-                               0, s)) != hipSuccess)
-        return e;
+    // (the per-iteration state was reset by the previous iteration's last kernel, or by the caller)
     // Step 1: P1.  r = y - P f
     // P and P^T: on the fly, or from the stored matrix (the paper's two strategies, Sec. 2.3)
     auto proj = [&](const float* x, const float* xT, float al, float be, const float* cc, float* out, double* part) {
@@ -298,7 +284,7 @@ static hipError_t enqueue_iteration(const Ctx& c, hipStream_t s)
         if ((e = launch_rmse_part(p, c.f, c.f_ref, W.part_rmse, s)) != hipSuccess) return e;
     }
     return launch_iter_end(p, W.st, W.part_res, M > 0, W.part_rmse, c.f_ref != nullptr, W.st_sigma, W.st_steps,
-                           W.st_resid, W.st_rmse, s);
+                           W.st_resid, W.st_rmse, W.hist, sigma_init(q), s);
 }
 
 static bool no_graph()
@@ -641,7 +627,7 @@ int eptv_reconstruct(eptv_plan h, const eptv_params* q, const float* y, float* f
     hipStream_t s = (hipStream_t)stream;
     const int K = q->outer_iters, T = q->tv_iters;
 
-    EPTV_HIP(launch_state_init(W.st, W.hist, select_rank(p, q->edge_quantile), -1.0f, 1, s));
+    EPTV_HIP(launch_state_init(W.st, W.hist, select_rank(p, q->edge_quantile), sigma_init(*q), 1, s));
     if (q->zero_init) EPTV_HIP(launch_fill(f, (size_t)p.nx * p.ny, 0.0f, s));
     EPTV_HIP(launch_transpose(f, W.fT, p.nx, p.ny, s));
 

@@ -10,12 +10,17 @@
 // the transposed image, so the 64 lanes of a wave, which sit in neighbouring
 // rows of one column, touch contiguous memory in both sweep directions.
 //
-// P^T is pixel-driven (Sec. 2.3: one thread per pixel avoids the write
-// conflicts of a ray-driven scatter).  For every view a pixel finds the bins
-// whose rays can meet it from its angular position seen from the source, and
-// evaluates the same chord expression as the projector, so the float32 P^T is
-// exactly the transpose of the float32 P (not the interpolating approximation
-// of Eq. 11).  Views are summed in ascending order; there are no atomics.
+// P^T is computed per 16x16 pixel tile (Sec. 2.3: the tile's block owns its
+// pixels, so the write conflicts of a ray-driven scatter cannot arise): the
+// rays that can meet the tile are walked through it with the projector's own
+// cell arithmetic, so the float32 P^T is exactly the transpose of the float32
+// P (not the interpolating approximation of Eq. 11, which is provided
+// separately).  Summation order is fixed; there are no atomics.
+//
+// Each kernel's per-block work is a __device__ function of the block's
+// coordinates, shared by the one-slice kernels here and the batched kernels
+// (batch.hip), which walk a list of (slice, block) items.
+#include "batch.h"
 #include "eptv_internal.h"
 #include "reduce.h"
 
@@ -49,17 +54,14 @@ __device__ __forceinline__ CellTap cell_tap(long long lo, const RayFx& R, float 
 }
 
 template <int NSEG>
-__global__ __launch_bounds__(64 * NSEG) void k_project(const RayFx* __restrict__ rays,
-                                                       const int2* __restrict__ range,
-                                                       const float* __restrict__ x,
-                                                       const float* __restrict__ xT, int nx, int ny,
-                                                       int B, float alpha, float beta,
-                                                       const float* c, float* q, double* partial)
+__device__ __forceinline__ void project_block(const RayFx* __restrict__ rays, const int2* __restrict__ range,
+                                              const float* __restrict__ x, const float* __restrict__ xT, int nx,
+                                              int ny, int B, float alpha, float beta, const float* c, float* q,
+                                              double* partial, int bx, int v, int part_id, float (*red)[64],
+                                              double* lds)
 {
-    __shared__ float red[NSEG][64];
-    __shared__ double lds[1];
     const int lane = threadIdx.x & 63, seg = threadIdx.x >> 6;
-    const int b = blockIdx.x * 64 + lane, v = blockIdx.y;
+    const int b = bx * 64 + lane;
     float acc = 0.0f, acc1 = 0.0f;
     if (b < B) {
         const int id = v * B + b;
@@ -123,8 +125,22 @@ __global__ __launch_bounds__(64 * NSEG) void k_project(const RayFx* __restrict__
     }
     if (partial) {
         __syncthreads();
-        if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = lds[0];
+        if (threadIdx.x == 0) partial[part_id] = lds[0];
     }
+}
+
+template <int NSEG>
+__global__ __launch_bounds__(64 * NSEG) void k_project(const RayFx* __restrict__ rays,
+                                                       const int2* __restrict__ range,
+                                                       const float* __restrict__ x,
+                                                       const float* __restrict__ xT, int nx, int ny,
+                                                       int B, float alpha, float beta,
+                                                       const float* c, float* q, double* partial)
+{
+    __shared__ float red[NSEG][64];
+    __shared__ double lds[1];
+    project_block<NSEG>(rays, range, x, xT, nx, ny, B, alpha, beta, c, q, partial, blockIdx.x, blockIdx.y,
+                        blockIdx.y * gridDim.x + blockIdx.x, red, lds);
 }
 
 int project_blocks(const Plan& p) { return ((p.B + 63) / 64) * p.V; }
@@ -173,24 +189,24 @@ struct BpEntry {
     float pad;
 };
 
-__global__ __launch_bounds__(256) void k_backproject(const RayFx* __restrict__ rays,
-                                                     const int2* __restrict__ range,
-                                                     const int* __restrict__ list_off,
-                                                     const int* __restrict__ list,
-                                                     const float* __restrict__ r, int nx, int ny,
-                                                     float alpha, float beta, const float* c, float* z,
-                                                     float* zT, double* partial)
+struct BpShared {
+    BpEntry ent[kBpChunk];
+    float acc[kBpGroups][kTile][kTile + 1];
+    float tile[kTile][kTile + 1];
+    double lds[4];
+};
+
+__device__ __forceinline__ void backproject_block(const RayFx* __restrict__ rays, const int2* __restrict__ range,
+                                                  const int* __restrict__ list_off, const int* __restrict__ list,
+                                                  const float* __restrict__ r, int nx, int ny, float alpha,
+                                                  float beta, const float* c, float* z, float* zT, double* partial,
+                                                  int bx, int by, int tile_id, BpShared& S)
 {
-    __shared__ BpEntry ent[kBpChunk];
-    __shared__ float acc[kBpGroups][kTile][kTile + 1];
-    __shared__ float tile[kTile][kTile + 1];
-    __shared__ double lds[4];
     const int tx = threadIdx.x & (kTile - 1), ty = threadIdx.x / kTile;
     const int line = tx, grp = ty;  // the same split read as (sweep line, group)
-    const int i0 = blockIdx.x * kTile, j0 = blockIdx.y * kTile;
-    for (int g = 0; g < kBpGroups; ++g) acc[g][ty][tx] = 0.0f;
-    const int t = blockIdx.y * gridDim.x + blockIdx.x;
-    const int beg = list_off[t], end = list_off[t + 1];
+    const int i0 = bx * kTile, j0 = by * kTile;
+    for (int g = 0; g < kBpGroups; ++g) S.acc[g][ty][tx] = 0.0f;
+    const int beg = list_off[tile_id], end = list_off[tile_id + 1];
     for (int base = beg; base < end; base += kBpChunk) {
         const int n = min(kBpChunk, end - base);
         __syncthreads();
@@ -201,22 +217,22 @@ __global__ __launch_bounds__(256) void k_backproject(const RayFx* __restrict__ r
             e.range = range[id];
             e.r = r[id];
             e.pad = 0.0f;
-            ent[threadIdx.x] = e;
+            S.ent[threadIdx.x] = e;
         }
         __syncthreads();
         for (int k = grp; k < n; k += kBpGroups) {
-            const BpEntry& e = ent[k];
+            const BpEntry& e = S.ent[k];
             const bool rows = e.ray.wfull < 0.0f;  // swept row by row
             const int ks = (rows ? j0 : i0) + line;
             if (ks < e.range.x || ks >= e.range.y) continue;
             const CellW w = cell_weights(cell_lo(e.ray, ks), e.ray.span, e.ray.w32, fabsf(e.ray.wfull));
             const int m = w.m0 - (rows ? i0 : j0);
             if ((unsigned)m < (unsigned)kTile) {
-                float& a = rows ? acc[grp][line][m] : acc[grp][m][line];
+                float& a = rows ? S.acc[grp][line][m] : S.acc[grp][m][line];
                 a = fmaf(w.c0, e.r, a);
             }
             if ((unsigned)(m + 1) < (unsigned)kTile) {
-                float& a = rows ? acc[grp][line][m + 1] : acc[grp][m + 1][line];
+                float& a = rows ? S.acc[grp][line][m + 1] : S.acc[grp][m + 1][line];
                 a = fmaf(w.c1, e.r, a);
             }
         }
@@ -226,7 +242,7 @@ __global__ __launch_bounds__(256) void k_backproject(const RayFx* __restrict__ r
     const bool in = i < nx && j < ny;
     float sum = 0.0f;
 #pragma unroll
-    for (int g = 0; g < kBpGroups; ++g) sum += acc[g][ty][tx];
+    for (int g = 0; g < kBpGroups; ++g) sum += S.acc[g][ty][tx];
     float out = 0.0f;
     if (in) {
         const size_t id = (size_t)j * nx + i;
@@ -235,15 +251,28 @@ __global__ __launch_bounds__(256) void k_backproject(const RayFx* __restrict__ r
         z[id] = out;
     }
     if (zT) {
-        tile[ty][tx] = out;
+        S.tile[ty][tx] = out;
         __syncthreads();
         const int it = i0 + ty, jt = j0 + tx;
-        if (it < nx && jt < ny) zT[(size_t)it * ny + jt] = tile[tx][ty];
+        if (it < nx && jt < ny) zT[(size_t)it * ny + jt] = S.tile[tx][ty];
     }
     if (partial) {
-        const double s2 = block_sum<256>((double)out * (double)out, lds);
-        if (threadIdx.x == 0) partial[t] = s2;
+        const double s2 = block_sum<256>((double)out * (double)out, S.lds);
+        if (threadIdx.x == 0) partial[tile_id] = s2;
     }
+}
+
+__global__ __launch_bounds__(256) void k_backproject(const RayFx* __restrict__ rays,
+                                                     const int2* __restrict__ range,
+                                                     const int* __restrict__ list_off,
+                                                     const int* __restrict__ list,
+                                                     const float* __restrict__ r, int nx, int ny,
+                                                     float alpha, float beta, const float* c, float* z,
+                                                     float* zT, double* partial)
+{
+    __shared__ BpShared S;
+    backproject_block(rays, range, list_off, list, r, nx, ny, alpha, beta, c, z, zT, partial, blockIdx.x,
+                      blockIdx.y, blockIdx.y * gridDim.x + blockIdx.x, S);
 }
 
 int image_tile_blocks(const Plan& p) { return ((p.nx + kTile - 1) / kTile) * ((p.ny + kTile - 1) / kTile); }
@@ -406,11 +435,10 @@ hipError_t launch_backproject_interp(const Plan& p, const float* r, float alpha,
 }
 
 // ------------------------------------------------------------------ layout helpers
-__global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ src, float* __restrict__ dst,
-                                                   int nx, int ny)
+__device__ __forceinline__ void transpose_block(const float* __restrict__ src, float* __restrict__ dst, int nx,
+                                                int ny, int tbx, int tby, float (*t)[33])
 {
-    __shared__ float t[32][33];
-    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const int bx = tbx * 32, by = tby * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
     for (int k = ty; k < 32; k += 8) {
         const int i = bx + tx, j = by + k;
@@ -421,6 +449,13 @@ __global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ src
         const int i = bx + k, j = by + tx;
         if (i < nx && j < ny) dst[(size_t)i * ny + j] = t[tx][k];
     }
+}
+
+__global__ __launch_bounds__(256) void k_transpose(const float* __restrict__ src, float* __restrict__ dst,
+                                                   int nx, int ny)
+{
+    __shared__ float t[32][33];
+    transpose_block(src, dst, nx, ny, blockIdx.x, blockIdx.y, t);
 }
 
 hipError_t launch_transpose(const float* src, float* dst, int nx, int ny, hipStream_t s)
@@ -441,6 +476,115 @@ hipError_t launch_fill(float* dst, size_t n, float value, hipStream_t s)
     if (n == 0) return hipSuccess;
     const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
     hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(256), 0, s, dst, n, value);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ batched kernels
+// Persistent grids over (slice, block) items; see batch.h.  Each item runs the
+// one-slice kernel's block function; a barrier separates items because the
+// block's LDS is reused.
+template <int NSEG>
+__global__ __launch_bounds__(64 * NSEG) void kb_project(const SliceDev* __restrict__ sl, const int2* __restrict__ items,
+                                                        int n_items, int xs, int xTs, float alpha, float beta, int cs,
+                                                        int outs, int parts)
+{
+    __shared__ float red[NSEG][64];
+    __shared__ double lds[1];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 w = items[it];
+        const SliceDev& d = sl[w.x];
+        __syncthreads();
+        project_block<NSEG>(d.rays, d.range, d.buf[xs], d.buf[xTs], d.nx, d.ny, d.B, alpha, beta, bsel(d, cs),
+                            d.buf[outs], psel(d, parts), w.y % d.proj_gx, w.y / d.proj_gx, w.y, red, lds);
+    }
+}
+
+hipError_t blaunch_project(const BatchDev& b, int x, int xT, float alpha, float beta, int c, int out, int part,
+                           hipStream_t s)
+{
+    const int n = b.n_items[kShProj], g = b.grid[kShProj];
+    if (n == 0) return hipSuccess;
+    switch (b.proj_seg) {
+    case 4:
+        hipLaunchKernelGGL(kb_project<4>, dim3(g), dim3(256), 0, s, b.slices, b.items[kShProj], n, x, xT, alpha, beta,
+                           c, out, part);
+        break;
+    case 8:
+        hipLaunchKernelGGL(kb_project<8>, dim3(g), dim3(512), 0, s, b.slices, b.items[kShProj], n, x, xT, alpha, beta,
+                           c, out, part);
+        break;
+    default:
+        hipLaunchKernelGGL(kb_project<16>, dim3(g), dim3(1024), 0, s, b.slices, b.items[kShProj], n, x, xT, alpha,
+                           beta, c, out, part);
+        break;
+    }
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void kb_backproject(const SliceDev* __restrict__ sl, const int2* __restrict__ items,
+                                                      int n_items, int rs, float alpha, float beta, int cs, int zs,
+                                                      int zTs, int parts)
+{
+    __shared__ BpShared S;
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 w = items[it];
+        const SliceDev& d = sl[w.x];
+        __syncthreads();
+        backproject_block(d.rays, d.range, d.list_off, d.list, d.buf[rs], d.nx, d.ny, alpha, beta, bsel(d, cs),
+                          d.buf[zs], bsel(d, zTs), psel(d, parts), w.y % d.t16x, w.y / d.t16x, w.y, S);
+    }
+}
+
+hipError_t blaunch_backproject(const BatchDev& b, int r, float alpha, float beta, int c, int z, int zT, int part,
+                               hipStream_t s)
+{
+    const int n = b.n_items[kShT16];
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(kb_backproject, dim3(b.grid[kShT16]), dim3(256), 0, s, b.slices, b.items[kShT16], n, r, alpha,
+                       beta, c, z, zT, part);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void kb_transpose(const SliceDev* __restrict__ sl, const int2* __restrict__ items,
+                                                    int n_items, int srcs, int dsts)
+{
+    __shared__ float t[32][33];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 w = items[it];
+        const SliceDev& d = sl[w.x];
+        __syncthreads();
+        transpose_block(d.buf[srcs], d.buf[dsts], d.nx, d.ny, w.y % d.t32x, w.y / d.t32x, t);
+    }
+}
+
+hipError_t blaunch_transpose(const BatchDev& b, int src, int dst, hipStream_t s)
+{
+    const int n = b.n_items[kShT32];
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(kb_transpose, dim3(b.grid[kShT32]), dim3(256), 0, s, b.slices, b.items[kShT32], n, src, dst);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void kb_fill_zero(const SliceDev* __restrict__ sl, const int2* __restrict__ items,
+                                                    int n_items, int dsts)
+{
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 w = items[it];
+        const SliceDev& d = sl[w.x];
+        const int bx = (w.y % d.t32x) * 32, by = (w.y / d.t32x) * 32;
+        const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+        for (int k = ty; k < 32; k += 8) {
+            const int i = bx + tx, j = by + k;
+            if (i < d.nx && j < d.ny) d.buf[dsts][(size_t)j * d.nx + i] = 0.0f;
+        }
+    }
+}
+
+hipError_t blaunch_fill_zero(const BatchDev& b, int dst, hipStream_t s)
+{
+    const int n = b.n_items[kShT32];
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(kb_fill_zero, dim3(b.grid[kShT32]), dim3(256), 0, s, b.slices, b.items[kShT32], n, dst);
     return hipGetLastError();
 }
 

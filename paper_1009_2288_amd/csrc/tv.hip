@@ -12,6 +12,7 @@
 // Every kernel reads a pixel's 3x3 neighbourhood; each half-edge is owned by
 // exactly one pixel (its left / lower pixel, or the border pixel for the
 // edges on the left and bottom image border) for the energy sums.
+#include "batch.h"
 #include "eptv_internal.h"
 #include "reduce.h"
 
@@ -88,13 +89,12 @@ __device__ __forceinline__ void hist_add(uint32_t* h, uint32_t bin)
 }
 
 // Edge index: x-edge (i+1/2, j) -> j*(nx+1) + i+1; y-edge (i, j+1/2) -> ny*(nx+1) + (j+1)*nx + i.
-__global__ __launch_bounds__(256) void k_edges_hist(const float* __restrict__ f, int nx, int ny, float eps2,
-                                                    uint32_t* keys, uint32_t* hist0)
+__device__ __forceinline__ void edges_hist_block(const float* __restrict__ f, int nx, int ny, float eps2,
+                                                 uint32_t* keys, uint32_t* hist0, int bx, int by, uint32_t* h)
 {
-    __shared__ uint32_t h[kSelectBins];
     for (int b = threadIdx.x; b < kSelectBins; b += 256) h[b] = 0u;
     __syncthreads();
-    const int i = blockIdx.x * kT + (threadIdx.x & (kT - 1)), j = blockIdx.y * kT + threadIdx.x / kT;
+    const int i = bx * kT + (threadIdx.x & (kT - 1)), j = by * kT + threadIdx.x / kT;
     if (i < nx && j < ny) {
         Nbhd N;
         load_nbhd(f, nx, ny, i, j, N);
@@ -121,6 +121,13 @@ __global__ __launch_bounds__(256) void k_edges_hist(const float* __restrict__ f,
         if (h[b]) atomicAdd(&hist0[b], h[b]);
 }
 
+__global__ __launch_bounds__(256) void k_edges_hist(const float* __restrict__ f, int nx, int ny, float eps2,
+                                                    uint32_t* keys, uint32_t* hist0)
+{
+    __shared__ uint32_t h[kSelectBins];
+    edges_hist_block(f, nx, ny, eps2, keys, hist0, blockIdx.x, blockIdx.y, h);
+}
+
 hipError_t launch_edges_hist(const Plan& p, const float* f, float eps2, uint32_t* keys, uint32_t* hist0,
                              hipStream_t s)
 {
@@ -131,23 +138,29 @@ hipError_t launch_edges_hist(const Plan& p, const float* f, float eps2, uint32_t
 
 // pass 1: digit = bits 20..10 among keys whose bits 31..21 equal the prefix;
 // pass 2: digit = bits 9..0 among keys whose bits 31..10 equal the prefix.
-__global__ __launch_bounds__(256) void k_select_hist(const uint32_t* __restrict__ keys, size_t n, int pass,
-                                                     const DevState* st, uint32_t* hist)
+__device__ __forceinline__ void select_hist_block(const uint32_t* __restrict__ keys, size_t n, int pass,
+                                                  const DevState* st, uint32_t* hist, int blk, int nblk, uint32_t* h)
 {
-    __shared__ uint32_t h[kSelectBins];
     for (int b = threadIdx.x; b < kSelectBins; b += 256) h[b] = 0u;
     __syncthreads();
     const int hshift = pass == 1 ? 21 : 10;
     const int dshift = pass == 1 ? 10 : 0;
     const uint32_t dmask = pass == 1 ? 2047u : 1023u;
     const uint32_t want = st->prefix >> hshift;
-    for (size_t e = (size_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (size_t)gridDim.x * 256) {
+    for (size_t e = (size_t)blk * 256 + threadIdx.x; e < n; e += (size_t)nblk * 256) {
         const uint32_t k = keys[e];
         if ((k >> hshift) == want) hist_add(h, (k >> dshift) & dmask);
     }
     __syncthreads();
     for (int b = threadIdx.x; b < kSelectBins; b += 256)
         if (h[b]) atomicAdd(&hist[b], h[b]);
+}
+
+__global__ __launch_bounds__(256) void k_select_hist(const uint32_t* __restrict__ keys, size_t n, int pass,
+                                                     const DevState* st, uint32_t* hist)
+{
+    __shared__ uint32_t h[kSelectBins];
+    select_hist_block(keys, n, pass, st, hist, blockIdx.x, gridDim.x, h);
 }
 
 int select_blocks(const Plan& p)
@@ -166,10 +179,17 @@ hipError_t launch_select_hist(const Plan& p, int pass, const uint32_t* keys, con
 // The digit whose bucket holds the rank (an inclusive scan over 256 groups of
 // buckets), folded into the prefix; the histogram is cleared for its next use.
 // After the last digit the prefix is the bit pattern of the selected magnitude.
-__global__ __launch_bounds__(256) void k_select_finalize(DevState* st, int pass, uint32_t* hist, float floor_)
+struct SelShared {
+    uint32_t sums[256];
+    uint32_t found_digit, found_before;
+};
+
+__device__ __forceinline__ void select_finalize_block(DevState* st, int pass, uint32_t* hist, float floor_,
+                                                      SelShared& S)
 {
-    __shared__ uint32_t sums[256];
-    __shared__ uint32_t found_digit, found_before;
+    uint32_t* sums = S.sums;
+    uint32_t& found_digit = S.found_digit;
+    uint32_t& found_before = S.found_before;
     const int nb = pass == 2 ? 1024 : 2048;
     const int per = nb / 256;
     const int t = threadIdx.x;
@@ -210,6 +230,12 @@ __global__ __launch_bounds__(256) void k_select_finalize(DevState* st, int pass,
     }
 }
 
+__global__ __launch_bounds__(256) void k_select_finalize(DevState* st, int pass, uint32_t* hist, float floor_)
+{
+    __shared__ SelShared S;
+    select_finalize_block(st, pass, hist, floor_, S);
+}
+
 hipError_t launch_select_finalize(DevState* st, int pass, uint32_t* hist, float sigma_floor, hipStream_t s)
 {
     hipLaunchKernelGGL(k_select_finalize, dim3(1), dim3(256), 0, s, st, pass, hist, sigma_floor);
@@ -239,15 +265,15 @@ __device__ __forceinline__ float stepped(float f, float g, int k, float t) { ret
 // one, f - t g_prev (the previous step's decision in st_prev), and stored to
 // f_out.  Per-block partials: (Q(f) = sum of w TV over owned edges +
 // lambda/2 (f - v)^2, ||g||^2).
-__global__ __launch_bounds__(256) void k_tv_grad(const float* __restrict__ f, const float* __restrict__ g_prev,
-                                                 const DevState* st_prev, float* __restrict__ f_out,
-                                                 const float* __restrict__ v, int nx, int ny, float lambda,
-                                                 const DevState* st, float inv_s2_direct, float eps2,
-                                                 float* __restrict__ g, float* wx, float* wy, double* part)
+__device__ __forceinline__ void tv_grad_block(const float* __restrict__ f, const float* __restrict__ g_prev,
+                                              const DevState* st_prev, float* __restrict__ f_out,
+                                              const float* __restrict__ v, int nx, int ny, float lambda,
+                                              const DevState* st, float inv_s2_direct, float eps2,
+                                              float* __restrict__ g, float* wx, float* wy, double* part, int bx,
+                                              int by, int b, int nb, double* lds)
 {
-    __shared__ double lds[4];
     const float inv_s2 = st ? st->inv_sigma2 : inv_s2_direct;
-    const int i = blockIdx.x * kT + (threadIdx.x & (kT - 1)), j = blockIdx.y * kT + threadIdx.x / kT;
+    const int i = bx * kT + (threadIdx.x & (kT - 1)), j = by * kT + threadIdx.x / kT;
     double q = 0.0, gg = 0.0;
     if (i < nx && j < ny) {
         Nbhd N;
@@ -295,11 +321,21 @@ __global__ __launch_bounds__(256) void k_tv_grad(const float* __restrict__ f, co
         const double qs = block_sum<256>(q, lds);
         const double gs = block_sum<256>(gg, lds);
         if (threadIdx.x == 0) {  // slot-major: [Q | ||g||^2][block]
-            const int b = blockIdx.y * gridDim.x + blockIdx.x, nb = gridDim.x * gridDim.y;
             part[b] = qs;
             part[nb + b] = gs;
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_tv_grad(const float* __restrict__ f, const float* __restrict__ g_prev,
+                                                 const DevState* st_prev, float* __restrict__ f_out,
+                                                 const float* __restrict__ v, int nx, int ny, float lambda,
+                                                 const DevState* st, float inv_s2_direct, float eps2,
+                                                 float* __restrict__ g, float* wx, float* wy, double* part)
+{
+    __shared__ double lds[4];
+    tv_grad_block(f, g_prev, st_prev, f_out, v, nx, ny, lambda, st, inv_s2_direct, eps2, g, wx, wy, part,
+                  blockIdx.x, blockIdx.y, blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y, lds);
 }
 
 hipError_t launch_tv_grad(const Plan& p, const float* f, const float* g_prev, const DevState* st_prev, float* f_out,
@@ -324,170 +360,213 @@ __device__ __forceinline__ float cand_t(float t0, float shrink, int k)
     return t;
 }
 
-// Candidate range of pass p: [0, 8) first, then 16 at a time.
-__host__ __device__ __forceinline__ int pass_first(int pass) { return pass == 0 ? 0 : kArmijoFirst + kArmijoMore * (pass - 1); }
-
-// Q(f - t_k g) for the NC candidates of one pass, with the weights frozen at
-// f: per-block partial sums, slot-major [kArmijoSlots][block].
+// Energies Q(f - t_k g) of pixel (i, j)'s share (its own fidelity term and the
+// half-edges it owns) for NC consecutive candidates from k0, with the weights
+// frozen at f.
 template <int NC>
-__global__ __launch_bounds__(256) void k_armijo(const float* __restrict__ f, const float* __restrict__ g,
-                                                const float* __restrict__ v, const float* __restrict__ wx,
-                                                const float* __restrict__ wy, int nx, int ny, float lambda,
-                                                float eps2, float t0, float shrink, int pass, const DevState* st,
-                                                double* part)
+__device__ __forceinline__ void candidate_energies(const float* f, const float* g, const float* v, const float* wx,
+                                                   const float* wy, int nx, int ny, int i, int j, float lambda,
+                                                   float eps2, float t0, float shrink, int k0, double* e)
 {
-    __shared__ double red[4][NC];
-    if (pass > 0 && st->decided) return;  // uniform: an earlier pass already chose a step
-    const int i = blockIdx.x * kT + (threadIdx.x & (kT - 1)), j = blockIdx.y * kT + threadIdx.x / kT;
-    double e[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) e[c] = 0.0;
-    if (i < nx && j < ny) {
-        Nbhd F, G;
-        load_nbhd(f, nx, ny, i, j, F);
-        load_nbhd(g, nx, ny, i, j, G);
-        const size_t xo = (size_t)j * (nx + 1);
-        const float wR = wx[xo + i + 1], wU = wy[(size_t)(j + 1) * nx + i];
-        const float wL = i == 0 ? wx[xo] : 0.0f, wD = j == 0 ? wy[i] : 0.0f;
-        const float vv = v[(size_t)j * nx + i];
-        float t = cand_t(t0, shrink, pass_first(pass));
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            Nbhd H;
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int bb = 0; bb < 3; ++bb) H.n[a][bb] = fmaf(-t, G.n[a][bb], F.n[a][bb]);
-            float s = wR * tv_right(H, eps2) + wU * tv_up(H, eps2);
-            if (i == 0) s += wL * tv_left(H, eps2);
-            if (j == 0) s += wD * tv_down(H, eps2);
-            const float d = H.n[1][1] - vv;
-            e[c] = (double)s + 0.5 * (double)lambda * (double)d * (double)d;
-            t *= shrink;
-        }
-    }
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    Nbhd F, G;
+    load_nbhd(f, nx, ny, i, j, F);
+    load_nbhd(g, nx, ny, i, j, G);
+    const size_t xo = (size_t)j * (nx + 1);
+    const float wR = wx[xo + i + 1], wU = wy[(size_t)(j + 1) * nx + i];
+    const float wL = i == 0 ? wx[xo] : 0.0f, wD = j == 0 ? wy[i] : 0.0f;
+    const float vv = v[(size_t)j * nx + i];
+    float t = cand_t(t0, shrink, k0);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
+        Nbhd H;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int bb = 0; bb < 3; ++bb) H.n[a][bb] = fmaf(-t, G.n[a][bb], F.n[a][bb]);
+        float s = wR * tv_right(H, eps2) + wU * tv_up(H, eps2);
+        if (i == 0) s += wL * tv_left(H, eps2);
+        if (j == 0) s += wD * tv_down(H, eps2);
+        const float d = H.n[1][1] - vv;
+        e[c] += (double)s + 0.5 * (double)lambda * (double)d * (double)d;
+        t *= shrink;
+    }
+}
+
+// Candidates k = 0 .. kArmijoFirst-1 over the whole image: per-block
+// partial sums, slot-major [kArmijoFirst][block].
+__device__ __forceinline__ void armijo_block(const float* __restrict__ f, const float* __restrict__ g,
+                                             const float* __restrict__ v, const float* __restrict__ wx,
+                                             const float* __restrict__ wy, int nx, int ny, float lambda, float eps2,
+                                             float t0, float shrink, double* part, int bx, int by, int b, int nb,
+                                             double (*red)[kArmijoFirst])
+{
+    const int i = bx * kT + (threadIdx.x & (kT - 1)), j = by * kT + threadIdx.x / kT;
+    double e[kArmijoFirst];
+#pragma unroll
+    for (int c = 0; c < kArmijoFirst; ++c) e[c] = 0.0;
+    if (i < nx && j < ny) candidate_energies<kArmijoFirst>(f, g, v, wx, wy, nx, ny, i, j, lambda, eps2, t0, shrink, 0, e);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+    for (int c = 0; c < kArmijoFirst; ++c) {
         const double sc = wave_sum(e[c]);
         if (l == 0) red[w][c] = sc;
     }
     __syncthreads();
-    if (threadIdx.x < NC) {
+    if (threadIdx.x < kArmijoFirst) {
         const int c = threadIdx.x;
-        part[(size_t)c * (gridDim.x * gridDim.y) + blockIdx.y * gridDim.x + blockIdx.x] =
-            red[0][c] + red[1][c] + red[2][c] + red[3][c];
+        part[(size_t)c * nb + b] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
     }
+}
+
+__global__ __launch_bounds__(256) void k_armijo(const float* __restrict__ f, const float* __restrict__ g,
+                                                const float* __restrict__ v, const float* __restrict__ wx,
+                                                const float* __restrict__ wy, int nx, int ny, float lambda,
+                                                float eps2, float t0, float shrink, double* part)
+{
+    __shared__ double red[4][kArmijoFirst];
+    armijo_block(f, g, v, wx, wy, nx, ny, lambda, eps2, t0, shrink, part, blockIdx.x, blockIdx.y,
+                 blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y, red);
 }
 
 int armijo_blocks(const Plan& p) { return ((p.nx + kT - 1) / kT) * ((p.ny + kT - 1) / kT); }
 
-hipError_t launch_armijo(const Plan& p, int pass, const float* f, const float* g, const float* v, const float* wx,
-                         const float* wy, float lambda, float eps2, float t0, float shrink, const DevState* st,
-                         double* part, hipStream_t s)
+hipError_t launch_armijo(const Plan& p, const float* f, const float* g, const float* v, const float* wx,
+                         const float* wy, float lambda, float eps2, float t0, float shrink, double* part,
+                         hipStream_t s)
 {
     dim3 grid((p.nx + kT - 1) / kT, (p.ny + kT - 1) / kT);
-    if (pass == 0)
-        hipLaunchKernelGGL(k_armijo<kArmijoFirst>, grid, dim3(256), 0, s, f, g, v, wx, wy, p.nx, p.ny, lambda, eps2,
-                           t0, shrink, pass, st, part);
-    else
-        hipLaunchKernelGGL(k_armijo<kArmijoMore>, grid, dim3(256), 0, s, f, g, v, wx, wy, p.nx, p.ny, lambda, eps2,
-                           t0, shrink, pass, st, part);
+    hipLaunchKernelGGL(k_armijo, grid, dim3(256), 0, s, f, g, v, wx, wy, p.nx, p.ny, lambda, eps2, t0, shrink, part);
     return hipGetLastError();
 }
 
-// The decision of one pass: the first candidate with Q_k <= Q0 - c t_k ||g||^2.
-// Pass 0 also closes Q0 and ||g||^2 from the gradient kernel's partials.
-// After the last allowed candidate without acceptance the step is skipped
+// The Armijo decision: the first candidate with Q_k <= Q0 - c t_k ||g||^2.
+// One block of 256 threads closes Q0, ||g||^2 (gradient kernel's partials)
+// and the first kArmijoFirst candidate energies (Armijo kernel's partials):
+// thread t sums blocks t, t + 256, ... of every slot in order, the per-thread
+// sums go through LDS, and each wave reduces a few slots with a fixed
+// butterfly.  Should none of the first candidates pass while more backtracks
+// are allowed (which a reasonable first step t0 never needs), this block goes
+// on alone through the image, kArmijoMore candidates at a time: slow, but the
+// decision is the same.  Without an accepted candidate the step is skipped
 // (k = -1, t = 0).  The accepted index is recorded for the iteration.
-// One block of 1024 threads: thread t loads the partials of blocks t,
-// t + 1024, ... of every slot (slot-major, so each wave load is contiguous;
-// all loads are in flight together, and they are far ones: the partials were
-// written on every XCD), then every slot is summed by a fixed butterfly within
-// each wave and over the 16 waves in order.
-constexpr int kFinThreads = 1024;
-constexpr int kFinVals = kArmijoSlots + 2;
+constexpr int kDecThreads = 256;
+constexpr int kDecVals = kArmijoMore + 2;
 
-__global__ __launch_bounds__(kFinThreads) void k_armijo_finalize(DevState* st, const double* part_grad,
-                                                                 const double* part_arm, int nb, int pass,
-                                                                 int max_bt, double c_arm, float t0, float shrink,
-                                                                 int32_t* st_k, int step, int T)
+template <int NV>
+__device__ __forceinline__ void decide_reduce(double* v, double (*red)[kDecThreads], double* tot)
 {
-    __shared__ double red[kFinThreads / 64][kFinVals];
-    __shared__ double tot[kFinVals];
-    if (pass > 0 && st->decided) return;
-    double v[kFinVals];
+    // v[0..NV) per thread -> tot[0..NV) block sums, fixed order
 #pragma unroll
-    for (int c = 0; c < kFinVals; ++c) v[c] = 0.0;
-    const int nc = pass == 0 ? kArmijoFirst : kArmijoMore;
-    for (int b = threadIdx.x; b < nb; b += kFinThreads) {
-#pragma unroll
-        for (int c = 0; c < kArmijoSlots; ++c)
-            if (c < nc) v[c] += part_arm[(size_t)c * nb + b];
-        if (pass == 0) {
-            v[kArmijoSlots] += part_grad[b];
-            v[kArmijoSlots + 1] += part_grad[nb + b];
-        }
-    }
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-    for (int c = 0; c < kFinVals; ++c) {
-        const double r = wave_sum(v[c]);
-        if (lane == 0) red[w][c] = r;
+    for (int c = 0; c < NV; ++c) red[c][threadIdx.x] = v[c];
+    __syncthreads();
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    for (int c = w; c < NV; c += kDecThreads / 64) {
+        double a = 0.0;
+        for (int q = l; q < kDecThreads; q += 64) a += red[c][q];
+        a = wave_sum(a);
+        if (l == 0) tot[c] = a;
     }
     __syncthreads();
-    if (threadIdx.x < kFinVals) {
-        double s = 0.0;
-        for (int q = 0; q < kFinThreads / 64; ++q) s += red[q][threadIdx.x];
-        tot[threadIdx.x] = s;
+}
+
+struct DecShared {
+    double red[kDecVals][kDecThreads];
+    double tot[kDecVals];
+    int verdict;
+};
+
+__device__ __forceinline__ void armijo_decide_block(DevState* st, const double* part_grad, const double* part_arm,
+                                                    int nb, int max_bt, double c_arm, float t0, float shrink,
+                                                    int32_t* st_k, int step, int T, const float* f, const float* g,
+                                                    const float* v, const float* wx, const float* wy, int nx, int ny,
+                                                    float lambda, float eps2, DecShared& S)
+{
+    double (*red)[kDecThreads] = S.red;
+    double* tot = S.tot;
+    int& verdict = S.verdict;
+    double a[kArmijoFirst + 2];
+#pragma unroll
+    for (int c = 0; c < kArmijoFirst + 2; ++c) a[c] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kDecThreads) {
+#pragma unroll
+        for (int c = 0; c < kArmijoFirst; ++c) a[c] += part_arm[(size_t)c * nb + b];
+        a[kArmijoFirst] += part_grad[b];
+        a[kArmijoFirst + 1] += part_grad[nb + b];
     }
-    __syncthreads();
+    decide_reduce<kArmijoFirst + 2>(a, red, tot);
+    const double q0 = tot[kArmijoFirst], g2 = tot[kArmijoFirst + 1];
     if (threadIdx.x == 0) {
-        if (pass == 0) {
-            st->q0 = tot[kArmijoSlots];
-            st->gg = tot[kArmijoSlots + 1];
-        }
-        const double q0 = pass == 0 ? tot[kArmijoSlots] : st->q0;
-        const double g2 = pass == 0 ? tot[kArmijoSlots + 1] : st->gg;
-        const int first = pass_first(pass);
         int kk = -1;
-        float tk = 0.0f;
-        for (int cc = 0; cc < nc; ++cc) {
-            const int k = first + cc;
-            if (k > max_bt) break;
-            const float t = cand_t(t0, shrink, k);
-            if (tot[cc] <= q0 - c_arm * (double)t * g2) {
+        for (int k = 0; k < kArmijoFirst && k <= max_bt; ++k)
+            if (tot[k] <= q0 - c_arm * (double)cand_t(t0, shrink, k) * g2) {
                 kk = k;
-                tk = t;
                 break;
             }
+        verdict = kk;
+    }
+    __syncthreads();
+    int kk = verdict;
+    // rare: continue the backtracking over the whole image in this block
+    for (int k0 = kArmijoFirst; kk < 0 && k0 <= max_bt; k0 += kArmijoMore) {
+        double e[kArmijoMore];
+#pragma unroll
+        for (int c = 0; c < kArmijoMore; ++c) e[c] = 0.0;
+        for (int px = threadIdx.x; px < nx * ny; px += kDecThreads)
+            candidate_energies<kArmijoMore>(f, g, v, wx, wy, nx, ny, px % nx, px / nx, lambda, eps2, t0, shrink, k0,
+                                            e);
+        decide_reduce<kArmijoMore>(e, red, tot);
+        if (threadIdx.x == 0) {
+            int found = -1;
+            for (int c = 0; c < kArmijoMore && k0 + c <= max_bt; ++c)
+                if (tot[c] <= q0 - c_arm * (double)cand_t(t0, shrink, k0 + c) * g2) {
+                    found = k0 + c;
+                    break;
+                }
+            verdict = found;
         }
-        const bool last_pass = first + nc > max_bt;
-        st->decided = kk >= 0 || last_pass;
+        __syncthreads();
+        kk = verdict;
+    }
+    if (threadIdx.x == 0) {
+        st->q0 = q0;
+        st->gg = g2;
         st->k = kk;
-        st->t = tk;
-        if ((kk >= 0 || last_pass) && st_k) st_k[(size_t)st->iter * T + step] = kk;
+        st->t = kk >= 0 ? cand_t(t0, shrink, kk) : 0.0f;
+        if (st_k) st_k[(size_t)st->iter * T + step] = kk;
     }
 }
 
-hipError_t launch_armijo_finalize(const Plan& p, DevState* st, const double* part_grad, const double* part_arm,
-                                  int pass, int max_bt, double c_arm, float t0, float shrink, int32_t* st_k, int step,
-                                  int T, hipStream_t s)
+__global__ __launch_bounds__(kDecThreads) void k_armijo_decide(DevState* st, const double* part_grad,
+                                                               const double* part_arm, int nb, int max_bt,
+                                                               double c_arm, float t0, float shrink, int32_t* st_k,
+                                                               int step, int T, const float* f, const float* g,
+                                                               const float* v, const float* wx, const float* wy,
+                                                               int nx, int ny, float lambda, float eps2)
 {
-    hipLaunchKernelGGL(k_armijo_finalize, dim3(1), dim3(kFinThreads), 0, s, st, part_grad, part_arm,
-                       armijo_blocks(p), pass, max_bt, c_arm, t0, shrink, st_k, step, T);
+    __shared__ DecShared S;
+    armijo_decide_block(st, part_grad, part_arm, nb, max_bt, c_arm, t0, shrink, st_k, step, T, f, g, v, wx, wy, nx,
+                        ny, lambda, eps2, S);
+}
+
+hipError_t launch_armijo_decide(const Plan& p, DevState* st, const double* part_grad, const double* part_arm,
+                                int max_bt, double c_arm, float t0, float shrink, int32_t* st_k, int step, int T,
+                                const float* f, const float* g, const float* v, const float* wx, const float* wy,
+                                float lambda, float eps2, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_armijo_decide, dim3(1), dim3(kDecThreads), 0, s, st, part_grad, part_arm, armijo_blocks(p),
+                       max_bt, c_arm, t0, shrink, st_k, step, T, f, g, v, wx, wy, p.nx, p.ny, lambda, eps2);
     return hipGetLastError();
 }
 
 // f_out = f - t g (unchanged when no step was accepted), optional truncation at
 // zero (step 3 of the algorithm) and optional transposed copy for the projector.
-__global__ __launch_bounds__(256) void k_p2_update(const DevState* st, const float* fcur, const float* __restrict__ g,
-                                                   float* fout, float* foutT, int clamp, int nx, int ny)
+__device__ __forceinline__ void p2_update_block(const DevState* st, const float* fcur, const float* __restrict__ g,
+                                                float* fout, float* foutT, int clamp, int nx, int ny, int tbx,
+                                                int tby, float (*tl)[33])
 {
-    __shared__ float tl[32][33];
     const int k = st->k;
     const float t = st->t;
-    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const int bx = tbx * 32, by = tby * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     for (int r = ty; r < 32; r += 8) {
         const int i = bx + tx, j = by + r;
@@ -509,6 +588,13 @@ __global__ __launch_bounds__(256) void k_p2_update(const DevState* st, const flo
     }
 }
 
+__global__ __launch_bounds__(256) void k_p2_update(const DevState* st, const float* fcur, const float* __restrict__ g,
+                                                   float* fout, float* foutT, int clamp, int nx, int ny)
+{
+    __shared__ float tl[32][33];
+    p2_update_block(st, fcur, g, fout, foutT, clamp, nx, ny, blockIdx.x, blockIdx.y, tl);
+}
+
 hipError_t launch_p2_update(const Plan& p, const DevState* st, const float* fcur, const float* g, float* fout,
                             float* foutT, int clamp, hipStream_t s)
 {
@@ -517,11 +603,10 @@ hipError_t launch_p2_update(const Plan& p, const DevState* st, const float* fcur
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_copy_clamp(const float* src, float* dst, float* dstT, int clamp, int nx,
-                                                    int ny)
+__device__ __forceinline__ void copy_clamp_block(const float* src, float* dst, float* dstT, int clamp, int nx, int ny,
+                                                 int tbx, int tby, float (*tl)[33])
 {
-    __shared__ float tl[32][33];
-    const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+    const int bx = tbx * 32, by = tby * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     for (int r = ty; r < 32; r += 8) {
         const int i = bx + tx, j = by + r;
@@ -541,6 +626,13 @@ __global__ __launch_bounds__(256) void k_copy_clamp(const float* src, float* dst
             if (i < nx && j < ny) dstT[(size_t)i * ny + j] = tl[tx][r];
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_copy_clamp(const float* src, float* dst, float* dstT, int clamp, int nx,
+                                                    int ny)
+{
+    __shared__ float tl[32][33];
+    copy_clamp_block(src, dst, dstT, clamp, nx, ny, blockIdx.x, blockIdx.y, tl);
 }
 
 hipError_t launch_copy_clamp(const Plan& p, const float* src, float* dst, float* dstT, int clamp, hipStream_t s)
@@ -646,6 +738,173 @@ hipError_t launch_tv_vjp(const Plan& p, const float* f, const float* u, float la
     const float inv_s2 = std::isinf(sigma) ? 0.0f : 1.0f / (sigma * sigma);
     hipLaunchKernelGGL(k_vjp_edges, grid, dim3(256), 0, s, f, u, p.nx, p.ny, inv_s2, eps2, e3);
     hipLaunchKernelGGL(k_vjp_gather, grid, dim3(256), 0, s, e3, u, p.nx, p.ny, lambda, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ batched kernels (see batch.h)
+__global__ __launch_bounds__(256) void kb_edges_hist(const SliceDev* __restrict__ sl, const int2* __restrict__ items,
+                                                     int n_items, int imgs, float eps2)
+{
+    __shared__ uint32_t h[kSelectBins];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 w = items[it];
+        const SliceDev& d = sl[w.x];
+        __syncthreads();
+        edges_hist_block(d.buf[imgs], d.nx, d.ny, eps2, d.keys, d.hist, w.y % d.t16x, w.y / d.t16x, h);
+    }
+}
+
+hipError_t blaunch_edges_hist(const BatchDev& b, int img, float eps2, hipStream_t s)
+{
+    const int n = b.n_items[kShT16];
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(kb_edges_hist, dim3(b.grid[kShT16]), dim3(256), 0, s, b.slices, b.items[kShT16], n, img, eps2);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void kb_select_hist(const SliceDev* __restrict__ sl, const int2* __restrict__ items,
+                                                      int n_items, int pass)
+{
+    __shared__ uint32_t h[kSelectBins];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 w = items[it];
+        const SliceDev& d = sl[w.x];
+        __syncthreads();
+        select_hist_block(d.keys, (size_t)d.n_edges, pass, d.st, d.hist + pass * kSelectBins, w.y, d.sel_blocks, h);
+    }
+}
+
+hipError_t blaunch_select_hist(const BatchDev& b, int pass, hipStream_t s)
+{
+    const int n = b.n_items[kShSel];
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(kb_select_hist, dim3(b.grid[kShSel]), dim3(256), 0, s, b.slices, b.items[kShSel], n, pass);
+    return hipGetLastError();
+}
+
+// one block per slice
+__global__ __launch_bounds__(256) void kb_select_finalize(const SliceDev* __restrict__ sl, int pass, float floor_)
+{
+    __shared__ SelShared S;
+    const SliceDev& d = sl[blockIdx.x];
+    select_finalize_block(d.st, pass, d.hist + pass * kSelectBins, floor_, S);
+}
+
+hipError_t blaunch_select_finalize(const BatchDev& b, int pass, float floor_, hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_select_finalize, dim3(b.n), dim3(256), 0, s, b.slices, pass, floor_);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void kb_tv_grad(const SliceDev* __restrict__ sl, const int2* __restrict__ items,
+                                                  int n_items, int fs, int gps, int fos, int vs, float lambda,
+                                                  float eps2, int gs)
+{
+    __shared__ double lds[4];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 w = items[it];
+        const SliceDev& d = sl[w.x];
+        __syncthreads();
+        tv_grad_block(d.buf[fs], bsel(d, gps), d.st, bsel(d, fos), d.buf[vs], d.nx, d.ny, lambda, d.st, 0.0f, eps2,
+                      d.buf[gs], d.buf[kBufWX], d.buf[kBufWY], d.part[kPartGrad], w.y % d.t16x, w.y / d.t16x, w.y,
+                      d.t16x * d.t16y, lds);
+    }
+}
+
+hipError_t blaunch_tv_grad(const BatchDev& b, int f, int g_prev, int f_out, int v, float lambda, float eps2, int g,
+                           hipStream_t s)
+{
+    const int n = b.n_items[kShT16];
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(kb_tv_grad, dim3(b.grid[kShT16]), dim3(256), 0, s, b.slices, b.items[kShT16], n, f, g_prev,
+                       f_out, v, lambda, eps2, g);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void kb_armijo(const SliceDev* __restrict__ sl, const int2* __restrict__ items,
+                                                 int n_items, int fs, int gs, int vs, float lambda, float eps2, float t0,
+                                                 float shrink)
+{
+    __shared__ double red[4][kArmijoFirst];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 w = items[it];
+        const SliceDev& d = sl[w.x];
+        __syncthreads();
+        armijo_block(d.buf[fs], d.buf[gs], d.buf[vs], d.buf[kBufWX], d.buf[kBufWY], d.nx, d.ny, lambda, eps2, t0,
+                     shrink, d.part[kPartArm], w.y % d.t16x, w.y / d.t16x, w.y, d.t16x * d.t16y, red);
+    }
+}
+
+hipError_t blaunch_armijo(const BatchDev& b, int f, int g, int v, float lambda, float eps2, float t0, float shrink,
+                          hipStream_t s)
+{
+    const int n = b.n_items[kShT16];
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(kb_armijo, dim3(b.grid[kShT16]), dim3(256), 0, s, b.slices, b.items[kShT16], n, f, g, v, lambda,
+                       eps2, t0, shrink);
+    return hipGetLastError();
+}
+
+// one block per slice
+__global__ __launch_bounds__(kDecThreads) void kb_armijo_decide(const SliceDev* __restrict__ sl, int max_bt,
+                                                                double c_arm, float t0, float shrink, int step, int T,
+                                                                int fs, int gs, int vs, float lambda, float eps2)
+{
+    __shared__ DecShared S;
+    const SliceDev& d = sl[blockIdx.x];
+    armijo_decide_block(d.st, d.part[kPartGrad], d.part[kPartArm], d.t16x * d.t16y, max_bt, c_arm, t0, shrink,
+                        d.st_k, step, T, d.buf[fs], d.buf[gs], d.buf[vs], d.buf[kBufWX], d.buf[kBufWY], d.nx, d.ny,
+                        lambda, eps2, S);
+}
+
+hipError_t blaunch_armijo_decide(const BatchDev& b, int max_bt, double c_arm, float t0, float shrink, int step, int T,
+                                 int f, int g, int v, float lambda, float eps2, hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_armijo_decide, dim3(b.n), dim3(kDecThreads), 0, s, b.slices, max_bt, c_arm, t0, shrink,
+                       step, T, f, g, v, lambda, eps2);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void kb_p2_update(const SliceDev* __restrict__ sl, const int2* __restrict__ items,
+                                                    int n_items, int fcs, int gs, int fos, int fTs, int clamp)
+{
+    __shared__ float tl[32][33];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 w = items[it];
+        const SliceDev& d = sl[w.x];
+        __syncthreads();
+        p2_update_block(d.st, d.buf[fcs], d.buf[gs], d.buf[fos], bsel(d, fTs), clamp, d.nx, d.ny, w.y % d.t32x,
+                        w.y / d.t32x, tl);
+    }
+}
+
+hipError_t blaunch_p2_update(const BatchDev& b, int fcur, int g, int fout, int foutT, int clamp, hipStream_t s)
+{
+    const int n = b.n_items[kShT32];
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(kb_p2_update, dim3(b.grid[kShT32]), dim3(256), 0, s, b.slices, b.items[kShT32], n, fcur, g,
+                       fout, foutT, clamp);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void kb_copy_clamp(const SliceDev* __restrict__ sl, const int2* __restrict__ items,
+                                                     int n_items, int srcs, int dsts, int dTs, int clamp)
+{
+    __shared__ float tl[32][33];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 w = items[it];
+        const SliceDev& d = sl[w.x];
+        __syncthreads();
+        copy_clamp_block(d.buf[srcs], d.buf[dsts], bsel(d, dTs), clamp, d.nx, d.ny, w.y % d.t32x, w.y / d.t32x, tl);
+    }
+}
+
+hipError_t blaunch_copy_clamp(const BatchDev& b, int src, int dst, int dstT, int clamp, hipStream_t s)
+{
+    const int n = b.n_items[kShT32];
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(kb_copy_clamp, dim3(b.grid[kShT32]), dim3(256), 0, s, b.slices, b.items[kShT32], n, src, dst,
+                       dstT, clamp);
     return hipGetLastError();
 }
 

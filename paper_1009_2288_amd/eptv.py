@@ -25,7 +25,9 @@ SYMBOLS = ["eptv_plan_create", "eptv_plan_destroy", "eptv_plan_nnz", "eptv_works
            "eptv_project_dual", "eptv_backproject", "eptv_tv_gradient", "eptv_select_sigma", "eptv_tv_step", "eptv_reconstruct",
            "eptv_status_string", "eptv_last_error", "eptv_geometry_matrix", "eptv_plan_store_matrix",
            "eptv_project_stored", "eptv_backproject_stored", "eptv_backproject_interp",
-           "eptv_tv_gradient_vjp"]
+           "eptv_tv_gradient_vjp", "eptv_batch_create", "eptv_batch_destroy", "eptv_batch_size", "eptv_batch_plan",
+           "eptv_batch_workspace_bytes", "eptv_batch_set_launch", "eptv_batch_get_launch", "eptv_batch_tune",
+           "eptv_batch_reconstruct"]
 
 
 class EptvError(RuntimeError):
@@ -106,6 +108,16 @@ def _lib() -> C.CDLL:
         L.eptv_project_dual.argtypes = [vp, vp, vp, vp, C.c_float, C.c_float, vp]
         L.eptv_backproject.argtypes = [vp, vp, vp, C.c_float, C.c_float, vp, sz, vp]
         L.eptv_tv_gradient.argtypes = [vp, vp, vp, C.c_float, C.c_float, C.c_float, vp, vp, vp, vp, sz, vp]
+        L.eptv_batch_create.argtypes = [C.POINTER(_Geometry), C.c_int, C.POINTER(vp)]
+        L.eptv_batch_destroy.argtypes = [vp]
+        L.eptv_batch_size.argtypes = [vp, C.POINTER(C.c_int)]
+        L.eptv_batch_plan.argtypes = [vp, C.c_int, C.POINTER(vp)]
+        L.eptv_batch_workspace_bytes.argtypes = [vp, C.POINTER(_Params), C.POINTER(sz)]
+        L.eptv_batch_set_launch.argtypes = [vp, C.c_int, C.c_int, C.c_int]
+        L.eptv_batch_get_launch.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.eptv_batch_tune.argtypes = [vp, C.c_int, vp, C.POINTER(C.c_float), C.POINTER(C.c_float)]
+        L.eptv_batch_reconstruct.argtypes = [vp, C.POINTER(_Params), C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp,
+                                             sz, C.POINTER(_Stats), vp]
         L.eptv_tv_gradient_vjp.argtypes = [vp, vp, vp, C.c_float, C.c_float, C.c_float, vp, vp, sz, vp]
         L.eptv_select_sigma.argtypes = [vp, vp, C.c_double, C.c_float, C.c_float, vp, vp, sz, vp]
         L.eptv_tv_step.argtypes = [vp, C.POINTER(_Params), vp, vp, C.c_float, C.c_int, vp, sz, C.POINTER(_Stats), vp]
@@ -187,11 +199,24 @@ class Plan:
         self._h = h
         self._ws = None
 
+    @classmethod
+    def _borrow(cls, handle, geom, device, owner) -> "Plan":
+        """A Plan object for a plan owned by someone else (a batch slice)."""
+        self = cls.__new__(cls)
+        self.device = device
+        self.nx, self.ny = int(geom.nx), int(geom.ny)
+        self.n_views, self.n_bins = int(geom.n_views), int(geom.n_bins)
+        self._ang = None
+        self._h = handle
+        self._ws = None
+        self._owner = owner
+        return self
+
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and _L is not None:
+        if h is not None and _L is not None and getattr(self, "_owner", None) is None:
             _L.eptv_plan_destroy(h)
-            self._h = None
+        self._h = None
 
     # ------------------------------------------------------------- helpers
     @property
@@ -378,3 +403,106 @@ class Plan:
             if f_ref is None:
                 rec.pop("rmse")
         return f, rec
+
+
+class Batch:
+    """Slices of different geometries iterated together (``eptv_batch``): every
+    phase of an outer iteration is one launch over all slices."""
+
+    def __init__(self, geoms, device: Optional[torch.device] = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libeptv needs a ROCm GPU; none is visible")
+        self.device = torch.device(device if device is not None else "cuda")
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.geoms = list(geoms)
+        structs, self._keep = [], []
+        for g in self.geoms:
+            cg, keep = _geometry(g)
+            structs.append(cg)
+            self._keep.append(keep)
+        arr = (_Geometry * len(structs))(*structs)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(_lib().eptv_batch_create(arr, len(structs), C.byref(h)), "eptv_batch_create")
+        self._h = h
+        self._ws = None
+        self.plans = []
+        for i, g in enumerate(self.geoms):
+            ph = C.c_void_p()
+            _check(_lib().eptv_batch_plan(self._h, i, C.byref(ph)), "eptv_batch_plan")
+            self.plans.append(Plan._borrow(ph, g, self.device, self))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _L is not None:
+            for p in getattr(self, "plans", []):
+                p._h = None
+            _L.eptv_batch_destroy(h)
+        self._h = None
+
+    def __len__(self) -> int:
+        return len(self.geoms)
+
+    def workspace(self, params: Params) -> torch.Tensor:
+        n = C.c_size_t()
+        cp = params._c()
+        _check(_lib().eptv_batch_workspace_bytes(self._h, C.byref(cp), C.byref(n)), "eptv_batch_workspace_bytes")
+        if self._ws is None or self._ws.numel() < n.value:
+            self._ws = torch.empty(int(n.value), dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def set_launch(self, proj_seg: int, proj_blocks_per_cu: int, tile_blocks_per_cu: int) -> None:
+        _check(_lib().eptv_batch_set_launch(self._h, proj_seg, proj_blocks_per_cu, tile_blocks_per_cu),
+               "eptv_batch_set_launch")
+
+    def launch(self) -> dict:
+        a, b, c = C.c_int(), C.c_int(), C.c_int()
+        _check(_lib().eptv_batch_get_launch(self._h, C.byref(a), C.byref(b), C.byref(c)), "eptv_batch_get_launch")
+        return {"proj_seg": a.value, "proj_grid": b.value, "tile_grid": c.value}
+
+    def tune(self, reps: int = 10, stream=None) -> dict:
+        pm, bm = C.c_float(), C.c_float()
+        _check(_lib().eptv_batch_tune(self._h, reps, _stream(stream), C.byref(pm), C.byref(bm)), "eptv_batch_tune")
+        return {"project_ms": pm.value, "backproject_ms": bm.value, **self.launch()}
+
+    def reconstruct(self, ys, params: Params, fs=None, f_refs=None, stats: bool = True, stream=None):
+        """params.outer_iters iterations on every slice; returns (list of f, list of stats dicts or None)."""
+        import numpy as np
+        n = len(self)
+        ys = [p._sino(y, f"y[{i}]") for i, (p, y) in enumerate(zip(self.plans, ys))]
+        if fs is None:
+            fs = [torch.zeros((p.ny, p.nx), dtype=torch.float32, device=self.device) for p in self.plans]
+        fs = [p._img(f, f"f[{i}]") for i, (p, f) in enumerate(zip(self.plans, fs))]
+        if f_refs is not None:
+            f_refs = [p._img(r, f"f_ref[{i}]") for i, (p, r) in enumerate(zip(self.plans, f_refs))]
+        if len(ys) != n or len(fs) != n or (f_refs is not None and len(f_refs) != n):
+            raise ValueError(f"expected {n} slices")
+        ws = self.workspace(params)
+        K, T = params.outer_iters, params.tv_iters
+        yp = (C.c_void_p * n)(*[y.data_ptr() for y in ys])
+        fp = (C.c_void_p * n)(*[f.data_ptr() for f in fs])
+        rp = (C.c_void_p * n)(*[r.data_ptr() for r in f_refs]) if f_refs is not None else None
+        recs, sts = None, None
+        if stats:
+            recs = [{"sigma": np.zeros(max(K, 1), np.float32), "armijo_k": np.zeros(max(K * T, 1), np.int32),
+                     "cgls_steps": np.zeros(max(K, 1), np.int32), "cgls_resid": np.zeros(max(K, 1)),
+                     "rmse": np.zeros(max(K, 1))} for _ in range(n)]
+            sts = (_Stats * n)(*[_Stats(r["sigma"].ctypes.data_as(C.POINTER(C.c_float)),
+                                        r["armijo_k"].ctypes.data_as(C.POINTER(C.c_int32)),
+                                        r["cgls_steps"].ctypes.data_as(C.POINTER(C.c_int32)),
+                                        r["cgls_resid"].ctypes.data_as(C.POINTER(C.c_double)),
+                                        r["rmse"].ctypes.data_as(C.POINTER(C.c_double))) for r in recs])
+        cp = params._c()
+        _check(_lib().eptv_batch_reconstruct(self._h, C.byref(cp), yp, fp, rp, ws.data_ptr(), ws.numel(), sts,
+                                             _stream(stream)), "eptv_batch_reconstruct")
+        if recs is not None:
+            out = []
+            for r in recs:
+                d = {k: v[:K].copy() for k, v in r.items() if k != "armijo_k"}
+                d["armijo_k"] = r["armijo_k"][:K * T].reshape(K, T).copy()
+                if f_refs is None:
+                    d.pop("rmse")
+                out.append(d)
+            recs = out
+        return fs, recs

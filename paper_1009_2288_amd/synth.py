@@ -278,3 +278,41 @@ def make_case(name: str, seed: int = 0) -> Case:
     y = noisy_sinogram(p, i0, seed + 1000)
     img = raster(ell, g.nx, g.ny, g.pixel_mm)
     return Case(name, g, ell, img, p, y, i0, seed)
+
+
+def scaled(ellipses: list[Ellipse], k: float) -> list[Ellipse]:
+    """The same phantom with every length multiplied by ``k`` (values kept)."""
+    return [Ellipse(e.cx * k, e.cy * k, e.a * k, e.b * k, e.angle, e.mu) for e in ellipses]
+
+
+def batch_cases(n: int = 64, seed: int = 0, sizes=(256, 384, 512), views=(20, 60), bins=(368, 736),
+                i0=(1e4, 1e5), with_phantom: bool = True) -> list[Case]:
+    """Slices of uneven size for the batched workload: image side uniform in
+    ``sizes`` (1 mm pixels), views uniform in ``views`` (inclusive), bins
+    uniform in ``bins`` (inclusive), I0 log-uniform in ``i0``; SAD 1000 mm, SDD
+    1500 mm, the fan just covering the image.  Slice ``i`` uses the thorax
+    phantom of seed ``seed + i`` (``+ 100000`` until its inserts fit) scaled
+    to its field (side / 512), and noise
+    seed ``seed + i + 1000``.  The shape draws use PCG64(seed + 50000).
+    ``with_phantom=False`` skips the (slow) supersampled raster; the case's
+    phantom is then None."""
+    rng = np.random.Generator(np.random.PCG64(seed + 50000))
+    out = []
+    for i in range(n):
+        side = int(rng.choice(sizes))
+        v = int(rng.integers(views[0], views[1] + 1))
+        b = int(rng.integers(bins[0], bins[1] + 1))
+        i0_ = float(np.exp(rng.uniform(np.log(i0[0]), np.log(i0[1]))))
+        g = Geometry(side, side, 1.0, v, b, fan_dbeta(side, side, 1.0, 1000.0, b), 1000.0, 1500.0)
+        ps = seed + i
+        while True:  # a few seeds leave no room for the inserts; take the next one
+            try:
+                ell = scaled(phantom_paper(ps), side / 512.0)
+                break
+            except RuntimeError:
+                ps += 100000
+        pr = line_integrals(ell, g)
+        y = noisy_sinogram(pr, i0_, seed + i + 1000)
+        img = raster(ell, side, side, 1.0) if with_phantom else None
+        out.append(Case(f"batch{i}", g, ell, img, pr, y, i0_, seed + i))
+    return out

@@ -4,6 +4,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -71,3 +72,19 @@ def test_null_arguments_are_rejected(lib):
     assert lib.eptv_plan_destroy(None) == 1
     assert lib.eptv_project(None, None, None, 1.0, 0.0, None, 0, None) == 1
     assert lib.eptv_reconstruct(None, None, None, None, None, None, 0, None, None) == 1
+
+
+def test_batch_cases_shapes_are_seeded_and_in_range():
+    from paper_1009_2288_amd import synth
+    a = synth.batch_cases(5, 2, with_phantom=False)
+    b = synth.batch_cases(5, 2, with_phantom=False)
+    for x, y in zip(a, b):
+        assert x.geom == y.geom and np.array_equal(x.y, y.y)
+        assert x.geom.nx in (256, 384, 512) and 20 <= x.geom.n_views <= 60 and 368 <= x.geom.n_bins <= 736
+        assert 1e4 <= x.i0 <= 1e5 and x.phantom is None
+
+
+def test_batch_create_rejects_bad_input_without_gpu(lib):
+    out = C.c_void_p()
+    assert lib.eptv_batch_create(None, 1, C.byref(out)) == 1
+    assert lib.eptv_batch_destroy(None) == 1
