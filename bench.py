@@ -27,6 +27,35 @@ sys.path.insert(0, ROOT)
 FP32_VECTOR_PEAK = 157.3e12  # MI355X published FP32 vector peak, FLOP/s
 HBM_PEAK = 8.0e12            # MI355X published HBM3E bandwidth, B/s
 
+# HBM bytes per launch of the operator kernels on this workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
+# scaled by what the counter reads for a plain 256 MiB device copy (FETCH_SIZE
+# x 2.0, WRITE_SIZE x 1.0); see profiles/eptv_operators_512x512_40views_pmc_bytes.md.
+# Each entry holds the hash of the kernel's source file when the counters were
+# taken: if the source has changed since, the figure is stale and reported as
+# null.
+PMC_TRAFFIC = {
+    "project": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "7012b6bc1a09b6fc",
+                "bytes": (8336.7 * 2.0 + 115.0 * 1.0) * 1024},
+    "backproject": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "7012b6bc1a09b6fc",
+                    "bytes": (5980.5 * 2.0 + 1024.0 * 1.0) * 1024},
+    "project_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "8f4892c0ac95405b",
+                       "bytes": (60999.1 * 2.0 + 125.2 * 1.0) * 1024},
+    "backproject_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "8f4892c0ac95405b",
+                           "bytes": (56344.3 * 2.0 + 1304.0 * 1.0) * 1024},
+}
+
+
+def pmc_traffic(kernel):
+    import hashlib
+    e = PMC_TRAFFIC.get(kernel)
+    if e is None:
+        return None
+    with open(os.path.join(ROOT, e["source"]), "rb") as fh:
+        if hashlib.sha256(fh.read()).hexdigest()[:16] != e["sha256_16"]:
+            return None
+    return e["bytes"]
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -137,6 +166,9 @@ def main():
     ap.add_argument("--rmse-seeds", type=int, default=10, help="seeds for the time-to-RMSE leg (0 to skip)")
     ap.add_argument("--batch-slices", type=int, default=64, help="slices of the batched leg (0 to skip)")
     ap.add_argument("--batch-iters", type=int, default=20)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="finally copy a buffer of this many MiB on the device (a plain copy kernel of known "
+                         "size, to calibrate hardware byte counters against)")
     ap.add_argument("--operator", choices=["fly", "stored"], default="fly",
                     help="P and P^T on the fly, or from the stored float32 matrix")
     args = ap.parse_args()
@@ -210,13 +242,13 @@ def main():
         nbytes = 8.0 * nnz + 8.0 * (rows + 1) + 4.0 * (n_in + n_out)
         achieved = nbytes / (t_dom * 1e-3)
         roof = {"bound": "hbm", "kernel": dom + "_stored", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": None, "avg_ms": t_dom,
-                "algorithmic_bytes_per_launch": nbytes, "nnz": nnz}
+                "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": pmc_traffic(dom + "_stored"),
+                "avg_ms": t_dom, "algorithmic_bytes_per_launch": nbytes, "nnz": nnz}
     else:
         flops = 2.0 * nnz
         achieved = flops / (t_dom * 1e-3)
         roof = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK, "traffic": pmc_traffic(dom),
                 "avg_ms": t_dom, "algorithmic_flops_per_launch": flops, "nnz": nnz}
     roof["operators_avg_ms"] = op_ms
     log("bench: " + ", ".join(f"{k} {v * 1e3:.1f} us" for k, v in op_ms.items()) + f", nnz {nnz}")
@@ -265,6 +297,11 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+    if args.copy_mib > 0:
+        src = torch.ones(args.copy_mib * 2**18, dtype=torch.float32, device="cuda")
+        dst = src.clone()
+        torch.cuda.synchronize()
+        log(f"bench: copied {args.copy_mib} MiB ({float(dst[-1]):.0f})")
 
 
 if __name__ == "__main__":
