@@ -265,6 +265,46 @@ int eptv_batch_tune(eptv_batch batch, int reps, void* stream, float* proj_ms, fl
 int eptv_batch_reconstruct(eptv_batch batch, const eptv_params* params, const float* const* y, float* const* f,
                            const float* const* f_ref, void* ws, size_t ws_bytes, eptv_stats* stats, void* stream);
 
+/* ------------------------------------------------------------------ the U-Net
+ * A convolutional network (not part of the paper) that maps an early EPTV
+ * reconstruction to the half-edge weight maps of Eq. 5 / A3 and to an image,
+ * used to start the EPTV iteration of Sec. 2.2 closer to its end.  Encoder
+ * levels of two 3x3 convolutions (base << level channels, ReLU) joined by 2x2
+ * average pooling; decoder levels of a stride-2 2x2 transposed convolution
+ * (ReLU), concatenation with the encoder's output of that level, two 3x3
+ * convolutions (ReLU); a final 1x1 convolution.  bf16 weights and
+ * activations, fp32 accumulation on the matrix cores, fp32 master weights
+ * and Adam.  Tensors at the boundary are device fp32 NHWC [n][h][w][c].
+ * Parameters: a flat fp32 array, per layer (encoder levels first, then the
+ * decoder from the bottom up, then the 1x1) weights laid out
+ * [3][3][C_in][C_out] / [2][2][C_in][C_out] / [C_in][C_out], then the bias. */
+typedef struct eptv_unet_s* eptv_unet;
+
+/* height and width must be multiples of 2^(levels-1); base a multiple of 8
+ * when levels > 1.  Buffers are sized for max_batch images. */
+int eptv_unet_create(int c_in, int c_out, int base, int levels, int max_batch, int height, int width,
+                     eptv_unet* out);
+int eptv_unet_destroy(eptv_unet net);
+int eptv_unet_param_count(eptv_unet net, long long* n);
+/* Host arrays of eptv_unet_param_count floats; set_params also clears the
+ * Adam moments.  All three synchronise the stream. */
+int eptv_unet_set_params(eptv_unet net, const float* params, void* stream);
+int eptv_unet_get_params(eptv_unet net, float* params, void* stream);
+int eptv_unet_get_grads(eptv_unet net, float* grads, void* stream);
+/* y = net(x) for n <= max_batch images; x [n][h][w][c_in], y [n][h][w][c_out]. */
+int eptv_unet_forward(eptv_unet net, const float* x, int n, float* y, void* stream);
+/* Gradients of sum(dy * y) for the last forward's batch: parameter gradients
+ * (overwritten, read with eptv_unet_get_grads) and, if dx is given, the input
+ * gradient [n][h][w][c_in]. */
+int eptv_unet_backward(eptv_unet net, const float* dy, float* dx, void* stream);
+/* One Adam step (Kingma & Ba) on the parameters with the current gradients;
+ * step counts from 1. */
+int eptv_unet_adam(eptv_unet net, float lr, float beta1, float beta2, float eps, int step, void* stream);
+/* loss = mean((y - target)^2) over n floats into a device float; dy (may be
+ * NULL) = its gradient 2 (y - target) / n. */
+int eptv_unet_mse(eptv_unet net, const float* y, const float* target, size_t n, float* dy, float* loss,
+                  void* stream);
+
 const char* eptv_status_string(int status);
 
 /* Last HIP error text seen by the library on this thread ("" if none). */

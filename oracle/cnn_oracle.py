@@ -10,6 +10,14 @@ The network is not part of the paper (which has no learned component); it
 maps an early EPTV reconstruction to the half-edge weight maps of Eq. 5 / A3
 and to an image, for warm-starting the EPTV iteration of Sec. 2.2.
 
+Precision: float64 arithmetic.  The network is specified with bf16 weights
+and activations and fp32 accumulation; ``bf16`` rounds to that format, and
+the forward / backward passes take an optional ``store`` function applied
+wherever such an implementation stores a tensor (each layer's output, the
+pooled and the upsampled features, each layer's input gradient, the skip
+gradient after the pooling path joins it), so the reference can follow the
+specified storage precision while computing every sum exactly.
+
 Layout: activations [N][H][W][C] (channels last); 3x3 convolution weights
 [3][3][C_in][C_out] (cross-correlation, zero padding 1, stride 1); 2x2
 transposed-convolution weights [2][2][C_in][C_out] (stride 2); 1x1 weights
@@ -18,6 +26,18 @@ transposed-convolution weights [2][2][C_in][C_out] (stride 2); 1x1 weights
 from __future__ import annotations
 
 import numpy as np
+
+
+def bf16(a):
+    """Round to the nearest bfloat16 (8-bit significand), ties to even; float64 out."""
+    a = np.asarray(a, np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _same(a):
+    return a
 
 
 # ------------------------------------------------------------------ layers
@@ -129,59 +149,65 @@ def _levels(p: dict) -> int:
     return sum(1 for k in p if k.startswith("e") and k.endswith("a.w"))
 
 
-def unet_forward(p: dict, x):
+def unet_forward(p: dict, x, store=_same):
     """Returns (output, cache).  Every conv but the head is followed by a ReLU."""
     L = _levels(p)
+    x = store(x)
     cache = {"x": x}
     h = x
     skips = []
     for l in range(L):
         if l > 0:
-            h = avgpool2(h)
+            h = store(avgpool2(h))
         cache[f"e{l}a.in"] = h
-        h = relu(conv3x3(h, p[f"e{l}a.w"], p[f"e{l}a.b"]))
+        h = store(relu(conv3x3(h, p[f"e{l}a.w"], p[f"e{l}a.b"])))
         cache[f"e{l}a.out"] = h
-        h = relu(conv3x3(h, p[f"e{l}b.w"], p[f"e{l}b.b"]))
+        h = store(relu(conv3x3(h, p[f"e{l}b.w"], p[f"e{l}b.b"])))
         cache[f"e{l}b.in"] = cache[f"e{l}a.out"]
         cache[f"e{l}b.out"] = h
         skips.append(h)
     for l in range(L - 2, -1, -1):
         cache[f"u{l}.in"] = h
-        h = relu(tconv2x2(h, p[f"u{l}.w"], p[f"u{l}.b"]))
+        h = store(relu(tconv2x2(h, p[f"u{l}.w"], p[f"u{l}.b"])))
         cache[f"u{l}.out"] = h
         h = np.concatenate([skips[l], h], axis=3)
         cache[f"d{l}a.in"] = h
-        h = relu(conv3x3(h, p[f"d{l}a.w"], p[f"d{l}a.b"]))
+        h = store(relu(conv3x3(h, p[f"d{l}a.w"], p[f"d{l}a.b"])))
         cache[f"d{l}a.out"] = h
         cache[f"d{l}b.in"] = h
-        h = relu(conv3x3(h, p[f"d{l}b.w"], p[f"d{l}b.b"]))
+        h = store(relu(conv3x3(h, p[f"d{l}b.w"], p[f"d{l}b.b"])))
         cache[f"d{l}b.out"] = h
     cache["head.in"] = h
     return conv1x1(h, p["head.w"], p["head.b"]), cache
 
 
-def unet_backward(p: dict, cache: dict, dout) -> dict:
+def unet_backward(p: dict, cache: dict, dout, store=_same) -> dict:
     """Gradients of sum(dout * output) with respect to every parameter (and "x")."""
     L = _levels(p)
     g = {}
+    dout = store(dout)
     dh, g["head.w"], g["head.b"] = conv1x1_backward(cache["head.in"], p["head.w"], dout)
+    dh = store(dh)
     dskip = [None] * L
     for l in range(0, L - 1):
         dh = relu_backward(cache[f"d{l}b.out"], dh)
         dh, g[f"d{l}b.w"], g[f"d{l}b.b"] = conv3x3_backward(cache[f"d{l}b.in"], p[f"d{l}b.w"], dh)
-        dh = relu_backward(cache[f"d{l}a.out"], dh)
+        dh = relu_backward(cache[f"d{l}a.out"], store(dh))
         dh, g[f"d{l}a.w"], g[f"d{l}a.b"] = conv3x3_backward(cache[f"d{l}a.in"], p[f"d{l}a.w"], dh)
+        dh = store(dh)
         cs = cache[f"e{l}b.out"].shape[3]
         dskip[l], dh = dh[..., :cs], dh[..., cs:]
         dh = relu_backward(cache[f"u{l}.out"], dh)
         dh, g[f"u{l}.w"], g[f"u{l}.b"] = tconv2x2_backward(cache[f"u{l}.in"], p[f"u{l}.w"], dh)
+        dh = store(dh)
     for l in range(L - 1, -1, -1):
         if dskip[l] is not None:
-            dh = dh + dskip[l]
+            dh = store(dh + dskip[l])
         dh = relu_backward(cache[f"e{l}b.out"], dh)
         dh, g[f"e{l}b.w"], g[f"e{l}b.b"] = conv3x3_backward(cache[f"e{l}b.in"], p[f"e{l}b.w"], dh)
-        dh = relu_backward(cache[f"e{l}a.out"], dh)
+        dh = relu_backward(cache[f"e{l}a.out"], store(dh))
         dh, g[f"e{l}a.w"], g[f"e{l}a.b"] = conv3x3_backward(cache[f"e{l}a.in"], p[f"e{l}a.w"], dh)
+        dh = store(dh)
         if l > 0:
             dh = avgpool2_backward(dh)
     g["x"] = dh

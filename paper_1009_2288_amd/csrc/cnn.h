@@ -1,0 +1,61 @@
+// cnn.h -- the U-Net layer kernels (cnn.hip) and the network (unet.cpp).
+// Internal to the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstddef>
+#include <cstdint>
+
+namespace eptv {
+
+enum ConvMode : int { kConv3 = 0, kPoint = 1, kUp = 2, kUpBack = 3 };
+
+// One implicit-GEMM convolution.  x / y are NHWC bf16 (uint16 bit patterns)
+// with channel stride *_cs and channel offset *_co (a slice of a wider
+// tensor); y32, if set, receives fp32 output instead of y.  h, w: the GEMM's
+// pixel grid (the input grid; kUp writes 2h x 2w, kUpBack reads 2h x 2w).
+struct ConvArgs {
+    const uint16_t* x = nullptr;
+    int x_cs = 0, x_co = 0;
+    uint16_t* y = nullptr;
+    float* y32 = nullptr;
+    int y_cs = 0, y_co = 0;
+    const uint16_t* wt = nullptr;  // packed [q][n_pad][k_pad]
+    const float* bias = nullptr;   // [cout] or null
+    int n_img = 0, h = 0, w = 0;
+    int cin = 0;   // GEMM input channels (per parity for kUpBack)
+    int cout = 0;  // GEMM output channels
+    int n_pad = 0, k_pad = 0;
+    int relu = 0;
+};
+
+inline int pad64(int n) { return (n + 63) / 64 * 64; }
+
+hipError_t launch_conv(const ConvArgs& a, int mode, hipStream_t s);
+int wgrad_chunks(const ConvArgs& a, int chunk_px);
+hipError_t launch_wgrad(const ConvArgs& a, int mode, const uint16_t* dy, int dy_cs, int dy_co, int chunk_px,
+                        float* part, float* out, hipStream_t s);
+hipError_t launch_bias_grad(const uint16_t* dy, const float* dy32, int cs, int co, int npix, int c, float* db,
+                            hipStream_t s);
+hipError_t launch_relu_mask(uint16_t* dy, int dcs, int dco, const uint16_t* y, int ycs, int yco, int npix, int c,
+                            hipStream_t s);
+hipError_t launch_avgpool(const uint16_t* x, int xcs, int xco, uint16_t* y, int n_img, int h, int w, int c,
+                          hipStream_t s);
+hipError_t launch_avgpool_back(const uint16_t* dy, uint16_t* dx, int dxcs, int dxco, int n_img, int h, int w, int c,
+                               int accumulate, hipStream_t s);
+hipError_t launch_to_bf16(const float* x, uint16_t* y, size_t n, hipStream_t s);
+hipError_t launch_to_f32(const uint16_t* x, float* y, size_t n, hipStream_t s);
+hipError_t launch_add_slice(const uint16_t* src, int scs, int sco, uint16_t* dst, int dcs, int dco, int npix, int c,
+                            hipStream_t s);
+hipError_t launch_pack(const float* w, int mode, int back, int ci, int co, int n_pad, int k_pad, uint16_t* out,
+                       hipStream_t s);
+hipError_t launch_unpack_grad(const float* g, int mode, int ci, int co, int n_pad, int k_pad, float* out,
+                              hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, size_t n, float lr, float b1, float b2, float eps,
+                       int step, hipStream_t s);
+hipError_t launch_mse(const float* y, const float* t, size_t n, float* dy, double* part, int nblocks, float* loss,
+                      hipStream_t s);
+
+}  // namespace eptv

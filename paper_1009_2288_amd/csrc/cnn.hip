@@ -1,0 +1,557 @@
+// cnn.hip -- the U-Net's layers on gfx950: bf16 operands, fp32 accumulation
+// on the matrix cores (v_mfma_f32_16x16x32_bf16).
+//
+// Every convolution is one implicit GEMM, out[p][n] = sum_k A(p, k) W[n][k],
+// p an output pixel, n an output channel, k a (tap, input channel) pair, with
+// A gathered from the input on the fly (no im2col buffer):
+//   kConv3  3x3 cross-correlation, zero padding 1: k = tap * C_in + c,
+//           A(p, k) = X[y + dy(tap)][x + dx(tap)][c]
+//   kPoint  1x1: A(p, k) = X[p][k]
+//   kUp     stride-2 2x2 transposed convolution, one GEMM per output parity
+//           q = (a, c): A(p, k) = X[p][k], written to (2y + a, 2x + c)
+//   kUpBack its backward data pass: k = q * C_out + o,
+//           A(p, k) = dY[2y + a][2x + c][o]
+// Tensors are NHWC bf16 with a channel stride, so a layer can read or write a
+// channel slice of a wider tensor (the decoder's concatenation of skip and
+// upsampled features is never copied).  Weights are packed [n][k] (k
+// contiguous, K and N padded to multiples of 64 with zeros).
+//
+// MFMA 16x16x32 bf16 operand layout (lane l of 64): A holds row l % 16,
+// columns 8 (l / 16) .. +7; B holds column l % 16, rows 8 (l / 16) .. +7;
+// the 4 accumulators hold rows 4 (l / 16) .. +3 of column l % 16.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "cnn.h"
+
+namespace eptv {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    // round to nearest even (finite inputs)
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+union Frag {
+    bf16x8 v;
+    uint4 u;
+    uint16_t h[8];
+};
+
+__device__ __forceinline__ Frag zero_frag()
+{
+    Frag f;
+    f.u = make_uint4(0u, 0u, 0u, 0u);
+    return f;
+}
+
+// 8 consecutive k of A(p, k) for one pixel p = (img, y, x) of the GEMM grid.
+template <int MODE>
+__device__ __forceinline__ Frag gather_a(const ConvArgs& a, int img, int y, int x, int k)
+{
+    Frag f = zero_frag();
+    if (MODE == kConv3) {
+        if (a.cin % 8 == 0) {
+            if (k >= 9 * a.cin) return f;
+            const int tap = k / a.cin, c = k - tap * a.cin;
+            const int ys = y + tap / 3 - 1, xs = x + tap % 3 - 1;
+            if ((unsigned)ys >= (unsigned)a.h || (unsigned)xs >= (unsigned)a.w) return f;
+            f.u = *reinterpret_cast<const uint4*>(a.x + (((size_t)img * a.h + ys) * a.w + xs) * a.x_cs + a.x_co + c);
+        } else {
+            for (int i = 0; i < 8; ++i) {
+                const int kk = k + i;
+                if (kk >= 9 * a.cin) break;
+                const int tap = kk / a.cin, c = kk - tap * a.cin;
+                const int ys = y + tap / 3 - 1, xs = x + tap % 3 - 1;
+                if ((unsigned)ys < (unsigned)a.h && (unsigned)xs < (unsigned)a.w)
+                    f.h[i] = a.x[(((size_t)img * a.h + ys) * a.w + xs) * a.x_cs + a.x_co + c];
+            }
+        }
+    } else if (MODE == kPoint || MODE == kUp) {
+        if (a.cin % 8 == 0) {
+            if (k >= a.cin) return f;
+            f.u = *reinterpret_cast<const uint4*>(a.x + (((size_t)img * a.h + y) * a.w + x) * a.x_cs + a.x_co + k);
+        } else {
+            for (int i = 0; i < 8 && k + i < a.cin; ++i)
+                f.h[i] = a.x[(((size_t)img * a.h + y) * a.w + x) * a.x_cs + a.x_co + k + i];
+        }
+    } else {  // kUpBack: the input is the 2h x 2w gradient with cin channels per parity
+        if (k >= 4 * a.cin) return f;
+        const int q = k / a.cin, o = k - q * a.cin;
+        const int ys = 2 * y + (q >> 1), xs = 2 * x + (q & 1);
+        f.u = *reinterpret_cast<const uint4*>(a.x + (((size_t)img * 2 * a.h + ys) * 2 * a.w + xs) * a.x_cs + a.x_co +
+                                              o);
+    }
+    return f;
+}
+
+// Block: 4 waves x 16 consecutive pixels of the flattened (image, y, x) order
+// of the GEMM grid, x 64 output channels; grid (pixel groups, channel blocks,
+// parity q for kUp).  Each lane decodes its own pixel, so any image size works.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_conv(ConvArgs a)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int npix = a.n_img * a.h * a.w;
+    const int p0 = blockIdx.x * 64 + wave * 16;
+    if (p0 >= npix) return;  // whole wave
+    const int n0 = blockIdx.y * 64;
+    const int q = MODE == kUp ? (int)blockIdx.z : 0;
+    const uint16_t* wq = a.wt + (size_t)q * a.n_pad * a.k_pad;
+    const int mrow = lane & 15, kq = (lane >> 4) * 8;
+    // this lane's A row: pixel p0 + mrow
+    const int pa = p0 + mrow;
+    const bool va = pa < npix;
+    const int ia = pa / (a.h * a.w), ra = pa - ia * a.h * a.w, ya = ra / a.w, xa = ra - ya * a.w;
+    floatx4 acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k0 = 0; k0 < a.k_pad; k0 += 32) {
+        const Frag fa = va ? gather_a<MODE>(a, ia, ya, xa, k0 + kq) : zero_frag();
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            Frag fb;
+            fb.u = *reinterpret_cast<const uint4*>(wq + (size_t)(n0 + 16 * j + mrow) * a.k_pad + k0 + kq);
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa.v, fb.v, acc[j], 0, 0, 0);
+        }
+    }
+    // epilogue: accumulator r of lane l is pixel p0 + 4 (l / 16) + r, channel n0 + 16 j + l % 16
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int p = p0 + (lane >> 4) * 4 + r;
+        if (p >= npix) continue;
+        const int img = p / (a.h * a.w), rr = p - img * a.h * a.w, y = rr / a.w, x = rr - y * a.w;
+        size_t pix;
+        if (MODE == kUp)
+            pix = ((size_t)img * 2 * a.h + 2 * y + (q >> 1)) * 2 * a.w + 2 * x + (q & 1);
+        else
+            pix = (size_t)p;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int n = n0 + 16 * j + mrow;
+            if (n >= a.cout) continue;
+            float v = acc[j][r] + (a.bias ? a.bias[n] : 0.0f);
+            if (a.relu) v = fmaxf(v, 0.0f);
+            if (a.y32)
+                a.y32[pix * a.y_cs + a.y_co + n] = v;
+            else
+                a.y[pix * a.y_cs + a.y_co + n] = f2bf(v);
+        }
+    }
+}
+
+hipError_t launch_conv(const ConvArgs& a, int mode, hipStream_t s)
+{
+    const int npix = a.n_img * a.h * a.w;
+    dim3 grid((unsigned)((npix + 63) / 64), (unsigned)(a.n_pad / 64), mode == kUp ? 4u : 1u);
+    switch (mode) {
+    case kConv3: hipLaunchKernelGGL(k_conv<kConv3>, grid, dim3(256), 0, s, a); break;
+    case kPoint: hipLaunchKernelGGL(k_conv<kPoint>, grid, dim3(256), 0, s, a); break;
+    case kUp: hipLaunchKernelGGL(k_conv<kUp>, grid, dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL(k_conv<kUpBack>, grid, dim3(256), 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ weight gradients
+// dW[n][k] = sum_p dY[p][n] A(p, k), split over chunks of pixels: block
+// (chunk, n block, k block) writes its 64 x 64 fp32 partial; k_wgrad_reduce
+// sums the chunks in order.  MFMA rows are n (A' = dY^T), columns k, and the
+// reduction runs over 32 pixels per instruction.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_wgrad(ConvArgs a, const uint16_t* __restrict__ dy, int dy_cs, int dy_co,
+                                               int chunk_px, float* part)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int chunk = blockIdx.x;
+    const int n0 = blockIdx.y * 64 + wave * 16;
+    const int k0 = blockIdx.z * 64;
+    const int q = MODE == kUp ? (int)(k0 / a.k_pad) : 0;  // kUp: the 4 parities side by side along k
+    const int kb = MODE == kUp ? k0 - q * a.k_pad : k0;
+    const int row = lane & 15, pq = (lane >> 4) * 8;
+    const int npix = a.n_img * a.h * a.w;
+    const int p_beg = chunk * chunk_px, p_end = min(npix, p_beg + chunk_px);
+    floatx4 acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int p0 = p_beg; p0 < p_end; p0 += 32) {
+        Frag fa = zero_frag();
+        const int n = n0 + row;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int p = p0 + pq + i;
+            if (p < p_end && n < a.cout) {
+                size_t pix = (size_t)p;
+                if (MODE == kUp) {
+                    const int img = p / (a.h * a.w), r = p - img * a.h * a.w, yy = r / a.w, xx = r - yy * a.w;
+                    pix = ((size_t)img * 2 * a.h + 2 * yy + (q >> 1)) * 2 * a.w + 2 * xx + (q & 1);
+                }
+                fa.h[i] = dy[pix * dy_cs + dy_co + n];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            Frag fb = zero_frag();
+            const int k = kb + 16 * j + row;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int p = p0 + pq + i;
+                if (p >= p_end) break;
+                const int img = p / (a.h * a.w), r = p - img * a.h * a.w, yy = r / a.w, xx = r - yy * a.w;
+                if (MODE == kConv3) {
+                    if (k < 9 * a.cin) {
+                        const int tap = k / a.cin, c = k - tap * a.cin;
+                        const int ys = yy + tap / 3 - 1, xs = xx + tap % 3 - 1;
+                        if ((unsigned)ys < (unsigned)a.h && (unsigned)xs < (unsigned)a.w)
+                            fb.h[i] = a.x[(((size_t)img * a.h + ys) * a.w + xs) * a.x_cs + a.x_co + c];
+                    }
+                } else if (MODE == kPoint || MODE == kUp) {
+                    if (k < a.cin) fb.h[i] = a.x[(size_t)p * a.x_cs + a.x_co + k];
+                } else {  // kUpBack
+                    if (k < 4 * a.cin) {
+                        const int qq = k / a.cin, o = k - qq * a.cin;
+                        const int ys = 2 * yy + (qq >> 1), xs = 2 * xx + (qq & 1);
+                        fb.h[i] = a.x[(((size_t)img * 2 * a.h + ys) * 2 * a.w + xs) * a.x_cs + a.x_co + o];
+                    }
+                }
+            }
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa.v, fb.v, acc[j], 0, 0, 0);
+        }
+    }
+    // partial[chunk][n][k] over the padded n x (4 or 1) k_pad grid
+    const int kw = MODE == kUp ? 4 * a.k_pad : a.k_pad;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int n = n0 + (lane >> 4) * 4 + r, k = k0 + 16 * j + row;
+            part[((size_t)chunk * a.n_pad + n) * kw + k] = acc[j][r];
+        }
+}
+
+__global__ void k_wgrad_reduce(const float* __restrict__ part, int chunks, size_t per, float* out)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < per; i += (size_t)gridDim.x * blockDim.x) {
+        float s = 0.0f;
+        for (int c = 0; c < chunks; ++c) s += part[(size_t)c * per + i];
+        out[i] = s;
+    }
+}
+
+int wgrad_chunks(const ConvArgs& a, int chunk_px)
+{
+    const int npix = a.n_img * a.h * a.w;
+    return (npix + chunk_px - 1) / chunk_px;
+}
+
+hipError_t launch_wgrad(const ConvArgs& a, int mode, const uint16_t* dy, int dy_cs, int dy_co, int chunk_px,
+                        float* part, float* out, hipStream_t s)
+{
+    const int chunks = wgrad_chunks(a, chunk_px);
+    const int kw = mode == kUp ? 4 * a.k_pad : a.k_pad;
+    dim3 grid((unsigned)chunks, (unsigned)(a.n_pad / 64), (unsigned)(kw / 64));
+    switch (mode) {
+    case kConv3:
+        hipLaunchKernelGGL(k_wgrad<kConv3>, grid, dim3(256), 0, s, a, dy, dy_cs, dy_co, chunk_px, part);
+        break;
+    case kPoint:
+        hipLaunchKernelGGL(k_wgrad<kPoint>, grid, dim3(256), 0, s, a, dy, dy_cs, dy_co, chunk_px, part);
+        break;
+    case kUp: hipLaunchKernelGGL(k_wgrad<kUp>, grid, dim3(256), 0, s, a, dy, dy_cs, dy_co, chunk_px, part); break;
+    default:
+        hipLaunchKernelGGL(k_wgrad<kUpBack>, grid, dim3(256), 0, s, a, dy, dy_cs, dy_co, chunk_px, part);
+        break;
+    }
+    const size_t per = (size_t)a.n_pad * kw;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)std::min<size_t>((per + 255) / 256, 4096)), dim3(256), 0, s,
+                       part, chunks, per, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ elementwise
+// bias gradient: db[n] = sum over pixels of dy[p][n] (fixed order per n)
+__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ dy, int cs, int co, int npix, int c,
+                                                   const float* dy32, float* db)
+{
+    __shared__ float red[256];
+    const int n = blockIdx.x;
+    float s = 0.0f;
+    for (int p = threadIdx.x; p < npix; p += 256)
+        s += dy32 ? dy32[(size_t)p * cs + co + n] : bf2f(dy[(size_t)p * cs + co + n]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) db[n] = red[0];
+}
+
+hipError_t launch_bias_grad(const uint16_t* dy, const float* dy32, int cs, int co, int npix, int c, float* db,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bias_grad, dim3((unsigned)c), dim3(256), 0, s, dy, cs, co, npix, c, dy32, db);
+    return hipGetLastError();
+}
+
+// dy *= (y > 0): the ReLU's backward, in place on a channel slice
+__global__ void k_relu_mask(uint16_t* dy, int dcs, int dco, const uint16_t* y, int ycs, int yco, int npix, int c)
+{
+    const size_t n = (size_t)npix * c;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t p = i / c, k = i - p * c;
+        if (!(bf2f(y[p * ycs + yco + k]) > 0.0f)) dy[p * dcs + dco + k] = 0;
+    }
+}
+
+hipError_t launch_relu_mask(uint16_t* dy, int dcs, int dco, const uint16_t* y, int ycs, int yco, int npix, int c,
+                            hipStream_t s)
+{
+    const size_t n = (size_t)npix * c;
+    hipLaunchKernelGGL(k_relu_mask, dim3((unsigned)std::min<size_t>((n + 255) / 256, 8192)), dim3(256), 0, s, dy, dcs,
+                       dco, y, ycs, yco, npix, c);
+    return hipGetLastError();
+}
+
+// 2x2 average pooling and its adjoint (channel slices)
+__global__ void k_avgpool(const uint16_t* x, int xcs, int xco, uint16_t* y, int n_img, int h, int w, int c)
+{
+    const size_t n = (size_t)n_img * (h / 2) * (w / 2) * c;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(i % c);
+        size_t t = i / c;
+        const int xo = (int)(t % (w / 2));
+        t /= (w / 2);
+        const int yo = (int)(t % (h / 2));
+        const int img = (int)(t / (h / 2));
+        float s = 0.0f;
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx)
+                s += bf2f(x[(((size_t)img * h + 2 * yo + dy) * w + 2 * xo + dx) * xcs + xco + k]);
+        y[i] = f2bf(0.25f * s);
+    }
+}
+
+__global__ void k_avgpool_back(const uint16_t* dy, uint16_t* dx, int dxcs, int dxco, int n_img, int h, int w, int c,
+                               int accumulate)
+{
+    // dx has h x w pixels; dy has h/2 x w/2 with c channels (dense)
+    const size_t n = (size_t)n_img * h * w * c;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(i % c);
+        size_t t = i / c;
+        const int x = (int)(t % w);
+        t /= w;
+        const int y = (int)(t % h);
+        const int img = (int)(t / h);
+        float v = 0.25f * bf2f(dy[(((size_t)img * (h / 2) + y / 2) * (w / 2) + x / 2) * c + k]);
+        uint16_t* d = dx + (((size_t)img * h + y) * w + x) * dxcs + dxco + k;
+        if (accumulate) v += bf2f(*d);
+        *d = f2bf(v);
+    }
+}
+
+hipError_t launch_avgpool(const uint16_t* x, int xcs, int xco, uint16_t* y, int n_img, int h, int w, int c,
+                          hipStream_t s)
+{
+    const size_t n = (size_t)n_img * (h / 2) * (w / 2) * c;
+    hipLaunchKernelGGL(k_avgpool, dim3((unsigned)std::min<size_t>((n + 255) / 256, 8192)), dim3(256), 0, s, x, xcs, xco,
+                       y, n_img, h, w, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_avgpool_back(const uint16_t* dy, uint16_t* dx, int dxcs, int dxco, int n_img, int h, int w, int c,
+                               int accumulate, hipStream_t s)
+{
+    const size_t n = (size_t)n_img * h * w * c;
+    hipLaunchKernelGGL(k_avgpool_back, dim3((unsigned)std::min<size_t>((n + 255) / 256, 8192)), dim3(256), 0, s, dy, dx,
+                       dxcs, dxco, n_img, h, w, c, accumulate);
+    return hipGetLastError();
+}
+
+// fp32 <-> bf16 (dense)
+__global__ void k_to_bf16(const float* x, uint16_t* y, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        y[i] = f2bf(x[i]);
+}
+
+hipError_t launch_to_bf16(const float* x, uint16_t* y, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)std::min<size_t>((n + 255) / 256, 8192)), dim3(256), 0, s, x, y, n);
+    return hipGetLastError();
+}
+
+__global__ void k_to_f32(const uint16_t* x, float* y, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        y[i] = bf2f(x[i]);
+}
+
+hipError_t launch_to_f32(const uint16_t* x, float* y, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)std::min<size_t>((n + 255) / 256, 8192)), dim3(256), 0, s, x, y, n);
+    return hipGetLastError();
+}
+
+// accumulate a bf16 channel slice into another (the skip gradient joins the encoder's)
+__global__ void k_add_slice(const uint16_t* src, int scs, int sco, uint16_t* dst, int dcs, int dco, int npix, int c)
+{
+    const size_t n = (size_t)npix * c;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t p = i / c, k = i - p * c;
+        uint16_t* d = dst + p * dcs + dco + k;
+        *d = f2bf(bf2f(*d) + bf2f(src[p * scs + sco + k]));
+    }
+}
+
+hipError_t launch_add_slice(const uint16_t* src, int scs, int sco, uint16_t* dst, int dcs, int dco, int npix, int c,
+                            hipStream_t s)
+{
+    const size_t n = (size_t)npix * c;
+    hipLaunchKernelGGL(k_add_slice, dim3((unsigned)std::min<size_t>((n + 255) / 256, 8192)), dim3(256), 0, s, src, scs,
+                       sco, dst, dcs, dco, npix, c);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ weights
+// fp32 master (oracle layout) -> packed bf16 GEMM operands
+//   conv3 forward: W[a][c][i][o] -> P[o][(3a+c) Ci + i]
+//   conv3 backward data: P[i][(8 - tap) Co + o] (flipped taps, in/out swapped)
+//   1x1: W[i][o] -> P[o][i];  backward data: P[i][o]
+//   up (2x2, stride 2) forward: W[a][c][i][o] -> P[q = 2a + c][o][i]
+//   up backward data: P[i][q Co + o]
+__global__ void k_pack(const float* w, int mode, int back, int ci, int co, int n_pad, int k_pad, uint16_t* out)
+{
+    const int nq = (mode == kUp && !back) ? 4 : 1;
+    const size_t total = (size_t)nq * n_pad * k_pad;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int q = (int)(e / ((size_t)n_pad * k_pad));
+        const size_t r = e - (size_t)q * n_pad * k_pad;
+        const int n = (int)(r / k_pad), k = (int)(r - (size_t)n * k_pad);
+        float v = 0.0f;
+        if (mode == kConv3 && !back) {
+            if (n < co && k < 9 * ci) v = w[((size_t)(k / ci) * ci + k % ci) * co + n];
+        } else if (mode == kConv3) {
+            if (n < ci && k < 9 * co) {
+                const int tap = 8 - k / co, o = k % co;
+                v = w[((size_t)tap * ci + n) * co + o];
+            }
+        } else if (mode == kPoint && !back) {
+            if (n < co && k < ci) v = w[(size_t)k * co + n];
+        } else if (mode == kPoint) {
+            if (n < ci && k < co) v = w[(size_t)n * co + k];
+        } else if (!back) {  // up forward, parity q
+            if (n < co && k < ci) v = w[((size_t)q * ci + k) * co + n];
+        } else {  // up backward data
+            if (n < ci && k < 4 * co) {
+                const int qq = k / co, o = k % co;
+                v = w[((size_t)qq * ci + n) * co + o];
+            }
+        }
+        out[e] = f2bf(v);
+    }
+}
+
+hipError_t launch_pack(const float* w, int mode, int back, int ci, int co, int n_pad, int k_pad, uint16_t* out,
+                       hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pack, dim3(1024), dim3(256), 0, s, w, mode, back, ci, co, n_pad, k_pad, out);
+    return hipGetLastError();
+}
+
+// packed [q][n_pad][k_pad] fp32 weight gradient -> oracle layout gradient
+__global__ void k_unpack_grad(const float* g, int mode, int ci, int co, int n_pad, int k_pad, float* out)
+{
+    const size_t total = mode == kConv3 ? (size_t)9 * ci * co : (mode == kUp ? (size_t)4 * ci * co : (size_t)ci * co);
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+        const int o = (int)(e % co);
+        const size_t t = e / co;
+        const int i = (int)(t % ci), tap = (int)(t / ci);
+        size_t src;
+        if (mode == kConv3)
+            src = (size_t)o * k_pad + (size_t)tap * ci + i;
+        else if (mode == kPoint)
+            src = (size_t)o * k_pad + i;
+        else  // gradient of the up weights laid out [n][4 k_pad] (the 4 parities side by side)
+            src = (size_t)o * 4 * k_pad + (size_t)tap * k_pad + i;
+        out[e] = g[src];
+    }
+}
+
+hipError_t launch_unpack_grad(const float* g, int mode, int ci, int co, int n_pad, int k_pad, float* out,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL(k_unpack_grad, dim3(1024), dim3(256), 0, s, g, mode, ci, co, n_pad, k_pad, out);
+    return hipGetLastError();
+}
+
+// Adam (Kingma & Ba, Algorithm 1) on the fp32 masters
+__global__ void k_adam(float* p, const float* g, float* m, float* v, size_t n, float lr, float b1, float b2, float eps,
+                       float c1, float c2)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, size_t n, float lr, float b1, float b2, float eps,
+                       int step, hipStream_t s)
+{
+    const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)std::min<size_t>((n + 255) / 256, 4096)), dim3(256), 0, s, p, g, m, v, n,
+                       lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+// mean squared error and its gradient (fp32 NHWC, dense)
+__global__ __launch_bounds__(256) void k_mse(const float* y, const float* t, size_t n, float* dy, double* part)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    const float sc = 2.0f / (float)n;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const float d = y[i] - t[i];
+        s += (double)d * d;
+        if (dy) dy[i] = sc * d;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_sum_parts(const double* part, int n, double scale, float* out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += part[i];
+        out[0] = (float)(s * scale);
+    }
+}
+
+hipError_t launch_mse(const float* y, const float* t, size_t n, float* dy, double* part, int nblocks, float* loss,
+                      hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mse, dim3((unsigned)nblocks), dim3(256), 0, s, y, t, n, dy, part);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, part, nblocks, 1.0 / (double)n, loss);
+    return hipGetLastError();
+}
+
+}  // namespace eptv

@@ -27,7 +27,9 @@ SYMBOLS = ["eptv_plan_create", "eptv_plan_destroy", "eptv_plan_nnz", "eptv_works
            "eptv_project_stored", "eptv_backproject_stored", "eptv_backproject_interp",
            "eptv_tv_gradient_vjp", "eptv_batch_create", "eptv_batch_destroy", "eptv_batch_size", "eptv_batch_plan",
            "eptv_batch_workspace_bytes", "eptv_batch_set_launch", "eptv_batch_get_launch", "eptv_batch_tune",
-           "eptv_batch_reconstruct"]
+           "eptv_batch_reconstruct", "eptv_unet_create", "eptv_unet_destroy", "eptv_unet_param_count",
+           "eptv_unet_set_params", "eptv_unet_get_params", "eptv_unet_get_grads", "eptv_unet_forward",
+           "eptv_unet_backward", "eptv_unet_adam", "eptv_unet_mse"]
 
 
 class EptvError(RuntimeError):
@@ -118,6 +120,16 @@ def _lib() -> C.CDLL:
         L.eptv_batch_tune.argtypes = [vp, C.c_int, vp, C.POINTER(C.c_float), C.POINTER(C.c_float)]
         L.eptv_batch_reconstruct.argtypes = [vp, C.POINTER(_Params), C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp,
                                              sz, C.POINTER(_Stats), vp]
+        L.eptv_unet_create.argtypes = [C.c_int] * 7 + [C.POINTER(vp)]
+        L.eptv_unet_destroy.argtypes = [vp]
+        L.eptv_unet_param_count.argtypes = [vp, C.POINTER(C.c_longlong)]
+        L.eptv_unet_set_params.argtypes = [vp, vp, vp]
+        L.eptv_unet_get_params.argtypes = [vp, vp, vp]
+        L.eptv_unet_get_grads.argtypes = [vp, vp, vp]
+        L.eptv_unet_forward.argtypes = [vp, vp, C.c_int, vp, vp]
+        L.eptv_unet_backward.argtypes = [vp, vp, vp, vp]
+        L.eptv_unet_adam.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int, vp]
+        L.eptv_unet_mse.argtypes = [vp, vp, vp, sz, vp, vp, vp]
         L.eptv_tv_gradient_vjp.argtypes = [vp, vp, vp, C.c_float, C.c_float, C.c_float, vp, vp, sz, vp]
         L.eptv_select_sigma.argtypes = [vp, vp, C.c_double, C.c_float, C.c_float, vp, vp, sz, vp]
         L.eptv_tv_step.argtypes = [vp, C.POINTER(_Params), vp, vp, C.c_float, C.c_int, vp, sz, C.POINTER(_Stats), vp]
@@ -506,3 +518,86 @@ class Batch:
                 out.append(d)
             recs = out
         return fs, recs
+
+
+class UNet:
+    """The edge-weight / warm-start network (``eptv_unet``): bf16 MFMA layers,
+    fp32 masters, Adam.  Tensors are float32 NHWC on the GPU."""
+
+    def __init__(self, c_in: int, c_out: int, base: int, levels: int, max_batch: int, height: int, width: int):
+        if not torch.cuda.is_available():
+            raise RuntimeError("libeptv needs a ROCm GPU; none is visible")
+        self.c_in, self.c_out, self.base, self.levels = c_in, c_out, base, levels
+        self.max_batch, self.h, self.w = max_batch, height, width
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        h = C.c_void_p()
+        _check(_lib().eptv_unet_create(c_in, c_out, base, levels, max_batch, height, width, C.byref(h)),
+               "eptv_unet_create")
+        self._h = h
+        n = C.c_longlong()
+        _check(_lib().eptv_unet_param_count(self._h, C.byref(n)), "eptv_unet_param_count")
+        self.n_params = int(n.value)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _L is not None:
+            _L.eptv_unet_destroy(h)
+        self._h = None
+
+    def set_params(self, flat, stream=None) -> None:
+        import numpy as np
+        a = np.ascontiguousarray(np.asarray(flat, dtype=np.float32).reshape(-1))
+        if a.size != self.n_params:
+            raise ValueError(f"expected {self.n_params} parameters, got {a.size}")
+        _check(_lib().eptv_unet_set_params(self._h, a.ctypes.data, _stream(stream)), "eptv_unet_set_params")
+
+    def params(self, stream=None):
+        import numpy as np
+        a = np.zeros(self.n_params, np.float32)
+        _check(_lib().eptv_unet_get_params(self._h, a.ctypes.data, _stream(stream)), "eptv_unet_get_params")
+        return a
+
+    def grads(self, stream=None):
+        import numpy as np
+        a = np.zeros(self.n_params, np.float32)
+        _check(_lib().eptv_unet_get_grads(self._h, a.ctypes.data, _stream(stream)), "eptv_unet_get_grads")
+        return a
+
+    def _act(self, t: torch.Tensor, c: int, name: str) -> torch.Tensor:
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or t.device != self.device:
+            raise TypeError(f"{name} must be a float32 tensor on {self.device}")
+        if t.dim() != 4 or tuple(t.shape[1:]) != (self.h, self.w, c) or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous [n][{self.h}][{self.w}][{c}], got {tuple(t.shape)}")
+        if not 1 <= t.shape[0] <= self.max_batch:
+            raise ValueError(f"{name}: batch {t.shape[0]} outside 1..{self.max_batch}")
+        return t
+
+    def forward(self, x: torch.Tensor, stream=None) -> torch.Tensor:
+        x = self._act(x, self.c_in, "x")
+        y = torch.empty((x.shape[0], self.h, self.w, self.c_out), dtype=torch.float32, device=self.device)
+        _check(_lib().eptv_unet_forward(self._h, x.data_ptr(), x.shape[0], y.data_ptr(), _stream(stream)),
+               "eptv_unet_forward")
+        return y
+
+    def backward(self, dy: torch.Tensor, want_dx: bool = False, stream=None):
+        dy = self._act(dy, self.c_out, "dy")
+        dx = torch.empty((dy.shape[0], self.h, self.w, self.c_in), dtype=torch.float32,
+                         device=self.device) if want_dx else None
+        _check(_lib().eptv_unet_backward(self._h, dy.data_ptr(), dx.data_ptr() if dx is not None else None,
+                                         _stream(stream)), "eptv_unet_backward")
+        return dx
+
+    def adam(self, lr: float, step: int, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8,
+             stream=None) -> None:
+        _check(_lib().eptv_unet_adam(self._h, lr, beta1, beta2, eps, step, _stream(stream)), "eptv_unet_adam")
+
+    def mse(self, y: torch.Tensor, target: torch.Tensor, want_grad: bool = True, stream=None):
+        """(loss as a 1-element device tensor, dy or None)."""
+        if y.shape != target.shape or not y.is_contiguous() or not target.is_contiguous():
+            raise ValueError("y and target must be contiguous and of one shape")
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        dy = torch.empty_like(y) if want_grad else None
+        _check(_lib().eptv_unet_mse(self._h, y.data_ptr(), target.data_ptr(), y.numel(),
+                                    dy.data_ptr() if dy is not None else None, loss.data_ptr(), _stream(stream)),
+               "eptv_unet_mse")
+        return loss, dy

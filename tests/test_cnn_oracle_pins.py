@@ -120,3 +120,24 @@ def test_mse_gradient_finite_differences():
     assert np.isclose(loss, np.mean((y - t) ** 2))
     a = {"y": y}
     _fd_check(lambda: C.mse(a["y"], t)[0], a, [g], ["y"])
+
+
+def test_bf16_rounding_known_values():
+    """bfloat16 keeps 8 significand bits: 1 + 2^-8 is a tie (to even: 1),
+    1 + 3 * 2^-8 rounds up to 1 + 2^-6, and exactly representable values stay."""
+    vals = np.array([1.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -2.5, 3.0 * 2.0 ** -130, 1.0 + 2.0 ** -7])
+    want = np.array([1.0, 1.0, 1.0 + 2.0 ** -6, -2.5, 3.0 * 2.0 ** -130, 1.0 + 2.0 ** -7])
+    np.testing.assert_array_equal(C.bf16(vals), want)
+
+
+def test_unet_store_identity_is_the_exact_network():
+    """With the default store the passes are the exact ones pinned above; with
+    bf16 storage they stay within bf16 resolution on the forward output."""
+    rng = np.random.default_rng(9)
+    p = C.unet_init(C.unet_shapes(1, 2, 4, 2), seed=10)
+    x = rng.normal(size=(1, 8, 8, 1))
+    y, _ = C.unet_forward(p, x)
+    y2, _ = C.unet_forward(p, x, store=lambda a: a)
+    np.testing.assert_array_equal(y, y2)
+    yb, _ = C.unet_forward(p, x, store=C.bf16)
+    assert np.linalg.norm(yb - y) <= 2e-2 * np.linalg.norm(y)
