@@ -474,11 +474,22 @@ double orc_select_sigma(int nx, int ny, const double* f, double eps, double q, d
  * g of Eq. 9, step by Armijo backtracking t = t0 shrink^k until
  * Q(f - t g) <= Q(f) - c t ||g||^2, the weights recomputed at every step
  * (EPTV algorithm, step 2) and held fixed inside the line search. */
+/* The same descent with given half-edge weights in place of Eq. 5's
+ * w = exp(-TV^2 / sigma^2) (NULL: the adaptive weights). */
+static int tv_step_with(int nx, int ny, const orc_params* p, double* f, const double* v, double sigma, int n_steps,
+                        int* k_out, double* margin_out, double* sigma_out, const double* wx_in, const double* wy_in);
+
 int orc_tv_step(int nx, int ny, const orc_params* p, double* f, const double* v,
                 double sigma, int n_steps, int* k_out, double* margin_out, double* sigma_out)
 {
+    return tv_step_with(nx, ny, p, f, v, sigma, n_steps, k_out, margin_out, sigma_out, NULL, NULL);
+}
+
+static int tv_step_with(int nx, int ny, const orc_params* p, double* f, const double* v, double sigma, int n_steps,
+                        int* k_out, double* margin_out, double* sigma_out, const double* wx_in, const double* wy_in)
+{
     size_t np = (size_t)nx * ny, ex = n_xedges(nx, ny), ey = n_yedges(nx, ny);
-    if (sigma < 0) sigma = orc_select_sigma(nx, ny, f, p->tv_eps, p->edge_quantile, p->sigma_floor);
+    if (sigma < 0 && !wx_in) sigma = orc_select_sigma(nx, ny, f, p->tv_eps, p->edge_quantile, p->sigma_floor);
     if (sigma_out) *sigma_out = sigma;
     double* tvx = (double*)malloc(sizeof(double) * ex);
     double* tvy = (double*)malloc(sizeof(double) * ey);
@@ -490,8 +501,13 @@ int orc_tv_step(int nx, int ny, const orc_params* p, double* f, const double* v,
 
     for (int s = 0; s < n_steps; ++s) {
         orc_tv_edges(nx, ny, f, p->tv_eps, tvx, tvy);
-        weights(ex, tvx, sigma, wx);
-        weights(ey, tvy, sigma, wy);
+        if (wx_in) {
+            memcpy(wx, wx_in, sizeof(double) * ex);
+            memcpy(wy, wy_in, sizeof(double) * ey);
+        } else {
+            weights(ex, tvx, sigma, wx);
+            weights(ey, tvy, sigma, wy);
+        }
         gradient_with(nx, ny, f, v, p->lambda, tvx, tvy, wx, wy, g);
         double q0 = orc_surrogate(nx, ny, f, v, p->lambda, wx, wy, p->tv_eps);
         double gg = 0.0;
@@ -593,9 +609,18 @@ int orc_cgls(const orc_matrix* m, const double* y, double* u, int iters, double*
  *      place, as the paper's on-the-fly code does (Sec. 2.3);
  *   2. P2 by gradient descent from v (or f^(k)), sigma chosen once from the
  *      P2 start image, weights updated at every descent step;
- *   3. negative pixels set to zero. */
+ *   3. negative pixels set to zero.
+ * With given half-edge weights, the first frozen_iters iterations use them in
+ * P2 in place of Eq. 5 (no sigma is chosen there). */
 int orc_reconstruct(const orc_matrix* m, const orc_params* p, const double* y, double* f,
                     const double* f_ref, orc_stats* st)
+{
+    return orc_reconstruct_weighted(m, p, y, f, f_ref, st, NULL, NULL, 0);
+}
+
+int orc_reconstruct_weighted(const orc_matrix* m, const orc_params* p, const double* y, double* f,
+                             const double* f_ref, orc_stats* st, const double* wx_in, const double* wy_in,
+                             int frozen_iters)
 {
     if (!m || !p || !y || !f || p->outer_iters < 0 || p->tv_iters < 0 || p->cgls_iters < 0) return 1;
     const int nx = m->nx, ny = m->ny, T = p->tv_iters;
@@ -622,10 +647,15 @@ int orc_reconstruct(const orc_matrix* m, const orc_params* p, const double* y, d
         }
         /* step 2 */
         memcpy(w, p->p2_start ? f : v, sizeof(double) * nc);
+        const int frozen = wx_in && wy_in && k < frozen_iters;
         double sigma = p->sigma_fixed;
-        if (sigma < 0) sigma = orc_select_sigma(nx, ny, w, p->tv_eps, p->edge_quantile, p->sigma_floor);
-        orc_tv_step(nx, ny, p, w, v, sigma, T, st && st->armijo_k ? st->armijo_k + (size_t)k * T : NULL,
-                    st && st->armijo_margin ? st->armijo_margin + (size_t)k * T : NULL, NULL);
+        if (frozen)
+            sigma = 0.0; /* recorded as 0: the given weights replace Eq. 5 */
+        else if (sigma < 0)
+            sigma = orc_select_sigma(nx, ny, w, p->tv_eps, p->edge_quantile, p->sigma_floor);
+        tv_step_with(nx, ny, p, w, v, sigma, T, st && st->armijo_k ? st->armijo_k + (size_t)k * T : NULL,
+                     st && st->armijo_margin ? st->armijo_margin + (size_t)k * T : NULL, NULL,
+                     frozen ? wx_in : NULL, frozen ? wy_in : NULL);
         /* step 3 */
         if (p->positivity)
             for (size_t i = 0; i < nc; ++i)

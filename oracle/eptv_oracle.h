@@ -119,6 +119,11 @@ int orc_tv_step(int nx, int ny, const orc_params* p, double* f, const double* v,
 /* The outer EPTV loop. f is the warm start unless zero_init. */
 int orc_reconstruct(const orc_matrix* m, const orc_params* p, const double* y, double* f,
                     const double* f_ref, orc_stats* st);
+/* The same, with the half-edge weights wx_in [ny][nx+1], wy_in [ny+1][nx]
+ * used in place of Eq. 5's weights during the first frozen_iters iterations. */
+int orc_reconstruct_weighted(const orc_matrix* m, const orc_params* p, const double* y, double* f,
+                             const double* f_ref, orc_stats* st, const double* wx_in, const double* wy_in,
+                             int frozen_iters);
 
 int orc_num_threads(void);
 

@@ -564,3 +564,49 @@ def test_generator_poisson_statistics():
     n = counts.size
     assert abs(counts.mean() - lam) < 4 * math.sqrt(lam / n)
     assert abs(counts.var() / lam - 1) < 4 * math.sqrt(2.0 / n)
+
+
+# ------------------------------------------------------------------ given (frozen) edge weights
+
+def _pin_case(oracle):
+    g = geom(14, 12, 10, 40)
+    M = oracle.Matrix(g)
+    rng = np.random.default_rng(41)
+    f_true = np.zeros((g.ny, g.nx))
+    f_true[3:9, 4:10] = 0.02
+    y = M.project(f_true) + 1e-4 * rng.normal(size=(g.n_views, g.n_bins))
+    return g, M, y
+
+
+def test_frozen_unit_weights_are_plain_tv(oracle):
+    """w = 1 on every half-edge is Eq. 5 with sigma = inf: plain TV."""
+    g, M, y = _pin_case(oracle)
+    ones = (np.ones((g.ny, g.nx + 1)), np.ones((g.ny + 1, g.nx)))
+    K = 4
+    fw, sw = M.reconstruct(y, oracle.Params(outer_iters=K, lam=200.0), weights=ones, frozen_iters=K)
+    ft, st = M.reconstruct(y, oracle.Params(outer_iters=K, lam=200.0, sigma_fixed=float("inf")))
+    np.testing.assert_array_equal(fw, ft)
+    np.testing.assert_array_equal(sw["armijo_k"], st["armijo_k"])
+
+
+def test_frozen_zero_weights_remove_p2(oracle):
+    """w = 0: the direction is lambda (f - v), zero at the start v, so P2 keeps v
+    and the iteration is the one without P2."""
+    g, M, y = _pin_case(oracle)
+    zeros = (np.zeros((g.ny, g.nx + 1)), np.zeros((g.ny + 1, g.nx)))
+    fw, _ = M.reconstruct(y, oracle.Params(outer_iters=3, lam=200.0), weights=zeros, frozen_iters=3)
+    fn, _ = M.reconstruct(y, oracle.Params(outer_iters=3, lam=200.0, tv_iters=0))
+    np.testing.assert_allclose(fw, fn, rtol=0, atol=1e-15)
+
+
+def test_frozen_then_adaptive(oracle):
+    """After the frozen iterations the weights are Eq. 5's again: a run frozen
+    for 2 of 5 iterations equals 2 frozen iterations then 3 adaptive ones."""
+    g, M, y = _pin_case(oracle)
+    rng = np.random.default_rng(42)
+    w = (rng.uniform(size=(g.ny, g.nx + 1)), rng.uniform(size=(g.ny + 1, g.nx)))
+    f5, s5 = M.reconstruct(y, oracle.Params(outer_iters=5, lam=200.0), weights=w, frozen_iters=2)
+    f2, s2 = M.reconstruct(y, oracle.Params(outer_iters=2, lam=200.0), weights=w, frozen_iters=2)
+    f3, s3 = M.reconstruct(y, oracle.Params(outer_iters=3, lam=200.0, zero_init=0), f0=f2)
+    np.testing.assert_array_equal(f5, f3)
+    assert np.all(s5["sigma"][:2] == 0.0) and np.all(s5["sigma"][2:] > 0.0)
