@@ -224,6 +224,16 @@ int eptv_tv_step(eptv_plan plan, const eptv_params* params, float* f, const floa
 int eptv_reconstruct(eptv_plan plan, const eptv_params* params, const float* y, float* f,
                      const float* f_ref, void* ws, size_t ws_bytes, eptv_stats* stats, void* stream);
 
+/* eptv_reconstruct with given half-edge weights: during the first
+ * frozen_iters outer iterations P2 uses wx [ny][nx+1] / wy [ny+1][nx]
+ * (device, the layout of eptv_tv_gradient's weights) in place of Eq. 5's
+ * w = exp(-TV^2/sigma^2), and no sigma is chosen (recorded as -1); later
+ * iterations are the adaptive ones.  For starting the iteration from proposed
+ * weights (e.g. a network's). */
+int eptv_reconstruct_weighted(eptv_plan plan, const eptv_params* params, const float* y, float* f,
+                              const float* f_ref, const float* wx, const float* wy, int frozen_iters, void* ws,
+                              size_t ws_bytes, eptv_stats* stats, void* stream);
+
 /* ------------------------------------------------------------------ batches
  * Many slices, each with its own geometry (image size, views, bins), iterated
  * together: every phase of the EPTV iteration (Sec. 2.2) is one launch for

@@ -650,7 +650,7 @@ int orc_reconstruct_weighted(const orc_matrix* m, const orc_params* p, const dou
         const int frozen = wx_in && wy_in && k < frozen_iters;
         double sigma = p->sigma_fixed;
         if (frozen)
-            sigma = 0.0; /* recorded as 0: the given weights replace Eq. 5 */
+            sigma = -1.0; /* recorded as -1: no sigma, the given weights replace Eq. 5 */
         else if (sigma < 0)
             sigma = orc_select_sigma(nx, ny, w, p->tv_eps, p->edge_quantile, p->sigma_floor);
         tv_step_with(nx, ny, p, w, v, sigma, T, st && st->armijo_k ? st->armijo_k + (size_t)k * T : NULL,

@@ -125,6 +125,9 @@ struct Plan {
     // cached graph of one outer iteration
     hipGraphExec_t gexec = nullptr;
     std::vector<uint64_t> gkey;
+    // and of an iteration with given (frozen) edge weights
+    hipGraphExec_t gexec_w = nullptr;
+    std::vector<uint64_t> gkey_w;
 };
 
 // ---------------------------------------------------------------- workspace
@@ -212,10 +215,10 @@ hipError_t launch_sigma_out(const DevState* st, float* out, hipStream_t s);
 // candidates, the decision, the final update
 hipError_t launch_tv_vjp(const Plan& p, const float* f, const float* u, float lambda, float sigma, float eps2,
                          float* e3, float* out, hipStream_t s);
-hipError_t launch_tv_grad(const Plan& p, const float* f, const float* g_prev, const DevState* st_prev,
-                          float* f_out, const float* v, float lambda, const DevState* st,
-                          float sigma_direct, float eps2, float* g, float* wx, float* wy, double* part,
-                          hipStream_t s);
+hipError_t launch_tv_grad(const Plan& p, const float* f, const float* g_prev, const DevState* st_prev, float* f_out,
+                          const float* v, float lambda, const DevState* st, float sigma_direct, float eps2, float* g,
+                          float* wx, float* wy, double* part, hipStream_t s, const float* wx_in = nullptr,
+                          const float* wy_in = nullptr);
 hipError_t launch_armijo(const Plan& p, const float* f, const float* g, const float* v, const float* wx,
                          const float* wy, float lambda, float eps2, float t0, float shrink, double* part,
                          hipStream_t s);

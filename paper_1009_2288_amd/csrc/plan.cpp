@@ -170,6 +170,8 @@ struct Ctx {
     const float* y;
     float* f;
     const float* f_ref;
+    const float* wx_in = nullptr;  // given half-edge weights for P2 (frozen iterations), or null
+    const float* wy_in = nullptr;
 };
 
 float t0_of(const eptv_params& q)
@@ -201,7 +203,8 @@ float sigma_init(const eptv_params& q) { return q.sigma_fixed < 0 ? -1.0f : (flo
 // its gradient kernel, so only the last step has an update kernel of its own.
 
 static hipError_t enqueue_p2(const Plan& p, Workspace& W, const eptv_params& q, const float* start, const float* v,
-                             int n_steps, float* fout, float* foutT, int clamp, int32_t* st_k, hipStream_t s)
+                             int n_steps, float* fout, float* foutT, int clamp, int32_t* st_k, hipStream_t s,
+                             const float* wx_in = nullptr, const float* wy_in = nullptr)
 {
     hipError_t e;
     const float eps2 = (float)(q.tv_eps * q.tv_eps);
@@ -214,7 +217,7 @@ static hipError_t enqueue_p2(const Plan& p, Workspace& W, const eptv_params& q, 
         const float* gprev = t > 0 ? gbuf[(t - 1) & 1] : nullptr;
         float* fnext = t > 0 ? fbuf[t & 1] : nullptr;
         if ((e = launch_tv_grad(p, fcur, gprev, W.st, fnext, v, (float)q.lambda, W.st, 0.0f, eps2, g, W.wx, W.wy,
-                                W.part_grad, s)) != hipSuccess)
+                                W.part_grad, s, wx_in, wy_in)) != hipSuccess)
             return e;
         if (t > 0) fcur = fnext;
         if ((e = launch_armijo(p, fcur, g, v, W.wx, W.wy, (float)q.lambda, eps2, t0, shrink, W.part_arm, s)) !=
@@ -274,12 +277,13 @@ static hipError_t enqueue_iteration(const Ctx& c, hipStream_t s)
     }
     // Step 2: P2 from v (or f^(k)), sigma chosen once from the start image.
     const float* start = q.p2_start ? c.f : W.u;
-    if (adaptive && T > 0) {
+    if (adaptive && T > 0 && !c.wx_in) {
         if ((e = enqueue_select(p, W, start, (float)(q.tv_eps * q.tv_eps), (float)q.sigma_floor, s)) != hipSuccess)
             return e;
     }
     // Step 3 (positivity) is fused into the last descent update.
-    if ((e = enqueue_p2(p, W, q, start, W.u, T, c.f, W.fT, q.positivity, W.st_k, s)) != hipSuccess) return e;
+    if ((e = enqueue_p2(p, W, q, start, W.u, T, c.f, W.fT, q.positivity, W.st_k, s, c.wx_in, c.wy_in)) != hipSuccess)
+        return e;
     if (c.f_ref) {
         if ((e = launch_rmse_part(p, c.f, c.f_ref, W.part_rmse, s)) != hipSuccess) return e;
     }
@@ -385,6 +389,7 @@ int eptv_plan_destroy(eptv_plan h)
     if (!h) return EPTV_ERR_ARG;
     Plan& p = h->p;
     if (p.gexec) hipGraphExecDestroy(p.gexec);
+    if (p.gexec_w) hipGraphExecDestroy(p.gexec_w);
     if (p.cap_stream) hipStreamDestroy(p.cap_stream);
     if (p.rays.d_ray) hipFree(p.rays.d_ray);
     if (p.mat.d_rowptr) hipFree(p.mat.d_rowptr);
@@ -613,8 +618,9 @@ int eptv_tv_step(eptv_plan h, const eptv_params* q, float* f, const float* v, fl
     return EPTV_OK;
 }
 
-int eptv_reconstruct(eptv_plan h, const eptv_params* q, const float* y, float* f, const float* f_ref, void* ws,
-                     size_t ws_bytes, eptv_stats* stats, void* stream)
+static int reconstruct_impl(eptv_plan h, const eptv_params* q, const float* y, float* f, const float* f_ref,
+                            const float* wx_in, const float* wy_in, int frozen, void* ws, size_t ws_bytes,
+                            eptv_stats* stats, void* stream)
 {
     if (!h || !y || !f) return EPTV_ERR_ARG;
     int rc = check_params(q);
@@ -626,57 +632,67 @@ int eptv_reconstruct(eptv_plan h, const eptv_params* q, const float* y, float* f
     if (rc != EPTV_OK) return rc;
     hipStream_t s = (hipStream_t)stream;
     const int K = q->outer_iters, T = q->tv_iters;
+    frozen = std::min(std::max(frozen, 0), K);
 
     EPTV_HIP(launch_state_init(W.st, W.hist, select_rank(p, q->edge_quantile), sigma_init(*q), 1, s));
     if (q->zero_init) EPTV_HIP(launch_fill(f, (size_t)p.nx * p.ny, 0.0f, s));
     EPTV_HIP(launch_transpose(f, W.fT, p.nx, p.ny, s));
 
     Ctx c{p, W, *q, y, f, f_ref};
-    if (K > 0) {
+    Ctx cw{p, W, *q, y, f, f_ref, wx_in, wy_in};
+    // one captured graph per kind of iteration (adaptive, or with the given weights)
+    auto run = [&](const Ctx& cc, int count, hipGraphExec_t& gexec, std::vector<uint64_t>& gkey) -> int {
+        if (count <= 0) return EPTV_OK;
         if (no_graph()) {
-            for (int k = 0; k < K; ++k) EPTV_HIP(enqueue_iteration(c, s));
-        } else {
-            std::lock_guard<std::mutex> lock(h->graph_mu);
-            std::vector<uint64_t> key;
-            auto put = [&](const void* ptr, size_t n) {
-                const unsigned char* b = (const unsigned char*)ptr;
-                for (size_t i = 0; i < n; i += 8) {
-                    uint64_t word = 0;
-                    std::memcpy(&word, b + i, std::min<size_t>(8, n - i));
-                    key.push_back(word);
-                }
-            };
-            eptv_params qk = *q;
-            qk.outer_iters = 0;
-            qk.zero_init = 0;
-            put(&qk, sizeof qk);
-            const void* ptrs[5] = {ws, y, f, f_ref, (const void*)(uintptr_t)ws_bytes};
-            put(ptrs, sizeof ptrs);
-            if (!p.gexec || key != p.gkey) {
-                if (p.gexec) {
-                    hipGraphExecDestroy(p.gexec);
-                    p.gexec = nullptr;
-                }
-                hipGraph_t graph = nullptr;
-                EPTV_HIP(hipStreamBeginCapture(p.cap_stream, hipStreamCaptureModeThreadLocal));
-                hipError_t e = enqueue_iteration(c, p.cap_stream);
-                hipError_t e2 = hipStreamEndCapture(p.cap_stream, &graph);
-                if (e != hipSuccess) {
-                    if (graph) hipGraphDestroy(graph);
-                    return hip_fail(e, "enqueue_iteration (capture)");
-                }
-                if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
-                e = hipGraphInstantiate(&p.gexec, graph, nullptr, nullptr, 0);
-                hipGraphDestroy(graph);
-                if (e != hipSuccess) {
-                    p.gexec = nullptr;
-                    return hip_fail(e, "hipGraphInstantiate");
-                }
-                p.gkey = key;
-            }
-            for (int k = 0; k < K; ++k) EPTV_HIP(hipGraphLaunch(p.gexec, s));
+            for (int k = 0; k < count; ++k) EPTV_HIP(enqueue_iteration(cc, s));
+            return EPTV_OK;
         }
+        std::vector<uint64_t> key;
+        auto put = [&](const void* ptr, size_t n) {
+            const unsigned char* b = (const unsigned char*)ptr;
+            for (size_t i = 0; i < n; i += 8) {
+                uint64_t word = 0;
+                std::memcpy(&word, b + i, std::min<size_t>(8, n - i));
+                key.push_back(word);
+            }
+        };
+        eptv_params qk = *q;
+        qk.outer_iters = 0;
+        qk.zero_init = 0;
+        put(&qk, sizeof qk);
+        const void* ptrs[7] = {ws, y, f, f_ref, (const void*)(uintptr_t)ws_bytes, cc.wx_in, cc.wy_in};
+        put(ptrs, sizeof ptrs);
+        if (!gexec || key != gkey) {
+            if (gexec) {
+                hipGraphExecDestroy(gexec);
+                gexec = nullptr;
+            }
+            hipGraph_t graph = nullptr;
+            EPTV_HIP(hipStreamBeginCapture(p.cap_stream, hipStreamCaptureModeThreadLocal));
+            hipError_t e = enqueue_iteration(cc, p.cap_stream);
+            hipError_t e2 = hipStreamEndCapture(p.cap_stream, &graph);
+            if (e != hipSuccess) {
+                if (graph) hipGraphDestroy(graph);
+                return hip_fail(e, "enqueue_iteration (capture)");
+            }
+            if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+            e = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                gexec = nullptr;
+                return hip_fail(e, "hipGraphInstantiate");
+            }
+            gkey = key;
+        }
+        for (int k = 0; k < count; ++k) EPTV_HIP(hipGraphLaunch(gexec, s));
+        return EPTV_OK;
+    };
+    {
+        std::lock_guard<std::mutex> lock(h->graph_mu);
+        rc = run(cw, wx_in ? frozen : 0, p.gexec_w, p.gkey_w);
+        if (rc == EPTV_OK) rc = run(c, K - (wx_in ? frozen : 0), p.gexec, p.gkey);
     }
+    if (rc != EPTV_OK) return rc;
     if (stats) {
         const size_t kk = (size_t)K;
         if (kk) {
@@ -692,6 +708,20 @@ int eptv_reconstruct(eptv_plan h, const eptv_params* q, const float* y, float* f
         EPTV_HIP(hipStreamSynchronize(s));
     }
     return EPTV_OK;
+}
+
+int eptv_reconstruct(eptv_plan h, const eptv_params* q, const float* y, float* f, const float* f_ref, void* ws,
+                     size_t ws_bytes, eptv_stats* stats, void* stream)
+{
+    return reconstruct_impl(h, q, y, f, f_ref, nullptr, nullptr, 0, ws, ws_bytes, stats, stream);
+}
+
+int eptv_reconstruct_weighted(eptv_plan h, const eptv_params* q, const float* y, float* f, const float* f_ref,
+                              const float* wx, const float* wy, int frozen_iters, void* ws, size_t ws_bytes,
+                              eptv_stats* stats, void* stream)
+{
+    if (!wx || !wy || frozen_iters < 0) return EPTV_ERR_ARG;
+    return reconstruct_impl(h, q, y, f, f_ref, wx, wy, frozen_iters, ws, ws_bytes, stats, stream);
 }
 
 }  // extern "C"

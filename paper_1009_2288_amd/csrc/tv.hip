@@ -270,7 +270,8 @@ __device__ __forceinline__ void tv_grad_block(const float* __restrict__ f, const
                                               const float* __restrict__ v, int nx, int ny, float lambda,
                                               const DevState* st, float inv_s2_direct, float eps2,
                                               float* __restrict__ g, float* wx, float* wy, double* part, int bx,
-                                              int by, int b, int nb, double* lds)
+                                              int by, int b, int nb, double* lds, const float* wx_in = nullptr,
+                                              const float* wy_in = nullptr)
 {
     const float inv_s2 = st ? st->inv_sigma2 : inv_s2_direct;
     const int i = bx * kT + (threadIdx.x & (kT - 1)), j = by * kT + threadIdx.x / kT;
@@ -292,8 +293,12 @@ __device__ __forceinline__ void tv_grad_block(const float* __restrict__ f, const
         }
         const float c = N.n[1][1];
         const float tR = tv_right(N, eps2), tL = tv_left(N, eps2), tU = tv_up(N, eps2), tD = tv_down(N, eps2);
-        const float wR = weight(tR, inv_s2), wL = weight(tL, inv_s2), wU = weight(tU, inv_s2),
-                    wD = weight(tD, inv_s2);
+        // Eq. 5's weights, or the caller's (given half-edge weights in place of Eq. 5)
+        const size_t xw = (size_t)j * (nx + 1);
+        const float wR = wx_in ? wx_in[xw + i + 1] : weight(tR, inv_s2);
+        const float wL = wx_in ? wx_in[xw + i] : weight(tL, inv_s2);
+        const float wU = wy_in ? wy_in[(size_t)(j + 1) * nx + i] : weight(tU, inv_s2);
+        const float wD = wy_in ? wy_in[(size_t)j * nx + i] : weight(tD, inv_s2);
         const float FR = wR * (N.n[2][1] - c) / tR;
         const float FL = wL * (c - N.n[0][1]) / tL;
         const float FU = wU * (N.n[1][2] - c) / tU;
@@ -331,22 +336,25 @@ __global__ __launch_bounds__(256) void k_tv_grad(const float* __restrict__ f, co
                                                  const DevState* st_prev, float* __restrict__ f_out,
                                                  const float* __restrict__ v, int nx, int ny, float lambda,
                                                  const DevState* st, float inv_s2_direct, float eps2,
-                                                 float* __restrict__ g, float* wx, float* wy, double* part)
+                                                 float* __restrict__ g, float* wx, float* wy, double* part,
+                                                 const float* wx_in, const float* wy_in)
 {
     __shared__ double lds[4];
     tv_grad_block(f, g_prev, st_prev, f_out, v, nx, ny, lambda, st, inv_s2_direct, eps2, g, wx, wy, part,
-                  blockIdx.x, blockIdx.y, blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y, lds);
+                  blockIdx.x, blockIdx.y, blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y, lds, wx_in,
+                  wy_in);
 }
 
 hipError_t launch_tv_grad(const Plan& p, const float* f, const float* g_prev, const DevState* st_prev, float* f_out,
                           const float* v, float lambda, const DevState* st, float sigma_direct, float eps2, float* g,
-                          float* wx, float* wy, double* part, hipStream_t s)
+                          float* wx, float* wy, double* part, hipStream_t s, const float* wx_in,
+                          const float* wy_in)
 {
     const float inv_s2 = (sigma_direct > 0.0f && std::isfinite(sigma_direct)) ? 1.0f / (sigma_direct * sigma_direct)
                                                                              : 0.0f;
     dim3 grid((p.nx + kT - 1) / kT, (p.ny + kT - 1) / kT);
     hipLaunchKernelGGL(k_tv_grad, grid, dim3(256), 0, s, f, g_prev, st_prev, f_out, v, p.nx, p.ny, lambda, st, inv_s2,
-                       eps2, g, wx, wy, part);
+                       eps2, g, wx, wy, part, wx_in, wy_in);
     return hipGetLastError();
 }
 

@@ -29,7 +29,7 @@ SYMBOLS = ["eptv_plan_create", "eptv_plan_destroy", "eptv_plan_nnz", "eptv_works
            "eptv_batch_workspace_bytes", "eptv_batch_set_launch", "eptv_batch_get_launch", "eptv_batch_tune",
            "eptv_batch_reconstruct", "eptv_unet_create", "eptv_unet_destroy", "eptv_unet_param_count",
            "eptv_unet_set_params", "eptv_unet_get_params", "eptv_unet_get_grads", "eptv_unet_forward",
-           "eptv_unet_backward", "eptv_unet_adam", "eptv_unet_mse"]
+           "eptv_unet_backward", "eptv_unet_adam", "eptv_unet_mse", "eptv_reconstruct_weighted"]
 
 
 class EptvError(RuntimeError):
@@ -134,6 +134,8 @@ def _lib() -> C.CDLL:
         L.eptv_select_sigma.argtypes = [vp, vp, C.c_double, C.c_float, C.c_float, vp, vp, sz, vp]
         L.eptv_tv_step.argtypes = [vp, C.POINTER(_Params), vp, vp, C.c_float, C.c_int, vp, sz, C.POINTER(_Stats), vp]
         L.eptv_reconstruct.argtypes = [vp, C.POINTER(_Params), vp, vp, vp, vp, sz, C.POINTER(_Stats), vp]
+        L.eptv_reconstruct_weighted.argtypes = [vp, C.POINTER(_Params), vp, vp, vp, vp, vp, C.c_int, vp, sz,
+                                                C.POINTER(_Stats), vp]
         L.eptv_geometry_matrix.argtypes = [C.POINTER(_Geometry), C.POINTER(C.c_longlong), vp, vp, vp]
         L.eptv_plan_store_matrix.argtypes = [vp, C.POINTER(sz)]
         L.eptv_project_stored.argtypes = [vp, vp, vp, C.c_float, C.c_float, vp]
@@ -382,8 +384,11 @@ class Plan:
         return (ks[:n_steps].copy(), float(sg[0])) if stats else None
 
     def reconstruct(self, y: torch.Tensor, params: Params, f: Optional[torch.Tensor] = None,
-                    f_ref: Optional[torch.Tensor] = None, stats: bool = True, stream=None):
-        """Run params.outer_iters EPTV iterations; returns (f, stats dict or None)."""
+                    f_ref: Optional[torch.Tensor] = None, stats: bool = True, stream=None, weights=None,
+                    frozen_iters: int = 0):
+        """Run params.outer_iters EPTV iterations; returns (f, stats dict or None).
+        weights: optional (wx [ny][nx+1], wy [ny+1][nx]) device tensors used in
+        place of Eq. 5's weights during the first frozen_iters iterations."""
         import numpy as np
         y = self._sino(y, "y")
         if f is None:
@@ -406,9 +411,17 @@ class Plan:
                         rec["rmse"].ctypes.data_as(C.POINTER(C.c_double)))
             stp = C.byref(st)
         cp = params._c()
-        _check(_lib().eptv_reconstruct(self._h, C.byref(cp), y.data_ptr(), f.data_ptr(),
-                                       f_ref.data_ptr() if f_ref is not None else None, ws.data_ptr(), ws.numel(),
-                                       stp, _stream(stream)), "eptv_reconstruct")
+        if weights is not None:
+            wx = self._t(weights[0], (self.ny, self.nx + 1), "wx")
+            wy = self._t(weights[1], (self.ny + 1, self.nx), "wy")
+            _check(_lib().eptv_reconstruct_weighted(self._h, C.byref(cp), y.data_ptr(), f.data_ptr(),
+                                                    f_ref.data_ptr() if f_ref is not None else None, wx.data_ptr(),
+                                                    wy.data_ptr(), int(frozen_iters), ws.data_ptr(), ws.numel(),
+                                                    stp, _stream(stream)), "eptv_reconstruct_weighted")
+        else:
+            _check(_lib().eptv_reconstruct(self._h, C.byref(cp), y.data_ptr(), f.data_ptr(),
+                                           f_ref.data_ptr() if f_ref is not None else None, ws.data_ptr(),
+                                           ws.numel(), stp, _stream(stream)), "eptv_reconstruct")
         if rec is not None:
             rec = {k: v[:K].copy() for k, v in rec.items() if k != "armijo_k"} | {
                 "armijo_k": rec["armijo_k"][:K * T].reshape(K, T).copy()}

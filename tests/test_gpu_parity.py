@@ -396,3 +396,25 @@ def test_reconstruct_interp_bp(E, oracle, K, kw):
     assert well_separated(so)
     assert np.array_equal(sg["armijo_k"], so["armijo_k"])
     assert rel(f, fo) <= 1e-4
+
+
+# ------------------------------------------------------------------ given (frozen) edge weights
+
+@pytest.mark.parametrize("frozen", [3, 20])
+def test_reconstruct_with_given_weights(E, oracle, frozen):
+    """Weights proposed from outside (here: Eq. 5's weights of a blurred phantom)
+    used in place of Eq. 5 for the first iterations, then adaptive."""
+    c = synth.make_case("small", 0)
+    g = c.geom
+    P, M = plan(E, "small"), matrix(oracle, "small")
+    _, wx, wy = oracle.tv_gradient(c.phantom, c.phantom, 1.0, 0.004, 1e-4)
+    wx, wy = wx.astype(np.float32), wy.astype(np.float32)
+    y = c.y.astype(np.float32)
+    K = 20
+    fo, so = M.reconstruct(y, oracle_params(oracle, K), f_ref=c.phantom, weights=(wx, wy), frozen_iters=frozen)
+    f, sg = P.reconstruct(dev(y), E.Params(outer_iters=K, lam=1000.0), f_ref=dev(c.phantom),
+                          weights=(dev(wx), dev(wy)), frozen_iters=frozen)
+    assert well_separated(so)
+    assert np.array_equal(sg["armijo_k"], so["armijo_k"])
+    assert np.all(sg["sigma"][:frozen] == -1.0)
+    assert rel(f.cpu().numpy(), fo) <= 1e-4

@@ -609,4 +609,4 @@ def test_frozen_then_adaptive(oracle):
     f2, s2 = M.reconstruct(y, oracle.Params(outer_iters=2, lam=200.0), weights=w, frozen_iters=2)
     f3, s3 = M.reconstruct(y, oracle.Params(outer_iters=3, lam=200.0, zero_init=0), f0=f2)
     np.testing.assert_array_equal(f5, f3)
-    assert np.all(s5["sigma"][:2] == 0.0) and np.all(s5["sigma"][2:] > 0.0)
+    assert np.all(s5["sigma"][:2] == -1.0) and np.all(s5["sigma"][2:] > 0.0)
