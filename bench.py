@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK = 157.3e12  # MI355X published FP32 vector peak, FLOP/s
 HBM_PEAK = 8.0e12            # MI355X published HBM3E bandwidth, B/s
+BF16_MFMA_PEAK = 2.5e15      # MI355X published dense bf16 matrix-core peak, FLOP/s
 
 # HBM bytes per launch of the operator kernels on this workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
@@ -91,39 +92,61 @@ def cpu_baseline(case, iters):
             "seconds": dt}
 
 
-def time_to_rmse(E, synth, P, base, torch, np, seeds):
-    """Seconds of plain GPU EPTV until the RMSE to the phantom reaches the FP64
-    oracle's RMSE after 100 iterations (tests/golden/rmse_targets_paper.json),
-    the device-side RMSE record included in the timed run; median over seeds."""
+def time_to_rmse(E, synth, P, torch, np, seeds):
+    """Seconds until the RMSE to the phantom reaches the FP64 oracle's RMSE
+    after 100 iterations (tests/golden/rmse_targets_paper.json), the
+    device-side RMSE record included in the timed run; median over seeds.
+    Plain EPTV from zero, and (when the trained network is present) the
+    CNN-assisted pipeline: 3 plain iterations, the U-Net's proposal of image
+    and edge weights, EPTV warm-started from it with the weights frozen for
+    its first iteration."""
+    from paper_1009_2288_amd import cnn_assist as A
     with open(os.path.join(ROOT, "tests", "golden", "rmse_targets_paper.json")) as fh:
         targets = json.load(fh)
+    net = A.network(max_batch=1, params=A.load_params()) if os.path.exists(A.WEIGHTS) else None
     per = []
-    s = torch.cuda.current_stream()
     for seed in seeds:
         c = synth.make_case("paper", seed)
         y = torch.from_numpy(c.y.astype(np.float32)).cuda()
         ref = torch.from_numpy(c.phantom.astype(np.float32)).cuda()
         target = targets["seeds"][str(seed)]["rmse_final"]
-        _, st = P.reconstruct(y, E.Params(outer_iters=100, zero_init=1, **base), f_ref=ref)
-        hit = np.nonzero(st["rmse"] <= target)[0]
-        if hit.size == 0:
-            per.append({"seed": seed, "target": target, "iterations": None, "seconds": None})
-            continue
-        n = int(hit[0]) + 1
-        f = torch.zeros_like(ref)
+        r = {"seed": seed, "target": target, "plain": A.time_to_rmse(P, y, ref, target)}
+        if net is not None:
+            r["cnn"] = A.time_to_rmse(P, y, ref, target, net=net)
+        per.append(r)
+
+    def med(kind, key):
+        v = [p[kind][key] for p in per if kind in p]
+        return float(np.median(v)) if v and all(x is not None for x in v) else None
+
+    out = {"target": "FP64 oracle RMSE to the phantom after 100 iterations, same seed",
+           "plain_seconds_median": med("plain", "seconds"),
+           "plain_iterations_median": med("plain", "iterations"),
+           "per_seed": per}
+    if net is not None:
+        out["cnn_seconds_median"] = med("cnn", "seconds")
+        out["cnn_warm_iterations_median"] = med("cnn", "iterations")
+        if out["cnn_seconds_median"] and out["plain_seconds_median"]:
+            out["cnn_speedup"] = out["plain_seconds_median"] / out["cnn_seconds_median"]
+        out["cnn_pipeline"] = (f"{A.N0} plain iterations + U-Net ({A.NET['levels']} levels, base {A.NET['base']}, "
+                               f"bf16 MFMA) + EPTV warm start, proposed weights frozen for 1 iteration")
+        # the network alone: forward time and matrix-core rate at 512^2
+        x = torch.zeros((1, 512, 512, 1), dtype=torch.float32, device="cuda")
+        for _ in range(3):
+            net.forward(x)
+        s = torch.cuda.current_stream()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record(s)
-        P.reconstruct(y, E.Params(outer_iters=n, zero_init=1, **base), f=f, f_ref=ref, stats=False)
+        for _ in range(20):
+            net.forward(x)
         e1.record(s)
         torch.cuda.synchronize()
-        per.append({"seed": seed, "target": target, "iterations": n, "seconds": e0.elapsed_time(e1) / 1e3,
-                    "rmse": float(st["rmse"][n - 1])})
-    secs = [p["seconds"] for p in per if p["seconds"] is not None]
-    return {"target": "FP64 oracle RMSE to the phantom after 100 iterations, same seed",
-            "plain_seconds_median": float(np.median(secs)) if len(secs) == len(per) else None,
-            "plain_iterations_median": float(np.median([p["iterations"] for p in per if p["iterations"]])),
-            "per_seed": per}
+        ms = e0.elapsed_time(e1) / 20
+        fl = A.forward_flops(512, 512)
+        out["unet_forward"] = {"ms": ms, "algorithmic_gflop": fl / 1e9, "tflops": fl / ms / 1e9,
+                               "mfma_bf16_peak_frac": fl / (ms * 1e-3) / BF16_MFMA_PEAK}
+    return out
 
 
 def batch_leg(E, synth, torch, np, n_slices, iters, warmup):
@@ -256,8 +279,9 @@ def main():
     ttr = None
     if args.rmse_seeds > 0:
         log(f"bench: time to the oracle's RMSE, seeds 0-{args.rmse_seeds - 1}")
-        ttr = time_to_rmse(eptv, synth, P, base, torch, np, range(args.rmse_seeds))
-        log(f"bench: plain EPTV reaches the oracle RMSE in {ttr['plain_seconds_median']} s (median)")
+        ttr = time_to_rmse(eptv, synth, P, torch, np, range(args.rmse_seeds))
+        log(f"bench: plain EPTV reaches the oracle RMSE in {ttr['plain_seconds_median']} s (median), "
+            f"CNN-assisted in {ttr.get('cnn_seconds_median')} s")
 
     bat = None
     if args.batch_slices > 0:

@@ -315,6 +315,25 @@ int eptv_unet_adam(eptv_unet net, float lr, float beta1, float beta2, float eps,
 int eptv_unet_mse(eptv_unet net, const float* y, const float* target, size_t n, float* dy, float* loss,
                   void* stream);
 
+/* EPTV images and half-edge weights (Eq. 5 / A3) as network tensors, for
+ * n_img images of ny x nx stored one after another: f and f_base
+ * [n_img][ny][nx], wx [n_img][ny][nx+1], wy [n_img][ny+1][nx], maps NHWC fp32
+ * (all device).  The image channel is scale * (f - f_base) (f_base may be
+ * NULL: scale * f); scale > 0 brings the attenuation image (mm^-1), or its
+ * change from a base image, to unit order for the network.  With weights,
+ * maps has 3 channels: 0 = wx[j][i+1] (the half-edge right of pixel (i, j)),
+ * 1 = wy[j+1][i] (the half-edge above it), 2 = the image channel; with
+ * wx = wy = NULL, the image channel alone. */
+int eptv_maps_from_eptv(int n_img, int ny, int nx, const float* f, const float* f_base, const float* wx,
+                        const float* wy, float scale, float* maps, void* stream);
+/* The inverse for 3-channel maps: f = max(channel 2 / scale + f_base, 0)
+ * (f_base may be NULL), weights clamped to [0, 1]; the half-edges on the left
+ * (wx[j][0]) and bottom (wy[0][i]) border, which no pixel's channels hold,
+ * take the weight of the adjacent half-edge of their row / column.  The
+ * weights are ready for eptv_reconstruct_weighted, f for its warm start. */
+int eptv_maps_to_eptv(int n_img, int ny, int nx, const float* maps, float scale, const float* f_base, float* f,
+                      float* wx, float* wy, void* stream);
+
 const char* eptv_status_string(int status);
 
 /* Last HIP error text seen by the library on this thread ("" if none). */

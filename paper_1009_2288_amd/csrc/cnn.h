@@ -37,8 +37,8 @@ hipError_t launch_conv(const ConvArgs& a, int mode, hipStream_t s);
 int wgrad_chunks(const ConvArgs& a, int chunk_px);
 hipError_t launch_wgrad(const ConvArgs& a, int mode, const uint16_t* dy, int dy_cs, int dy_co, int chunk_px,
                         float* part, float* out, hipStream_t s);
-hipError_t launch_bias_grad(const uint16_t* dy, const float* dy32, int cs, int co, int npix, int c, float* db,
-                            hipStream_t s);
+hipError_t launch_bias_grad(const uint16_t* dy, const float* dy32, int cs, int co, int npix, int c, int chunk_px,
+                            float* part, float* db, hipStream_t s);
 hipError_t launch_relu_mask(uint16_t* dy, int dcs, int dco, const uint16_t* y, int ycs, int yco, int npix, int c,
                             hipStream_t s);
 hipError_t launch_avgpool(const uint16_t* x, int xcs, int xco, uint16_t* y, int n_img, int h, int w, int c,
@@ -46,6 +46,10 @@ hipError_t launch_avgpool(const uint16_t* x, int xcs, int xco, uint16_t* y, int 
 hipError_t launch_avgpool_back(const uint16_t* dy, uint16_t* dx, int dxcs, int dxco, int n_img, int h, int w, int c,
                                int accumulate, hipStream_t s);
 hipError_t launch_to_bf16(const float* x, uint16_t* y, size_t n, hipStream_t s);
+hipError_t launch_eptv_to_maps(const float* f, const float* f_base, const float* wx, const float* wy, int n_img,
+                               int ny, int nx, float scale, float* y, hipStream_t s);
+hipError_t launch_maps_to_eptv(const float* y, const float* f_base, int n_img, int ny, int nx, float scale, float* f,
+                               float* wx, float* wy, hipStream_t s);
 hipError_t launch_to_f32(const uint16_t* x, float* y, size_t n, hipStream_t s);
 hipError_t launch_add_slice(const uint16_t* src, int scs, int sco, uint16_t* dst, int dcs, int dco, int npix, int c,
                             hipStream_t s);

@@ -66,12 +66,12 @@ __device__ __forceinline__ Frag gather_a(const ConvArgs& a, int img, int y, int 
             if ((unsigned)ys >= (unsigned)a.h || (unsigned)xs >= (unsigned)a.w) return f;
             f.u = *reinterpret_cast<const uint4*>(a.x + (((size_t)img * a.h + ys) * a.w + xs) * a.x_cs + a.x_co + c);
         } else {
+#pragma unroll
             for (int i = 0; i < 8; ++i) {
                 const int kk = k + i;
-                if (kk >= 9 * a.cin) break;
                 const int tap = kk / a.cin, c = kk - tap * a.cin;
                 const int ys = y + tap / 3 - 1, xs = x + tap % 3 - 1;
-                if ((unsigned)ys < (unsigned)a.h && (unsigned)xs < (unsigned)a.w)
+                if (kk < 9 * a.cin && (unsigned)ys < (unsigned)a.h && (unsigned)xs < (unsigned)a.w)
                     f.h[i] = a.x[(((size_t)img * a.h + ys) * a.w + xs) * a.x_cs + a.x_co + c];
             }
         }
@@ -80,8 +80,9 @@ __device__ __forceinline__ Frag gather_a(const ConvArgs& a, int img, int y, int 
             if (k >= a.cin) return f;
             f.u = *reinterpret_cast<const uint4*>(a.x + (((size_t)img * a.h + y) * a.w + x) * a.x_cs + a.x_co + k);
         } else {
-            for (int i = 0; i < 8 && k + i < a.cin; ++i)
-                f.h[i] = a.x[(((size_t)img * a.h + y) * a.w + x) * a.x_cs + a.x_co + k + i];
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (k + i < a.cin) f.h[i] = a.x[(((size_t)img * a.h + y) * a.w + x) * a.x_cs + a.x_co + k + i];
         }
     } else {  // kUpBack: the input is the 2h x 2w gradient with cin channels per parity
         if (k >= 4 * a.cin) return f;
@@ -93,70 +94,127 @@ __device__ __forceinline__ Frag gather_a(const ConvArgs& a, int img, int y, int 
     return f;
 }
 
-// Block: 4 waves x 16 consecutive pixels of the flattened (image, y, x) order
-// of the GEMM grid, x 64 output channels; grid (pixel groups, channel blocks,
-// parity q for kUp).  Each lane decodes its own pixel, so any image size works.
-template <int MODE>
+// Block: 4 waves, each RT x 16 consecutive pixels of the flattened (image, y,
+// x) order of the GEMM grid, x 64 output channels; grid (pixel groups,
+// channel blocks, parity q for kUp).  The block's 64 weight rows are staged in
+// LDS a K-chunk at a time and shared by the 4 waves; the A operand is gathered
+// straight from the input (each lane decodes its own pixels, so any image size
+// works), one K-step ahead of the matrix instructions that use it.
+constexpr int kConvKC = 256;           // K-chunk of staged weights
+constexpr int kConvLd = kConvKC + 8;   // LDS row pitch (bf16), 16 B of padding
+
+template <int MODE, int RT>
 __global__ __launch_bounds__(256) void k_conv(ConvArgs a)
 {
+    __shared__ __attribute__((aligned(16))) uint16_t wlds[64 * kConvLd];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int npix = a.n_img * a.h * a.w;
-    const int p0 = blockIdx.x * 64 + wave * 16;
-    if (p0 >= npix) return;  // whole wave
+    const int hw = a.h * a.w, npix = a.n_img * hw;
+    const int p0 = (blockIdx.x * 4 + wave) * (16 * RT);
     const int n0 = blockIdx.y * 64;
     const int q = MODE == kUp ? (int)blockIdx.z : 0;
     const uint16_t* wq = a.wt + (size_t)q * a.n_pad * a.k_pad;
     const int mrow = lane & 15, kq = (lane >> 4) * 8;
-    // this lane's A row: pixel p0 + mrow
-    const int pa = p0 + mrow;
-    const bool va = pa < npix;
-    const int ia = pa / (a.h * a.w), ra = pa - ia * a.h * a.w, ya = ra / a.w, xa = ra - ya * a.w;
-    floatx4 acc[4];
+    int ia[RT], ya[RT], xa[RT];
+    bool va[RT];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int k0 = 0; k0 < a.k_pad; k0 += 32) {
-        const Frag fa = va ? gather_a<MODE>(a, ia, ya, xa, k0 + kq) : zero_frag();
+    for (int i = 0; i < RT; ++i) {
+        const int p = p0 + 16 * i + mrow;
+        va[i] = p < npix;
+        ia[i] = p / hw;
+        const int r = p - ia[i] * hw;
+        ya[i] = r / a.w;
+        xa[i] = r - ya[i] * a.w;
+    }
+    floatx4 acc[RT][4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            Frag fb;
-            fb.u = *reinterpret_cast<const uint4*>(wq + (size_t)(n0 + 16 * j + mrow) * a.k_pad + k0 + kq);
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa.v, fb.v, acc[j], 0, 0, 0);
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    Frag fa[RT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i) fa[i] = va[i] ? gather_a<MODE>(a, ia[i], ya[i], xa[i], kq) : zero_frag();
+    for (int kc = 0; kc < a.k_pad; kc += kConvKC) {
+        const int kn = min(kConvKC, a.k_pad - kc);  // a multiple of 64
+        __syncthreads();                             // the previous chunk is consumed
+        const int per_row = kn / 8;
+        for (int idx = threadIdx.x; idx < 64 * per_row; idx += 256) {
+            const int row = idx / per_row, c8 = idx - row * per_row;
+            *reinterpret_cast<uint4*>(wlds + row * kConvLd + c8 * 8) =
+                *reinterpret_cast<const uint4*>(wq + (size_t)(n0 + row) * a.k_pad + kc + c8 * 8);
+        }
+        __syncthreads();
+        for (int k0 = 0; k0 < kn; k0 += 32) {
+            const int kg = kc + k0 + 32;  // next K-step
+            Frag fn[RT];
+#pragma unroll
+            for (int i = 0; i < RT; ++i)
+                fn[i] = (kg < a.k_pad && va[i]) ? gather_a<MODE>(a, ia[i], ya[i], xa[i], kg + kq) : zero_frag();
+            Frag fb[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                fb[j].u = *reinterpret_cast<const uint4*>(wlds + (16 * j + mrow) * kConvLd + k0 + kq);
+#pragma unroll
+            for (int i = 0; i < RT; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i].v, fb[j].v, acc[i][j], 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < RT; ++i) fa[i] = fn[i];
         }
     }
-    // epilogue: accumulator r of lane l is pixel p0 + 4 (l / 16) + r, channel n0 + 16 j + l % 16
+    // epilogue: accumulator r of lane l, row tile i, column tile j is pixel
+    // p0 + 16 i + 4 (l / 16) + r, channel n0 + 16 j + l % 16
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int p = p0 + (lane >> 4) * 4 + r;
-        if (p >= npix) continue;
-        const int img = p / (a.h * a.w), rr = p - img * a.h * a.w, y = rr / a.w, x = rr - y * a.w;
-        size_t pix;
-        if (MODE == kUp)
-            pix = ((size_t)img * 2 * a.h + 2 * y + (q >> 1)) * 2 * a.w + 2 * x + (q & 1);
-        else
-            pix = (size_t)p;
+    for (int i = 0; i < RT; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int n = n0 + 16 * j + mrow;
-            if (n >= a.cout) continue;
-            float v = acc[j][r] + (a.bias ? a.bias[n] : 0.0f);
-            if (a.relu) v = fmaxf(v, 0.0f);
-            if (a.y32)
-                a.y32[pix * a.y_cs + a.y_co + n] = v;
-            else
-                a.y[pix * a.y_cs + a.y_co + n] = f2bf(v);
+        for (int r = 0; r < 4; ++r) {
+            const int p = p0 + 16 * i + (lane >> 4) * 4 + r;
+            if (p >= npix) continue;
+            size_t pix;
+            if (MODE == kUp) {
+                const int img = p / hw, rr = p - img * hw, y = rr / a.w, x = rr - y * a.w;
+                pix = ((size_t)img * 2 * a.h + 2 * y + (q >> 1)) * 2 * a.w + 2 * x + (q & 1);
+            } else {
+                pix = (size_t)p;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int n = n0 + 16 * j + mrow;
+                if (n >= a.cout) continue;
+                float v = acc[i][j][r] + (a.bias ? a.bias[n] : 0.0f);
+                if (a.relu) v = fmaxf(v, 0.0f);
+                if (a.y32)
+                    a.y32[pix * a.y_cs + a.y_co + n] = v;
+                else
+                    a.y[pix * a.y_cs + a.y_co + n] = f2bf(v);
+            }
         }
-    }
+}
+
+template <int MODE>
+static void conv_launch_rt(const ConvArgs& a, int rt, dim3 grid, hipStream_t s)
+{
+    if (rt == 4)
+        hipLaunchKernelGGL((k_conv<MODE, 4>), grid, dim3(256), 0, s, a);
+    else if (rt == 2)
+        hipLaunchKernelGGL((k_conv<MODE, 2>), grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_conv<MODE, 1>), grid, dim3(256), 0, s, a);
 }
 
 hipError_t launch_conv(const ConvArgs& a, int mode, hipStream_t s)
 {
     const int npix = a.n_img * a.h * a.w;
-    dim3 grid((unsigned)((npix + 63) / 64), (unsigned)(a.n_pad / 64), mode == kUp ? 4u : 1u);
+    const int cblk = a.n_pad / 64, par = mode == kUp ? 4 : 1;
+    // the largest row-tile count that still gives about two blocks per CU
+    int rt = 4;
+    while (rt > 1 && (long long)((npix + 64 * rt - 1) / (64 * rt)) * cblk * par < 512) rt /= 2;
+    dim3 grid((unsigned)((npix + 64 * rt - 1) / (64 * rt)), (unsigned)cblk, (unsigned)par);
     switch (mode) {
-    case kConv3: hipLaunchKernelGGL(k_conv<kConv3>, grid, dim3(256), 0, s, a); break;
-    case kPoint: hipLaunchKernelGGL(k_conv<kPoint>, grid, dim3(256), 0, s, a); break;
-    case kUp: hipLaunchKernelGGL(k_conv<kUp>, grid, dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL(k_conv<kUpBack>, grid, dim3(256), 0, s, a); break;
+    case kConv3: conv_launch_rt<kConv3>(a, rt, grid, s); break;
+    case kPoint: conv_launch_rt<kPoint>(a, rt, grid, s); break;
+    case kUp: conv_launch_rt<kUp>(a, rt, grid, s); break;
+    default: conv_launch_rt<kUpBack>(a, rt, grid, s); break;
     }
     return hipGetLastError();
 }
@@ -164,77 +222,98 @@ hipError_t launch_conv(const ConvArgs& a, int mode, hipStream_t s)
 // ------------------------------------------------------------------ weight gradients
 // dW[n][k] = sum_p dY[p][n] A(p, k), split over chunks of pixels: block
 // (chunk, n block, k block) writes its 64 x 64 fp32 partial; k_wgrad_reduce
-// sums the chunks in order.  MFMA rows are n (A' = dY^T), columns k, and the
-// reduction runs over 32 pixels per instruction.
+// sums the chunks in order.  The reduction runs over pixels, which are not
+// contiguous in NHWC, so each 64-pixel step stages dY and A transposed in LDS
+// ([channel][pixel], four pixels per 8-byte store); then each wave (2 x 2
+// arrangement) forms a 32 n x 32 k tile with MFMA rows n (A' = dY^T) and
+// columns k, 32 pixels per instruction.
+constexpr int kWgLd = 72;  // LDS pitch in bf16 (64 pixels + 16 B)
+
 template <int MODE>
 __global__ __launch_bounds__(256) void k_wgrad(ConvArgs a, const uint16_t* __restrict__ dy, int dy_cs, int dy_co,
                                                int chunk_px, float* part)
 {
+    __shared__ __attribute__((aligned(16))) uint16_t t_dy[64 * kWgLd];
+    __shared__ __attribute__((aligned(16))) uint16_t t_a[64 * kWgLd];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int chunk = blockIdx.x;
-    const int n0 = blockIdx.y * 64 + wave * 16;
+    const int n0 = blockIdx.y * 64;
     const int k0 = blockIdx.z * 64;
     const int q = MODE == kUp ? (int)(k0 / a.k_pad) : 0;  // kUp: the 4 parities side by side along k
     const int kb = MODE == kUp ? k0 - q * a.k_pad : k0;
-    const int row = lane & 15, pq = (lane >> 4) * 8;
-    const int npix = a.n_img * a.h * a.w;
+    const int hw = a.h * a.w, npix = a.n_img * hw;
     const int p_beg = chunk * chunk_px, p_end = min(npix, p_beg + chunk_px);
-    floatx4 acc[4];
+    // loader role: threads 0-127 stage dY, 128-255 stage A; 4 pixels x 8 channels each
+    const int lt = threadIdx.x & 127, lg = lt >> 3, lc = (lt & 7) * 8;
+    const bool load_dy = threadIdx.x < 128;
+    const bool dy_vec = (dy_cs % 8 == 0) && (dy_co % 8 == 0) && (n0 + lc + 8 <= a.cout);
+    // compute role
+    const int wn = wave >> 1, wk = wave & 1, row = lane & 15, pq = (lane >> 4) * 8;
+    floatx4 acc[2][2];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int p0 = p_beg; p0 < p_end; p0 += 32) {
-        Frag fa = zero_frag();
-        const int n = n0 + row;
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int p = p0 + pq + i;
-            if (p < p_end && n < a.cout) {
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int ps = p_beg; ps < p_end; ps += 64) {
+        Frag v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            v[u] = zero_frag();
+            const int p = ps + lg * 4 + u;
+            if (p >= p_end) continue;
+            const int img = p / hw, r = p - img * hw, yy = r / a.w, xx = r - yy * a.w;
+            if (load_dy) {
                 size_t pix = (size_t)p;
-                if (MODE == kUp) {
-                    const int img = p / (a.h * a.w), r = p - img * a.h * a.w, yy = r / a.w, xx = r - yy * a.w;
-                    pix = ((size_t)img * 2 * a.h + 2 * yy + (q >> 1)) * 2 * a.w + 2 * xx + (q & 1);
+                if (MODE == kUp) pix = ((size_t)img * 2 * a.h + 2 * yy + (q >> 1)) * 2 * a.w + 2 * xx + (q & 1);
+                const uint16_t* src = dy + pix * dy_cs + dy_co + n0 + lc;
+                if (dy_vec) {
+                    v[u].u = *reinterpret_cast<const uint4*>(src);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        if (n0 + lc + i < a.cout) v[u].h[i] = src[i];
                 }
-                fa.h[i] = dy[pix * dy_cs + dy_co + n];
+            } else {
+                v[u] = gather_a<MODE == kConv3 ? kConv3 : kPoint>(a, img, yy, xx, kb + lc);
             }
         }
+        __syncthreads();  // the previous step's tiles are consumed
+        uint16_t* dst = load_dy ? t_dy : t_a;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            Frag fb = zero_frag();
-            const int k = kb + 16 * j + row;
+        for (int i = 0; i < 8; ++i) {
+            uint2 w;
+            w.x = (uint32_t)v[0].h[i] | ((uint32_t)v[1].h[i] << 16);
+            w.y = (uint32_t)v[2].h[i] | ((uint32_t)v[3].h[i] << 16);
+            *reinterpret_cast<uint2*>(dst + (lc + i) * kWgLd + lg * 4) = w;
+        }
+        __syncthreads();
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int p = p0 + pq + i;
-                if (p >= p_end) break;
-                const int img = p / (a.h * a.w), r = p - img * a.h * a.w, yy = r / a.w, xx = r - yy * a.w;
-                if (MODE == kConv3) {
-                    if (k < 9 * a.cin) {
-                        const int tap = k / a.cin, c = k - tap * a.cin;
-                        const int ys = yy + tap / 3 - 1, xs = xx + tap % 3 - 1;
-                        if ((unsigned)ys < (unsigned)a.h && (unsigned)xs < (unsigned)a.w)
-                            fb.h[i] = a.x[(((size_t)img * a.h + ys) * a.w + xs) * a.x_cs + a.x_co + c];
-                    }
-                } else if (MODE == kPoint || MODE == kUp) {
-                    if (k < a.cin) fb.h[i] = a.x[(size_t)p * a.x_cs + a.x_co + k];
-                } else {  // kUpBack
-                    if (k < 4 * a.cin) {
-                        const int qq = k / a.cin, o = k - qq * a.cin;
-                        const int ys = 2 * yy + (qq >> 1), xs = 2 * xx + (qq & 1);
-                        fb.h[i] = a.x[(((size_t)img * 2 * a.h + ys) * 2 * a.w + xs) * a.x_cs + a.x_co + o];
-                    }
-                }
-            }
-            acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa.v, fb.v, acc[j], 0, 0, 0);
+        for (int s2 = 0; s2 < 64; s2 += 32) {
+            Frag fa[2], fb[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                fa[i].u = *reinterpret_cast<const uint4*>(t_dy + (32 * wn + 16 * i + row) * kWgLd + s2 + pq);
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                fb[j].u = *reinterpret_cast<const uint4*>(t_a + (32 * wk + 16 * j + row) * kWgLd + s2 + pq);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i].v, fb[j].v, acc[i][j], 0, 0, 0);
         }
     }
     // partial[chunk][n][k] over the padded n x (4 or 1) k_pad grid
     const int kw = MODE == kUp ? 4 * a.k_pad : a.k_pad;
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int n = n0 + (lane >> 4) * 4 + r, k = k0 + 16 * j + row;
-            part[((size_t)chunk * a.n_pad + n) * kw + k] = acc[j][r];
-        }
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int n = n0 + 32 * wn + 16 * i + (lane >> 4) * 4 + r, k = k0 + 32 * wk + 16 * j + row;
+                part[((size_t)chunk * a.n_pad + n) * kw + k] = acc[i][j][r];
+            }
 }
 
 __global__ void k_wgrad_reduce(const float* __restrict__ part, int chunks, size_t per, float* out)
@@ -277,28 +356,37 @@ hipError_t launch_wgrad(const ConvArgs& a, int mode, const uint16_t* dy, int dy_
 }
 
 // ------------------------------------------------------------------ elementwise
-// bias gradient: db[n] = sum over pixels of dy[p][n] (fixed order per n)
-__global__ __launch_bounds__(256) void k_bias_grad(const uint16_t* __restrict__ dy, int cs, int co, int npix, int c,
-                                                   const float* dy32, float* db)
+// bias gradient: db[n] = sum over pixels of dy[p][n].  Block b sums the
+// pixels of chunk b for every channel (64 consecutive channels per wave row,
+// so each pixel's channels are read as one contiguous run) into
+// part[b][n]; k_wgrad_reduce then adds the chunks in order (deterministic).
+__global__ __launch_bounds__(256) void k_bias_part(const uint16_t* __restrict__ dy, int cs, int co, int npix, int c,
+                                                   const float* dy32, int chunk_px, float* part)
 {
-    __shared__ float red[256];
-    const int n = blockIdx.x;
-    float s = 0.0f;
-    for (int p = threadIdx.x; p < npix; p += 256)
-        s += dy32 ? dy32[(size_t)p * cs + co + n] : bf2f(dy[(size_t)p * cs + co + n]);
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __shared__ float red[4][64];
+    const int lane = threadIdx.x & 63, ph = threadIdx.x >> 6;
+    const int p_beg = blockIdx.x * chunk_px, p_end = min(npix, p_beg + chunk_px);
+    for (int c0 = 0; c0 < c; c0 += 64) {
+        const int n = c0 + lane;
+        float s = 0.0f;
+        if (n < c)
+            for (int p = p_beg + ph; p < p_end; p += 4)
+                s += dy32 ? dy32[(size_t)p * cs + co + n] : bf2f(dy[(size_t)p * cs + co + n]);
+        red[ph][lane] = s;
+        __syncthreads();
+        if (ph == 0 && n < c) part[(size_t)blockIdx.x * c + n] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) db[n] = red[0];
 }
 
-hipError_t launch_bias_grad(const uint16_t* dy, const float* dy32, int cs, int co, int npix, int c, float* db,
-                            hipStream_t s)
+hipError_t launch_bias_grad(const uint16_t* dy, const float* dy32, int cs, int co, int npix, int c, int chunk_px,
+                            float* part, float* db, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_bias_grad, dim3((unsigned)c), dim3(256), 0, s, dy, cs, co, npix, c, dy32, db);
+    const int chunks = (npix + chunk_px - 1) / chunk_px;
+    hipLaunchKernelGGL(k_bias_part, dim3((unsigned)chunks), dim3(256), 0, s, dy, cs, co, npix, c, dy32, chunk_px,
+                       part);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)std::min((c + 255) / 256, 4096)), dim3(256), 0, s, part, chunks,
+                       (size_t)c, db);
     return hipGetLastError();
 }
 
@@ -551,6 +639,74 @@ hipError_t launch_mse(const float* y, const float* t, size_t n, float* dy, doubl
 {
     hipLaunchKernelGGL(k_mse, dim3((unsigned)nblocks), dim3(256), 0, s, y, t, n, dy, part);
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, part, nblocks, 1.0 / (double)n, loss);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ EPTV <-> network tensors
+// Network tensors are NHWC fp32 on the pixel grid.  With weights, channel 0 is
+// the weight of the half-edge right of pixel (i, j) (wx[j][i+1]), channel 1 of
+// the half-edge above it (wy[j+1][i]), channel 2 the image, minus an optional
+// base image, times `scale`; without weights, that image channel alone.
+__global__ void k_eptv_to_maps(const float* f, const float* f_base, const float* wx, const float* wy, int n_img,
+                               int ny, int nx, float scale, float* y)
+{
+    const size_t per = (size_t)ny * nx, n = (size_t)n_img * per;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        const float v = (f_base ? f[e] - f_base[e] : f[e]) * scale;
+        if (!wx) {
+            y[e] = v;
+            continue;
+        }
+        const size_t img = e / per, pix = e - img * per;
+        const int j = (int)(pix / nx), i = (int)(pix - (size_t)j * nx);
+        y[e * 3 + 0] = wx[img * (size_t)ny * (nx + 1) + (size_t)j * (nx + 1) + i + 1];
+        y[e * 3 + 1] = wy[img * (size_t)(ny + 1) * nx + (size_t)(j + 1) * nx + i];
+        y[e * 3 + 2] = v;
+    }
+}
+
+// The inverse for a 3-channel tensor: the image is channel 2 divided by
+// `scale`, plus the optional base image, truncated at zero; the weights are
+// clamped to [0, 1]; the half-edges on the left and bottom border, which no
+// pixel's channels hold, take the weight of the adjacent half-edge of the
+// same row / column.
+__global__ void k_maps_to_eptv(const float* y, const float* f_base, int n_img, int ny, int nx, float inv_scale,
+                               float* f, float* wx, float* wy)
+{
+    const size_t per = (size_t)ny * nx, n = (size_t)n_img * per;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        const size_t img = e / per, pix = e - img * per;
+        const int j = (int)(pix / nx), i = (int)(pix - (size_t)j * nx);
+        const float* yy = y + e * 3;
+        const float w0 = fminf(fmaxf(yy[0], 0.0f), 1.0f), w1 = fminf(fmaxf(yy[1], 0.0f), 1.0f);
+        const float v = yy[2] * inv_scale;
+        f[e] = fmaxf(f_base ? v + f_base[e] : v, 0.0f);
+        float* wxi = wx + img * (size_t)ny * (nx + 1);
+        float* wyi = wy + img * (size_t)(ny + 1) * nx;
+        wxi[(size_t)j * (nx + 1) + i + 1] = w0;
+        if (i == 0) wxi[(size_t)j * (nx + 1)] = w0;
+        wyi[(size_t)(j + 1) * nx + i] = w1;
+        if (j == 0) wyi[i] = w1;
+    }
+}
+
+static unsigned grid_for(size_t n) { return (unsigned)std::min<size_t>(std::max<size_t>((n + 255) / 256, 1), 4096); }
+
+hipError_t launch_eptv_to_maps(const float* f, const float* f_base, const float* wx, const float* wy, int n_img,
+                               int ny, int nx, float scale, float* y, hipStream_t s)
+{
+    const size_t n = (size_t)n_img * ny * nx;
+    hipLaunchKernelGGL(k_eptv_to_maps, dim3(grid_for(n)), dim3(256), 0, s, f, f_base, wx, wy, n_img, ny, nx, scale,
+                       y);
+    return hipGetLastError();
+}
+
+hipError_t launch_maps_to_eptv(const float* y, const float* f_base, int n_img, int ny, int nx, float scale, float* f,
+                               float* wx, float* wy, hipStream_t s)
+{
+    const size_t n = (size_t)n_img * ny * nx;
+    hipLaunchKernelGGL(k_maps_to_eptv, dim3(grid_for(n)), dim3(256), 0, s, y, f_base, n_img, ny, nx, 1.0f / scale, f,
+                       wx, wy);
     return hipGetLastError();
 }
 

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
@@ -173,7 +174,7 @@ static hipError_t layer_grads(eptv_unet_s& u, int li, int n, int h, int w, const
     e = launch_unpack_grad(Ly.gpack, Ly.mode, Ly.ci, Ly.co, Ly.n_pad, Ly.k_pad, u.grads + Ly.w_off, s);
     if (e != hipSuccess) return e;
     const int oh = Ly.mode == kUp ? 2 * h : h, ow = Ly.mode == kUp ? 2 * w : w;
-    return launch_bias_grad(dy, dy32, dycs, dyco, n * oh * ow, Ly.co, u.grads + Ly.b_off, s);
+    return launch_bias_grad(dy, dy32, dycs, dyco, n * oh * ow, Ly.co, kChunkPx, u.part, u.grads + Ly.b_off, s);
 }
 
 // backward data of layer li: gradient of its input from its output gradient
@@ -387,6 +388,9 @@ int eptv_unet_create(int c_in, int c_out, int base, int levels, int max_batch, i
         const size_t npix = B * (height >> Ly.lev) * (width >> Ly.lev);
         const size_t chunks = (npix + kChunkPx - 1) / kChunkPx;
         part = std::max(part, chunks * Ly.n_pad * (Ly.mode == kUp ? 4 : 1) * Ly.k_pad);
+        // bias partials run over the layer's output pixels (4x the GEMM grid for kUp)
+        const size_t out_px = Ly.mode == kUp ? 4 * npix : npix;
+        part = std::max(part, (out_px + kChunkPx - 1) / kChunkPx * (size_t)Ly.co);
     }
     u->part_floats = part;
     if (e == hipSuccess) e = dalloc(*u, &u->part, part);
@@ -471,6 +475,24 @@ int eptv_unet_mse(eptv_unet u, const float* y, const float* target, size_t n, fl
 {
     if (!u || !y || !target || !loss || n == 0) return EPTV_ERR_ARG;
     EPTV_HIP(launch_mse(y, target, n, dy, u->mse_part, kMseBlocks, loss, (hipStream_t)stream));
+    return EPTV_OK;
+}
+
+int eptv_maps_from_eptv(int n_img, int ny, int nx, const float* f, const float* f_base, const float* wx,
+                        const float* wy, float scale, float* maps, void* stream)
+{
+    if (n_img < 1 || ny < 1 || nx < 1 || !f || !maps || (!wx) != (!wy) || !(scale > 0) || !std::isfinite(scale))
+        return EPTV_ERR_ARG;
+    EPTV_HIP(launch_eptv_to_maps(f, f_base, wx, wy, n_img, ny, nx, scale, maps, (hipStream_t)stream));
+    return EPTV_OK;
+}
+
+int eptv_maps_to_eptv(int n_img, int ny, int nx, const float* maps, float scale, const float* f_base, float* f,
+                      float* wx, float* wy, void* stream)
+{
+    if (n_img < 1 || ny < 1 || nx < 1 || !maps || !f || !wx || !wy || !(scale > 0) || !std::isfinite(scale))
+        return EPTV_ERR_ARG;
+    EPTV_HIP(launch_maps_to_eptv(maps, f_base, n_img, ny, nx, scale, f, wx, wy, (hipStream_t)stream));
     return EPTV_OK;
 }
 

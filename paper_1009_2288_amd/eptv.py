@@ -29,7 +29,8 @@ SYMBOLS = ["eptv_plan_create", "eptv_plan_destroy", "eptv_plan_nnz", "eptv_works
            "eptv_batch_workspace_bytes", "eptv_batch_set_launch", "eptv_batch_get_launch", "eptv_batch_tune",
            "eptv_batch_reconstruct", "eptv_unet_create", "eptv_unet_destroy", "eptv_unet_param_count",
            "eptv_unet_set_params", "eptv_unet_get_params", "eptv_unet_get_grads", "eptv_unet_forward",
-           "eptv_unet_backward", "eptv_unet_adam", "eptv_unet_mse", "eptv_reconstruct_weighted"]
+           "eptv_unet_backward", "eptv_unet_adam", "eptv_unet_mse", "eptv_reconstruct_weighted",
+           "eptv_maps_from_eptv", "eptv_maps_to_eptv"]
 
 
 class EptvError(RuntimeError):
@@ -130,6 +131,8 @@ def _lib() -> C.CDLL:
         L.eptv_unet_backward.argtypes = [vp, vp, vp, vp]
         L.eptv_unet_adam.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int, vp]
         L.eptv_unet_mse.argtypes = [vp, vp, vp, sz, vp, vp, vp]
+        L.eptv_maps_from_eptv.argtypes = [C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, C.c_float, vp, vp]
+        L.eptv_maps_to_eptv.argtypes = [C.c_int, C.c_int, C.c_int, vp, C.c_float, vp, vp, vp, vp, vp]
         L.eptv_tv_gradient_vjp.argtypes = [vp, vp, vp, C.c_float, C.c_float, C.c_float, vp, vp, sz, vp]
         L.eptv_select_sigma.argtypes = [vp, vp, C.c_double, C.c_float, C.c_float, vp, vp, sz, vp]
         L.eptv_tv_step.argtypes = [vp, C.POINTER(_Params), vp, vp, C.c_float, C.c_int, vp, sz, C.POINTER(_Stats), vp]
@@ -614,3 +617,57 @@ class UNet:
                                     dy.data_ptr() if dy is not None else None, loss.data_ptr(), _stream(stream)),
                "eptv_unet_mse")
         return loss, dy
+
+
+def _dev_f32(t, shape, name):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float32 GPU tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+def maps_from_eptv(f: torch.Tensor, wx: Optional[torch.Tensor] = None, wy: Optional[torch.Tensor] = None,
+                   scale: float = 1.0, f_base: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
+                   stream=None) -> torch.Tensor:
+    """Network tensor [n][ny][nx][3] (wx right, wy above, scale*(f - f_base))
+    or, without weights, [n][ny][nx][1], from f [n][ny][nx] (or [ny][nx]);
+    written into ``out`` when given."""
+    f3 = f if f.dim() == 3 else f.view(1, *f.shape)
+    n, ny, nx = f3.shape
+    _dev_f32(f3, (n, ny, nx), "f")
+    if f_base is not None:
+        f_base = _dev_f32(f_base if f_base.dim() == 3 else f_base.view(1, *f_base.shape), (n, ny, nx), "f_base")
+    if (wx is None) != (wy is None):
+        raise ValueError("give both weight maps or neither")
+    c = 1
+    if wx is not None:
+        wx = _dev_f32(wx if wx.dim() == 3 else wx.view(1, *wx.shape), (n, ny, nx + 1), "wx")
+        wy = _dev_f32(wy if wy.dim() == 3 else wy.view(1, *wy.shape), (n, ny + 1, nx), "wy")
+        c = 3
+    if out is None:
+        out = torch.empty((n, ny, nx, c), dtype=torch.float32, device=f.device)
+    _dev_f32(out, (n, ny, nx, c), "out")
+    _check(_lib().eptv_maps_from_eptv(n, ny, nx, f3.data_ptr(), f_base.data_ptr() if f_base is not None else None,
+                                      wx.data_ptr() if wx is not None else None,
+                                      wy.data_ptr() if wy is not None else None, scale, out.data_ptr(),
+                                      _stream(stream)), "eptv_maps_from_eptv")
+    return out
+
+
+def maps_to_eptv(maps: torch.Tensor, scale: float = 1.0, f_base: Optional[torch.Tensor] = None, stream=None):
+    """(f [n][ny][nx], wx [n][ny][nx+1], wy [n][ny+1][nx]) from a 3-channel
+    network tensor [n][ny][nx][3]: f = max(channel 2 / scale + f_base, 0)."""
+    if maps.dim() != 4 or maps.shape[3] != 3:
+        raise ValueError(f"maps must be [n][ny][nx][3], got {tuple(maps.shape)}")
+    n, ny, nx, _ = maps.shape
+    _dev_f32(maps, (n, ny, nx, 3), "maps")
+    if f_base is not None:
+        f_base = _dev_f32(f_base if f_base.dim() == 3 else f_base.view(1, *f_base.shape), (n, ny, nx), "f_base")
+    f = torch.empty((n, ny, nx), dtype=torch.float32, device=maps.device)
+    wx = torch.empty((n, ny, nx + 1), dtype=torch.float32, device=maps.device)
+    wy = torch.empty((n, ny + 1, nx), dtype=torch.float32, device=maps.device)
+    _check(_lib().eptv_maps_to_eptv(n, ny, nx, maps.data_ptr(), scale,
+                                    f_base.data_ptr() if f_base is not None else None, f.data_ptr(), wx.data_ptr(),
+                                    wy.data_ptr(), _stream(stream)), "eptv_maps_to_eptv")
+    return f, wx, wy

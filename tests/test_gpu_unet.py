@@ -51,6 +51,7 @@ def unflatten(flat, shapes):
     (1, 3, 8, 1, 2, 16, 24),     # one level: 3x3 convs (scalar and vector gathers) and the 1x1 head
     (2, 3, 8, 3, 2, 32, 32),     # pooling, transposed convs, skip concatenation
     (1, 3, 16, 4, 1, 64, 64),    # four levels
+    (1, 3, 8, 2, 3, 48, 80),     # several pixel chunks in the gradient sums, a ragged last one
 ])
 def test_unet_forward_and_gradients_match_oracle(E, c_in, c_out, base, levels, n, h, w):
     shapes = C.unet_shapes(c_in, c_out, base, levels)
@@ -101,3 +102,40 @@ def test_unet_adam_step_matches_oracle(E):
     pd, gd = {"a": before.copy()}, {"a": g}
     C.adam_step(pd, gd, {"a": np.zeros_like(g)}, {"a": np.zeros_like(g)}, step=1, lr=1e-3)
     np.testing.assert_allclose(after, pd["a"], rtol=1e-5, atol=1e-7)
+
+
+def test_maps_between_eptv_and_network_layout(E):
+    """The 3-channel network layout of an image and its half-edge weights and
+    back: a pure re-indexing with the image scaled, clamps on the way back,
+    the border half-edges copied from their neighbours (bit for bit)."""
+    rng = np.random.default_rng(4)
+    n, ny, nx, s = 2, 5, 7, 50.0
+    f = rng.uniform(0, 0.03, (n, ny, nx)).astype(np.float32)
+    wx = rng.uniform(0, 1, (n, ny, nx + 1)).astype(np.float32)
+    wy = rng.uniform(0, 1, (n, ny + 1, nx)).astype(np.float32)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    m = E.maps_from_eptv(dev(f), dev(wx), dev(wy), scale=s).cpu().numpy()
+    assert m.shape == (n, ny, nx, 3)
+    assert np.array_equal(m[..., 0], wx[:, :, 1:])
+    assert np.array_equal(m[..., 1], wy[:, 1:, :])
+    assert np.array_equal(m[..., 2], f * np.float32(s))
+    m1 = E.maps_from_eptv(dev(f[0]), scale=s).cpu().numpy()
+    assert m1.shape == (1, ny, nx, 1) and np.array_equal(m1[0, ..., 0], f[0] * np.float32(s))
+    # back, from maps with out-of-range values
+    q = rng.uniform(-0.5, 1.5, (n, ny, nx, 3)).astype(np.float32)
+    f2, wx2, wy2 = (t.cpu().numpy() for t in E.maps_to_eptv(dev(q), scale=s))
+    inv = np.float32(1) / np.float32(s)
+    assert np.array_equal(f2, np.maximum(q[..., 2] * inv, 0))
+    assert np.array_equal(wx2[:, :, 1:], np.clip(q[..., 0], 0, 1))
+    assert np.array_equal(wx2[:, :, 0], wx2[:, :, 1])
+    assert np.array_equal(wy2[:, 1:, :], np.clip(q[..., 1], 0, 1))
+    assert np.array_equal(wy2[:, 0, :], wy2[:, 1, :])
+    # residual form: the image channel relative to a base image
+    b = rng.uniform(0, 0.03, (n, ny, nx)).astype(np.float32)
+    mr = E.maps_from_eptv(dev(f), dev(wx), dev(wy), scale=s, f_base=dev(b)).cpu().numpy()
+    assert np.array_equal(mr[..., 2], (f - b) * np.float32(s))
+    f3, _, _ = (t.cpu().numpy() for t in E.maps_to_eptv(dev(q), scale=s, f_base=dev(b)))
+    want = np.maximum(q[..., 2].astype(np.float64) * inv + b, 0)
+    assert np.allclose(f3, want, rtol=2 ** -23, atol=1e-12)
+    assert E._lib().eptv_maps_to_eptv(1, ny, nx, m.ctypes.data, 0.0, None, None, None, None,
+                                      None) == E.EPTV_ERR_ARG
