@@ -35,10 +35,11 @@ inline int pad64(int n) { return (n + 63) / 64 * 64; }
 
 hipError_t launch_conv(const ConvArgs& a, int mode, hipStream_t s);
 int wgrad_chunks(const ConvArgs& a, int chunk_px);
+// dW (unpacked later) into out and, if bias_out is given, the bias gradient
+// sum_p dY[p][n] into bias_out[cout]; part and bpart are partial-sum scratch
 hipError_t launch_wgrad(const ConvArgs& a, int mode, const uint16_t* dy, int dy_cs, int dy_co, int chunk_px,
-                        float* part, float* out, hipStream_t s);
-hipError_t launch_bias_grad(const uint16_t* dy, const float* dy32, int cs, int co, int npix, int c, int chunk_px,
-                            float* part, float* db, hipStream_t s);
+                        float* part, float* out, float* bpart, float* bias_out, hipStream_t s);
+
 hipError_t launch_relu_mask(uint16_t* dy, int dcs, int dco, const uint16_t* y, int ycs, int yco, int npix, int c,
                             hipStream_t s);
 hipError_t launch_avgpool(const uint16_t* x, int xcs, int xco, uint16_t* y, int n_img, int h, int w, int c,

@@ -103,19 +103,53 @@ __device__ __forceinline__ Frag gather_a(const ConvArgs& a, int img, int y, int 
 constexpr int kConvKC = 256;           // K-chunk of staged weights
 constexpr int kConvLd = kConvKC + 8;   // LDS row pitch (bf16), 16 B of padding
 
-template <int MODE, int RT>
+// Workgroups are handed to the 8 XCDs round robin; renumber the pixel tiles
+// so that each XCD walks one contiguous band of them and the rows above and
+// below a tile (the 3x3 taps) sit in the same L2.  A bijection on
+// [0, 8 floor(G/8)), the identity on the tail.
+__device__ __forceinline__ int xcd_band(int b, int G)
+{
+    const int per = G >> 3;
+    if (b >= per * 8) return b;
+    return (b & 7) * per + (b >> 3);
+}
+
+// The A operand when every 32-wide K-step lies inside one tap (C_in a
+// multiple of 32, 16-byte aligned channel slices): the tap, its offset and the
+// channel base are uniform over the wave, so a lane only adds its own pixel's
+// base address and checks its row / column.
+template <int MODE>
+__device__ __forceinline__ Frag gather_fast(const ConvArgs& a, const uint16_t* base, int y, int x, bool v, int k)
+{
+    Frag f = zero_frag();
+    if (MODE == kConv3) {
+        const int tap = k / a.cin, c0 = k - tap * a.cin;
+        const int dy = tap / 3 - 1, dx = tap - (tap / 3) * 3 - 1;
+        if (v && tap < 9 && (unsigned)(y + dy) < (unsigned)a.h && (unsigned)(x + dx) < (unsigned)a.w)
+            f.u = *reinterpret_cast<const uint4*>(base + ((long)dy * a.w + dx) * a.x_cs + c0);
+    } else {  // kPoint, kUp
+        if (v && k < a.cin) f.u = *reinterpret_cast<const uint4*>(base + k);
+    }
+    return f;
+}
+
+template <int MODE, int RT, int NT>
 __global__ __launch_bounds__(256) void k_conv(ConvArgs a)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t wlds[64 * kConvLd];
+    constexpr int BN = 16 * NT;  // output channels per block
+    __shared__ __attribute__((aligned(16))) uint16_t wlds[BN * kConvLd];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int hw = a.h * a.w, npix = a.n_img * hw;
-    const int p0 = (blockIdx.x * 4 + wave) * (16 * RT);
-    const int n0 = blockIdx.y * 64;
+    const int tile = xcd_band((int)blockIdx.x, (int)gridDim.x);
+    const int p0 = (tile * 4 + wave) * (16 * RT);
+    const int n0 = blockIdx.y * BN;
     const int q = MODE == kUp ? (int)blockIdx.z : 0;
     const uint16_t* wq = a.wt + (size_t)q * a.n_pad * a.k_pad;
     const int mrow = lane & 15, kq = (lane >> 4) * 8;
+    const bool fast = MODE != kUpBack && a.cin % 32 == 0 && a.x_cs % 8 == 0 && a.x_co % 8 == 0;
     int ia[RT], ya[RT], xa[RT];
     bool va[RT];
+    const uint16_t* base[RT];
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
         const int p = p0 + 16 * i + mrow;
@@ -124,42 +158,52 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a)
         const int r = p - ia[i] * hw;
         ya[i] = r / a.w;
         xa[i] = r - ya[i] * a.w;
+        base[i] = a.x + (size_t)(va[i] ? p : 0) * a.x_cs + a.x_co + kq;
     }
-    floatx4 acc[RT][4];
+    auto gather = [&](int i, int k) -> Frag {
+        if (fast) return gather_fast<MODE == kUpBack ? kPoint : MODE>(a, base[i], ya[i], xa[i], va[i], k);
+        return (va[i] && k < a.k_pad) ? gather_a<MODE>(a, ia[i], ya[i], xa[i], k + kq) : zero_frag();
+    };
+    floatx4 acc[RT][NT];
 #pragma unroll
     for (int i = 0; i < RT; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-    Frag fa[RT];
+        for (int j = 0; j < NT; ++j) acc[i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    // A operand two K-steps ahead of its use: fa (this step), f1 (the next)
+    Frag fa[RT], f1[RT];
 #pragma unroll
-    for (int i = 0; i < RT; ++i) fa[i] = va[i] ? gather_a<MODE>(a, ia[i], ya[i], xa[i], kq) : zero_frag();
+    for (int i = 0; i < RT; ++i) {
+        fa[i] = gather(i, 0);
+        f1[i] = gather(i, 32);
+    }
     for (int kc = 0; kc < a.k_pad; kc += kConvKC) {
         const int kn = min(kConvKC, a.k_pad - kc);  // a multiple of 64
         __syncthreads();                             // the previous chunk is consumed
         const int per_row = kn / 8;
-        for (int idx = threadIdx.x; idx < 64 * per_row; idx += 256) {
+        for (int idx = threadIdx.x; idx < BN * per_row; idx += 256) {
             const int row = idx / per_row, c8 = idx - row * per_row;
             *reinterpret_cast<uint4*>(wlds + row * kConvLd + c8 * 8) =
                 *reinterpret_cast<const uint4*>(wq + (size_t)(n0 + row) * a.k_pad + kc + c8 * 8);
         }
         __syncthreads();
         for (int k0 = 0; k0 < kn; k0 += 32) {
-            const int kg = kc + k0 + 32;  // next K-step
             Frag fn[RT];
 #pragma unroll
-            for (int i = 0; i < RT; ++i)
-                fn[i] = (kg < a.k_pad && va[i]) ? gather_a<MODE>(a, ia[i], ya[i], xa[i], kg + kq) : zero_frag();
-            Frag fb[4];
+            for (int i = 0; i < RT; ++i) fn[i] = gather(i, kc + k0 + 64);  // two K-steps ahead
+            Frag fb[NT];
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < NT; ++j)
                 fb[j].u = *reinterpret_cast<const uint4*>(wlds + (16 * j + mrow) * kConvLd + k0 + kq);
 #pragma unroll
             for (int i = 0; i < RT; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
+                for (int j = 0; j < NT; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i].v, fb[j].v, acc[i][j], 0, 0, 0);
 #pragma unroll
-            for (int i = 0; i < RT; ++i) fa[i] = fn[i];
+            for (int i = 0; i < RT; ++i) {
+                fa[i] = f1[i];
+                f1[i] = fn[i];
+            }
         }
     }
     // epilogue: accumulator r of lane l, row tile i, column tile j is pixel
@@ -178,7 +222,7 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a)
                 pix = (size_t)p;
             }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < NT; ++j) {
                 const int n = n0 + 16 * j + mrow;
                 if (n >= a.cout) continue;
                 float v = acc[i][j][r] + (a.bias ? a.bias[n] : 0.0f);
@@ -191,30 +235,87 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a)
         }
 }
 
-template <int MODE>
+template <int MODE, int NT>
 static void conv_launch_rt(const ConvArgs& a, int rt, dim3 grid, hipStream_t s)
 {
     if (rt == 4)
-        hipLaunchKernelGGL((k_conv<MODE, 4>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_conv<MODE, 4, NT>), grid, dim3(256), 0, s, a);
     else if (rt == 2)
-        hipLaunchKernelGGL((k_conv<MODE, 2>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_conv<MODE, 2, NT>), grid, dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL((k_conv<MODE, 1>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_conv<MODE, 1, NT>), grid, dim3(256), 0, s, a);
+}
+
+template <int MODE>
+static void conv_launch(const ConvArgs& a, int rt, int nt, dim3 grid, hipStream_t s)
+{
+    if (nt == 2)
+        conv_launch_rt<MODE, 2>(a, rt, grid, s);
+    else
+        conv_launch_rt<MODE, 4>(a, rt, grid, s);
+}
+
+// A 3x3 convolution of a one-channel input (the first layer): K = 9 is too
+// thin for the matrix cores, so one thread per output pixel forms every
+// channel with fp32 products of the bf16 operands (exact) and fp32 sums.
+constexpr int kC1MaxOut = 64;
+
+__global__ __launch_bounds__(256) void k_conv3_c1(ConvArgs a)
+{
+    __shared__ float wt[kC1MaxOut * 9];
+    __shared__ float bs[kC1MaxOut];
+    for (int i = threadIdx.x; i < a.cout * 9; i += 256) wt[i] = bf2f(a.wt[(size_t)(i / 9) * a.k_pad + i % 9]);
+    for (int i = threadIdx.x; i < a.cout; i += 256) bs[i] = a.bias ? a.bias[i] : 0.0f;
+    __syncthreads();
+    const int hw = a.h * a.w, npix = a.n_img * hw;
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= npix) return;
+    const int img = p / hw, r = p - img * hw, y = r / a.w, x = r - y * a.w;
+    float v[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int ys = y + t / 3 - 1, xs = x + t % 3 - 1;
+        v[t] = ((unsigned)ys < (unsigned)a.h && (unsigned)xs < (unsigned)a.w)
+                   ? bf2f(a.x[(((size_t)img * a.h + ys) * a.w + xs) * a.x_cs + a.x_co])
+                   : 0.0f;
+    }
+    uint16_t* out = a.y + (size_t)p * a.y_cs + a.y_co;
+    for (int n0 = 0; n0 < a.cout; n0 += 8) {
+        Frag o;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int n = n0 + j;
+            float acc = 0.0f;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) acc += v[t] * wt[(n < a.cout ? n : 0) * 9 + t];
+            float val = acc + bs[n < a.cout ? n : 0];
+            if (a.relu) val = fmaxf(val, 0.0f);
+            o.h[j] = f2bf(val);
+        }
+        *reinterpret_cast<uint4*>(out + n0) = o.u;
+    }
 }
 
 hipError_t launch_conv(const ConvArgs& a, int mode, hipStream_t s)
 {
     const int npix = a.n_img * a.h * a.w;
-    const int cblk = a.n_pad / 64, par = mode == kUp ? 4 : 1;
+    if (mode == kConv3 && a.cin == 1 && !a.y32 && a.cout % 8 == 0 && a.cout <= kC1MaxOut && a.y_cs % 8 == 0 &&
+        a.y_co % 8 == 0) {
+        hipLaunchKernelGGL(k_conv3_c1, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
+    // 32 output channels or fewer: a 32-wide channel tile (no padded half)
+    const int nt = a.cout <= 32 ? 2 : 4;
+    const int cblk = (a.cout + 16 * nt - 1) / (16 * nt), par = mode == kUp ? 4 : 1;
     // the largest row-tile count that still gives about two blocks per CU
     int rt = 4;
     while (rt > 1 && (long long)((npix + 64 * rt - 1) / (64 * rt)) * cblk * par < 512) rt /= 2;
     dim3 grid((unsigned)((npix + 64 * rt - 1) / (64 * rt)), (unsigned)cblk, (unsigned)par);
     switch (mode) {
-    case kConv3: conv_launch_rt<kConv3>(a, rt, grid, s); break;
-    case kPoint: conv_launch_rt<kPoint>(a, rt, grid, s); break;
-    case kUp: conv_launch_rt<kUp>(a, rt, grid, s); break;
-    default: conv_launch_rt<kUpBack>(a, rt, grid, s); break;
+    case kConv3: conv_launch<kConv3>(a, rt, nt, grid, s); break;
+    case kPoint: conv_launch<kPoint>(a, rt, nt, grid, s); break;
+    case kUp: conv_launch<kUp>(a, rt, nt, grid, s); break;
+    default: conv_launch<kUpBack>(a, rt, nt, grid, s); break;
     }
     return hipGetLastError();
 }
@@ -231,7 +332,7 @@ constexpr int kWgLd = 72;  // LDS pitch in bf16 (64 pixels + 16 B)
 
 template <int MODE>
 __global__ __launch_bounds__(256) void k_wgrad(ConvArgs a, const uint16_t* __restrict__ dy, int dy_cs, int dy_co,
-                                               int chunk_px, float* part)
+                                               int chunk_px, float* part, float* bpart)
 {
     __shared__ __attribute__((aligned(16))) uint16_t t_dy[64 * kWgLd];
     __shared__ __attribute__((aligned(16))) uint16_t t_a[64 * kWgLd];
@@ -254,6 +355,11 @@ __global__ __launch_bounds__(256) void k_wgrad(ConvArgs a, const uint16_t* __res
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    // the bias gradient sum_p dY[p][n] rides along in the first k block of
+    // each parity: thread t sums channel t % 64 over pixels 16 (t / 64) .. +15
+    // of every staged step
+    const bool do_bias = bpart && kb == 0;
+    float bsum = 0.0f;
     for (int ps = p_beg; ps < p_end; ps += 64) {
         Frag v[4];
 #pragma unroll
@@ -287,6 +393,15 @@ __global__ __launch_bounds__(256) void k_wgrad(ConvArgs a, const uint16_t* __res
             *reinterpret_cast<uint2*>(dst + (lc + i) * kWgLd + lg * 4) = w;
         }
         __syncthreads();
+        if (do_bias) {
+            Frag b0, b1;
+            b0.u = *reinterpret_cast<const uint4*>(t_dy + (threadIdx.x & 63) * kWgLd + (threadIdx.x >> 6) * 16);
+            b1.u = *reinterpret_cast<const uint4*>(t_dy + (threadIdx.x & 63) * kWgLd + (threadIdx.x >> 6) * 16 + 8);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) bsum += bf2f(b0.h[i]);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) bsum += bf2f(b1.h[i]);
+        }
 #pragma unroll
         for (int s2 = 0; s2 < 64; s2 += 32) {
             Frag fa[2], fb[2];
@@ -314,13 +429,26 @@ __global__ __launch_bounds__(256) void k_wgrad(ConvArgs a, const uint16_t* __res
                 const int n = n0 + 32 * wn + 16 * i + (lane >> 4) * 4 + r, k = k0 + 32 * wk + 16 * j + row;
                 part[((size_t)chunk * a.n_pad + n) * kw + k] = acc[i][j][r];
             }
+    if (do_bias) {
+        __syncthreads();  // every wave is done with the tiles
+        float* red = reinterpret_cast<float*>(t_a);
+        red[threadIdx.x] = bsum;
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            const int t = threadIdx.x;
+            const float v = (red[t] + red[64 + t]) + (red[128 + t] + red[192 + t]);
+            const int nq = MODE == kUp ? 4 : 1;
+            bpart[((size_t)chunk * nq + q) * a.n_pad + n0 + t] = v;
+        }
+    }
 }
 
-__global__ void k_wgrad_reduce(const float* __restrict__ part, int chunks, size_t per, float* out)
+// out[i] = sum over c < chunks of part[c * stride + i], i < count, chunks in order
+__global__ void k_wgrad_reduce(const float* __restrict__ part, int chunks, size_t stride, size_t count, float* out)
 {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < per; i += (size_t)gridDim.x * blockDim.x) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
         float s = 0.0f;
-        for (int c = 0; c < chunks; ++c) s += part[(size_t)c * per + i];
+        for (int c = 0; c < chunks; ++c) s += part[(size_t)c * stride + i];
         out[i] = s;
     }
 }
@@ -332,64 +460,38 @@ int wgrad_chunks(const ConvArgs& a, int chunk_px)
 }
 
 hipError_t launch_wgrad(const ConvArgs& a, int mode, const uint16_t* dy, int dy_cs, int dy_co, int chunk_px,
-                        float* part, float* out, hipStream_t s)
+                        float* part, float* out, float* bpart, float* bias_out, hipStream_t s)
 {
     const int chunks = wgrad_chunks(a, chunk_px);
     const int kw = mode == kUp ? 4 * a.k_pad : a.k_pad;
+    float* bp = bias_out ? bpart : nullptr;
     dim3 grid((unsigned)chunks, (unsigned)(a.n_pad / 64), (unsigned)(kw / 64));
     switch (mode) {
     case kConv3:
-        hipLaunchKernelGGL(k_wgrad<kConv3>, grid, dim3(256), 0, s, a, dy, dy_cs, dy_co, chunk_px, part);
+        hipLaunchKernelGGL(k_wgrad<kConv3>, grid, dim3(256), 0, s, a, dy, dy_cs, dy_co, chunk_px, part, bp);
         break;
     case kPoint:
-        hipLaunchKernelGGL(k_wgrad<kPoint>, grid, dim3(256), 0, s, a, dy, dy_cs, dy_co, chunk_px, part);
+        hipLaunchKernelGGL(k_wgrad<kPoint>, grid, dim3(256), 0, s, a, dy, dy_cs, dy_co, chunk_px, part, bp);
         break;
-    case kUp: hipLaunchKernelGGL(k_wgrad<kUp>, grid, dim3(256), 0, s, a, dy, dy_cs, dy_co, chunk_px, part); break;
+    case kUp:
+        hipLaunchKernelGGL(k_wgrad<kUp>, grid, dim3(256), 0, s, a, dy, dy_cs, dy_co, chunk_px, part, bp);
+        break;
     default:
-        hipLaunchKernelGGL(k_wgrad<kUpBack>, grid, dim3(256), 0, s, a, dy, dy_cs, dy_co, chunk_px, part);
+        hipLaunchKernelGGL(k_wgrad<kUpBack>, grid, dim3(256), 0, s, a, dy, dy_cs, dy_co, chunk_px, part, bp);
         break;
     }
     const size_t per = (size_t)a.n_pad * kw;
     hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)std::min<size_t>((per + 255) / 256, 4096)), dim3(256), 0, s,
-                       part, chunks, per, out);
+                       part, chunks, per, per, out);
+    if (bias_out) {
+        const int nq = mode == kUp ? 4 : 1;
+        hipLaunchKernelGGL(k_wgrad_reduce, dim3(1), dim3(256), 0, s, bpart, chunks * nq, (size_t)a.n_pad,
+                           (size_t)a.cout, bias_out);
+    }
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ elementwise
-// bias gradient: db[n] = sum over pixels of dy[p][n].  Block b sums the
-// pixels of chunk b for every channel (64 consecutive channels per wave row,
-// so each pixel's channels are read as one contiguous run) into
-// part[b][n]; k_wgrad_reduce then adds the chunks in order (deterministic).
-__global__ __launch_bounds__(256) void k_bias_part(const uint16_t* __restrict__ dy, int cs, int co, int npix, int c,
-                                                   const float* dy32, int chunk_px, float* part)
-{
-    __shared__ float red[4][64];
-    const int lane = threadIdx.x & 63, ph = threadIdx.x >> 6;
-    const int p_beg = blockIdx.x * chunk_px, p_end = min(npix, p_beg + chunk_px);
-    for (int c0 = 0; c0 < c; c0 += 64) {
-        const int n = c0 + lane;
-        float s = 0.0f;
-        if (n < c)
-            for (int p = p_beg + ph; p < p_end; p += 4)
-                s += dy32 ? dy32[(size_t)p * cs + co + n] : bf2f(dy[(size_t)p * cs + co + n]);
-        red[ph][lane] = s;
-        __syncthreads();
-        if (ph == 0 && n < c) part[(size_t)blockIdx.x * c + n] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
-        __syncthreads();
-    }
-}
-
-hipError_t launch_bias_grad(const uint16_t* dy, const float* dy32, int cs, int co, int npix, int c, int chunk_px,
-                            float* part, float* db, hipStream_t s)
-{
-    const int chunks = (npix + chunk_px - 1) / chunk_px;
-    hipLaunchKernelGGL(k_bias_part, dim3((unsigned)chunks), dim3(256), 0, s, dy, cs, co, npix, c, dy32, chunk_px,
-                       part);
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)std::min((c + 255) / 256, 4096)), dim3(256), 0, s, part, chunks,
-                       (size_t)c, db);
-    return hipGetLastError();
-}
-
 // dy *= (y > 0): the ReLU's backward, in place on a channel slice
 __global__ void k_relu_mask(uint16_t* dy, int dcs, int dco, const uint16_t* y, int ycs, int yco, int npix, int c)
 {

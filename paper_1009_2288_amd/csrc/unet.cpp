@@ -59,6 +59,7 @@ struct eptv_unet_s {
     eptv::Tensor g_bout;
     float* part = nullptr;                            // weight-gradient partials
     size_t part_floats = 0;
+    float* bpart = nullptr;                           // bias-gradient partials
     double* mse_part = nullptr;
     std::vector<void*> allocs;
 };
@@ -162,19 +163,17 @@ static hipError_t forward(eptv_unet_s& u, const float* x, int n, float* y, hipSt
 // weight and bias gradients of layer li from its input x (slice) and its
 // output gradient dy (slice, already masked by the ReLU)
 static hipError_t layer_grads(eptv_unet_s& u, int li, int n, int h, int w, const uint16_t* xp, int xcs, int xco,
-                              const uint16_t* dy, int dycs, int dyco, const float* dy32, hipStream_t s)
+                              const uint16_t* dy, int dycs, int dyco, hipStream_t s)
 {
     Layer& Ly = u.layers[li];
     ConvArgs a = conv_args(u, Ly, n, h, w, false);
     a.x = xp;
     a.x_cs = xcs;
     a.x_co = xco;
-    hipError_t e = launch_wgrad(a, Ly.mode, dy, dycs, dyco, kChunkPx, u.part, Ly.gpack, s);
+    hipError_t e = launch_wgrad(a, Ly.mode, dy, dycs, dyco, kChunkPx, u.part, Ly.gpack, u.bpart,
+                                u.grads + Ly.b_off, s);
     if (e != hipSuccess) return e;
-    e = launch_unpack_grad(Ly.gpack, Ly.mode, Ly.ci, Ly.co, Ly.n_pad, Ly.k_pad, u.grads + Ly.w_off, s);
-    if (e != hipSuccess) return e;
-    const int oh = Ly.mode == kUp ? 2 * h : h, ow = Ly.mode == kUp ? 2 * w : w;
-    return launch_bias_grad(dy, dy32, dycs, dyco, n * oh * ow, Ly.co, kChunkPx, u.part, u.grads + Ly.b_off, s);
+    return launch_unpack_grad(Ly.gpack, Ly.mode, Ly.ci, Ly.co, Ly.n_pad, Ly.k_pad, u.grads + Ly.w_off, s);
 }
 
 // backward data of layer li: gradient of its input from its output gradient
@@ -200,7 +199,7 @@ static hipError_t backward(eptv_unet_s& u, const float* dy, float* dx, hipStream
     const int hl = layer_index(u, 'h', 0, 0);
     const Tensor& last = L > 1 ? u.db[0] : u.bout;
     if ((e = launch_to_bf16(dy, u.g_head.p, (size_t)n * u.h * u.w * u.c_out, s)) != hipSuccess) return e;
-    if ((e = layer_grads(u, hl, n, u.h, u.w, last.p, last.c, 0, u.g_head.p, u.c_out, 0, dy, s)) != hipSuccess)
+    if ((e = layer_grads(u, hl, n, u.h, u.w, last.p, last.c, 0, u.g_head.p, u.c_out, 0, s)) != hipSuccess)
         return e;
     Tensor g_last = L > 1 ? u.g_db[0] : u.g_bout;
     if ((e = layer_back(u, hl, n, u.h, u.w, u.g_head.p, u.c_out, 0, g_last.p, g_last.c, 0, s)) != hipSuccess)
@@ -210,17 +209,17 @@ static hipError_t backward(eptv_unet_s& u, const float* dy, float* dx, hipStream
         const int h = u.h >> l, w = u.w >> l, C = u.base << l, np = n * h * w;
         const int lb = layer_index(u, 'd', l, 'b'), la = layer_index(u, 'd', l, 'a'), lu = layer_index(u, 'u', l, 0);
         if ((e = launch_relu_mask(u.g_db[l].p, C, 0, u.db[l].p, C, 0, np, C, s)) != hipSuccess) return e;
-        if ((e = layer_grads(u, lb, n, h, w, u.da[l].p, C, 0, u.g_db[l].p, C, 0, nullptr, s)) != hipSuccess) return e;
+        if ((e = layer_grads(u, lb, n, h, w, u.da[l].p, C, 0, u.g_db[l].p, C, 0, s)) != hipSuccess) return e;
         if ((e = layer_back(u, lb, n, h, w, u.g_db[l].p, C, 0, u.g_da[l].p, C, 0, s)) != hipSuccess) return e;
         if ((e = launch_relu_mask(u.g_da[l].p, C, 0, u.da[l].p, C, 0, np, C, s)) != hipSuccess) return e;
-        if ((e = layer_grads(u, la, n, h, w, u.cat[l].p, 2 * C, 0, u.g_da[l].p, C, 0, nullptr, s)) != hipSuccess)
+        if ((e = layer_grads(u, la, n, h, w, u.cat[l].p, 2 * C, 0, u.g_da[l].p, C, 0, s)) != hipSuccess)
             return e;
         if ((e = layer_back(u, la, n, h, w, u.g_da[l].p, C, 0, u.g_cat[l].p, 2 * C, 0, s)) != hipSuccess) return e;
         // the upsampled half: ReLU mask, then the transposed convolution
         if ((e = launch_relu_mask(u.g_cat[l].p, 2 * C, C, u.cat[l].p, 2 * C, C, np, C, s)) != hipSuccess) return e;
         const Tensor& up_in = l == L - 2 ? u.bout : u.db[l + 1];
         Tensor& g_up_in = l == L - 2 ? u.g_bout : u.g_db[l + 1];
-        if ((e = layer_grads(u, lu, n, h / 2, w / 2, up_in.p, up_in.c, 0, u.g_cat[l].p, 2 * C, C, nullptr, s)) !=
+        if ((e = layer_grads(u, lu, n, h / 2, w / 2, up_in.p, up_in.c, 0, u.g_cat[l].p, 2 * C, C, s)) !=
             hipSuccess)
             return e;
         if ((e = layer_back(u, lu, n, h / 2, w / 2, u.g_cat[l].p, 2 * C, C, g_up_in.p, g_up_in.c, 0, s)) != hipSuccess)
@@ -239,11 +238,11 @@ static hipError_t backward(eptv_unet_s& u, const float* dy, float* dx, hipStream
                 return e;
         }
         if ((e = launch_relu_mask(gout.p, gout.c, 0, out.p, out.c, 0, np, C, s)) != hipSuccess) return e;
-        if ((e = layer_grads(u, lb, n, h, w, u.a[l].p, C, 0, gout.p, gout.c, 0, nullptr, s)) != hipSuccess) return e;
+        if ((e = layer_grads(u, lb, n, h, w, u.a[l].p, C, 0, gout.p, gout.c, 0, s)) != hipSuccess) return e;
         if ((e = layer_back(u, lb, n, h, w, gout.p, gout.c, 0, u.g_a[l].p, C, 0, s)) != hipSuccess) return e;
         if ((e = launch_relu_mask(u.g_a[l].p, C, 0, u.a[l].p, C, 0, np, C, s)) != hipSuccess) return e;
         const Tensor& inp = l == 0 ? u.xin : u.in[l];
-        if ((e = layer_grads(u, la, n, h, w, inp.p, inp.c, 0, u.g_a[l].p, C, 0, nullptr, s)) != hipSuccess) return e;
+        if ((e = layer_grads(u, la, n, h, w, inp.p, inp.c, 0, u.g_a[l].p, C, 0, s)) != hipSuccess) return e;
         if (l > 0) {
             if ((e = layer_back(u, la, n, h, w, u.g_a[l].p, C, 0, u.g_in[l].p, u.g_in[l].c, 0, s)) != hipSuccess)
                 return e;
@@ -340,7 +339,7 @@ int eptv_unet_create(int c_in, int c_out, int base, int levels, int max_batch, i
     hipError_t e = hipSuccess;
     for (float** p : {&u->params, &u->grads, &u->adam_m, &u->adam_v})
         if (e == hipSuccess) e = dalloc(*u, p, u->n_params);
-    size_t part = 0;
+    size_t part = 0, bpart = 0;
     for (Layer& Ly : u->layers) {
         const int q = Ly.mode == kUp ? 4 : 1;
         if (e == hipSuccess) e = dalloc(*u, &Ly.wf, (size_t)q * Ly.n_pad * Ly.k_pad);
@@ -388,12 +387,11 @@ int eptv_unet_create(int c_in, int c_out, int base, int levels, int max_batch, i
         const size_t npix = B * (height >> Ly.lev) * (width >> Ly.lev);
         const size_t chunks = (npix + kChunkPx - 1) / kChunkPx;
         part = std::max(part, chunks * Ly.n_pad * (Ly.mode == kUp ? 4 : 1) * Ly.k_pad);
-        // bias partials run over the layer's output pixels (4x the GEMM grid for kUp)
-        const size_t out_px = Ly.mode == kUp ? 4 * npix : npix;
-        part = std::max(part, (out_px + kChunkPx - 1) / kChunkPx * (size_t)Ly.co);
+        bpart = std::max(bpart, chunks * (Ly.mode == kUp ? 4 : 1) * Ly.n_pad);  // one row per chunk and parity
     }
     u->part_floats = part;
     if (e == hipSuccess) e = dalloc(*u, &u->part, part);
+    if (e == hipSuccess) e = dalloc(*u, &u->bpart, bpart);
     if (e == hipSuccess) e = dalloc(*u, &u->mse_part, (size_t)kMseBlocks);
     if (e != hipSuccess) {
         const int rc = hip_fail(e, "eptv_unet_create");
