@@ -149,6 +149,38 @@ def time_to_rmse(E, synth, P, torch, np, seeds):
     return out
 
 
+def unet_training_leg(torch, np, steps, batch=8):
+    """Training throughput of the EPTV-assist U-Net (4 levels, base 32, 512^2)
+    on the library's kernels: forward, MSE, backward, Adam per step, batch 8;
+    inputs are random (the kernels' work does not depend on the values)."""
+    from paper_1009_2288_amd import cnn_assist as A
+    net = A.network(max_batch=batch)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    x = torch.randn((batch, 512, 512, 1), generator=g, device="cuda")
+    t = torch.randn((batch, 512, 512, 3), generator=g, device="cuda")
+
+    def step(i):
+        y = net.forward(x)
+        _, dy = net.mse(y, t)
+        net.backward(dy)
+        net.adam(1e-4, i + 1)
+
+    step(0)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    for i in range(steps):
+        step(i + 1)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    fl = 3.0 * A.forward_flops(512, 512) * batch  # forward + data gradient + weight gradient
+    return {"batch": batch, "steps": steps, "ms_per_step": ms, "images_per_s": batch * 1e3 / ms,
+            "algorithmic_tflops": fl / ms / 1e9, "mfma_bf16_peak_frac": fl / (ms * 1e-3) / BF16_MFMA_PEAK}
+
+
 def batch_leg(E, synth, torch, np, n_slices, iters, warmup):
     """The batched workload: n_slices slices of 256^2 / 384^2 / 512^2, 20-60
     views, 368-736 bins, I0 1e4-1e5 (seed 0), every phase one launch over all
@@ -189,6 +221,8 @@ def main():
     ap.add_argument("--rmse-seeds", type=int, default=10, help="seeds for the time-to-RMSE leg (0 to skip)")
     ap.add_argument("--batch-slices", type=int, default=64, help="slices of the batched leg (0 to skip)")
     ap.add_argument("--batch-iters", type=int, default=20)
+    ap.add_argument("--unet-train-steps", type=int, default=10,
+                    help="timed training steps of the EPTV-assist U-Net (0 to skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="finally copy a buffer of this many MiB on the device (a plain copy kernel of known "
                          "size, to calibrate hardware byte counters against)")
@@ -290,6 +324,13 @@ def main():
         log(f"bench: batch {bat['ms_per_batch_iteration']:.3f} ms per iteration of all slices, "
             f"{bat['equivalent_512x512x40_iterations_per_s']:.1f} equivalent 512^2/40 it/s, launch {bat['launch']}")
 
+    cnn_train = None
+    if args.unet_train_steps > 0:
+        log(f"bench: U-Net training, {args.unet_train_steps} steps of batch 8")
+        cnn_train = unet_training_leg(torch, np, args.unet_train_steps)
+        log(f"bench: U-Net training {cnn_train['ms_per_step']:.2f} ms per step, "
+            f"{cnn_train['algorithmic_tflops']:.0f} TFLOP/s")
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"bench: CPU oracle baseline, {args.cpu_iters} iterations")
@@ -317,6 +358,7 @@ def main():
         "rmse_vs_phantom": rmse,
         "time_to_rmse": ttr,
         "batch": bat,
+        "cnn_training": cnn_train,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -35,6 +35,10 @@ inline int pad64(int n) { return (n + 63) / 64 * 64; }
 
 hipError_t launch_conv(const ConvArgs& a, int mode, hipStream_t s);
 int wgrad_chunks(const ConvArgs& a, int chunk_px);
+// pixels per weight-gradient chunk for a layer with npix GEMM pixels and an
+// n_pad x kw partial tile grid (also sizes the partial buffers)
+int wgrad_chunk_px(int npix, int n_pad, int kw);
+int wgrad_max_chunks(int npix, int n_pad, int kw);
 // dW (unpacked later) into out and, if bias_out is given, the bias gradient
 // sum_p dY[p][n] into bias_out[cout]; part and bpart are partial-sum scratch
 hipError_t launch_wgrad(const ConvArgs& a, int mode, const uint16_t* dy, int dy_cs, int dy_co, int chunk_px,

@@ -255,6 +255,104 @@ static void conv_launch(const ConvArgs& a, int rt, int nt, dim3 grid, hipStream_
         conv_launch_rt<MODE, 4>(a, rt, grid, s);
 }
 
+// ------------------------------------------------------------------ 3x3 convolutions from LDS tiles
+// The block's output is a TH x 32 rectangle of one image; per chunk of 32
+// input channels it stages the (TH + 2) x 34 input patch (zero outside the
+// image) and the 9 taps' weights of its output channels in LDS, then every
+// tap's A operand is an LDS read at a fixed offset from the lane's own pixel:
+// the 9-fold reuse of each input value comes from LDS, not from global
+// memory, and the inner loop is LDS reads and matrix instructions only.
+constexpr int kPatchW = 34;             // 32 columns + halo
+constexpr int kPatchPS = 40;            // bf16 per patch pixel (32 channels + 16 B)
+constexpr int kTapLd = 9 * 32 + 8;      // bf16 per weight row (9 taps x 32 channels + 16 B)
+
+template <int TH, int NT>
+__global__ __launch_bounds__(256) void k_conv3_tile(ConvArgs a)
+{
+    constexpr int BN = 16 * NT;       // output channels per block
+    constexpr int RPW = TH / 4;       // image rows per wave
+    constexpr int RT = 2 * RPW;       // 16-pixel row tiles per wave
+    __shared__ __attribute__((aligned(16))) uint16_t patch[(TH + 2) * kPatchW * kPatchPS];
+    __shared__ __attribute__((aligned(16))) uint16_t wts[BN * kTapLd];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tiles_x = (a.w + 31) / 32, tiles_y = (a.h + TH - 1) / TH;
+    int t = xcd_band((int)blockIdx.x, (int)gridDim.x);
+    const int img = t / (tiles_x * tiles_y);
+    t -= img * tiles_x * tiles_y;
+    const int ty = t / tiles_x, tx = t - ty * tiles_x;
+    const int y0 = ty * TH, x0 = tx * 32;
+    const int n0 = blockIdx.y * BN;
+    const int mrow = lane & 15, kq = (lane >> 4) * 8;
+    int lbase[RT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+        const int lr = wave * RPW + (i >> 1), lc = (i & 1) * 16 + mrow;
+        lbase[i] = ((lr + 1) * kPatchW + lc + 1) * kPatchPS + kq;
+    }
+    floatx4 acc[RT][NT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int c0 = 0; c0 < a.cin; c0 += 32) {
+        __syncthreads();  // the previous chunk is consumed
+        for (int idx = threadIdx.x; idx < (TH + 2) * kPatchW * 4; idx += 256) {
+            const int px = idx >> 2, part = idx & 3;
+            const int pr = px / kPatchW, pc = px - pr * kPatchW;
+            const int y = y0 - 1 + pr, x = x0 - 1 + pc;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if ((unsigned)y < (unsigned)a.h && (unsigned)x < (unsigned)a.w)
+                v = *reinterpret_cast<const uint4*>(a.x + (((size_t)img * a.h + y) * a.w + x) * a.x_cs + a.x_co +
+                                                    c0 + part * 8);
+            *reinterpret_cast<uint4*>(patch + px * kPatchPS + part * 8) = v;
+        }
+        for (int idx = threadIdx.x; idx < BN * 36; idx += 256) {
+            const int row = idx / 36, rem = idx - row * 36, tap = rem >> 2, part = rem & 3;
+            *reinterpret_cast<uint4*>(wts + row * kTapLd + tap * 32 + part * 8) = *reinterpret_cast<const uint4*>(
+                a.wt + (size_t)(n0 + row) * a.k_pad + tap * a.cin + c0 + part * 8);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int toff = ((tap / 3 - 1) * kPatchW + (tap % 3 - 1)) * kPatchPS;
+            Frag fb[NT];
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+                fb[j].u = *reinterpret_cast<const uint4*>(wts + (16 * j + mrow) * kTapLd + tap * 32 + kq);
+#pragma unroll
+            for (int i = 0; i < RT; ++i) {
+                Frag fa;
+                fa.u = *reinterpret_cast<const uint4*>(patch + lbase[i] + toff);
+#pragma unroll
+                for (int j = 0; j < NT; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa.v, fb[j].v, acc[i][j], 0, 0, 0);
+            }
+        }
+    }
+    // epilogue: accumulator r of lane l, row tile i, column tile j is the
+    // pixel at local row wave * RPW + i / 2, column (i % 2) * 16 + 4 (l / 16) + r,
+    // channel n0 + 16 j + l % 16
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int y = y0 + wave * RPW + (i >> 1), x = x0 + (i & 1) * 16 + (lane >> 4) * 4 + r;
+            if (y >= a.h || x >= a.w) continue;
+            const size_t pix = ((size_t)img * a.h + y) * a.w + x;
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const int n = n0 + 16 * j + mrow;
+                if (n >= a.cout) continue;
+                float v = acc[i][j][r] + (a.bias ? a.bias[n] : 0.0f);
+                if (a.relu) v = fmaxf(v, 0.0f);
+                if (a.y32)
+                    a.y32[pix * a.y_cs + a.y_co + n] = v;
+                else
+                    a.y[pix * a.y_cs + a.y_co + n] = f2bf(v);
+            }
+        }
+}
+
 // A 3x3 convolution of a one-channel input (the first layer): K = 9 is too
 // thin for the matrix cores, so one thread per output pixel forms every
 // channel with fp32 products of the bf16 operands (exact) and fp32 sums.
@@ -306,6 +404,26 @@ hipError_t launch_conv(const ConvArgs& a, int mode, hipStream_t s)
     }
     // 32 output channels or fewer: a 32-wide channel tile (no padded half)
     const int nt = a.cout <= 32 ? 2 : 4;
+    if (mode == kConv3 && a.cin % 32 == 0 && a.x_cs % 8 == 0 && a.x_co % 8 == 0) {
+        // tile shape: the largest that still gives enough blocks (8 rows and
+        // 64 channels preferred; smaller layers fall back to 4 rows, then to
+        // 32-channel tiles)
+        const long long t8 = (long long)a.n_img * ((a.h + 7) / 8) * ((a.w + 31) / 32);
+        const long long t4 = (long long)a.n_img * ((a.h + 3) / 4) * ((a.w + 31) / 32);
+        const long long c4 = (a.cout + 63) / 64, c2 = (a.cout + 31) / 32;
+        int th = 0, tn = 0;
+        if (t8 * (nt == 4 ? c4 : c2) >= 512) th = 8, tn = nt;
+        else if (t4 * (nt == 4 ? c4 : c2) >= 256) th = 4, tn = nt;
+        else if (t4 * c2 >= 256) th = 4, tn = 2;
+        if (th) {
+            dim3 g((unsigned)(th == 8 ? t8 : t4), (unsigned)(tn == 4 ? c4 : c2));
+            if (th == 8 && tn == 4) hipLaunchKernelGGL((k_conv3_tile<8, 4>), g, dim3(256), 0, s, a);
+            else if (th == 8) hipLaunchKernelGGL((k_conv3_tile<8, 2>), g, dim3(256), 0, s, a);
+            else if (tn == 4) hipLaunchKernelGGL((k_conv3_tile<4, 4>), g, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((k_conv3_tile<4, 2>), g, dim3(256), 0, s, a);
+            return hipGetLastError();
+        }
+    }
     const int cblk = (a.cout + 16 * nt - 1) / (16 * nt), par = mode == kUp ? 4 : 1;
     // the largest row-tile count that still gives about two blocks per CU
     int rt = 4;
@@ -448,7 +566,15 @@ __global__ void k_wgrad_reduce(const float* __restrict__ part, int chunks, size_
 {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
         float s = 0.0f;
-        for (int c = 0; c < chunks; ++c) s += part[(size_t)c * stride + i];
+        int c = 0;
+        for (; c + 8 <= chunks; c += 8) {  // 8 loads in flight, added in chunk order
+            float v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = part[(size_t)(c + j) * stride + i];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s += v[j];
+        }
+        for (; c < chunks; ++c) s += part[(size_t)c * stride + i];
         out[i] = s;
     }
 }
@@ -457,6 +583,22 @@ int wgrad_chunks(const ConvArgs& a, int chunk_px)
 {
     const int npix = a.n_img * a.h * a.w;
     return (npix + chunk_px - 1) / chunk_px;
+}
+
+int wgrad_max_chunks(int npix, int n_pad, int kw)
+{
+    // about 1024 blocks in all (4 per CU), but no chunk under 1024 pixels;
+    // fewer chunks also keep the ordered chunk sum short.  Non-decreasing in
+    // npix, so the largest batch bounds every smaller one.
+    const int per_chunk = (n_pad / 64) * (kw / 64);
+    return std::max(1, std::min((1024 + per_chunk - 1) / per_chunk, (npix + 1023) / 1024));
+}
+
+int wgrad_chunk_px(int npix, int n_pad, int kw)
+{
+    const int chunks = wgrad_max_chunks(npix, n_pad, kw);
+    const int px = (npix + chunks - 1) / chunks;
+    return (px + 63) / 64 * 64;  // ceil(npix / px) <= chunks
 }
 
 hipError_t launch_wgrad(const ConvArgs& a, int mode, const uint16_t* dy, int dy_cs, int dy_co, int chunk_px,
@@ -502,9 +644,32 @@ __global__ void k_relu_mask(uint16_t* dy, int dcs, int dco, const uint16_t* y, i
     }
 }
 
+// the same, 8 channels (16 bytes) per thread for 16-byte aligned slices
+__global__ void k_relu_mask8(uint16_t* dy, int dcs, int dco, const uint16_t* y, int ycs, int yco, int npix, int c8)
+{
+    const size_t n = (size_t)npix * c8;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t p = i / c8, k = (i - p * c8) * 8;
+        Frag yv, dv;
+        yv.u = *reinterpret_cast<const uint4*>(y + p * ycs + yco + k);
+        uint4* dp = reinterpret_cast<uint4*>(dy + p * dcs + dco + k);
+        dv.u = *dp;
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+            if (!(bf2f(yv.h[j]) > 0.0f)) dv.h[j] = 0;
+        *dp = dv.u;
+    }
+}
+
 hipError_t launch_relu_mask(uint16_t* dy, int dcs, int dco, const uint16_t* y, int ycs, int yco, int npix, int c,
                             hipStream_t s)
 {
+    if (c % 8 == 0 && dcs % 8 == 0 && dco % 8 == 0 && ycs % 8 == 0 && yco % 8 == 0) {
+        const size_t n = (size_t)npix * (c / 8);
+        hipLaunchKernelGGL(k_relu_mask8, dim3((unsigned)std::min<size_t>((n + 255) / 256, 8192)), dim3(256), 0, s,
+                           dy, dcs, dco, y, ycs, yco, npix, c / 8);
+        return hipGetLastError();
+    }
     const size_t n = (size_t)npix * c;
     hipLaunchKernelGGL(k_relu_mask, dim3((unsigned)std::min<size_t>((n + 255) / 256, 8192)), dim3(256), 0, s, dy, dcs,
                        dco, y, ycs, yco, npix, c);

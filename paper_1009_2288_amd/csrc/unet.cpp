@@ -66,7 +66,6 @@ struct eptv_unet_s {
 
 namespace eptv {
 
-static constexpr int kChunkPx = 4096;  // pixels per weight-gradient partial
 static constexpr int kMseBlocks = 1024;
 
 static int layer_index(const eptv_unet_s& u, const char kind, int level, char sub)
@@ -170,7 +169,8 @@ static hipError_t layer_grads(eptv_unet_s& u, int li, int n, int h, int w, const
     a.x = xp;
     a.x_cs = xcs;
     a.x_co = xco;
-    hipError_t e = launch_wgrad(a, Ly.mode, dy, dycs, dyco, kChunkPx, u.part, Ly.gpack, u.bpart,
+    const int cpx = wgrad_chunk_px(n * h * w, Ly.n_pad, (Ly.mode == kUp ? 4 : 1) * Ly.k_pad);
+    hipError_t e = launch_wgrad(a, Ly.mode, dy, dycs, dyco, cpx, u.part, Ly.gpack, u.bpart,
                                 u.grads + Ly.b_off, s);
     if (e != hipSuccess) return e;
     return launch_unpack_grad(Ly.gpack, Ly.mode, Ly.ci, Ly.co, Ly.n_pad, Ly.k_pad, u.grads + Ly.w_off, s);
@@ -385,7 +385,7 @@ int eptv_unet_create(int c_in, int c_out, int base, int levels, int max_batch, i
     // weight-gradient partials: the largest layer
     for (const Layer& Ly : u->layers) {
         const size_t npix = B * (height >> Ly.lev) * (width >> Ly.lev);
-        const size_t chunks = (npix + kChunkPx - 1) / kChunkPx;
+        const size_t chunks = wgrad_max_chunks((int)npix, Ly.n_pad, (Ly.mode == kUp ? 4 : 1) * Ly.k_pad);
         part = std::max(part, chunks * Ly.n_pad * (Ly.mode == kUp ? 4 : 1) * Ly.k_pad);
         bpart = std::max(bpart, chunks * (Ly.mode == kUp ? 4 : 1) * Ly.n_pad);  // one row per chunk and parity
     }
