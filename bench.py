@@ -47,6 +47,29 @@ PMC_TRAFFIC = {
 }
 
 
+# Vector-ALU activity of the operator kernels on this workload from a
+# rocprofv3 --pmc pass (VALUBusy, SQ_INSTS_VALU); see
+# profiles/eptv_and_unet_valu_mfma_pmc.md.  Reported only while the kernel
+# source's hash matches.
+PMC_VALU = {
+    "project": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "7012b6bc1a09b6fc",
+                "valu_busy": 0.300, "valu_wave_instructions": 7.31e6},
+    "backproject": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "7012b6bc1a09b6fc",
+                    "valu_busy": 0.482, "valu_wave_instructions": 11.52e6},
+}
+
+
+def pmc_valu(kernel, nnz):
+    import hashlib
+    e = PMC_VALU.get(kernel)
+    if e is None:
+        return None
+    with open(os.path.join(ROOT, e["source"]), "rb") as fh:
+        if hashlib.sha256(fh.read()).hexdigest()[:16] != e["sha256_16"]:
+            return None
+    return {"valu_busy": e["valu_busy"], "valu_instructions_per_nnz": e["valu_wave_instructions"] * 64 / nnz}
+
+
 def pmc_traffic(kernel):
     import hashlib
     e = PMC_TRAFFIC.get(kernel)
@@ -306,7 +329,8 @@ def main():
         achieved = flops / (t_dom * 1e-3)
         roof = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK, "traffic": pmc_traffic(dom),
-                "avg_ms": t_dom, "algorithmic_flops_per_launch": flops, "nnz": nnz}
+                "avg_ms": t_dom, "algorithmic_flops_per_launch": flops, "nnz": nnz,
+                "pmc_valu": pmc_valu(dom, nnz)}
     roof["operators_avg_ms"] = op_ms
     log("bench: " + ", ".join(f"{k} {v * 1e3:.1f} us" for k, v in op_ms.items()) + f", nnz {nnz}")
 
