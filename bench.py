@@ -120,7 +120,7 @@ def time_to_rmse(E, synth, P, torch, np, seeds):
     after 100 iterations (tests/golden/rmse_targets_paper.json), the
     device-side RMSE record included in the timed run; median over seeds.
     Plain EPTV from zero, and (when the trained network is present) the
-    CNN-assisted pipeline: 3 plain iterations, the U-Net's proposal of image
+    CNN-assisted pipeline: plain iterations (1), the U-Net's proposal of image
     and edge weights, EPTV warm-started from it with the weights frozen for
     its first iteration."""
     from paper_1009_2288_amd import cnn_assist as A

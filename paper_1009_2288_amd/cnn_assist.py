@@ -35,12 +35,17 @@ from . import eptv as E
 from . import synth
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-WEIGHTS = os.path.join(HERE, "weights", "eptv_unet_512_n3_k30.npz")
-
 IN_SCALE = 50.0      # attenuation (mm^-1) of the input image to unit order
 RES_SCALE = 1000.0   # the image change f^(k_t) - f^(n0) to unit order
-N0 = 3               # plain iterations before the network
+N0 = 1               # plain iterations before the network
 K_T = 30             # plain iterations behind the targets
+
+
+def weights_path(n0: int = None, k_t: int = K_T) -> str:
+    return os.path.join(HERE, "weights", f"eptv_unet_512_n{N0 if n0 is None else n0}_k{k_t}.npz")
+
+
+WEIGHTS = weights_path()
 NET = dict(c_in=1, c_out=3, base=32, levels=4)
 SOLVER = dict(cgls_iters=3, tv_iters=5, lam=1000.0, edge_quantile=0.9, tv_eps=1e-4)
 
@@ -195,7 +200,7 @@ def make_pairs(cases, n0: int = N0, k_t: int = K_T, solver: Optional[dict] = Non
 
 @dataclass
 class TrainConfig:
-    epochs: int = 12
+    epochs: int = 10
     batch: int = 8
     lr: float = 1e-3
     lr_final: float = 2e-5
@@ -278,7 +283,7 @@ def assisted_reconstruct(P: E.Plan, net: E.UNet, y: torch.Tensor, outer_iters: i
 
 
 def time_to_rmse(P: E.Plan, y: torch.Tensor, ref: torch.Tensor, target: float, net: Optional[E.UNet] = None,
-                 frozen_iters: int = 1, max_iters: int = 100, reps: int = 3):
+                 frozen_iters: int = 1, max_iters: int = 100, reps: int = 3, n0: int = N0):
     """Seconds (best of ``reps``, HIP events on the current stream) until the
     RMSE to ``ref`` is <= target: plain EPTV from zero, or (with ``net``) the
     assisted pipeline.  The iteration count comes from an untimed run with
@@ -286,7 +291,7 @@ def time_to_rmse(P: E.Plan, y: torch.Tensor, ref: torch.Tensor, target: float, n
     if net is None:
         _, st = P.reconstruct(y, E.Params(outer_iters=max_iters, zero_init=1, **SOLVER), f_ref=ref)
     else:
-        _, st = assisted_reconstruct(P, net, y, max_iters, frozen_iters, f_ref=ref)
+        _, st = assisted_reconstruct(P, net, y, max_iters, frozen_iters, n0=n0, f_ref=ref)
     hit = np.nonzero(st["rmse"] <= target)[0]
     if hit.size == 0:
         return {"iterations": None, "seconds": None, "rmse_min": float(st["rmse"].min())}
@@ -300,7 +305,7 @@ def time_to_rmse(P: E.Plan, y: torch.Tensor, ref: torch.Tensor, target: float, n
         if net is None:
             f, _ = P.reconstruct(y, E.Params(outer_iters=k, zero_init=1, **SOLVER), f_ref=ref, stats=False)
         else:
-            f, _ = assisted_reconstruct(P, net, y, k, frozen_iters, f_ref=ref, stats=False)
+            f, _ = assisted_reconstruct(P, net, y, k, frozen_iters, n0=n0, f_ref=ref, stats=False)
         e1.record(s)
         torch.cuda.synchronize()
         sec = e0.elapsed_time(e1) / 1e3

@@ -63,7 +63,7 @@ def oracle_params(A, flat):
 
 def test_trained_network_full_size_matches_oracle(E, A, trained):
     """The 512^2 network with the trained parameters on the real network input
-    (3 plain EPTV iterations of evaluation seed 0), the launch configuration
+    (the early EPTV image of evaluation seed 0), the launch configuration
     of the assisted pipeline, against the FP64 oracle with bf16 storage.
 
     Output: <= 2e-3 (as in the small-network tests).  Parameter gradients: a
