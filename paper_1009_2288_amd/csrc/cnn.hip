@@ -29,6 +29,7 @@ namespace eptv {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t f2bf(float f)
 {
@@ -265,23 +266,38 @@ static void conv_launch(const ConvArgs& a, int rt, int nt, dim3 grid, hipStream_
 constexpr int kPatchW = 34;             // 32 columns + halo
 constexpr int kPatchPS = 40;            // bf16 per patch pixel (32 channels + 16 B)
 constexpr int kTapLd = 9 * 32 + 8;      // bf16 per weight row (9 taps x 32 channels + 16 B)
+constexpr int kTileBlocksPerCu = 2;     // persistent blocks per CU
 
 template <int TH, int NT>
-__global__ __launch_bounds__(256) void k_conv3_tile(ConvArgs a)
+__global__ __launch_bounds__(256) void k_conv3_tile(ConvArgs a, int ntiles)
 {
     constexpr int BN = 16 * NT;       // output channels per block
     constexpr int RPW = TH / 4;       // image rows per wave
     constexpr int RT = 2 * RPW;       // 16-pixel row tiles per wave
+    constexpr int PN = (TH + 2) * kPatchW * 4, PPT = (PN + 255) / 256;  // patch uint4s, per thread
+    constexpr int WN = BN * 36, WPT = (WN + 255) / 256;                 // weight uint4s, per thread
     __shared__ __attribute__((aligned(16))) uint16_t patch[(TH + 2) * kPatchW * kPatchPS];
     __shared__ __attribute__((aligned(16))) uint16_t wts[BN * kTapLd];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int tiles_x = (a.w + 31) / 32, tiles_y = (a.h + TH - 1) / TH;
-    int t = xcd_band((int)blockIdx.x, (int)gridDim.x);
-    const int img = t / (tiles_x * tiles_y);
-    t -= img * tiles_x * tiles_y;
-    const int ty = t / tiles_x, tx = t - ty * tiles_x;
-    const int y0 = ty * TH, x0 = tx * 32;
     const int n0 = blockIdx.y * BN;
+    const int nch = a.cin / 32;
+    // persistent blocks: block b walks tiles of one contiguous band per XCD
+    // (workgroups go to the 8 XCDs round robin), so neighbouring tiles share
+    // an L2; without a multiple of 8 blocks, a plain stride
+    const int G = (int)gridDim.x, b = (int)blockIdx.x;
+    int t_first, t_step, t_end;
+    if (G % 8 == 0) {
+        const int band = (ntiles + 7) / 8, xcd = b & 7;
+        t_first = xcd * band + (b >> 3);
+        t_step = G >> 3;
+        t_end = min(ntiles, (xcd + 1) * band);
+    } else {
+        t_first = b;
+        t_step = G;
+        t_end = ntiles;
+    }
+    if (t_first >= t_end) return;  // whole block, before any barrier
     const int mrow = lane & 15, kq = (lane >> 4) * 8;
     int lbase[RT];
 #pragma unroll
@@ -289,29 +305,76 @@ __global__ __launch_bounds__(256) void k_conv3_tile(ConvArgs a)
         const int lr = wave * RPW + (i >> 1), lc = (i & 1) * 16 + mrow;
         lbase[i] = ((lr + 1) * kPatchW + lc + 1) * kPatchPS + kq;
     }
+    auto tile_origin = [&](int t, int& img, int& y0, int& x0) __attribute__((always_inline)) {
+        img = t / (tiles_x * tiles_y);
+        const int r = t - img * tiles_x * tiles_y;
+        const int ty = r / tiles_x;
+        y0 = ty * TH;
+        x0 = (r - ty * tiles_x) * 32;
+    };
+    u32x4 pr[PPT], wr[WPT];
+    auto fetch_patch = [&](int t, int c0) __attribute__((always_inline)) {
+        int img, y0, x0;
+        tile_origin(t, img, y0, x0);
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) {
+            const int idx = threadIdx.x + 256 * u;
+            const int px = idx >> 2, part = idx & 3;
+            const int pr_ = px / kPatchW, pc = px - pr_ * kPatchW;
+            const int y = y0 - 1 + pr_, x = x0 - 1 + pc;
+            pr[u] = u32x4{0u, 0u, 0u, 0u};
+            if (idx < PN && (unsigned)y < (unsigned)a.h && (unsigned)x < (unsigned)a.w)
+                pr[u] = *reinterpret_cast<const u32x4*>(a.x + (((size_t)img * a.h + y) * a.w + x) * a.x_cs + a.x_co +
+                                                        c0 + part * 8);
+        }
+    };
+    auto fetch_w = [&](int c0) __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < WPT; ++u) {
+            const int idx = threadIdx.x + 256 * u;
+            const int row = idx / 36, rem = idx - row * 36, tap = rem >> 2, part = rem & 3;
+            wr[u] = idx < WN ? *reinterpret_cast<const u32x4*>(a.wt + (size_t)(n0 + row) * a.k_pad + tap * a.cin +
+                                                               c0 + part * 8)
+                             : u32x4{0u, 0u, 0u, 0u};
+        }
+    };
     floatx4 acc[RT][NT];
 #pragma unroll
     for (int i = 0; i < RT; ++i)
 #pragma unroll
         for (int j = 0; j < NT; ++j) acc[i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int c0 = 0; c0 < a.cin; c0 += 32) {
-        __syncthreads();  // the previous chunk is consumed
-        for (int idx = threadIdx.x; idx < (TH + 2) * kPatchW * 4; idx += 256) {
-            const int px = idx >> 2, part = idx & 3;
-            const int pr = px / kPatchW, pc = px - pr * kPatchW;
-            const int y = y0 - 1 + pr, x = x0 - 1 + pc;
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if ((unsigned)y < (unsigned)a.h && (unsigned)x < (unsigned)a.w)
-                v = *reinterpret_cast<const uint4*>(a.x + (((size_t)img * a.h + y) * a.w + x) * a.x_cs + a.x_co +
-                                                    c0 + part * 8);
-            *reinterpret_cast<uint4*>(patch + px * kPatchPS + part * 8) = v;
+    int t = t_first, c = 0;
+    bool w_staged = false;
+    fetch_patch(t, 0);
+    fetch_w(0);
+    while (true) {
+        __syncthreads();  // the previous item is consumed
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) {
+            const int idx = threadIdx.x + 256 * u;
+            if (idx < PN) *reinterpret_cast<u32x4*>(patch + (idx >> 2) * kPatchPS + (idx & 3) * 8) = pr[u];
         }
-        for (int idx = threadIdx.x; idx < BN * 36; idx += 256) {
-            const int row = idx / 36, rem = idx - row * 36, tap = rem >> 2, part = rem & 3;
-            *reinterpret_cast<uint4*>(wts + row * kTapLd + tap * 32 + part * 8) = *reinterpret_cast<const uint4*>(
-                a.wt + (size_t)(n0 + row) * a.k_pad + tap * a.cin + c0 + part * 8);
+        if (nch > 1 || !w_staged) {
+#pragma unroll
+            for (int u = 0; u < WPT; ++u) {
+                const int idx = threadIdx.x + 256 * u;
+                const int row = idx / 36, rem = idx - row * 36;
+                if (idx < WN) *reinterpret_cast<u32x4*>(wts + row * kTapLd + (rem >> 2) * 32 + (rem & 3) * 8) = wr[u];
+            }
+            w_staged = true;
         }
         __syncthreads();
+        // the next (tile, chunk) item is fetched while this one is computed
+        int tn = t, cn = c + 1;
+        if (cn == nch) {
+            cn = 0;
+            tn = t + t_step;
+        }
+        const bool more = tn < t_end;
+        if (more) {
+            fetch_patch(tn, cn * 32);
+            if (nch > 1) fetch_w(cn * 32);
+        }
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
             const int toff = ((tap / 3 - 1) * kPatchW + (tap % 3 - 1)) * kPatchPS;
@@ -328,29 +391,40 @@ __global__ __launch_bounds__(256) void k_conv3_tile(ConvArgs a)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa.v, fb[j].v, acc[i][j], 0, 0, 0);
             }
         }
-    }
-    // epilogue: accumulator r of lane l, row tile i, column tile j is the
-    // pixel at local row wave * RPW + i / 2, column (i % 2) * 16 + 4 (l / 16) + r,
-    // channel n0 + 16 j + l % 16
+        if (c == nch - 1) {
+            // epilogue: accumulator r of lane l, row tile i, column tile j is
+            // the pixel at local row wave * RPW + i / 2, column
+            // (i % 2) * 16 + 4 (l / 16) + r, channel n0 + 16 j + l % 16
+            int img, y0, x0;
+            tile_origin(t, img, y0, x0);
 #pragma unroll
-    for (int i = 0; i < RT; ++i)
+            for (int i = 0; i < RT; ++i)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int y = y0 + wave * RPW + (i >> 1), x = x0 + (i & 1) * 16 + (lane >> 4) * 4 + r;
-            if (y >= a.h || x >= a.w) continue;
-            const size_t pix = ((size_t)img * a.h + y) * a.w + x;
+                for (int r = 0; r < 4; ++r) {
+                    const int y = y0 + wave * RPW + (i >> 1), x = x0 + (i & 1) * 16 + (lane >> 4) * 4 + r;
+                    if (y >= a.h || x >= a.w) continue;
+                    const size_t pix = ((size_t)img * a.h + y) * a.w + x;
 #pragma unroll
-            for (int j = 0; j < NT; ++j) {
-                const int n = n0 + 16 * j + mrow;
-                if (n >= a.cout) continue;
-                float v = acc[i][j][r] + (a.bias ? a.bias[n] : 0.0f);
-                if (a.relu) v = fmaxf(v, 0.0f);
-                if (a.y32)
-                    a.y32[pix * a.y_cs + a.y_co + n] = v;
-                else
-                    a.y[pix * a.y_cs + a.y_co + n] = f2bf(v);
-            }
+                    for (int j = 0; j < NT; ++j) {
+                        const int n = n0 + 16 * j + mrow;
+                        if (n >= a.cout) continue;
+                        float v = acc[i][j][r] + (a.bias ? a.bias[n] : 0.0f);
+                        if (a.relu) v = fmaxf(v, 0.0f);
+                        if (a.y32)
+                            a.y32[pix * a.y_cs + a.y_co + n] = v;
+                        else
+                            a.y[pix * a.y_cs + a.y_co + n] = f2bf(v);
+                    }
+                }
+#pragma unroll
+            for (int i = 0; i < RT; ++i)
+#pragma unroll
+                for (int j = 0; j < NT; ++j) acc[i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
         }
+        if (!more) break;
+        t = tn;
+        c = cn;
+    }
 }
 
 // A 3x3 convolution of a one-channel input (the first layer): K = 9 is too
@@ -416,11 +490,16 @@ hipError_t launch_conv(const ConvArgs& a, int mode, hipStream_t s)
         else if (t4 * (nt == 4 ? c4 : c2) >= 256) th = 4, tn = nt;
         else if (t4 * c2 >= 256) th = 4, tn = 2;
         if (th) {
-            dim3 g((unsigned)(th == 8 ? t8 : t4), (unsigned)(tn == 4 ? c4 : c2));
-            if (th == 8 && tn == 4) hipLaunchKernelGGL((k_conv3_tile<8, 4>), g, dim3(256), 0, s, a);
-            else if (th == 8) hipLaunchKernelGGL((k_conv3_tile<8, 2>), g, dim3(256), 0, s, a);
-            else if (tn == 4) hipLaunchKernelGGL((k_conv3_tile<4, 4>), g, dim3(256), 0, s, a);
-            else hipLaunchKernelGGL((k_conv3_tile<4, 2>), g, dim3(256), 0, s, a);
+            // persistent blocks: about kTileBlocksPerCu per CU over all channel blocks
+            const long long nt_ = th == 8 ? t8 : t4, cbn = tn == 4 ? c4 : c2;
+            const long long want = std::max(8LL, (long long)kTileBlocksPerCu * 256 / cbn / 8 * 8);
+            const int G = (int)std::min(nt_, want);
+            dim3 g((unsigned)G, (unsigned)cbn);
+            const int ntl = (int)nt_;
+            if (th == 8 && tn == 4) hipLaunchKernelGGL((k_conv3_tile<8, 4>), g, dim3(256), 0, s, a, ntl);
+            else if (th == 8) hipLaunchKernelGGL((k_conv3_tile<8, 2>), g, dim3(256), 0, s, a, ntl);
+            else if (tn == 4) hipLaunchKernelGGL((k_conv3_tile<4, 4>), g, dim3(256), 0, s, a, ntl);
+            else hipLaunchKernelGGL((k_conv3_tile<4, 2>), g, dim3(256), 0, s, a, ntl);
             return hipGetLastError();
         }
     }
