@@ -476,17 +476,25 @@ double orc_select_sigma(int nx, int ny, const double* f, double eps, double q, d
  * (EPTV algorithm, step 2) and held fixed inside the line search. */
 /* The same descent with given half-edge weights in place of Eq. 5's
  * w = exp(-TV^2 / sigma^2) (NULL: the adaptive weights). */
+/* With replay (NULL: search), step s takes the given backtrack index
+ * instead of searching (-1: no step), and margin_out[s] certifies it against
+ * this function's own inequality: the smaller of (thr - Q_k)/|Q0| for the
+ * replayed index and (Q_j - thr_j)/|Q0| for every earlier index j (all of
+ * them when the index is -1) -- non-negative when the search would have made
+ * the same decision, negative by how much it would not. */
 static int tv_step_with(int nx, int ny, const orc_params* p, double* f, const double* v, double sigma, int n_steps,
-                        int* k_out, double* margin_out, double* sigma_out, const double* wx_in, const double* wy_in);
+                        int* k_out, double* margin_out, double* sigma_out, const double* wx_in, const double* wy_in,
+                        const int* replay);
 
 int orc_tv_step(int nx, int ny, const orc_params* p, double* f, const double* v,
                 double sigma, int n_steps, int* k_out, double* margin_out, double* sigma_out)
 {
-    return tv_step_with(nx, ny, p, f, v, sigma, n_steps, k_out, margin_out, sigma_out, NULL, NULL);
+    return tv_step_with(nx, ny, p, f, v, sigma, n_steps, k_out, margin_out, sigma_out, NULL, NULL, NULL);
 }
 
 static int tv_step_with(int nx, int ny, const orc_params* p, double* f, const double* v, double sigma, int n_steps,
-                        int* k_out, double* margin_out, double* sigma_out, const double* wx_in, const double* wy_in)
+                        int* k_out, double* margin_out, double* sigma_out, const double* wx_in, const double* wy_in,
+                        const int* replay)
 {
     size_t np = (size_t)nx * ny, ex = n_xedges(nx, ny), ey = n_yedges(nx, ny);
     if (sigma < 0 && !wx_in) sigma = orc_select_sigma(nx, ny, f, p->tv_eps, p->edge_quantile, p->sigma_floor);
@@ -515,17 +523,34 @@ static int tv_step_with(int nx, int ny, const orc_params* p, double* f, const do
 
         int acc = -1;
         double margin = HUGE_VAL, t = t0;
-        for (int k = 0; k <= p->armijo_max_backtracks; ++k) {
-            for (size_t i = 0; i < np; ++i) h[i] = f[i] - t * g[i];
-            double qk = orc_surrogate(nx, ny, h, v, p->lambda, wx, wy, p->tv_eps);
-            double thr = q0 - p->armijo_c * t * gg;
-            double rel = fabs(qk - thr) / (fabs(q0) > 0 ? fabs(q0) : 1.0);
-            if (rel < margin) margin = rel;
-            if (qk <= thr) {
-                acc = k;
-                break;
+        const double scale = fabs(q0) > 0 ? fabs(q0) : 1.0;
+        if (replay) {
+            /* the given decision, certified against every trial the search would make */
+            const int kr = replay[s];
+            const int last = kr >= 0 ? kr : p->armijo_max_backtracks;
+            for (int k = 0; k <= last; ++k) {
+                for (size_t i = 0; i < np; ++i) h[i] = f[i] - t * g[i];
+                double qk = orc_surrogate(nx, ny, h, v, p->lambda, wx, wy, p->tv_eps);
+                double thr = q0 - p->armijo_c * t * gg;
+                double cert = (k == kr ? thr - qk : qk - thr) / scale;
+                if (cert < margin) margin = cert;
+                if (k == kr) break;
+                t *= p->armijo_shrink;
             }
-            t *= p->armijo_shrink;
+            acc = kr;
+        } else {
+            for (int k = 0; k <= p->armijo_max_backtracks; ++k) {
+                for (size_t i = 0; i < np; ++i) h[i] = f[i] - t * g[i];
+                double qk = orc_surrogate(nx, ny, h, v, p->lambda, wx, wy, p->tv_eps);
+                double thr = q0 - p->armijo_c * t * gg;
+                double rel = fabs(qk - thr) / scale;
+                if (rel < margin) margin = rel;
+                if (qk <= thr) {
+                    acc = k;
+                    break;
+                }
+                t *= p->armijo_shrink;
+            }
         }
         if (acc >= 0) memcpy(f, h, sizeof(double) * np);
         if (k_out) k_out[s] = acc;
@@ -618,9 +643,27 @@ int orc_reconstruct(const orc_matrix* m, const orc_params* p, const double* y, d
     return orc_reconstruct_weighted(m, p, y, f, f_ref, st, NULL, NULL, 0);
 }
 
+static int reconstruct_impl(const orc_matrix* m, const orc_params* p, const double* y, double* f,
+                            const double* f_ref, orc_stats* st, const double* wx_in, const double* wy_in,
+                            int frozen_iters, const int* replay);
+
 int orc_reconstruct_weighted(const orc_matrix* m, const orc_params* p, const double* y, double* f,
                              const double* f_ref, orc_stats* st, const double* wx_in, const double* wy_in,
                              int frozen_iters)
+{
+    return reconstruct_impl(m, p, y, f, f_ref, st, wx_in, wy_in, frozen_iters, NULL);
+}
+
+int orc_reconstruct_replay(const orc_matrix* m, const orc_params* p, const double* y, double* f,
+                           const double* f_ref, orc_stats* st, const int* armijo_replay)
+{
+    if (!armijo_replay) return 1;
+    return reconstruct_impl(m, p, y, f, f_ref, st, NULL, NULL, 0, armijo_replay);
+}
+
+static int reconstruct_impl(const orc_matrix* m, const orc_params* p, const double* y, double* f,
+                            const double* f_ref, orc_stats* st, const double* wx_in, const double* wy_in,
+                            int frozen_iters, const int* replay)
 {
     if (!m || !p || !y || !f || p->outer_iters < 0 || p->tv_iters < 0 || p->cgls_iters < 0) return 1;
     const int nx = m->nx, ny = m->ny, T = p->tv_iters;
@@ -655,7 +698,7 @@ int orc_reconstruct_weighted(const orc_matrix* m, const orc_params* p, const dou
             sigma = orc_select_sigma(nx, ny, w, p->tv_eps, p->edge_quantile, p->sigma_floor);
         tv_step_with(nx, ny, p, w, v, sigma, T, st && st->armijo_k ? st->armijo_k + (size_t)k * T : NULL,
                      st && st->armijo_margin ? st->armijo_margin + (size_t)k * T : NULL, NULL,
-                     frozen ? wx_in : NULL, frozen ? wy_in : NULL);
+                     frozen ? wx_in : NULL, frozen ? wy_in : NULL, replay ? replay + (size_t)k * T : NULL);
         /* step 3 */
         if (p->positivity)
             for (size_t i = 0; i < nc; ++i)

@@ -125,6 +125,14 @@ int orc_reconstruct_weighted(const orc_matrix* m, const orc_params* p, const dou
                              const double* f_ref, orc_stats* st, const double* wx_in, const double* wy_in,
                              int frozen_iters);
 
+/* Replay mode: the outer loop with the Armijo decisions taken from
+ * armijo_replay [K*T] (backtrack index per descent step, -1 = no step)
+ * instead of searching; st->armijo_margin then certifies each decision
+ * against this implementation's own inequality (>= 0: the search agrees;
+ * negative: by how much, relative to |Q0|, it would not). */
+int orc_reconstruct_replay(const orc_matrix* m, const orc_params* p, const double* y, double* f,
+                           const double* f_ref, orc_stats* st, const int* armijo_replay);
+
 int orc_num_threads(void);
 
 #ifdef __cplusplus

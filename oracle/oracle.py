@@ -120,6 +120,8 @@ def lib() -> C.CDLL:
         L.orc_reconstruct.argtypes = [C.c_void_p, C.POINTER(_Params), dp, dp, dp, C.POINTER(_Stats)]
         L.orc_reconstruct_weighted.argtypes = [C.c_void_p, C.POINTER(_Params), dp, dp, dp, C.POINTER(_Stats), dp, dp,
                                                C.c_int]
+        L.orc_reconstruct_replay.argtypes = [C.c_void_p, C.POINTER(_Params), dp, dp, dp, C.POINTER(_Stats),
+                                             C.POINTER(C.c_int)]
         L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -223,9 +225,12 @@ class Matrix:
         return u.reshape(self.ny, self.nx), int(steps), float(res[0])
 
     def reconstruct(self, y, params: Params, f0=None, f_ref=None, weights=None,
-                    frozen_iters: int = 0) -> tuple[np.ndarray, dict]:
+                    frozen_iters: int = 0, armijo_replay=None) -> tuple[np.ndarray, dict]:
         """weights: optional (wx [ny][nx+1], wy [ny+1][nx]) used in place of
-        Eq. 5's weights during the first frozen_iters iterations."""
+        Eq. 5's weights during the first frozen_iters iterations.
+        armijo_replay: optional [K][T] backtrack indices (-1: no step) taken
+        instead of searching; armijo_margin then holds the signed
+        certification of each (>= 0: the oracle's own search agrees)."""
         K, T = params.outer_iters, params.tv_iters
         f = np.zeros(self.nx * self.ny) if f0 is None else _f64(f0).reshape(-1).copy()
         st = {"sigma": np.zeros(K), "armijo_k": np.zeros(max(K * T, 1), np.int32),
@@ -235,7 +240,13 @@ class Matrix:
                     _i(st["cgls_steps"]), _d(st["cgls_resid"]), _d(st["rmse"]))
         ref = _f64(f_ref).reshape(-1) if f_ref is not None else None
         cp = params._c()
-        if weights is not None:
+        if armijo_replay is not None:
+            assert weights is None
+            rp = np.ascontiguousarray(np.asarray(armijo_replay, dtype=np.int32).reshape(-1))
+            assert rp.size == K * T
+            rc = lib().orc_reconstruct_replay(self._h, C.byref(cp), _d(_f64(y).reshape(-1)), _d(f),
+                                              _d(ref) if ref is not None else None, C.byref(cs), _i(rp))
+        elif weights is not None:
             wx, wy = _f64(weights[0]), _f64(weights[1])
             assert wx.shape == (self.ny, self.nx + 1) and wy.shape == (self.ny + 1, self.nx)
             rc = lib().orc_reconstruct_weighted(self._h, C.byref(cp), _d(_f64(y).reshape(-1)), _d(f),

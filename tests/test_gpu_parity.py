@@ -263,6 +263,34 @@ def test_reconstruct_paper_case_20_iterations(E, oracle):
     np.testing.assert_allclose(sg["sigma"], so["sigma"], rtol=1e-4)
 
 
+def test_reconstruct_paper_case_100_iterations_replay(E, oracle):
+    """512^2 / 40 x 736 over the workload's full K = 100, in replay mode: the
+    GPU runs free and records its Armijo indices; the oracle takes them
+    instead of searching and certifies each against its own FP64 inequality
+    (slack 1e-6 |Q0|: over these 500 decisions the oracle's own free run has
+    two near-ties below 1e-5, where float32 may decide either way), and then
+    the images must agree to 1e-4."""
+    c = synth.make_case("paper", 0)
+    P = plan(E, "paper")
+    M = matrix(oracle, "paper")
+    y = c.y.astype(np.float32)
+    f, sg = P.reconstruct(dev(y), E.Params(outer_iters=100, lam=1000.0), f_ref=dev(c.phantom))
+    fo, so = M.reconstruct(y, oracle_params(oracle, 100), f_ref=c.phantom, armijo_replay=sg["armijo_k"])
+    worst = float(so["armijo_margin"].min())
+    print("replay certification: min margin", worst, "steps", sg["armijo_k"].size)
+    assert worst >= -1e-6
+    rs = np.abs(sg["sigma"] - so["sigma"]) / so["sigma"]
+    rr = np.abs(sg["rmse"] - so["rmse"]) / so["rmse"]
+    print("image", rel(f.cpu().numpy(), fo), "sigma max rel", rs.max(), "at", rs.argmax(), "rmse max rel", rr.max())
+    assert rel(f.cpu().numpy(), fo) <= 1e-4
+    np.testing.assert_allclose(sg["rmse"], so["rmse"], rtol=1e-4)
+    # sigma is an order statistic of neighbour differences (~5e-4 mm^-1) of
+    # images whose values (~2e-2) agree to ~1e-5: the same absolute deviation
+    # (<= 2 max |f_gpu - f_oracle| per half-edge, the statistic being
+    # 1-Lipschitz) is ~40x larger relative to sigma than to the image
+    np.testing.assert_allclose(sg["sigma"], so["sigma"], rtol=1e-3)
+
+
 @pytest.mark.parametrize("kw", [dict(cgls_iters=0, mu=1.0, lam=2000.0, p2_start=1),
                                 dict(tv_iters=0), dict(sigma_fixed=float("inf")),
                                 dict(cgls_iters=1, tv_iters=2, edge_quantile=0.5, positivity=0)])

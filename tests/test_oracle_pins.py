@@ -610,3 +610,41 @@ def test_frozen_then_adaptive(oracle):
     f3, s3 = M.reconstruct(y, oracle.Params(outer_iters=3, lam=200.0, zero_init=0), f0=f2)
     np.testing.assert_array_equal(f5, f3)
     assert np.all(s5["sigma"][:2] == -1.0) and np.all(s5["sigma"][2:] > 0.0)
+
+
+# ------------------------------------------------------------------ replay mode
+
+def test_replay_of_own_decisions_reproduces_the_free_run(oracle):
+    """Replaying the oracle's own Armijo indices gives the free run's image
+    bit for bit, and every decision certifies (margin >= 0: the search would
+    make it)."""
+    g, M, y = _pin_case(oracle)
+    prm = oracle.Params(outer_iters=6, lam=200.0)
+    f, st = M.reconstruct(y, prm)
+    fr, sr = M.reconstruct(y, prm, armijo_replay=st["armijo_k"])
+    np.testing.assert_array_equal(fr, f)
+    np.testing.assert_array_equal(sr["armijo_k"], st["armijo_k"])
+    assert float(sr["armijo_margin"].min()) >= 0.0
+    # for decisions the search agrees with, the signed certification is the
+    # search's own decision margin (the same trials, the same distances)
+    np.testing.assert_array_equal(sr["armijo_margin"], st["armijo_margin"])
+
+
+def test_replay_flags_a_wrong_decision(oracle):
+    """A replayed index one larger than the search's (a step the search would
+    have accepted earlier) and one smaller (a step that fails the rule) both
+    certify negative at that step."""
+    g, M, y = _pin_case(oracle)
+    prm = oracle.Params(outer_iters=3, lam=200.0)
+    _, st = M.reconstruct(y, prm)
+    ks = st["armijo_k"].copy()
+    s = np.argwhere(ks >= 1)[0]
+    later = ks.copy()
+    later[tuple(s)] += 1
+    _, sl = M.reconstruct(y, prm, armijo_replay=later)
+    assert sl["armijo_margin"][tuple(s)] < 0.0
+    assert np.all(sl["armijo_margin"].reshape(-1)[:np.ravel_multi_index(tuple(s), ks.shape)] >= 0.0)
+    earlier = ks.copy()
+    earlier[tuple(s)] -= 1
+    _, se = M.reconstruct(y, prm, armijo_replay=earlier)
+    assert se["armijo_margin"][tuple(s)] < 0.0
