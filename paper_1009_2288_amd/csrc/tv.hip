@@ -89,11 +89,11 @@ __device__ __forceinline__ void hist_add(uint32_t* h, uint32_t bin)
 }
 
 // Edge index: x-edge (i+1/2, j) -> j*(nx+1) + i+1; y-edge (i, j+1/2) -> ny*(nx+1) + (j+1)*nx + i.
-__device__ __forceinline__ void edges_hist_block(const float* __restrict__ f, int nx, int ny, float eps2,
-                                                 uint32_t* keys, uint32_t* hist0, int bx, int by, uint32_t* h)
+// One 16x16 tile's half-edge magnitudes into keys and the block's LDS
+// histogram of their top 11 bits.
+__device__ __forceinline__ void edges_tile(const float* __restrict__ f, int nx, int ny, float eps2, uint32_t* keys,
+                                           int bx, int by, uint32_t* h)
 {
-    for (int b = threadIdx.x; b < kSelectBins; b += 256) h[b] = 0u;
-    __syncthreads();
     const int i = bx * kT + (threadIdx.x & (kT - 1)), j = by * kT + threadIdx.x / kT;
     if (i < nx && j < ny) {
         Nbhd N;
@@ -116,23 +116,42 @@ __device__ __forceinline__ void edges_hist_block(const float* __restrict__ f, in
             hist_add(h, k >> 21);
         }
     }
+}
+
+__device__ __forceinline__ void hist_clear(uint32_t* h)
+{
+    for (int b = threadIdx.x; b < kSelectBins; b += 256) h[b] = 0u;
+    __syncthreads();
+}
+
+__device__ __forceinline__ void hist_flush(const uint32_t* h, uint32_t* hist0)
+{
     __syncthreads();
     for (int b = threadIdx.x; b < kSelectBins; b += 256)
         if (h[b]) atomicAdd(&hist0[b], h[b]);
 }
 
+// Persistent over tiles: the flat half-edge magnitudes pile into a few
+// histogram bins, so the global atomics per bin (one per block) are what
+// serialise; a block walks several tiles and flushes once.
 __global__ __launch_bounds__(256) void k_edges_hist(const float* __restrict__ f, int nx, int ny, float eps2,
                                                     uint32_t* keys, uint32_t* hist0)
 {
     __shared__ uint32_t h[kSelectBins];
-    edges_hist_block(f, nx, ny, eps2, keys, hist0, blockIdx.x, blockIdx.y, h);
+    const int tx = (nx + kT - 1) / kT, nt = tx * ((ny + kT - 1) / kT);
+    hist_clear(h);
+    for (int t = blockIdx.x; t < nt; t += gridDim.x) edges_tile(f, nx, ny, eps2, keys, t % tx, t / tx, h);
+    hist_flush(h, hist0);
 }
+
+constexpr int kEdgesHistBlocks = 256;
 
 hipError_t launch_edges_hist(const Plan& p, const float* f, float eps2, uint32_t* keys, uint32_t* hist0,
                              hipStream_t s)
 {
-    dim3 grid((p.nx + kT - 1) / kT, (p.ny + kT - 1) / kT);
-    hipLaunchKernelGGL(k_edges_hist, grid, dim3(256), 0, s, f, p.nx, p.ny, eps2, keys, hist0);
+    const int nt = ((p.nx + kT - 1) / kT) * ((p.ny + kT - 1) / kT);
+    hipLaunchKernelGGL(k_edges_hist, dim3((unsigned)std::min(nt, kEdgesHistBlocks)), dim3(256), 0, s, f, p.nx, p.ny,
+                       eps2, keys, hist0);
     return hipGetLastError();
 }
 
@@ -750,16 +769,31 @@ hipError_t launch_tv_vjp(const Plan& p, const float* f, const float* u, float la
 }
 
 // ------------------------------------------------------------------ batched kernels (see batch.h)
+// A block takes a contiguous run of the (slice, tile) items (slice-major), so
+// it accumulates one slice's histogram over several tiles and flushes it
+// only when the slice changes (the flushes' global atomics are what
+// serialise: flat regions put most half-edges into a few bins).
 __global__ __launch_bounds__(256) void kb_edges_hist(const SliceDev* __restrict__ sl, const int2* __restrict__ items,
                                                      int n_items, int imgs, float eps2)
 {
     __shared__ uint32_t h[kSelectBins];
-    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const int per = (n_items + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int beg = (int)blockIdx.x * per, end = min(n_items, beg + per);
+    if (beg >= end) return;  // whole block
+    hist_clear(h);
+    int cur = items[beg].x;
+    for (int it = beg; it < end; ++it) {
         const int2 w = items[it];
+        if (w.x != cur) {  // uniform over the block
+            hist_flush(h, sl[cur].hist);
+            __syncthreads();
+            hist_clear(h);
+            cur = w.x;
+        }
         const SliceDev& d = sl[w.x];
-        __syncthreads();
-        edges_hist_block(d.buf[imgs], d.nx, d.ny, eps2, d.keys, d.hist, w.y % d.t16x, w.y / d.t16x, h);
+        edges_tile(d.buf[imgs], d.nx, d.ny, eps2, d.keys, w.y % d.t16x, w.y / d.t16x, h);
     }
+    hist_flush(h, sl[cur].hist);
 }
 
 hipError_t blaunch_edges_hist(const BatchDev& b, int img, float eps2, hipStream_t s)
