@@ -88,3 +88,32 @@ def test_batch_create_rejects_bad_input_without_gpu(lib):
     out = C.c_void_p()
     assert lib.eptv_batch_create(None, 1, C.byref(out)) == 1
     assert lib.eptv_batch_destroy(None) == 1
+
+
+def test_network_entry_points_reject_bad_input_without_gpu(lib):
+    """The U-Net and tensor-conversion calls check their arguments before any
+    HIP call: impossible shapes, a missing output, non-positive scales."""
+    out = C.c_void_p()
+    # channels, base, levels, batch, sizes; height/width must divide by 2^(levels-1)
+    assert lib.eptv_unet_create(0, 3, 32, 4, 1, 512, 512, C.byref(out)) == 1
+    assert lib.eptv_unet_create(1, 3, 32, 0, 1, 512, 512, C.byref(out)) == 1
+    assert lib.eptv_unet_create(1, 3, 32, 4, 0, 512, 512, C.byref(out)) == 1
+    assert lib.eptv_unet_create(1, 3, 32, 4, 1, 100, 512, C.byref(out)) == 1
+    assert lib.eptv_unet_create(1, 3, 12, 4, 1, 512, 512, C.byref(out)) == 1   # base not a multiple of 8
+    assert lib.eptv_unet_create(1, 3, 32, 4, 1, 512, 512, None) == 1
+    assert not out.value
+    assert lib.eptv_unet_destroy(None) == 1
+    n = C.c_longlong()
+    assert lib.eptv_unet_param_count(None, C.byref(n)) == 1
+    assert lib.eptv_unet_forward(None, None, 1, None, None) == 1
+    assert lib.eptv_unet_backward(None, None, None, None) == 1
+    assert lib.eptv_unet_adam(None, 1e-3, 0.9, 0.999, 1e-8, 1, None) == 1
+    assert lib.eptv_unet_mse(None, None, None, 0, None, None, None) == 1
+    fake = C.c_void_p(16)  # never dereferenced: the checks fail first
+    assert lib.eptv_maps_from_eptv(0, 4, 4, fake, None, None, None, 1.0, fake, None) == 1
+    assert lib.eptv_maps_from_eptv(1, 4, 4, fake, None, fake, None, 1.0, fake, None) == 1  # one weight map only
+    assert lib.eptv_maps_from_eptv(1, 4, 4, fake, None, None, None, 0.0, fake, None) == 1
+    assert lib.eptv_maps_from_eptv(1, 4, 4, fake, None, None, None, float("inf"), fake, None) == 1
+    assert lib.eptv_maps_to_eptv(1, 4, 4, fake, -1.0, None, fake, fake, fake, None) == 1
+    assert lib.eptv_maps_to_eptv(1, 4, 4, fake, 1.0, None, fake, None, fake, None) == 1
+    assert lib.eptv_reconstruct_weighted(None, None, None, None, None, None, None, 0, None, 0, None, None) == 1
