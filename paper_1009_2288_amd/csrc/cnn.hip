@@ -148,17 +148,23 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a)
     const uint16_t* wq = a.wt + (size_t)q * a.n_pad * a.k_pad;
     const int mrow = lane & 15, kq = (lane >> 4) * 8;
     const bool fast = MODE != kUpBack && a.cin % 32 == 0 && a.x_cs % 8 == 0 && a.x_co % 8 == 0;
-    int ia[RT], ya[RT], xa[RT];
+    // With the image width a multiple of 16, a 16-pixel row tile lies in one
+    // image row: its (image, row, first column) is decoded once, uniformly
+    // over the wave, and a lane only adds its column offset.
+    const bool row16 = a.w % 16 == 0;
+    int ia[RT], ya[RT], xa[RT], xt[RT];
     bool va[RT];
     const uint16_t* base[RT];
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
         const int p = p0 + 16 * i + mrow;
         va[i] = p < npix;
-        ia[i] = p / hw;
-        const int r = p - ia[i] * hw;
+        const int pd = row16 ? p0 + 16 * i : p;
+        ia[i] = pd / hw;
+        const int r = pd - ia[i] * hw;
         ya[i] = r / a.w;
-        xa[i] = r - ya[i] * a.w;
+        xt[i] = r - ya[i] * a.w;
+        xa[i] = row16 ? xt[i] + mrow : xt[i];
         base[i] = a.x + (size_t)(va[i] ? p : 0) * a.x_cs + a.x_co + kq;
     }
     auto gather = [&](int i, int k) -> Frag {
@@ -217,7 +223,17 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a)
             if (p >= npix) continue;
             size_t pix;
             if (MODE == kUp) {
-                const int img = p / hw, rr = p - img * hw, y = rr / a.w, x = rr - y * a.w;
+                int img, y, x;
+                if (row16) {
+                    img = ia[i];
+                    y = ya[i];
+                    x = xt[i] + (lane >> 4) * 4 + r;
+                } else {
+                    img = p / hw;
+                    const int rr = p - img * hw;
+                    y = rr / a.w;
+                    x = rr - y * a.w;
+                }
                 pix = ((size_t)img * 2 * a.h + 2 * y + (q >> 1)) * 2 * a.w + 2 * x + (q & 1);
             } else {
                 pix = (size_t)p;
@@ -793,9 +809,69 @@ __global__ void k_avgpool_back(const uint16_t* dy, uint16_t* dx, int dxcs, int d
     }
 }
 
+// The same two, 8 channels (16 bytes) per thread for 16-byte aligned slices
+// (the same sums in the same order).
+__global__ void k_avgpool8(const uint16_t* x, int xcs, int xco, uint16_t* y, int n_img, int h, int w, int c8)
+{
+    const size_t n = (size_t)n_img * (h / 2) * (w / 2) * c8;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(i % c8) * 8;
+        const size_t t = i / c8;
+        const int xo = (int)(t % (w / 2));
+        const size_t t2 = t / (w / 2);
+        const int yo = (int)(t2 % (h / 2));
+        const int img = (int)(t2 / (h / 2));
+        Frag v[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d)
+            v[d].u = *reinterpret_cast<const uint4*>(
+                x + (((size_t)img * h + 2 * yo + (d >> 1)) * w + 2 * xo + (d & 1)) * xcs + xco + k);
+        Frag o;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            float sum = 0.0f;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) sum += bf2f(v[d].h[j]);
+            o.h[j] = f2bf(0.25f * sum);
+        }
+        *reinterpret_cast<uint4*>(y + t * (size_t)c8 * 8 + k) = o.u;
+    }
+}
+
+__global__ void k_avgpool_back8(const uint16_t* dy, uint16_t* dx, int dxcs, int dxco, int n_img, int h, int w, int c8,
+                                int accumulate)
+{
+    const size_t n = (size_t)n_img * h * w * c8;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(i % c8) * 8;
+        const size_t t = i / c8;
+        const int x = (int)(t % w);
+        const size_t t2 = t / w;
+        const int y = (int)(t2 % h);
+        const int img = (int)(t2 / h);
+        Frag g, o;
+        g.u = *reinterpret_cast<const uint4*>(dy + (((size_t)img * (h / 2) + y / 2) * (w / 2) + x / 2) * c8 * 8 + k);
+        uint4* d = reinterpret_cast<uint4*>(dx + t * dxcs + dxco + k);
+        if (accumulate) o.u = *d;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            float v = 0.25f * bf2f(g.h[j]);
+            if (accumulate) v += bf2f(o.h[j]);
+            o.h[j] = f2bf(v);
+        }
+        *d = o.u;
+    }
+}
+
 hipError_t launch_avgpool(const uint16_t* x, int xcs, int xco, uint16_t* y, int n_img, int h, int w, int c,
                           hipStream_t s)
 {
+    if (c % 8 == 0 && xcs % 8 == 0 && xco % 8 == 0) {
+        const size_t n8 = (size_t)n_img * (h / 2) * (w / 2) * (c / 8);
+        hipLaunchKernelGGL(k_avgpool8, dim3((unsigned)std::min<size_t>((n8 + 255) / 256, 8192)), dim3(256), 0, s, x,
+                           xcs, xco, y, n_img, h, w, c / 8);
+        return hipGetLastError();
+    }
     const size_t n = (size_t)n_img * (h / 2) * (w / 2) * c;
     hipLaunchKernelGGL(k_avgpool, dim3((unsigned)std::min<size_t>((n + 255) / 256, 8192)), dim3(256), 0, s, x, xcs, xco,
                        y, n_img, h, w, c);
@@ -805,6 +881,12 @@ hipError_t launch_avgpool(const uint16_t* x, int xcs, int xco, uint16_t* y, int 
 hipError_t launch_avgpool_back(const uint16_t* dy, uint16_t* dx, int dxcs, int dxco, int n_img, int h, int w, int c,
                                int accumulate, hipStream_t s)
 {
+    if (c % 8 == 0 && dxcs % 8 == 0 && dxco % 8 == 0) {
+        const size_t n8 = (size_t)n_img * h * w * (c / 8);
+        hipLaunchKernelGGL(k_avgpool_back8, dim3((unsigned)std::min<size_t>((n8 + 255) / 256, 8192)), dim3(256), 0, s,
+                           dy, dx, dxcs, dxco, n_img, h, w, c / 8, accumulate);
+        return hipGetLastError();
+    }
     const size_t n = (size_t)n_img * h * w * c;
     hipLaunchKernelGGL(k_avgpool_back, dim3((unsigned)std::min<size_t>((n + 255) / 256, 8192)), dim3(256), 0, s, dy, dx,
                        dxcs, dxco, n_img, h, w, c, accumulate);
