@@ -179,9 +179,8 @@ static hipError_t enqueue_batch_iteration(const BatchDev& b, const eptv_params& 
         const int g = gbuf[t & 1];
         const int gprev = t > 0 ? gbuf[(t - 1) & 1] : kNoBuf;
         const int fnext = t > 0 ? fbuf[t & 1] : kNoBuf;
-        EPTV_TRY(blaunch_tv_grad(b, fcur, gprev, fnext, kBufU, (float)q.lambda, eps2, g, s));
+        EPTV_TRY(blaunch_tv_armijo(b, fcur, gprev, fnext, kBufU, (float)q.lambda, eps2, g, t0, shrink, s));
         if (t > 0) fcur = fnext;
-        EPTV_TRY(blaunch_armijo(b, fcur, g, kBufU, (float)q.lambda, eps2, t0, shrink, s));
         EPTV_TRY(blaunch_armijo_decide(b, q.armijo_max_backtracks, q.armijo_c, t0, shrink, t, T, fcur, g, kBufU,
                                        (float)q.lambda, eps2, s));
     }

@@ -91,10 +91,8 @@ hipError_t blaunch_gd_p1(const BatchDev& b, float step, hipStream_t s);
 hipError_t blaunch_edges_hist(const BatchDev& b, int img, float eps2, hipStream_t s);
 hipError_t blaunch_select_hist(const BatchDev& b, int pass, hipStream_t s);
 hipError_t blaunch_select_finalize(const BatchDev& b, int pass, float floor_, hipStream_t s);
-hipError_t blaunch_tv_grad(const BatchDev& b, int f, int g_prev, int f_out, int v, float lambda, float eps2, int g,
-                           hipStream_t s);
-hipError_t blaunch_armijo(const BatchDev& b, int f, int g, int v, float lambda, float eps2, float t0, float shrink,
-                          hipStream_t s);
+hipError_t blaunch_tv_armijo(const BatchDev& b, int f, int g_prev, int f_out, int v, float lambda, float eps2, int g,
+                             float t0, float shrink, hipStream_t s);
 hipError_t blaunch_armijo_decide(const BatchDev& b, int max_bt, double c_arm, float t0, float shrink, int step, int T,
                                  int f, int g, int v, float lambda, float eps2, hipStream_t s);
 hipError_t blaunch_p2_update(const BatchDev& b, int fcur, int g, int fout, int foutT, int clamp, hipStream_t s);

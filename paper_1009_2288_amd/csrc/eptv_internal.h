@@ -219,9 +219,13 @@ hipError_t launch_tv_grad(const Plan& p, const float* f, const float* g_prev, co
                           const float* v, float lambda, const DevState* st, float sigma_direct, float eps2, float* g,
                           float* wx, float* wy, double* part, hipStream_t s, const float* wx_in = nullptr,
                           const float* wy_in = nullptr);
-hipError_t launch_armijo(const Plan& p, const float* f, const float* g, const float* v, const float* wx,
-                         const float* wy, float lambda, float eps2, float t0, float shrink, double* part,
-                         hipStream_t s);
+// One descent step's direction (as launch_tv_grad, with the weights and
+// partials) and the first Armijo trials (as launch_armijo) in one pass.
+hipError_t launch_tv_armijo(const Plan& p, const float* f, const float* g_prev, const DevState* st_prev,
+                            float* f_out, const float* v, float lambda, const DevState* st, float eps2, float* g,
+                            float* wx, float* wy, double* part_grad, double* part_arm, float t0, float shrink,
+                            hipStream_t s, const float* wx_in = nullptr, const float* wy_in = nullptr);
+
 hipError_t launch_armijo_decide(const Plan& p, DevState* st, const double* part_grad, const double* part_arm,
                                 int max_bt, double c_arm, float t0, float shrink, int32_t* st_k, int step, int T,
                                 const float* f, const float* g, const float* v, const float* wx, const float* wy,

@@ -216,13 +216,11 @@ static hipError_t enqueue_p2(const Plan& p, Workspace& W, const eptv_params& q, 
         float* g = gbuf[t & 1];
         const float* gprev = t > 0 ? gbuf[(t - 1) & 1] : nullptr;
         float* fnext = t > 0 ? fbuf[t & 1] : nullptr;
-        if ((e = launch_tv_grad(p, fcur, gprev, W.st, fnext, v, (float)q.lambda, W.st, 0.0f, eps2, g, W.wx, W.wy,
-                                W.part_grad, s, wx_in, wy_in)) != hipSuccess)
+        // the direction at the current iterate and the first Armijo trials, one pass
+        if ((e = launch_tv_armijo(p, fcur, gprev, W.st, fnext, v, (float)q.lambda, W.st, eps2, g, W.wx, W.wy,
+                                  W.part_grad, W.part_arm, t0, shrink, s, wx_in, wy_in)) != hipSuccess)
             return e;
         if (t > 0) fcur = fnext;
-        if ((e = launch_armijo(p, fcur, g, v, W.wx, W.wy, (float)q.lambda, eps2, t0, shrink, W.part_arm, s)) !=
-            hipSuccess)
-            return e;
         if ((e = launch_armijo_decide(p, W.st, W.part_grad, W.part_arm, q.armijo_max_backtracks, q.armijo_c, t0,
                                       shrink, st_k, t, n_steps, fcur, g, v, W.wx, W.wy, (float)q.lambda, eps2, s)) !=
             hipSuccess)

@@ -419,52 +419,184 @@ __device__ __forceinline__ void candidate_energies(const float* f, const float* 
     }
 }
 
-// Candidates k = 0 .. kArmijoFirst-1 over the whole image: per-block
-// partial sums, slot-major [kArmijoFirst][block].
-__device__ __forceinline__ void armijo_block(const float* __restrict__ f, const float* __restrict__ g,
-                                             const float* __restrict__ v, const float* __restrict__ wx,
-                                             const float* __restrict__ wy, int nx, int ny, float lambda, float eps2,
-                                             float t0, float shrink, double* part, int bx, int by, int b, int nb,
-                                             double (*red)[kArmijoFirst])
+// ------------------------------------------------------------------ one descent step's direction and trials, fused
+// The direction of tv_grad_block and the first kArmijoFirst Armijo trials
+// (candidate_energies) in one pass: the block forms the current iterate on
+// its tile plus a 2-pixel halo in LDS, the direction on the tile plus a
+// 1-pixel halo (halo values recomputed with the same operations as their
+// owning block, so they are bit-identical), and the trial energies of its
+// own pixels from those.  Per-block partials: [Q | ||g||^2][block] and
+// [trial][block], each summed over the block's pixels in a fixed order.
+struct TvArmShared {
+    float f[kT + 4][kT + 4];   // current iterate, tile + 2-pixel halo
+    float g[kT + 2][kT + 2];   // direction, tile + 1-pixel halo
+    float w[4][kT][kT];        // own pixels' weights: right, left, up, down
+    float e[kT][kT];           // own pixels' weighted half-edge sum
+    float dv[kT][kT];          // own pixels' f - v
+    double lds[4];
+    double red[4][kArmijoFirst];
+};
+
+__device__ __forceinline__ void tv_armijo_block(const float* __restrict__ f, const float* __restrict__ g_prev,
+                                                const DevState* st_prev, float* __restrict__ f_out,
+                                                const float* __restrict__ v, int nx, int ny, float lambda,
+                                                const DevState* st, float eps2, float* __restrict__ g, float* wx,
+                                                float* wy, double* part_grad, double* part_arm, float t0,
+                                                float shrink, int bx, int by, int b, int nb, TvArmShared& S,
+                                                const float* wx_in = nullptr, const float* wy_in = nullptr)
 {
-    const int i = bx * kT + (threadIdx.x & (kT - 1)), j = by * kT + threadIdx.x / kT;
-    double e[kArmijoFirst];
+    const float inv_s2 = st->inv_sigma2;
+    const int i0 = bx * kT, j0 = by * kT;
+    const int kp = g_prev ? st_prev->k : -1;
+    const float tp = g_prev ? st_prev->t : 0.0f;
+    // the current iterate on the window (zero outside the image, like pix())
+    for (int idx = threadIdx.x; idx < (kT + 4) * (kT + 4); idx += 256) {
+        const int li = idx % (kT + 4), lj = idx / (kT + 4);
+        const int gi = i0 - 2 + li, gj = j0 - 2 + lj;
+        float val = 0.0f;
+        if ((unsigned)gi < (unsigned)nx && (unsigned)gj < (unsigned)ny) {
+            const size_t id = (size_t)gj * nx + gi;
+            val = f[id];
+            if (g_prev) val = stepped(val, g_prev[id], kp, tp);
+        }
+        S.f[lj][li] = val;
+    }
+    __syncthreads();
+    const int ti = threadIdx.x & (kT - 1), tj = threadIdx.x / kT;
+    const int i = i0 + ti, j = j0 + tj;
+    const bool own = i < nx && j < ny;
+    if (g_prev && own) f_out[(size_t)j * nx + i] = S.f[tj + 2][ti + 2];
+    // the direction on the tile and its 1-pixel halo
+    for (int idx = threadIdx.x; idx < (kT + 2) * (kT + 2); idx += 256) {
+        const int li = idx % (kT + 2), lj = idx / (kT + 2);
+        const int gi = i0 - 1 + li, gj = j0 - 1 + lj;
+        float gv = 0.0f;
+        if ((unsigned)gi < (unsigned)nx && (unsigned)gj < (unsigned)ny) {
+            Nbhd N;
 #pragma unroll
-    for (int c = 0; c < kArmijoFirst; ++c) e[c] = 0.0;
-    if (i < nx && j < ny) candidate_energies<kArmijoFirst>(f, g, v, wx, wy, nx, ny, i, j, lambda, eps2, t0, shrink, 0, e);
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int bb = 0; bb < 3; ++bb) N.n[a][bb] = S.f[lj + bb][li + a];
+            const float c = N.n[1][1];
+            const float tR = tv_right(N, eps2), tL = tv_left(N, eps2), tU = tv_up(N, eps2), tD = tv_down(N, eps2);
+            const size_t xw = (size_t)gj * (nx + 1);
+            const float wR = wx_in ? wx_in[xw + gi + 1] : weight(tR, inv_s2);
+            const float wL = wx_in ? wx_in[xw + gi] : weight(tL, inv_s2);
+            const float wU = wy_in ? wy_in[(size_t)(gj + 1) * nx + gi] : weight(tU, inv_s2);
+            const float wD = wy_in ? wy_in[(size_t)gj * nx + gi] : weight(tD, inv_s2);
+            const float FR = wR * (N.n[2][1] - c) / tR;
+            const float FL = wL * (c - N.n[0][1]) / tL;
+            const float FU = wU * (N.n[1][2] - c) / tU;
+            const float FD = wD * (c - N.n[1][0]) / tD;
+            const size_t id = (size_t)gj * nx + gi;
+            const float dv = c - v[id];
+            gv = lambda * dv - (FR - FL) - (FU - FD);
+            if (li >= 1 && li <= kT && lj >= 1 && lj <= kT) {  // an own pixel
+                g[id] = gv;
+                if (wx) {
+                    wx[xw + gi + 1] = wR;
+                    if (gi == 0) wx[xw] = wL;
+                }
+                if (wy) {
+                    wy[(size_t)(gj + 1) * nx + gi] = wU;
+                    if (gj == 0) wy[gi] = wD;
+                }
+                float e = wR * tR + wU * tU;
+                if (gi == 0) e += wL * tL;
+                if (gj == 0) e += wD * tD;
+                S.w[0][lj - 1][li - 1] = wR;
+                S.w[1][lj - 1][li - 1] = wL;
+                S.w[2][lj - 1][li - 1] = wU;
+                S.w[3][lj - 1][li - 1] = wD;
+                S.e[lj - 1][li - 1] = e;
+                S.dv[lj - 1][li - 1] = dv;
+            }
+        }
+        S.g[lj][li] = gv;
+    }
+    __syncthreads();
+    // the partials of the direction kernel, in its thread order
+    double q = 0.0, gg = 0.0;
+    double en[kArmijoFirst];
+#pragma unroll
+    for (int c = 0; c < kArmijoFirst; ++c) en[c] = 0.0;
+    if (own) {
+        const float dv = S.dv[tj][ti], gv = S.g[tj + 1][ti + 1];
+        q = (double)S.e[tj][ti] + 0.5 * (double)lambda * (double)dv * (double)dv;
+        gg = (double)gv * (double)gv;
+        // the trial energies, as candidate_energies with the weights frozen at f
+        Nbhd F, G;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int bb = 0; bb < 3; ++bb) {
+                F.n[a][bb] = S.f[tj + 1 + bb][ti + 1 + a];
+                G.n[a][bb] = S.g[tj + bb][ti + a];
+            }
+        const float wR = S.w[0][tj][ti], wU = S.w[2][tj][ti];
+        const float wL = i == 0 ? S.w[1][tj][ti] : 0.0f, wD = j == 0 ? S.w[3][tj][ti] : 0.0f;
+        const float vv = v[(size_t)j * nx + i];
+        float t = t0;
+#pragma unroll
+        for (int c = 0; c < kArmijoFirst; ++c) {
+            Nbhd H;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int bb = 0; bb < 3; ++bb) H.n[a][bb] = fmaf(-t, G.n[a][bb], F.n[a][bb]);
+            float sm = wR * tv_right(H, eps2) + wU * tv_up(H, eps2);
+            if (i == 0) sm += wL * tv_left(H, eps2);
+            if (j == 0) sm += wD * tv_down(H, eps2);
+            const float d = H.n[1][1] - vv;
+            en[c] += (double)sm + 0.5 * (double)lambda * (double)d * (double)d;
+            t *= shrink;
+        }
+    }
+    const double qs = block_sum<256>(q, S.lds);
+    const double gs = block_sum<256>(gg, S.lds);
+    if (threadIdx.x == 0) {  // slot-major: [Q | ||g||^2][block]
+        part_grad[b] = qs;
+        part_grad[nb + b] = gs;
+    }
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
 #pragma unroll
     for (int c = 0; c < kArmijoFirst; ++c) {
-        const double sc = wave_sum(e[c]);
-        if (l == 0) red[w][c] = sc;
+        const double sc = wave_sum(en[c]);
+        if (l == 0) S.red[w][c] = sc;
     }
     __syncthreads();
     if (threadIdx.x < kArmijoFirst) {
         const int c = threadIdx.x;
-        part[(size_t)c * nb + b] = red[0][c] + red[1][c] + red[2][c] + red[3][c];
+        part_arm[(size_t)c * nb + b] = S.red[0][c] + S.red[1][c] + S.red[2][c] + S.red[3][c];
     }
 }
 
-__global__ __launch_bounds__(256) void k_armijo(const float* __restrict__ f, const float* __restrict__ g,
-                                                const float* __restrict__ v, const float* __restrict__ wx,
-                                                const float* __restrict__ wy, int nx, int ny, float lambda,
-                                                float eps2, float t0, float shrink, double* part)
+__global__ __launch_bounds__(256) void k_tv_armijo(const float* __restrict__ f, const float* __restrict__ g_prev,
+                                                   const DevState* st_prev, float* __restrict__ f_out,
+                                                   const float* __restrict__ v, int nx, int ny, float lambda,
+                                                   const DevState* st, float eps2, float* __restrict__ g, float* wx,
+                                                   float* wy, double* part_grad, double* part_arm, float t0,
+                                                   float shrink, const float* wx_in, const float* wy_in)
 {
-    __shared__ double red[4][kArmijoFirst];
-    armijo_block(f, g, v, wx, wy, nx, ny, lambda, eps2, t0, shrink, part, blockIdx.x, blockIdx.y,
-                 blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y, red);
+    __shared__ TvArmShared S;
+    tv_armijo_block(f, g_prev, st_prev, f_out, v, nx, ny, lambda, st, eps2, g, wx, wy, part_grad, part_arm, t0,
+                    shrink, blockIdx.x, blockIdx.y, blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y, S,
+                    wx_in, wy_in);
+}
+
+hipError_t launch_tv_armijo(const Plan& p, const float* f, const float* g_prev, const DevState* st_prev,
+                            float* f_out, const float* v, float lambda, const DevState* st, float eps2, float* g,
+                            float* wx, float* wy, double* part_grad, double* part_arm, float t0, float shrink,
+                            hipStream_t s, const float* wx_in, const float* wy_in)
+{
+    dim3 grid((p.nx + kT - 1) / kT, (p.ny + kT - 1) / kT);
+    hipLaunchKernelGGL(k_tv_armijo, grid, dim3(256), 0, s, f, g_prev, st_prev, f_out, v, p.nx, p.ny, lambda, st,
+                       eps2, g, wx, wy, part_grad, part_arm, t0, shrink, wx_in, wy_in);
+    return hipGetLastError();
 }
 
 int armijo_blocks(const Plan& p) { return ((p.nx + kT - 1) / kT) * ((p.ny + kT - 1) / kT); }
 
-hipError_t launch_armijo(const Plan& p, const float* f, const float* g, const float* v, const float* wx,
-                         const float* wy, float lambda, float eps2, float t0, float shrink, double* part,
-                         hipStream_t s)
-{
-    dim3 grid((p.nx + kT - 1) / kT, (p.ny + kT - 1) / kT);
-    hipLaunchKernelGGL(k_armijo, grid, dim3(256), 0, s, f, g, v, wx, wy, p.nx, p.ny, lambda, eps2, t0, shrink, part);
-    return hipGetLastError();
-}
 
 // The Armijo decision: the first candidate with Q_k <= Q0 - c t_k ||g||^2.
 // One block of 256 threads closes Q0, ||g||^2 (gradient kernel's partials)
@@ -838,54 +970,31 @@ hipError_t blaunch_select_finalize(const BatchDev& b, int pass, float floor_, hi
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void kb_tv_grad(const SliceDev* __restrict__ sl, const int2* __restrict__ items,
-                                                  int n_items, int fs, int gps, int fos, int vs, float lambda,
-                                                  float eps2, int gs)
+__global__ __launch_bounds__(256) void kb_tv_armijo(const SliceDev* __restrict__ sl, const int2* __restrict__ items,
+                                                    int n_items, int fs, int gps, int fos, int vs, float lambda,
+                                                    float eps2, int gs, float t0, float shrink)
 {
-    __shared__ double lds[4];
+    __shared__ TvArmShared S;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 w = items[it];
         const SliceDev& d = sl[w.x];
         __syncthreads();
-        tv_grad_block(d.buf[fs], bsel(d, gps), d.st, bsel(d, fos), d.buf[vs], d.nx, d.ny, lambda, d.st, 0.0f, eps2,
-                      d.buf[gs], d.buf[kBufWX], d.buf[kBufWY], d.part[kPartGrad], w.y % d.t16x, w.y / d.t16x, w.y,
-                      d.t16x * d.t16y, lds);
+        tv_armijo_block(d.buf[fs], bsel(d, gps), d.st, bsel(d, fos), d.buf[vs], d.nx, d.ny, lambda, d.st, eps2,
+                        d.buf[gs], d.buf[kBufWX], d.buf[kBufWY], d.part[kPartGrad], d.part[kPartArm], t0, shrink,
+                        w.y % d.t16x, w.y / d.t16x, w.y, d.t16x * d.t16y, S);
     }
 }
 
-hipError_t blaunch_tv_grad(const BatchDev& b, int f, int g_prev, int f_out, int v, float lambda, float eps2, int g,
-                           hipStream_t s)
+hipError_t blaunch_tv_armijo(const BatchDev& b, int f, int g_prev, int f_out, int v, float lambda, float eps2, int g,
+                             float t0, float shrink, hipStream_t s)
 {
     const int n = b.n_items[kShT16];
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(kb_tv_grad, dim3(b.grid[kShT16]), dim3(256), 0, s, b.slices, b.items[kShT16], n, f, g_prev,
-                       f_out, v, lambda, eps2, g);
+    hipLaunchKernelGGL(kb_tv_armijo, dim3(b.grid[kShT16]), dim3(256), 0, s, b.slices, b.items[kShT16], n, f, g_prev,
+                       f_out, v, lambda, eps2, g, t0, shrink);
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void kb_armijo(const SliceDev* __restrict__ sl, const int2* __restrict__ items,
-                                                 int n_items, int fs, int gs, int vs, float lambda, float eps2, float t0,
-                                                 float shrink)
-{
-    __shared__ double red[4][kArmijoFirst];
-    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
-        const int2 w = items[it];
-        const SliceDev& d = sl[w.x];
-        __syncthreads();
-        armijo_block(d.buf[fs], d.buf[gs], d.buf[vs], d.buf[kBufWX], d.buf[kBufWY], d.nx, d.ny, lambda, eps2, t0,
-                     shrink, d.part[kPartArm], w.y % d.t16x, w.y / d.t16x, w.y, d.t16x * d.t16y, red);
-    }
-}
-
-hipError_t blaunch_armijo(const BatchDev& b, int f, int g, int v, float lambda, float eps2, float t0, float shrink,
-                          hipStream_t s)
-{
-    const int n = b.n_items[kShT16];
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(kb_armijo, dim3(b.grid[kShT16]), dim3(256), 0, s, b.slices, b.items[kShT16], n, f, g, v, lambda,
-                       eps2, t0, shrink);
-    return hipGetLastError();
-}
 
 // one block per slice
 __global__ __launch_bounds__(kDecThreads) void kb_armijo_decide(const SliceDev* __restrict__ sl, int max_bt,
