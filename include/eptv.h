@@ -97,6 +97,11 @@ typedef struct {
     int interp_bp;       /* 1: P1 uses the Eq. 11 interpolating backprojector in place
                             of P^T (the paper's on-the-fly code, Sec. 2.3); 0: the
                             exact transpose */
+    int check_every;     /* with stop_rmse > 0 and f_ref given: read the RMSE to f_ref
+                            back after every check_every-th outer iteration (0 = 1) */
+    double stop_rmse;    /* > 0: stop at the first checked iteration whose RMSE to
+                            f_ref is <= stop_rmse (the paper's iteration count is
+                            case-dependent, Sec. 2.2); 0: run outer_iters */
 } eptv_params;
 
 /* Optional per-iteration records, host arrays filled when a call that takes
@@ -107,6 +112,8 @@ typedef struct {
     int32_t* cgls_steps; /* [K]   CGLS steps actually run (breakdown stops early) */
     double* cgls_resid;  /* [K]   ||y - P v||^2 at the end of each CGLS P1 */
     double* rmse;        /* [K]   root-mean-square difference to f_ref, if given */
+    int32_t* iters_run;  /* [1]   outer iterations actually run (fewer than K after an
+                            early stop); the arrays above hold that many entries */
 } eptv_stats;
 
 typedef struct eptv_plan_s* eptv_plan;
@@ -224,6 +231,15 @@ int eptv_tv_step(eptv_plan plan, const eptv_params* params, float* f, const floa
 int eptv_reconstruct(eptv_plan plan, const eptv_params* params, const float* y, float* f,
                      const float* f_ref, void* ws, size_t ws_bytes, eptv_stats* stats, void* stream);
 
+/* eptv_reconstruct with the Armijo decisions given: armijo_replay (host,
+ * [K*T] backtrack indices in -1 .. armijo_max_backtracks, -1 = no step) is
+ * taken instead of the search in every descent step (the line search of
+ * Sec. 2.2 with a recorded outcome), e.g. to follow another implementation's
+ * trajectory through near-ties.  EPTV_ERR_ARG for indices out of range. */
+int eptv_reconstruct_replay(eptv_plan plan, const eptv_params* params, const float* y, float* f,
+                            const float* f_ref, const int32_t* armijo_replay, void* ws, size_t ws_bytes,
+                            eptv_stats* stats, void* stream);
+
 /* eptv_reconstruct with given half-edge weights: during the first
  * frozen_iters outer iterations P2 uses wx [ny][nx+1] / wy [ny+1][nx]
  * (device, the layout of eptv_tv_gradient's weights) in place of Eq. 5's
@@ -241,8 +257,8 @@ int eptv_reconstruct_weighted(eptv_plan plan, const eptv_params* params, const f
  * and one outer iteration of all slices is one captured graph.  Each slice's
  * arithmetic is that of eptv_reconstruct on its own plan; with the
  * projector's launch shape at 16 segments (the one-slice default) the images
- * are identical bit for bit.  The stored-matrix and Eq. 11 variants are
- * one-slice only (EPTV_ERR_ARG here). */
+ * are identical bit for bit.  The stored-matrix and Eq. 11 variants and the
+ * early stop are one-slice only (EPTV_ERR_ARG here). */
 typedef struct eptv_batch_s* eptv_batch;
 
 /* One plan per geometry (geoms[0 .. n_slices-1]); owns them. */

@@ -286,28 +286,26 @@ def time_to_rmse(P: E.Plan, y: torch.Tensor, ref: torch.Tensor, target: float, n
                  frozen_iters: int = 1, max_iters: int = 100, reps: int = 3, n0: int = N0):
     """Seconds (best of ``reps``, HIP events on the current stream) until the
     RMSE to ``ref`` is <= target: plain EPTV from zero, or (with ``net``) the
-    assisted pipeline.  The iteration count comes from an untimed run with
-    the per-iteration RMSE record; the timed run records it too."""
-    if net is None:
-        _, st = P.reconstruct(y, E.Params(outer_iters=max_iters, zero_init=1, **SOLVER), f_ref=ref)
-    else:
-        _, st = assisted_reconstruct(P, net, y, max_iters, frozen_iters, n0=n0, f_ref=ref)
-    hit = np.nonzero(st["rmse"] <= target)[0]
-    if hit.size == 0:
-        return {"iterations": None, "seconds": None, "rmse_min": float(st["rmse"].min())}
-    k = int(hit[0]) + 1
+    assisted pipeline.  The runs stop themselves (``stop_rmse``, the RMSE
+    record read back after every iteration), so the time includes each
+    iteration's check."""
     s = torch.cuda.current_stream()
-    best = None
+    best, st = None, None
     for _ in range(reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record(s)
         if net is None:
-            f, _ = P.reconstruct(y, E.Params(outer_iters=k, zero_init=1, **SOLVER), f_ref=ref, stats=False)
+            _, st = P.reconstruct(y, E.Params(outer_iters=max_iters, zero_init=1, stop_rmse=target, **SOLVER),
+                                  f_ref=ref)
         else:
-            f, _ = assisted_reconstruct(P, net, y, k, frozen_iters, n0=n0, f_ref=ref, stats=False)
+            _, st = assisted_reconstruct(P, net, y, max_iters, frozen_iters, n0=n0, f_ref=ref,
+                                         solver={"stop_rmse": target})
         e1.record(s)
         torch.cuda.synchronize()
         sec = e0.elapsed_time(e1) / 1e3
         best = sec if best is None else min(best, sec)
+    k = st["iters_run"]
+    if st["rmse"][k - 1] > target:
+        return {"iterations": None, "seconds": None, "rmse_min": float(st["rmse"].min())}
     return {"iterations": k, "seconds": best, "rmse": float(st["rmse"][k - 1])}

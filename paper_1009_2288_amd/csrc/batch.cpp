@@ -425,7 +425,7 @@ int eptv_batch_reconstruct(eptv_batch b, const eptv_params* q, const float* cons
     if (!b || !y || !f) return EPTV_ERR_ARG;
     int rc = check_params(q);
     if (rc != EPTV_OK) return rc;
-    if (q->stored_matrix || q->interp_bp) return EPTV_ERR_ARG;  // one-slice variants only
+    if (q->stored_matrix || q->interp_bp || q->stop_rmse > 0) return EPTV_ERR_ARG;  // one-slice variants only
     for (int i = 0; i < b->bd.n; ++i)
         if (!y[i] || !f[i] || (f_ref && !f_ref[i])) return EPTV_ERR_ARG;
     if (!ws || ((uintptr_t)ws & 255)) return EPTV_ERR_WORKSPACE;

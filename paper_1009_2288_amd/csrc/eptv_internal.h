@@ -229,7 +229,8 @@ hipError_t launch_tv_armijo(const Plan& p, const float* f, const float* g_prev, 
 hipError_t launch_armijo_decide(const Plan& p, DevState* st, const double* part_grad, const double* part_arm,
                                 int max_bt, double c_arm, float t0, float shrink, int32_t* st_k, int step, int T,
                                 const float* f, const float* g, const float* v, const float* wx, const float* wy,
-                                float lambda, float eps2, hipStream_t s);
+                                float lambda, float eps2, hipStream_t s,
+                                int replay = 0);
 hipError_t launch_p2_update(const Plan& p, const DevState* st, const float* fcur, const float* g,
                             float* fout, float* foutT, int clamp, hipStream_t s);
 hipError_t launch_copy_clamp(const Plan& p, const float* src, float* dst, float* dstT, int clamp,

@@ -152,6 +152,7 @@ int check_params(const eptv_params* q)
     if ((long long)q->outer_iters * q->tv_iters > (1LL << 28)) return EPTV_ERR_ARG;
     if ((q->stored_matrix != 0 && q->stored_matrix != 1) || (q->interp_bp != 0 && q->interp_bp != 1))
         return EPTV_ERR_ARG;
+    if (q->check_every < 0 || !(q->stop_rmse >= 0) || !std::isfinite(q->stop_rmse)) return EPTV_ERR_ARG;
     return EPTV_OK;
 }
 
@@ -172,6 +173,7 @@ struct Ctx {
     const float* f_ref;
     const float* wx_in = nullptr;  // given half-edge weights for P2 (frozen iterations), or null
     const float* wy_in = nullptr;
+    int replay = 0;                // 1: the Armijo decisions come from the step records (uploaded by the caller)
 };
 
 float t0_of(const eptv_params& q)
@@ -204,7 +206,7 @@ float sigma_init(const eptv_params& q) { return q.sigma_fixed < 0 ? -1.0f : (flo
 
 static hipError_t enqueue_p2(const Plan& p, Workspace& W, const eptv_params& q, const float* start, const float* v,
                              int n_steps, float* fout, float* foutT, int clamp, int32_t* st_k, hipStream_t s,
-                             const float* wx_in = nullptr, const float* wy_in = nullptr)
+                             const float* wx_in = nullptr, const float* wy_in = nullptr, int replay = 0)
 {
     hipError_t e;
     const float eps2 = (float)(q.tv_eps * q.tv_eps);
@@ -222,8 +224,8 @@ static hipError_t enqueue_p2(const Plan& p, Workspace& W, const eptv_params& q, 
             return e;
         if (t > 0) fcur = fnext;
         if ((e = launch_armijo_decide(p, W.st, W.part_grad, W.part_arm, q.armijo_max_backtracks, q.armijo_c, t0,
-                                      shrink, st_k, t, n_steps, fcur, g, v, W.wx, W.wy, (float)q.lambda, eps2, s)) !=
-            hipSuccess)
+                                      shrink, st_k, t, n_steps, fcur, g, v, W.wx, W.wy, (float)q.lambda, eps2, s,
+                                      replay)) != hipSuccess)
             return e;
     }
     if (n_steps == 0) return launch_copy_clamp(p, start, fout, foutT, clamp, s);
@@ -280,7 +282,8 @@ static hipError_t enqueue_iteration(const Ctx& c, hipStream_t s)
             return e;
     }
     // Step 3 (positivity) is fused into the last descent update.
-    if ((e = enqueue_p2(p, W, q, start, W.u, T, c.f, W.fT, q.positivity, W.st_k, s, c.wx_in, c.wy_in)) != hipSuccess)
+    if ((e = enqueue_p2(p, W, q, start, W.u, T, c.f, W.fT, q.positivity, W.st_k, s, c.wx_in, c.wy_in, c.replay)) !=
+        hipSuccess)
         return e;
     if (c.f_ref) {
         if ((e = launch_rmse_part(p, c.f, c.f_ref, W.part_rmse, s)) != hipSuccess) return e;
@@ -617,8 +620,8 @@ int eptv_tv_step(eptv_plan h, const eptv_params* q, float* f, const float* v, fl
 }
 
 static int reconstruct_impl(eptv_plan h, const eptv_params* q, const float* y, float* f, const float* f_ref,
-                            const float* wx_in, const float* wy_in, int frozen, void* ws, size_t ws_bytes,
-                            eptv_stats* stats, void* stream)
+                            const float* wx_in, const float* wy_in, int frozen, const int32_t* replay, void* ws,
+                            size_t ws_bytes, eptv_stats* stats, void* stream)
 {
     if (!h || !y || !f) return EPTV_ERR_ARG;
     int rc = check_params(q);
@@ -632,17 +635,44 @@ static int reconstruct_impl(eptv_plan h, const eptv_params* q, const float* y, f
     const int K = q->outer_iters, T = q->tv_iters;
     frozen = std::min(std::max(frozen, 0), K);
 
+    if (replay) {
+        for (size_t i = 0; i < (size_t)K * T; ++i)
+            if (replay[i] < -1 || replay[i] > q->armijo_max_backtracks) return EPTV_ERR_ARG;
+    }
+    const bool stop = f_ref && q->stop_rmse > 0;
+    const int every = std::max(1, q->check_every);
+
     EPTV_HIP(launch_state_init(W.st, W.hist, select_rank(p, q->edge_quantile), sigma_init(*q), 1, s));
     if (q->zero_init) EPTV_HIP(launch_fill(f, (size_t)p.nx * p.ny, 0.0f, s));
     EPTV_HIP(launch_transpose(f, W.fT, p.nx, p.ny, s));
+    // replay: the decisions are read back from the step records
+    if (replay && (size_t)K * T)
+        EPTV_HIP(hipMemcpyAsync(W.st_k, replay, (size_t)K * T * 4, hipMemcpyHostToDevice, s));
 
     Ctx c{p, W, *q, y, f, f_ref};
+    c.replay = replay ? 1 : 0;
     Ctx cw{p, W, *q, y, f, f_ref, wx_in, wy_in};
+    int done = 0;          // iterations run so far
+    bool stopped = false;  // the RMSE reached stop_rmse at a check
+    // after each iteration: every check_every-th one, read its RMSE record back
+    auto check = [&]() -> int {
+        ++done;
+        if (!stop || done % every) return EPTV_OK;
+        double r = 0.0;
+        EPTV_HIP(hipMemcpyAsync(&r, W.st_rmse + (done - 1), sizeof r, hipMemcpyDeviceToHost, s));
+        EPTV_HIP(hipStreamSynchronize(s));
+        if (r <= q->stop_rmse) stopped = true;
+        return EPTV_OK;
+    };
     // one captured graph per kind of iteration (adaptive, or with the given weights)
     auto run = [&](const Ctx& cc, int count, hipGraphExec_t& gexec, std::vector<uint64_t>& gkey) -> int {
-        if (count <= 0) return EPTV_OK;
+        if (count <= 0 || stopped) return EPTV_OK;
         if (no_graph()) {
-            for (int k = 0; k < count; ++k) EPTV_HIP(enqueue_iteration(cc, s));
+            for (int k = 0; k < count && !stopped; ++k) {
+                EPTV_HIP(enqueue_iteration(cc, s));
+                const int rc_ = check();
+                if (rc_ != EPTV_OK) return rc_;
+            }
             return EPTV_OK;
         }
         std::vector<uint64_t> key;
@@ -658,7 +688,8 @@ static int reconstruct_impl(eptv_plan h, const eptv_params* q, const float* y, f
         qk.outer_iters = 0;
         qk.zero_init = 0;
         put(&qk, sizeof qk);
-        const void* ptrs[7] = {ws, y, f, f_ref, (const void*)(uintptr_t)ws_bytes, cc.wx_in, cc.wy_in};
+        const void* ptrs[8] = {ws, y, f, f_ref, (const void*)(uintptr_t)ws_bytes, cc.wx_in, cc.wy_in,
+                               (const void*)(uintptr_t)cc.replay};
         put(ptrs, sizeof ptrs);
         if (!gexec || key != gkey) {
             if (gexec) {
@@ -682,7 +713,11 @@ static int reconstruct_impl(eptv_plan h, const eptv_params* q, const float* y, f
             }
             gkey = key;
         }
-        for (int k = 0; k < count; ++k) EPTV_HIP(hipGraphLaunch(gexec, s));
+        for (int k = 0; k < count && !stopped; ++k) {
+            EPTV_HIP(hipGraphLaunch(gexec, s));
+            const int rc_ = check();
+            if (rc_ != EPTV_OK) return rc_;
+        }
         return EPTV_OK;
     };
     {
@@ -692,7 +727,8 @@ static int reconstruct_impl(eptv_plan h, const eptv_params* q, const float* y, f
     }
     if (rc != EPTV_OK) return rc;
     if (stats) {
-        const size_t kk = (size_t)K;
+        const size_t kk = (size_t)done;  // the records of the iterations that ran
+        if (stats->iters_run) *stats->iters_run = done;
         if (kk) {
             if (stats->sigma) EPTV_HIP(hipMemcpyAsync(stats->sigma, W.st_sigma, kk * 4, hipMemcpyDeviceToHost, s));
             if (stats->armijo_k && T > 0)
@@ -711,7 +747,15 @@ static int reconstruct_impl(eptv_plan h, const eptv_params* q, const float* y, f
 int eptv_reconstruct(eptv_plan h, const eptv_params* q, const float* y, float* f, const float* f_ref, void* ws,
                      size_t ws_bytes, eptv_stats* stats, void* stream)
 {
-    return reconstruct_impl(h, q, y, f, f_ref, nullptr, nullptr, 0, ws, ws_bytes, stats, stream);
+    return reconstruct_impl(h, q, y, f, f_ref, nullptr, nullptr, 0, nullptr, ws, ws_bytes, stats, stream);
+}
+
+int eptv_reconstruct_replay(eptv_plan h, const eptv_params* q, const float* y, float* f, const float* f_ref,
+                            const int32_t* armijo_replay, void* ws, size_t ws_bytes, eptv_stats* stats,
+                            void* stream)
+{
+    if (!armijo_replay) return EPTV_ERR_ARG;
+    return reconstruct_impl(h, q, y, f, f_ref, nullptr, nullptr, 0, armijo_replay, ws, ws_bytes, stats, stream);
 }
 
 int eptv_reconstruct_weighted(eptv_plan h, const eptv_params* q, const float* y, float* f, const float* f_ref,
@@ -719,7 +763,7 @@ int eptv_reconstruct_weighted(eptv_plan h, const eptv_params* q, const float* y,
                               eptv_stats* stats, void* stream)
 {
     if (!wx || !wy || frozen_iters < 0) return EPTV_ERR_ARG;
-    return reconstruct_impl(h, q, y, f, f_ref, wx, wy, frozen_iters, ws, ws_bytes, stats, stream);
+    return reconstruct_impl(h, q, y, f, f_ref, wx, wy, frozen_iters, nullptr, ws, ws_bytes, stats, stream);
 }
 
 }  // extern "C"

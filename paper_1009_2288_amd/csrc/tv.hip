@@ -638,7 +638,7 @@ __device__ __forceinline__ void armijo_decide_block(DevState* st, const double* 
                                                     int nb, int max_bt, double c_arm, float t0, float shrink,
                                                     int32_t* st_k, int step, int T, const float* f, const float* g,
                                                     const float* v, const float* wx, const float* wy, int nx, int ny,
-                                                    float lambda, float eps2, DecShared& S)
+                                                    float lambda, float eps2, DecShared& S, int replay = 0)
 {
     double (*red)[kDecThreads] = S.red;
     double* tot = S.tot;
@@ -656,17 +656,21 @@ __device__ __forceinline__ void armijo_decide_block(DevState* st, const double* 
     const double q0 = tot[kArmijoFirst], g2 = tot[kArmijoFirst + 1];
     if (threadIdx.x == 0) {
         int kk = -1;
-        for (int k = 0; k < kArmijoFirst && k <= max_bt; ++k)
-            if (tot[k] <= q0 - c_arm * (double)cand_t(t0, shrink, k) * g2) {
-                kk = k;
-                break;
-            }
+        if (replay) {  // the caller's decision, recorded for this step (-1: no step)
+            kk = st_k[(size_t)st->iter * T + step];
+        } else {
+            for (int k = 0; k < kArmijoFirst && k <= max_bt; ++k)
+                if (tot[k] <= q0 - c_arm * (double)cand_t(t0, shrink, k) * g2) {
+                    kk = k;
+                    break;
+                }
+        }
         verdict = kk;
     }
     __syncthreads();
     int kk = verdict;
     // rare: continue the backtracking over the whole image in this block
-    for (int k0 = kArmijoFirst; kk < 0 && k0 <= max_bt; k0 += kArmijoMore) {
+    for (int k0 = kArmijoFirst; !replay && kk < 0 && k0 <= max_bt; k0 += kArmijoMore) {
         double e[kArmijoMore];
 #pragma unroll
         for (int c = 0; c < kArmijoMore; ++c) e[c] = 0.0;
@@ -700,20 +704,21 @@ __global__ __launch_bounds__(kDecThreads) void k_armijo_decide(DevState* st, con
                                                                double c_arm, float t0, float shrink, int32_t* st_k,
                                                                int step, int T, const float* f, const float* g,
                                                                const float* v, const float* wx, const float* wy,
-                                                               int nx, int ny, float lambda, float eps2)
+                                                               int nx, int ny, float lambda, float eps2, int replay)
 {
     __shared__ DecShared S;
     armijo_decide_block(st, part_grad, part_arm, nb, max_bt, c_arm, t0, shrink, st_k, step, T, f, g, v, wx, wy, nx,
-                        ny, lambda, eps2, S);
+                        ny, lambda, eps2, S, replay);
 }
 
 hipError_t launch_armijo_decide(const Plan& p, DevState* st, const double* part_grad, const double* part_arm,
                                 int max_bt, double c_arm, float t0, float shrink, int32_t* st_k, int step, int T,
                                 const float* f, const float* g, const float* v, const float* wx, const float* wy,
-                                float lambda, float eps2, hipStream_t s)
+                                float lambda, float eps2, hipStream_t s, int replay)
 {
     hipLaunchKernelGGL(k_armijo_decide, dim3(1), dim3(kDecThreads), 0, s, st, part_grad, part_arm, armijo_blocks(p),
-                       max_bt, c_arm, t0, shrink, st_k, step, T, f, g, v, wx, wy, p.nx, p.ny, lambda, eps2);
+                       max_bt, c_arm, t0, shrink, st_k, step, T, f, g, v, wx, wy, p.nx, p.ny, lambda, eps2,
+                       replay && st_k ? 1 : 0);
     return hipGetLastError();
 }
 

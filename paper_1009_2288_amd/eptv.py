@@ -30,7 +30,7 @@ SYMBOLS = ["eptv_plan_create", "eptv_plan_destroy", "eptv_plan_nnz", "eptv_works
            "eptv_batch_reconstruct", "eptv_unet_create", "eptv_unet_destroy", "eptv_unet_param_count",
            "eptv_unet_set_params", "eptv_unet_get_params", "eptv_unet_get_grads", "eptv_unet_forward",
            "eptv_unet_backward", "eptv_unet_adam", "eptv_unet_mse", "eptv_reconstruct_weighted",
-           "eptv_maps_from_eptv", "eptv_maps_to_eptv"]
+           "eptv_maps_from_eptv", "eptv_maps_to_eptv", "eptv_reconstruct_replay"]
 
 
 class EptvError(RuntimeError):
@@ -55,13 +55,14 @@ class _Params(C.Structure):
                 ("sigma_fixed", C.c_double), ("sigma_floor", C.c_double), ("tv_eps", C.c_double),
                 ("armijo_c", C.c_double), ("armijo_shrink", C.c_double), ("armijo_t0", C.c_double),
                 ("armijo_max_backtracks", C.c_int), ("p2_start", C.c_int), ("positivity", C.c_int),
-                ("stored_matrix", C.c_int), ("interp_bp", C.c_int)]
+                ("stored_matrix", C.c_int), ("interp_bp", C.c_int), ("check_every", C.c_int),
+                ("stop_rmse", C.c_double)]
 
 
 class _Stats(C.Structure):
     _fields_ = [("sigma", C.POINTER(C.c_float)), ("armijo_k", C.POINTER(C.c_int32)),
                 ("cgls_steps", C.POINTER(C.c_int32)), ("cgls_resid", C.POINTER(C.c_double)),
-                ("rmse", C.POINTER(C.c_double))]
+                ("rmse", C.POINTER(C.c_double)), ("iters_run", C.POINTER(C.c_int32))]
 
 
 @dataclass
@@ -86,6 +87,8 @@ class Params:
     positivity: int = 1
     stored_matrix: int = 0
     interp_bp: int = 0
+    check_every: int = 1
+    stop_rmse: float = 0.0
 
     def _c(self) -> _Params:
         d = asdict(self)
@@ -137,6 +140,8 @@ def _lib() -> C.CDLL:
         L.eptv_select_sigma.argtypes = [vp, vp, C.c_double, C.c_float, C.c_float, vp, vp, sz, vp]
         L.eptv_tv_step.argtypes = [vp, C.POINTER(_Params), vp, vp, C.c_float, C.c_int, vp, sz, C.POINTER(_Stats), vp]
         L.eptv_reconstruct.argtypes = [vp, C.POINTER(_Params), vp, vp, vp, vp, sz, C.POINTER(_Stats), vp]
+        L.eptv_reconstruct_replay.argtypes = [vp, C.POINTER(_Params), vp, vp, vp, C.POINTER(C.c_int32), vp, sz,
+                                              C.POINTER(_Stats), vp]
         L.eptv_reconstruct_weighted.argtypes = [vp, C.POINTER(_Params), vp, vp, vp, vp, vp, C.c_int, vp, sz,
                                                 C.POINTER(_Stats), vp]
         L.eptv_geometry_matrix.argtypes = [C.POINTER(_Geometry), C.POINTER(C.c_longlong), vp, vp, vp]
@@ -388,10 +393,13 @@ class Plan:
 
     def reconstruct(self, y: torch.Tensor, params: Params, f: Optional[torch.Tensor] = None,
                     f_ref: Optional[torch.Tensor] = None, stats: bool = True, stream=None, weights=None,
-                    frozen_iters: int = 0):
-        """Run params.outer_iters EPTV iterations; returns (f, stats dict or None).
+                    frozen_iters: int = 0, armijo_replay=None):
+        """Run params.outer_iters EPTV iterations (fewer after an early stop,
+        params.stop_rmse); returns (f, stats dict or None).
         weights: optional (wx [ny][nx+1], wy [ny+1][nx]) device tensors used in
-        place of Eq. 5's weights during the first frozen_iters iterations."""
+        place of Eq. 5's weights during the first frozen_iters iterations.
+        armijo_replay: optional [K][T] backtrack indices taken instead of the
+        line search (eptv_reconstruct_replay)."""
         import numpy as np
         y = self._sino(y, "y")
         if f is None:
@@ -403,6 +411,7 @@ class Plan:
         K, T = params.outer_iters, params.tv_iters
         rec = None
         stp = None
+        done = np.zeros(1, np.int32)
         if stats:
             rec = {"sigma": np.zeros(max(K, 1), np.float32), "armijo_k": np.zeros(max(K * T, 1), np.int32),
                    "cgls_steps": np.zeros(max(K, 1), np.int32), "cgls_resid": np.zeros(max(K, 1)),
@@ -411,10 +420,21 @@ class Plan:
                         rec["armijo_k"].ctypes.data_as(C.POINTER(C.c_int32)),
                         rec["cgls_steps"].ctypes.data_as(C.POINTER(C.c_int32)),
                         rec["cgls_resid"].ctypes.data_as(C.POINTER(C.c_double)),
-                        rec["rmse"].ctypes.data_as(C.POINTER(C.c_double)))
+                        rec["rmse"].ctypes.data_as(C.POINTER(C.c_double)),
+                        done.ctypes.data_as(C.POINTER(C.c_int32)))
             stp = C.byref(st)
         cp = params._c()
-        if weights is not None:
+        if armijo_replay is not None:
+            if weights is not None:
+                raise ValueError("armijo_replay and weights cannot be combined")
+            rp = np.ascontiguousarray(np.asarray(armijo_replay, dtype=np.int32).reshape(-1))
+            if rp.size != K * T:
+                raise ValueError(f"armijo_replay must hold outer_iters * tv_iters = {K * T} indices")
+            _check(_lib().eptv_reconstruct_replay(self._h, C.byref(cp), y.data_ptr(), f.data_ptr(),
+                                                  f_ref.data_ptr() if f_ref is not None else None,
+                                                  rp.ctypes.data_as(C.POINTER(C.c_int32)), ws.data_ptr(),
+                                                  ws.numel(), stp, _stream(stream)), "eptv_reconstruct_replay")
+        elif weights is not None:
             wx = self._t(weights[0], (self.ny, self.nx + 1), "wx")
             wy = self._t(weights[1], (self.ny + 1, self.nx), "wy")
             _check(_lib().eptv_reconstruct_weighted(self._h, C.byref(cp), y.data_ptr(), f.data_ptr(),
@@ -426,8 +446,9 @@ class Plan:
                                            f_ref.data_ptr() if f_ref is not None else None, ws.data_ptr(),
                                            ws.numel(), stp, _stream(stream)), "eptv_reconstruct")
         if rec is not None:
-            rec = {k: v[:K].copy() for k, v in rec.items() if k != "armijo_k"} | {
-                "armijo_k": rec["armijo_k"][:K * T].reshape(K, T).copy()}
+            n = int(done[0])  # iterations run (an early stop leaves fewer than K records)
+            rec = {k: v[:n].copy() for k, v in rec.items() if k != "armijo_k"} | {
+                "armijo_k": rec["armijo_k"][:n * T].reshape(n, T).copy(), "iters_run": n}
             if f_ref is None:
                 rec.pop("rmse")
         return f, rec

@@ -446,3 +446,48 @@ def test_reconstruct_with_given_weights(E, oracle, frozen):
     assert np.array_equal(sg["armijo_k"], so["armijo_k"])
     assert np.all(sg["sigma"][:frozen] == -1.0)
     assert rel(f.cpu().numpy(), fo) <= 1e-4
+
+
+def test_early_stop_at_the_rmse_target(E):
+    """stop_rmse: the run ends at the first checked iteration whose RMSE record
+    is at or below the target, with the image of a run of exactly that many
+    iterations; with check_every = 4 only every 4th record is looked at."""
+    c = synth.make_case("small", 0)
+    P = plan(E, "small")
+    y, ref = dev(c.y.astype(np.float32)), dev(c.phantom)
+    K = 50
+    _, full = P.reconstruct(y, E.Params(outer_iters=K, lam=1000.0), f_ref=ref)
+    target = float(np.sort(full["rmse"])[K // 3])
+    hit = int(np.nonzero(full["rmse"] <= target)[0][0]) + 1
+    f1, s1 = P.reconstruct(y, E.Params(outer_iters=K, lam=1000.0, stop_rmse=target), f_ref=ref)
+    assert s1["iters_run"] == hit and hit < K
+    f2, _ = P.reconstruct(y, E.Params(outer_iters=hit, lam=1000.0), f_ref=ref)
+    assert torch.equal(f1, f2)
+    np.testing.assert_array_equal(s1["rmse"], full["rmse"][:hit])
+    _, s4 = P.reconstruct(y, E.Params(outer_iters=K, lam=1000.0, stop_rmse=target, check_every=4), f_ref=ref)
+    checked = [k for k in range(4, K + 1, 4) if full["rmse"][k - 1] <= target]
+    assert s4["iters_run"] == (checked[0] if checked else K)
+    # no reference image: nothing to check, the full count runs
+    _, s0 = P.reconstruct(y, E.Params(outer_iters=7, lam=1000.0, stop_rmse=target))
+    assert s0["iters_run"] == 7
+
+
+def test_replay_of_recorded_decisions(E):
+    """eptv_reconstruct_replay: the recorded decisions reproduce the free run
+    bit for bit; a changed decision is taken as given; out-of-range indices
+    are rejected."""
+    c = synth.make_case("small", 1)
+    P = plan(E, "small")
+    y = dev(c.y.astype(np.float32))
+    prm = E.Params(outer_iters=6, lam=1000.0)
+    f1, s1 = P.reconstruct(y, prm)
+    f2, s2 = P.reconstruct(y, prm, armijo_replay=s1["armijo_k"])
+    assert torch.equal(f1, f2)
+    assert np.array_equal(s2["armijo_k"], s1["armijo_k"])
+    alt = s1["armijo_k"].copy()
+    alt[2, 0] += 1
+    f3, s3 = P.reconstruct(y, prm, armijo_replay=alt)
+    assert np.array_equal(s3["armijo_k"], alt)
+    assert not torch.equal(f3, f1)
+    with pytest.raises(E.EptvError):
+        P.reconstruct(y, prm, armijo_replay=np.full_like(alt, 21))
