@@ -239,7 +239,8 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--kernel-reps", type=int, default=200)
-    ap.add_argument("--cpu-iters", type=int, default=50)
+    ap.add_argument("--cpu-iters", type=int, default=120,
+                    help="outer iterations of the FP64 oracle for cpu_baseline (~10 s on 16 host threads)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rmse-seeds", type=int, default=10, help="seeds for the time-to-RMSE leg (0 to skip)")
     ap.add_argument("--batch-slices", type=int, default=64, help="slices of the batched leg (0 to skip)")
