@@ -85,6 +85,23 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def achievable_hbm(torch, mib: int = 2048, reps: int = 10) -> float:
+    """Bytes per second of a device-to-device copy of `mib` MiB (read + write)."""
+    src = torch.empty(mib * 2**18, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    sec = a.elapsed_time(b) / 1e3 / reps
+    del src, dst
+    return 2.0 * mib * 2**20 / sec
+
+
 def kernel_avg_ms(fn, reps, torch):
     s = torch.cuda.current_stream()
     fn()
@@ -115,7 +132,7 @@ def cpu_baseline(case, iters):
             "seconds": dt}
 
 
-def time_to_rmse(E, synth, P, torch, np, seeds):
+def time_to_rmse(E, synth, P, torch, np, seeds, solver):
     """Seconds until the RMSE to the phantom reaches the FP64 oracle's RMSE
     after 100 iterations (tests/golden/rmse_targets_paper.json), the
     device-side RMSE record included in the timed run; median over seeds.
@@ -133,9 +150,9 @@ def time_to_rmse(E, synth, P, torch, np, seeds):
         y = torch.from_numpy(c.y.astype(np.float32)).cuda()
         ref = torch.from_numpy(c.phantom.astype(np.float32)).cuda()
         target = targets["seeds"][str(seed)]["rmse_final"]
-        r = {"seed": seed, "target": target, "plain": A.time_to_rmse(P, y, ref, target)}
+        r = {"seed": seed, "target": target, "plain": A.time_to_rmse(P, y, ref, target, solver=solver)}
         if net is not None:
-            r["cnn"] = A.time_to_rmse(P, y, ref, target, net=net)
+            r["cnn"] = A.time_to_rmse(P, y, ref, target, net=net, solver=solver)
         per.append(r)
 
     def med(kind, key):
@@ -250,8 +267,9 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="finally copy a buffer of this many MiB on the device (a plain copy kernel of known "
                          "size, to calibrate hardware byte counters against)")
-    ap.add_argument("--operator", choices=["fly", "stored"], default="fly",
-                    help="P and P^T on the fly, or from the stored float32 matrix")
+    ap.add_argument("--operator", choices=["fly", "stored"], default="stored",
+                    help="P and P^T of the headline figure: from the stored float32 matrix (the paper's "
+                         "look-up tables) or on the fly; the other is timed and reported beside it")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
@@ -274,29 +292,33 @@ def main():
     ref = torch.from_numpy(case.phantom.astype(np.float32)).cuda()
     f = torch.zeros((g.ny, g.nx), dtype=torch.float32, device="cuda")
     stored = args.operator == "stored"
-    if stored:
-        log(f"bench: storing the system matrix ({P.store_matrix() / 2**20:.0f} MiB)")
-    base = dict(cgls_iters=3, tv_iters=5, lam=1000.0, edge_quantile=0.9, tv_eps=1e-4, stored_matrix=int(stored))
+    log(f"bench: storing the system matrix ({P.store_matrix() / 2**20:.0f} MiB)")
+    base = dict(cgls_iters=3, tv_iters=5, lam=1000.0, edge_quantile=0.9, tv_eps=1e-4)
 
-    log(f"bench: warmup {args.warmup} iterations")
-    P.reconstruct(y, eptv.Params(outer_iters=args.warmup, zero_init=1, **base), f=f, stats=False)
-    torch.cuda.synchronize()
+    def iterations(use_stored):
+        """Iterations/s of `args.steps` outer iterations after `args.warmup`."""
+        prm = dict(base, stored_matrix=int(use_stored))
+        f = torch.zeros((g.ny, g.nx), dtype=torch.float32, device="cuda")
+        P.reconstruct(y, eptv.Params(outer_iters=args.warmup, zero_init=1, **prm), f=f, stats=False)
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(s)
+        P.reconstruct(y, eptv.Params(outer_iters=args.steps, zero_init=0, **prm), f=f, stats=False)
+        e1.record(s)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms_total = e0.elapsed_time(e1)
+        rmse = float(torch.sqrt(torch.mean((f - ref) ** 2)).item())
+        name = "stored" if use_stored else "fly"
+        log(f"bench: {name}: {args.steps / (ms_total / 1e3):.1f} it/s ({ms_total / args.steps:.4f} ms/iteration, "
+            f"wall {wall:.3f} s), rmse {rmse:.3e}")
+        return args.steps / (ms_total / 1e3), ms_total / args.steps, rmse, f
 
-    log(f"bench: timing {args.steps} iterations")
-    s = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(s)
-    P.reconstruct(y, eptv.Params(outer_iters=args.steps, zero_init=0, **base), f=f, stats=False)
-    e1.record(s)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_total = e0.elapsed_time(e1)
-    ms_step = ms_total / args.steps
-    its = args.steps / (ms_total / 1e3)
-    rmse = float(torch.sqrt(torch.mean((f - ref) ** 2)).item())
-    log(f"bench: {its:.1f} it/s ({ms_step:.4f} ms/iteration, wall {wall:.3f} s), rmse {rmse:.3e}")
+    log(f"bench: warmup {args.warmup}, timing {args.steps} iterations per operator")
+    its, ms_step, rmse, f = iterations(stored)
+    its_o, ms_o, rmse_o, _ = iterations(not stored)
 
     # dominant kernels, timed live on the stream they run on
     x = f.clone()
@@ -305,40 +327,52 @@ def main():
     z = P.new_image()
     r = y.clone()
     ops = {"project_dual": lambda: P.project_dual(x, xT, q), "backproject": lambda: P.backproject(r, z),
-           "backproject_interp": lambda: P.backproject_interp(r, z)}
-    if stored:
-        ops.update({"project_stored": lambda: P.project_stored(x, q),
-                    "backproject_stored": lambda: P.backproject_stored(r, z)})
+           "backproject_interp": lambda: P.backproject_interp(r, z),
+           "project_stored": lambda: P.project_stored_dual(x, xT, q),
+           "backproject_stored": lambda: P.backproject_stored(r, z)}
     op_ms = {k: kernel_avg_ms(fn, args.kernel_reps, torch) for k, fn in ops.items()}
-    t_proj = op_ms["project_stored" if stored else "project_dual"]
-    t_bp = op_ms["backproject_stored" if stored else "backproject"]
-    per_it = {"project": 4 * t_proj, "backproject": 3 * t_bp}
-    dom = max(per_it, key=per_it.get)
-    t_dom = t_proj if dom == "project" else t_bp
-    if stored:
-        # one CSR (or CSC) pass: 4-byte value and 4-byte index per nonzero,
-        # 8-byte offsets per row (column), the input vector once, the output once
-        n_img, n_sino = g.nx * g.ny, g.n_views * g.n_bins
-        rows, n_in, n_out = (n_sino, n_img, n_sino) if dom == "project" else (n_img, n_sino, n_img)
-        nbytes = 8.0 * nnz + 8.0 * (rows + 1) + 4.0 * (n_in + n_out)
-        achieved = nbytes / (t_dom * 1e-3)
-        roof = {"bound": "hbm", "kernel": dom + "_stored", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": pmc_traffic(dom + "_stored"),
-                "avg_ms": t_dom, "algorithmic_bytes_per_launch": nbytes, "nnz": nnz}
-    else:
+    log("bench: " + ", ".join(f"{k} {v * 1e3:.1f} us" for k, v in op_ms.items()) + f", nnz {nnz}")
+
+    def roofline(use_stored):
+        t_proj = op_ms["project_stored" if use_stored else "project_dual"]
+        t_bp = op_ms["backproject_stored" if use_stored else "backproject"]
+        per_it = {"project": 4 * t_proj, "backproject": 3 * t_bp}
+        dom = max(per_it, key=per_it.get)
+        t_dom = t_proj if dom == "project" else t_bp
+        if use_stored:
+            # one CSR (or CSC) pass: 4-byte value and 4-byte index per nonzero
+            # (the padding to 4 entries per row is overhead, not counted), a
+            # 4-byte offset per row (column), the input vector once, the output once
+            n_img, n_sino = g.nx * g.ny, g.n_views * g.n_bins
+            rows, n_in, n_out = (n_sino, n_img, n_sino) if dom == "project" else (n_img, n_sino, n_img)
+            nbytes = 8.0 * nnz + 4.0 * (rows + 1) + 4.0 * (n_in + n_out)
+            achieved = nbytes / (t_dom * 1e-3)
+            return {"bound": "hbm", "kernel": dom + "_stored", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
+                    "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": pmc_traffic(dom + "_stored"),
+                    "avg_ms": t_dom, "algorithmic_bytes_per_launch": nbytes, "nnz": nnz}
         flops = 2.0 * nnz
         achieved = flops / (t_dom * 1e-3)
-        roof = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
+        return {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK, "traffic": pmc_traffic(dom),
                 "avg_ms": t_dom, "algorithmic_flops_per_launch": flops, "nnz": nnz,
                 "pmc_valu": pmc_valu(dom, nnz)}
+
+    roof = roofline(stored)
     roof["operators_avg_ms"] = op_ms
+    other = {"operator": "fly" if stored else "stored", "value": its_o, "ms_per_step": ms_o,
+             "rmse_vs_phantom": rmse_o, "roofline": roofline(not stored)}
+    if roof["bound"] == "hbm":
+        # what HBM delivers to a plain device copy far larger than the 256 MB
+        # Infinity Cache (read + write bytes per second)
+        hbm = achievable_hbm(torch)
+        roof["achievable_hbm_gbps"] = hbm / 1e9
+        roof["frac_of_achievable"] = roof["achieved"] * 1e9 / hbm
     log("bench: " + ", ".join(f"{k} {v * 1e3:.1f} us" for k, v in op_ms.items()) + f", nnz {nnz}")
 
     ttr = None
     if args.rmse_seeds > 0:
         log(f"bench: time to the oracle's RMSE, seeds 0-{args.rmse_seeds - 1}")
-        ttr = time_to_rmse(eptv, synth, P, torch, np, range(args.rmse_seeds))
+        ttr = time_to_rmse(eptv, synth, P, torch, np, range(args.rmse_seeds), {"stored_matrix": int(stored)})
         log(f"bench: plain EPTV reaches the oracle RMSE in {ttr['plain_seconds_median']} s (median), "
             f"CNN-assisted in {ttr.get('cnn_seconds_median')} s")
 
@@ -381,6 +415,7 @@ def main():
                    "image": [g.ny, g.nx], "views": g.n_views, "bins": g.n_bins, "cgls_iters": 3, "tv_iters": 5,
                    "graph": os.environ.get("EPTV_NO_GRAPH", "0") in ("", "0"), "operator": args.operator},
         "rmse_vs_phantom": rmse,
+        "other_operator": other,
         "time_to_rmse": ttr,
         "batch": bat,
         "cnn_training": cnn_train,

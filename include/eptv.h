@@ -136,15 +136,24 @@ int eptv_plan_nnz(eptv_plan plan, long long* nnz);
 int eptv_geometry_matrix(const eptv_geometry* geom, long long* nnz, long long* rowptr, int* col, float* val);
 
 /* Store that matrix on the plan's device, by ray (CSR, for P) and by pixel
- * (CSC, for P^T): 16 bytes per nonzero plus the offsets (215 MB at 512^2 /
- * 40 views x 736 bins).  Owned by the plan; built once, later calls only
- * report the size.  Synchronous. */
+ * (CSC, for P^T): 16 bytes per nonzero plus the offsets and a padding of each
+ * ray and pixel to a multiple of 4 entries (219 MB at 512^2 / 40 views x 736
+ * bins).  A ray swept row by row indexes the transposed image, so that its
+ * entries lie along the fast axis of the image it reads.  Owned by the plan;
+ * built once, later calls only report the size.  Synchronous. */
 int eptv_plan_store_matrix(eptv_plan plan, size_t* device_bytes);
 
 /* q = alpha P x + beta q and z = alpha P^T r + beta z from the stored matrix
  * (EPTV_ERR_ARG if it is not stored).  Same matrix as eptv_project /
- * eptv_backproject bit for bit; only the summation order differs. */
-int eptv_project_stored(eptv_plan plan, const float* x, float* q, float alpha, float beta, void* stream);
+ * eptv_backproject bit for bit; only the summation order differs.
+ * eptv_project_stored transposes x into the workspace (ws: as for
+ * eptv_project); eptv_project_stored_dual takes the transposed image xT
+ * ([nx][ny]) from the caller, as eptv_project_dual does, and needs no
+ * workspace. */
+int eptv_project_stored(eptv_plan plan, const float* x, float* q, float alpha, float beta, void* ws,
+                        size_t ws_bytes, void* stream);
+int eptv_project_stored_dual(eptv_plan plan, const float* x, const float* xT, float* q, float alpha, float beta,
+                             void* stream);
 int eptv_backproject_stored(eptv_plan plan, const float* r, float* z, float alpha, float beta, void* stream);
 
 /* Workspace bytes for the calls below (device memory the caller allocates and

@@ -283,12 +283,15 @@ def assisted_reconstruct(P: E.Plan, net: E.UNet, y: torch.Tensor, outer_iters: i
 
 
 def time_to_rmse(P: E.Plan, y: torch.Tensor, ref: torch.Tensor, target: float, net: Optional[E.UNet] = None,
-                 frozen_iters: int = 1, max_iters: int = 100, reps: int = 3, n0: int = N0):
+                 frozen_iters: int = 1, max_iters: int = 100, reps: int = 3, n0: int = N0,
+                 solver: Optional[dict] = None):
     """Seconds (best of ``reps``, HIP events on the current stream) until the
     RMSE to ``ref`` is <= target: plain EPTV from zero, or (with ``net``) the
     assisted pipeline.  The runs stop themselves (``stop_rmse``, the RMSE
     record read back after every iteration), so the time includes each
-    iteration's check."""
+    iteration's check.  ``solver`` overrides entries of SOLVER (e.g.
+    ``stored_matrix=1`` once the plan holds the matrix)."""
+    solver = {**SOLVER, **(solver or {})}
     s = torch.cuda.current_stream()
     best, st = None, None
     for _ in range(reps):
@@ -296,11 +299,11 @@ def time_to_rmse(P: E.Plan, y: torch.Tensor, ref: torch.Tensor, target: float, n
         torch.cuda.synchronize()
         e0.record(s)
         if net is None:
-            _, st = P.reconstruct(y, E.Params(outer_iters=max_iters, zero_init=1, stop_rmse=target, **SOLVER),
+            _, st = P.reconstruct(y, E.Params(outer_iters=max_iters, zero_init=1, stop_rmse=target, **solver),
                                   f_ref=ref)
         else:
             _, st = assisted_reconstruct(P, net, y, max_iters, frozen_iters, n0=n0, f_ref=ref,
-                                         solver={"stop_rmse": target})
+                                         solver={**solver, "stop_rmse": target})
         e1.record(s)
         torch.cuda.synchronize()
         sec = e0.elapsed_time(e1) / 1e3

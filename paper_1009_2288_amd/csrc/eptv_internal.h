@@ -102,14 +102,21 @@ struct DevState {
 };
 
 // The float32 system matrix stored on the device (optional, see spmv.hip).
+// Entries are (other index, float bits of the length) pairs; every row and
+// column is padded to a multiple of kStoredPad entries with its last index and
+// length 0, so a lane's entries are whole, aligned 16-byte loads.  The CSR
+// copy is split in chunks of kStoredChunk entries per ray (the last one
+// shorter), each stored as n/2 pairs of entries (l, n/2 + l).
+constexpr int kStoredPad = 4;
+constexpr int kStoredChunk = 128;
 struct StoredMatrix {
-    long long nnz = 0;
-    int* d_rowptr = nullptr;  // [V*B + 1] CSR by ray
-    int* d_col = nullptr;     // [nnz] pixel index
-    float* d_val = nullptr;   // [nnz] length
-    int* d_colptr = nullptr;  // [nx*ny + 1] CSC by pixel
-    int* d_row = nullptr;     // [nnz] ray index
-    float* d_cval = nullptr;  // [nnz] length
+    long long nnz = 0;          // nonzeros, padding excluded
+    long long slots = 0;        // entries per copy, padding included
+    int* d_rowptr = nullptr;    // [V*B + 1] CSR by ray, offsets into d_rent
+    int2* d_rent = nullptr;     // [slots] (pixel index into x, or into x transposed for
+                                //  rays swept row by row; length)
+    int* d_colptr = nullptr;    // [nx*ny + 1] CSC by pixel, offsets into d_cent
+    int2* d_cent = nullptr;     // [slots of the CSC copy] (ray index, length)
     size_t bytes = 0;
 };
 
@@ -185,7 +192,7 @@ hipError_t launch_backproject(const Plan& p, const float* r, float alpha, float 
 hipError_t launch_backproject_interp(const Plan& p, const float* r, float alpha, float beta, const float* c,
                                      float* z, float* zT, double* partial, hipStream_t s);
 
-hipError_t launch_project_stored(const Plan& p, const float* x, float alpha, float beta, const float* c, float* q,
+hipError_t launch_project_stored(const Plan& p, const float* x, const float* xT, float alpha, float beta, const float* c, float* q,
                                  double* partial, hipStream_t s);
 hipError_t launch_backproject_stored(const Plan& p, const float* r, float alpha, float beta, const float* c, float* z,
                                      float* zT, double* partial, hipStream_t s);

@@ -34,6 +34,7 @@ struct HostCsr {
     std::vector<long long> rowptr;
     std::vector<int> col;
     std::vector<float> val;
+    std::vector<char> rows;  // per ray: swept row by row
 };
 
 static void build_csr(const Plan& p, HostCsr& m)
@@ -42,6 +43,7 @@ static void build_csr(const Plan& p, HostCsr& m)
     m.rowptr.assign((size_t)nrow + 1, 0);
     m.col.clear();
     m.val.clear();
+    m.rows.clear();
     for (int v = 0; v < p.V; ++v)
         for (int b = 0; b < p.B; ++b) {
             const double beta = ((double)b - 0.5 * (p.B - 1) + p.bin_offset) * p.dbeta;
@@ -50,6 +52,7 @@ static void build_csr(const Plan& p, HostCsr& m)
                 m.col.push_back((int)pix);
                 m.val.push_back(c);
             });
+            m.rows.push_back(R.rows ? 1 : 0);
             m.rowptr[(size_t)v * p.B + b + 1] = (long long)m.col.size();
         }
 }
@@ -245,7 +248,7 @@ static hipError_t enqueue_iteration(const Ctx& c, hipStream_t s)
     // Step 1: P1.  r = y - P f
     // P and P^T: on the fly, or from the stored matrix (the paper's two strategies, Sec. 2.3)
     auto proj = [&](const float* x, const float* xT, float al, float be, const float* cc, float* out, double* part) {
-        return q.stored_matrix ? launch_project_stored(p, x, al, be, cc, out, part, s)
+        return q.stored_matrix ? launch_project_stored(p, x, xT, al, be, cc, out, part, s)
                                : launch_project(p, x, xT, al, be, cc, out, part, s);
     };
     // P^T: the exact transpose (on the fly or stored), or the Eq. 11 operator
@@ -394,11 +397,9 @@ int eptv_plan_destroy(eptv_plan h)
     if (p.cap_stream) hipStreamDestroy(p.cap_stream);
     if (p.rays.d_ray) hipFree(p.rays.d_ray);
     if (p.mat.d_rowptr) hipFree(p.mat.d_rowptr);
-    if (p.mat.d_col) hipFree(p.mat.d_col);
-    if (p.mat.d_val) hipFree(p.mat.d_val);
+    if (p.mat.d_rent) hipFree(p.mat.d_rent);
     if (p.mat.d_colptr) hipFree(p.mat.d_colptr);
-    if (p.mat.d_row) hipFree(p.mat.d_row);
-    if (p.mat.d_cval) hipFree(p.mat.d_cval);
+    if (p.mat.d_cent) hipFree(p.mat.d_cent);
     if (p.rays.d_range) hipFree(p.rays.d_range);
     if (p.rays.d_view) hipFree(p.rays.d_view);
     if (p.rays.d_view_d) hipFree(p.rays.d_view_d);
@@ -441,50 +442,86 @@ int eptv_plan_store_matrix(eptv_plan h, size_t* device_bytes)
         const long long nnz = (long long)m.col.size();
         if (nnz >= (1LL << 31) || (long long)p.nx * p.ny >= (1LL << 31)) return EPTV_ERR_ARG;
         const int nrow = p.V * p.B, npix = p.nx * p.ny;
-        std::vector<int> rowptr(m.rowptr.begin(), m.rowptr.end());
         // the same entries grouped by pixel, rays ascending
-        std::vector<int> colptr((size_t)npix + 1, 0), rowi((size_t)nnz);
+        std::vector<long long> colcnt((size_t)npix + 1, 0);
+        for (long long e = 0; e < nnz; ++e) colcnt[(size_t)m.col[e] + 1]++;
+        for (int c = 0; c < npix; ++c) colcnt[(size_t)c + 1] += colcnt[c];
+        std::vector<int> rowi((size_t)nnz);
         std::vector<float> cval((size_t)nnz);
-        for (long long e = 0; e < nnz; ++e) colptr[(size_t)m.col[e] + 1]++;
-        for (int c = 0; c < npix; ++c) colptr[(size_t)c + 1] += colptr[c];
-        std::vector<int> fill(colptr.begin(), colptr.end() - 1);
-        for (int r = 0; r < nrow; ++r)
-            for (long long e = m.rowptr[r]; e < m.rowptr[r + 1]; ++e) {
-                const int at = fill[m.col[e]]++;
-                rowi[at] = r;
-                cval[at] = m.val[e];
+        {
+            std::vector<long long> fill(colcnt.begin(), colcnt.end() - 1);
+            for (int r = 0; r < nrow; ++r)
+                for (long long e = m.rowptr[r]; e < m.rowptr[r + 1]; ++e) {
+                    const long long at = fill[m.col[e]]++;
+                    rowi[at] = r;
+                    cval[at] = m.val[e];
+                }
+        }
+        // padded, interleaved copies (see StoredMatrix)
+        auto pack = [](int n, const long long* ptr, const int* idx, const float* val, bool chunked,
+                       std::vector<int>& pptr, std::vector<int2>& ent) -> bool {
+            pptr.assign((size_t)n + 1, 0);
+            long long at = 0;
+            for (int i = 0; i < n; ++i) {
+                const long long len = ptr[i + 1] - ptr[i];
+                at += (len + kStoredPad - 1) / kStoredPad * kStoredPad;
+                if (at >= (1LL << 31)) return false;
+                pptr[(size_t)i + 1] = (int)at;
             }
+            ent.assign((size_t)at, int2{0, 0});
+            for (int i = 0; i < n; ++i) {
+                long long o = pptr[i];
+                for (long long e = ptr[i]; e < ptr[i + 1]; ++e, ++o) {
+                    float v = val[e];
+                    int bits;
+                    std::memcpy(&bits, &v, 4);
+                    ent[(size_t)o] = int2{idx[e], bits};
+                }
+                for (; o < pptr[(size_t)i + 1]; ++o) ent[(size_t)o] = int2{idx[ptr[i + 1] - 1], 0};
+                if (!chunked) continue;
+                // chunks of kStoredChunk: slot l of a chunk of n holds entries l and n/2 + l
+                for (long long c0 = pptr[i]; c0 < pptr[(size_t)i + 1]; c0 += kStoredChunk) {
+                    const long long nc = std::min<long long>(kStoredChunk, pptr[(size_t)i + 1] - c0), h = nc / 2;
+                    std::vector<int2> t(ent.begin() + c0, ent.begin() + c0 + nc);
+                    for (long long l = 0; l < h; ++l) {
+                        ent[(size_t)(c0 + 2 * l)] = t[(size_t)l];
+                        ent[(size_t)(c0 + 2 * l + 1)] = t[(size_t)(h + l)];
+                    }
+                }
+            }
+            return true;
+        };
+        // the P copy: rays swept row by row index the transposed image
+        std::vector<int> tcol(m.col);
+        for (int r = 0; r < nrow; ++r)
+            if (m.rows[r])
+                for (long long e = m.rowptr[r]; e < m.rowptr[r + 1]; ++e)
+                    tcol[e] = (m.col[e] % p.nx) * p.ny + m.col[e] / p.nx;
+        std::vector<int> rowptr, colptr;
+        std::vector<int2> rent, cent;
+        if (!pack(nrow, m.rowptr.data(), tcol.data(), m.val.data(), true, rowptr, rent) ||
+            !pack(npix, colcnt.data(), rowi.data(), cval.data(), false, colptr, cent))
+            return EPTV_ERR_ARG;
         StoredMatrix& S = p.mat;
         hipError_t e = hipMalloc(&S.d_rowptr, rowptr.size() * 4);
-        if (e == hipSuccess) e = hipMalloc(&S.d_col, (size_t)nnz * 4);
-        if (e == hipSuccess) e = hipMalloc(&S.d_val, (size_t)nnz * 4);
+        if (e == hipSuccess) e = hipMalloc(&S.d_rent, rent.size() * 8);
         if (e == hipSuccess) e = hipMalloc(&S.d_colptr, colptr.size() * 4);
-        if (e == hipSuccess) e = hipMalloc(&S.d_row, (size_t)nnz * 4);
-        if (e == hipSuccess) e = hipMalloc(&S.d_cval, (size_t)nnz * 4);
+        if (e == hipSuccess) e = hipMalloc(&S.d_cent, cent.size() * 8);
         if (e == hipSuccess) e = hipMemcpy(S.d_rowptr, rowptr.data(), rowptr.size() * 4, hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(S.d_col, m.col.data(), (size_t)nnz * 4, hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(S.d_val, m.val.data(), (size_t)nnz * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(S.d_rent, rent.data(), rent.size() * 8, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(S.d_colptr, colptr.data(), colptr.size() * 4, hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(S.d_row, rowi.data(), (size_t)nnz * 4, hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(S.d_cval, cval.data(), (size_t)nnz * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(S.d_cent, cent.data(), cent.size() * 8, hipMemcpyHostToDevice);
         if (e != hipSuccess) {
-            for (void* ptr : {(void*)S.d_rowptr, (void*)S.d_col, (void*)S.d_val, (void*)S.d_colptr, (void*)S.d_row,
-                              (void*)S.d_cval})
+            for (void* ptr : {(void*)S.d_rowptr, (void*)S.d_rent, (void*)S.d_colptr, (void*)S.d_cent})
                 if (ptr) hipFree(ptr);
             S = StoredMatrix();
             return hip_fail(e, "eptv_plan_store_matrix");
         }
+        S.slots = (long long)rent.size();
         S.nnz = nnz;
-        S.bytes = (rowptr.size() + colptr.size()) * 4 + (size_t)nnz * 16;
+        S.bytes = (rowptr.size() + colptr.size()) * 4 + (rent.size() + cent.size()) * 8;
     }
     if (device_bytes) *device_bytes = p.mat.bytes;
-    return EPTV_OK;
-}
-
-int eptv_project_stored(eptv_plan h, const float* x, float* q, float alpha, float beta, void* stream)
-{
-    if (!h || !x || !q || !h->p.mat.d_rowptr) return EPTV_ERR_ARG;
-    EPTV_HIP(launch_project_stored(h->p, x, alpha, beta, q, q, nullptr, (hipStream_t)stream));
     return EPTV_OK;
 }
 
@@ -533,6 +570,27 @@ int eptv_project_dual(eptv_plan h, const float* x, const float* xT, float* q, fl
 {
     if (!h || !x || !xT || !q) return EPTV_ERR_ARG;
     EPTV_HIP(launch_project(h->p, x, xT, alpha, beta, q, q, nullptr, (hipStream_t)stream));
+    return EPTV_OK;
+}
+
+int eptv_project_stored(eptv_plan h, const float* x, float* q, float alpha, float beta, void* ws, size_t ws_bytes,
+                        void* stream)
+{
+    if (!h || !x || !q || !h->p.mat.d_rowptr) return EPTV_ERR_ARG;
+    Workspace W;
+    int rc = bind_ws(h->p, 1, 0, ws, ws_bytes, &W);
+    if (rc != EPTV_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    EPTV_HIP(launch_transpose(x, W.fT, h->p.nx, h->p.ny, s));
+    EPTV_HIP(launch_project_stored(h->p, x, W.fT, alpha, beta, q, q, nullptr, s));
+    return EPTV_OK;
+}
+
+int eptv_project_stored_dual(eptv_plan h, const float* x, const float* xT, float* q, float alpha, float beta,
+                             void* stream)
+{
+    if (!h || !x || !xT || !q || !h->p.mat.d_rowptr) return EPTV_ERR_ARG;
+    EPTV_HIP(launch_project_stored(h->p, x, xT, alpha, beta, q, q, nullptr, (hipStream_t)stream));
     return EPTV_OK;
 }
 

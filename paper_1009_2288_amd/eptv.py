@@ -24,7 +24,7 @@ EPTV_OK, EPTV_ERR_ARG, EPTV_ERR_GEOMETRY, EPTV_ERR_WORKSPACE, EPTV_ERR_HIP, EPTV
 SYMBOLS = ["eptv_plan_create", "eptv_plan_destroy", "eptv_plan_nnz", "eptv_workspace_bytes", "eptv_project",
            "eptv_project_dual", "eptv_backproject", "eptv_tv_gradient", "eptv_select_sigma", "eptv_tv_step", "eptv_reconstruct",
            "eptv_status_string", "eptv_last_error", "eptv_geometry_matrix", "eptv_plan_store_matrix",
-           "eptv_project_stored", "eptv_backproject_stored", "eptv_backproject_interp",
+           "eptv_project_stored", "eptv_project_stored_dual", "eptv_backproject_stored", "eptv_backproject_interp",
            "eptv_tv_gradient_vjp", "eptv_batch_create", "eptv_batch_destroy", "eptv_batch_size", "eptv_batch_plan",
            "eptv_batch_workspace_bytes", "eptv_batch_set_launch", "eptv_batch_get_launch", "eptv_batch_tune",
            "eptv_batch_reconstruct", "eptv_unet_create", "eptv_unet_destroy", "eptv_unet_param_count",
@@ -146,7 +146,8 @@ def _lib() -> C.CDLL:
                                                 C.POINTER(_Stats), vp]
         L.eptv_geometry_matrix.argtypes = [C.POINTER(_Geometry), C.POINTER(C.c_longlong), vp, vp, vp]
         L.eptv_plan_store_matrix.argtypes = [vp, C.POINTER(sz)]
-        L.eptv_project_stored.argtypes = [vp, vp, vp, C.c_float, C.c_float, vp]
+        L.eptv_project_stored.argtypes = [vp, vp, vp, C.c_float, C.c_float, vp, sz, vp]
+        L.eptv_project_stored_dual.argtypes = [vp, vp, vp, vp, C.c_float, C.c_float, vp]
         L.eptv_backproject_stored.argtypes = [vp, vp, vp, C.c_float, C.c_float, vp]
         L.eptv_backproject_interp.argtypes = [vp, vp, vp, C.c_float, C.c_float, vp]
         L.eptv_status_string.argtypes = [C.c_int]
@@ -309,10 +310,22 @@ class Plan:
 
     def project_stored(self, x: torch.Tensor, out: Optional[torch.Tensor] = None, alpha: float = 1.0,
                        beta: float = 0.0, stream=None) -> torch.Tensor:
+        """out = alpha P x + beta out from the stored matrix."""
         x = self._img(x, "x")
         out = self._sino(out if out is not None else self.new_sinogram(), "out")
-        _check(_lib().eptv_project_stored(self._h, x.data_ptr(), out.data_ptr(), alpha, beta, _stream(stream)),
-               "eptv_project_stored")
+        ws = self.workspace()
+        _check(_lib().eptv_project_stored(self._h, x.data_ptr(), out.data_ptr(), alpha, beta, ws.data_ptr(),
+                                          ws.numel(), _stream(stream)), "eptv_project_stored")
+        return out
+
+    def project_stored_dual(self, x: torch.Tensor, xT: torch.Tensor, out: Optional[torch.Tensor] = None,
+                            alpha: float = 1.0, beta: float = 0.0, stream=None) -> torch.Tensor:
+        """project_stored with xT the same image transposed ([nx][ny])."""
+        x = self._img(x, "x")
+        xT = self._t(xT, (self.nx, self.ny), "xT")
+        out = self._sino(out if out is not None else self.new_sinogram(), "out")
+        _check(_lib().eptv_project_stored_dual(self._h, x.data_ptr(), xT.data_ptr(), out.data_ptr(), alpha, beta,
+                                               _stream(stream)), "eptv_project_stored_dual")
         return out
 
     def backproject_stored(self, r: torch.Tensor, out: Optional[torch.Tensor] = None, alpha: float = 1.0,

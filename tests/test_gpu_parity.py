@@ -263,18 +263,23 @@ def test_reconstruct_paper_case_20_iterations(E, oracle):
     np.testing.assert_allclose(sg["sigma"], so["sigma"], rtol=1e-4)
 
 
-def test_reconstruct_paper_case_100_iterations_replay(E, oracle):
+@pytest.mark.parametrize("stored", [0, 1], ids=["fly", "stored"])
+def test_reconstruct_paper_case_100_iterations_replay(E, oracle, stored):
     """512^2 / 40 x 736 over the workload's full K = 100, in replay mode: the
     GPU runs free and records its Armijo indices; the oracle takes them
     instead of searching and certifies each against its own FP64 inequality
     (slack 1e-6 |Q0|: over these 500 decisions the oracle's own free run has
     two near-ties below 1e-5, where float32 may decide either way), and then
-    the images must agree to 1e-4."""
+    the images must agree to 1e-4.  With P and P^T on the fly and from the
+    stored matrix."""
     c = synth.make_case("paper", 0)
     P = plan(E, "paper")
+    if stored:
+        P.store_matrix()
     M = matrix(oracle, "paper")
     y = c.y.astype(np.float32)
-    f, sg = P.reconstruct(dev(y), E.Params(outer_iters=100, lam=1000.0), f_ref=dev(c.phantom))
+    f, sg = P.reconstruct(dev(y), E.Params(outer_iters=100, lam=1000.0, stored_matrix=stored),
+                          f_ref=dev(c.phantom))
     fo, so = M.reconstruct(y, oracle_params(oracle, 100), f_ref=c.phantom, armijo_replay=sg["armijo_k"])
     worst = float(so["armijo_margin"].min())
     print("replay certification: min margin", worst, "steps", sg["armijo_k"].size)
@@ -383,6 +388,9 @@ def test_stored_matrix_parity(E, oracle, name):
     out = dev(q0 := synth.random_sinogram(g.n_views, g.n_bins, 43))
     P.project_stored(dev(x), out, alpha=2.0, beta=-1.0)
     assert rel(out.cpu().numpy(), 2.0 * M.project(x) - q0) <= 1e-5
+    # the caller's transposed copy gives the same result bit for bit
+    xd = dev(x)
+    assert torch.equal(P.project_stored_dual(xd, xd.t().contiguous()), P.project_stored(xd))
 
 
 def test_reconstruct_stored_matrix(E, oracle):
