@@ -185,12 +185,14 @@ static hipError_t enqueue_batch_iteration(const BatchDev& b, const eptv_params& 
                                        (float)q.lambda, eps2, s));
     }
     // Step 3 (positivity) fused into the last update
-    if (T == 0)
+    // (the update also forms the squared errors to the references, per tile)
+    if (T == 0) {
         EPTV_TRY(blaunch_copy_clamp(b, start, kBufF, kBufFT, q.positivity, s));
-    else
-        EPTV_TRY(blaunch_p2_update(b, fcur, gbuf[(T - 1) & 1], kBufF, kBufFT, q.positivity, s));
-    if (with_ref) EPTV_TRY(blaunch_rmse_part(b, kBufF, s));
-    EPTV_TRY(blaunch_iter_end(b, M > 0, with_ref, sigma_init(q), s));
+        if (with_ref) EPTV_TRY(blaunch_rmse_part(b, kBufF, s));
+    } else {
+        EPTV_TRY(blaunch_p2_update(b, fcur, gbuf[(T - 1) & 1], kBufF, kBufFT, q.positivity, with_ref, s));
+    }
+    EPTV_TRY(blaunch_iter_end(b, M > 0, with_ref, T > 0, sigma_init(q), s));
 #undef EPTV_TRY
     return hipSuccess;
 }

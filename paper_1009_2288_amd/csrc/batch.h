@@ -95,10 +95,12 @@ hipError_t blaunch_tv_armijo(const BatchDev& b, int f, int g_prev, int f_out, in
                              float t0, float shrink, hipStream_t s);
 hipError_t blaunch_armijo_decide(const BatchDev& b, int max_bt, double c_arm, float t0, float shrink, int step, int T,
                                  int f, int g, int v, float lambda, float eps2, hipStream_t s);
-hipError_t blaunch_p2_update(const BatchDev& b, int fcur, int g, int fout, int foutT, int clamp, hipStream_t s);
+hipError_t blaunch_p2_update(const BatchDev& b, int fcur, int g, int fout, int foutT, int clamp, int rmse,
+                             hipStream_t s);
 hipError_t blaunch_copy_clamp(const BatchDev& b, int src, int dst, int dstT, int clamp, hipStream_t s);
 hipError_t blaunch_rmse_part(const BatchDev& b, int f, hipStream_t s);
-hipError_t blaunch_iter_end(const BatchDev& b, bool with_resid, bool with_rmse, float sigma_fixed, hipStream_t s);
+hipError_t blaunch_iter_end(const BatchDev& b, bool with_resid, bool with_rmse, bool rmse_tiles, float sigma_fixed,
+                            hipStream_t s);
 hipError_t blaunch_state_init(const BatchDev& b, float sigma_fixed, int zero_iter, hipStream_t s);
 hipError_t blaunch_transpose(const BatchDev& b, int src, int dst, hipStream_t s);
 hipError_t blaunch_fill_zero(const BatchDev& b, int dst, hipStream_t s);

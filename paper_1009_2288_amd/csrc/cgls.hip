@@ -227,13 +227,15 @@ __device__ __forceinline__ void reset_iteration_state(DevState* st, uint32_t* hi
     }
 }
 
+// ||r||^2 from n_res partials, the squared error to the reference from
+// n_rmse partials (the RMSE kernel's, or the final P2 update's per tile).
 __device__ __forceinline__ void iter_end_block(DevState* st, const double* part_res, int n_res, int with_resid,
-                                               const double* part_rmse, int with_rmse, double npix, float* st_sigma,
-                                               int32_t* st_steps, double* st_resid, double* st_rmse, uint32_t* hist,
-                                               float sigma_fixed, double* lds)
+                                               const double* part_rmse, int n_rmse, int with_rmse, double npix,
+                                               float* st_sigma, int32_t* st_steps, double* st_resid, double* st_rmse,
+                                               uint32_t* hist, float sigma_fixed, double* lds)
 {
     const double res = with_resid ? block_sum_partials<256>(part_res, n_res, 1, lds) : 0.0;
-    const double e = with_rmse ? block_sum_partials<256>(part_rmse, kRmseBlocks, 1, lds) : 0.0;
+    const double e = with_rmse ? block_sum_partials<256>(part_rmse, n_rmse, 1, lds) : 0.0;
     if (threadIdx.x == 0) {
         const int it = st->iter;
         if (st_sigma) st_sigma[it] = st->sigma;
@@ -247,21 +249,22 @@ __device__ __forceinline__ void iter_end_block(DevState* st, const double* part_
 }
 
 __global__ __launch_bounds__(256) void k_iter_end(DevState* st, const double* part_res, int n_res, int with_resid,
-                                                  const double* part_rmse, int with_rmse, double npix,
+                                                  const double* part_rmse, int n_rmse, int with_rmse, double npix,
                                                   float* st_sigma, int32_t* st_steps, double* st_resid,
                                                   double* st_rmse, uint32_t* hist, float sigma_fixed)
 {
     __shared__ double lds[4];
-    iter_end_block(st, part_res, n_res, with_resid, part_rmse, with_rmse, npix, st_sigma, st_steps, st_resid, st_rmse,
-                   hist, sigma_fixed, lds);
+    iter_end_block(st, part_res, n_res, with_resid, part_rmse, n_rmse, with_rmse, npix, st_sigma, st_steps, st_resid,
+                   st_rmse, hist, sigma_fixed, lds);
 }
 
 hipError_t launch_iter_end(const Plan& p, DevState* st, const double* part_res, int with_resid,
-                           const double* part_rmse, int with_rmse, float* st_sigma, int32_t* st_steps,
+                           const double* part_rmse, int n_rmse, int with_rmse, float* st_sigma, int32_t* st_steps,
                            double* st_resid, double* st_rmse, uint32_t* hist, float sigma_fixed, hipStream_t s)
 {
     hipLaunchKernelGGL(k_iter_end, dim3(1), dim3(256), 0, s, st, part_res, sino_blocks(p), with_resid, part_rmse,
-                       with_rmse, (double)p.nx * p.ny, st_sigma, st_steps, st_resid, st_rmse, hist, sigma_fixed);
+                       n_rmse, with_rmse, (double)p.nx * p.ny, st_sigma, st_steps, st_resid, st_rmse, hist,
+                       sigma_fixed);
     return hipGetLastError();
 }
 
@@ -361,20 +364,24 @@ hipError_t blaunch_rmse_part(const BatchDev& b, int f, hipStream_t s)
 }
 
 // one block per slice
+// rmse_tiles: the squared errors come from the final update's 32 x 32 tiles
+// (else from the RMSE kernel's kRmseBlocks partials)
 __global__ __launch_bounds__(256) void kb_iter_end(const SliceDev* __restrict__ sl, int with_resid, int with_rmse,
-                                                   float sigma_fixed)
+                                                   int rmse_tiles, float sigma_fixed)
 {
     __shared__ double lds[4];
     const SliceDev& d = sl[blockIdx.x];
     const int rm = with_rmse && d.buf[kBufFRef] != nullptr;
-    iter_end_block(d.st, d.part[kPartRes], d.axpy_sino, with_resid, d.part[kPartRmse], rm, (double)d.nx * d.ny,
-                   d.st_sigma, d.st_steps, d.st_resid, d.st_rmse, d.hist, sigma_fixed, lds);
+    iter_end_block(d.st, d.part[kPartRes], d.axpy_sino, with_resid, d.part[kPartRmse],
+                   rmse_tiles ? d.t32x * d.t32y : kRmseBlocks, rm, (double)d.nx * d.ny, d.st_sigma, d.st_steps,
+                   d.st_resid, d.st_rmse, d.hist, sigma_fixed, lds);
 }
 
-hipError_t blaunch_iter_end(const BatchDev& b, bool with_resid, bool with_rmse, float sigma_fixed, hipStream_t s)
+hipError_t blaunch_iter_end(const BatchDev& b, bool with_resid, bool with_rmse, bool rmse_tiles, float sigma_fixed,
+                            hipStream_t s)
 {
     hipLaunchKernelGGL(kb_iter_end, dim3(b.n), dim3(256), 0, s, b.slices, (int)with_resid, (int)with_rmse,
-                       sigma_fixed);
+                       (int)rmse_tiles, sigma_fixed);
     return hipGetLastError();
 }
 

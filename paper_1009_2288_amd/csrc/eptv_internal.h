@@ -238,8 +238,12 @@ hipError_t launch_armijo_decide(const Plan& p, DevState* st, const double* part_
                                 const float* f, const float* g, const float* v, const float* wx, const float* wy,
                                 float lambda, float eps2, hipStream_t s,
                                 int replay = 0);
+// With ref, also one partial of the squared error to ref per 32 x 32 tile
+// (update_tiles of them) in part_rmse.
+int update_tiles(const Plan& p);
 hipError_t launch_p2_update(const Plan& p, const DevState* st, const float* fcur, const float* g,
-                            float* fout, float* foutT, int clamp, hipStream_t s);
+                            float* fout, float* foutT, int clamp, hipStream_t s, const float* ref = nullptr,
+                            double* part_rmse = nullptr);
 hipError_t launch_copy_clamp(const Plan& p, const float* src, float* dst, float* dstT, int clamp,
                              hipStream_t s);
 
@@ -247,7 +251,7 @@ hipError_t launch_copy_clamp(const Plan& p, const float* src, float* dst, float*
 hipError_t launch_rmse_part(const Plan& p, const float* f, const float* ref, double* part,
                             hipStream_t s);
 hipError_t launch_iter_end(const Plan& p, DevState* st, const double* part_res, int with_resid,
-                           const double* part_rmse, int with_rmse, float* st_sigma, int32_t* st_steps,
+                           const double* part_rmse, int n_rmse, int with_rmse, float* st_sigma, int32_t* st_steps,
                            double* st_resid, double* st_rmse, uint32_t* hist, float sigma_fixed, hipStream_t s);
 
 }  // namespace eptv

@@ -130,7 +130,8 @@ size_t workspace_layout(const Plan& p, int K, int T, char* base, Workspace* w)
     W.part_grad = (double*)take((size_t)armijo_blocks(p) * 2 * 8);
     W.part_arm = (double*)take((size_t)armijo_blocks(p) * kArmijoFirst * 8);
     W.part_res = (double*)take((size_t)sino_blocks(p) * 8);
-    W.part_rmse = (double*)take((size_t)kRmseBlocks * 8);
+    // per-block squared errors: the RMSE kernel's, or the final P2 update's (one per 32 x 32 tile)
+    W.part_rmse = (double*)take((size_t)std::max(kRmseBlocks, update_tiles(p)) * 8);
     W.st = (DevState*)take(sizeof(DevState));
     W.st_sigma = (float*)take(kcap * 4);
     W.st_k = (int32_t*)take(ktcap * 4);
@@ -209,7 +210,8 @@ float sigma_init(const eptv_params& q) { return q.sigma_fixed < 0 ? -1.0f : (flo
 
 static hipError_t enqueue_p2(const Plan& p, Workspace& W, const eptv_params& q, const float* start, const float* v,
                              int n_steps, float* fout, float* foutT, int clamp, int32_t* st_k, hipStream_t s,
-                             const float* wx_in = nullptr, const float* wy_in = nullptr, int replay = 0)
+                             const float* wx_in = nullptr, const float* wy_in = nullptr, int replay = 0,
+                             const float* f_ref = nullptr)
 {
     hipError_t e;
     const float eps2 = (float)(q.tv_eps * q.tv_eps);
@@ -232,7 +234,7 @@ static hipError_t enqueue_p2(const Plan& p, Workspace& W, const eptv_params& q, 
             return e;
     }
     if (n_steps == 0) return launch_copy_clamp(p, start, fout, foutT, clamp, s);
-    return launch_p2_update(p, W.st, fcur, gbuf[(n_steps - 1) & 1], fout, foutT, clamp, s);
+    return launch_p2_update(p, W.st, fcur, gbuf[(n_steps - 1) & 1], fout, foutT, clamp, s, f_ref, W.part_rmse);
 }
 
 // One outer iteration of the EPTV algorithm (Sec. 2.2), entirely on `s`.
@@ -285,14 +287,16 @@ static hipError_t enqueue_iteration(const Ctx& c, hipStream_t s)
             return e;
     }
     // Step 3 (positivity) is fused into the last descent update.
-    if ((e = enqueue_p2(p, W, q, start, W.u, T, c.f, W.fT, q.positivity, W.st_k, s, c.wx_in, c.wy_in, c.replay)) !=
-        hipSuccess)
+    // With a reference, the last update also forms the squared errors per tile.
+    if ((e = enqueue_p2(p, W, q, start, W.u, T, c.f, W.fT, q.positivity, W.st_k, s, c.wx_in, c.wy_in, c.replay,
+                        c.f_ref)) != hipSuccess)
         return e;
-    if (c.f_ref) {
+    if (c.f_ref && T == 0) {
         if ((e = launch_rmse_part(p, c.f, c.f_ref, W.part_rmse, s)) != hipSuccess) return e;
     }
-    return launch_iter_end(p, W.st, W.part_res, M > 0, W.part_rmse, c.f_ref != nullptr, W.st_sigma, W.st_steps,
-                           W.st_resid, W.st_rmse, W.hist, sigma_init(q), s);
+    return launch_iter_end(p, W.st, W.part_res, M > 0, W.part_rmse, T > 0 ? update_tiles(p) : kRmseBlocks,
+                           c.f_ref != nullptr, W.st_sigma, W.st_steps, W.st_resid, W.st_rmse, W.hist, sigma_init(q),
+                           s);
 }
 
 static bool no_graph()

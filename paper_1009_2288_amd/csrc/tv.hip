@@ -752,18 +752,48 @@ __device__ __forceinline__ void p2_update_block(const DevState* st, const float*
     }
 }
 
-__global__ __launch_bounds__(256) void k_p2_update(const DevState* st, const float* fcur, const float* __restrict__ g,
-                                                   float* fout, float* foutT, int clamp, int nx, int ny)
+// Squared error to ref over the pixels of 32 x 32 update tile (tbx, tby), in
+// the order p2_update_block writes them (thread (tx, ty): rows ty, ty + 8, ...),
+// summed over the block (valid in all threads).  Contains __syncthreads().
+__device__ __forceinline__ double update_tile_sq_err(const float* fout, const float* ref, int nx, int ny, int tbx,
+                                                     int tby, double* lds)
 {
-    __shared__ float tl[32][33];
-    p2_update_block(st, fcur, g, fout, foutT, clamp, nx, ny, blockIdx.x, blockIdx.y, tl);
+    const int i = tbx * 32 + (threadIdx.x & 31);
+    double e2 = 0.0;
+    for (int r = threadIdx.x >> 5; r < 32; r += 8) {
+        const int j = tby * 32 + r;
+        if (i < nx && j < ny) {
+            const double d = (double)fout[(size_t)j * nx + i] - (double)ref[(size_t)j * nx + i];
+            e2 += d * d;
+        }
+    }
+    return block_sum<256>(e2, lds);
 }
 
+// With a reference, each block also writes the squared error of its new
+// pixels (one partial per 32 x 32 tile) for the iteration's RMSE record, so
+// that needs no kernel of its own.
+__global__ __launch_bounds__(256) void k_p2_update(const DevState* st, const float* fcur, const float* __restrict__ g,
+                                                   float* fout, float* foutT, int clamp, int nx, int ny,
+                                                   const float* ref, double* part_rmse)
+{
+    __shared__ float tl[32][33];
+    __shared__ double lds[4];
+    p2_update_block(st, fcur, g, fout, foutT, clamp, nx, ny, blockIdx.x, blockIdx.y, tl);
+    if (ref) {
+        const double e2 = update_tile_sq_err(fout, ref, nx, ny, blockIdx.x, blockIdx.y, lds);
+        if (threadIdx.x == 0) part_rmse[blockIdx.y * gridDim.x + blockIdx.x] = e2;
+    }
+}
+
+int update_tiles(const Plan& p) { return ((p.nx + 31) / 32) * ((p.ny + 31) / 32); }
+
 hipError_t launch_p2_update(const Plan& p, const DevState* st, const float* fcur, const float* g, float* fout,
-                            float* foutT, int clamp, hipStream_t s)
+                            float* foutT, int clamp, hipStream_t s, const float* ref, double* part_rmse)
 {
     dim3 grid((p.nx + 31) / 32, (p.ny + 31) / 32);
-    hipLaunchKernelGGL(k_p2_update, grid, dim3(256), 0, s, st, fcur, g, fout, foutT, clamp, p.nx, p.ny);
+    hipLaunchKernelGGL(k_p2_update, grid, dim3(256), 0, s, st, fcur, g, fout, foutT, clamp, p.nx, p.ny, ref,
+                       part_rmse);
     return hipGetLastError();
 }
 
@@ -1021,25 +1051,35 @@ hipError_t blaunch_armijo_decide(const BatchDev& b, int max_bt, double c_arm, fl
     return hipGetLastError();
 }
 
+// With `rmse`, a slice with a reference also gets its per-tile squared errors
+// (as the one-slice update does), for the iteration's RMSE record.
 __global__ __launch_bounds__(256) void kb_p2_update(const SliceDev* __restrict__ sl, const int2* __restrict__ items,
-                                                    int n_items, int fcs, int gs, int fos, int fTs, int clamp)
+                                                    int n_items, int fcs, int gs, int fos, int fTs, int clamp,
+                                                    int rmse)
 {
     __shared__ float tl[32][33];
+    __shared__ double lds[4];
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 w = items[it];
         const SliceDev& d = sl[w.x];
         __syncthreads();
         p2_update_block(d.st, d.buf[fcs], d.buf[gs], d.buf[fos], bsel(d, fTs), clamp, d.nx, d.ny, w.y % d.t32x,
                         w.y / d.t32x, tl);
+        if (rmse && d.buf[kBufFRef]) {  // uniform per item
+            const double e2 = update_tile_sq_err(d.buf[fos], d.buf[kBufFRef], d.nx, d.ny, w.y % d.t32x,
+                                                 w.y / d.t32x, lds);
+            if (threadIdx.x == 0) d.part[kPartRmse][w.y] = e2;
+        }
     }
 }
 
-hipError_t blaunch_p2_update(const BatchDev& b, int fcur, int g, int fout, int foutT, int clamp, hipStream_t s)
+hipError_t blaunch_p2_update(const BatchDev& b, int fcur, int g, int fout, int foutT, int clamp, int rmse,
+                             hipStream_t s)
 {
     const int n = b.n_items[kShT32];
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(kb_p2_update, dim3(b.grid[kShT32]), dim3(256), 0, s, b.slices, b.items[kShT32], n, fcur, g,
-                       fout, foutT, clamp);
+                       fout, foutT, clamp, rmse);
     return hipGetLastError();
 }
 
