@@ -91,6 +91,7 @@ struct DevState {
     uint32_t prefix;
     uint32_t rank;               // rank still to find below the digits chosen so far
     uint32_t rank0;              // the order statistic's rank (set once per run)
+    uint32_t sel_prefix[2], sel_rank[2];  // one-slice path: prefix and rank after digits 0 and 1
     float sigma;
     float inv_sigma2;
     // P2 (Armijo): the current step's energies and decision
@@ -212,10 +213,10 @@ hipError_t launch_gd_p1(const Plan& p, const float* f, const float* z, float ste
 // sigma: three histogram passes, each closed by a one-block kernel
 hipError_t launch_edges_hist(const Plan& p, const float* f, float eps2, uint32_t* keys,
                              uint32_t* hist0, hipStream_t s);
-hipError_t launch_select_hist(const Plan& p, int pass, const uint32_t* keys, const DevState* st,
-                              uint32_t* hist, hipStream_t s);
-hipError_t launch_select_finalize(DevState* st, int pass, uint32_t* hist, float sigma_floor,
-                                  hipStream_t s);
+// pass 1 and 2 (each first closing the previous digit), then the last digit and sigma
+hipError_t launch_select_pass(const Plan& p, int pass, const uint32_t* keys, DevState* st, uint32_t* hist,
+                              hipStream_t s);
+hipError_t launch_select_sigma(DevState* st, const uint32_t* hist, float sigma_floor, hipStream_t s);
 hipError_t launch_sigma_out(const DevState* st, float* out, hipStream_t s);
 
 // P2: direction (optionally applying the previous step first), Armijo

@@ -191,13 +191,9 @@ static hipError_t enqueue_select(const Plan& p, Workspace& W, const float* img, 
 {
     hipError_t e;
     if ((e = launch_edges_hist(p, img, eps2, W.keys, W.hist, s)) != hipSuccess) return e;
-    if ((e = launch_select_finalize(W.st, 0, W.hist, floor_, s)) != hipSuccess) return e;
-    for (int pass = 1; pass <= 2; ++pass) {
-        if ((e = launch_select_hist(p, pass, W.keys, W.st, W.hist + pass * kSelectBins, s)) != hipSuccess) return e;
-        if ((e = launch_select_finalize(W.st, pass, W.hist + pass * kSelectBins, floor_, s)) != hipSuccess)
-            return e;
-    }
-    return hipSuccess;
+    for (int pass = 1; pass <= 2; ++pass)
+        if ((e = launch_select_pass(p, pass, W.keys, W.st, W.hist, s)) != hipSuccess) return e;
+    return launch_select_sigma(W.st, W.hist, floor_, s);
 }
 
 // sigma the per-iteration state starts from: fixed, or -1 (chosen by the selection)

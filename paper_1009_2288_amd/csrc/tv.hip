@@ -158,14 +158,14 @@ hipError_t launch_edges_hist(const Plan& p, const float* f, float eps2, uint32_t
 // pass 1: digit = bits 20..10 among keys whose bits 31..21 equal the prefix;
 // pass 2: digit = bits 9..0 among keys whose bits 31..10 equal the prefix.
 __device__ __forceinline__ void select_hist_block(const uint32_t* __restrict__ keys, size_t n, int pass,
-                                                  const DevState* st, uint32_t* hist, int blk, int nblk, uint32_t* h)
+                                                  uint32_t prefix, uint32_t* hist, int blk, int nblk, uint32_t* h)
 {
     for (int b = threadIdx.x; b < kSelectBins; b += 256) h[b] = 0u;
     __syncthreads();
     const int hshift = pass == 1 ? 21 : 10;
     const int dshift = pass == 1 ? 10 : 0;
     const uint32_t dmask = pass == 1 ? 2047u : 1023u;
-    const uint32_t want = st->prefix >> hshift;
+    const uint32_t want = prefix >> hshift;
     for (size_t e = (size_t)blk * 256 + threadIdx.x; e < n; e += (size_t)nblk * 256) {
         const uint32_t k = keys[e];
         if ((k >> hshift) == want) hist_add(h, (k >> dshift) & dmask);
@@ -175,40 +175,20 @@ __device__ __forceinline__ void select_hist_block(const uint32_t* __restrict__ k
         if (h[b]) atomicAdd(&hist[b], h[b]);
 }
 
-__global__ __launch_bounds__(256) void k_select_hist(const uint32_t* __restrict__ keys, size_t n, int pass,
-                                                     const DevState* st, uint32_t* hist)
-{
-    __shared__ uint32_t h[kSelectBins];
-    select_hist_block(keys, n, pass, st, hist, blockIdx.x, gridDim.x, h);
-}
-
-int select_blocks(const Plan& p)
-{
-    const size_t n = n_edges(p);
-    return (int)std::max<size_t>(1, std::min<size_t>((n + 2047) / 2048, 512));
-}
-
-hipError_t launch_select_hist(const Plan& p, int pass, const uint32_t* keys, const DevState* st, uint32_t* hist,
-                              hipStream_t s)
-{
-    hipLaunchKernelGGL(k_select_hist, dim3(select_blocks(p)), dim3(256), 0, s, keys, n_edges(p), pass, st, hist);
-    return hipGetLastError();
-}
-
-// The digit whose bucket holds the rank (an inclusive scan over 256 groups of
-// buckets), folded into the prefix; the histogram is cleared for its next use.
-// After the last digit the prefix is the bit pattern of the selected magnitude.
+// The digit of pass `pass` whose bucket holds `rank` (an inclusive scan over
+// 256 groups of buckets) and the count of keys in the buckets below it, in
+// S.found_digit / S.found_before for every thread.  After the last digit the
+// prefix is the bit pattern of the selected magnitude.
 struct SelShared {
     uint32_t sums[256];
     uint32_t found_digit, found_before;
 };
 
-__device__ __forceinline__ void select_finalize_block(DevState* st, int pass, uint32_t* hist, float floor_,
-                                                      SelShared& S)
+__device__ __forceinline__ int digit_shift(int pass) { return pass == 0 ? 21 : (pass == 1 ? 10 : 0); }
+
+__device__ __forceinline__ void select_digit(const uint32_t* hist, int pass, uint32_t rank, SelShared& S)
 {
     uint32_t* sums = S.sums;
-    uint32_t& found_digit = S.found_digit;
-    uint32_t& found_before = S.found_before;
     const int nb = pass == 2 ? 1024 : 2048;
     const int per = nb / 256;
     const int t = threadIdx.x;
@@ -216,8 +196,8 @@ __device__ __forceinline__ void select_finalize_block(DevState* st, int pass, ui
     for (int e = 0; e < per; ++e) local += hist[t * per + e];
     sums[t] = local;
     if (t == 0) {  // only kept if the rank exceeded the count, which cannot happen
-        found_digit = (uint32_t)(nb - 1);
-        found_before = 0u;
+        S.found_digit = (uint32_t)(nb - 1);
+        S.found_before = 0u;
     }
     __syncthreads();
     for (int o = 1; o < 256; o <<= 1) {
@@ -226,21 +206,29 @@ __device__ __forceinline__ void select_finalize_block(DevState* st, int pass, ui
         sums[t] += add;
         __syncthreads();
     }
-    const uint32_t rank = st->rank;
     const uint32_t before_group = t ? sums[t - 1] : 0u;
     if (before_group <= rank && rank < sums[t]) {
         uint32_t before = before_group;
         int d = t * per;
         while (d < t * per + per - 1 && before + hist[d] <= rank) before += hist[d++];
-        found_digit = (uint32_t)d;
-        found_before = before;
+        S.found_digit = (uint32_t)d;
+        S.found_before = before;
     }
     __syncthreads();
-    for (int e = 0; e < per; ++e) hist[t * per + e] = 0u;
-    if (t == 0) {
-        const int shift = pass == 0 ? 21 : (pass == 1 ? 10 : 0);
-        st->prefix |= found_digit << shift;
-        st->rank = rank - found_before;
+}
+
+// One digit closed: folded into the prefix, the rank reduced, the histogram
+// cleared for its next use; after pass 2, sigma.
+__device__ __forceinline__ void select_finalize_block(DevState* st, int pass, uint32_t* hist, float floor_,
+                                                      SelShared& S)
+{
+    const uint32_t rank = st->rank;
+    select_digit(hist, pass, rank, S);
+    const int per = (pass == 2 ? 1024 : 2048) / 256;
+    for (int e = 0; e < per; ++e) hist[threadIdx.x * per + e] = 0u;
+    if (threadIdx.x == 0) {
+        st->prefix |= S.found_digit << digit_shift(pass);
+        st->rank = rank - S.found_before;
         if (pass == 2) {
             const float sg = fmaxf(__uint_as_float(st->prefix), floor_);
             st->sigma = sg;
@@ -249,15 +237,58 @@ __device__ __forceinline__ void select_finalize_block(DevState* st, int pass, ui
     }
 }
 
-__global__ __launch_bounds__(256) void k_select_finalize(DevState* st, int pass, uint32_t* hist, float floor_)
+// One-slice passes 1 and 2: every block first closes the previous pass's
+// digit itself from that pass's histogram (the same computation in every
+// block), so the digit needs no kernel of its own; block 0 records the
+// prefix and rank after it for the next pass (in entries no block of this
+// launch reads).  hist: the three passes' histograms.
+__global__ __launch_bounds__(256) void k_select_pass(const uint32_t* __restrict__ keys, size_t n, int pass,
+                                                     DevState* st, uint32_t* hist)
 {
+    __shared__ uint32_t h[kSelectBins];
     __shared__ SelShared S;
-    select_finalize_block(st, pass, hist, floor_, S);
+    const uint32_t pin = pass == 1 ? st->prefix : st->sel_prefix[0];
+    const uint32_t rin = pass == 1 ? st->rank : st->sel_rank[0];
+    select_digit(hist + (pass - 1) * kSelectBins, pass - 1, rin, S);
+    const uint32_t pout = pin | (S.found_digit << digit_shift(pass - 1));
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->sel_prefix[pass - 1] = pout;
+        st->sel_rank[pass - 1] = rin - S.found_before;
+    }
+    select_hist_block(keys, n, pass, pout, hist + pass * kSelectBins, blockIdx.x, gridDim.x, h);
 }
 
-hipError_t launch_select_finalize(DevState* st, int pass, uint32_t* hist, float sigma_floor, hipStream_t s)
+int select_blocks(const Plan& p)
 {
-    hipLaunchKernelGGL(k_select_finalize, dim3(1), dim3(256), 0, s, st, pass, hist, sigma_floor);
+    const size_t n = n_edges(p);
+    return (int)std::max<size_t>(1, std::min<size_t>((n + 2047) / 2048, 512));
+}
+
+hipError_t launch_select_pass(const Plan& p, int pass, const uint32_t* keys, DevState* st, uint32_t* hist,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL(k_select_pass, dim3(select_blocks(p)), dim3(256), 0, s, keys, n_edges(p), pass, st, hist);
+    return hipGetLastError();
+}
+
+// The last digit and sigma = max(selected magnitude, floor), one block.
+__global__ __launch_bounds__(256) void k_select_sigma(DevState* st, const uint32_t* hist, float floor_)
+{
+    __shared__ SelShared S;
+    const uint32_t rin = st->sel_rank[1];
+    select_digit(hist + 2 * kSelectBins, 2, rin, S);
+    if (threadIdx.x == 0) {
+        st->prefix = st->sel_prefix[1] | S.found_digit;
+        st->rank = rin - S.found_before;
+        const float sg = fmaxf(__uint_as_float(st->prefix), floor_);
+        st->sigma = sg;
+        st->inv_sigma2 = 1.0f / (sg * sg);
+    }
+}
+
+hipError_t launch_select_sigma(DevState* st, const uint32_t* hist, float sigma_floor, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_select_sigma, dim3(1), dim3(256), 0, s, st, hist, sigma_floor);
     return hipGetLastError();
 }
 
@@ -979,7 +1010,8 @@ __global__ __launch_bounds__(256) void kb_select_hist(const SliceDev* __restrict
         const int2 w = items[it];
         const SliceDev& d = sl[w.x];
         __syncthreads();
-        select_hist_block(d.keys, (size_t)d.n_edges, pass, d.st, d.hist + pass * kSelectBins, w.y, d.sel_blocks, h);
+        select_hist_block(d.keys, (size_t)d.n_edges, pass, d.st->prefix, d.hist + pass * kSelectBins, w.y,
+                          d.sel_blocks, h);
     }
 }
 
