@@ -40,10 +40,10 @@ PMC_TRAFFIC = {
                 "bytes": (8336.7 * 2.0 + 115.0 * 1.0) * 1024},
     "backproject": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "7012b6bc1a09b6fc",
                     "bytes": (5980.5 * 2.0 + 1024.0 * 1.0) * 1024},
-    "project_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "8f4892c0ac95405b",
-                       "bytes": (60999.1 * 2.0 + 125.2 * 1.0) * 1024},
-    "backproject_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "8f4892c0ac95405b",
-                           "bytes": (56344.3 * 2.0 + 1304.0 * 1.0) * 1024},
+    "project_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "9627430b42c3fee4",
+                       "bytes": (69835.5 * 2.0 + 116.3 * 1.0) * 1024},
+    "backproject_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "9627430b42c3fee4",
+                           "bytes": (56062.3 * 2.0 + 1027.7 * 1.0) * 1024},
 }
 
 
