@@ -25,6 +25,11 @@ __device__ __forceinline__ float pix(const float* f, int nx, int ny, int i, int 
     return (i >= 0 && i < nx && j >= 0 && j < ny) ? f[(size_t)j * nx + i] : 0.0f;
 }
 
+// Square root of a positive normal float (here >= eps^2) with the hardware
+// instruction (within 1 ulp), not the correctly rounded expansion (a dozen
+// instructions): the P2 kernels take 36 of them per pixel.
+__device__ __forceinline__ float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // Magnitude of the half-edge between pixel values a and b, whose neighbouring
 // pixel pairs on the two sides across the edge direction are (au, bu) and (ad, bd).
 __device__ __forceinline__ float tv_edge(float a, float b, float au, float bu, float ad, float bd, float eps2)
@@ -32,7 +37,7 @@ __device__ __forceinline__ float tv_edge(float a, float b, float au, float bu, f
     const float d = b - a;
     const float m0 = 0.5f * (a + b), mu = 0.5f * (au + bu), md = 0.5f * (ad + bd);
     const float t1 = mu - m0, t2 = m0 - md;
-    return sqrtf(d * d + 0.5f * (t1 * t1) + 0.5f * (t2 * t2) + eps2);
+    return hw_sqrt(d * d + 0.5f * (t1 * t1) + 0.5f * (t2 * t2) + eps2);
 }
 
 // N[a][b] = f(i + a - 1, j + b - 1): a indexes x, b indexes y.
@@ -884,7 +889,7 @@ __device__ __forceinline__ void vjp_coef(float a, float b, float au, float bu, f
 {
     const float d = b - a;
     const float m0 = 0.5f * (a + b), t1 = 0.5f * (au + bu) - m0, t2 = m0 - 0.5f * (ad + bd);
-    const float tv = sqrtf(d * d + 0.5f * (t1 * t1) + 0.5f * (t2 * t2) + eps2);
+    const float tv = hw_sqrt(d * d + 0.5f * (t1 * t1) + 0.5f * (t2 * t2) + eps2);
     const float itv = 1.0f / tv;
     const float w = expf(-(tv * tv) * inv_s2);
     const float c = w * d * (itv + 2.0f * tv * inv_s2) * (itv * itv);
