@@ -27,8 +27,11 @@ __device__ __forceinline__ float pix(const float* f, int nx, int ny, int i, int 
 
 // Square root of a positive normal float (here >= eps^2) with the hardware
 // instruction (within 1 ulp), not the correctly rounded expansion (a dozen
-// instructions): the P2 kernels take 36 of them per pixel.
+// instructions): the P2 kernels take 36 of them per pixel.  The same for the
+// reciprocal of a magnitude and for the weights' exponential below.
 __device__ __forceinline__ float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+// Reciprocal of a positive normal float with the hardware instruction (within 1 ulp).
+__device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Magnitude of the half-edge between pixel values a and b, whose neighbouring
 // pixel pairs on the two sides across the edge direction are (au, bu) and (ad, bd).
@@ -309,7 +312,7 @@ hipError_t launch_sigma_out(const DevState* st, float* out, hipStream_t s)
 }
 
 // ------------------------------------------------------------------ direction g (Eq. 9, A2)
-__device__ __forceinline__ float weight(float tv, float inv_s2) { return expf(-(tv * tv) * inv_s2); }
+__device__ __forceinline__ float weight(float tv, float inv_s2) { return __expf(-(tv * tv) * inv_s2); }
 
 // The step f - t g of the previous descent step (none when it was rejected),
 // evaluated with the same float operation as the final update kernel.
@@ -354,10 +357,10 @@ __device__ __forceinline__ void tv_grad_block(const float* __restrict__ f, const
         const float wL = wx_in ? wx_in[xw + i] : weight(tL, inv_s2);
         const float wU = wy_in ? wy_in[(size_t)(j + 1) * nx + i] : weight(tU, inv_s2);
         const float wD = wy_in ? wy_in[(size_t)j * nx + i] : weight(tD, inv_s2);
-        const float FR = wR * (N.n[2][1] - c) / tR;
-        const float FL = wL * (c - N.n[0][1]) / tL;
-        const float FU = wU * (N.n[1][2] - c) / tU;
-        const float FD = wD * (c - N.n[1][0]) / tD;
+        const float FR = wR * (N.n[2][1] - c) * hw_rcp(tR);
+        const float FL = wL * (c - N.n[0][1]) * hw_rcp(tL);
+        const float FU = wU * (N.n[1][2] - c) * hw_rcp(tU);
+        const float FD = wD * (c - N.n[1][0]) * hw_rcp(tD);
         const size_t id = (size_t)j * nx + i;
         const float dv = c - v[id];
         const float gv = lambda * dv - (FR - FL) - (FU - FD);
@@ -520,10 +523,10 @@ __device__ __forceinline__ void tv_armijo_block(const float* __restrict__ f, con
             const float wL = wx_in ? wx_in[xw + gi] : weight(tL, inv_s2);
             const float wU = wy_in ? wy_in[(size_t)(gj + 1) * nx + gi] : weight(tU, inv_s2);
             const float wD = wy_in ? wy_in[(size_t)gj * nx + gi] : weight(tD, inv_s2);
-            const float FR = wR * (N.n[2][1] - c) / tR;
-            const float FL = wL * (c - N.n[0][1]) / tL;
-            const float FU = wU * (N.n[1][2] - c) / tU;
-            const float FD = wD * (c - N.n[1][0]) / tD;
+            const float FR = wR * (N.n[2][1] - c) * hw_rcp(tR);
+            const float FL = wL * (c - N.n[0][1]) * hw_rcp(tL);
+            const float FU = wU * (N.n[1][2] - c) * hw_rcp(tU);
+            const float FD = wD * (c - N.n[1][0]) * hw_rcp(tD);
             const size_t id = (size_t)gj * nx + gi;
             const float dv = c - v[id];
             gv = lambda * dv - (FR - FL) - (FU - FD);
@@ -890,8 +893,8 @@ __device__ __forceinline__ void vjp_coef(float a, float b, float au, float bu, f
     const float d = b - a;
     const float m0 = 0.5f * (a + b), t1 = 0.5f * (au + bu) - m0, t2 = m0 - 0.5f * (ad + bd);
     const float tv = hw_sqrt(d * d + 0.5f * (t1 * t1) + 0.5f * (t2 * t2) + eps2);
-    const float itv = 1.0f / tv;
-    const float w = expf(-(tv * tv) * inv_s2);
+    const float itv = hw_rcp(tv);
+    const float w = weight(tv, inv_s2);
     const float c = w * d * (itv + 2.0f * tv * inv_s2) * (itv * itv);
     const float ue = ub - ua;
     e3[e] = ue * (w * itv - c * d);
