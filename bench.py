@@ -59,6 +59,33 @@ PMC_VALU = {
 }
 
 
+# L2 read bytes per launch (L1-to-L2 read requests x 128-byte lines) from a
+# rocprofv3 --pmc pass; see profiles/eptv_operators_512x512_40views_pmc_l2.md.
+# Reported only while the kernel source's hash matches.
+PMC_L2 = {
+    "project": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "7012b6bc1a09b6fc",
+                "read_requests": 1.645e6},
+    "backproject": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "7012b6bc1a09b6fc",
+                    "read_requests": 0.460e6},
+    "project_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "9627430b42c3fee4",
+                       "read_requests": 1.735e6},
+    "backproject_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "9627430b42c3fee4",
+                           "read_requests": 1.695e6},
+}
+
+
+def pmc_l2(kernel, avg_ms):
+    import hashlib
+    e = PMC_L2.get(kernel)
+    if e is None:
+        return None
+    with open(os.path.join(ROOT, e["source"]), "rb") as fh:
+        if hashlib.sha256(fh.read()).hexdigest()[:16] != e["sha256_16"]:
+            return None
+    b = e["read_requests"] * 128.0
+    return {"l2_read_bytes_per_launch": b, "l2_read_gbps": b / (avg_ms * 1e-3) / 1e9}
+
+
 def pmc_valu(kernel, nnz):
     import hashlib
     e = PMC_VALU.get(kernel)
@@ -349,13 +376,14 @@ def main():
             achieved = nbytes / (t_dom * 1e-3)
             return {"bound": "hbm", "kernel": dom + "_stored", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
                     "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": pmc_traffic(dom + "_stored"),
-                    "avg_ms": t_dom, "algorithmic_bytes_per_launch": nbytes, "nnz": nnz}
+                    "avg_ms": t_dom, "algorithmic_bytes_per_launch": nbytes, "nnz": nnz,
+                    "pmc_l2": pmc_l2(dom + "_stored", t_dom)}
         flops = 2.0 * nnz
         achieved = flops / (t_dom * 1e-3)
         return {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK, "traffic": pmc_traffic(dom),
                 "avg_ms": t_dom, "algorithmic_flops_per_launch": flops, "nnz": nnz,
-                "pmc_valu": pmc_valu(dom, nnz)}
+                "pmc_valu": pmc_valu(dom, nnz), "pmc_l2": pmc_l2(dom, t_dom)}
 
     roof = roofline(stored)
     roof["operators_avg_ms"] = op_ms
