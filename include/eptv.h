@@ -140,7 +140,9 @@ int eptv_geometry_matrix(const eptv_geometry* geom, long long* nnz, long long* r
  * ray and pixel to a multiple of 4 entries (219 MB at 512^2 / 40 views x 736
  * bins).  A ray swept row by row indexes the transposed image, so that its
  * entries lie along the fast axis of the image it reads.  Owned by the plan;
- * built once, later calls only report the size.  Synchronous. */
+ * built once, later calls only report the size.  Synchronous.  EPTV_ERR_ARG
+ * when a copy would hold 2^31 entries or more (int32 offsets); EPTV_ERR_HIP
+ * when device memory runs out (nothing is kept then). */
 int eptv_plan_store_matrix(eptv_plan plan, size_t* device_bytes);
 
 /* q = alpha P x + beta q and z = alpha P^T r + beta z from the stored matrix
