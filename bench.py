@@ -152,11 +152,24 @@ def cpu_baseline(case, iters):
     t0 = time.perf_counter()
     M.reconstruct(y, p)
     dt = time.perf_counter() - t0
+    # one operator call each, on the phantom and the data
+    x = case.phantom.astype(np.float32)
+    t1 = time.perf_counter()
+    M.project(x)
+    t2 = time.perf_counter()
+    M.backproject(y)
+    t3 = time.perf_counter()
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": iters / dt, "unit": "iterations/s", "cores": O.num_threads(), "kind": "oracle",
             "sample": f"first {iters} outer iterations of the same 512^2/40-view workload (seed 0), "
                       f"FP64 oracle with a stored Siddon system matrix; matrix build ({M.nnz} nonzeros) "
                       f"excluded like the GPU plan creation",
-            "seconds": dt}
+            "seconds": dt, "project_ms": (t2 - t1) * 1e3, "backproject_ms": (t3 - t2) * 1e3, "cpu_model": model}
 
 
 def time_to_rmse(E, synth, P, torch, np, seeds, solver):
@@ -346,6 +359,16 @@ def main():
     log(f"bench: warmup {args.warmup}, timing {args.steps} iterations per operator")
     its, ms_step, rmse, f = iterations(stored)
     its_o, ms_o, rmse_o, _ = iterations(not stored)
+    # the headline operator once more with every kernel launched on its own (no graph)
+    had = os.environ.get("EPTV_NO_GRAPH")
+    os.environ["EPTV_NO_GRAPH"] = "1"
+    try:
+        its_ng, ms_ng, _, _ = iterations(stored)
+    finally:
+        if had is None:
+            os.environ.pop("EPTV_NO_GRAPH", None)
+        else:
+            os.environ["EPTV_NO_GRAPH"] = had
 
     # dominant kernels, timed live on the stream they run on
     x = f.clone()
@@ -444,6 +467,8 @@ def main():
                    "graph": os.environ.get("EPTV_NO_GRAPH", "0") in ("", "0"), "operator": args.operator},
         "rmse_vs_phantom": rmse,
         "other_operator": other,
+        "without_graph": {"value": its_ng, "ms_per_step": ms_ng,
+                          "note": "same operator, each of the iteration's kernels launched on the stream"},
         "time_to_rmse": ttr,
         "batch": bat,
         "cnn_training": cnn_train,
