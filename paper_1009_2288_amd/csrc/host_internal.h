@@ -13,6 +13,12 @@
 struct eptv_plan_s {
     eptv::Plan p;
     std::mutex graph_mu;
+    // page-locked host staging for reconstruct's small reads back (the RMSE
+    // check, the per-iteration records): a copy into it needs no bounce
+    // buffer of the runtime's.  Grown on demand; used under host_mu.
+    std::mutex host_mu;
+    void* host_buf = nullptr;
+    size_t host_bytes = 0;
 };
 
 namespace eptv {

@@ -392,6 +392,7 @@ int eptv_plan_destroy(eptv_plan h)
 {
     if (!h) return EPTV_ERR_ARG;
     Plan& p = h->p;
+    if (h->host_buf) (void)hipHostFree(h->host_buf);
     if (p.gexec) hipGraphExecDestroy(p.gexec);
     if (p.gexec_w) hipGraphExecDestroy(p.gexec_w);
     if (p.cap_stream) hipStreamDestroy(p.cap_stream);
@@ -677,6 +678,23 @@ int eptv_tv_step(eptv_plan h, const eptv_params* q, float* f, const float* v, fl
     return EPTV_OK;
 }
 
+// The plan's page-locked staging, at least `bytes`; call with h->host_mu held
+// and nothing in flight into the old buffer.
+static hipError_t host_staging(eptv_plan h, size_t bytes, void** out)
+{
+    if (h->host_bytes < bytes) {
+        if (h->host_buf) (void)hipHostFree(h->host_buf);
+        h->host_buf = nullptr;
+        h->host_bytes = 0;
+        const size_t n = std::max<size_t>(bytes, 4096);
+        const hipError_t e = hipHostMalloc(&h->host_buf, n, hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+        h->host_bytes = n;
+    }
+    *out = h->host_buf;
+    return hipSuccess;
+}
+
 static int reconstruct_impl(eptv_plan h, const eptv_params* q, const float* y, float* f, const float* f_ref,
                             const float* wx_in, const float* wy_in, int frozen, const int32_t* replay, void* ws,
                             size_t ws_bytes, eptv_stats* stats, void* stream)
@@ -716,9 +734,13 @@ static int reconstruct_impl(eptv_plan h, const eptv_params* q, const float* y, f
     auto check = [&]() -> int {
         ++done;
         if (!stop || done % every) return EPTV_OK;
-        double r = 0.0;
-        EPTV_HIP(hipMemcpyAsync(&r, W.st_rmse + (done - 1), sizeof r, hipMemcpyDeviceToHost, s));
+        std::lock_guard<std::mutex> hl(h->host_mu);
+        void* hb = nullptr;
+        EPTV_HIP(host_staging(h, sizeof(double), &hb));
+        EPTV_HIP(hipMemcpyAsync(hb, W.st_rmse + (done - 1), sizeof(double), hipMemcpyDeviceToHost, s));
         EPTV_HIP(hipStreamSynchronize(s));
+        double r = 0.0;
+        std::memcpy(&r, hb, sizeof r);
         if (r <= q->stop_rmse) stopped = true;
         return EPTV_OK;
     };
@@ -787,17 +809,32 @@ static int reconstruct_impl(eptv_plan h, const eptv_params* q, const float* y, f
     if (stats) {
         const size_t kk = (size_t)done;  // the records of the iterations that ran
         if (stats->iters_run) *stats->iters_run = done;
-        if (kk) {
-            if (stats->sigma) EPTV_HIP(hipMemcpyAsync(stats->sigma, W.st_sigma, kk * 4, hipMemcpyDeviceToHost, s));
-            if (stats->armijo_k && T > 0)
-                EPTV_HIP(hipMemcpyAsync(stats->armijo_k, W.st_k, kk * T * 4, hipMemcpyDeviceToHost, s));
-            if (stats->cgls_steps)
-                EPTV_HIP(hipMemcpyAsync(stats->cgls_steps, W.st_steps, kk * 4, hipMemcpyDeviceToHost, s));
-            if (stats->cgls_resid)
-                EPTV_HIP(hipMemcpyAsync(stats->cgls_resid, W.st_resid, kk * 8, hipMemcpyDeviceToHost, s));
-            if (stats->rmse && f_ref) EPTV_HIP(hipMemcpyAsync(stats->rmse, W.st_rmse, kk * 8, hipMemcpyDeviceToHost, s));
-        }
+        // every record into the page-locked staging, one synchronisation, then
+        // into the caller's arrays
+        struct Part {
+            void* dst;
+            const void* src;
+            size_t n, at;
+        } parts[5];
+        int np = 0;
+        size_t at = 0;
+        auto add = [&](void* dst, const void* src, size_t n) {
+            if (!dst || !n) return;
+            parts[np++] = Part{dst, src, n, at};
+            at += (n + 15) & ~(size_t)15;
+        };
+        add(stats->sigma, W.st_sigma, kk * 4);
+        add(T > 0 ? stats->armijo_k : nullptr, W.st_k, kk * T * 4);
+        add(stats->cgls_steps, W.st_steps, kk * 4);
+        add(stats->cgls_resid, W.st_resid, kk * 8);
+        add(f_ref ? stats->rmse : nullptr, W.st_rmse, kk * 8);
+        std::lock_guard<std::mutex> hl(h->host_mu);
+        void* hb = nullptr;
+        EPTV_HIP(host_staging(h, std::max<size_t>(at, 16), &hb));
+        for (int i = 0; i < np; ++i)
+            EPTV_HIP(hipMemcpyAsync((char*)hb + parts[i].at, parts[i].src, parts[i].n, hipMemcpyDeviceToHost, s));
         EPTV_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i < np; ++i) std::memcpy(parts[i].dst, (const char*)hb + parts[i].at, parts[i].n);
     }
     return EPTV_OK;
 }
