@@ -184,6 +184,10 @@ int armijo_blocks(const Plan& p);
 int select_blocks(const Plan& p);
 constexpr int kRmseBlocks = 256;
 
+// zero f and fT (zero != 0) or transpose f into fT, and reset the device state
+// with the selection rank and the iteration counter (one launch)
+hipError_t launch_recon_start(float* f, float* fT, int nx, int ny, int zero, DevState* st, uint32_t* hist,
+                              uint32_t rank, float sigma_fixed, hipStream_t s);
 hipError_t launch_transpose(const float* src, float* dst, int nx, int ny, hipStream_t s);
 hipError_t launch_fill(float* dst, size_t n, float value, hipStream_t s);
 hipError_t launch_project(const Plan& p, const float* x, const float* xT, float alpha, float beta,

@@ -718,9 +718,8 @@ static int reconstruct_impl(eptv_plan h, const eptv_params* q, const float* y, f
     const bool stop = f_ref && q->stop_rmse > 0;
     const int every = std::max(1, q->check_every);
 
-    EPTV_HIP(launch_state_init(W.st, W.hist, select_rank(p, q->edge_quantile), sigma_init(*q), 1, s));
-    if (q->zero_init) EPTV_HIP(launch_fill(f, (size_t)p.nx * p.ny, 0.0f, s));
-    EPTV_HIP(launch_transpose(f, W.fT, p.nx, p.ny, s));
+    EPTV_HIP(launch_recon_start(f, W.fT, p.nx, p.ny, q->zero_init != 0, W.st, W.hist,
+                                select_rank(p, q->edge_quantile), sigma_init(*q), s));
     // replay: the decisions are read back from the step records
     if (replay && (size_t)K * T)
         EPTV_HIP(hipMemcpyAsync(W.st_k, replay, (size_t)K * T * 4, hipMemcpyHostToDevice, s));

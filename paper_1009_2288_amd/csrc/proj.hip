@@ -23,6 +23,7 @@
 #include "batch.h"
 #include "eptv_internal.h"
 #include "reduce.h"
+#include "state.h"
 
 namespace eptv {
 
@@ -462,6 +463,39 @@ hipError_t launch_transpose(const float* src, float* dst, int nx, int ny, hipStr
 {
     dim3 grid((nx + 31) / 32, (ny + 31) / 32);
     hipLaunchKernelGGL(k_transpose, grid, dim3(256), 0, s, src, dst, nx, ny);
+    return hipGetLastError();
+}
+
+// The start of a reconstruction in one launch: the image zeroed (when asked)
+// or else transposed into fT, each block one 32 x 32 tile, and the device
+// state reset by block 0 (as k_state_init), so no separate kernels are needed.
+__global__ __launch_bounds__(256) void k_recon_start(float* f, float* __restrict__ fT, int nx, int ny, int zero,
+                                                     DevState* st, uint32_t* hist, uint32_t rank, float sigma_fixed)
+{
+    __shared__ float t[32][33];
+    if (zero) {
+        const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+        for (int k = ty; k < 32; k += 8) {
+            const int i = blockIdx.x * 32 + tx, j = blockIdx.y * 32 + k;
+            if (i < nx && j < ny) f[(size_t)j * nx + i] = 0.0f;
+            const int it = blockIdx.x * 32 + k, jt = blockIdx.y * 32 + tx;
+            if (it < nx && jt < ny) fT[(size_t)it * ny + jt] = 0.0f;
+        }
+    } else {
+        transpose_block(f, fT, nx, ny, blockIdx.x, blockIdx.y, t);
+    }
+    if (blockIdx.x == 0 && blockIdx.y == 0) {
+        if (threadIdx.x == 0) st->rank0 = rank;
+        reset_iteration_state(st, hist, sigma_fixed);
+        if (threadIdx.x == 0) st->iter = 0;
+    }
+}
+
+hipError_t launch_recon_start(float* f, float* fT, int nx, int ny, int zero, DevState* st, uint32_t* hist,
+                              uint32_t rank, float sigma_fixed, hipStream_t s)
+{
+    dim3 grid((nx + 31) / 32, (ny + 31) / 32);
+    hipLaunchKernelGGL(k_recon_start, grid, dim3(256), 0, s, f, fT, nx, ny, zero, st, hist, rank, sigma_fixed);
     return hipGetLastError();
 }
 
