@@ -56,6 +56,7 @@ typedef enum {
 
 /* Scanner geometry (Sec. 3; App. III Eq. A6).  view_angles_rad is a host array
  * of n_views angles, or NULL for equally spaced views over a full turn.  The
+ * image has at least 2 x 2 pixels (else EPTV_ERR_ARG).  The
  * source must lie outside the circle through the image corners, and the fan
  * (bin angles (b - (n_bins-1)/2 + bin_offset) dbeta_rad, one bin beyond each
  * end included) must stay within +-pi/2 of the central ray; otherwise

@@ -77,7 +77,8 @@ static Plan host_plan(const eptv_geometry* g)
 int validate_geometry(const eptv_geometry* g)
 {
     if (!g) return EPTV_ERR_ARG;
-    if (g->nx <= 0 || g->ny <= 0 || g->n_views <= 0 || g->n_bins <= 0) return EPTV_ERR_ARG;
+    // at least 2 x 2 pixels: the projector reads a cell's two pixels as one pair
+    if (g->nx < 2 || g->ny < 2 || g->n_views <= 0 || g->n_bins <= 0) return EPTV_ERR_ARG;
     if (g->nx > 32768 || g->ny > 32768 || (long long)g->n_views * g->n_bins > (1LL << 30)) return EPTV_ERR_ARG;
     if (!(g->pixel_mm > 0) || !std::isfinite(g->pixel_mm)) return EPTV_ERR_GEOMETRY;
     if (!(g->dbeta_rad > 0) || !std::isfinite(g->dbeta_rad) || !std::isfinite(g->bin_offset))

@@ -35,11 +35,17 @@ constexpr int kProjSeg = EPTV_PROJ_SEG;  // sweep segments (waves) per block of 
 constexpr int kProjUnroll = 4;           // sweep cells whose loads are issued together
 
 // Contribution of one sweep cell: the (at most two) pixels the ray crosses in
-// it, with out-of-image cells weighted 0 and their loads pointed at cell 0.
+// it, m0 and m0 + 1, neighbours along the line the image layout stores
+// contiguously.  Both come from one 8-byte load at `b` = m0 clamped to
+// [0, ncross - 2]; `s0` / `s1` say which half holds m0 / m0 + 1, and
+// out-of-image pixels are weighted 0 (the load then stays inside the line).
 struct CellTap {
-    int i0, i1;
+    int b;
+    bool s0, s1;  // true: the second float of the pair
     float a0, a1;
 };
+
+typedef float f32x2a4 __attribute__((ext_vector_type(2), aligned(4)));  // 4-byte aligned pair
 
 __device__ __forceinline__ CellTap cell_tap(long long lo, const RayFx& R, float wfull, int ncross)
 {
@@ -47,8 +53,9 @@ __device__ __forceinline__ CellTap cell_tap(long long lo, const RayFx& R, float 
     const bool in0 = (unsigned)w.m0 < (unsigned)ncross;
     const bool in1 = (unsigned)(w.m0 + 1) < (unsigned)ncross;
     CellTap t;
-    t.i0 = in0 ? w.m0 : 0;
-    t.i1 = in1 ? w.m0 + 1 : 0;
+    t.b = min(max(w.m0, 0), ncross - 2);
+    t.s0 = w.m0 != t.b;
+    t.s1 = w.m0 + 1 != t.b;
     t.a0 = in0 ? w.c0 : 0.0f;
     t.a1 = in1 ? w.c1 : 0.0f;
     return t;
@@ -85,23 +92,22 @@ __device__ __forceinline__ void project_block(const RayFx* __restrict__ rays, co
                 t[u] = cell_tap(lo, R, wfull, ncross);
                 lo += R.step;
             }
-            float p0[kProjUnroll], p1[kProjUnroll];
+            f32x2a4 pr[kProjUnroll];
+#pragma unroll
+            for (int u = 0; u < kProjUnroll; ++u)
+                pr[u] = *reinterpret_cast<const f32x2a4*>(line + u * ncross + t[u].b);
 #pragma unroll
             for (int u = 0; u < kProjUnroll; ++u) {
-                p0[u] = line[u * ncross + t[u].i0];
-                p1[u] = line[u * ncross + t[u].i1];
-            }
-#pragma unroll
-            for (int u = 0; u < kProjUnroll; ++u) {
-                acc = fmaf(t[u].a0, p0[u], acc);
-                acc1 = fmaf(t[u].a1, p1[u], acc1);
+                acc = fmaf(t[u].a0, t[u].s0 ? pr[u].y : pr[u].x, acc);
+                acc1 = fmaf(t[u].a1, t[u].s1 ? pr[u].y : pr[u].x, acc1);
             }
             line += (size_t)kProjUnroll * ncross;
         }
         for (; k < k1; ++k) {
             const CellTap t = cell_tap(lo, R, wfull, ncross);
-            acc = fmaf(t.a0, line[t.i0], acc);
-            acc1 = fmaf(t.a1, line[t.i1], acc1);
+            const f32x2a4 pv = *reinterpret_cast<const f32x2a4*>(line + t.b);
+            acc = fmaf(t.a0, t.s0 ? pv.y : pv.x, acc);
+            acc1 = fmaf(t.a1, t.s1 ? pv.y : pv.x, acc1);
             lo += R.step;
             line += ncross;
         }

@@ -53,6 +53,7 @@ def test_status_strings(lib):
     ("dbeta_rad", 0.02, 2),     # 256 bins x 0.02 rad: the fan would exceed 180 degrees
     ("pixel_mm", -1.0, 2),
     ("nx", 0, 1),
+    ("ny", 1, 1),               # a one-pixel-high image (the projector reads pixel pairs)
     ("n_bins", -3, 1),
     ("sdd_mm", 100.0, 2),       # detector closer than the source distance
 ])
