@@ -36,10 +36,10 @@ BF16_MFMA_PEAK = 2.5e15      # MI355X published dense bf16 matrix-core peak, FLO
 # taken: if the source has changed since, the figure is stale and reported as
 # null.
 PMC_TRAFFIC = {
-    "project": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "7012b6bc1a09b6fc",
-                "bytes": (8336.7 * 2.0 + 115.0 * 1.0) * 1024},
-    "backproject": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "7012b6bc1a09b6fc",
-                    "bytes": (5980.5 * 2.0 + 1024.0 * 1.0) * 1024},
+    "project": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "0984a5026983ecf3",
+                "bytes": (8330.6 * 2.0 + 115.0 * 1.0) * 1024},
+    "backproject": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "0984a5026983ecf3",
+                    "bytes": (5977.4 * 2.0 + 1024.0 * 1.0) * 1024},
     "project_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "9627430b42c3fee4",
                        "bytes": (69835.5 * 2.0 + 116.3 * 1.0) * 1024},
     "backproject_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "9627430b42c3fee4",
@@ -52,10 +52,10 @@ PMC_TRAFFIC = {
 # profiles/eptv_and_unet_valu_mfma_pmc.md.  Reported only while the kernel
 # source's hash matches.
 PMC_VALU = {
-    "project": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "7012b6bc1a09b6fc",
-                "valu_busy": 0.300, "valu_wave_instructions": 7.31e6},
-    "backproject": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "7012b6bc1a09b6fc",
-                    "valu_busy": 0.482, "valu_wave_instructions": 11.52e6},
+    "project": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "0984a5026983ecf3",
+                "valu_busy": 0.406, "valu_wave_instructions": 8.54e6},
+    "backproject": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "0984a5026983ecf3",
+                    "valu_busy": 0.494, "valu_wave_instructions": 11.47e6},
 }
 
 
@@ -63,9 +63,9 @@ PMC_VALU = {
 # rocprofv3 --pmc pass; see profiles/eptv_operators_512x512_40views_pmc_l2.md.
 # Reported only while the kernel source's hash matches.
 PMC_L2 = {
-    "project": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "7012b6bc1a09b6fc",
-                "read_requests": 1.645e6},
-    "backproject": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "7012b6bc1a09b6fc",
+    "project": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "0984a5026983ecf3",
+                "read_requests": 1.351e6},
+    "backproject": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "0984a5026983ecf3",
                     "read_requests": 0.460e6},
     "project_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "9627430b42c3fee4",
                        "read_requests": 1.735e6},
