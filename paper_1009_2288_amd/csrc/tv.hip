@@ -685,11 +685,23 @@ __device__ __forceinline__ void armijo_decide_block(DevState* st, const double* 
     double a[kArmijoFirst + 2];
 #pragma unroll
     for (int c = 0; c < kArmijoFirst + 2; ++c) a[c] = 0.0;
-    for (int b = threadIdx.x; b < nb; b += kDecThreads) {
+    // four blocks per thread at a time, all their loads issued before the sums
+    // (the same order of additions as one block at a time)
+    constexpr int kDecRounds = 4;
+    for (int b0 = threadIdx.x; b0 < nb; b0 += kDecRounds * kDecThreads) {
+        double v[kDecRounds][kArmijoFirst + 2];
 #pragma unroll
-        for (int c = 0; c < kArmijoFirst; ++c) a[c] += part_arm[(size_t)c * nb + b];
-        a[kArmijoFirst] += part_grad[b];
-        a[kArmijoFirst + 1] += part_grad[nb + b];
+        for (int r = 0; r < kDecRounds; ++r) {
+            const int b = b0 + r * kDecThreads;
+#pragma unroll
+            for (int c = 0; c < kArmijoFirst; ++c) v[r][c] = b < nb ? part_arm[(size_t)c * nb + b] : 0.0;
+            v[r][kArmijoFirst] = b < nb ? part_grad[b] : 0.0;
+            v[r][kArmijoFirst + 1] = b < nb ? part_grad[nb + b] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < kDecRounds; ++r)
+#pragma unroll
+            for (int c = 0; c < kArmijoFirst + 2; ++c) a[c] += v[r][c];
     }
     decide_reduce<kArmijoFirst + 2>(a, red, tot);
     const double q0 = tot[kArmijoFirst], g2 = tot[kArmijoFirst + 1];
