@@ -26,6 +26,9 @@ sys.path.insert(0, ROOT)
 
 FP32_VECTOR_PEAK = 157.3e12  # MI355X published FP32 vector peak, FLOP/s
 HBM_PEAK = 8.0e12            # MI355X published HBM3E bandwidth, B/s
+# P and P^T of an outer iteration (the stored_matrix solver parameter):
+# on the fly, both from the stored matrix, or P on the fly and P^T stored
+OPERATORS = {"fly": 0, "stored": 1, "hybrid": 2}
 BF16_MFMA_PEAK = 2.5e15      # MI355X published dense bf16 matrix-core peak, FLOP/s
 
 # HBM bytes per launch of the operator kernels on this workload, from two
@@ -307,9 +310,10 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="finally copy a buffer of this many MiB on the device (a plain copy kernel of known "
                          "size, to calibrate hardware byte counters against)")
-    ap.add_argument("--operator", choices=["fly", "stored"], default="stored",
+    ap.add_argument("--operator", choices=list(OPERATORS), default="stored",
                     help="P and P^T of the headline figure: from the stored float32 matrix (the paper's "
-                         "look-up tables) or on the fly; the other is timed and reported beside it")
+                         "look-up tables), on the fly, or P on the fly with P^T stored (hybrid); the others "
+                         "are timed and reported beside it")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
@@ -331,13 +335,12 @@ def main():
     y = torch.from_numpy(case.y.astype(np.float32)).cuda()
     ref = torch.from_numpy(case.phantom.astype(np.float32)).cuda()
     f = torch.zeros((g.ny, g.nx), dtype=torch.float32, device="cuda")
-    stored = args.operator == "stored"
     log(f"bench: storing the system matrix ({P.store_matrix() / 2**20:.0f} MiB)")
     base = dict(cgls_iters=3, tv_iters=5, lam=1000.0, edge_quantile=0.9, tv_eps=1e-4)
 
-    def iterations(use_stored):
+    def iterations(mode):
         """Iterations/s of `args.steps` outer iterations after `args.warmup`."""
-        prm = dict(base, stored_matrix=int(use_stored))
+        prm = dict(base, stored_matrix=OPERATORS[mode])
         f = torch.zeros((g.ny, g.nx), dtype=torch.float32, device="cuda")
         P.reconstruct(y, eptv.Params(outer_iters=args.warmup, zero_init=1, **prm), f=f, stats=False)
         s = torch.cuda.current_stream()
@@ -351,19 +354,18 @@ def main():
         wall = time.perf_counter() - t0
         ms_total = e0.elapsed_time(e1)
         rmse = float(torch.sqrt(torch.mean((f - ref) ** 2)).item())
-        name = "stored" if use_stored else "fly"
-        log(f"bench: {name}: {args.steps / (ms_total / 1e3):.1f} it/s ({ms_total / args.steps:.4f} ms/iteration, "
+        log(f"bench: {mode}: {args.steps / (ms_total / 1e3):.1f} it/s ({ms_total / args.steps:.4f} ms/iteration, "
             f"wall {wall:.3f} s), rmse {rmse:.3e}")
         return args.steps / (ms_total / 1e3), ms_total / args.steps, rmse, f
 
     log(f"bench: warmup {args.warmup}, timing {args.steps} iterations per operator")
-    its, ms_step, rmse, f = iterations(stored)
-    its_o, ms_o, rmse_o, _ = iterations(not stored)
+    its, ms_step, rmse, f = iterations(args.operator)
+    others = {m: iterations(m)[:3] for m in OPERATORS if m != args.operator}
     # the headline operator once more with every kernel launched on its own (no graph)
     had = os.environ.get("EPTV_NO_GRAPH")
     os.environ["EPTV_NO_GRAPH"] = "1"
     try:
-        its_ng, ms_ng, _, _ = iterations(stored)
+        its_ng, ms_ng, _, _ = iterations(args.operator)
     finally:
         if had is None:
             os.environ.pop("EPTV_NO_GRAPH", None)
@@ -383,13 +385,15 @@ def main():
     op_ms = {k: kernel_avg_ms(fn, args.kernel_reps, torch) for k, fn in ops.items()}
     log("bench: " + ", ".join(f"{k} {v * 1e3:.1f} us" for k, v in op_ms.items()) + f", nnz {nnz}")
 
-    def roofline(use_stored):
-        t_proj = op_ms["project_stored" if use_stored else "project_dual"]
-        t_bp = op_ms["backproject_stored" if use_stored else "backproject"]
-        per_it = {"project": 4 * t_proj, "backproject": 3 * t_bp}
+    def roofline(mode):
+        # the operator kernels of an outer iteration: 4 P calls and 3 P^T calls
+        k_proj = "project_stored" if mode == "stored" else "project_dual"
+        k_bp = "backproject" if mode == "fly" else "backproject_stored"
+        per_it = {"project": 4 * op_ms[k_proj], "backproject": 3 * op_ms[k_bp]}
         dom = max(per_it, key=per_it.get)
-        t_dom = t_proj if dom == "project" else t_bp
-        if use_stored:
+        kern = k_proj if dom == "project" else k_bp
+        t_dom = op_ms[kern]
+        if kern.endswith("_stored"):
             # one CSR (or CSC) pass: 4-byte value and 4-byte index per nonzero
             # (the padding to 4 entries per row is overhead, not counted), a
             # 4-byte offset per row (column), the input vector once, the output once
@@ -408,10 +412,10 @@ def main():
                 "avg_ms": t_dom, "algorithmic_flops_per_launch": flops, "nnz": nnz,
                 "pmc_valu": pmc_valu(dom, nnz), "pmc_l2": pmc_l2(dom, t_dom)}
 
-    roof = roofline(stored)
+    roof = roofline(args.operator)
     roof["operators_avg_ms"] = op_ms
-    other = {"operator": "fly" if stored else "stored", "value": its_o, "ms_per_step": ms_o,
-             "rmse_vs_phantom": rmse_o, "roofline": roofline(not stored)}
+    other = [{"operator": m, "stored_matrix": OPERATORS[m], "value": v[0], "ms_per_step": v[1],
+              "rmse_vs_phantom": v[2], "roofline": roofline(m)} for m, v in others.items()]
     if roof["bound"] == "hbm":
         # what HBM delivers to a plain device copy far larger than the 256 MB
         # Infinity Cache (read + write bytes per second)
@@ -423,7 +427,7 @@ def main():
     ttr = None
     if args.rmse_seeds > 0:
         log(f"bench: time to the oracle's RMSE, seeds 0-{args.rmse_seeds - 1}")
-        ttr = time_to_rmse(eptv, synth, P, torch, np, range(args.rmse_seeds), {"stored_matrix": int(stored)})
+        ttr = time_to_rmse(eptv, synth, P, torch, np, range(args.rmse_seeds), {"stored_matrix": OPERATORS[args.operator]})
         log(f"bench: plain EPTV reaches the oracle RMSE in {ttr['plain_seconds_median']} s (median), "
             f"CNN-assisted in {ttr.get('cnn_seconds_median')} s")
 
@@ -466,7 +470,7 @@ def main():
                    "image": [g.ny, g.nx], "views": g.n_views, "bins": g.n_bins, "cgls_iters": 3, "tv_iters": 5,
                    "graph": os.environ.get("EPTV_NO_GRAPH", "0") in ("", "0"), "operator": args.operator},
         "rmse_vs_phantom": rmse,
-        "other_operator": other,
+        "other_operators": other,
         "without_graph": {"value": its_ng, "ms_per_step": ms_ng,
                           "note": "same operator, each of the iteration's kernels launched on the stream"},
         "time_to_rmse": ttr,

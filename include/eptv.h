@@ -94,7 +94,11 @@ typedef struct {
     int p2_start;        /* 0: P2 starts at v (P1's output); 1: at f^(k) */
     int positivity;      /* 1: step 3 of the algorithm (f = max(f, 0)) */
     int stored_matrix;   /* 1: P and P^T from the matrix kept by eptv_plan_store_matrix
-                            (the look-up-table strategy of Sec. 2.3); 0: on the fly */
+                            (the look-up-table strategy of Sec. 2.3); 0: on the fly;
+                            2: P on the fly and P^T from the stored matrix (the same
+                            float32 matrix either way, so P^T stays P's exact
+                            transpose).  1 and 2 need the stored matrix (else
+                            EPTV_ERR_ARG) */
     int interp_bp;       /* 1: P1 uses the Eq. 11 interpolating backprojector in place
                             of P^T (the paper's on-the-fly code, Sec. 2.3); 0: the
                             exact transpose */

@@ -155,7 +155,7 @@ int check_params(const eptv_params* q)
                             q->armijo_max_backtracks > 4096 || !(q->armijo_c >= 0)))
         return EPTV_ERR_ARG;
     if ((long long)q->outer_iters * q->tv_iters > (1LL << 28)) return EPTV_ERR_ARG;
-    if ((q->stored_matrix != 0 && q->stored_matrix != 1) || (q->interp_bp != 0 && q->interp_bp != 1))
+    if (q->stored_matrix < 0 || q->stored_matrix > 2 || (q->interp_bp != 0 && q->interp_bp != 1))
         return EPTV_ERR_ARG;
     if (q->check_every < 0 || !(q->stop_rmse >= 0) || !std::isfinite(q->stop_rmse)) return EPTV_ERR_ARG;
     return EPTV_OK;
@@ -245,9 +245,11 @@ static hipError_t enqueue_iteration(const Ctx& c, hipStream_t s)
     hipError_t e;
     // (the per-iteration state was reset by the previous iteration's last kernel, or by the caller)
     // Step 1: P1.  r = y - P f
-    // P and P^T: on the fly, or from the stored matrix (the paper's two strategies, Sec. 2.3)
+    // P and P^T: on the fly, or from the stored matrix (the paper's two strategies,
+    // Sec. 2.3), or P on the fly and P^T stored (stored_matrix = 2); both are the
+    // same float32 matrix, so the pair stays exactly adjoint
     auto proj = [&](const float* x, const float* xT, float al, float be, const float* cc, float* out, double* part) {
-        return q.stored_matrix ? launch_project_stored(p, x, xT, al, be, cc, out, part, s)
+        return q.stored_matrix == 1 ? launch_project_stored(p, x, xT, al, be, cc, out, part, s)
                                : launch_project(p, x, xT, al, be, cc, out, part, s);
     };
     // P^T: the exact transpose (on the fly or stored), or the Eq. 11 operator

@@ -263,15 +263,15 @@ def test_reconstruct_paper_case_20_iterations(E, oracle):
     np.testing.assert_allclose(sg["sigma"], so["sigma"], rtol=1e-4)
 
 
-@pytest.mark.parametrize("stored", [0, 1], ids=["fly", "stored"])
+@pytest.mark.parametrize("stored", [0, 1, 2], ids=["fly", "stored", "fly_P_stored_PT"])
 def test_reconstruct_paper_case_100_iterations_replay(E, oracle, stored):
     """512^2 / 40 x 736 over the workload's full K = 100, in replay mode: the
     GPU runs free and records its Armijo indices; the oracle takes them
     instead of searching and certifies each against its own FP64 inequality
     (slack 1e-6 |Q0|: over these 500 decisions the oracle's own free run has
     two near-ties below 1e-5, where float32 may decide either way), and then
-    the images must agree to 1e-4.  With P and P^T on the fly and from the
-    stored matrix."""
+    the images must agree to 1e-4.  With P and P^T on the fly, from the
+    stored matrix, and P on the fly with P^T stored."""
     c = synth.make_case("paper", 0)
     P = plan(E, "paper")
     if stored:
@@ -351,6 +351,13 @@ def test_workspace_and_argument_errors(E):
     assert lib.eptv_project(P._h, x.data_ptr(), q.data_ptr(), 1.0, 0.0, ws.data_ptr() + 8, need, None) == 3
     with pytest.raises(E.EptvError):
         P.reconstruct(torch.zeros((30, 256), device="cuda"), E.Params(outer_iters=2, cgls_iters=65))
+    for sm in (-1, 3):
+        with pytest.raises(E.EptvError):
+            P.reconstruct(torch.zeros((30, 256), device="cuda"), E.Params(outer_iters=1, stored_matrix=sm))
+    fresh = E.Plan(GEOMS["small"]())  # no stored matrix: both stored modes are refused
+    for sm in (1, 2):
+        with pytest.raises(E.EptvError):
+            fresh.reconstruct(torch.zeros((30, 256), device="cuda"), E.Params(outer_iters=1, stored_matrix=sm))
     with pytest.raises(ValueError):
         P.project(torch.zeros((64, 128), device="cuda"))
     with pytest.raises(TypeError):
@@ -393,11 +400,12 @@ def test_stored_matrix_parity(E, oracle, name):
     assert torch.equal(P.project_stored_dual(xd, xd.t().contiguous()), P.project_stored(xd))
 
 
-def test_reconstruct_stored_matrix(E, oracle):
+@pytest.mark.parametrize("stored", [1, 2], ids=["stored", "fly_P_stored_PT"])
+def test_reconstruct_stored_matrix(E, oracle, stored):
     c = synth.make_case("small", 0)
     P = plan(E, "small")
     P.store_matrix()
-    f, sg, fo, so = run_pair(E, oracle, "small", c, 50, stored_matrix=1)
+    f, sg, fo, so = run_pair(E, oracle, "small", c, 50, stored_matrix=stored)
     assert well_separated(so)
     assert np.array_equal(sg["armijo_k"], so["armijo_k"])
     assert rel(f, fo) <= 1e-4
