@@ -242,8 +242,10 @@ int eptv_tv_step(eptv_plan plan, const eptv_params* params, float* f, const floa
  * from the P2 start image, P2 by eptv_tv_step's descent, positivity; f holds
  * f^(K) on return.  y [n_views][n_bins] are the log-transformed data.
  * f_ref (may be NULL) is an image the per-iteration RMSE is measured
- * against.  One outer iteration is captured once as a HIP graph and replayed
- * (set EPTV_NO_GRAPH=1 in the environment to launch kernels directly). */
+ * against.  The iteration's kernels are launched on the stream one by one;
+ * with EPTV_GRAPH=1 in the environment one outer iteration is captured once
+ * as a HIP graph and replayed instead (same results bit for bit; on MI355X
+ * the direct launches are slightly faster while the host thread is idle). */
 int eptv_reconstruct(eptv_plan plan, const eptv_params* params, const float* y, float* f,
                      const float* f_ref, void* ws, size_t ws_bytes, eptv_stats* stats, void* stream);
 
@@ -270,7 +272,8 @@ int eptv_reconstruct_weighted(eptv_plan plan, const eptv_params* params, const f
  * Many slices, each with its own geometry (image size, views, bins), iterated
  * together: every phase of the EPTV iteration (Sec. 2.2) is one launch for
  * the whole batch, a persistent grid walking a list of (slice, block) items,
- * and one outer iteration of all slices is one captured graph.  Each slice's
+ * and with EPTV_GRAPH=1 one outer iteration of all slices is one captured
+ * graph (as for eptv_reconstruct).  Each slice's
  * arithmetic is that of eptv_reconstruct on its own plan; with the
  * projector's launch shape at 16 segments (the one-slice default) the images
  * are identical bit for bit.  The stored-matrix and Eq. 11 variants and the

@@ -52,16 +52,16 @@ def test_batch_equals_single_slices_bit_for_bit(E, graph):
     cases = small_batch()
     B = E.Batch([c.geom for c in cases])
     B.set_launch(16, 2, 8)  # the one-slice projector shape
-    old = os.environ.get("EPTV_NO_GRAPH")
-    os.environ["EPTV_NO_GRAPH"] = "0" if graph else "1"
+    old = os.environ.get("EPTV_GRAPH")
+    os.environ["EPTV_GRAPH"] = "1" if graph else "0"
     try:
         fs, sts = B.reconstruct([dev(c.y) for c in cases], E.Params(outer_iters=8, **PRM),
                                 f_refs=[dev(c.phantom) for c in cases])
     finally:
         if old is None:
-            os.environ.pop("EPTV_NO_GRAPH", None)
+            os.environ.pop("EPTV_GRAPH", None)
         else:
-            os.environ["EPTV_NO_GRAPH"] = old
+            os.environ["EPTV_GRAPH"] = old
     for i, c in enumerate(cases):
         f1, st1 = single(E, c, 8)
         assert np.array_equal(fs[i].cpu().numpy(), f1), i

@@ -319,12 +319,14 @@ def test_reconstruct_is_deterministic_and_graph_equals_direct(E, monkeypatch):
     P = plan(E, "small")
     prm = E.Params(outer_iters=6)
     y = dev(c.y)
+    monkeypatch.delenv("EPTV_GRAPH", raising=False)
     f1, _ = P.reconstruct(y, prm, stats=False)
     f2, _ = P.reconstruct(y, prm, stats=False)
-    monkeypatch.setenv("EPTV_NO_GRAPH", "1")
+    monkeypatch.setenv("EPTV_GRAPH", "1")
     f3, _ = P.reconstruct(y, prm, stats=False)
+    f4, _ = P.reconstruct(y, prm, stats=False)  # the captured graph replayed by a second call
     torch.cuda.synchronize()
-    assert torch.equal(f1, f2) and torch.equal(f1, f3)
+    assert torch.equal(f1, f2) and torch.equal(f1, f3) and torch.equal(f1, f4)
 
 
 def test_warm_start_split_equals_straight_run(E):
