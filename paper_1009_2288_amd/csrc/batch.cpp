@@ -1,8 +1,8 @@
 // batch.cpp -- host side of the batched EPTV iteration (eptv_batch_* of
 // eptv.h): one plan per slice, the (slice, block) work lists of every block
 // shape, the per-slice device descriptors, the tuner that picks the launch
-// shapes, and the outer loop replaying one captured graph per iteration of
-// the whole batch.
+// shapes, and the outer loop (each iteration of the whole batch launched
+// phase by phase, or replayed from one captured graph with EPTV_GRAPH=1).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

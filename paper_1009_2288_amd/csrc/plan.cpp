@@ -1,5 +1,6 @@
 // plan.cpp -- host side of libeptv: geometry tables, workspace layout, the
-// enqueue of one outer iteration, graph capture and the C ABI of eptv.h.
+// enqueue of one outer iteration, its launch (kernel by kernel, or as a
+// captured graph) and the C ABI of eptv.h.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -752,7 +753,8 @@ static int reconstruct_impl(eptv_plan h, const eptv_params* q, const float* y, f
         if (r <= q->stop_rmse) stopped = true;
         return EPTV_OK;
     };
-    // one captured graph per kind of iteration (adaptive, or with the given weights)
+    // the iteration launched kernel by kernel, or (EPTV_GRAPH=1) one captured
+    // graph per kind of iteration (adaptive, or with the given weights)
     auto run = [&](const Ctx& cc, int count, hipGraphExec_t& gexec, std::vector<uint64_t>& gkey) -> int {
         if (count <= 0 || stopped) return EPTV_OK;
         if (no_graph()) {
