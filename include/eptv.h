@@ -125,7 +125,12 @@ typedef struct eptv_plan_s* eptv_plan;
 
 /* Precompute the per-ray and per-view tables of a geometry on the current
  * device.  Allocates device memory; the plan owns it until eptv_plan_destroy.
- * A plan is immutable after creation and may be shared by several streams. */
+ * A plan is immutable after creation and may be shared by several streams.
+ * Sizes: 2 <= nx, ny <= 32768 and n_views x n_bins <= 2^30 (else
+ * EPTV_ERR_ARG, checked before any device call); EPTV_ERR_GEOMETRY for a
+ * scanner that cannot see the whole image (source inside the circle through
+ * its corners, detector nearer than the source, a fan of 180 degrees or more,
+ * non-finite values). */
 int eptv_plan_create(const eptv_geometry* geom, eptv_plan* out);
 int eptv_plan_destroy(eptv_plan plan);
 

@@ -55,6 +55,8 @@ def test_status_strings(lib):
     ("nx", 0, 1),
     ("ny", 1, 1),               # a one-pixel-high image (the projector reads pixel pairs)
     ("n_bins", -3, 1),
+    ("nx", 32769, 1),           # beyond the largest image side (32768)
+    ("n_views", 5_000_000, 1),  # 1.28e9 rays: beyond the 2^30 limit on views x bins
     ("sdd_mm", 100.0, 2),       # detector closer than the source distance
 ])
 def test_plan_create_rejects_bad_geometry_without_gpu(lib, field, value, status):
