@@ -57,9 +57,9 @@ PMC_TRAFFIC = {
 # source's hash matches.
 PMC_VALU = {
     "project": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "0984a5026983ecf3",
-                "valu_busy": 0.406, "valu_wave_instructions": 8.54e6},
+                "valu_busy": 0.401, "valu_wave_instructions": 8.54e6},
     "backproject": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "0984a5026983ecf3",
-                    "valu_busy": 0.494, "valu_wave_instructions": 11.47e6},
+                    "valu_busy": 0.492, "valu_wave_instructions": 11.47e6},
 }
 
 
