@@ -236,7 +236,8 @@ hipError_t launch_tv_grad(const Plan& p, const float* f, const float* g_prev, co
 hipError_t launch_tv_armijo(const Plan& p, const float* f, const float* g_prev, const DevState* st_prev,
                             float* f_out, const float* v, float lambda, const DevState* st, float eps2, float* g,
                             float* wx, float* wy, double* part_grad, double* part_arm, float t0, float shrink,
-                            hipStream_t s, const float* wx_in = nullptr, const float* wy_in = nullptr);
+                            hipStream_t s, const float* wx_in = nullptr, const float* wy_in = nullptr,
+                            DevState* sel_st = nullptr, const uint32_t* sel_hist = nullptr, float sel_floor = 0.0f);
 
 hipError_t launch_armijo_decide(const Plan& p, DevState* st, const double* part_grad, const double* part_arm,
                                 int max_bt, double c_arm, float t0, float shrink, int32_t* st_k, int step, int T,

@@ -188,14 +188,16 @@ float t0_of(const eptv_params& q)
 }
 
 // sigma from the half-edge magnitudes of `img` (radix select, three digits).
+// The selection of sigma (three digit passes); with last_digit false the
+// last digit is left to the first P2 kernel (enqueue_p2's close_sigma).
 static hipError_t enqueue_select(const Plan& p, Workspace& W, const float* img, float eps2, float floor_,
-                                 hipStream_t s)
+                                 hipStream_t s, bool last_digit = true)
 {
     hipError_t e;
     if ((e = launch_edges_hist(p, img, eps2, W.keys, W.hist, s)) != hipSuccess) return e;
     for (int pass = 1; pass <= 2; ++pass)
         if ((e = launch_select_pass(p, pass, W.keys, W.st, W.hist, s)) != hipSuccess) return e;
-    return launch_select_sigma(W.st, W.hist, floor_, s);
+    return last_digit ? launch_select_sigma(W.st, W.hist, floor_, s) : hipSuccess;
 }
 
 // sigma the per-iteration state starts from: fixed, or -1 (chosen by the selection)
@@ -209,7 +211,7 @@ float sigma_init(const eptv_params& q) { return q.sigma_fixed < 0 ? -1.0f : (flo
 static hipError_t enqueue_p2(const Plan& p, Workspace& W, const eptv_params& q, const float* start, const float* v,
                              int n_steps, float* fout, float* foutT, int clamp, int32_t* st_k, hipStream_t s,
                              const float* wx_in = nullptr, const float* wy_in = nullptr, int replay = 0,
-                             const float* f_ref = nullptr)
+                             const float* f_ref = nullptr, bool close_sigma = false)
 {
     hipError_t e;
     const float eps2 = (float)(q.tv_eps * q.tv_eps);
@@ -222,8 +224,11 @@ static hipError_t enqueue_p2(const Plan& p, Workspace& W, const eptv_params& q, 
         const float* gprev = t > 0 ? gbuf[(t - 1) & 1] : nullptr;
         float* fnext = t > 0 ? fbuf[t & 1] : nullptr;
         // the direction at the current iterate and the first Armijo trials, one pass
+        // (the first step closes sigma's last digit when the selection left it open)
+        const bool sel = close_sigma && t == 0;
         if ((e = launch_tv_armijo(p, fcur, gprev, W.st, fnext, v, (float)q.lambda, W.st, eps2, g, W.wx, W.wy,
-                                  W.part_grad, W.part_arm, t0, shrink, s, wx_in, wy_in)) != hipSuccess)
+                                  W.part_grad, W.part_arm, t0, shrink, s, wx_in, wy_in, sel ? W.st : nullptr,
+                                  sel ? W.hist + 2 * kSelectBins : nullptr, (float)q.sigma_floor)) != hipSuccess)
             return e;
         if (t > 0) fcur = fnext;
         if ((e = launch_armijo_decide(p, W.st, W.part_grad, W.part_arm, q.armijo_max_backtracks, q.armijo_c, t0,
@@ -282,14 +287,16 @@ static hipError_t enqueue_iteration(const Ctx& c, hipStream_t s)
     }
     // Step 2: P2 from v (or f^(k)), sigma chosen once from the start image.
     const float* start = q.p2_start ? c.f : W.u;
-    if (adaptive && T > 0 && !c.wx_in) {
-        if ((e = enqueue_select(p, W, start, (float)(q.tv_eps * q.tv_eps), (float)q.sigma_floor, s)) != hipSuccess)
+    const bool select = adaptive && T > 0 && !c.wx_in;
+    if (select) {  // the last digit is closed by the first descent step's kernel
+        if ((e = enqueue_select(p, W, start, (float)(q.tv_eps * q.tv_eps), (float)q.sigma_floor, s, false)) !=
+            hipSuccess)
             return e;
     }
     // Step 3 (positivity) is fused into the last descent update.
     // With a reference, the last update also forms the squared errors per tile.
     if ((e = enqueue_p2(p, W, q, start, W.u, T, c.f, W.fT, q.positivity, W.st_k, s, c.wx_in, c.wy_in, c.replay,
-                        c.f_ref)) != hipSuccess)
+                        c.f_ref, select)) != hipSuccess)
         return e;
     if (c.f_ref && T == 0) {
         if ((e = launch_rmse_part(p, c.f, c.f_ref, W.part_rmse, s)) != hipSuccess) return e;

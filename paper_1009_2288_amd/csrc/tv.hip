@@ -474,6 +474,7 @@ struct TvArmShared {
     float dv[kT][kT];          // own pixels' f - v
     double lds[4];
     double red[4][kArmijoFirst];
+    SelShared sel;
 };
 
 __device__ __forceinline__ void tv_armijo_block(const float* __restrict__ f, const float* __restrict__ g_prev,
@@ -482,23 +483,53 @@ __device__ __forceinline__ void tv_armijo_block(const float* __restrict__ f, con
                                                 const DevState* st, float eps2, float* __restrict__ g, float* wx,
                                                 float* wy, double* part_grad, double* part_arm, float t0,
                                                 float shrink, int bx, int by, int b, int nb, TvArmShared& S,
-                                                const float* wx_in = nullptr, const float* wy_in = nullptr)
+                                                const float* wx_in = nullptr, const float* wy_in = nullptr,
+                                                DevState* sel_st = nullptr, const uint32_t* sel_hist = nullptr,
+                                                float sel_floor = 0.0f)
 {
-    const float inv_s2 = st->inv_sigma2;
     const int i0 = bx * kT, j0 = by * kT;
     const int kp = g_prev ? st_prev->k : -1;
     const float tp = g_prev ? st_prev->t : 0.0f;
-    // the current iterate on the window (zero outside the image, like pix())
-    for (int idx = threadIdx.x; idx < (kT + 4) * (kT + 4); idx += 256) {
+    // the current iterate on the window (zero outside the image, like pix()),
+    // loaded into registers first so that the loads overlap the selection below
+    constexpr int kWin = (kT + 4) * (kT + 4), kWinPer = (kWin + 255) / 256;
+    float fv[kWinPer];
+#pragma unroll
+    for (int u = 0; u < kWinPer; ++u) {
+        const int idx = threadIdx.x + 256 * u;
         const int li = idx % (kT + 4), lj = idx / (kT + 4);
         const int gi = i0 - 2 + li, gj = j0 - 2 + lj;
         float val = 0.0f;
-        if ((unsigned)gi < (unsigned)nx && (unsigned)gj < (unsigned)ny) {
+        if (idx < kWin && (unsigned)gi < (unsigned)nx && (unsigned)gj < (unsigned)ny) {
             const size_t id = (size_t)gj * nx + gi;
             val = f[id];
             if (g_prev) val = stepped(val, g_prev[id], kp, tp);
         }
-        S.f[lj][li] = val;
+        fv[u] = val;
+    }
+    // sigma: the first descent step of an adaptive iteration closes the
+    // selection's last digit itself (the same computation in every block, as
+    // k_select_sigma would do it); block 0 records it for the later steps
+    float inv_s2;
+    if (sel_hist) {
+        const uint32_t rin = sel_st->sel_rank[1];
+        select_digit(sel_hist, 2, rin, S.sel);
+        const uint32_t prefix = sel_st->sel_prefix[1] | S.sel.found_digit;
+        const float sg = fmaxf(__uint_as_float(prefix), sel_floor);
+        inv_s2 = 1.0f / (sg * sg);
+        if (b == 0 && threadIdx.x == 0) {
+            sel_st->prefix = prefix;
+            sel_st->rank = rin - S.sel.found_before;
+            sel_st->sigma = sg;
+            sel_st->inv_sigma2 = inv_s2;
+        }
+    } else {
+        inv_s2 = st->inv_sigma2;
+    }
+#pragma unroll
+    for (int u = 0; u < kWinPer; ++u) {
+        const int idx = threadIdx.x + 256 * u;
+        if (idx < kWin) S.f[idx / (kT + 4)][idx % (kT + 4)] = fv[u];
     }
     __syncthreads();
     const int ti = threadIdx.x & (kT - 1), tj = threadIdx.x / kT;
@@ -615,22 +646,24 @@ __global__ __launch_bounds__(256) void k_tv_armijo(const float* __restrict__ f, 
                                                    const float* __restrict__ v, int nx, int ny, float lambda,
                                                    const DevState* st, float eps2, float* __restrict__ g, float* wx,
                                                    float* wy, double* part_grad, double* part_arm, float t0,
-                                                   float shrink, const float* wx_in, const float* wy_in)
+                                                   float shrink, const float* wx_in, const float* wy_in,
+                                                   DevState* sel_st, const uint32_t* sel_hist, float sel_floor)
 {
     __shared__ TvArmShared S;
     tv_armijo_block(f, g_prev, st_prev, f_out, v, nx, ny, lambda, st, eps2, g, wx, wy, part_grad, part_arm, t0,
                     shrink, blockIdx.x, blockIdx.y, blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y, S,
-                    wx_in, wy_in);
+                    wx_in, wy_in, sel_st, sel_hist, sel_floor);
 }
 
 hipError_t launch_tv_armijo(const Plan& p, const float* f, const float* g_prev, const DevState* st_prev,
                             float* f_out, const float* v, float lambda, const DevState* st, float eps2, float* g,
                             float* wx, float* wy, double* part_grad, double* part_arm, float t0, float shrink,
-                            hipStream_t s, const float* wx_in, const float* wy_in)
+                            hipStream_t s, const float* wx_in, const float* wy_in, DevState* sel_st,
+                            const uint32_t* sel_hist, float sel_floor)
 {
     dim3 grid((p.nx + kT - 1) / kT, (p.ny + kT - 1) / kT);
     hipLaunchKernelGGL(k_tv_armijo, grid, dim3(256), 0, s, f, g_prev, st_prev, f_out, v, p.nx, p.ny, lambda, st,
-                       eps2, g, wx, wy, part_grad, part_arm, t0, shrink, wx_in, wy_in);
+                       eps2, g, wx, wy, part_grad, part_arm, t0, shrink, wx_in, wy_in, sel_st, sel_hist, sel_floor);
     return hipGetLastError();
 }
 
