@@ -490,28 +490,32 @@ __device__ __forceinline__ void tv_armijo_block(const float* __restrict__ f, con
     const int i0 = bx * kT, j0 = by * kT;
     const int kp = g_prev ? st_prev->k : -1;
     const float tp = g_prev ? st_prev->t : 0.0f;
-    // the current iterate on the window (zero outside the image, like pix()),
-    // loaded into registers first so that the loads overlap the selection below
-    constexpr int kWin = (kT + 4) * (kT + 4), kWinPer = (kWin + 255) / 256;
-    float fv[kWinPer];
-#pragma unroll
-    for (int u = 0; u < kWinPer; ++u) {
-        const int idx = threadIdx.x + 256 * u;
+    // the current iterate on the window (zero outside the image, like pix())
+    constexpr int kWin = (kT + 4) * (kT + 4);
+    auto win_value = [&](int idx) {
         const int li = idx % (kT + 4), lj = idx / (kT + 4);
         const int gi = i0 - 2 + li, gj = j0 - 2 + lj;
         float val = 0.0f;
-        if (idx < kWin && (unsigned)gi < (unsigned)nx && (unsigned)gj < (unsigned)ny) {
+        if ((unsigned)gi < (unsigned)nx && (unsigned)gj < (unsigned)ny) {
             const size_t id = (size_t)gj * nx + gi;
             val = f[id];
             if (g_prev) val = stepped(val, g_prev[id], kp, tp);
         }
-        fv[u] = val;
-    }
-    // sigma: the first descent step of an adaptive iteration closes the
-    // selection's last digit itself (the same computation in every block, as
-    // k_select_sigma would do it); block 0 records it for the later steps
+        return val;
+    };
     float inv_s2;
     if (sel_hist) {
+        // sigma: the first descent step of an adaptive iteration closes the
+        // selection's last digit itself (the same computation in every block,
+        // as k_select_sigma would do it; block 0 records it for the later
+        // steps), with the window's loads issued first so that they overlap it
+        constexpr int kWinPer = (kWin + 255) / 256;
+        float fv[kWinPer];
+#pragma unroll
+        for (int u = 0; u < kWinPer; ++u) {
+            const int idx = threadIdx.x + 256 * u;
+            fv[u] = idx < kWin ? win_value(idx) : 0.0f;
+        }
         const uint32_t rin = sel_st->sel_rank[1];
         select_digit(sel_hist, 2, rin, S.sel);
         const uint32_t prefix = sel_st->sel_prefix[1] | S.sel.found_digit;
@@ -523,13 +527,14 @@ __device__ __forceinline__ void tv_armijo_block(const float* __restrict__ f, con
             sel_st->sigma = sg;
             sel_st->inv_sigma2 = inv_s2;
         }
+#pragma unroll
+        for (int u = 0; u < kWinPer; ++u) {
+            const int idx = threadIdx.x + 256 * u;
+            if (idx < kWin) S.f[idx / (kT + 4)][idx % (kT + 4)] = fv[u];
+        }
     } else {
         inv_s2 = st->inv_sigma2;
-    }
-#pragma unroll
-    for (int u = 0; u < kWinPer; ++u) {
-        const int idx = threadIdx.x + 256 * u;
-        if (idx < kWin) S.f[idx / (kT + 4)][idx % (kT + 4)] = fv[u];
+        for (int idx = threadIdx.x; idx < kWin; idx += 256) S.f[idx / (kT + 4)][idx % (kT + 4)] = win_value(idx);
     }
     __syncthreads();
     const int ti = threadIdx.x & (kT - 1), tj = threadIdx.x / kT;
