@@ -314,10 +314,13 @@ def test_reconstruct_variants_ragged(E, oracle, kw):
     assert rel(f, fo) <= 1e-4, kw
 
 
-def test_reconstruct_is_deterministic_and_graph_equals_direct(E, monkeypatch):
+@pytest.mark.parametrize("stored", [0, 1, 2], ids=["fly", "stored", "fly_P_stored_PT"])
+def test_reconstruct_is_deterministic_and_graph_equals_direct(E, monkeypatch, stored):
     c = synth.make_case("small", 1)
     P = plan(E, "small")
-    prm = E.Params(outer_iters=6)
+    if stored:
+        P.store_matrix()
+    prm = E.Params(outer_iters=6, stored_matrix=stored)
     y = dev(c.y)
     monkeypatch.delenv("EPTV_GRAPH", raising=False)
     f1, _ = P.reconstruct(y, prm, stats=False)
