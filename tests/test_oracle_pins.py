@@ -497,6 +497,133 @@ def test_armijo_steps_decrease_frozen_surrogate(oracle):
         f = f1
 
 
+def a3_edges_by_definition(f, eps):
+    """Every half-edge magnitude of Eq. A3 written out from the equation, one
+    edge at a time, with ghost pixels 0 (zero boundary): x-edges [ny][nx+1]
+    (entry [j][i+1] = edge (i+1/2, j)), y-edges [ny+1][nx] (entry [j+1][i] =
+    edge (i, j+1/2))."""
+    ny, nx = f.shape
+
+    def at(i, j):
+        return float(f[j, i]) if 0 <= i < nx and 0 <= j < ny else 0.0
+
+    tx = np.zeros((ny, nx + 1))
+    ty = np.zeros((ny + 1, nx))
+    for j in range(ny):
+        for i in range(-1, nx):
+            mid = [(at(i, jj) + at(i + 1, jj)) / 2 for jj in (j - 1, j, j + 1)]
+            tx[j, i + 1] = math.sqrt((at(i + 1, j) - at(i, j)) ** 2 + (mid[2] - mid[1]) ** 2 / 2
+                                     + (mid[1] - mid[0]) ** 2 / 2 + eps * eps)
+    for j in range(-1, ny):
+        for i in range(nx):
+            mid = [(at(ii, j) + at(ii, j + 1)) / 2 for ii in (i - 1, i, i + 1)]
+            ty[j + 1, i] = math.sqrt((at(i, j + 1) - at(i, j)) ** 2 + (mid[2] - mid[1]) ** 2 / 2
+                                     + (mid[1] - mid[0]) ** 2 / 2 + eps * eps)
+    return tx, ty
+
+
+@pytest.mark.parametrize("a,b,h,lam", [(2, 2, 1.0, 3.0), (3, 5, 0.02, 1000.0), (7, 4, 2.5, 0.25)])
+def test_surrogate_rectangle_closed_form(oracle, a, b, h, lam):
+    """The P2 energy compared by the Armijo rule (Sec. 2.2 with Eq. 8's
+    splitting term; App. II Eq. A3), Q(h) = lambda/2 ||h - v||^2 + sum_e w_e
+    TV_e(h), for an a x b rectangle of height h, v = 0, w = 1, eps = 0:
+    lambda/2 a b h^2 + h[(2 + 2 sqrt 2)(a + b) + 4 sqrt 2 - 8]."""
+    f = rect_image(16, a, b, h)
+    ones_x, ones_y = np.ones((16, 17)), np.ones((17, 16))
+    q = oracle.surrogate(f, np.zeros_like(f), lam, ones_x, ones_y, 0.0)
+    closed = 0.5 * lam * a * b * h * h + h * ((2 + 2 * math.sqrt(2)) * (a + b) + 4 * math.sqrt(2) - 8)
+    assert abs(q - closed) <= 1e-13 * closed
+    # the data term alone (w = 0): lambda/2, not lambda, times the squared distance to v
+    v = np.full_like(f, 0.5 * h)
+    q0 = oracle.surrogate(f, v, lam, np.zeros((16, 17)), np.zeros((17, 16)), 0.0)
+    assert abs(q0 - 0.5 * lam * (a * b * (0.5 * h) ** 2 + (256 - a * b) * (0.5 * h) ** 2)) <= 1e-13 * q0
+    # only the y-edges weighted: their share of the rectangle's multiset, by
+    # hand.  The 2a y-edges crossing the top and bottom sides have main
+    # difference h (magnitude h, or 3h/(2 sqrt 2) in the 4 corner columns);
+    # along each vertical side the columns just inside and just outside hold
+    # b - 1 y-edges each with a transverse difference h (h/sqrt 2); the 4
+    # y-edges diagonal to the corners see h/2 (h/(2 sqrt 2)).
+    qy = oracle.surrogate(f, np.zeros_like(f), lam, np.zeros((16, 17)), ones_y, 0.0)
+    r2 = math.sqrt(2.0)
+    want_y = h * (2 * (a - 2) + 4 * 3 / (2 * r2) + 4 * (b - 1) / r2 + 4 / (2 * r2))
+    assert abs((qy - 0.5 * lam * a * b * h * h) - want_y) <= 1e-13 * want_y
+
+
+def test_surrogate_with_random_weights_against_eq_a3_by_definition(oracle):
+    """Q with independent random weights on the two edge families and a random
+    v, against the definition evaluated edge by edge in this test.  That
+    evaluation is first tied to the hand-derived half-edge multiset of a
+    rectangle, so it is not the oracle's formula retyped unchecked."""
+    a, b, h = 4, 3, 0.7
+    f = rect_image(12, a, b, h, i0=4, j0=4)
+    tx, ty = a3_edges_by_definition(f, 0.0)
+    vals = np.sort(np.concatenate([tx.ravel(), ty.ravel()]))
+    exp = []
+    for val, c in rect_edge_multiset(a, b, h):
+        exp += [val] * c
+    np.testing.assert_allclose(vals[vals > 0], np.sort(exp), rtol=1e-14)
+    rng = np.random.default_rng(41)
+    for img, eps in ((f, 0.0), (rng.uniform(0, 0.03, size=(9, 11)), 1e-3)):
+        ny, nx = img.shape
+        v = rng.uniform(0, 0.03, size=img.shape)
+        wx = rng.uniform(0, 1, size=(ny, nx + 1))
+        wy = rng.uniform(0, 2, size=(ny + 1, nx))
+        lam = 37.0
+        tx, ty = a3_edges_by_definition(img, eps)
+        want = 0.5 * lam * float(np.sum((img - v) ** 2)) + float(np.sum(wx * tx)) + float(np.sum(wy * ty))
+        got = oracle.surrogate(img, v, lam, wx, wy, eps)
+        assert abs(got - want) <= 1e-13 * abs(want)
+        # each family's weights enter with their own edges (swapped families differ)
+        if nx != ny:
+            continue
+        swapped = oracle.surrogate(img, v, lam, wy.T.copy(), wx.T.copy(), eps)
+        assert abs(swapped - got) > 1e-6 * abs(got)
+
+
+def test_iteration_records_against_direct_computation(oracle):
+    """The per-step records of one outer iteration, recomputed independently:
+    CGLS gamma_m = ||A^T r_m||^2 and delta_m = ||A s_m||^2 by the App. I
+    recurrences written here with the brute-force dense matrix (A f = 0 at the
+    zero start), and the Armijo energies Q0 / Q1 of the first descent step as
+    the P2 energy evaluated at v and at v - t g with Eq. A3 by definition and
+    Eq. 5's weights at v."""
+    g, M, A, y = full_rank_case(oracle)
+    A = dense_bruteforce(g)
+    Mst, lam, eps = 3, 50.0, 1e-3
+    p = oracle.Params(outer_iters=1, cgls_iters=Mst, tv_iters=2, lam=lam, tv_eps=eps, sigma_fixed=0.05)
+    _, st = M.reconstruct(y, p)
+    yv = y.ravel()
+    r = yv.copy()
+    u = np.zeros(64)
+    s = A.T @ r
+    gam = s @ s
+    for m in range(Mst):
+        assert abs(st["cgls_gamma"][0, m] - gam) <= 1e-9 * gam
+        q = A @ s
+        dl = q @ q
+        assert abs(st["cgls_delta"][0, m] - dl) <= 1e-9 * dl
+        a = gam / dl
+        u += a * s
+        r -= a * q
+        z = A.T @ r
+        gn = z @ z
+        s = z + (gn / gam) * s
+        gam = gn
+    v = u.reshape(8, 8)
+    tx, ty = a3_edges_by_definition(v, eps)
+    wx, wy = np.exp(-(tx / 0.05) ** 2), np.exp(-(ty / 0.05) ** 2)
+    q0 = float(np.sum(wx * tx) + np.sum(wy * ty))  # h = v: no data term
+    assert abs(st["armijo_q0"][0, 0] - q0) <= 1e-8 * q0
+    k = int(st["armijo_k"][0, 0])
+    assert k >= 0
+    gdir, _, _ = oracle.tv_gradient(v, v, lam, 0.05, eps)
+    h = v - (1.0 / lam) * 0.5 ** k * gdir
+    th, tyh = a3_edges_by_definition(h, eps)
+    q1 = 0.5 * lam * float(np.sum((h - v) ** 2)) + float(np.sum(wx * th) + np.sum(wy * tyh))
+    assert abs(st["armijo_q1"][0, 0] - q1) <= 1e-8 * q1
+    assert st["armijo_q1"][0, 0] <= q0
+
+
 def test_energy_monotone_theorem_case(oracle):
     """Gradient-form P1 with step 1/lambda, lambda >= mu ||P||^2, plain TV
     weights, P2 from f^(k), no truncation: majorisation-minimisation makes
