@@ -51,7 +51,7 @@ typedef enum {
     EPTV_ERR_GEOMETRY = 2,  /* source inside the image circle, dbeta <= 0 ... */
     EPTV_ERR_WORKSPACE = 3, /* workspace missing or smaller than required */
     EPTV_ERR_HIP = 4,       /* a HIP runtime call failed */
-    EPTV_ERR_NONFINITE = 5  /* reserved */
+    EPTV_ERR_NONFINITE = 5  /* an input holds NaN or +-inf (only with eptv_params.check_finite) */
 } eptv_status;
 
 /* Scanner geometry (Sec. 3; App. III Eq. A6).  view_angles_rad is a host array
@@ -107,6 +107,10 @@ typedef struct {
     double stop_rmse;    /* > 0: stop at the first checked iteration whose RMSE to
                             f_ref is <= stop_rmse (the paper's iteration count is
                             case-dependent, Sec. 2.2); 0: run outer_iters */
+    int check_finite;    /* 1: before iterating, scan y (and the warm start f when
+                            zero_init = 0) on the device and return EPTV_ERR_NONFINITE,
+                            with nothing else enqueued and f untouched, if any value is
+                            NaN or infinite (synchronises the stream once); 0: no scan */
 } eptv_params;
 
 /* Optional per-iteration records, host arrays filled when a call that takes
@@ -119,6 +123,18 @@ typedef struct {
     double* rmse;        /* [K]   root-mean-square difference to f_ref, if given */
     int32_t* iters_run;  /* [1]   outer iterations actually run (fewer than K after an
                             early stop); the arrays above hold that many entries */
+    /* The Armijo energies of each GD step (Sec. 2.2): Q(h) = lambda/2 ||h - v||^2 +
+     * sum_e w_e TV_e(h) with the step's weights, at the step's start point
+     * (armijo_q0) and at the accepted point f - t g (armijo_q1; = armijo_q0 when
+     * the step is skipped).  Sums in float64 of the float32 terms. */
+    double* armijo_q0;   /* [K*T] */
+    double* armijo_q1;   /* [K*T] */
+    /* CGLS scalars of each P1 (App. I), step m = 0..M-1 of iteration k at
+     * [k*M + m]: gamma_m = ||P^T r_m||^2 and delta_m = ||P s_m||^2 as the step
+     * computed them; 0 for steps after a breakdown (delta_m is also 0 for the
+     * step whose gamma_m stopped CGLS).  Empty for the gradient form of P1. */
+    double* cgls_gamma;  /* [K*M] */
+    double* cgls_delta;  /* [K*M] */
 } eptv_stats;
 
 typedef struct eptv_plan_s* eptv_plan;

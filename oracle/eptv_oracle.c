@@ -484,17 +484,19 @@ double orc_select_sigma(int nx, int ny, const double* f, double eps, double q, d
  * the same decision, negative by how much it would not. */
 static int tv_step_with(int nx, int ny, const orc_params* p, double* f, const double* v, double sigma, int n_steps,
                         int* k_out, double* margin_out, double* sigma_out, const double* wx_in, const double* wy_in,
-                        const int* replay);
+                        const int* replay, double* q0_out, double* q1_out);
 
 int orc_tv_step(int nx, int ny, const orc_params* p, double* f, const double* v,
                 double sigma, int n_steps, int* k_out, double* margin_out, double* sigma_out)
 {
-    return tv_step_with(nx, ny, p, f, v, sigma, n_steps, k_out, margin_out, sigma_out, NULL, NULL, NULL);
+    return tv_step_with(nx, ny, p, f, v, sigma, n_steps, k_out, margin_out, sigma_out, NULL, NULL, NULL, NULL, NULL);
 }
 
+/* q0_out / q1_out (may be NULL): Q at each step's start and at the accepted
+ * point (Q at the start again when no step is taken). */
 static int tv_step_with(int nx, int ny, const orc_params* p, double* f, const double* v, double sigma, int n_steps,
                         int* k_out, double* margin_out, double* sigma_out, const double* wx_in, const double* wy_in,
-                        const int* replay)
+                        const int* replay, double* q0_out, double* q1_out)
 {
     size_t np = (size_t)nx * ny, ex = n_xedges(nx, ny), ey = n_yedges(nx, ny);
     if (sigma < 0 && !wx_in) sigma = orc_select_sigma(nx, ny, f, p->tv_eps, p->edge_quantile, p->sigma_floor);
@@ -522,7 +524,7 @@ static int tv_step_with(int nx, int ny, const orc_params* p, double* f, const do
         for (size_t i = 0; i < np; ++i) gg += g[i] * g[i];
 
         int acc = -1;
-        double margin = HUGE_VAL, t = t0;
+        double margin = HUGE_VAL, t = t0, q_acc = q0;
         const double scale = fabs(q0) > 0 ? fabs(q0) : 1.0;
         if (replay) {
             /* the given decision, certified against every trial the search would make */
@@ -534,7 +536,10 @@ static int tv_step_with(int nx, int ny, const orc_params* p, double* f, const do
                 double thr = q0 - p->armijo_c * t * gg;
                 double cert = (k == kr ? thr - qk : qk - thr) / scale;
                 if (cert < margin) margin = cert;
-                if (k == kr) break;
+                if (k == kr) {
+                    q_acc = qk;
+                    break;
+                }
                 t *= p->armijo_shrink;
             }
             acc = kr;
@@ -547,6 +552,7 @@ static int tv_step_with(int nx, int ny, const orc_params* p, double* f, const do
                 if (rel < margin) margin = rel;
                 if (qk <= thr) {
                     acc = k;
+                    q_acc = qk;
                     break;
                 }
                 t *= p->armijo_shrink;
@@ -555,6 +561,8 @@ static int tv_step_with(int nx, int ny, const orc_params* p, double* f, const do
         if (acc >= 0) memcpy(f, h, sizeof(double) * np);
         if (k_out) k_out[s] = acc;
         if (margin_out) margin_out[s] = margin;
+        if (q0_out) q0_out[s] = q0;
+        if (q1_out) q1_out[s] = q_acc;
     }
     free(tvx);
     free(tvy);
@@ -585,7 +593,19 @@ static void backproject_with(const orc_matrix* m, int interp, const double* r, d
         orc_backproject(m, r, z);
 }
 
+static int cgls_rec(const orc_matrix* m, int interp_bp, const double* y, double* u, int iters, double* resid,
+                    double* gamma_out, double* delta_out);
+
 int orc_cgls_with(const orc_matrix* m, int interp_bp, const double* y, double* u, int iters, double* resid)
+{
+    return cgls_rec(m, interp_bp, y, u, iters, resid, NULL, NULL);
+}
+
+/* gamma_out / delta_out (may be NULL, iters entries): ||P^T r||^2 at the top
+ * of every step reached and ||P s||^2 of every step that formed it; 0 for
+ * the entries after a breakdown. */
+static int cgls_rec(const orc_matrix* m, int interp_bp, const double* y, double* u, int iters, double* resid,
+                    double* gamma_out, double* delta_out)
 {
     size_t nr = (size_t)m->n_rows, nc = (size_t)m->n_cols;
     double* r = (double*)malloc(sizeof(double) * nr);
@@ -599,9 +619,15 @@ int orc_cgls_with(const orc_matrix* m, int interp_bp, const double* y, double* u
     double gam = dot(nc, z, z), gam0 = gam;
     int steps = 0;
     for (int it = 0; it < iters; ++it) {
+        if (gamma_out) gamma_out[it] = 0.0;
+        if (delta_out) delta_out[it] = 0.0;
+    }
+    for (int it = 0; it < iters; ++it) {
+        if (gamma_out) gamma_out[it] = gam;
         if (!(gam > 1e-30 * gam0)) break;
         orc_project(m, s, q);
         double del = dot(nr, q, q);
+        if (delta_out) delta_out[it] = del;
         if (!(del > 0.0)) break;
         double a = gam / del;
         for (size_t i = 0; i < nc; ++i) u[i] += a * s[i];
@@ -679,7 +705,10 @@ static int reconstruct_impl(const orc_matrix* m, const orc_params* p, const doub
         double resid = 0.0;
         int steps = 0;
         if (p->cgls_iters > 0) {
-            steps = orc_cgls_with(m, p->interp_bp, y, v, p->cgls_iters, &resid);
+            const size_t at = (size_t)k * p->cgls_iters;
+            steps = cgls_rec(m, p->interp_bp, y, v, p->cgls_iters, &resid,
+                             st && st->cgls_gamma ? st->cgls_gamma + at : NULL,
+                             st && st->cgls_delta ? st->cgls_delta + at : NULL);
         } else {
             orc_project(m, f, q);
             for (size_t i = 0; i < nr; ++i) q[i] -= y[i];
@@ -698,7 +727,9 @@ static int reconstruct_impl(const orc_matrix* m, const orc_params* p, const doub
             sigma = orc_select_sigma(nx, ny, w, p->tv_eps, p->edge_quantile, p->sigma_floor);
         tv_step_with(nx, ny, p, w, v, sigma, T, st && st->armijo_k ? st->armijo_k + (size_t)k * T : NULL,
                      st && st->armijo_margin ? st->armijo_margin + (size_t)k * T : NULL, NULL,
-                     frozen ? wx_in : NULL, frozen ? wy_in : NULL, replay ? replay + (size_t)k * T : NULL);
+                     frozen ? wx_in : NULL, frozen ? wy_in : NULL, replay ? replay + (size_t)k * T : NULL,
+                     st && st->armijo_q0 ? st->armijo_q0 + (size_t)k * T : NULL,
+                     st && st->armijo_q1 ? st->armijo_q1 + (size_t)k * T : NULL);
         /* step 3 */
         if (p->positivity)
             for (size_t i = 0; i < nc; ++i)

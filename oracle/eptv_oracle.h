@@ -105,6 +105,10 @@ typedef struct {              /* every pointer may be NULL */
     int* cgls_steps;          /* [K] */
     double* cgls_resid;       /* [K] ||y - P v||^2 at the end of P1 */
     double* rmse;             /* [K] vs f_ref when given */
+    double* armijo_q0;        /* [K*T] Q at each descent step's start */
+    double* armijo_q1;        /* [K*T] Q at the accepted point (= armijo_q0 when skipped) */
+    double* cgls_gamma;       /* [K*M] ||P^T r_m||^2 of each CGLS step reached, else 0 */
+    double* cgls_delta;       /* [K*M] ||P s_m||^2 of each step that computed it, else 0 */
 } orc_stats;
 
 /* CGLS on min ||P u - y||^2 from the given u (App. I). Returns steps run. */

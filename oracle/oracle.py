@@ -52,7 +52,9 @@ class _Stats(C.Structure):
     _fields_ = [("sigma", C.POINTER(C.c_double)), ("armijo_k", C.POINTER(C.c_int)),
                 ("armijo_margin", C.POINTER(C.c_double)), ("energy", C.POINTER(C.c_double)),
                 ("cgls_steps", C.POINTER(C.c_int)), ("cgls_resid", C.POINTER(C.c_double)),
-                ("rmse", C.POINTER(C.c_double))]
+                ("rmse", C.POINTER(C.c_double)), ("armijo_q0", C.POINTER(C.c_double)),
+                ("armijo_q1", C.POINTER(C.c_double)), ("cgls_gamma", C.POINTER(C.c_double)),
+                ("cgls_delta", C.POINTER(C.c_double))]
 
 
 @dataclass
@@ -231,13 +233,16 @@ class Matrix:
         armijo_replay: optional [K][T] backtrack indices (-1: no step) taken
         instead of searching; armijo_margin then holds the signed
         certification of each (>= 0: the oracle's own search agrees)."""
-        K, T = params.outer_iters, params.tv_iters
+        K, T, M = params.outer_iters, params.tv_iters, params.cgls_iters
         f = np.zeros(self.nx * self.ny) if f0 is None else _f64(f0).reshape(-1).copy()
         st = {"sigma": np.zeros(K), "armijo_k": np.zeros(max(K * T, 1), np.int32),
               "armijo_margin": np.zeros(max(K * T, 1)), "energy": np.zeros(K),
-              "cgls_steps": np.zeros(K, np.int32), "cgls_resid": np.zeros(K), "rmse": np.zeros(K)}
+              "cgls_steps": np.zeros(K, np.int32), "cgls_resid": np.zeros(K), "rmse": np.zeros(K),
+              "armijo_q0": np.zeros(max(K * T, 1)), "armijo_q1": np.zeros(max(K * T, 1)),
+              "cgls_gamma": np.zeros(max(K * M, 1)), "cgls_delta": np.zeros(max(K * M, 1))}
         cs = _Stats(_d(st["sigma"]), _i(st["armijo_k"]), _d(st["armijo_margin"]), _d(st["energy"]),
-                    _i(st["cgls_steps"]), _d(st["cgls_resid"]), _d(st["rmse"]))
+                    _i(st["cgls_steps"]), _d(st["cgls_resid"]), _d(st["rmse"]), _d(st["armijo_q0"]),
+                    _d(st["armijo_q1"]), _d(st["cgls_gamma"]), _d(st["cgls_delta"]))
         ref = _f64(f_ref).reshape(-1) if f_ref is not None else None
         cp = params._c()
         if armijo_replay is not None:
@@ -257,8 +262,10 @@ class Matrix:
                                        _d(ref) if ref is not None else None, C.byref(cs))
         if rc != 0:
             raise ValueError(f"orc_reconstruct failed ({rc})")
-        st["armijo_k"] = st["armijo_k"][:K * T].reshape(K, T)
-        st["armijo_margin"] = st["armijo_margin"][:K * T].reshape(K, T)
+        for key in ("armijo_k", "armijo_margin", "armijo_q0", "armijo_q1"):
+            st[key] = st[key][:K * T].reshape(K, T)
+        for key in ("cgls_gamma", "cgls_delta"):
+            st[key] = st[key][:K * M].reshape(K, M)
         if ref is None:
             st.pop("rmse")
         return f.reshape(self.ny, self.nx), st

@@ -89,13 +89,13 @@ static int default_grid(int shape, int n_items)
     return std::max(1, std::min(n_items, per_cu * kCUs));
 }
 
-static size_t batch_ws_layout(const eptv_batch_s& b, int K, int T, char* base, std::vector<Workspace>* Ws)
+static size_t batch_ws_layout(const eptv_batch_s& b, int K, int T, int M, char* base, std::vector<Workspace>* Ws)
 {
     size_t off = 0;
     if (Ws) Ws->resize(b.plans.size());
     for (size_t i = 0; i < b.plans.size(); ++i) {
         Workspace W;
-        const size_t need = workspace_layout(b.plans[i]->p, K, T, base ? base + off : nullptr, &W);
+        const size_t need = workspace_layout(b.plans[i]->p, K, T, M, base ? base + off : nullptr, &W);
         if (Ws) (*Ws)[i] = W;
         off += (need + 255) & ~(size_t)255;
     }
@@ -126,6 +126,11 @@ static int bind_batch(eptv_batch_s& b, const eptv_params& q, const std::vector<W
         d.st_steps = W.st_steps;
         d.st_resid = W.st_resid;
         d.st_rmse = W.st_rmse;
+        d.st_q0 = W.st_q0;
+        d.st_q1 = W.st_q1;
+        d.st_gamma = W.st_gamma;
+        d.st_delta = W.st_delta;
+        d.cgls_iters = q.cgls_iters;
         b.h_stage[i] = d;
     }
     EPTV_HIP(hipMemcpyAsync(b.d_slices, b.h_stage, sizeof(SliceDev) * b.bd.n, hipMemcpyHostToDevice, s));
@@ -301,7 +306,7 @@ int eptv_batch_workspace_bytes(eptv_batch b, const eptv_params* q, size_t* bytes
     if (!b || !q || !bytes) return EPTV_ERR_ARG;
     const int rc = check_params(q);
     if (rc != EPTV_OK) return rc;
-    *bytes = batch_ws_layout(*b, q->outer_iters, q->tv_iters, nullptr, nullptr);
+    *bytes = batch_ws_layout(*b, q->outer_iters, q->tv_iters, q->cgls_iters, nullptr, nullptr);
     return EPTV_OK;
 }
 
@@ -343,7 +348,7 @@ int eptv_batch_tune(eptv_batch b, int reps, void* stream, float* proj_ms, float*
     q.sigma_floor = 1e-12;
     q.sigma_fixed = -1.0;
     q.lambda = 1.0;
-    const size_t bytes = batch_ws_layout(*b, 1, 0, nullptr, nullptr);
+    const size_t bytes = batch_ws_layout(*b, 1, 0, 0, nullptr, nullptr);
     std::vector<float*> img(b->bd.n), sino(b->bd.n);
     char* ws = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -371,7 +376,7 @@ int eptv_batch_tune(eptv_batch b, int reps, void* stream, float* proj_ms, float*
     }
     std::lock_guard<std::mutex> lock(b->mu);
     std::vector<Workspace> Ws;
-    batch_ws_layout(*b, 1, 0, ws, &Ws);
+    batch_ws_layout(*b, 1, 0, 0, ws, &Ws);
     rc = bind_batch(*b, q, Ws, (const float* const*)sino.data(), img.data(), nullptr, s);
     if (rc != EPTV_OK) {
         cleanup();
@@ -433,13 +438,14 @@ int eptv_batch_reconstruct(eptv_batch b, const eptv_params* q, const float* cons
     if (!b || !y || !f) return EPTV_ERR_ARG;
     int rc = check_params(q);
     if (rc != EPTV_OK) return rc;
-    if (q->stored_matrix || q->interp_bp || q->stop_rmse > 0) return EPTV_ERR_ARG;  // one-slice variants only
+    if (q->stored_matrix || q->interp_bp || q->stop_rmse > 0 || q->check_finite)
+        return EPTV_ERR_ARG;  // one-slice variants only
     for (int i = 0; i < b->bd.n; ++i)
         if (!y[i] || !f[i] || (f_ref && !f_ref[i])) return EPTV_ERR_ARG;
     if (!ws || ((uintptr_t)ws & 255)) return EPTV_ERR_WORKSPACE;
     const int K = q->outer_iters, T = q->tv_iters;
     std::vector<Workspace> Ws;
-    if (batch_ws_layout(*b, K, T, (char*)ws, &Ws) > ws_bytes) return EPTV_ERR_WORKSPACE;
+    if (batch_ws_layout(*b, K, T, q->cgls_iters, (char*)ws, &Ws) > ws_bytes) return EPTV_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     std::lock_guard<std::mutex> lock(b->mu);
     rc = bind_batch(*b, *q, Ws, y, f, f_ref, s);
@@ -507,6 +513,15 @@ int eptv_batch_reconstruct(eptv_batch b, const eptv_params* q, const float* cons
             if (st.cgls_steps) EPTV_HIP(hipMemcpyAsync(st.cgls_steps, W.st_steps, kk * 4, hipMemcpyDeviceToHost, s));
             if (st.cgls_resid) EPTV_HIP(hipMemcpyAsync(st.cgls_resid, W.st_resid, kk * 8, hipMemcpyDeviceToHost, s));
             if (st.rmse && with_ref) EPTV_HIP(hipMemcpyAsync(st.rmse, W.st_rmse, kk * 8, hipMemcpyDeviceToHost, s));
+            if (st.armijo_q0 && T > 0)
+                EPTV_HIP(hipMemcpyAsync(st.armijo_q0, W.st_q0, kk * T * 8, hipMemcpyDeviceToHost, s));
+            if (st.armijo_q1 && T > 0)
+                EPTV_HIP(hipMemcpyAsync(st.armijo_q1, W.st_q1, kk * T * 8, hipMemcpyDeviceToHost, s));
+            const size_t M = (size_t)q->cgls_iters;
+            if (st.cgls_gamma && M)
+                EPTV_HIP(hipMemcpyAsync(st.cgls_gamma, W.st_gamma, kk * M * 8, hipMemcpyDeviceToHost, s));
+            if (st.cgls_delta && M)
+                EPTV_HIP(hipMemcpyAsync(st.cgls_delta, W.st_delta, kk * M * 8, hipMemcpyDeviceToHost, s));
         }
         EPTV_HIP(hipStreamSynchronize(s));
     }

@@ -63,6 +63,11 @@ struct SliceDev {
     int32_t* st_steps;
     double* st_resid;
     double* st_rmse;
+    double* st_q0;
+    double* st_q1;
+    double* st_gamma;
+    double* st_delta;
+    int cgls_iters;        // M, the stride of st_gamma / st_delta
 };
 
 // Item lists, one per block shape.

@@ -55,13 +55,15 @@ __device__ __forceinline__ void cgls_axpy_block(DevState* st, int m, const doubl
     const double d = block_sum_partials<kAxpyBlock>(part_proj, n_proj, 1, lds);
     const double g0 = m == 0 ? g : st->gamma0;
     const int was = m == 0 ? 1 : st->active[m - 1];
-    const int active = was && (g > 1e-30 * g0) && (d > 0.0);
+    const bool g_ok = g > 1e-30 * g0;
+    const int active = was && g_ok && (d > 0.0);
     const float a = active ? (float)(g / d) : 0.0f;
     if (blk == 0 && threadIdx.x == 0) {
         if (m == 0) {
             st->gamma[0] = g;
             st->gamma0 = g;
         }
+        st->delta[m] = was && g_ok ? d : 0.0;  // a step stopped by gamma_m forms no delta_m
         st->a[m] = a;
         st->active[m] = active;
         if (active) st->cg_steps = m + 1;
@@ -214,12 +216,21 @@ hipError_t launch_rmse_part(const Plan& p, const float* f, const float* ref, dou
 __device__ __forceinline__ void iter_end_block(DevState* st, const double* part_res, int n_res, int with_resid,
                                                const double* part_rmse, int n_rmse, int with_rmse, double npix,
                                                float* st_sigma, int32_t* st_steps, double* st_resid, double* st_rmse,
-                                               uint32_t* hist, float sigma_fixed, double* lds)
+                                               int M, double* st_gamma, double* st_delta, uint32_t* hist,
+                                               float sigma_fixed, double* lds)
 {
     const double res = with_resid ? block_sum_partials<256>(part_res, n_res, 1, lds) : 0.0;
     const double e = with_rmse ? block_sum_partials<256>(part_rmse, n_rmse, 1, lds) : 0.0;
+    const int it = st->iter;
+    // the CGLS scalars of the steps reached (gamma_m is recorded for every
+    // step that the previous ones left active, including one it stopped)
+    for (int m = threadIdx.x; m < M; m += blockDim.x) {
+        const int reached = m == 0 || st->active[m - 1];
+        if (st_gamma) st_gamma[(size_t)it * M + m] = reached ? st->gamma[m] : 0.0;
+        if (st_delta) st_delta[(size_t)it * M + m] = reached ? st->delta[m] : 0.0;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        const int it = st->iter;
         if (st_sigma) st_sigma[it] = st->sigma;
         if (st_steps) st_steps[it] = st->cg_steps;
         if (st_resid) st_resid[it] = res;
@@ -233,20 +244,40 @@ __device__ __forceinline__ void iter_end_block(DevState* st, const double* part_
 __global__ __launch_bounds__(256) void k_iter_end(DevState* st, const double* part_res, int n_res, int with_resid,
                                                   const double* part_rmse, int n_rmse, int with_rmse, double npix,
                                                   float* st_sigma, int32_t* st_steps, double* st_resid,
-                                                  double* st_rmse, uint32_t* hist, float sigma_fixed)
+                                                  double* st_rmse, int M, double* st_gamma, double* st_delta,
+                                                  uint32_t* hist, float sigma_fixed)
 {
     __shared__ double lds[4];
     iter_end_block(st, part_res, n_res, with_resid, part_rmse, n_rmse, with_rmse, npix, st_sigma, st_steps, st_resid,
-                   st_rmse, hist, sigma_fixed, lds);
+                   st_rmse, M, st_gamma, st_delta, hist, sigma_fixed, lds);
 }
 
 hipError_t launch_iter_end(const Plan& p, DevState* st, const double* part_res, int with_resid,
                            const double* part_rmse, int n_rmse, int with_rmse, float* st_sigma, int32_t* st_steps,
-                           double* st_resid, double* st_rmse, uint32_t* hist, float sigma_fixed, hipStream_t s)
+                           double* st_resid, double* st_rmse, int M, double* st_gamma, double* st_delta,
+                           uint32_t* hist, float sigma_fixed, hipStream_t s)
 {
     hipLaunchKernelGGL(k_iter_end, dim3(1), dim3(256), 0, s, st, part_res, sino_blocks(p), with_resid, part_rmse,
-                       n_rmse, with_rmse, (double)p.nx * p.ny, st_sigma, st_steps, st_resid, st_rmse, hist,
-                       sigma_fixed);
+                       n_rmse, with_rmse, (double)p.nx * p.ny, st_sigma, st_steps, st_resid, st_rmse, M, st_gamma,
+                       st_delta, hist, sigma_fixed);
+    return hipGetLastError();
+}
+
+// The optional input check: one block walks the array and records whether any
+// value is NaN or infinite, as the flag's new value (first array) or or-ed
+// into it (later ones), so nothing has to be cleared before.
+__global__ __launch_bounds__(1024) void k_scan_finite(const float* __restrict__ a, size_t n, DevState* st,
+                                                      int accumulate)
+{
+    int bad = 0;
+    for (size_t i = threadIdx.x; i < n; i += 1024) bad |= !__builtin_isfinite(a[i]);
+    bad = __syncthreads_or(bad);
+    if (threadIdx.x == 0) st->nonfinite = (bad || (accumulate && st->nonfinite)) ? 1 : 0;
+}
+
+hipError_t launch_scan_finite(const float* a, size_t n, DevState* st, int accumulate, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scan_finite, dim3(1), dim3(1024), 0, s, a, n, st, accumulate);
     return hipGetLastError();
 }
 
@@ -356,7 +387,7 @@ __global__ __launch_bounds__(256) void kb_iter_end(const SliceDev* __restrict__ 
     const int rm = with_rmse && d.buf[kBufFRef] != nullptr;
     iter_end_block(d.st, d.part[kPartRes], d.axpy_sino, with_resid, d.part[kPartRmse],
                    rmse_tiles ? d.t32x * d.t32y : kRmseBlocks, rm, (double)d.nx * d.ny, d.st_sigma, d.st_steps,
-                   d.st_resid, d.st_rmse, d.hist, sigma_fixed, lds);
+                   d.st_resid, d.st_rmse, d.cgls_iters, d.st_gamma, d.st_delta, d.hist, sigma_fixed, lds);
 }
 
 hipError_t blaunch_iter_end(const BatchDev& b, bool with_resid, bool with_rmse, bool rmse_tiles, float sigma_fixed,

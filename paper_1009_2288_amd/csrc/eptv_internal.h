@@ -83,6 +83,7 @@ constexpr int kArmijoMore = 16;    // candidates per round of the rare longer se
 struct DevState {
     // P1 (CGLS): per-step entries, written by the step's vector kernels
     double gamma[kMaxCgls + 1];  // ||P^T r_m||^2
+    double delta[kMaxCgls];      // ||P s_m||^2 of each step that formed it (0 after a breakdown)
     double gamma0;
     float a[kMaxCgls], b[kMaxCgls];
     int active[kMaxCgls];        // CGLS still running after step m
@@ -100,6 +101,7 @@ struct DevState {
     float t;
     // bookkeeping
     int iter;
+    int nonfinite;               // the input scan found NaN or inf
 };
 
 // The float32 system matrix stored on the device (optional, see spmv.hip).
@@ -168,10 +170,14 @@ struct Workspace {
     int32_t* st_steps;   // [K]
     double* st_resid;    // [K]
     double* st_rmse;     // [K]
+    double* st_q0;       // [K*T] Armijo energy at each descent step's start
+    double* st_q1;       // [K*T] and at the accepted point
+    double* st_gamma;    // [K*M] CGLS gamma_m
+    double* st_delta;    // [K*M] CGLS delta_m
     size_t bytes;
 };
 
-size_t workspace_layout(const Plan& p, int K, int T, char* base, Workspace* w);
+size_t workspace_layout(const Plan& p, int K, int T, int M, char* base, Workspace* w);
 
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `s` and return hipGetLastError().
@@ -239,10 +245,11 @@ hipError_t launch_tv_armijo(const Plan& p, const float* f, const float* g_prev, 
                             hipStream_t s, const float* wx_in = nullptr, const float* wy_in = nullptr,
                             DevState* sel_st = nullptr, const uint32_t* sel_hist = nullptr, float sel_floor = 0.0f);
 
+// st_k / st_q0 / st_q1: the per-step records ([K*T], entry iter*T + step)
 hipError_t launch_armijo_decide(const Plan& p, DevState* st, const double* part_grad, const double* part_arm,
-                                int max_bt, double c_arm, float t0, float shrink, int32_t* st_k, int step, int T,
-                                const float* f, const float* g, const float* v, const float* wx, const float* wy,
-                                float lambda, float eps2, hipStream_t s,
+                                int max_bt, double c_arm, float t0, float shrink, int32_t* st_k, double* st_q0,
+                                double* st_q1, int step, int T, const float* f, const float* g, const float* v,
+                                const float* wx, const float* wy, float lambda, float eps2, hipStream_t s,
                                 int replay = 0);
 // With ref, also one partial of the squared error to ref per 32 x 32 tile
 // (update_tiles of them) in part_rmse.
@@ -256,8 +263,13 @@ hipError_t launch_copy_clamp(const Plan& p, const float* src, float* dst, float*
 // bookkeeping
 hipError_t launch_rmse_part(const Plan& p, const float* f, const float* ref, double* part,
                             hipStream_t s);
+// M: CGLS steps per P1, whose gamma_m / delta_m go to st_gamma / st_delta ([K*M])
 hipError_t launch_iter_end(const Plan& p, DevState* st, const double* part_res, int with_resid,
                            const double* part_rmse, int n_rmse, int with_rmse, float* st_sigma, int32_t* st_steps,
-                           double* st_resid, double* st_rmse, uint32_t* hist, float sigma_fixed, hipStream_t s);
+                           double* st_resid, double* st_rmse, int M, double* st_gamma, double* st_delta,
+                           uint32_t* hist, float sigma_fixed, hipStream_t s);
+// st->nonfinite = whether a[0..n) holds NaN or inf (accumulate: or-ed into the
+// flag of an earlier scan); one block, no other state touched
+hipError_t launch_scan_finite(const float* a, size_t n, DevState* st, int accumulate, hipStream_t s);
 
 }  // namespace eptv

@@ -99,7 +99,7 @@ int validate_geometry(const eptv_geometry* g)
 // ------------------------------------------------------------------ workspace
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t workspace_layout(const Plan& p, int K, int T, char* base, Workspace* w)
+size_t workspace_layout(const Plan& p, int K, int T, int M, char* base, Workspace* w)
 {
     const size_t ni = (size_t)p.nx * p.ny, ns = (size_t)p.V * p.B;
     const size_t kcap = (size_t)std::max(K, 1), ktcap = std::max<size_t>((size_t)std::max(K, 1) * std::max(T, 0), 4096);
@@ -140,13 +140,27 @@ size_t workspace_layout(const Plan& p, int K, int T, char* base, Workspace* w)
     W.st_steps = (int32_t*)take(kcap * 4);
     W.st_resid = (double*)take(kcap * 8);
     W.st_rmse = (double*)take(kcap * 8);
+    W.st_q0 = (double*)take(ktcap * 8);
+    W.st_q1 = (double*)take(ktcap * 8);
+    W.st_gamma = (double*)take(kcap * (size_t)std::max(M, 0) * 8);
+    W.st_delta = (double*)take(kcap * (size_t)std::max(M, 0) * 8);
     W.bytes = off;
     return off;
+}
+
+// eps of Eq. A3 as the P2 kernels use it: its float square must be a positive
+// normal number, so every half-edge magnitude is at least eps > 0 and the
+// fluxes of Eq. A2 (which divide by the magnitude) stay finite on flat regions.
+bool tv_eps_ok(double eps)
+{
+    const float e2 = (float)(eps * eps);
+    return eps > 0 && std::isnormal(e2);
 }
 
 int check_params(const eptv_params* q)
 {
     if (!q) return EPTV_ERR_ARG;
+    if (q->tv_iters > 0 && !tv_eps_ok(q->tv_eps)) return EPTV_ERR_ARG;
     if (q->outer_iters < 0 || q->cgls_iters < 0 || q->cgls_iters > kMaxCgls || q->tv_iters < 0) return EPTV_ERR_ARG;
     if (q->tv_iters > 0 && !(q->lambda > 0)) return EPTV_ERR_ARG;
     if (q->cgls_iters == 0 && !(q->mu >= 0 && q->lambda > 0)) return EPTV_ERR_ARG;
@@ -156,6 +170,8 @@ int check_params(const eptv_params* q)
                             q->armijo_max_backtracks > 4096 || !(q->armijo_c >= 0)))
         return EPTV_ERR_ARG;
     if ((long long)q->outer_iters * q->tv_iters > (1LL << 28)) return EPTV_ERR_ARG;
+    if ((long long)q->outer_iters * q->cgls_iters > (1LL << 28)) return EPTV_ERR_ARG;
+    if (q->check_finite != 0 && q->check_finite != 1) return EPTV_ERR_ARG;
     if (q->stored_matrix < 0 || q->stored_matrix > 2 || (q->interp_bp != 0 && q->interp_bp != 1))
         return EPTV_ERR_ARG;
     if (q->check_every < 0 || !(q->stop_rmse >= 0) || !std::isfinite(q->stop_rmse)) return EPTV_ERR_ARG;
@@ -232,8 +248,8 @@ static hipError_t enqueue_p2(const Plan& p, Workspace& W, const eptv_params& q, 
             return e;
         if (t > 0) fcur = fnext;
         if ((e = launch_armijo_decide(p, W.st, W.part_grad, W.part_arm, q.armijo_max_backtracks, q.armijo_c, t0,
-                                      shrink, st_k, t, n_steps, fcur, g, v, W.wx, W.wy, (float)q.lambda, eps2, s,
-                                      replay)) != hipSuccess)
+                                      shrink, st_k, W.st_q0, W.st_q1, t, n_steps, fcur, g, v, W.wx, W.wy,
+                                      (float)q.lambda, eps2, s, replay)) != hipSuccess)
             return e;
     }
     if (n_steps == 0) return launch_copy_clamp(p, start, fout, foutT, clamp, s);
@@ -302,8 +318,8 @@ static hipError_t enqueue_iteration(const Ctx& c, hipStream_t s)
         if ((e = launch_rmse_part(p, c.f, c.f_ref, W.part_rmse, s)) != hipSuccess) return e;
     }
     return launch_iter_end(p, W.st, W.part_res, M > 0, W.part_rmse, T > 0 ? update_tiles(p) : kRmseBlocks,
-                           c.f_ref != nullptr, W.st_sigma, W.st_steps, W.st_resid, W.st_rmse, W.hist, sigma_init(q),
-                           s);
+                           c.f_ref != nullptr, W.st_sigma, W.st_steps, W.st_resid, W.st_rmse, M, W.st_gamma,
+                           W.st_delta, W.hist, sigma_init(q), s);
 }
 
 // Kernels are launched on the stream one by one unless EPTV_GRAPH is set to a
@@ -560,14 +576,14 @@ int eptv_workspace_bytes(eptv_plan h, const eptv_params* q, size_t* bytes)
         K = q->outer_iters;
         T = q->tv_iters;
     }
-    *bytes = workspace_layout(h->p, K, T, nullptr, nullptr);
+    *bytes = workspace_layout(h->p, K, T, q ? q->cgls_iters : 0, nullptr, nullptr);
     return EPTV_OK;
 }
 
-static int bind_ws(const Plan& p, int K, int T, void* ws, size_t ws_bytes, Workspace* W)
+static int bind_ws(const Plan& p, int K, int T, int M, void* ws, size_t ws_bytes, Workspace* W)
 {
     if (!ws || ((uintptr_t)ws & 255)) return EPTV_ERR_WORKSPACE;
-    const size_t need = workspace_layout(p, K, T, (char*)ws, W);
+    const size_t need = workspace_layout(p, K, T, M, (char*)ws, W);
     return ws_bytes >= need ? EPTV_OK : EPTV_ERR_WORKSPACE;
 }
 
@@ -576,7 +592,7 @@ int eptv_project(eptv_plan h, const float* x, float* q, float alpha, float beta,
 {
     if (!h || !x || !q) return EPTV_ERR_ARG;
     Workspace W;
-    int rc = bind_ws(h->p, 1, 0, ws, ws_bytes, &W);
+    int rc = bind_ws(h->p, 1, 0, 0, ws, ws_bytes, &W);
     if (rc != EPTV_OK) return rc;
     hipStream_t s = (hipStream_t)stream;
     EPTV_HIP(launch_transpose(x, W.fT, h->p.nx, h->p.ny, s));
@@ -596,7 +612,7 @@ int eptv_project_stored(eptv_plan h, const float* x, float* q, float alpha, floa
 {
     if (!h || !x || !q || !h->p.mat.d_rowptr) return EPTV_ERR_ARG;
     Workspace W;
-    int rc = bind_ws(h->p, 1, 0, ws, ws_bytes, &W);
+    int rc = bind_ws(h->p, 1, 0, 0, ws, ws_bytes, &W);
     if (rc != EPTV_OK) return rc;
     hipStream_t s = (hipStream_t)stream;
     EPTV_HIP(launch_transpose(x, W.fT, h->p.nx, h->p.ny, s));
@@ -617,7 +633,7 @@ int eptv_backproject(eptv_plan h, const float* r, float* z, float alpha, float b
 {
     if (!h || !r || !z) return EPTV_ERR_ARG;
     Workspace W;
-    int rc = bind_ws(h->p, 1, 0, ws, ws_bytes, &W);
+    int rc = bind_ws(h->p, 1, 0, 0, ws, ws_bytes, &W);
     if (rc != EPTV_OK) return rc;
     EPTV_HIP(launch_backproject(h->p, r, alpha, beta, z, z, nullptr, nullptr, (hipStream_t)stream));
     return EPTV_OK;
@@ -634,9 +650,9 @@ int eptv_tv_gradient(eptv_plan h, const float* f, const float* v, float lambda, 
                      float* wx, float* wy, void* ws, size_t ws_bytes, void* stream)
 {
     if (!h || !f || !v || !g) return EPTV_ERR_ARG;
-    if (!(sigma > 0) || !(tv_eps >= 0) || !std::isfinite(lambda)) return EPTV_ERR_ARG;
+    if (!(sigma > 0) || !tv_eps_ok(tv_eps) || !std::isfinite(lambda)) return EPTV_ERR_ARG;
     Workspace W;
-    int rc = bind_ws(h->p, 1, 0, ws, ws_bytes, &W);
+    int rc = bind_ws(h->p, 1, 0, 0, ws, ws_bytes, &W);
     if (rc != EPTV_OK) return rc;
     EPTV_HIP(launch_tv_grad(h->p, f, nullptr, nullptr, nullptr, v, lambda, nullptr, sigma, tv_eps * tv_eps, g, wx, wy,
                             nullptr, (hipStream_t)stream));
@@ -647,9 +663,9 @@ int eptv_tv_gradient_vjp(eptv_plan h, const float* f, const float* u, float lamb
                          float* out, void* ws, size_t ws_bytes, void* stream)
 {
     if (!h || !f || !u || !out) return EPTV_ERR_ARG;
-    if (!(sigma > 0) || !(tv_eps > 0) || !std::isfinite(tv_eps) || !std::isfinite(lambda)) return EPTV_ERR_ARG;
+    if (!(sigma > 0) || !tv_eps_ok(tv_eps) || !std::isfinite(lambda)) return EPTV_ERR_ARG;
     Workspace W;
-    int rc = bind_ws(h->p, 1, 0, ws, ws_bytes, &W);
+    int rc = bind_ws(h->p, 1, 0, 0, ws, ws_bytes, &W);
     if (rc != EPTV_OK) return rc;
     EPTV_HIP(launch_tv_vjp(h->p, f, u, lambda, sigma, tv_eps * tv_eps, W.edge3, out, (hipStream_t)stream));
     return EPTV_OK;
@@ -661,7 +677,7 @@ int eptv_select_sigma(eptv_plan h, const float* f, double q, float tv_eps, float
     if (!h || !f || !sigma_out) return EPTV_ERR_ARG;
     if (!(q > 0 && q <= 1) || !(tv_eps >= 0) || !(sigma_floor > 0)) return EPTV_ERR_ARG;
     Workspace W;
-    int rc = bind_ws(h->p, 1, 0, ws, ws_bytes, &W);
+    int rc = bind_ws(h->p, 1, 0, 0, ws, ws_bytes, &W);
     if (rc != EPTV_OK) return rc;
     hipStream_t s = (hipStream_t)stream;
     EPTV_HIP(launch_state_init(W.st, W.hist, select_rank(h->p, q), -1.0f, 1, s));
@@ -675,11 +691,11 @@ int eptv_tv_step(eptv_plan h, const eptv_params* q, float* f, const float* v, fl
 {
     if (!h || !f || !v || n_steps < 0 || n_steps > 4096) return EPTV_ERR_ARG;
     if (!q || !(q->lambda > 0) || !(q->armijo_shrink > 0 && q->armijo_shrink < 1) || q->armijo_max_backtracks < 0 ||
-        q->armijo_max_backtracks > 4096 || !(q->tv_eps >= 0) || !(q->sigma_floor > 0))
+        q->armijo_max_backtracks > 4096 || !tv_eps_ok(q->tv_eps) || !(q->sigma_floor > 0))
         return EPTV_ERR_ARG;
     if (sigma < 0 && !(q->edge_quantile > 0 && q->edge_quantile <= 1)) return EPTV_ERR_ARG;
     Workspace W;
-    int rc = bind_ws(h->p, 1, 0, ws, ws_bytes, &W);
+    int rc = bind_ws(h->p, 1, 0, 0, ws, ws_bytes, &W);
     if (rc != EPTV_OK) return rc;
     hipStream_t s = (hipStream_t)stream;
     const Plan& p = h->p;
@@ -690,6 +706,10 @@ int eptv_tv_step(eptv_plan h, const eptv_params* q, float* f, const float* v, fl
         if (stats->sigma) EPTV_HIP(hipMemcpyAsync(stats->sigma, &W.st->sigma, 4, hipMemcpyDeviceToHost, s));
         if (stats->armijo_k && n_steps > 0)
             EPTV_HIP(hipMemcpyAsync(stats->armijo_k, W.st_k, (size_t)n_steps * 4, hipMemcpyDeviceToHost, s));
+        if (stats->armijo_q0 && n_steps > 0)
+            EPTV_HIP(hipMemcpyAsync(stats->armijo_q0, W.st_q0, (size_t)n_steps * 8, hipMemcpyDeviceToHost, s));
+        if (stats->armijo_q1 && n_steps > 0)
+            EPTV_HIP(hipMemcpyAsync(stats->armijo_q1, W.st_q1, (size_t)n_steps * 8, hipMemcpyDeviceToHost, s));
         EPTV_HIP(hipStreamSynchronize(s));
     }
     return EPTV_OK;
@@ -722,7 +742,7 @@ static int reconstruct_impl(eptv_plan h, const eptv_params* q, const float* y, f
     Plan& p = h->p;
     if (q->stored_matrix && !p.mat.d_rowptr) return EPTV_ERR_ARG;
     Workspace W;
-    rc = bind_ws(p, q->outer_iters, q->tv_iters, ws, ws_bytes, &W);
+    rc = bind_ws(p, q->outer_iters, q->tv_iters, q->cgls_iters, ws, ws_bytes, &W);
     if (rc != EPTV_OK) return rc;
     hipStream_t s = (hipStream_t)stream;
     const int K = q->outer_iters, T = q->tv_iters;
@@ -734,6 +754,20 @@ static int reconstruct_impl(eptv_plan h, const eptv_params* q, const float* y, f
     }
     const bool stop = f_ref && q->stop_rmse > 0;
     const int every = std::max(1, q->check_every);
+
+    if (q->check_finite) {
+        // the optional input check, before anything else is enqueued
+        EPTV_HIP(launch_scan_finite(y, (size_t)p.V * p.B, W.st, 0, s));
+        if (!q->zero_init) EPTV_HIP(launch_scan_finite(f, (size_t)p.nx * p.ny, W.st, 1, s));
+        std::lock_guard<std::mutex> hl(h->host_mu);
+        void* hb = nullptr;
+        EPTV_HIP(host_staging(h, sizeof(int), &hb));
+        EPTV_HIP(hipMemcpyAsync(hb, &W.st->nonfinite, sizeof(int), hipMemcpyDeviceToHost, s));
+        EPTV_HIP(hipStreamSynchronize(s));
+        int bad = 0;
+        std::memcpy(&bad, hb, sizeof bad);
+        if (bad) return EPTV_ERR_NONFINITE;
+    }
 
     EPTV_HIP(launch_recon_start(f, W.fT, p.nx, p.ny, q->zero_init != 0, W.st, W.hist,
                                 select_rank(p, q->edge_quantile), sigma_init(*q), s));
@@ -832,7 +866,7 @@ static int reconstruct_impl(eptv_plan h, const eptv_params* q, const float* y, f
             void* dst;
             const void* src;
             size_t n, at;
-        } parts[5];
+        } parts[9];
         int np = 0;
         size_t at = 0;
         auto add = [&](void* dst, const void* src, size_t n) {
@@ -845,6 +879,11 @@ static int reconstruct_impl(eptv_plan h, const eptv_params* q, const float* y, f
         add(stats->cgls_steps, W.st_steps, kk * 4);
         add(stats->cgls_resid, W.st_resid, kk * 8);
         add(f_ref ? stats->rmse : nullptr, W.st_rmse, kk * 8);
+        add(T > 0 ? stats->armijo_q0 : nullptr, W.st_q0, kk * T * 8);
+        add(T > 0 ? stats->armijo_q1 : nullptr, W.st_q1, kk * T * 8);
+        const int M = q->cgls_iters;
+        add(M > 0 ? stats->cgls_gamma : nullptr, W.st_gamma, kk * M * 8);
+        add(M > 0 ? stats->cgls_delta : nullptr, W.st_delta, kk * M * 8);
         std::lock_guard<std::mutex> hl(h->host_mu);
         void* hb = nullptr;
         EPTV_HIP(host_staging(h, std::max<size_t>(at, 16), &hb));

@@ -708,14 +708,16 @@ __device__ __forceinline__ void decide_reduce(double* v, double (*red)[kDecThrea
 struct DecShared {
     double red[kDecVals][kDecThreads];
     double tot[kDecVals];
+    double q_acc;  // the energy at the accepted point
     int verdict;
 };
 
 __device__ __forceinline__ void armijo_decide_block(DevState* st, const double* part_grad, const double* part_arm,
                                                     int nb, int max_bt, double c_arm, float t0, float shrink,
-                                                    int32_t* st_k, int step, int T, const float* f, const float* g,
-                                                    const float* v, const float* wx, const float* wy, int nx, int ny,
-                                                    float lambda, float eps2, DecShared& S, int replay = 0)
+                                                    int32_t* st_k, double* st_q0, double* st_q1, int step, int T,
+                                                    const float* f, const float* g, const float* v, const float* wx,
+                                                    const float* wy, int nx, int ny, float lambda, float eps2,
+                                                    DecShared& S, int replay = 0)
 {
     double (*red)[kDecThreads] = S.red;
     double* tot = S.tot;
@@ -755,9 +757,25 @@ __device__ __forceinline__ void armijo_decide_block(DevState* st, const double* 
                 }
         }
         verdict = kk;
+        // the energy at the accepted point (the start's when none; later
+        // candidates are filled in below)
+        S.q_acc = kk < 0 ? q0 : (kk < kArmijoFirst ? tot[kk] : 0.0);
     }
     __syncthreads();
     int kk = verdict;
+    if (replay && kk >= kArmijoFirst) {
+        // a given index beyond the fused trials: evaluate that candidate (the
+        // sums in the order the search below would form them)
+        double e[kArmijoMore];
+#pragma unroll
+        for (int c = 0; c < kArmijoMore; ++c) e[c] = 0.0;
+        for (int px = threadIdx.x; px < nx * ny; px += kDecThreads)
+            candidate_energies<kArmijoMore>(f, g, v, wx, wy, nx, ny, px % nx, px / nx, lambda, eps2, t0, shrink, kk,
+                                            e);
+        decide_reduce<kArmijoMore>(e, red, tot);
+        if (threadIdx.x == 0) S.q_acc = tot[0];
+        __syncthreads();
+    }
     // rare: continue the backtracking over the whole image in this block
     for (int k0 = kArmijoFirst; !replay && kk < 0 && k0 <= max_bt; k0 += kArmijoMore) {
         double e[kArmijoMore];
@@ -772,6 +790,7 @@ __device__ __forceinline__ void armijo_decide_block(DevState* st, const double* 
             for (int c = 0; c < kArmijoMore && k0 + c <= max_bt; ++c)
                 if (tot[c] <= q0 - c_arm * (double)cand_t(t0, shrink, k0 + c) * g2) {
                     found = k0 + c;
+                    S.q_acc = tot[c];
                     break;
                 }
             verdict = found;
@@ -784,30 +803,35 @@ __device__ __forceinline__ void armijo_decide_block(DevState* st, const double* 
         st->gg = g2;
         st->k = kk;
         st->t = kk >= 0 ? cand_t(t0, shrink, kk) : 0.0f;
-        if (st_k) st_k[(size_t)st->iter * T + step] = kk;
+        const size_t rec = (size_t)st->iter * T + step;
+        if (st_k) st_k[rec] = kk;
+        if (st_q0) st_q0[rec] = q0;
+        if (st_q1) st_q1[rec] = S.q_acc;
     }
 }
 
 __global__ __launch_bounds__(kDecThreads) void k_armijo_decide(DevState* st, const double* part_grad,
                                                                const double* part_arm, int nb, int max_bt,
                                                                double c_arm, float t0, float shrink, int32_t* st_k,
-                                                               int step, int T, const float* f, const float* g,
-                                                               const float* v, const float* wx, const float* wy,
-                                                               int nx, int ny, float lambda, float eps2, int replay)
+                                                               double* st_q0, double* st_q1, int step, int T,
+                                                               const float* f, const float* g, const float* v,
+                                                               const float* wx, const float* wy, int nx, int ny,
+                                                               float lambda, float eps2, int replay)
 {
     __shared__ DecShared S;
-    armijo_decide_block(st, part_grad, part_arm, nb, max_bt, c_arm, t0, shrink, st_k, step, T, f, g, v, wx, wy, nx,
-                        ny, lambda, eps2, S, replay);
+    armijo_decide_block(st, part_grad, part_arm, nb, max_bt, c_arm, t0, shrink, st_k, st_q0, st_q1, step, T, f, g, v,
+                        wx, wy, nx, ny, lambda, eps2, S, replay);
 }
 
 hipError_t launch_armijo_decide(const Plan& p, DevState* st, const double* part_grad, const double* part_arm,
-                                int max_bt, double c_arm, float t0, float shrink, int32_t* st_k, int step, int T,
-                                const float* f, const float* g, const float* v, const float* wx, const float* wy,
-                                float lambda, float eps2, hipStream_t s, int replay)
+                                int max_bt, double c_arm, float t0, float shrink, int32_t* st_k, double* st_q0,
+                                double* st_q1, int step, int T, const float* f, const float* g, const float* v,
+                                const float* wx, const float* wy, float lambda, float eps2, hipStream_t s,
+                                int replay)
 {
     hipLaunchKernelGGL(k_armijo_decide, dim3(1), dim3(kDecThreads), 0, s, st, part_grad, part_arm, armijo_blocks(p),
-                       max_bt, c_arm, t0, shrink, st_k, step, T, f, g, v, wx, wy, p.nx, p.ny, lambda, eps2,
-                       replay && st_k ? 1 : 0);
+                       max_bt, c_arm, t0, shrink, st_k, st_q0, st_q1, step, T, f, g, v, wx, wy, p.nx, p.ny, lambda,
+                       eps2, replay && st_k ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -1129,8 +1153,8 @@ __global__ __launch_bounds__(kDecThreads) void kb_armijo_decide(const SliceDev* 
     __shared__ DecShared S;
     const SliceDev& d = sl[blockIdx.x];
     armijo_decide_block(d.st, d.part[kPartGrad], d.part[kPartArm], d.t16x * d.t16y, max_bt, c_arm, t0, shrink,
-                        d.st_k, step, T, d.buf[fs], d.buf[gs], d.buf[vs], d.buf[kBufWX], d.buf[kBufWY], d.nx, d.ny,
-                        lambda, eps2, S);
+                        d.st_k, d.st_q0, d.st_q1, step, T, d.buf[fs], d.buf[gs], d.buf[vs], d.buf[kBufWX],
+                        d.buf[kBufWY], d.nx, d.ny, lambda, eps2, S);
 }
 
 hipError_t blaunch_armijo_decide(const BatchDev& b, int max_bt, double c_arm, float t0, float shrink, int step, int T,

@@ -56,13 +56,44 @@ class _Params(C.Structure):
                 ("armijo_c", C.c_double), ("armijo_shrink", C.c_double), ("armijo_t0", C.c_double),
                 ("armijo_max_backtracks", C.c_int), ("p2_start", C.c_int), ("positivity", C.c_int),
                 ("stored_matrix", C.c_int), ("interp_bp", C.c_int), ("check_every", C.c_int),
-                ("stop_rmse", C.c_double)]
+                ("stop_rmse", C.c_double), ("check_finite", C.c_int)]
 
 
 class _Stats(C.Structure):
     _fields_ = [("sigma", C.POINTER(C.c_float)), ("armijo_k", C.POINTER(C.c_int32)),
                 ("cgls_steps", C.POINTER(C.c_int32)), ("cgls_resid", C.POINTER(C.c_double)),
-                ("rmse", C.POINTER(C.c_double)), ("iters_run", C.POINTER(C.c_int32))]
+                ("rmse", C.POINTER(C.c_double)), ("iters_run", C.POINTER(C.c_int32)),
+                ("armijo_q0", C.POINTER(C.c_double)), ("armijo_q1", C.POINTER(C.c_double)),
+                ("cgls_gamma", C.POINTER(C.c_double)), ("cgls_delta", C.POINTER(C.c_double))]
+
+
+def _records(K: int, T: int, M: int) -> dict:
+    """Host arrays for every per-iteration record of eptv_stats."""
+    import numpy as np
+    return {"sigma": np.zeros(max(K, 1), np.float32), "armijo_k": np.zeros(max(K * T, 1), np.int32),
+            "cgls_steps": np.zeros(max(K, 1), np.int32), "cgls_resid": np.zeros(max(K, 1)),
+            "rmse": np.zeros(max(K, 1)), "armijo_q0": np.zeros(max(K * T, 1)), "armijo_q1": np.zeros(max(K * T, 1)),
+            "cgls_gamma": np.zeros(max(K * M, 1)), "cgls_delta": np.zeros(max(K * M, 1))}
+
+
+def _stats_of(rec: dict, done=None) -> "_Stats":
+    dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
+    return _Stats(rec["sigma"].ctypes.data_as(C.POINTER(C.c_float)),
+                  rec["armijo_k"].ctypes.data_as(C.POINTER(C.c_int32)),
+                  rec["cgls_steps"].ctypes.data_as(C.POINTER(C.c_int32)), dp(rec["cgls_resid"]), dp(rec["rmse"]),
+                  done.ctypes.data_as(C.POINTER(C.c_int32)) if done is not None else None, dp(rec["armijo_q0"]),
+                  dp(rec["armijo_q1"]), dp(rec["cgls_gamma"]), dp(rec["cgls_delta"]))
+
+
+def _shape_records(rec: dict, n: int, T: int, M: int) -> dict:
+    """The first n iterations' records, per-step ones as [n][T] / [n][M]."""
+    out = {k: v[:n].copy() for k, v in rec.items() if k not in ("armijo_k", "armijo_q0", "armijo_q1",
+                                                                  "cgls_gamma", "cgls_delta")}
+    for k in ("armijo_k", "armijo_q0", "armijo_q1"):
+        out[k] = rec[k][:n * T].reshape(n, T).copy()
+    for k in ("cgls_gamma", "cgls_delta"):
+        out[k] = rec[k][:n * M].reshape(n, M).copy()
+    return out
 
 
 @dataclass
@@ -89,6 +120,7 @@ class Params:
     interp_bp: int = 0
     check_every: int = 1
     stop_rmse: float = 0.0
+    check_finite: int = 0
 
     def _c(self) -> _Params:
         d = asdict(self)
@@ -397,11 +429,15 @@ class Plan:
         ws = self.workspace()
         ks = np.zeros(max(n_steps, 1), np.int32)
         sg = np.zeros(1, np.float32)
+        q0 = np.zeros(max(n_steps, 1))
+        q1 = np.zeros(max(n_steps, 1))
+        dp = C.POINTER(C.c_double)
         st = _Stats(sg.ctypes.data_as(C.POINTER(C.c_float)), ks.ctypes.data_as(C.POINTER(C.c_int32)), None, None,
-                    None)
+                    None, None, q0.ctypes.data_as(dp), q1.ctypes.data_as(dp), None, None)
         cp = params._c()
         _check(_lib().eptv_tv_step(self._h, C.byref(cp), f.data_ptr(), v.data_ptr(), sigma, n_steps, ws.data_ptr(),
                                    ws.numel(), C.byref(st) if stats else None, _stream(stream)), "eptv_tv_step")
+        self.last_tv_step_energies = (q0[:n_steps].copy(), q1[:n_steps].copy()) if stats else None
         return (ks[:n_steps].copy(), float(sg[0])) if stats else None
 
     def reconstruct(self, y: torch.Tensor, params: Params, f: Optional[torch.Tensor] = None,
@@ -421,20 +457,13 @@ class Plan:
         if f_ref is not None:
             f_ref = self._img(f_ref, "f_ref")
         ws = self.workspace(params)
-        K, T = params.outer_iters, params.tv_iters
+        K, T, M = params.outer_iters, params.tv_iters, params.cgls_iters
         rec = None
         stp = None
         done = np.zeros(1, np.int32)
         if stats:
-            rec = {"sigma": np.zeros(max(K, 1), np.float32), "armijo_k": np.zeros(max(K * T, 1), np.int32),
-                   "cgls_steps": np.zeros(max(K, 1), np.int32), "cgls_resid": np.zeros(max(K, 1)),
-                   "rmse": np.zeros(max(K, 1))}
-            st = _Stats(rec["sigma"].ctypes.data_as(C.POINTER(C.c_float)),
-                        rec["armijo_k"].ctypes.data_as(C.POINTER(C.c_int32)),
-                        rec["cgls_steps"].ctypes.data_as(C.POINTER(C.c_int32)),
-                        rec["cgls_resid"].ctypes.data_as(C.POINTER(C.c_double)),
-                        rec["rmse"].ctypes.data_as(C.POINTER(C.c_double)),
-                        done.ctypes.data_as(C.POINTER(C.c_int32)))
+            rec = _records(K, T, M)
+            st = _stats_of(rec, done)
             stp = C.byref(st)
         cp = params._c()
         if armijo_replay is not None:
@@ -460,8 +489,7 @@ class Plan:
                                            ws.numel(), stp, _stream(stream)), "eptv_reconstruct")
         if rec is not None:
             n = int(done[0])  # iterations run (an early stop leaves fewer than K records)
-            rec = {k: v[:n].copy() for k, v in rec.items() if k != "armijo_k"} | {
-                "armijo_k": rec["armijo_k"][:n * T].reshape(n, T).copy(), "iters_run": n}
+            rec = _shape_records(rec, n, T, M) | {"iters_run": n}
             if f_ref is None:
                 rec.pop("rmse")
         return f, rec
@@ -541,28 +569,21 @@ class Batch:
         if len(ys) != n or len(fs) != n or (f_refs is not None and len(f_refs) != n):
             raise ValueError(f"expected {n} slices")
         ws = self.workspace(params)
-        K, T = params.outer_iters, params.tv_iters
+        K, T, M = params.outer_iters, params.tv_iters, params.cgls_iters
         yp = (C.c_void_p * n)(*[y.data_ptr() for y in ys])
         fp = (C.c_void_p * n)(*[f.data_ptr() for f in fs])
         rp = (C.c_void_p * n)(*[r.data_ptr() for r in f_refs]) if f_refs is not None else None
         recs, sts = None, None
         if stats:
-            recs = [{"sigma": np.zeros(max(K, 1), np.float32), "armijo_k": np.zeros(max(K * T, 1), np.int32),
-                     "cgls_steps": np.zeros(max(K, 1), np.int32), "cgls_resid": np.zeros(max(K, 1)),
-                     "rmse": np.zeros(max(K, 1))} for _ in range(n)]
-            sts = (_Stats * n)(*[_Stats(r["sigma"].ctypes.data_as(C.POINTER(C.c_float)),
-                                        r["armijo_k"].ctypes.data_as(C.POINTER(C.c_int32)),
-                                        r["cgls_steps"].ctypes.data_as(C.POINTER(C.c_int32)),
-                                        r["cgls_resid"].ctypes.data_as(C.POINTER(C.c_double)),
-                                        r["rmse"].ctypes.data_as(C.POINTER(C.c_double))) for r in recs])
+            recs = [_records(K, T, M) for _ in range(n)]
+            sts = (_Stats * n)(*[_stats_of(r) for r in recs])
         cp = params._c()
         _check(_lib().eptv_batch_reconstruct(self._h, C.byref(cp), yp, fp, rp, ws.data_ptr(), ws.numel(), sts,
                                              _stream(stream)), "eptv_batch_reconstruct")
         if recs is not None:
             out = []
             for r in recs:
-                d = {k: v[:K].copy() for k, v in r.items() if k != "armijo_k"}
-                d["armijo_k"] = r["armijo_k"][:K * T].reshape(K, T).copy()
+                d = _shape_records(r, K, T, M)
                 if f_refs is None:
                     d.pop("rmse")
                 out.append(d)

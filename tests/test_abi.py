@@ -120,3 +120,34 @@ def test_network_entry_points_reject_bad_input_without_gpu(lib):
     assert lib.eptv_maps_to_eptv(1, 4, 4, fake, -1.0, None, fake, fake, fake, None) == 1
     assert lib.eptv_maps_to_eptv(1, 4, 4, fake, 1.0, None, fake, None, fake, None) == 1
     assert lib.eptv_reconstruct_weighted(None, None, None, None, None, None, None, 0, None, 0, None, None) == 1
+
+
+def test_p2_calls_reject_an_eps_whose_square_is_not_normal(lib):
+    """The P2 calls divide by the half-edge magnitudes, which eps bounds below:
+    eps <= 0, NaN, or an eps whose float square is zero or subnormal is
+    rejected before any device call (a fake plan handle is never touched)."""
+    from paper_1009_2288_amd import eptv
+    fake = C.c_void_p(16)
+    n = C.c_size_t()
+    for bad in (0.0, -1e-4, 1e-30, 1e-20, float("nan"), float("inf")):
+        prm = eptv.Params(tv_eps=bad)._c()
+        assert lib.eptv_workspace_bytes(fake, C.byref(prm), C.byref(n)) == 1, bad
+        assert lib.eptv_tv_step(fake, C.byref(prm), fake, fake, -1.0, 1, fake, 1 << 20, None, None) == 1, bad
+        assert lib.eptv_tv_gradient(fake, fake, fake, 1000.0, 0.01, bad, fake, None, None, fake, 1 << 20,
+                                    None) == 1, bad
+        assert lib.eptv_tv_gradient_vjp(fake, fake, fake, 1000.0, 0.01, bad, fake, fake, 1 << 20, None) == 1, bad
+
+
+def test_nonfinite_status_and_params_layout(lib):
+    from paper_1009_2288_amd import eptv
+    assert lib.eptv_status_string(eptv.EPTV_ERR_NONFINITE) == b"non-finite input"
+    # the check flag must be 0 or 1; checked before the plan is touched
+    fake = C.c_void_p(16)
+    n = C.c_size_t()
+    prm = eptv.Params(check_finite=2)._c()
+    assert lib.eptv_workspace_bytes(fake, C.byref(prm), C.byref(n)) == 1
+    # the binding's structs end with the header's last fields
+    src = open(HEADER).read()
+    assert src.index("int check_finite;") > src.index("double stop_rmse;")
+    assert [f[0] for f in eptv._Params._fields_][-1] == "check_finite"
+    assert [f[0] for f in eptv._Stats._fields_][-4:] == ["armijo_q0", "armijo_q1", "cgls_gamma", "cgls_delta"]

@@ -1,0 +1,200 @@
+"""Parity with the FP64 oracle on the hot path's rare branches, each forced by
+its inputs (through the C ABI):
+
+* the Armijo search past the first 8 candidates, which the decision kernel
+  finishes over the whole image (Sec. 2.2, the line search of P2);
+* a descent step skipped because no candidate within the backtracking cap
+  passes;
+* CGLS breakdown, which freezes P1 for the rest of the outer iteration (App. I);
+* the optional non-finite input scan, and the per-step records (Armijo energies
+  before and after, CGLS gamma and delta) against the oracle's own.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1009_2288_amd import synth
+from paper_1009_2288_amd.synth import Geometry
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(autouse=True)
+def announce(request):
+    sys.__stderr__.write(f"\n[gpu-case] {request.node.nodeid}\n")
+    sys.__stderr__.flush()
+    yield
+
+
+@pytest.fixture(scope="module")
+def E():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm GPU")
+    from paper_1009_2288_amd import eptv
+    eptv.library()
+    return eptv
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+_cache = {}
+
+
+def small(E, oracle):
+    if "small" not in _cache:
+        g = synth.geometry_small()
+        _cache["small"] = (g, E.Plan(g), oracle.Matrix(g), synth.make_case("small", 0))
+    return _cache["small"]
+
+
+def run_both(E, oracle, K, **kw):
+    g, P, M, c = small(E, oracle)
+    y = c.y.astype(np.float32)
+    fo, so = M.reconstruct(y, oracle.Params(outer_iters=K, **kw), f_ref=c.phantom)
+    f, sg = P.reconstruct(dev(y), E.Params(outer_iters=K, **kw), f_ref=dev(c.phantom))
+    return f.cpu().numpy(), sg, fo, so
+
+
+def test_armijo_search_beyond_the_fused_trials(E, oracle):
+    """First trial step 512/lambda: every one of the 8 fused candidates fails,
+    and the decision kernel's continuation over the whole image (16
+    candidates per round) finds the accepted index, as the oracle's plain
+    backtracking does."""
+    lam = 1000.0
+    f, sg, fo, so = run_both(E, oracle, 4, lam=lam, armijo_t0=512.0 / lam)
+    print("indices", so["armijo_k"].ravel(), "min margin", so["armijo_margin"].min())
+    assert so["armijo_k"].min() >= 8, "the case must need the continuation"
+    assert so["armijo_margin"].min() > 1e-5
+    assert np.array_equal(sg["armijo_k"], so["armijo_k"])
+    assert rel(f, fo) <= 1e-4
+    np.testing.assert_allclose(sg["armijo_q0"], so["armijo_q0"], rtol=1e-5)
+    np.testing.assert_allclose(sg["armijo_q1"], so["armijo_q1"], rtol=1e-5)
+
+
+@pytest.mark.parametrize("max_bt", [5, 12])
+def test_skipped_descent_step(E, oracle, max_bt):
+    """With the first step 512/lambda and at most max_bt halvings no candidate
+    (max_bt = 5), or only some (max_bt = 12, decided partly by the
+    continuation), passes: the step is skipped (k = -1, the iterate kept) on
+    both sides, and its recorded energy after equals the one before."""
+    lam = 1000.0
+    f, sg, fo, so = run_both(E, oracle, 3, lam=lam, armijo_t0=512.0 / lam, armijo_max_backtracks=max_bt)
+    print("indices", so["armijo_k"].ravel(), "min margin", so["armijo_margin"].min())
+    assert (so["armijo_k"] == -1).any()
+    assert so["armijo_margin"].min() > 1e-5
+    assert np.array_equal(sg["armijo_k"], so["armijo_k"])
+    skipped = sg["armijo_k"] == -1
+    assert np.array_equal(sg["armijo_q1"][skipped], sg["armijo_q0"][skipped])
+    assert rel(f, fo) <= 1e-4
+    np.testing.assert_allclose(sg["armijo_q0"], so["armijo_q0"], rtol=1e-5)
+    if max_bt == 5:
+        # no step taken anywhere: P2 leaves v as it is, so f is positivity(v)
+        assert skipped.all()
+
+
+def test_replayed_index_beyond_the_fused_trials(E, oracle):
+    """A replayed decision past the first 8 candidates: the GPU evaluates that
+    candidate's energy for the record, and follows the oracle's trajectory."""
+    g, P, M, c = small(E, oracle)
+    lam = 1000.0
+    kw = dict(outer_iters=3, lam=lam, armijo_t0=512.0 / lam)
+    y = c.y.astype(np.float32)
+    fo, so = M.reconstruct(y, oracle.Params(**kw), f_ref=c.phantom)
+    assert so["armijo_k"].min() >= 8
+    f, sg = P.reconstruct(dev(y), E.Params(**kw), f_ref=dev(c.phantom), armijo_replay=so["armijo_k"])
+    assert np.array_equal(sg["armijo_k"], so["armijo_k"])
+    assert rel(f.cpu().numpy(), fo) <= 1e-4
+    np.testing.assert_allclose(sg["armijo_q1"], so["armijo_q1"], rtol=1e-5)
+
+
+def one_ray_geometry():
+    """A 2 x 2 image seen by one ray along a grid line (view angle 0, one bin):
+    the ray crosses the two pixels of the upper row with length 1 each, so
+    P = [0, 0, 1, 1] and one CGLS step reaches the exact solution in any
+    arithmetic: r1 = r0 - (1/2)(2 r0) = 0."""
+    return Geometry(2, 2, 1.0, 1, 1, 0.1, 10.0, 20.0, 0.0, np.array([0.0]))
+
+
+def test_cgls_breakdown_after_the_exact_step(E, oracle):
+    """gamma_1 = 0 after the first step stops CGLS (App. I): one step per outer
+    iteration on both sides, the records of the stopped step equal."""
+    g = one_ray_geometry()
+    P, M = E.Plan(g), oracle.Matrix(g)
+    y = np.array([[0.75]], np.float32)
+    kw = dict(outer_iters=4, lam=10.0, edge_quantile=0.5)
+    fo, so = M.reconstruct(y, oracle.Params(**kw))
+    f, sg = P.reconstruct(dev(y), E.Params(**kw))
+    print("oracle steps", so["cgls_steps"], "gamma", so["cgls_gamma"], "delta", so["cgls_delta"])
+    assert np.all(so["cgls_steps"] == 1)
+    assert np.array_equal(sg["cgls_steps"], so["cgls_steps"])
+    assert np.all(sg["cgls_gamma"][:, 1] == 0.0) and np.all(sg["cgls_delta"][:, 1:] == 0.0)
+    np.testing.assert_allclose(sg["cgls_gamma"], so["cgls_gamma"], rtol=1e-5, atol=0)
+    np.testing.assert_allclose(sg["cgls_delta"], so["cgls_delta"], rtol=1e-5, atol=0)
+    np.testing.assert_allclose(sg["cgls_resid"], so["cgls_resid"], atol=1e-12)
+    assert np.array_equal(sg["armijo_k"], so["armijo_k"])
+    assert rel(f.cpu().numpy(), fo) <= 1e-5
+
+
+def test_cgls_breakdown_at_the_start(E, oracle):
+    """y = 0 from f = 0: gamma_0 = 0, so CGLS takes no step (App. I); P2 then
+    sees a zero direction and the image stays zero."""
+    g, P, M, c = small(E, oracle)
+    y = np.zeros((g.n_views, g.n_bins), np.float32)
+    kw = dict(outer_iters=2)
+    fo, so = M.reconstruct(y, oracle.Params(**kw))
+    f, sg = P.reconstruct(dev(y), E.Params(**kw))
+    assert np.all(so["cgls_steps"] == 0)
+    assert np.array_equal(sg["cgls_steps"], so["cgls_steps"])
+    assert np.all(sg["cgls_gamma"] == 0.0) and np.all(sg["cgls_delta"] == 0.0)
+    assert np.array_equal(sg["armijo_k"], so["armijo_k"])
+    assert float(torch.abs(f).max()) == 0.0 and np.abs(fo).max() == 0.0
+
+
+def test_records_match_the_oracle(E, oracle):
+    """The Armijo energies before / after each descent step and the CGLS
+    scalars of each step agree with the oracle's while the trajectories agree
+    closely (first iterations)."""
+    f, sg, fo, so = run_both(E, oracle, 6)
+    assert np.array_equal(sg["armijo_k"], so["armijo_k"])
+    for key in ("armijo_q0", "armijo_q1", "cgls_gamma", "cgls_delta"):
+        r = np.abs(sg[key] - so[key]).max() / np.abs(so[key]).max()
+        print(key, "max rel deviation", r)
+        np.testing.assert_allclose(sg[key], so[key], rtol=1e-4, err_msg=key)
+    # each accepted step lowers the energy by at least c t ||g||^2 >= 0
+    assert np.all(sg["armijo_q1"] <= sg["armijo_q0"])
+
+
+def test_nonfinite_input_scan(E, oracle):
+    """check_finite = 1: a NaN in y or an infinity in the warm start returns
+    EPTV_ERR_NONFINITE before anything runs (f untouched); clean inputs give
+    the same image as without the scan."""
+    g, P, M, c = small(E, oracle)
+    y = c.y.astype(np.float32)
+    f0 = dev(c.phantom)
+    bad = y.copy()
+    bad[3, 17] = np.nan
+    f = f0.clone()
+    with pytest.raises(E.EptvError) as ei:
+        P.reconstruct(dev(bad), E.Params(outer_iters=2, check_finite=1), f=f)
+    assert ei.value.status == E.EPTV_ERR_NONFINITE
+    assert torch.equal(f, f0)
+    warm = f0.clone()
+    warm[5, 9] = float("inf")
+    with pytest.raises(E.EptvError) as ei:
+        P.reconstruct(dev(y), E.Params(outer_iters=2, zero_init=0, check_finite=1), f=warm.clone())
+    assert ei.value.status == E.EPTV_ERR_NONFINITE
+    fa, _ = P.reconstruct(dev(y), E.Params(outer_iters=3, check_finite=1), stats=False)
+    fb, _ = P.reconstruct(dev(y), E.Params(outer_iters=3), stats=False)
+    torch.cuda.synchronize()
+    assert torch.equal(fa, fb)
