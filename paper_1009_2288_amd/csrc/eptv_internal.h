@@ -181,10 +181,8 @@ size_t workspace_layout(const Plan& p, int K, int T, int M, char* base, Workspac
 
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `s` and return hipGetLastError().
-size_t n_edges(const Plan& p);
 int project_blocks(const Plan& p);
 int image_tile_blocks(const Plan& p);
-void bp_tile_lists(const Plan& p, std::vector<int>& off, std::vector<int>& list);
 int sino_blocks(const Plan& p);
 int armijo_blocks(const Plan& p);
 int select_blocks(const Plan& p);

@@ -9,6 +9,7 @@
 #include <string>
 
 #include "eptv_internal.h"
+#include "tables.h"
 
 struct eptv_plan_s {
     eptv::Plan p;
@@ -25,12 +26,6 @@ namespace eptv {
 
 void set_last_error(const std::string& msg);
 int hip_fail(hipError_t e, const char* what);
-int validate_geometry(const eptv_geometry* g);
-int check_params(const eptv_params* q);
-bool tv_eps_ok(double eps);
-uint32_t select_rank(const Plan& p, double q);
-float t0_of(const eptv_params& q);
-float sigma_init(const eptv_params& q);
 
 #define EPTV_HIP(call)                                            \
     do {                                                          \

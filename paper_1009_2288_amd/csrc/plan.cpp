@@ -14,6 +14,7 @@
 #include "eptv_internal.h"
 #include "geometry.h"
 #include "host_internal.h"
+#include "tables.h"
 
 #include <vector>
 
@@ -27,73 +28,6 @@ int hip_fail(hipError_t e, const char* what)
 {
     g_last_error = std::string(what) + ": " + hipGetErrorString(e);
     return EPTV_ERR_HIP;
-}
-
-// The float32 system matrix of a plan, by ray (CSR): row v*B + b lists the
-// pixels the ray meets with their lengths, in sweep order.
-struct HostCsr {
-    std::vector<long long> rowptr;
-    std::vector<int> col;
-    std::vector<float> val;
-    std::vector<char> rows;  // per ray: swept row by row
-};
-
-static void build_csr(const Plan& p, HostCsr& m)
-{
-    const int nrow = p.V * p.B;
-    m.rowptr.assign((size_t)nrow + 1, 0);
-    m.col.clear();
-    m.val.clear();
-    m.rows.clear();
-    for (int v = 0; v < p.V; ++v)
-        for (int b = 0; b < p.B; ++b) {
-            const double beta = ((double)b - 0.5 * (p.B - 1) + p.bin_offset) * p.dbeta;
-            const HostRay R = make_ray(p, p.angles[v], beta);
-            for_each_entry(R, p, [&](long long pix, float c) {
-                m.col.push_back((int)pix);
-                m.val.push_back(c);
-            });
-            m.rows.push_back(R.rows ? 1 : 0);
-            m.rowptr[(size_t)v * p.B + b + 1] = (long long)m.col.size();
-        }
-}
-
-static Plan host_plan(const eptv_geometry* g)
-{
-    Plan p;
-    p.nx = g->nx;
-    p.ny = g->ny;
-    p.V = g->n_views;
-    p.B = g->n_bins;
-    p.pixel = g->pixel_mm;
-    p.dbeta = g->dbeta_rad;
-    p.bin_offset = g->bin_offset;
-    p.sad = g->sad_mm;
-    p.sdd = g->sdd_mm;
-    p.angles.resize(p.V);
-    for (int v = 0; v < p.V; ++v) p.angles[v] = g->view_angles_rad ? g->view_angles_rad[v] : 2.0 * M_PI * v / p.V;
-    return p;
-}
-
-int validate_geometry(const eptv_geometry* g)
-{
-    if (!g) return EPTV_ERR_ARG;
-    // at least 2 x 2 pixels: the projector reads a cell's two pixels as one pair
-    if (g->nx < 2 || g->ny < 2 || g->n_views <= 0 || g->n_bins <= 0) return EPTV_ERR_ARG;
-    if (g->nx > 32768 || g->ny > 32768 || (long long)g->n_views * g->n_bins > (1LL << 30)) return EPTV_ERR_ARG;
-    if (!(g->pixel_mm > 0) || !std::isfinite(g->pixel_mm)) return EPTV_ERR_GEOMETRY;
-    if (!(g->dbeta_rad > 0) || !std::isfinite(g->dbeta_rad) || !std::isfinite(g->bin_offset))
-        return EPTV_ERR_GEOMETRY;
-    const double half_diag = 0.5 * g->pixel_mm * std::sqrt((double)g->nx * g->nx + (double)g->ny * g->ny);
-    if (!(g->sad_mm > half_diag * (1.0 + 1e-6)) || !std::isfinite(g->sad_mm)) return EPTV_ERR_GEOMETRY;
-    if (!(g->sdd_mm >= g->sad_mm)) return EPTV_ERR_GEOMETRY;
-    const double edge = (0.5 * (g->n_bins - 1) + std::fabs(g->bin_offset)) * g->dbeta_rad;
-    // every ray, and the angle one bin beyond each detector end, points into the half-plane ahead
-    if (!(edge + g->dbeta_rad < 0.5 * M_PI)) return EPTV_ERR_GEOMETRY;
-    if (g->view_angles_rad)
-        for (int v = 0; v < g->n_views; ++v)
-            if (!std::isfinite(g->view_angles_rad[v])) return EPTV_ERR_GEOMETRY;
-    return EPTV_OK;
 }
 
 // ------------------------------------------------------------------ workspace
@@ -148,44 +82,6 @@ size_t workspace_layout(const Plan& p, int K, int T, int M, char* base, Workspac
     return off;
 }
 
-// eps of Eq. A3 as the P2 kernels use it: its float square must be a positive
-// normal number, so every half-edge magnitude is at least eps > 0 and the
-// fluxes of Eq. A2 (which divide by the magnitude) stay finite on flat regions.
-bool tv_eps_ok(double eps)
-{
-    const float e2 = (float)(eps * eps);
-    return eps > 0 && std::isnormal(e2);
-}
-
-int check_params(const eptv_params* q)
-{
-    if (!q) return EPTV_ERR_ARG;
-    if (q->tv_iters > 0 && !tv_eps_ok(q->tv_eps)) return EPTV_ERR_ARG;
-    if (q->outer_iters < 0 || q->cgls_iters < 0 || q->cgls_iters > kMaxCgls || q->tv_iters < 0) return EPTV_ERR_ARG;
-    if (q->tv_iters > 0 && !(q->lambda > 0)) return EPTV_ERR_ARG;
-    if (q->cgls_iters == 0 && !(q->mu >= 0 && q->lambda > 0)) return EPTV_ERR_ARG;
-    if (q->sigma_fixed < 0 && !(q->edge_quantile > 0 && q->edge_quantile <= 1)) return EPTV_ERR_ARG;
-    if (std::isnan(q->sigma_fixed) || !(q->tv_eps >= 0) || !(q->sigma_floor > 0)) return EPTV_ERR_ARG;
-    if (q->tv_iters > 0 && (!(q->armijo_shrink > 0 && q->armijo_shrink < 1) || q->armijo_max_backtracks < 0 ||
-                            q->armijo_max_backtracks > 4096 || !(q->armijo_c >= 0)))
-        return EPTV_ERR_ARG;
-    if ((long long)q->outer_iters * q->tv_iters > (1LL << 28)) return EPTV_ERR_ARG;
-    if ((long long)q->outer_iters * q->cgls_iters > (1LL << 28)) return EPTV_ERR_ARG;
-    if (q->check_finite != 0 && q->check_finite != 1) return EPTV_ERR_ARG;
-    if (q->stored_matrix < 0 || q->stored_matrix > 2 || (q->interp_bp != 0 && q->interp_bp != 1))
-        return EPTV_ERR_ARG;
-    if (q->check_every < 0 || !(q->stop_rmse >= 0) || !std::isfinite(q->stop_rmse)) return EPTV_ERR_ARG;
-    return EPTV_OK;
-}
-
-uint32_t select_rank(const Plan& p, double q)
-{
-    const double n = (double)n_edges(p);
-    long long k = (long long)std::ceil(q * n) - 1;
-    k = std::max(0LL, std::min(k, (long long)n - 1));
-    return (uint32_t)k;
-}
-
 struct Ctx {
     const Plan& p;
     Workspace& W;
@@ -198,10 +94,6 @@ struct Ctx {
     int replay = 0;                // 1: the Armijo decisions come from the step records (uploaded by the caller)
 };
 
-float t0_of(const eptv_params& q)
-{
-    return (float)(q.armijo_t0 > 0 ? q.armijo_t0 : 1.0 / q.lambda);
-}
 
 // sigma from the half-edge magnitudes of `img` (radix select, three digits).
 // The selection of sigma (three digit passes); with last_digit false the
@@ -216,8 +108,6 @@ static hipError_t enqueue_select(const Plan& p, Workspace& W, const float* img, 
     return last_digit ? launch_select_sigma(W.st, W.hist, floor_, s) : hipSuccess;
 }
 
-// sigma the per-iteration state starts from: fixed, or -1 (chosen by the selection)
-float sigma_init(const eptv_params& q) { return q.sigma_fixed < 0 ? -1.0f : (float)q.sigma_fixed; }
 
 // n_steps P2 descent steps (Sec. 2.2; Armijo line search) from `start`
 // towards v; the result goes to `fout` (and its transpose to foutT when
@@ -367,31 +257,16 @@ int eptv_plan_create(const eptv_geometry* geom, eptv_plan* out)
     Plan& p = h->p;
     p = host_plan(geom);
 
-    std::vector<RayFx> ray((size_t)p.V * p.B);
-    std::vector<int2> range((size_t)p.V * p.B);
-    std::vector<float2> view(p.V);
-    long long nnz = 0;
-    for (int v = 0; v < p.V; ++v) {
-        view[v] = make_float2((float)std::cos(p.angles[v]), (float)std::sin(p.angles[v]));
-        for (int b = 0; b < p.B; ++b) {
-            const double beta = ((double)b - 0.5 * (p.B - 1) + p.bin_offset) * p.dbeta;
-            const HostRay R = make_ray(p, p.angles[v], beta);
-            const size_t id = (size_t)v * p.B + b;
-            ray[id] = R.fx();
-            range[id] = make_int2(R.k_lo, R.k_hi);
-            for_each_entry(R, p, [&](long long, float) { ++nnz; });
-        }
-    }
-    p.nnz = nnz;
-    std::vector<int> list_off, list;
-    bp_tile_lists(p, list_off, list);
-    std::vector<double2> view_d(p.V);
-    for (int v = 0; v < p.V; ++v) view_d[v] = make_double2(std::cos(p.angles[v]), std::sin(p.angles[v]));
-    std::vector<double> tau(p.B + 2);
-    for (int b = -1; b <= p.B; ++b) {
-        const double beta = ((double)b - 0.5 * (p.B - 1) + p.bin_offset) * p.dbeta;
-        tau[b + 1] = std::tan(beta);  // |beta| < pi/2 by the geometry check
-    }
+    HostTables t;
+    build_tables(p, t);
+    p.nnz = t.nnz;
+    const auto& ray = t.ray;
+    const auto& range = t.range;
+    const auto& view = t.view;
+    const auto& view_d = t.view_d;
+    const auto& tau = t.tau;
+    const auto& list_off = t.list_off;
+    const auto& list = t.list;
     hipError_t e = hipGetDevice(&p.device);
     if (e == hipSuccess) e = hipMalloc(&p.rays.d_ray, ray.size() * sizeof(RayFx));
     if (e == hipSuccess) e = hipMalloc(&p.rays.d_range, range.size() * sizeof(int2));
@@ -471,71 +346,13 @@ int eptv_plan_store_matrix(eptv_plan h, size_t* device_bytes)
     if (!h) return EPTV_ERR_ARG;
     Plan& p = h->p;
     if (!p.mat.d_rowptr) {
-        HostCsr m;
-        build_csr(p, m);
-        const long long nnz = (long long)m.col.size();
-        if (nnz >= (1LL << 31) || (long long)p.nx * p.ny >= (1LL << 31)) return EPTV_ERR_ARG;
-        const int nrow = p.V * p.B, npix = p.nx * p.ny;
-        // the same entries grouped by pixel, rays ascending
-        std::vector<long long> colcnt((size_t)npix + 1, 0);
-        for (long long e = 0; e < nnz; ++e) colcnt[(size_t)m.col[e] + 1]++;
-        for (int c = 0; c < npix; ++c) colcnt[(size_t)c + 1] += colcnt[c];
-        std::vector<int> rowi((size_t)nnz);
-        std::vector<float> cval((size_t)nnz);
-        {
-            std::vector<long long> fill(colcnt.begin(), colcnt.end() - 1);
-            for (int r = 0; r < nrow; ++r)
-                for (long long e = m.rowptr[r]; e < m.rowptr[r + 1]; ++e) {
-                    const long long at = fill[m.col[e]]++;
-                    rowi[at] = r;
-                    cval[at] = m.val[e];
-                }
-        }
-        // padded, interleaved copies (see StoredMatrix)
-        auto pack = [](int n, const long long* ptr, const int* idx, const float* val, bool chunked,
-                       std::vector<int>& pptr, std::vector<int2>& ent) -> bool {
-            pptr.assign((size_t)n + 1, 0);
-            long long at = 0;
-            for (int i = 0; i < n; ++i) {
-                const long long len = ptr[i + 1] - ptr[i];
-                at += (len + kStoredPad - 1) / kStoredPad * kStoredPad;
-                if (at >= (1LL << 31)) return false;
-                pptr[(size_t)i + 1] = (int)at;
-            }
-            ent.assign((size_t)at, int2{0, 0});
-            for (int i = 0; i < n; ++i) {
-                long long o = pptr[i];
-                for (long long e = ptr[i]; e < ptr[i + 1]; ++e, ++o) {
-                    float v = val[e];
-                    int bits;
-                    std::memcpy(&bits, &v, 4);
-                    ent[(size_t)o] = int2{idx[e], bits};
-                }
-                for (; o < pptr[(size_t)i + 1]; ++o) ent[(size_t)o] = int2{idx[ptr[i + 1] - 1], 0};
-                if (!chunked) continue;
-                // chunks of kStoredChunk: slot l of a chunk of n holds entries l and n/2 + l
-                for (long long c0 = pptr[i]; c0 < pptr[(size_t)i + 1]; c0 += kStoredChunk) {
-                    const long long nc = std::min<long long>(kStoredChunk, pptr[(size_t)i + 1] - c0), h = nc / 2;
-                    std::vector<int2> t(ent.begin() + c0, ent.begin() + c0 + nc);
-                    for (long long l = 0; l < h; ++l) {
-                        ent[(size_t)(c0 + 2 * l)] = t[(size_t)l];
-                        ent[(size_t)(c0 + 2 * l + 1)] = t[(size_t)(h + l)];
-                    }
-                }
-            }
-            return true;
-        };
-        // the P copy: rays swept row by row index the transposed image
-        std::vector<int> tcol(m.col);
-        for (int r = 0; r < nrow; ++r)
-            if (m.rows[r])
-                for (long long e = m.rowptr[r]; e < m.rowptr[r + 1]; ++e)
-                    tcol[e] = (m.col[e] % p.nx) * p.ny + m.col[e] / p.nx;
-        std::vector<int> rowptr, colptr;
-        std::vector<int2> rent, cent;
-        if (!pack(nrow, m.rowptr.data(), tcol.data(), m.val.data(), true, rowptr, rent) ||
-            !pack(npix, colcnt.data(), rowi.data(), cval.data(), false, colptr, cent))
-            return EPTV_ERR_ARG;
+        HostStored hs;
+        if (pack_stored(p, hs) != EPTV_OK) return EPTV_ERR_ARG;
+        const auto& rowptr = hs.rowptr;
+        const auto& colptr = hs.colptr;
+        const auto& rent = hs.rent;
+        const auto& cent = hs.cent;
+        const long long nnz = hs.nnz;
         StoredMatrix& S = p.mat;
         hipError_t e = hipMalloc(&S.d_rowptr, rowptr.size() * 4);
         if (e == hipSuccess) e = hipMalloc(&S.d_rent, rent.size() * 8);

@@ -22,6 +22,7 @@
 // (batch.hip), which walk a list of (slice, block) items.
 #include "batch.h"
 #include "eptv_internal.h"
+#include "tables.h"
 #include "reduce.h"
 #include "state.h"
 
@@ -162,7 +163,7 @@ hipError_t launch_project(const Plan& p, const float* x, const float* xT, float 
 }
 
 // ------------------------------------------------------------------ backprojector
-constexpr int kTile = 16;
+constexpr int kTile = kBpTile;
 
 // lo0 + ks * step for 0 <= ks < 2^15 and |step| <= 2^32: the low word of step
 // in one 32x32->64 multiply-add, its high word (-1, 0 or 1) in a 24-bit one.
@@ -284,46 +285,6 @@ __global__ __launch_bounds__(256) void k_backproject(const RayFx* __restrict__ r
 
 int image_tile_blocks(const Plan& p) { return ((p.nx + kTile - 1) / kTile) * ((p.ny + kTile - 1) / kTile); }
 
-// Per tile, every ray that can meet one of its pixels, as global ray ids
-// (views ascending, bins ascending within a view).  The pixel centres span a
-// rectangle, so their angles seen from the source lie between those of its
-// corners; a ray through a pixel passes within d/sqrt(2) of its centre, i.e.
-// within asin(rad / l) of the centre's angle, largest at the rectangle point
-// nearest the source; half a bin more covers rounding.
-void bp_tile_lists(const Plan& p, std::vector<int>& off, std::vector<int>& list)
-{
-    const int gx = (p.nx + kTile - 1) / kTile, gy = (p.ny + kTile - 1) / kTile;
-    const double rad = p.pixel * std::sqrt(0.5) * (1.0 + 1e-6), bin_c = 0.5 * (p.B - 1) - p.bin_offset;
-    off.assign((size_t)gx * gy + 1, 0);
-    list.clear();
-    for (int ty = 0; ty < gy; ++ty)
-        for (int tx = 0; tx < gx; ++tx) {
-            const int i0 = tx * kTile, i1 = std::min(i0 + kTile, p.nx) - 1;
-            const int j0 = ty * kTile, j1 = std::min(j0 + kTile, p.ny) - 1;
-            const double x0 = (i0 + 0.5 - 0.5 * p.nx) * p.pixel, x1 = (i1 + 0.5 - 0.5 * p.nx) * p.pixel;
-            const double y0 = (j0 + 0.5 - 0.5 * p.ny) * p.pixel, y1 = (j1 + 0.5 - 0.5 * p.ny) * p.pixel;
-            for (int v = 0; v < p.V; ++v) {
-                const double cs = std::cos(p.angles[v]), sn = std::sin(p.angles[v]);
-                const double sx = -p.sad * cs, sy = -p.sad * sn;
-                double lo = 1e300, hi = -1e300;
-                for (int cnr = 0; cnr < 4; ++cnr) {
-                    const double px = (cnr & 1) ? x1 : x0, py = (cnr & 2) ? y1 : y0;
-                    const double along = px * cs + py * sn + p.sad, across = py * cs - px * sn;
-                    const double b = std::atan2(across, along) / p.dbeta + bin_c;
-                    lo = std::min(lo, b);
-                    hi = std::max(hi, b);
-                }
-                const double nxp = std::min(std::max(sx, x0), x1) - sx, nyp = std::min(std::max(sy, y0), y1) - sy;
-                const double lmin = std::sqrt(nxp * nxp + nyp * nyp);
-                const double hw = std::asin(std::min(1.0, rad / lmin)) / p.dbeta + 0.5;
-                const long long b0 = std::max(0LL, (long long)std::floor(lo - hw));
-                const long long b1 = std::min((long long)p.B - 1, (long long)std::ceil(hi + hw));
-                for (long long b = b0; b <= b1; ++b) list.push_back(v * p.B + (int)b);
-            }
-            off[(size_t)ty * gx + tx + 1] = (int)list.size();
-        }
-}
-
 hipError_t launch_backproject(const Plan& p, const float* r, float alpha, float beta, const float* c,
                               float* z, float* zT, double* partial, hipStream_t s)
 {
@@ -352,18 +313,21 @@ hipError_t launch_backproject(const Plan& p, const float* r, float alpha, float 
 // by one if the fraction leaves [0, 1).
 __device__ __forceinline__ float guess_atan(float t)
 {
-    // odd polynomial of degree 15 fitted to atan on [0, 1], reflected above 1
+    // odd polynomial of degree 15 for atan on [0, 1], reflected above 1; the
+    // coefficients are the near-minimax fit of Lawson's iteratively
+    // reweighted least squares (fit_atan.py beside this file prints them),
+    // 3.75e-8 rad at most in exact arithmetic
     const float a = fabsf(t);
     const bool big = a > 1.0f;
     const float u = big ? __builtin_amdgcn_rcpf(a) : a;
     const float u2 = u * u;
-    float p = -4.054555384e-03f;
-    p = fmaf(p, u2, 2.186291682e-02f);
-    p = fmaf(p, u2, -5.591227011e-02f);
-    p = fmaf(p, u2, 9.642193375e-02f);
-    p = fmaf(p, u2, -1.390862809e-01f);
-    p = fmaf(p, u2, 1.994656538e-01f);
-    p = fmaf(p, u2, -3.332986076e-01f);
+    float p = -4.054566622e-03f;
+    p = fmaf(p, u2, 2.186295575e-02f);
+    p = fmaf(p, u2, -5.591232369e-02f);
+    p = fmaf(p, u2, 9.642197100e-02f);
+    p = fmaf(p, u2, -1.390862946e-01f);
+    p = fmaf(p, u2, 1.994656563e-01f);
+    p = fmaf(p, u2, -3.332986078e-01f);
     p = fmaf(p, u2, 9.999993356e-01f);
     p *= u;
     p = big ? 1.5707963268f - p : p;

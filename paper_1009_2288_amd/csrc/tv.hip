@@ -14,6 +14,7 @@
 // edges on the left and bottom image border) for the energy sums.
 #include "batch.h"
 #include "eptv_internal.h"
+#include "tables.h"
 #include "reduce.h"
 
 namespace eptv {
@@ -73,7 +74,6 @@ __device__ __forceinline__ float tv_down(const Nbhd& N, float e2)
     return tv_edge(N.n[1][0], N.n[1][1], N.n[2][0], N.n[2][1], N.n[0][0], N.n[0][1], e2);
 }
 
-size_t n_edges(const Plan& p) { return (size_t)p.ny * (p.nx + 1) + (size_t)(p.ny + 1) * p.nx; }
 
 // ------------------------------------------------------------------ sigma (radix select)
 // sigma is the order statistic of rank `rank` of all half-edge magnitudes.
