@@ -289,6 +289,22 @@ int eptv_reconstruct_weighted(eptv_plan plan, const eptv_params* params, const f
                               const float* f_ref, const float* wx, const float* wy, int frozen_iters, void* ws,
                               size_t ws_bytes, eptv_stats* stats, void* stream);
 
+/* eptv_reconstruct for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same iteration and results, with the workspace taken from a fixed
+ * device array of the library instead of a caller's buffer.  That array
+ * (eptv_noalloc_scratch_bytes(), 32 MiB: a 512 x 512 image with thousands of
+ * per-iteration records) exists once per GPU until the process ends; params
+ * whose eptv_workspace_bytes exceed it are EPTV_ERR_WORKSPACE.  No call here
+ * allocates: no hipMalloc, no page-locked staging, no graph (EPTV_GRAPH is
+ * ignored; the kernels are launched one by one); stats are copied straight
+ * into the caller's host arrays.  The current device must be the plan's.
+ * Every call on one GPU shares its array: calls that overlap on one GPU
+ * (several streams or threads) race and must be serialised by the caller. */
+int eptv_reconstruct_noalloc(eptv_plan plan, const eptv_params* params, const float* y, float* f,
+                             const float* f_ref, eptv_stats* stats, void* stream);
+size_t eptv_noalloc_scratch_bytes(void);
+
 /* ------------------------------------------------------------------ batches
  * Many slices, each with its own geometry (image size, views, bins), iterated
  * together: every phase of the EPTV iteration (Sec. 2.2) is one launch for

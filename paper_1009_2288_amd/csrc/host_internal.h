@@ -26,6 +26,9 @@ namespace eptv {
 
 void set_last_error(const std::string& msg);
 int hip_fail(hipError_t e, const char* what);
+int reconstruct_impl(eptv_plan h, const eptv_params* q, const float* y, float* f, const float* f_ref,
+                     const float* wx_in, const float* wy_in, int frozen, const int32_t* replay, void* ws,
+                     size_t ws_bytes, eptv_stats* stats, void* stream, bool noalloc);
 
 #define EPTV_HIP(call)                                            \
     do {                                                          \

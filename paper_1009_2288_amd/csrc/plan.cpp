@@ -549,9 +549,35 @@ static hipError_t host_staging(eptv_plan h, size_t bytes, void** out)
     return hipSuccess;
 }
 
-static int reconstruct_impl(eptv_plan h, const eptv_params* q, const float* y, float* f, const float* f_ref,
-                            const float* wx_in, const float* wy_in, int frozen, const int32_t* replay, void* ws,
-                            size_t ws_bytes, eptv_stats* stats, void* stream)
+}  // extern "C"
+
+namespace eptv {
+
+// Reads n bytes of device memory back to the host after the stream's work so
+// far: through the plan's page-locked staging (grown on demand), or, for a
+// caller that must not allocate, straight into the destination.
+static int read_back(eptv_plan h, bool noalloc, void* dst, const void* src, size_t n, hipStream_t s)
+{
+    if (noalloc) {
+        EPTV_HIP(hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToHost, s));
+        EPTV_HIP(hipStreamSynchronize(s));
+        return EPTV_OK;
+    }
+    std::lock_guard<std::mutex> hl(h->host_mu);
+    void* hb = nullptr;
+    EPTV_HIP(host_staging(h, n, &hb));
+    EPTV_HIP(hipMemcpyAsync(hb, src, n, hipMemcpyDeviceToHost, s));
+    EPTV_HIP(hipStreamSynchronize(s));
+    std::memcpy(dst, hb, n);
+    return EPTV_OK;
+}
+
+// The outer loop behind every eptv_reconstruct* entry point.  With noalloc the
+// iteration is launched kernel by kernel whatever EPTV_GRAPH says (a graph's
+// instantiation allocates) and host reads go straight to their destination.
+int reconstruct_impl(eptv_plan h, const eptv_params* q, const float* y, float* f, const float* f_ref,
+                     const float* wx_in, const float* wy_in, int frozen, const int32_t* replay, void* ws,
+                     size_t ws_bytes, eptv_stats* stats, void* stream, bool noalloc)
 {
     if (!h || !y || !f) return EPTV_ERR_ARG;
     int rc = check_params(q);
@@ -576,13 +602,9 @@ static int reconstruct_impl(eptv_plan h, const eptv_params* q, const float* y, f
         // the optional input check, before anything else is enqueued
         EPTV_HIP(launch_scan_finite(y, (size_t)p.V * p.B, W.st, 0, s));
         if (!q->zero_init) EPTV_HIP(launch_scan_finite(f, (size_t)p.nx * p.ny, W.st, 1, s));
-        std::lock_guard<std::mutex> hl(h->host_mu);
-        void* hb = nullptr;
-        EPTV_HIP(host_staging(h, sizeof(int), &hb));
-        EPTV_HIP(hipMemcpyAsync(hb, &W.st->nonfinite, sizeof(int), hipMemcpyDeviceToHost, s));
-        EPTV_HIP(hipStreamSynchronize(s));
         int bad = 0;
-        std::memcpy(&bad, hb, sizeof bad);
+        rc = read_back(h, noalloc, &bad, &W.st->nonfinite, sizeof bad, s);
+        if (rc != EPTV_OK) return rc;
         if (bad) return EPTV_ERR_NONFINITE;
     }
 
@@ -601,13 +623,9 @@ static int reconstruct_impl(eptv_plan h, const eptv_params* q, const float* y, f
     auto check = [&]() -> int {
         ++done;
         if (!stop || done % every) return EPTV_OK;
-        std::lock_guard<std::mutex> hl(h->host_mu);
-        void* hb = nullptr;
-        EPTV_HIP(host_staging(h, sizeof(double), &hb));
-        EPTV_HIP(hipMemcpyAsync(hb, W.st_rmse + (done - 1), sizeof(double), hipMemcpyDeviceToHost, s));
-        EPTV_HIP(hipStreamSynchronize(s));
         double r = 0.0;
-        std::memcpy(&r, hb, sizeof r);
+        const int rc_ = read_back(h, noalloc, &r, W.st_rmse + (done - 1), sizeof r, s);
+        if (rc_ != EPTV_OK) return rc_;
         if (r <= q->stop_rmse) stopped = true;
         return EPTV_OK;
     };
@@ -615,7 +633,7 @@ static int reconstruct_impl(eptv_plan h, const eptv_params* q, const float* y, f
     // graph per kind of iteration (adaptive, or with the given weights)
     auto run = [&](const Ctx& cc, int count, hipGraphExec_t& gexec, std::vector<uint64_t>& gkey) -> int {
         if (count <= 0 || stopped) return EPTV_OK;
-        if (no_graph()) {
+        if (noalloc || no_graph()) {
             for (int k = 0; k < count && !stopped; ++k) {
                 EPTV_HIP(enqueue_iteration(cc, s));
                 const int rc_ = check();
@@ -701,6 +719,12 @@ static int reconstruct_impl(eptv_plan h, const eptv_params* q, const float* y, f
         const int M = q->cgls_iters;
         add(M > 0 ? stats->cgls_gamma : nullptr, W.st_gamma, kk * M * 8);
         add(M > 0 ? stats->cgls_delta : nullptr, W.st_delta, kk * M * 8);
+        if (noalloc) {
+            for (int i = 0; i < np; ++i)
+                EPTV_HIP(hipMemcpyAsync(parts[i].dst, parts[i].src, parts[i].n, hipMemcpyDeviceToHost, s));
+            EPTV_HIP(hipStreamSynchronize(s));
+            return EPTV_OK;
+        }
         std::lock_guard<std::mutex> hl(h->host_mu);
         void* hb = nullptr;
         EPTV_HIP(host_staging(h, std::max<size_t>(at, 16), &hb));
@@ -712,10 +736,14 @@ static int reconstruct_impl(eptv_plan h, const eptv_params* q, const float* y, f
     return EPTV_OK;
 }
 
+}  // namespace eptv
+
+extern "C" {
+
 int eptv_reconstruct(eptv_plan h, const eptv_params* q, const float* y, float* f, const float* f_ref, void* ws,
                      size_t ws_bytes, eptv_stats* stats, void* stream)
 {
-    return reconstruct_impl(h, q, y, f, f_ref, nullptr, nullptr, 0, nullptr, ws, ws_bytes, stats, stream);
+    return reconstruct_impl(h, q, y, f, f_ref, nullptr, nullptr, 0, nullptr, ws, ws_bytes, stats, stream, false);
 }
 
 int eptv_reconstruct_replay(eptv_plan h, const eptv_params* q, const float* y, float* f, const float* f_ref,
@@ -723,7 +751,7 @@ int eptv_reconstruct_replay(eptv_plan h, const eptv_params* q, const float* y, f
                             void* stream)
 {
     if (!armijo_replay) return EPTV_ERR_ARG;
-    return reconstruct_impl(h, q, y, f, f_ref, nullptr, nullptr, 0, armijo_replay, ws, ws_bytes, stats, stream);
+    return reconstruct_impl(h, q, y, f, f_ref, nullptr, nullptr, 0, armijo_replay, ws, ws_bytes, stats, stream, false);
 }
 
 int eptv_reconstruct_weighted(eptv_plan h, const eptv_params* q, const float* y, float* f, const float* f_ref,
@@ -731,7 +759,7 @@ int eptv_reconstruct_weighted(eptv_plan h, const eptv_params* q, const float* y,
                               eptv_stats* stats, void* stream)
 {
     if (!wx || !wy || frozen_iters < 0) return EPTV_ERR_ARG;
-    return reconstruct_impl(h, q, y, f, f_ref, wx, wy, frozen_iters, nullptr, ws, ws_bytes, stats, stream);
+    return reconstruct_impl(h, q, y, f, f_ref, wx, wy, frozen_iters, nullptr, ws, ws_bytes, stats, stream, false);
 }
 
 }  // extern "C"

@@ -30,7 +30,8 @@ SYMBOLS = ["eptv_plan_create", "eptv_plan_destroy", "eptv_plan_nnz", "eptv_works
            "eptv_batch_reconstruct", "eptv_unet_create", "eptv_unet_destroy", "eptv_unet_param_count",
            "eptv_unet_set_params", "eptv_unet_get_params", "eptv_unet_get_grads", "eptv_unet_forward",
            "eptv_unet_backward", "eptv_unet_adam", "eptv_unet_mse", "eptv_reconstruct_weighted",
-           "eptv_maps_from_eptv", "eptv_maps_to_eptv", "eptv_reconstruct_replay"]
+           "eptv_maps_from_eptv", "eptv_maps_to_eptv", "eptv_reconstruct_replay",
+           "eptv_reconstruct_noalloc", "eptv_noalloc_scratch_bytes"]
 
 
 class EptvError(RuntimeError):
@@ -172,6 +173,9 @@ def _lib() -> C.CDLL:
         L.eptv_select_sigma.argtypes = [vp, vp, C.c_double, C.c_float, C.c_float, vp, vp, sz, vp]
         L.eptv_tv_step.argtypes = [vp, C.POINTER(_Params), vp, vp, C.c_float, C.c_int, vp, sz, C.POINTER(_Stats), vp]
         L.eptv_reconstruct.argtypes = [vp, C.POINTER(_Params), vp, vp, vp, vp, sz, C.POINTER(_Stats), vp]
+        L.eptv_reconstruct_noalloc.argtypes = [vp, C.POINTER(_Params), vp, vp, vp, C.POINTER(_Stats), vp]
+        L.eptv_noalloc_scratch_bytes.argtypes = []
+        L.eptv_noalloc_scratch_bytes.restype = sz
         L.eptv_reconstruct_replay.argtypes = [vp, C.POINTER(_Params), vp, vp, vp, C.POINTER(C.c_int32), vp, sz,
                                               C.POINTER(_Stats), vp]
         L.eptv_reconstruct_weighted.argtypes = [vp, C.POINTER(_Params), vp, vp, vp, vp, vp, C.c_int, vp, sz,
@@ -493,6 +497,41 @@ class Plan:
             if f_ref is None:
                 rec.pop("rmse")
         return f, rec
+
+    def reconstruct_noalloc(self, y: torch.Tensor, params: Params, f: Optional[torch.Tensor] = None,
+                            f_ref: Optional[torch.Tensor] = None, stats: bool = True, stream=None):
+        """reconstruct() through eptv_reconstruct_noalloc: no workspace tensor
+        is allocated; the library's fixed device array serves instead."""
+        import numpy as np
+        y = self._sino(y, "y")
+        if f is None:
+            f = torch.zeros((self.ny, self.nx), dtype=torch.float32, device=self.device)
+        f = self._img(f, "f")
+        if f_ref is not None:
+            f_ref = self._img(f_ref, "f_ref")
+        K, T, M = params.outer_iters, params.tv_iters, params.cgls_iters
+        rec = None
+        stp = None
+        done = np.zeros(1, np.int32)
+        if stats:
+            rec = _records(K, T, M)
+            st = _stats_of(rec, done)
+            stp = C.byref(st)
+        cp = params._c()
+        _check(_lib().eptv_reconstruct_noalloc(self._h, C.byref(cp), y.data_ptr(), f.data_ptr(),
+                                               f_ref.data_ptr() if f_ref is not None else None, stp,
+                                               _stream(stream)), "eptv_reconstruct_noalloc")
+        if rec is not None:
+            n = int(done[0])
+            rec = _shape_records(rec, n, T, M) | {"iters_run": n}
+            if f_ref is None:
+                rec.pop("rmse")
+        return f, rec
+
+
+def noalloc_scratch_bytes() -> int:
+    """Size of the fixed device array eptv_reconstruct_noalloc works in."""
+    return int(_lib().eptv_noalloc_scratch_bytes())
 
 
 class Batch:
