@@ -112,11 +112,10 @@ static int bind_batch(eptv_batch_s& b, const eptv_params& q, const std::vector<W
         const Workspace& W = Ws[i];
         SliceDev d = slice_shape(p);
         d.rank = select_rank(p, q.edge_quantile);
-        float* bufs[kNumBufs] = {f[i],  W.fT, W.u,  W.s,  W.sT, W.z,          W.g,
-                                 W.g2,  W.f1, W.f2, W.wx, W.wy, W.r,          W.q,
+        float* bufs[kNumBufs] = {f[i], W.fT, W.u,  W.s,  W.sT, W.z, W.g, W.g2, W.f1, W.f2, W.r, W.q,
                                  (float*)y[i], f_ref ? (float*)f_ref[i] : nullptr};
         std::memcpy(d.buf, bufs, sizeof bufs);
-        double* parts[kNumParts] = {W.part_proj, W.part_bp, W.part_grad, W.part_arm, W.part_res, W.part_rmse};
+        double* parts[kNumParts] = {W.part_proj, W.part_bp, W.part_p2, W.part_res, W.part_rmse};
         std::memcpy(d.part, parts, sizeof parts);
         d.keys = W.keys;
         d.hist = W.hist;
@@ -179,15 +178,33 @@ static hipError_t enqueue_batch_iteration(const BatchDev& b, const eptv_params& 
     }
     const float t0 = t0_of(q), shrink = (float)q.armijo_shrink;
     const int gbuf[2] = {kBufG, kBufG2}, fbuf[2] = {kBufF1, kBufF2};
+    // the decision of step `step`: a kernel of its own per step, one block per slice
+    auto decision = [&](int step) {
+        P2Decide D{};
+        D.part = nullptr;
+        D.step = step;
+        D.T = T;
+        D.max_bt = q.armijo_max_backtracks;
+        D.c_arm = q.armijo_c;
+        D.t0 = t0;
+        D.shrink = shrink;
+        D.replay = 0;
+        return D;
+    };
     int fcur = start;
+    if (T == 1 && start == kBufF) {
+        // the last step's kernel reads its iterate across the whole image in
+        // the rare longer Armijo search while it writes f: keep them apart
+        EPTV_TRY(blaunch_copy_clamp(b, start, kBufF1, kNoBuf, 0, s));
+        fcur = kBufF1;
+    }
     for (int t = 0; t < T; ++t) {
-        const int g = gbuf[t & 1];
         const int gprev = t > 0 ? gbuf[(t - 1) & 1] : kNoBuf;
         const int fnext = t > 0 ? fbuf[t & 1] : kNoBuf;
-        EPTV_TRY(blaunch_tv_armijo(b, fcur, gprev, fnext, kBufU, (float)q.lambda, eps2, g, t0, shrink, s));
+        if (t > 0) EPTV_TRY(blaunch_p2_decide(b, fcur, gprev, kBufU, (float)q.lambda, eps2, decision(t - 1), s));
+        EPTV_TRY(blaunch_p2_step(b, fcur, gprev, fnext, kBufU, (float)q.lambda, eps2, gbuf[t & 1], t0, shrink,
+                                 decision(t - 1), s));
         if (t > 0) fcur = fnext;
-        EPTV_TRY(blaunch_armijo_decide(b, q.armijo_max_backtracks, q.armijo_c, t0, shrink, t, T, fcur, g, kBufU,
-                                       (float)q.lambda, eps2, s));
     }
     // Step 3 (positivity) fused into the last update
     // (the update also forms the squared errors to the references, per tile)
@@ -195,7 +212,9 @@ static hipError_t enqueue_batch_iteration(const BatchDev& b, const eptv_params& 
         EPTV_TRY(blaunch_copy_clamp(b, start, kBufF, kBufFT, q.positivity, s));
         if (with_ref) EPTV_TRY(blaunch_rmse_part(b, kBufF, s));
     } else {
-        EPTV_TRY(blaunch_p2_update(b, fcur, gbuf[(T - 1) & 1], kBufF, kBufFT, q.positivity, with_ref, s));
+        EPTV_TRY(blaunch_p2_decide(b, fcur, gbuf[(T - 1) & 1], kBufU, (float)q.lambda, eps2, decision(T - 1), s));
+        EPTV_TRY(blaunch_p2_final(b, fcur, gbuf[(T - 1) & 1], kBufF, kBufFT, q.positivity, with_ref, kBufU,
+                                  (float)q.lambda, eps2, decision(T - 1), s));
     }
     EPTV_TRY(blaunch_iter_end(b, M > 0, with_ref, T > 0, sigma_init(q), s));
 #undef EPTV_TRY

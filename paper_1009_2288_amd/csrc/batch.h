@@ -27,8 +27,6 @@ enum BufId : int {
     kBufG2,    // P2 direction (pong)
     kBufF1,    // P2 iterate (ping)
     kBufF2,    // P2 iterate (pong)
-    kBufWX,    // x-edge weights
-    kBufWY,    // y-edge weights
     kBufR,     // residual              [V][B]
     kBufQ,     // P s                   [V][B]
     kBufY,     // the sinogram y
@@ -36,7 +34,7 @@ enum BufId : int {
     kNumBufs
 };
 
-enum PartId : int { kPartProj, kPartBp, kPartGrad, kPartArm, kPartRes, kPartRmse, kNumParts };
+enum PartId : int { kPartProj, kPartBp, kPartP2, kPartRes, kPartRmse, kNumParts };
 
 constexpr int kNoBuf = -1;
 
@@ -96,11 +94,15 @@ hipError_t blaunch_gd_p1(const BatchDev& b, float step, hipStream_t s);
 hipError_t blaunch_edges_hist(const BatchDev& b, int img, float eps2, hipStream_t s);
 hipError_t blaunch_select_hist(const BatchDev& b, int pass, hipStream_t s);
 hipError_t blaunch_select_finalize(const BatchDev& b, int pass, float floor_, hipStream_t s);
-hipError_t blaunch_tv_armijo(const BatchDev& b, int f, int g_prev, int f_out, int v, float lambda, float eps2, int g,
-                             float t0, float shrink, hipStream_t s);
-hipError_t blaunch_armijo_decide(const BatchDev& b, int max_bt, double c_arm, float t0, float shrink, int step, int T,
-                                 int f, int g, int v, float lambda, float eps2, hipStream_t s);
-hipError_t blaunch_p2_update(const BatchDev& b, int fcur, int g, int fout, int foutT, int clamp, int rmse,
+// Descent step D.step + 1 (the previous step's decision read from the slice's
+// state) and the last step's update; blaunch_p2_decide takes each decision,
+// D carrying the constants (its pointers are each slice's own).
+hipError_t blaunch_p2_step(const BatchDev& b, int f, int g_prev, int f_out, int v, float lambda, float eps2, int g,
+                           float t0, float shrink, const P2Decide& D, hipStream_t s);
+hipError_t blaunch_p2_final(const BatchDev& b, int fcur, int g, int fout, int foutT, int clamp, int rmse, int v,
+                            float lambda, float eps2, const P2Decide& D, hipStream_t s);
+// One block per slice: step D.step's decision into the slice's state.
+hipError_t blaunch_p2_decide(const BatchDev& b, int f, int g, int v, float lambda, float eps2, const P2Decide& D,
                              hipStream_t s);
 hipError_t blaunch_copy_clamp(const BatchDev& b, int src, int dst, int dstT, int clamp, hipStream_t s);
 hipError_t blaunch_rmse_part(const BatchDev& b, int f, hipStream_t s);

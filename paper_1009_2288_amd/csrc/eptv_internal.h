@@ -77,6 +77,9 @@ constexpr int kMaxCgls = 64;
 constexpr int kSelectBins = 2048;  // 11-bit radix digits
 constexpr int kArmijoFirst = 8;    // Armijo candidates k = 0..7, evaluated by the whole grid
 constexpr int kArmijoMore = 16;    // candidates per round of the rare longer search
+constexpr int kP2T = 32;            // P2 descent-step tiles: 32 x 32 pixels
+constexpr int kP2Threads = kP2T * kP2T;  // one thread per pixel
+constexpr int kP2Slots = 2 + kArmijoFirst;  // per-block partials of a step: Q, ||g||^2, trial energies
 
 // Scalars that stay on the device.  Each entry is written by one kernel and
 // read only by later kernels on the stream (never by the writer's own grid).
@@ -95,8 +98,7 @@ struct DevState {
     uint32_t sel_prefix[2], sel_rank[2];  // one-slice path: prefix and rank after digits 0 and 1
     float sigma;
     float inv_sigma2;
-    // P2 (Armijo): the current step's energies and decision
-    double q0, gg;
+    // P2: a descent step's decision, when a kernel of its own takes it (batches)
     int k;
     float t;
     // bookkeeping
@@ -140,6 +142,19 @@ struct Plan {
     std::vector<uint64_t> gkey_w;
 };
 
+// The Armijo decision of one descent step, taken by the kernel after it.
+struct P2Decide {
+    const double* part;  // the step's partials [kP2Slots][blocks]; null: the decision is st->k, st->t
+    int step, T;         // the step and the steps per P2 (record index iter * T + step)
+    int max_bt;
+    double c_arm;
+    float t0, shrink;
+    int replay;          // 1: the index comes from st_k
+    int32_t* st_k;       // per-step records [K*T], may be null
+    double* st_q0;
+    double* st_q1;
+};
+
 // ---------------------------------------------------------------- workspace
 struct Workspace {
     float* fT;      // transposed image for the projector [nx][ny]
@@ -151,8 +166,6 @@ struct Workspace {
     float* g2;      // P2 direction (pong)
     float* f1;      // P2 iterate (ping)
     float* f2;      // P2 iterate (pong)
-    float* wx;      // x-edge weights [ny][nx+1]
-    float* wy;      // y-edge weights [ny+1][nx]
     float* r;       // CGLS residual [V][B]
     float* q;       // P s [V][B]
     uint32_t* keys; // edge magnitude bit patterns [n_edges]
@@ -160,8 +173,7 @@ struct Workspace {
     uint32_t* hist; // [3][kSelectBins]
     double* part_proj;  // ||P s||^2 per projector block
     double* part_bp;    // ||P^T r||^2 per backprojector block
-    double* part_grad;  // (Q, ||g||^2) per gradient block
-    double* part_arm;   // kArmijoFirst candidate energies per Armijo block (slot-major)
+    double* part_p2;    // descent-step partials, two by step parity: [2][kP2Slots][p2_blocks]
     double* part_res;   // ||r||^2 per sinogram block of the last CGLS axpy
     double* part_rmse;  // (f - f_ref)^2 per block
     DevState* st;
@@ -184,7 +196,6 @@ size_t workspace_layout(const Plan& p, int K, int T, int M, char* base, Workspac
 int project_blocks(const Plan& p);
 int image_tile_blocks(const Plan& p);
 int sino_blocks(const Plan& p);
-int armijo_blocks(const Plan& p);
 int select_blocks(const Plan& p);
 constexpr int kRmseBlocks = 256;
 
@@ -227,34 +238,29 @@ hipError_t launch_select_pass(const Plan& p, int pass, const uint32_t* keys, Dev
 hipError_t launch_select_sigma(DevState* st, const uint32_t* hist, float sigma_floor, hipStream_t s);
 hipError_t launch_sigma_out(const DevState* st, float* out, hipStream_t s);
 
-// P2: direction (optionally applying the previous step first), Armijo
-// candidates, the decision, the final update
+// P2 (Sec. 2.2): the stand-alone direction, its VJP, the descent steps
 hipError_t launch_tv_vjp(const Plan& p, const float* f, const float* u, float lambda, float sigma, float eps2,
                          float* e3, float* out, hipStream_t s);
-hipError_t launch_tv_grad(const Plan& p, const float* f, const float* g_prev, const DevState* st_prev, float* f_out,
-                          const float* v, float lambda, const DevState* st, float sigma_direct, float eps2, float* g,
-                          float* wx, float* wy, double* part, hipStream_t s, const float* wx_in = nullptr,
+// g = lambda (f - v) + A2 at f; sigma = inf gives w = 1; weights stored when
+// wx / wy are given; partials (Q, ||g||^2) per 16x16 block when part is given
+hipError_t launch_tv_grad(const Plan& p, const float* f, const float* v, float lambda, float sigma, float eps2,
+                          float* g, float* wx, float* wy, double* part, hipStream_t s, const float* wx_in = nullptr,
                           const float* wy_in = nullptr);
-// One descent step's direction (as launch_tv_grad, with the weights and
-// partials) and the first Armijo trials (as launch_armijo) in one pass.
-hipError_t launch_tv_armijo(const Plan& p, const float* f, const float* g_prev, const DevState* st_prev,
-                            float* f_out, const float* v, float lambda, const DevState* st, float eps2, float* g,
-                            float* wx, float* wy, double* part_grad, double* part_arm, float t0, float shrink,
-                            hipStream_t s, const float* wx_in = nullptr, const float* wy_in = nullptr,
-                            DevState* sel_st = nullptr, const uint32_t* sel_hist = nullptr, float sel_floor = 0.0f);
-
-// st_k / st_q0 / st_q1: the per-step records ([K*T], entry iter*T + step)
-hipError_t launch_armijo_decide(const Plan& p, DevState* st, const double* part_grad, const double* part_arm,
-                                int max_bt, double c_arm, float t0, float shrink, int32_t* st_k, double* st_q0,
-                                double* st_q1, int step, int T, const float* f, const float* g, const float* v,
-                                const float* wx, const float* wy, float lambda, float eps2, hipStream_t s,
-                                int replay = 0);
-// With ref, also one partial of the squared error to ref per 32 x 32 tile
-// (update_tiles of them) in part_rmse.
+// One kernel per descent step (32x32 tiles): the previous step's Armijo
+// decision (D; D.part null for the first step), the iterate, the direction and
+// this step's partials [kP2Slots][p2_blocks] (Q, ||g||^2, kArmijoFirst trial
+// energies); then one kernel deciding and applying the last step, with
+// positivity, the transposed copy and (with ref) one squared-error partial
+// per tile in part_rmse.
+int p2_blocks(const Plan& p);
 int update_tiles(const Plan& p);
-hipError_t launch_p2_update(const Plan& p, const DevState* st, const float* fcur, const float* g,
-                            float* fout, float* foutT, int clamp, hipStream_t s, const float* ref = nullptr,
-                            double* part_rmse = nullptr);
+hipError_t launch_p2_step(const Plan& p, const float* f, const float* g_prev, float* f_out, const float* v,
+                          float lambda, DevState* st, float eps2, float* g, double* part, float t0, float shrink,
+                          const float* wx_in, const float* wy_in, const uint32_t* sel_hist, float sel_floor,
+                          const P2Decide& D, hipStream_t s);
+hipError_t launch_p2_final(const Plan& p, const float* fcur, const float* g, float* fout, float* foutT, int clamp,
+                           const float* ref, double* part_rmse, const float* v, float lambda, const DevState* st,
+                           float eps2, const float* wx_in, const float* wy_in, const P2Decide& D, hipStream_t s);
 hipError_t launch_copy_clamp(const Plan& p, const float* src, float* dst, float* dstT, int clamp,
                              hipStream_t s);
 

@@ -54,8 +54,6 @@ size_t workspace_layout(const Plan& p, int K, int T, int M, char* base, Workspac
     W.g2 = (float*)take(ni * 4);
     W.f1 = (float*)take(ni * 4);
     W.f2 = (float*)take(ni * 4);
-    W.wx = (float*)take((size_t)p.ny * (p.nx + 1) * 4);
-    W.wy = (float*)take((size_t)(p.ny + 1) * p.nx * 4);
     W.r = (float*)take(ns * 4);
     W.q = (float*)take(ns * 4);
     W.keys = (uint32_t*)take(n_edges(p) * 4);
@@ -63,8 +61,7 @@ size_t workspace_layout(const Plan& p, int K, int T, int M, char* base, Workspac
     W.hist = (uint32_t*)take(3 * kSelectBins * 4);
     W.part_proj = (double*)take((size_t)project_blocks(p) * 8);
     W.part_bp = (double*)take((size_t)image_tile_blocks(p) * 8);
-    W.part_grad = (double*)take((size_t)armijo_blocks(p) * 2 * 8);
-    W.part_arm = (double*)take((size_t)armijo_blocks(p) * kArmijoFirst * 8);
+    W.part_p2 = (double*)take((size_t)2 * kP2Slots * p2_blocks(p) * 8);
     W.part_res = (double*)take((size_t)sino_blocks(p) * 8);
     // per-block squared errors: the RMSE kernel's, or the final P2 update's (one per 32 x 32 tile)
     W.part_rmse = (double*)take((size_t)std::max(kRmseBlocks, update_tiles(p)) * 8);
@@ -120,30 +117,50 @@ static hipError_t enqueue_p2(const Plan& p, Workspace& W, const eptv_params& q, 
                              const float* f_ref = nullptr, bool close_sigma = false)
 {
     hipError_t e;
+    if (n_steps == 0) return launch_copy_clamp(p, start, fout, foutT, clamp, s);
     const float eps2 = (float)(q.tv_eps * q.tv_eps);
     const float t0 = t0_of(q), shrink = (float)q.armijo_shrink;
+    const size_t np = (size_t)kP2Slots * p2_blocks(p);
     const float* fcur = start;
     float* gbuf[2] = {W.g, W.g2};
     float* fbuf[2] = {W.f1, W.f2};
+    // the decision of step `step`, taken by the kernel after it
+    auto decision = [&](int step) {
+        P2Decide D{};
+        D.part = step >= 0 ? W.part_p2 + (size_t)(step & 1) * np : nullptr;
+        D.step = step;
+        D.T = n_steps;
+        D.max_bt = q.armijo_max_backtracks;
+        D.c_arm = q.armijo_c;
+        D.t0 = t0;
+        D.shrink = shrink;
+        D.replay = replay;
+        D.st_k = st_k;
+        D.st_q0 = W.st_q0;
+        D.st_q1 = W.st_q1;
+        return D;
+    };
+    if (n_steps == 1 && start == fout) {
+        // the last step's kernel reads its iterate across the whole image in
+        // the rare longer Armijo search while it writes fout: keep them apart
+        if ((e = launch_copy_clamp(p, start, fbuf[0], nullptr, 0, s)) != hipSuccess) return e;
+        fcur = fbuf[0];
+    }
     for (int t = 0; t < n_steps; ++t) {
-        float* g = gbuf[t & 1];
-        const float* gprev = t > 0 ? gbuf[(t - 1) & 1] : nullptr;
-        float* fnext = t > 0 ? fbuf[t & 1] : nullptr;
-        // the direction at the current iterate and the first Armijo trials, one pass
-        // (the first step closes sigma's last digit when the selection left it open)
+        // step t: the decision of step t-1, the iterate, the direction and
+        // the first Armijo trials (the first step closes sigma's last digit
+        // when the selection left it open)
         const bool sel = close_sigma && t == 0;
-        if ((e = launch_tv_armijo(p, fcur, gprev, W.st, fnext, v, (float)q.lambda, W.st, eps2, g, W.wx, W.wy,
-                                  W.part_grad, W.part_arm, t0, shrink, s, wx_in, wy_in, sel ? W.st : nullptr,
-                                  sel ? W.hist + 2 * kSelectBins : nullptr, (float)q.sigma_floor)) != hipSuccess)
+        float* fnext = t > 0 ? fbuf[t & 1] : nullptr;
+        if ((e = launch_p2_step(p, fcur, t > 0 ? gbuf[(t - 1) & 1] : nullptr, fnext, v, (float)q.lambda, W.st, eps2,
+                                gbuf[t & 1], W.part_p2 + (size_t)(t & 1) * np, t0, shrink, wx_in, wy_in,
+                                sel ? W.hist + 2 * kSelectBins : nullptr, (float)q.sigma_floor, decision(t - 1),
+                                s)) != hipSuccess)
             return e;
         if (t > 0) fcur = fnext;
-        if ((e = launch_armijo_decide(p, W.st, W.part_grad, W.part_arm, q.armijo_max_backtracks, q.armijo_c, t0,
-                                      shrink, st_k, W.st_q0, W.st_q1, t, n_steps, fcur, g, v, W.wx, W.wy,
-                                      (float)q.lambda, eps2, s, replay)) != hipSuccess)
-            return e;
     }
-    if (n_steps == 0) return launch_copy_clamp(p, start, fout, foutT, clamp, s);
-    return launch_p2_update(p, W.st, fcur, gbuf[(n_steps - 1) & 1], fout, foutT, clamp, s, f_ref, W.part_rmse);
+    return launch_p2_final(p, fcur, gbuf[(n_steps - 1) & 1], fout, foutT, clamp, f_ref, W.part_rmse, v,
+                           (float)q.lambda, W.st, eps2, wx_in, wy_in, decision(n_steps - 1), s);
 }
 
 // One outer iteration of the EPTV algorithm (Sec. 2.2), entirely on `s`.
@@ -471,8 +488,7 @@ int eptv_tv_gradient(eptv_plan h, const float* f, const float* v, float lambda, 
     Workspace W;
     int rc = bind_ws(h->p, 1, 0, 0, ws, ws_bytes, &W);
     if (rc != EPTV_OK) return rc;
-    EPTV_HIP(launch_tv_grad(h->p, f, nullptr, nullptr, nullptr, v, lambda, nullptr, sigma, tv_eps * tv_eps, g, wx, wy,
-                            nullptr, (hipStream_t)stream));
+    EPTV_HIP(launch_tv_grad(h->p, f, v, lambda, sigma, tv_eps * tv_eps, g, wx, wy, nullptr, (hipStream_t)stream));
     return EPTV_OK;
 }
 

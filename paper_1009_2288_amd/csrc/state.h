@@ -8,7 +8,7 @@ namespace eptv {
 
 // Per-iteration records, the iteration counter, and the reset of the
 // per-iteration state for the next iteration (histograms, CGLS step count,
-// selection prefix, sigma, step decision), so no kernel of its own is needed.
+// selection prefix, sigma), so no kernel of its own is needed.
 __device__ __forceinline__ void reset_iteration_state(DevState* st, uint32_t* hist, float sigma_fixed)
 {
     for (int i = threadIdx.x; i < 3 * kSelectBins; i += blockDim.x) hist[i] = 0u;
@@ -18,8 +18,6 @@ __device__ __forceinline__ void reset_iteration_state(DevState* st, uint32_t* hi
         st->rank = st->rank0;
         st->sigma = sigma_fixed;
         st->inv_sigma2 = sigma_fixed >= 0.0f ? 1.0f / (sigma_fixed * sigma_fixed) : 0.0f;
-        st->k = -1;
-        st->t = 0.0f;
     }
 }
 

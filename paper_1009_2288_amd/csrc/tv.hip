@@ -196,31 +196,37 @@ __device__ __forceinline__ int digit_shift(int pass) { return pass == 0 ? 21 : (
 
 __device__ __forceinline__ void select_digit(const uint32_t* hist, int pass, uint32_t rank, SelShared& S)
 {
+    // threads 0..255 take part; wider blocks only join the barriers
     uint32_t* sums = S.sums;
     const int nb = pass == 2 ? 1024 : 2048;
     const int per = nb / 256;
     const int t = threadIdx.x;
-    uint32_t local = 0;
-    for (int e = 0; e < per; ++e) local += hist[t * per + e];
-    sums[t] = local;
+    const bool act = t < 256;
+    if (act) {
+        uint32_t local = 0;
+        for (int e = 0; e < per; ++e) local += hist[t * per + e];
+        sums[t] = local;
+    }
     if (t == 0) {  // only kept if the rank exceeded the count, which cannot happen
         S.found_digit = (uint32_t)(nb - 1);
         S.found_before = 0u;
     }
     __syncthreads();
     for (int o = 1; o < 256; o <<= 1) {
-        const uint32_t add = t >= o ? sums[t - o] : 0u;
+        const uint32_t add = act && t >= o ? sums[t - o] : 0u;
         __syncthreads();
-        sums[t] += add;
+        if (act) sums[t] += add;
         __syncthreads();
     }
-    const uint32_t before_group = t ? sums[t - 1] : 0u;
-    if (before_group <= rank && rank < sums[t]) {
-        uint32_t before = before_group;
-        int d = t * per;
-        while (d < t * per + per - 1 && before + hist[d] <= rank) before += hist[d++];
-        S.found_digit = (uint32_t)d;
-        S.found_before = before;
+    if (act) {
+        const uint32_t before_group = t ? sums[t - 1] : 0u;
+        if (before_group <= rank && rank < sums[t]) {
+            uint32_t before = before_group;
+            int d = t * per;
+            while (d < t * per + per - 1 && before + hist[d] <= rank) before += hist[d++];
+            S.found_digit = (uint32_t)d;
+            S.found_before = before;
+        }
     }
     __syncthreads();
 }
@@ -318,40 +324,23 @@ __device__ __forceinline__ float weight(float tv, float inv_s2) { return __expf(
 // evaluated with the same float operation as the final update kernel.
 __device__ __forceinline__ float stepped(float f, float g, int k, float t) { return k >= 0 ? fmaf(-t, g, f) : f; }
 
-// g = lambda (f - v) + A2 at the current iterate, with the weights at it.
-// When g_prev is given the current iterate is first formed from the previous
-// one, f - t g_prev (the previous step's decision in st_prev), and stored to
-// f_out.  Per-block partials: (Q(f) = sum of w TV over owned edges +
-// lambda/2 (f - v)^2, ||g||^2).
-__device__ __forceinline__ void tv_grad_block(const float* __restrict__ f, const float* __restrict__ g_prev,
-                                              const DevState* st_prev, float* __restrict__ f_out,
-                                              const float* __restrict__ v, int nx, int ny, float lambda,
-                                              const DevState* st, float inv_s2_direct, float eps2,
-                                              float* __restrict__ g, float* wx, float* wy, double* part, int bx,
-                                              int by, int b, int nb, double* lds, const float* wx_in = nullptr,
+// g = lambda (f - v) + A2 at f, with Eq. 5's weights at f (inv_s2 = 1/sigma^2,
+// 0 for sigma = inf) or the given ones; the weights are stored when wx / wy
+// are given.  Per-block partials (Q(f) = sum of w TV over owned edges +
+// lambda/2 (f - v)^2, ||g||^2) when `part` is given.
+__device__ __forceinline__ void tv_grad_block(const float* __restrict__ f, const float* __restrict__ v, int nx, int ny,
+                                              float lambda, float inv_s2, float eps2, float* __restrict__ g,
+                                              float* wx, float* wy, double* part, int bx, int by, int b, int nb,
+                                              double* lds, const float* wx_in = nullptr,
                                               const float* wy_in = nullptr)
 {
-    const float inv_s2 = st ? st->inv_sigma2 : inv_s2_direct;
     const int i = bx * kT + (threadIdx.x & (kT - 1)), j = by * kT + threadIdx.x / kT;
     double q = 0.0, gg = 0.0;
     if (i < nx && j < ny) {
         Nbhd N;
         load_nbhd(f, nx, ny, i, j, N);
-        if (g_prev) {
-            Nbhd G;
-            load_nbhd(g_prev, nx, ny, i, j, G);
-            const int kp = st_prev->k;
-            const float tp = st_prev->t;
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int b = 0; b < 3; ++b) N.n[a][b] = stepped(N.n[a][b], G.n[a][b], kp, tp);
-            // outside pixels stay zero: f and g are both zero there
-            f_out[(size_t)j * nx + i] = N.n[1][1];
-        }
         const float c = N.n[1][1];
         const float tR = tv_right(N, eps2), tL = tv_left(N, eps2), tU = tv_up(N, eps2), tD = tv_down(N, eps2);
-        // Eq. 5's weights, or the caller's (given half-edge weights in place of Eq. 5)
         const size_t xw = (size_t)j * (nx + 1);
         const float wR = wx_in ? wx_in[xw + i + 1] : weight(tR, inv_s2);
         const float wL = wx_in ? wx_in[xw + i] : weight(tL, inv_s2);
@@ -365,10 +354,9 @@ __device__ __forceinline__ void tv_grad_block(const float* __restrict__ f, const
         const float dv = c - v[id];
         const float gv = lambda * dv - (FR - FL) - (FU - FD);
         g[id] = gv;
-        const size_t xo = (size_t)j * (nx + 1);
         if (wx) {
-            wx[xo + i + 1] = wR;
-            if (i == 0) wx[xo] = wL;
+            wx[xw + i + 1] = wR;
+            if (i == 0) wx[xw] = wL;
         }
         if (wy) {
             wy[(size_t)(j + 1) * nx + i] = wU;
@@ -390,29 +378,24 @@ __device__ __forceinline__ void tv_grad_block(const float* __restrict__ f, const
     }
 }
 
-__global__ __launch_bounds__(256) void k_tv_grad(const float* __restrict__ f, const float* __restrict__ g_prev,
-                                                 const DevState* st_prev, float* __restrict__ f_out,
-                                                 const float* __restrict__ v, int nx, int ny, float lambda,
-                                                 const DevState* st, float inv_s2_direct, float eps2,
+__global__ __launch_bounds__(256) void k_tv_grad(const float* __restrict__ f, const float* __restrict__ v, int nx,
+                                                 int ny, float lambda, float inv_s2, float eps2,
                                                  float* __restrict__ g, float* wx, float* wy, double* part,
                                                  const float* wx_in, const float* wy_in)
 {
     __shared__ double lds[4];
-    tv_grad_block(f, g_prev, st_prev, f_out, v, nx, ny, lambda, st, inv_s2_direct, eps2, g, wx, wy, part,
-                  blockIdx.x, blockIdx.y, blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y, lds, wx_in,
-                  wy_in);
+    tv_grad_block(f, v, nx, ny, lambda, inv_s2, eps2, g, wx, wy, part, blockIdx.x, blockIdx.y,
+                  blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y, lds, wx_in, wy_in);
 }
 
-hipError_t launch_tv_grad(const Plan& p, const float* f, const float* g_prev, const DevState* st_prev, float* f_out,
-                          const float* v, float lambda, const DevState* st, float sigma_direct, float eps2, float* g,
-                          float* wx, float* wy, double* part, hipStream_t s, const float* wx_in,
+hipError_t launch_tv_grad(const Plan& p, const float* f, const float* v, float lambda, float sigma, float eps2,
+                          float* g, float* wx, float* wy, double* part, hipStream_t s, const float* wx_in,
                           const float* wy_in)
 {
-    const float inv_s2 = (sigma_direct > 0.0f && std::isfinite(sigma_direct)) ? 1.0f / (sigma_direct * sigma_direct)
-                                                                             : 0.0f;
+    const float inv_s2 = (sigma > 0.0f && std::isfinite(sigma)) ? 1.0f / (sigma * sigma) : 0.0f;
     dim3 grid((p.nx + kT - 1) / kT, (p.ny + kT - 1) / kT);
-    hipLaunchKernelGGL(k_tv_grad, grid, dim3(256), 0, s, f, g_prev, st_prev, f_out, v, p.nx, p.ny, lambda, st, inv_s2,
-                       eps2, g, wx, wy, part, wx_in, wy_in);
+    hipLaunchKernelGGL(k_tv_grad, grid, dim3(256), 0, s, f, v, p.nx, p.ny, lambda, inv_s2, eps2, g, wx, wy, part,
+                       wx_in, wy_in);
     return hipGetLastError();
 }
 
@@ -428,18 +411,29 @@ __device__ __forceinline__ float cand_t(float t0, float shrink, int k)
 
 // Energies Q(f - t_k g) of pixel (i, j)'s share (its own fidelity term and the
 // half-edges it owns) for NC consecutive candidates from k0, with the weights
-// frozen at f.
+// frozen at f: Eq. 5's, recomputed from f with the direction kernel's own
+// operations (so equal to the ones it used), or the given ones.
 template <int NC>
-__device__ __forceinline__ void candidate_energies(const float* f, const float* g, const float* v, const float* wx,
-                                                   const float* wy, int nx, int ny, int i, int j, float lambda,
-                                                   float eps2, float t0, float shrink, int k0, double* e)
+__device__ __forceinline__ void candidate_energies(const float* f, const float* g, const float* v, const float* wx_in,
+                                                   const float* wy_in, float inv_s2, int nx, int ny, int i, int j,
+                                                   float lambda, float eps2, float t0, float shrink, int k0, double* e)
 {
     Nbhd F, G;
     load_nbhd(f, nx, ny, i, j, F);
     load_nbhd(g, nx, ny, i, j, G);
     const size_t xo = (size_t)j * (nx + 1);
-    const float wR = wx[xo + i + 1], wU = wy[(size_t)(j + 1) * nx + i];
-    const float wL = i == 0 ? wx[xo] : 0.0f, wD = j == 0 ? wy[i] : 0.0f;
+    float wR, wU, wL = 0.0f, wD = 0.0f;
+    if (wx_in) {
+        wR = wx_in[xo + i + 1];
+        wU = wy_in[(size_t)(j + 1) * nx + i];
+        if (i == 0) wL = wx_in[xo];
+        if (j == 0) wD = wy_in[i];
+    } else {
+        wR = weight(tv_right(F, eps2), inv_s2);
+        wU = weight(tv_up(F, eps2), inv_s2);
+        if (i == 0) wL = weight(tv_left(F, eps2), inv_s2);
+        if (j == 0) wD = weight(tv_down(F, eps2), inv_s2);
+    }
     const float vv = v[(size_t)j * nx + i];
     float t = cand_t(t0, shrink, k0);
 #pragma unroll
@@ -458,148 +452,351 @@ __device__ __forceinline__ void candidate_energies(const float* f, const float* 
     }
 }
 
-// ------------------------------------------------------------------ one descent step's direction and trials, fused
-// The direction of tv_grad_block and the first kArmijoFirst Armijo trials
-// (candidate_energies) in one pass: the block forms the current iterate on
-// its tile plus a 2-pixel halo in LDS, the direction on the tile plus a
-// 1-pixel halo (halo values recomputed with the same operations as their
-// owning block, so they are bit-identical), and the trial energies of its
-// own pixels from those.  Per-block partials: [Q | ||g||^2][block] and
-// [trial][block], each summed over the block's pixels in a fixed order.
-struct TvArmShared {
-    float f[kT + 4][kT + 4];   // current iterate, tile + 2-pixel halo
-    float g[kT + 2][kT + 2];   // direction, tile + 1-pixel halo
-    float w[4][kT][kT];        // own pixels' weights: right, left, up, down
-    float e[kT][kT];           // own pixels' weighted half-edge sum
-    float dv[kT][kT];          // own pixels' f - v
-    double lds[4];
-    double red[4][kArmijoFirst];
+// ------------------------------------------------------------------ descent steps of P2 (Sec. 2.2)
+// One kernel per descent step, on 32x32 tiles with one thread per own pixel.
+// Step s's kernel
+//  * takes the Armijo decision of step s-1 itself, from that step's per-block
+//    partials: every block sums them in the same fixed order and so reaches
+//    the same decision, and no kernel of its own is launched for it (the
+//    slice's first block records it);
+//  * forms the iterate f_s = f_{s-1} - t g_{s-1} (f_0: the start image) on its
+//    tile plus a 2-pixel halo in LDS, and the direction g_s = lambda (f_s - v)
+//    + A2 (Eq. 9-10, App. II A2-A3) with Eq. 5's weights at f_s on the tile
+//    plus a 1-pixel halo (halo values recomputed with the same operations as
+//    in their owning block, so they are bit-identical);
+//  * writes step s's partials: Q(f_s), ||g_s||^2 and the energies
+//    Q(f_s - t_k g_s) of the first kArmijoFirst candidates with the weights
+//    frozen at f_s, each summed over the block in a fixed order.
+// A last kernel decides step T-1 and applies it, with the positivity
+// truncation (step 3 of the algorithm) and the transposed copy.  The
+// partials are double-buffered by step parity: step s reads step s-1's
+// while writing its own.
+constexpr int kP2Waves = kP2Threads / 64;
+constexpr int kP2Win = kP2T + 4;           // iterate window: 2-pixel halo
+constexpr int kP2Dir = kP2T + 2;           // direction window: 1-pixel halo
+constexpr int kP2Halo = 4 * kP2Dir - 4;    // direction positions on the halo ring
+constexpr int kRedVals = kArmijoMore > kP2Slots ? kArmijoMore : kP2Slots;
+
+int p2_blocks(const Plan& p) { return ((p.nx + kP2T - 1) / kP2T) * ((p.ny + kP2T - 1) / kP2T); }
+int update_tiles(const Plan& p) { return p2_blocks(p); }
+
+// Block sums of NV values per thread over NT threads in a fixed order (each
+// wave's butterfly, then the waves in order), in R.tot for every thread.
+// Contains __syncthreads().
+struct RedShared {
+    double red[kP2Waves][kRedVals];
+    double tot[kRedVals];
+};
+
+template <int NT, int NV>
+__device__ __forceinline__ void block_sums(const double* v, RedShared& R)
+{
+    static_assert(NT % 64 == 0 && NT <= kP2Threads && NV <= kRedVals, "reduction shape");
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+        const double s = wave_sum(v[c]);
+        if (l == 0) R.red[w][c] = s;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < NV) {
+        double a = 0.0;
+#pragma unroll
+        for (int q = 0; q < NT / 64; ++q) a += R.red[q][threadIdx.x];
+        R.tot[threadIdx.x] = a;
+    }
+    __syncthreads();
+}
+
+struct DecShared {
+    RedShared R;
+    double q_acc;  // the energy at the accepted point
+    int verdict;
+};
+
+// Block sums of the kP2Slots values of every thread of a kP2Threads block in a
+// fixed order: the values go to LDS by slot, lane l of wave c sums slot c's
+// entries l, l + 64, ... in order, and wave c's butterfly closes slot c.
+// Results in L.tot for every thread.  Starts and ends with __syncthreads(), so
+// the LDS may alias data the block has finished with.
+struct SlotSums {
+    double v[kP2Slots][kP2Threads];
+    double tot[kP2Slots];
+};
+
+__device__ __forceinline__ void slot_sums(const double* val, SlotSums& L)
+{
+    const int tid = threadIdx.x;
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < kP2Slots; ++c) L.v[c][tid] = val[c];
+    __syncthreads();
+    const int w = tid >> 6, l = tid & 63;
+    if (w < kP2Slots) {
+        double a = 0.0;
+#pragma unroll
+        for (int q = 0; q < kP2Threads / 64; ++q) a += L.v[w][l + 64 * q];
+        a = wave_sum(a);
+        if (l == 0) L.tot[w] = a;
+    }
+    __syncthreads();
+}
+
+struct P2Shared {
+    union {
+        struct {
+            float f[kP2Win][kP2Win];  // the iterate, tile + 2-pixel halo (the final kernel: the transposition tile)
+            float g[kP2Dir][kP2Dir];  // the direction, tile + 1-pixel halo
+        };
+        SlotSums sums;                // the step's partials (the decision's first, before the window is stored)
+    };
+    DecShared dec;
     SelShared sel;
 };
 
-__device__ __forceinline__ void tv_armijo_block(const float* __restrict__ f, const float* __restrict__ g_prev,
-                                                const DevState* st_prev, float* __restrict__ f_out,
-                                                const float* __restrict__ v, int nx, int ny, float lambda,
-                                                const DevState* st, float eps2, float* __restrict__ g, float* wx,
-                                                float* wy, double* part_grad, double* part_arm, float t0,
-                                                float shrink, int bx, int by, int b, int nb, TvArmShared& S,
-                                                const float* wx_in = nullptr, const float* wy_in = nullptr,
-                                                DevState* sel_st = nullptr, const uint32_t* sel_hist = nullptr,
-                                                float sel_floor = 0.0f)
+// The Armijo decision of descent step D.step (Sec. 2.2): the first candidate
+// t_k = t0 shrink^k, k <= max_bt, with Q_k <= Q0 - c t_k ||g||^2, from that
+// step's partials (nb blocks).  Should none of the fused candidates pass
+// while more backtracks are allowed (a reasonable t0 never needs it), the
+// block goes on through the whole image, kArmijoMore candidates at a time
+// (slow, the same decision); without an accepted candidate the step is
+// skipped (k = -1, t = 0).  With D.replay the index is the recorded one.
+// `record`: this block writes the step's records (index, Q0, Q at the
+// accepted point; a replayed index past the fused candidates has its energy
+// evaluated for the record).  f, g: the step's iterate and direction.  A
+// block of kP2Threads threads sums the partials through L (LDS it may share
+// with data it has not stored yet), a narrower one through S.R.
+template <int NT>
+__device__ __forceinline__ void p2_decide(const P2Decide& D, int nb, const DevState* st, bool record,
+                                          const float* f, const float* g, const float* v, const float* wx_in,
+                                          const float* wy_in, float inv_s2, int nx, int ny, float lambda, float eps2,
+                                          DecShared& S, SlotSums* L, int& k_out, float& t_out)
 {
-    const int i0 = bx * kT, j0 = by * kT;
-    const int kp = g_prev ? st_prev->k : -1;
-    const float tp = g_prev ? st_prev->t : 0.0f;
-    // the current iterate on the window (zero outside the image, like pix())
-    constexpr int kWin = (kT + 4) * (kT + 4);
-    auto win_value = [&](int idx) {
-        const int li = idx % (kT + 4), lj = idx / (kT + 4);
-        const int gi = i0 - 2 + li, gj = j0 - 2 + lj;
-        float val = 0.0f;
-        if ((unsigned)gi < (unsigned)nx && (unsigned)gj < (unsigned)ny) {
-            const size_t id = (size_t)gj * nx + gi;
-            val = f[id];
-            if (g_prev) val = stepped(val, g_prev[id], kp, tp);
+    double a[kP2Slots];
+#pragma unroll
+    for (int c = 0; c < kP2Slots; ++c) a[c] = 0.0;
+    for (int b = threadIdx.x; b < nb; b += NT) {
+#pragma unroll
+        for (int c = 0; c < kP2Slots; ++c) a[c] += D.part[(size_t)c * nb + b];
+    }
+    const double* tot;
+    if constexpr (NT == kP2Threads) {
+        slot_sums(a, *L);
+        tot = L->tot;
+    } else {
+        block_sums<NT, kP2Slots>(a, S.R);
+        tot = S.R.tot;
+    }
+    const double q0 = tot[0], g2 = tot[1];
+    const size_t rec = (size_t)st->iter * D.T + D.step;
+    if (threadIdx.x < 64) {
+        // candidate k tested by lane k; the first that passes is accepted
+        const int k = threadIdx.x;
+        const bool pass = !D.replay && k < kArmijoFirst && k <= D.max_bt &&
+                          tot[2 + (k < kArmijoFirst ? k : 0)] <=
+                              q0 - D.c_arm * (double)cand_t(D.t0, D.shrink, k < kArmijoFirst ? k : 0) * g2;
+        const unsigned long long mask = __ballot(pass);
+        if (threadIdx.x == 0) {
+            // the caller's decision for this step (-1: no step), or the search's
+            const int kk = D.replay ? D.st_k[rec] : (mask ? __ffsll((long long)mask) - 1 : -1);
+            S.verdict = kk;
+            S.q_acc = kk < 0 ? q0 : (kk < kArmijoFirst ? tot[2 + kk] : 0.0);
         }
-        return val;
-    };
+    }
+    __syncthreads();
+    int kk = S.verdict;
+    if (D.replay && kk >= kArmijoFirst && record) {
+        double e[kArmijoMore];
+#pragma unroll
+        for (int c = 0; c < kArmijoMore; ++c) e[c] = 0.0;
+        for (int px = threadIdx.x; px < nx * ny; px += NT)
+            candidate_energies<kArmijoMore>(f, g, v, wx_in, wy_in, inv_s2, nx, ny, px % nx, px / nx, lambda, eps2,
+                                            D.t0, D.shrink, kk, e);
+        block_sums<NT, kArmijoMore>(e, S.R);
+        if (threadIdx.x == 0) S.q_acc = S.R.tot[0];
+        __syncthreads();
+    }
+    for (int k0 = kArmijoFirst; !D.replay && kk < 0 && k0 <= D.max_bt; k0 += kArmijoMore) {
+        double e[kArmijoMore];
+#pragma unroll
+        for (int c = 0; c < kArmijoMore; ++c) e[c] = 0.0;
+        for (int px = threadIdx.x; px < nx * ny; px += NT)
+            candidate_energies<kArmijoMore>(f, g, v, wx_in, wy_in, inv_s2, nx, ny, px % nx, px / nx, lambda, eps2,
+                                            D.t0, D.shrink, k0, e);
+        block_sums<NT, kArmijoMore>(e, S.R);
+        if (threadIdx.x == 0) {
+            int found = -1;
+            for (int c = 0; c < kArmijoMore && k0 + c <= D.max_bt; ++c)
+                if (S.R.tot[c] <= q0 - D.c_arm * (double)cand_t(D.t0, D.shrink, k0 + c) * g2) {
+                    found = k0 + c;
+                    S.q_acc = S.R.tot[c];
+                    break;
+                }
+            S.verdict = found;
+        }
+        __syncthreads();
+        kk = S.verdict;
+    }
+    if (record && threadIdx.x == 0) {
+        if (D.st_k) D.st_k[rec] = kk;
+        if (D.st_q0) D.st_q0[rec] = q0;
+        if (D.st_q1) D.st_q1[rec] = S.q_acc;
+    }
+    k_out = kk;
+    t_out = kk >= 0 ? cand_t(D.t0, D.shrink, kk) : 0.0f;
+    __syncthreads();
+}
+
+// The direction g at window position (li, lj) of the 1-pixel-halo window
+// (pixel (i0 - 1 + li, j0 - 1 + lj)), from the iterate window in LDS: Eq. A3's
+// magnitudes of the pixel's four half-edges, Eq. 5's weights (or the given
+// ones), the A2 fluxes and lambda (f - v).
+struct DirOut {
+    float g, wR, wL, wU, wD, tR, tL, tU, tD, dv;
+};
+
+__device__ __forceinline__ DirOut p2_direction_at(const P2Shared& S, int li, int lj, int gi, int gj, int nx,
+                                                  const float* __restrict__ v, float lambda, float eps2,
+                                                  float inv_s2, const float* wx_in, const float* wy_in)
+{
+    Nbhd N;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb) N.n[a][bb] = S.f[lj + bb][li + a];
+    DirOut o;
+    const float c = N.n[1][1];
+    o.tR = tv_right(N, eps2);
+    o.tL = tv_left(N, eps2);
+    o.tU = tv_up(N, eps2);
+    o.tD = tv_down(N, eps2);
+    const size_t xw = (size_t)gj * (nx + 1);
+    o.wR = wx_in ? wx_in[xw + gi + 1] : weight(o.tR, inv_s2);
+    o.wL = wx_in ? wx_in[xw + gi] : weight(o.tL, inv_s2);
+    o.wU = wy_in ? wy_in[(size_t)(gj + 1) * nx + gi] : weight(o.tU, inv_s2);
+    o.wD = wy_in ? wy_in[(size_t)gj * nx + gi] : weight(o.tD, inv_s2);
+    const float FR = o.wR * (N.n[2][1] - c) * hw_rcp(o.tR);
+    const float FL = o.wL * (c - N.n[0][1]) * hw_rcp(o.tL);
+    const float FU = o.wU * (N.n[1][2] - c) * hw_rcp(o.tU);
+    const float FD = o.wD * (c - N.n[1][0]) * hw_rcp(o.tD);
+    o.dv = c - v[(size_t)gj * nx + gi];
+    o.g = lambda * o.dv - (FR - FL) - (FU - FD);
+    return o;
+}
+
+// Descent step `step` on tile (bx, by) = block b of nb (see above); with D.part
+// null the previous step's decision is read from st (a batch decides each
+// slice's step in a kernel of its own, one block per slice).  f: the
+// previous iterate f_{s-1} (g_prev its direction, null for step 0, when f is
+// the start image); f_out receives f_s for s > 0.  sel_hist: the first step of
+// an adaptive iteration closes sigma's last digit from that histogram (the
+// same computation in every block; block 0 records it), else sigma is st's.
+__device__ __forceinline__ void p2_step_block(const float* __restrict__ f, const float* __restrict__ g_prev,
+                                              float* __restrict__ f_out, const float* __restrict__ v, int nx, int ny,
+                                              float lambda, DevState* st, float eps2, float* __restrict__ g,
+                                              double* part, float t0, float shrink, int bx, int by, int b, int nb,
+                                              P2Shared& S, const float* wx_in, const float* wy_in,
+                                              const uint32_t* sel_hist, float sel_floor, const P2Decide& D)
+{
+    const int tid = threadIdx.x;
+    const int i0 = bx * kP2T, j0 = by * kP2T;
+    constexpr int kWin = kP2Win * kP2Win;
+    constexpr int kWinPer = (kWin + kP2Threads - 1) / kP2Threads;
+    // the window's loads first, so they overlap sigma's digit and the decision
+    float fv[kWinPer], gv[kWinPer];
+#pragma unroll
+    for (int u = 0; u < kWinPer; ++u) {
+        const int idx = tid + kP2Threads * u;
+        fv[u] = 0.0f;
+        gv[u] = 0.0f;
+        if (idx < kWin) {
+            const int gi = i0 - 2 + idx % kP2Win, gj = j0 - 2 + idx / kP2Win;
+            if ((unsigned)gi < (unsigned)nx && (unsigned)gj < (unsigned)ny) {
+                const size_t id = (size_t)gj * nx + gi;
+                fv[u] = f[id];
+                if (g_prev) gv[u] = g_prev[id];
+            }
+        }
+    }
     float inv_s2;
     if (sel_hist) {
-        // sigma: the first descent step of an adaptive iteration closes the
-        // selection's last digit itself (the same computation in every block,
-        // as k_select_sigma would do it; block 0 records it for the later
-        // steps), with the window's loads issued first so that they overlap it
-        constexpr int kWinPer = (kWin + 255) / 256;
-        float fv[kWinPer];
-#pragma unroll
-        for (int u = 0; u < kWinPer; ++u) {
-            const int idx = threadIdx.x + 256 * u;
-            fv[u] = idx < kWin ? win_value(idx) : 0.0f;
-        }
-        const uint32_t rin = sel_st->sel_rank[1];
+        const uint32_t rin = st->sel_rank[1];
         select_digit(sel_hist, 2, rin, S.sel);
-        const uint32_t prefix = sel_st->sel_prefix[1] | S.sel.found_digit;
+        const uint32_t prefix = st->sel_prefix[1] | S.sel.found_digit;
         const float sg = fmaxf(__uint_as_float(prefix), sel_floor);
         inv_s2 = 1.0f / (sg * sg);
-        if (b == 0 && threadIdx.x == 0) {
-            sel_st->prefix = prefix;
-            sel_st->rank = rin - S.sel.found_before;
-            sel_st->sigma = sg;
-            sel_st->inv_sigma2 = inv_s2;
-        }
-#pragma unroll
-        for (int u = 0; u < kWinPer; ++u) {
-            const int idx = threadIdx.x + 256 * u;
-            if (idx < kWin) S.f[idx / (kT + 4)][idx % (kT + 4)] = fv[u];
+        if (b == 0 && tid == 0) {
+            st->prefix = prefix;
+            st->rank = rin - S.sel.found_before;
+            st->sigma = sg;
+            st->inv_sigma2 = inv_s2;
         }
     } else {
         inv_s2 = st->inv_sigma2;
-        for (int idx = threadIdx.x; idx < kWin; idx += 256) S.f[idx / (kT + 4)][idx % (kT + 4)] = win_value(idx);
+    }
+    int kp = -1;
+    float tp = 0.0f;
+    if (g_prev) {
+        if (D.part) {
+            p2_decide<kP2Threads>(D, nb, st, b == 0, f, g_prev, v, wx_in, wy_in, inv_s2, nx, ny, lambda, eps2, S.dec,
+                                  &S.sums, kp, tp);
+        } else {  // taken by a kernel of its own
+            kp = st->k;
+            tp = st->t;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kWinPer; ++u) {
+        const int idx = tid + kP2Threads * u;
+        if (idx < kWin) S.f[idx / kP2Win][idx % kP2Win] = g_prev ? stepped(fv[u], gv[u], kp, tp) : fv[u];
     }
     __syncthreads();
-    const int ti = threadIdx.x & (kT - 1), tj = threadIdx.x / kT;
+    const int ti = tid & (kP2T - 1), tj = tid / kP2T;
     const int i = i0 + ti, j = j0 + tj;
     const bool own = i < nx && j < ny;
-    if (g_prev && own) f_out[(size_t)j * nx + i] = S.f[tj + 2][ti + 2];
-    // the direction on the tile and its 1-pixel halo
-    for (int idx = threadIdx.x; idx < (kT + 2) * (kT + 2); idx += 256) {
-        const int li = idx % (kT + 2), lj = idx / (kT + 2);
-        const int gi = i0 - 1 + li, gj = j0 - 1 + lj;
-        float gv = 0.0f;
-        if ((unsigned)gi < (unsigned)nx && (unsigned)gj < (unsigned)ny) {
-            Nbhd N;
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int bb = 0; bb < 3; ++bb) N.n[a][bb] = S.f[lj + bb][li + a];
-            const float c = N.n[1][1];
-            const float tR = tv_right(N, eps2), tL = tv_left(N, eps2), tU = tv_up(N, eps2), tD = tv_down(N, eps2);
-            const size_t xw = (size_t)gj * (nx + 1);
-            const float wR = wx_in ? wx_in[xw + gi + 1] : weight(tR, inv_s2);
-            const float wL = wx_in ? wx_in[xw + gi] : weight(tL, inv_s2);
-            const float wU = wy_in ? wy_in[(size_t)(gj + 1) * nx + gi] : weight(tU, inv_s2);
-            const float wD = wy_in ? wy_in[(size_t)gj * nx + gi] : weight(tD, inv_s2);
-            const float FR = wR * (N.n[2][1] - c) * hw_rcp(tR);
-            const float FL = wL * (c - N.n[0][1]) * hw_rcp(tL);
-            const float FU = wU * (N.n[1][2] - c) * hw_rcp(tU);
-            const float FD = wD * (c - N.n[1][0]) * hw_rcp(tD);
-            const size_t id = (size_t)gj * nx + gi;
-            const float dv = c - v[id];
-            gv = lambda * dv - (FR - FL) - (FU - FD);
-            if (li >= 1 && li <= kT && lj >= 1 && lj <= kT) {  // an own pixel
-                g[id] = gv;
-                if (wx) {
-                    wx[xw + gi + 1] = wR;
-                    if (gi == 0) wx[xw] = wL;
-                }
-                if (wy) {
-                    wy[(size_t)(gj + 1) * nx + gi] = wU;
-                    if (gj == 0) wy[gi] = wD;
-                }
-                float e = wR * tR + wU * tU;
-                if (gi == 0) e += wL * tL;
-                if (gj == 0) e += wD * tD;
-                S.w[0][lj - 1][li - 1] = wR;
-                S.w[1][lj - 1][li - 1] = wL;
-                S.w[2][lj - 1][li - 1] = wU;
-                S.w[3][lj - 1][li - 1] = wD;
-                S.e[lj - 1][li - 1] = e;
-                S.dv[lj - 1][li - 1] = dv;
-            }
+    // the own pixel's direction (its weights and terms kept for the trials)
+    DirOut o{};
+    if (own) {
+        o = p2_direction_at(S, ti + 1, tj + 1, i, j, nx, v, lambda, eps2, inv_s2, wx_in, wy_in);
+        const size_t id = (size_t)j * nx + i;
+        g[id] = o.g;
+        if (g_prev) f_out[id] = S.f[tj + 2][ti + 2];
+    }
+    S.g[tj + 1][ti + 1] = own ? o.g : 0.0f;
+    // the halo ring of the direction window
+    if (tid < kP2Halo) {
+        int li, lj;
+        if (tid < kP2Dir) {
+            li = tid;
+            lj = 0;
+        } else if (tid < 2 * kP2Dir) {
+            li = tid - kP2Dir;
+            lj = kP2Dir - 1;
+        } else if (tid < 2 * kP2Dir + kP2T) {
+            li = 0;
+            lj = tid - 2 * kP2Dir + 1;
+        } else {
+            li = kP2Dir - 1;
+            lj = tid - 2 * kP2Dir - kP2T + 1;
         }
-        S.g[lj][li] = gv;
+        const int gi = i0 - 1 + li, gj = j0 - 1 + lj;
+        float gh = 0.0f;
+        if ((unsigned)gi < (unsigned)nx && (unsigned)gj < (unsigned)ny)
+            gh = p2_direction_at(S, li, lj, gi, gj, nx, v, lambda, eps2, inv_s2, wx_in, wy_in).g;
+        S.g[lj][li] = gh;
     }
     __syncthreads();
-    // the partials of the direction kernel, in its thread order
-    double q = 0.0, gg = 0.0;
-    double en[kArmijoFirst];
+    // this step's partials: Q(f_s), ||g_s||^2 and the trial energies, the
+    // trials as candidate_energies with the weights frozen at f_s
+    double val[kP2Slots];
 #pragma unroll
-    for (int c = 0; c < kArmijoFirst; ++c) en[c] = 0.0;
+    for (int c = 0; c < kP2Slots; ++c) val[c] = 0.0;
     if (own) {
-        const float dv = S.dv[tj][ti], gv = S.g[tj + 1][ti + 1];
-        q = (double)S.e[tj][ti] + 0.5 * (double)lambda * (double)dv * (double)dv;
-        gg = (double)gv * (double)gv;
-        // the trial energies, as candidate_energies with the weights frozen at f
+        float e = o.wR * o.tR + o.wU * o.tU;
+        if (i == 0) e += o.wL * o.tL;
+        if (j == 0) e += o.wD * o.tD;
+        val[0] = (double)e + 0.5 * (double)lambda * (double)o.dv * (double)o.dv;
+        val[1] = (double)o.g * (double)o.g;
         Nbhd F, G;
 #pragma unroll
         for (int a = 0; a < 3; ++a)
@@ -608,9 +805,8 @@ __device__ __forceinline__ void tv_armijo_block(const float* __restrict__ f, con
                 F.n[a][bb] = S.f[tj + 1 + bb][ti + 1 + a];
                 G.n[a][bb] = S.g[tj + bb][ti + a];
             }
-        const float wR = S.w[0][tj][ti], wU = S.w[2][tj][ti];
-        const float wL = i == 0 ? S.w[1][tj][ti] : 0.0f, wD = j == 0 ? S.w[3][tj][ti] : 0.0f;
-        const float vv = v[(size_t)j * nx + i];
+        const float wL = i == 0 ? o.wL : 0.0f, wD = j == 0 ? o.wD : 0.0f;
+        const float vpix = v[(size_t)j * nx + i];
         float t = t0;
 #pragma unroll
         for (int c = 0; c < kArmijoFirst; ++c) {
@@ -619,294 +815,111 @@ __device__ __forceinline__ void tv_armijo_block(const float* __restrict__ f, con
             for (int a = 0; a < 3; ++a)
 #pragma unroll
                 for (int bb = 0; bb < 3; ++bb) H.n[a][bb] = fmaf(-t, G.n[a][bb], F.n[a][bb]);
-            float sm = wR * tv_right(H, eps2) + wU * tv_up(H, eps2);
+            float sm = o.wR * tv_right(H, eps2) + o.wU * tv_up(H, eps2);
             if (i == 0) sm += wL * tv_left(H, eps2);
             if (j == 0) sm += wD * tv_down(H, eps2);
-            const float d = H.n[1][1] - vv;
-            en[c] += (double)sm + 0.5 * (double)lambda * (double)d * (double)d;
+            const float d = H.n[1][1] - vpix;
+            val[2 + c] = (double)sm + 0.5 * (double)lambda * (double)d * (double)d;
             t *= shrink;
         }
     }
-    const double qs = block_sum<256>(q, S.lds);
-    const double gs = block_sum<256>(gg, S.lds);
-    if (threadIdx.x == 0) {  // slot-major: [Q | ||g||^2][block]
-        part_grad[b] = qs;
-        part_grad[nb + b] = gs;
-    }
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-#pragma unroll
-    for (int c = 0; c < kArmijoFirst; ++c) {
-        const double sc = wave_sum(en[c]);
-        if (l == 0) S.red[w][c] = sc;
-    }
-    __syncthreads();
-    if (threadIdx.x < kArmijoFirst) {
-        const int c = threadIdx.x;
-        part_arm[(size_t)c * nb + b] = S.red[0][c] + S.red[1][c] + S.red[2][c] + S.red[3][c];
-    }
+    slot_sums(val, S.sums);
+    if (tid < kP2Slots) part[(size_t)tid * nb + b] = S.sums.tot[tid];
 }
 
-__global__ __launch_bounds__(256) void k_tv_armijo(const float* __restrict__ f, const float* __restrict__ g_prev,
-                                                   const DevState* st_prev, float* __restrict__ f_out,
-                                                   const float* __restrict__ v, int nx, int ny, float lambda,
-                                                   const DevState* st, float eps2, float* __restrict__ g, float* wx,
-                                                   float* wy, double* part_grad, double* part_arm, float t0,
-                                                   float shrink, const float* wx_in, const float* wy_in,
-                                                   DevState* sel_st, const uint32_t* sel_hist, float sel_floor)
+// The last descent step's decision and update: f_out = f - t g (f unchanged
+// when the step was skipped), truncated at zero with `clamp`, its transposed
+// copy (foutT, for the projector) and, with a reference, the squared error of
+// the tile's new pixels (part_rmse[b], for the iteration's RMSE record).
+__device__ __forceinline__ void p2_final_block(const float* __restrict__ fcur, const float* __restrict__ g,
+                                               float* fout, float* foutT, int clamp, const float* ref,
+                                               double* part_rmse, const float* __restrict__ v, int nx, int ny,
+                                               float lambda, const DevState* st, float eps2, int bx, int by, int b,
+                                               int nb, P2Shared& S, const float* wx_in, const float* wy_in,
+                                               const P2Decide& D)
 {
-    __shared__ TvArmShared S;
-    tv_armijo_block(f, g_prev, st_prev, f_out, v, nx, ny, lambda, st, eps2, g, wx, wy, part_grad, part_arm, t0,
-                    shrink, blockIdx.x, blockIdx.y, blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y, S,
-                    wx_in, wy_in, sel_st, sel_hist, sel_floor);
-}
-
-hipError_t launch_tv_armijo(const Plan& p, const float* f, const float* g_prev, const DevState* st_prev,
-                            float* f_out, const float* v, float lambda, const DevState* st, float eps2, float* g,
-                            float* wx, float* wy, double* part_grad, double* part_arm, float t0, float shrink,
-                            hipStream_t s, const float* wx_in, const float* wy_in, DevState* sel_st,
-                            const uint32_t* sel_hist, float sel_floor)
-{
-    dim3 grid((p.nx + kT - 1) / kT, (p.ny + kT - 1) / kT);
-    hipLaunchKernelGGL(k_tv_armijo, grid, dim3(256), 0, s, f, g_prev, st_prev, f_out, v, p.nx, p.ny, lambda, st,
-                       eps2, g, wx, wy, part_grad, part_arm, t0, shrink, wx_in, wy_in, sel_st, sel_hist, sel_floor);
-    return hipGetLastError();
-}
-
-int armijo_blocks(const Plan& p) { return ((p.nx + kT - 1) / kT) * ((p.ny + kT - 1) / kT); }
-
-
-// The Armijo decision: the first candidate with Q_k <= Q0 - c t_k ||g||^2.
-// One block of 256 threads closes Q0, ||g||^2 (gradient kernel's partials)
-// and the first kArmijoFirst candidate energies (Armijo kernel's partials):
-// thread t sums blocks t, t + 256, ... of every slot in order, the per-thread
-// sums go through LDS, and each wave reduces a few slots with a fixed
-// butterfly.  Should none of the first candidates pass while more backtracks
-// are allowed (which a reasonable first step t0 never needs), this block goes
-// on alone through the image, kArmijoMore candidates at a time: slow, but the
-// decision is the same.  Without an accepted candidate the step is skipped
-// (k = -1, t = 0).  The accepted index is recorded for the iteration.
-constexpr int kDecThreads = 256;
-constexpr int kDecVals = kArmijoMore + 2;
-
-template <int NV>
-__device__ __forceinline__ void decide_reduce(double* v, double (*red)[kDecThreads], double* tot)
-{
-    // v[0..NV) per thread -> tot[0..NV) block sums, fixed order
-#pragma unroll
-    for (int c = 0; c < NV; ++c) red[c][threadIdx.x] = v[c];
-    __syncthreads();
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    for (int c = w; c < NV; c += kDecThreads / 64) {
-        double a = 0.0;
-        for (int q = l; q < kDecThreads; q += 64) a += red[c][q];
-        a = wave_sum(a);
-        if (l == 0) tot[c] = a;
+    const int tid = threadIdx.x;
+    const int ti = tid & (kP2T - 1), tj = tid / kP2T;
+    const int i0 = bx * kP2T, j0 = by * kP2T;
+    const int i = i0 + ti, j = j0 + tj;
+    const bool own = i < nx && j < ny;
+    const size_t id = (size_t)j * nx + i;
+    float fv = 0.0f, gv = 0.0f, rv = 0.0f;
+    if (own) {
+        fv = fcur[id];
+        gv = g[id];
+        if (ref) rv = ref[id];
     }
-    __syncthreads();
-}
-
-struct DecShared {
-    double red[kDecVals][kDecThreads];
-    double tot[kDecVals];
-    double q_acc;  // the energy at the accepted point
-    int verdict;
-};
-
-__device__ __forceinline__ void armijo_decide_block(DevState* st, const double* part_grad, const double* part_arm,
-                                                    int nb, int max_bt, double c_arm, float t0, float shrink,
-                                                    int32_t* st_k, double* st_q0, double* st_q1, int step, int T,
-                                                    const float* f, const float* g, const float* v, const float* wx,
-                                                    const float* wy, int nx, int ny, float lambda, float eps2,
-                                                    DecShared& S, int replay = 0)
-{
-    double (*red)[kDecThreads] = S.red;
-    double* tot = S.tot;
-    int& verdict = S.verdict;
-    double a[kArmijoFirst + 2];
-#pragma unroll
-    for (int c = 0; c < kArmijoFirst + 2; ++c) a[c] = 0.0;
-    // four blocks per thread at a time, all their loads issued before the sums
-    // (the same order of additions as one block at a time)
-    constexpr int kDecRounds = 4;
-    for (int b0 = threadIdx.x; b0 < nb; b0 += kDecRounds * kDecThreads) {
-        double v[kDecRounds][kArmijoFirst + 2];
-#pragma unroll
-        for (int r = 0; r < kDecRounds; ++r) {
-            const int b = b0 + r * kDecThreads;
-#pragma unroll
-            for (int c = 0; c < kArmijoFirst; ++c) v[r][c] = b < nb ? part_arm[(size_t)c * nb + b] : 0.0;
-            v[r][kArmijoFirst] = b < nb ? part_grad[b] : 0.0;
-            v[r][kArmijoFirst + 1] = b < nb ? part_grad[nb + b] : 0.0;
-        }
-#pragma unroll
-        for (int r = 0; r < kDecRounds; ++r)
-#pragma unroll
-            for (int c = 0; c < kArmijoFirst + 2; ++c) a[c] += v[r][c];
-    }
-    decide_reduce<kArmijoFirst + 2>(a, red, tot);
-    const double q0 = tot[kArmijoFirst], g2 = tot[kArmijoFirst + 1];
-    if (threadIdx.x == 0) {
-        int kk = -1;
-        if (replay) {  // the caller's decision, recorded for this step (-1: no step)
-            kk = st_k[(size_t)st->iter * T + step];
-        } else {
-            for (int k = 0; k < kArmijoFirst && k <= max_bt; ++k)
-                if (tot[k] <= q0 - c_arm * (double)cand_t(t0, shrink, k) * g2) {
-                    kk = k;
-                    break;
-                }
-        }
-        verdict = kk;
-        // the energy at the accepted point (the start's when none; later
-        // candidates are filled in below)
-        S.q_acc = kk < 0 ? q0 : (kk < kArmijoFirst ? tot[kk] : 0.0);
-    }
-    __syncthreads();
-    int kk = verdict;
-    if (replay && kk >= kArmijoFirst) {
-        // a given index beyond the fused trials: evaluate that candidate (the
-        // sums in the order the search below would form them)
-        double e[kArmijoMore];
-#pragma unroll
-        for (int c = 0; c < kArmijoMore; ++c) e[c] = 0.0;
-        for (int px = threadIdx.x; px < nx * ny; px += kDecThreads)
-            candidate_energies<kArmijoMore>(f, g, v, wx, wy, nx, ny, px % nx, px / nx, lambda, eps2, t0, shrink, kk,
-                                            e);
-        decide_reduce<kArmijoMore>(e, red, tot);
-        if (threadIdx.x == 0) S.q_acc = tot[0];
-        __syncthreads();
-    }
-    // rare: continue the backtracking over the whole image in this block
-    for (int k0 = kArmijoFirst; !replay && kk < 0 && k0 <= max_bt; k0 += kArmijoMore) {
-        double e[kArmijoMore];
-#pragma unroll
-        for (int c = 0; c < kArmijoMore; ++c) e[c] = 0.0;
-        for (int px = threadIdx.x; px < nx * ny; px += kDecThreads)
-            candidate_energies<kArmijoMore>(f, g, v, wx, wy, nx, ny, px % nx, px / nx, lambda, eps2, t0, shrink, k0,
-                                            e);
-        decide_reduce<kArmijoMore>(e, red, tot);
-        if (threadIdx.x == 0) {
-            int found = -1;
-            for (int c = 0; c < kArmijoMore && k0 + c <= max_bt; ++c)
-                if (tot[c] <= q0 - c_arm * (double)cand_t(t0, shrink, k0 + c) * g2) {
-                    found = k0 + c;
-                    S.q_acc = tot[c];
-                    break;
-                }
-            verdict = found;
-        }
-        __syncthreads();
-        kk = verdict;
-    }
-    if (threadIdx.x == 0) {
-        st->q0 = q0;
-        st->gg = g2;
-        st->k = kk;
-        st->t = kk >= 0 ? cand_t(t0, shrink, kk) : 0.0f;
-        const size_t rec = (size_t)st->iter * T + step;
-        if (st_k) st_k[rec] = kk;
-        if (st_q0) st_q0[rec] = q0;
-        if (st_q1) st_q1[rec] = S.q_acc;
-    }
-}
-
-__global__ __launch_bounds__(kDecThreads) void k_armijo_decide(DevState* st, const double* part_grad,
-                                                               const double* part_arm, int nb, int max_bt,
-                                                               double c_arm, float t0, float shrink, int32_t* st_k,
-                                                               double* st_q0, double* st_q1, int step, int T,
-                                                               const float* f, const float* g, const float* v,
-                                                               const float* wx, const float* wy, int nx, int ny,
-                                                               float lambda, float eps2, int replay)
-{
-    __shared__ DecShared S;
-    armijo_decide_block(st, part_grad, part_arm, nb, max_bt, c_arm, t0, shrink, st_k, st_q0, st_q1, step, T, f, g, v,
-                        wx, wy, nx, ny, lambda, eps2, S, replay);
-}
-
-hipError_t launch_armijo_decide(const Plan& p, DevState* st, const double* part_grad, const double* part_arm,
-                                int max_bt, double c_arm, float t0, float shrink, int32_t* st_k, double* st_q0,
-                                double* st_q1, int step, int T, const float* f, const float* g, const float* v,
-                                const float* wx, const float* wy, float lambda, float eps2, hipStream_t s,
-                                int replay)
-{
-    hipLaunchKernelGGL(k_armijo_decide, dim3(1), dim3(kDecThreads), 0, s, st, part_grad, part_arm, armijo_blocks(p),
-                       max_bt, c_arm, t0, shrink, st_k, st_q0, st_q1, step, T, f, g, v, wx, wy, p.nx, p.ny, lambda,
-                       eps2, replay && st_k ? 1 : 0);
-    return hipGetLastError();
-}
-
-// f_out = f - t g (unchanged when no step was accepted), optional truncation at
-// zero (step 3 of the algorithm) and optional transposed copy for the projector.
-__device__ __forceinline__ void p2_update_block(const DevState* st, const float* fcur, const float* __restrict__ g,
-                                                float* fout, float* foutT, int clamp, int nx, int ny, int tbx,
-                                                int tby, float (*tl)[33])
-{
-    const int k = st->k;
-    const float t = st->t;
-    const int bx = tbx * 32, by = tby * 32;
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    for (int r = ty; r < 32; r += 8) {
-        const int i = bx + tx, j = by + r;
-        float val = 0.0f;
-        if (i < nx && j < ny) {
-            const size_t id = (size_t)j * nx + i;
-            val = stepped(fcur[id], g[id], k, t);
-            if (clamp) val = fmaxf(val, 0.0f);
-            fout[id] = val;
-        }
-        tl[r][tx] = val;
+    int k = st->k;
+    float t = st->t;
+    if (D.part)
+        p2_decide<kP2Threads>(D, nb, st, b == 0, fcur, g, v, wx_in, wy_in, st->inv_sigma2, nx, ny, lambda, eps2,
+                              S.dec, &S.sums, k, t);
+    float val = 0.0f;
+    if (own) {
+        val = stepped(fv, gv, k, t);
+        if (clamp) val = fmaxf(val, 0.0f);
+        fout[id] = val;
     }
     if (foutT) {
+        S.f[tj][ti] = val;
         __syncthreads();
-        for (int r = ty; r < 32; r += 8) {
-            const int i = bx + r, j = by + tx;
-            if (i < nx && j < ny) foutT[(size_t)i * ny + j] = tl[tx][r];
-        }
+        const int it = i0 + tj, jt = j0 + ti;
+        if (it < nx && jt < ny) foutT[(size_t)it * ny + jt] = S.f[ti][tj];
     }
-}
-
-// Squared error to ref over the pixels of 32 x 32 update tile (tbx, tby), in
-// the order p2_update_block writes them (thread (tx, ty): rows ty, ty + 8, ...),
-// summed over the block (valid in all threads).  Contains __syncthreads().
-__device__ __forceinline__ double update_tile_sq_err(const float* fout, const float* ref, int nx, int ny, int tbx,
-                                                     int tby, double* lds)
-{
-    const int i = tbx * 32 + (threadIdx.x & 31);
-    double e2 = 0.0;
-    for (int r = threadIdx.x >> 5; r < 32; r += 8) {
-        const int j = tby * 32 + r;
-        if (i < nx && j < ny) {
-            const double d = (double)fout[(size_t)j * nx + i] - (double)ref[(size_t)j * nx + i];
-            e2 += d * d;
-        }
-    }
-    return block_sum<256>(e2, lds);
-}
-
-// With a reference, each block also writes the squared error of its new
-// pixels (one partial per 32 x 32 tile) for the iteration's RMSE record, so
-// that needs no kernel of its own.
-__global__ __launch_bounds__(256) void k_p2_update(const DevState* st, const float* fcur, const float* __restrict__ g,
-                                                   float* fout, float* foutT, int clamp, int nx, int ny,
-                                                   const float* ref, double* part_rmse)
-{
-    __shared__ float tl[32][33];
-    __shared__ double lds[4];
-    p2_update_block(st, fcur, g, fout, foutT, clamp, nx, ny, blockIdx.x, blockIdx.y, tl);
     if (ref) {
-        const double e2 = update_tile_sq_err(fout, ref, nx, ny, blockIdx.x, blockIdx.y, lds);
-        if (threadIdx.x == 0) part_rmse[blockIdx.y * gridDim.x + blockIdx.x] = e2;
+        double e2[1] = {0.0};
+        if (own) {
+            const double d = (double)val - (double)rv;
+            e2[0] = d * d;
+        }
+        block_sums<kP2Threads, 1>(e2, S.dec.R);
+        if (tid == 0) part_rmse[b] = S.dec.R.tot[0];
     }
 }
 
-int update_tiles(const Plan& p) { return ((p.nx + 31) / 32) * ((p.ny + 31) / 32); }
-
-hipError_t launch_p2_update(const Plan& p, const DevState* st, const float* fcur, const float* g, float* fout,
-                            float* foutT, int clamp, hipStream_t s, const float* ref, double* part_rmse)
+__global__ __launch_bounds__(kP2Threads) void k_p2_step(const float* __restrict__ f, const float* __restrict__ g_prev,
+                                                        float* __restrict__ f_out, const float* __restrict__ v,
+                                                        int nx, int ny, float lambda, DevState* st, float eps2,
+                                                        float* __restrict__ g, double* part, float t0, float shrink,
+                                                        const float* wx_in, const float* wy_in,
+                                                        const uint32_t* sel_hist, float sel_floor, P2Decide D)
 {
-    dim3 grid((p.nx + 31) / 32, (p.ny + 31) / 32);
-    hipLaunchKernelGGL(k_p2_update, grid, dim3(256), 0, s, st, fcur, g, fout, foutT, clamp, p.nx, p.ny, ref,
-                       part_rmse);
+    __shared__ P2Shared S;
+    p2_step_block(f, g_prev, f_out, v, nx, ny, lambda, st, eps2, g, part, t0, shrink, blockIdx.x, blockIdx.y,
+                  blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y, S, wx_in, wy_in, sel_hist, sel_floor,
+                  D);
+}
+
+hipError_t launch_p2_step(const Plan& p, const float* f, const float* g_prev, float* f_out, const float* v,
+                          float lambda, DevState* st, float eps2, float* g, double* part, float t0, float shrink,
+                          const float* wx_in, const float* wy_in, const uint32_t* sel_hist, float sel_floor,
+                          const P2Decide& D, hipStream_t s)
+{
+    dim3 grid((p.nx + kP2T - 1) / kP2T, (p.ny + kP2T - 1) / kP2T);
+    hipLaunchKernelGGL(k_p2_step, grid, dim3(kP2Threads), 0, s, f, g_prev, f_out, v, p.nx, p.ny, lambda, st, eps2, g,
+                       part, t0, shrink, wx_in, wy_in, sel_hist, sel_floor, D);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kP2Threads) void k_p2_final(const float* __restrict__ fcur, const float* __restrict__ g,
+                                                         float* fout, float* foutT, int clamp, const float* ref,
+                                                         double* part_rmse, const float* __restrict__ v, int nx,
+                                                         int ny, float lambda, const DevState* st, float eps2,
+                                                         const float* wx_in, const float* wy_in, P2Decide D)
+{
+    __shared__ P2Shared S;
+    p2_final_block(fcur, g, fout, foutT, clamp, ref, part_rmse, v, nx, ny, lambda, st, eps2, blockIdx.x, blockIdx.y,
+                   blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y, S, wx_in, wy_in, D);
+}
+
+hipError_t launch_p2_final(const Plan& p, const float* fcur, const float* g, float* fout, float* foutT, int clamp,
+                           const float* ref, double* part_rmse, const float* v, float lambda, const DevState* st,
+                           float eps2, const float* wx_in, const float* wy_in, const P2Decide& D, hipStream_t s)
+{
+    dim3 grid((p.nx + kP2T - 1) / kP2T, (p.ny + kP2T - 1) / kP2T);
+    hipLaunchKernelGGL(k_p2_final, grid, dim3(kP2Threads), 0, s, fcur, g, fout, foutT, clamp, ref, part_rmse, v, p.nx,
+                       p.ny, lambda, st, eps2, wx_in, wy_in, D);
     return hipGetLastError();
 }
 
@@ -1119,81 +1132,103 @@ hipError_t blaunch_select_finalize(const BatchDev& b, int pass, float floor_, hi
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void kb_tv_armijo(const SliceDev* __restrict__ sl, const int2* __restrict__ items,
-                                                    int n_items, int fs, int gps, int fos, int vs, float lambda,
-                                                    float eps2, int gs, float t0, float shrink)
+// The per-slice decision of a descent step: the batch-wide constants of D
+// with this slice's partials (by step parity) and records.
+__device__ __forceinline__ P2Decide slice_decision(const P2Decide& D, const SliceDev& d)
 {
-    __shared__ TvArmShared S;
-    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
-        const int2 w = items[it];
-        const SliceDev& d = sl[w.x];
-        __syncthreads();
-        tv_armijo_block(d.buf[fs], bsel(d, gps), d.st, bsel(d, fos), d.buf[vs], d.nx, d.ny, lambda, d.st, eps2,
-                        d.buf[gs], d.buf[kBufWX], d.buf[kBufWY], d.part[kPartGrad], d.part[kPartArm], t0, shrink,
-                        w.y % d.t16x, w.y / d.t16x, w.y, d.t16x * d.t16y, S);
-    }
+    P2Decide s = D;
+    s.part = d.part[kPartP2] + (size_t)(D.step & 1) * kP2Slots * (d.t32x * d.t32y);
+    s.st_k = d.st_k;
+    s.st_q0 = d.st_q0;
+    s.st_q1 = d.st_q1;
+    return s;
 }
 
-hipError_t blaunch_tv_armijo(const BatchDev& b, int f, int g_prev, int f_out, int v, float lambda, float eps2, int g,
-                             float t0, float shrink, hipStream_t s)
-{
-    const int n = b.n_items[kShT16];
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(kb_tv_armijo, dim3(b.grid[kShT16]), dim3(256), 0, s, b.slices, b.items[kShT16], n, f, g_prev,
-                       f_out, v, lambda, eps2, g, t0, shrink);
-    return hipGetLastError();
-}
-
-
-// one block per slice
-__global__ __launch_bounds__(kDecThreads) void kb_armijo_decide(const SliceDev* __restrict__ sl, int max_bt,
-                                                                double c_arm, float t0, float shrink, int step, int T,
-                                                                int fs, int gs, int vs, float lambda, float eps2)
+// One block per slice: descent step D.step's decision, into the slice's
+// state for the kernel after it (the one-slice kernels take it themselves in
+// every block; here every tile item would repeat it).
+__global__ __launch_bounds__(256) void kb_p2_decide(const SliceDev* __restrict__ sl, int fs, int gs, int vs,
+                                                    float lambda, float eps2, P2Decide D)
 {
     __shared__ DecShared S;
     const SliceDev& d = sl[blockIdx.x];
-    armijo_decide_block(d.st, d.part[kPartGrad], d.part[kPartArm], d.t16x * d.t16y, max_bt, c_arm, t0, shrink,
-                        d.st_k, d.st_q0, d.st_q1, step, T, d.buf[fs], d.buf[gs], d.buf[vs], d.buf[kBufWX],
-                        d.buf[kBufWY], d.nx, d.ny, lambda, eps2, S);
-}
-
-hipError_t blaunch_armijo_decide(const BatchDev& b, int max_bt, double c_arm, float t0, float shrink, int step, int T,
-                                 int f, int g, int v, float lambda, float eps2, hipStream_t s)
-{
-    hipLaunchKernelGGL(kb_armijo_decide, dim3(b.n), dim3(kDecThreads), 0, s, b.slices, max_bt, c_arm, t0, shrink,
-                       step, T, f, g, v, lambda, eps2);
-    return hipGetLastError();
-}
-
-// With `rmse`, a slice with a reference also gets its per-tile squared errors
-// (as the one-slice update does), for the iteration's RMSE record.
-__global__ __launch_bounds__(256) void kb_p2_update(const SliceDev* __restrict__ sl, const int2* __restrict__ items,
-                                                    int n_items, int fcs, int gs, int fos, int fTs, int clamp,
-                                                    int rmse)
-{
-    __shared__ float tl[32][33];
-    __shared__ double lds[4];
-    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
-        const int2 w = items[it];
-        const SliceDev& d = sl[w.x];
-        __syncthreads();
-        p2_update_block(d.st, d.buf[fcs], d.buf[gs], d.buf[fos], bsel(d, fTs), clamp, d.nx, d.ny, w.y % d.t32x,
-                        w.y / d.t32x, tl);
-        if (rmse && d.buf[kBufFRef]) {  // uniform per item
-            const double e2 = update_tile_sq_err(d.buf[fos], d.buf[kBufFRef], d.nx, d.ny, w.y % d.t32x,
-                                                 w.y / d.t32x, lds);
-            if (threadIdx.x == 0) d.part[kPartRmse][w.y] = e2;
-        }
+    int k;
+    float t;
+    p2_decide<256>(slice_decision(D, d), d.t32x * d.t32y, d.st, true, d.buf[fs], d.buf[gs], d.buf[vs], nullptr,
+                   nullptr, d.st->inv_sigma2, d.nx, d.ny, lambda, eps2, S, nullptr, k, t);
+    if (threadIdx.x == 0) {
+        d.st->k = k;
+        d.st->t = t;
     }
 }
 
-hipError_t blaunch_p2_update(const BatchDev& b, int fcur, int g, int fout, int foutT, int clamp, int rmse,
+hipError_t blaunch_p2_decide(const BatchDev& b, int f, int g, int v, float lambda, float eps2, const P2Decide& D,
                              hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_p2_decide, dim3(b.n), dim3(256), 0, s, b.slices, f, g, v, lambda, eps2, D);
+    return hipGetLastError();
+}
+
+// step D.step + 1; its predecessor's decision is the slice's state
+__global__ __launch_bounds__(kP2Threads) void kb_p2_step(const SliceDev* __restrict__ sl,
+                                                         const int2* __restrict__ items, int n_items, int fs, int gps,
+                                                         int fos, int vs, float lambda, float eps2, int gs, float t0,
+                                                         float shrink, P2Decide D)
+{
+    __shared__ P2Shared S;
+    const int step = D.step + 1;
+    D.part = nullptr;
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 w = items[it];
+        const SliceDev& d = sl[w.x];
+        const int nb = d.t32x * d.t32y;
+        __syncthreads();
+        p2_step_block(d.buf[fs], bsel(d, gps), bsel(d, fos), d.buf[vs], d.nx, d.ny, lambda, d.st, eps2, d.buf[gs],
+                      d.part[kPartP2] + (size_t)(step & 1) * kP2Slots * nb, t0, shrink, w.y % d.t32x, w.y / d.t32x,
+                      w.y, nb, S, nullptr, nullptr, nullptr, 0.0f, D);
+    }
+}
+
+static int p2_grid(const BatchDev& b) { return std::max(1, std::min(b.n_items[kShT32], 2 * 256)); }
+
+hipError_t blaunch_p2_step(const BatchDev& b, int f, int g_prev, int f_out, int v, float lambda, float eps2, int g,
+                           float t0, float shrink, const P2Decide& D, hipStream_t s)
 {
     const int n = b.n_items[kShT32];
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(kb_p2_update, dim3(b.grid[kShT32]), dim3(256), 0, s, b.slices, b.items[kShT32], n, fcur, g,
-                       fout, foutT, clamp, rmse);
+    hipLaunchKernelGGL(kb_p2_step, dim3(p2_grid(b)), dim3(kP2Threads), 0, s, b.slices, b.items[kShT32], n, f, g_prev,
+                       f_out, v, lambda, eps2, g, t0, shrink, D);
+    return hipGetLastError();
+}
+
+// The last step's update with the decision in the slice's state.  With
+// `rmse`, a slice with a reference also gets its per-tile squared errors (as
+// the one-slice update does), for the iteration's RMSE record.
+__global__ __launch_bounds__(kP2Threads) void kb_p2_final(const SliceDev* __restrict__ sl,
+                                                          const int2* __restrict__ items, int n_items, int fcs,
+                                                          int gs, int fos, int fTs, int clamp, int rmse, int vs,
+                                                          float lambda, float eps2, P2Decide D)
+{
+    __shared__ P2Shared S;
+    D.part = nullptr;
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 w = items[it];
+        const SliceDev& d = sl[w.x];
+        const float* ref = rmse ? d.buf[kBufFRef] : nullptr;
+        __syncthreads();
+        p2_final_block(d.buf[fcs], d.buf[gs], d.buf[fos], bsel(d, fTs), clamp, ref, d.part[kPartRmse], d.buf[vs],
+                       d.nx, d.ny, lambda, d.st, eps2, w.y % d.t32x, w.y / d.t32x, w.y, d.t32x * d.t32y, S, nullptr,
+                       nullptr, D);
+    }
+}
+
+hipError_t blaunch_p2_final(const BatchDev& b, int fcur, int g, int fout, int foutT, int clamp, int rmse, int v,
+                            float lambda, float eps2, const P2Decide& D, hipStream_t s)
+{
+    const int n = b.n_items[kShT32];
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(kb_p2_final, dim3(p2_grid(b)), dim3(kP2Threads), 0, s, b.slices, b.items[kShT32], n, fcur, g,
+                       fout, foutT, clamp, rmse, v, lambda, eps2, D);
     return hipGetLastError();
 }
 
