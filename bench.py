@@ -133,6 +133,17 @@ def achievable_hbm(torch, mib: int = 2048, reps: int = 10) -> float:
     return 2.0 * mib * 2**20 / sec
 
 
+def achievable_read(torch, eptv, mib: int = 2048, reps: int = 10) -> float:
+    """Bytes per second of the library's read-only streaming kernel over a
+    `mib` MiB buffer, far larger than the 256 MB Infinity Cache: the rate a
+    read-dominated kernel can reach from HBM on this GPU."""
+    buf = torch.empty(mib * 2**18, dtype=torch.float32, device="cuda").fill_(1.0)
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ms = kernel_avg_ms(lambda: eptv.stream_read(buf, sink), reps, torch)
+    del buf
+    return mib * 2**20 / (ms * 1e-3)
+
+
 def kernel_avg_ms(fn, reps, torch):
     s = torch.cuda.current_stream()
     fn()
@@ -146,44 +157,86 @@ def kernel_avg_ms(fn, reps, torch):
     return e0.elapsed_time(e1) / reps
 
 
-def cpu_baseline(case, iters):
+def host_cpu():
+    """The host CPU: model name, logical CPUs, physical cores (distinct
+    (package, core) pairs in /proc/cpuinfo) and the CPUs this process may use."""
+    model, logical, cores, cur = None, 0, set(), {}
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in list(fh) + [""]:
+                if not ln.strip():
+                    if "processor" in cur:
+                        logical += 1
+                        cores.add((cur.get("physical id"), cur.get("core id")))
+                        model = model or cur.get("model name")
+                    cur = {}
+                    continue
+                k, _, v = ln.partition(":")
+                cur[k.strip()] = v.strip()
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = os.cpu_count()
+    return {"model": model, "logical_cpus": logical or None, "physical_cores": len(cores) or None,
+            "cpus_available": allowed}
+
+
+def cpu_baseline(cases, iters_n, iters_1, small_iters):
+    """The FP64 oracle as it stands, on this host: the 512^2/40-view workload
+    (iters_n outer iterations on all available CPUs, iters_1 on one thread) and
+    the 128^2/30-view one (small_iters each way), matrix builds excluded like
+    the GPU plan creation; one oracle call of P and P^T at each thread count.
+    value: the 512^2 iterations per second on all available CPUs."""
     import numpy as np
     from oracle import oracle as O
 
-    M = O.Matrix(case.geom)
-    p = O.Params(outer_iters=iters, lam=1000.0, tv_eps=1e-4)
-    y = case.y.astype(np.float32)
-    t0 = time.perf_counter()
-    M.reconstruct(y, p)
-    dt = time.perf_counter() - t0
-    # one operator call each, on the phantom and the data
-    x = case.phantom.astype(np.float32)
-    t1 = time.perf_counter()
-    M.project(x)
-    t2 = time.perf_counter()
-    M.backproject(y)
-    t3 = time.perf_counter()
-    model = None
-    try:
-        with open("/proc/cpuinfo") as fh:
-            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), None)
-    except OSError:
-        pass
-    return {"value": iters / dt, "unit": "iterations/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"first {iters} outer iterations of the same 512^2/40-view workload (seed 0), "
-                      f"FP64 oracle with a stored Siddon system matrix; matrix build ({M.nnz} nonzeros) "
-                      f"excluded like the GPU plan creation",
-            "seconds": dt, "project_ms": (t2 - t1) * 1e3, "backproject_ms": (t3 - t2) * 1e3, "cpu_model": model}
+    cpu = host_cpu()
+    n_threads = max(1, int(cpu["cpus_available"] or 1))
+    runs = {}
+    for name, case, iters in (("paper", cases["paper"], (iters_n, iters_1)),
+                              ("small", cases["small"], (small_iters, small_iters))):
+        M = O.Matrix(case.geom)
+        y = case.y.astype(np.float32)
+        x = case.phantom.astype(np.float32)
+        for threads, k in ((n_threads, iters[0]), (1, iters[1])):
+            if k <= 0:
+                continue
+            O.set_num_threads(threads)
+            t0 = time.perf_counter()
+            M.reconstruct(y, O.Params(outer_iters=k, lam=1000.0, tv_eps=1e-4))
+            dt = time.perf_counter() - t0
+            t1 = time.perf_counter()
+            M.project(x)
+            t2 = time.perf_counter()
+            M.backproject(y)
+            t3 = time.perf_counter()
+            runs[f"{name}_{'1' if threads == 1 else 'n'}"] = {
+                "threads": O.num_threads(), "iterations": k, "seconds": dt, "iterations_per_s": k / dt,
+                "project_ms": (t2 - t1) * 1e3, "backproject_ms": (t3 - t2) * 1e3, "nnz": M.nnz}
+    O.set_num_threads(n_threads)
+    head = runs["paper_n"]
+    return {"value": head["iterations_per_s"], "unit": "iterations/s", "cores": head["threads"], "kind": "oracle",
+            "sample": f"the first {iters_n} outer iterations of the same 512^2/40-view workload (seed 0) on "
+                      f"{head['threads']} threads, FP64 oracle with a stored Siddon system matrix; matrix build "
+                      f"excluded like the GPU plan creation; beside it {iters_1} iterations on one thread and "
+                      f"{small_iters} iterations of the 128^2/30-view workload each way",
+            "seconds": head["seconds"], "project_ms": head["project_ms"], "backproject_ms": head["backproject_ms"],
+            "cpu": cpu, "runs": runs}
 
 
 def time_to_rmse(E, synth, P, torch, np, seeds, solver):
-    """Seconds until the RMSE to the phantom reaches the FP64 oracle's RMSE
-    after 100 iterations (tests/golden/rmse_targets_paper.json), the
-    device-side RMSE record included in the timed run; median over seeds.
-    Plain EPTV from zero, and (when the trained network is present) the
-    CNN-assisted pipeline: plain iterations (1), the U-Net's proposal of image
-    and edge weights, EPTV warm-started from it with the weights frozen for
-    its first iteration."""
+    """Seconds until the RMSE to the phantom reaches a target of the FP64
+    oracle's (tests/golden/rmse_targets_paper.json), the device-side RMSE
+    record included in the timed run; per seed the median of repeated runs,
+    over seeds the median.  Targets: the oracle's RMSE after 100 iterations,
+    and (stricter) its best RMSE over those iterations plus 0.1 % (the float32
+    trajectory follows the oracle's to ~1e-5, so its minimum may sit a hair
+    above).  Plain EPTV from zero, and (when the trained network is present)
+    the CNN-assisted pipeline: plain iterations (1), the U-Net's proposal of
+    image and edge weights, EPTV warm-started from it with the weights frozen
+    for its first iteration."""
     from paper_1009_2288_amd import cnn_assist as A
     with open(os.path.join(ROOT, "tests", "golden", "rmse_targets_paper.json")) as fh:
         targets = json.load(fh)
@@ -193,10 +246,14 @@ def time_to_rmse(E, synth, P, torch, np, seeds, solver):
         c = synth.make_case("paper", seed)
         y = torch.from_numpy(c.y.astype(np.float32)).cuda()
         ref = torch.from_numpy(c.phantom.astype(np.float32)).cuda()
-        target = targets["seeds"][str(seed)]["rmse_final"]
-        r = {"seed": seed, "target": target, "plain": A.time_to_rmse(P, y, ref, target, solver=solver)}
+        t_final = targets["seeds"][str(seed)]["rmse_final"]
+        t_min = targets["seeds"][str(seed)]["rmse_min"] * 1.001
+        r = {"seed": seed, "target": t_final, "target_min": t_min,
+             "plain": A.time_to_rmse(P, y, ref, t_final, solver=solver),
+             "plain_min": A.time_to_rmse(P, y, ref, t_min, solver=solver)}
         if net is not None:
-            r["cnn"] = A.time_to_rmse(P, y, ref, target, net=net, solver=solver)
+            r["cnn"] = A.time_to_rmse(P, y, ref, t_final, net=net, solver=solver)
+            r["cnn_min"] = A.time_to_rmse(P, y, ref, t_min, net=net, solver=solver)
         per.append(r)
 
     def med(kind, key):
@@ -204,14 +261,21 @@ def time_to_rmse(E, synth, P, torch, np, seeds, solver):
         return float(np.median(v)) if v and all(x is not None for x in v) else None
 
     out = {"target": "FP64 oracle RMSE to the phantom after 100 iterations, same seed",
+           "target_min": "FP64 oracle's best RMSE over its 100 iterations (about iteration 27) + 0.1 %, same seed",
            "plain_seconds_median": med("plain", "seconds"),
            "plain_iterations_median": med("plain", "iterations"),
+           "plain_min_seconds_median": med("plain_min", "seconds"),
+           "plain_min_iterations_median": med("plain_min", "iterations"),
            "per_seed": per}
     if net is not None:
         out["cnn_seconds_median"] = med("cnn", "seconds")
         out["cnn_warm_iterations_median"] = med("cnn", "iterations")
+        out["cnn_min_seconds_median"] = med("cnn_min", "seconds")
+        out["cnn_min_warm_iterations_median"] = med("cnn_min", "iterations")
         if out["cnn_seconds_median"] and out["plain_seconds_median"]:
             out["cnn_speedup"] = out["plain_seconds_median"] / out["cnn_seconds_median"]
+        if out["cnn_min_seconds_median"] and out["plain_min_seconds_median"]:
+            out["cnn_min_speedup"] = out["plain_min_seconds_median"] / out["cnn_min_seconds_median"]
         out["cnn_pipeline"] = (f"{A.N0} plain iterations + U-Net ({A.NET['levels']} levels, base {A.NET['base']}, "
                                f"bf16 MFMA) + EPTV warm start, proposed weights frozen for 1 iteration")
         # the network alone: forward time and matrix-core rate at 512^2
@@ -294,14 +358,82 @@ def batch_leg(E, synth, torch, np, n_slices, iters, warmup):
                         "I0 log-uniform 1e4-1e5; per iteration 3 CGLS steps, adaptive sigma, 5 Armijo steps"}
 
 
+def paper_scanner_geometry(synth, n_views):
+    """The paper's scanner (Sec. 3): an 888-unit arc detector at 1.0239 mm
+    pitch and 949.075 mm from the source, 541 mm from source to rotation
+    centre, a 512 x 512 image whose inscribed circle is the fan's field of view
+    (0.974 mm pixels; the corners lie outside the fan, as on a clinical
+    scanner)."""
+    import math
+    dbeta = 1.0239 / 949.075
+    pixel = 2.0 * 541.0 * math.sin(0.5 * 888 * dbeta) / 512
+    return synth.Geometry(512, 512, pixel, n_views, 888, dbeta, 541.0, 949.075)
+
+
+def stored_hbm_leg(E, synth, torch, np, reps, steps, n_views=200):
+    """The stored-matrix products (the paper's look-up tables, Sec. 2.3) on a
+    workload whose two copies exceed the 256 MB Infinity Cache, so every call
+    streams them from HBM: the paper's scanner at the chest case's 200 views
+    (Table 2).  Per-call kernel times (HIP events on the launching stream)
+    against the algorithmic bytes, the read-only streaming rate of this GPU,
+    and whole EPTV iterations at this size with each operator mode."""
+    g = paper_scanner_geometry(synth, n_views)
+    ell = synth.phantom_paper(0)
+    y_np = synth.noisy_sinogram(synth.line_integrals(ell, g), 5e4, 1000).astype(np.float32)
+    P = E.Plan(g)
+    nnz = P.nnz
+    mbytes = P.store_matrix()
+    y = torch.from_numpy(y_np).cuda()
+    x = torch.rand((g.ny, g.nx), generator=torch.Generator(device="cuda").manual_seed(1), device="cuda")
+    xT = x.t().contiguous()
+    q = P.new_sinogram()
+    z = P.new_image()
+    n_img, n_sino = g.nx * g.ny, g.n_views * g.n_bins
+    out = {"workload": f"the paper's scanner: 512x512 ({g.pixel_mm:.3f} mm pixels), {n_views} views x 888 bins, "
+                       f"SAD 541 mm, SDD 949.075 mm (the chest case of Table 2)",
+           "nnz": nnz, "matrix_bytes": mbytes}
+    for name, fn, rows, n_in, n_out in (
+            ("project_stored", lambda: P.project_stored_dual(x, xT, q), n_sino, n_img, n_sino),
+            ("backproject_stored", lambda: P.backproject_stored(y, z), n_img, n_sino, n_img)):
+        ms = kernel_avg_ms(fn, reps, torch)
+        nbytes = 8.0 * nnz + 4.0 * (rows + 1) + 4.0 * (n_in + n_out)
+        out[name] = {"avg_ms": ms, "algorithmic_bytes_per_launch": nbytes, "gbps": nbytes / (ms * 1e-3) / 1e9,
+                     "frac": nbytes / (ms * 1e-3) / HBM_PEAK}
+    rd = achievable_read(torch, E)
+    out["achievable_read_gbps"] = rd / 1e9
+    for name in ("project_stored", "backproject_stored"):
+        out[name]["frac_of_achievable"] = out[name]["gbps"] * 1e9 / rd
+    its = {}
+    base = dict(cgls_iters=3, tv_iters=5, lam=1000.0, edge_quantile=0.9, tv_eps=1e-4)
+    for mode in ("stored", "fly", "hybrid"):
+        prm = dict(base, stored_matrix=OPERATORS[mode])
+        f = torch.zeros((g.ny, g.nx), dtype=torch.float32, device="cuda")
+        P.reconstruct(y, E.Params(outer_iters=2, zero_init=1, **prm), f=f, stats=False)
+        s = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(s)
+        P.reconstruct(y, E.Params(outer_iters=steps, zero_init=0, **prm), f=f, stats=False)
+        e1.record(s)
+        torch.cuda.synchronize()
+        its[mode] = steps / (e0.elapsed_time(e1) / 1e3)
+    out["iterations_per_s"] = its
+    out["paper_context"] = "Table 2, chest: 200 views, 30 iterations in 9.8 s on a Tesla C1060 (0.327 s per iteration)"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--kernel-reps", type=int, default=200)
-    ap.add_argument("--cpu-iters", type=int, default=120,
-                    help="outer iterations of the FP64 oracle for cpu_baseline (~10 s on 16 host threads)")
+    ap.add_argument("--cpu-iters", type=int, default=60,
+                    help="outer iterations of the FP64 oracle on all host CPUs for cpu_baseline (512^2/40 views)")
+    ap.add_argument("--cpu-iters-1", type=int, default=20,
+                    help="outer iterations of the FP64 oracle on one thread (512^2/40 views)")
+    ap.add_argument("--cpu-small-iters", type=int, default=50,
+                    help="outer iterations of the FP64 oracle on the 128^2/30-view workload, each thread count")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rmse-seeds", type=int, default=10, help="seeds for the time-to-RMSE leg (0 to skip)")
     ap.add_argument("--batch-slices", type=int, default=64, help="slices of the batched leg (0 to skip)")
@@ -311,6 +443,9 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="finally copy a buffer of this many MiB on the device (a plain copy kernel of known "
                          "size, to calibrate hardware byte counters against)")
+    ap.add_argument("--hbm-views", type=int, default=200,
+                    help="views of the stored-matrix leg on the paper's scanner, whose matrix streams from HBM "
+                         "(0 to skip)")
     ap.add_argument("--operator", choices=list(OPERATORS), default="stored",
                     help="P and P^T of the headline figure: from the stored float32 matrix (the paper's "
                          "look-up tables), on the fly, or P on the fly with P^T stored (hybrid); the others "
@@ -420,11 +555,16 @@ def main():
     other = [{"operator": m, "stored_matrix": OPERATORS[m], "value": v[0], "ms_per_step": v[1],
               "rmse_vs_phantom": v[2], "roofline": roofline(m)} for m, v in others.items()]
     if roof["bound"] == "hbm":
-        # what HBM delivers to a plain device copy far larger than the 256 MB
-        # Infinity Cache (read + write bytes per second)
-        hbm = achievable_hbm(torch)
-        roof["achievable_hbm_gbps"] = hbm / 1e9
-        roof["frac_of_achievable"] = roof["achieved"] * 1e9 / hbm
+        # what HBM delivers to a read-only stream and to a device copy, both far
+        # larger than the 256 MB Infinity Cache; at this size the two matrix
+        # copies (together under 256 MB) are served partly by that cache between
+        # calls, so the fraction is cache-assisted (stored_hbm streams them)
+        rd = achievable_read(torch, eptv)
+        roof["achievable_read_gbps"] = rd / 1e9
+        roof["frac_of_achievable"] = roof["achieved"] * 1e9 / rd
+        roof["achievable_copy_gbps"] = achievable_hbm(torch) / 1e9
+        roof["note"] = ("cache-assisted: both stored copies (%.0f MB) fit the 256 MB Infinity Cache between calls"
+                        % (P.store_matrix() / 1e6))
     log("bench: " + ", ".join(f"{k} {v * 1e3:.1f} us" for k, v in op_ms.items()) + f", nnz {nnz}")
 
     ttr = None
@@ -441,6 +581,14 @@ def main():
         log(f"bench: batch {bat['ms_per_batch_iteration']:.3f} ms per iteration of all slices, "
             f"{bat['equivalent_512x512x40_iterations_per_s']:.1f} equivalent 512^2/40 it/s, launch {bat['launch']}")
 
+    hbm_leg = None
+    if args.hbm_views > 0:
+        log(f"bench: stored matrix streaming from HBM, the paper's scanner at {args.hbm_views} views")
+        hbm_leg = stored_hbm_leg(eptv, synth, torch, np, max(10, args.kernel_reps // 10), 10, args.hbm_views)
+        log(f"bench: stored P {hbm_leg['project_stored']['gbps']:.0f} GB/s, P^T "
+            f"{hbm_leg['backproject_stored']['gbps']:.0f} GB/s, read stream {hbm_leg['achievable_read_gbps']:.0f} "
+            f"GB/s, matrix {hbm_leg['matrix_bytes'] / 2**20:.0f} MiB, it/s {hbm_leg['iterations_per_s']}")
+
     cnn_train = None
     if args.unet_train_steps > 0:
         log(f"bench: U-Net training, {args.unet_train_steps} steps of batch 8")
@@ -450,9 +598,12 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        log(f"bench: CPU oracle baseline, {args.cpu_iters} iterations")
-        cpu = cpu_baseline(case, args.cpu_iters)
-        log(f"bench: oracle {cpu['value']:.3f} it/s on {cpu['cores']} threads")
+        log(f"bench: CPU oracle baseline, {args.cpu_iters} + {args.cpu_iters_1} iterations (512^2), "
+            f"{args.cpu_small_iters} x 2 (128^2)")
+        cpu = cpu_baseline({"paper": case, "small": synth.make_case("small", 0)}, args.cpu_iters, args.cpu_iters_1,
+                           args.cpu_small_iters)
+        log(f"bench: oracle {cpu['value']:.3f} it/s on {cpu['cores']} threads; "
+            + ", ".join(f"{k} {v['iterations_per_s']:.3f} it/s" for k, v in cpu["runs"].items()))
 
     out = {
         "metric": "EPTV iterations/s at 512^2 / 40 views",
@@ -480,6 +631,7 @@ def main():
                      else "same operator, the iteration captured once as a HIP graph and replayed")},
         "time_to_rmse": ttr,
         "batch": bat,
+        "stored_hbm": hbm_leg,
         "cnn_training": cnn_train,
         "roofline": roof,
         "cpu_baseline": cpu,

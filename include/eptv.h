@@ -305,6 +305,14 @@ int eptv_reconstruct_noalloc(eptv_plan plan, const eptv_params* params, const fl
                              const float* f_ref, eptv_stats* stats, void* stream);
 size_t eptv_noalloc_scratch_bytes(void);
 
+/* Measurement aid, not part of the method: reads `bytes` of device memory at
+ * buf once with 16-byte loads (buf and bytes multiples of 16), the rate a
+ * read-only stream reaches, to set beside the stored-matrix products (which
+ * mostly read).  sink: one device word, written only in a case no real buffer
+ * produces (it keeps the loads from being optimised away).  Asynchronous on
+ * the stream; EPTV_ERR_ARG for null pointers, zero size or misalignment. */
+int eptv_stream_read(const void* buf, size_t bytes, unsigned* sink, void* stream);
+
 /* ------------------------------------------------------------------ batches
  * Many slices, each with its own geometry (image size, views, bins), iterated
  * together: every phase of the EPTV iteration (Sec. 2.2) is one launch for

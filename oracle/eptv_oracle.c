@@ -43,6 +43,16 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Threads of the oracle's parallel loops from now on (n >= 1). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------ geometry
  * Sec. 3 / App. III Eq. A6: view theta_v (equally spaced over a full turn
  * unless given), source at -SAD (cos theta, sin theta), ray b leaves the

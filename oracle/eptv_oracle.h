@@ -138,6 +138,8 @@ int orc_reconstruct_replay(const orc_matrix* m, const orc_params* p, const doubl
                            const double* f_ref, orc_stats* st, const int* armijo_replay);
 
 int orc_num_threads(void);
+/* Threads of the parallel loops from now on (OpenMP builds; n >= 1). */
+void orc_set_num_threads(int n);
 
 #ifdef __cplusplus
 }

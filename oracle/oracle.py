@@ -125,6 +125,7 @@ def lib() -> C.CDLL:
         L.orc_reconstruct_replay.argtypes = [C.c_void_p, C.POINTER(_Params), dp, dp, dp, C.POINTER(_Stats),
                                              C.POINTER(C.c_int)]
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -156,6 +157,12 @@ def _geom(g) -> tuple[_Geom, Optional[np.ndarray]]:
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (timing only: the
+    results do not depend on it)."""
+    lib().orc_set_num_threads(int(n))
 
 
 def backproject_interp(g, r) -> np.ndarray:

@@ -283,17 +283,18 @@ def assisted_reconstruct(P: E.Plan, net: E.UNet, y: torch.Tensor, outer_iters: i
 
 
 def time_to_rmse(P: E.Plan, y: torch.Tensor, ref: torch.Tensor, target: float, net: Optional[E.UNet] = None,
-                 frozen_iters: int = 1, max_iters: int = 100, reps: int = 3, n0: int = N0,
+                 frozen_iters: int = 1, max_iters: int = 100, reps: int = 5, n0: int = N0,
                  solver: Optional[dict] = None):
-    """Seconds (best of ``reps``, HIP events on the current stream) until the
-    RMSE to ``ref`` is <= target: plain EPTV from zero, or (with ``net``) the
-    assisted pipeline.  The runs stop themselves (``stop_rmse``, the RMSE
-    record read back after every iteration), so the time includes each
-    iteration's check.  ``solver`` overrides entries of SOLVER (e.g.
+    """Seconds (median of ``reps`` runs, HIP events on the current stream)
+    until the RMSE to ``ref`` is <= target: plain EPTV from zero, or (with
+    ``net``) the assisted pipeline.  The runs stop themselves (``stop_rmse``,
+    the RMSE record read back after every iteration), so the time includes
+    each iteration's check.  ``solver`` overrides entries of SOLVER (e.g.
     ``stored_matrix=1`` once the plan holds the matrix)."""
+    import numpy as np
     solver = {**SOLVER, **(solver or {})}
     s = torch.cuda.current_stream()
-    best, st = None, None
+    secs, st = [], None
     for _ in range(reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -306,9 +307,9 @@ def time_to_rmse(P: E.Plan, y: torch.Tensor, ref: torch.Tensor, target: float, n
                                          solver={**solver, "stop_rmse": target})
         e1.record(s)
         torch.cuda.synchronize()
-        sec = e0.elapsed_time(e1) / 1e3
-        best = sec if best is None else min(best, sec)
+        secs.append(e0.elapsed_time(e1) / 1e3)
     k = st["iters_run"]
     if st["rmse"][k - 1] > target:
         return {"iterations": None, "seconds": None, "rmse_min": float(st["rmse"].min())}
-    return {"iterations": k, "seconds": best, "rmse": float(st["rmse"][k - 1])}
+    return {"iterations": k, "seconds": float(np.median(secs)), "rmse": float(st["rmse"][k - 1]),
+            "seconds_runs": [float(v) for v in secs]}

@@ -31,7 +31,7 @@ SYMBOLS = ["eptv_plan_create", "eptv_plan_destroy", "eptv_plan_nnz", "eptv_works
            "eptv_unet_set_params", "eptv_unet_get_params", "eptv_unet_get_grads", "eptv_unet_forward",
            "eptv_unet_backward", "eptv_unet_adam", "eptv_unet_mse", "eptv_reconstruct_weighted",
            "eptv_maps_from_eptv", "eptv_maps_to_eptv", "eptv_reconstruct_replay",
-           "eptv_reconstruct_noalloc", "eptv_noalloc_scratch_bytes"]
+           "eptv_reconstruct_noalloc", "eptv_noalloc_scratch_bytes", "eptv_stream_read"]
 
 
 class EptvError(RuntimeError):
@@ -176,6 +176,7 @@ def _lib() -> C.CDLL:
         L.eptv_reconstruct_noalloc.argtypes = [vp, C.POINTER(_Params), vp, vp, vp, C.POINTER(_Stats), vp]
         L.eptv_noalloc_scratch_bytes.argtypes = []
         L.eptv_noalloc_scratch_bytes.restype = sz
+        L.eptv_stream_read.argtypes = [vp, sz, vp, vp]
         L.eptv_reconstruct_replay.argtypes = [vp, C.POINTER(_Params), vp, vp, vp, C.POINTER(C.c_int32), vp, sz,
                                               C.POINTER(_Stats), vp]
         L.eptv_reconstruct_weighted.argtypes = [vp, C.POINTER(_Params), vp, vp, vp, vp, vp, C.c_int, vp, sz,
@@ -527,6 +528,15 @@ class Plan:
             if f_ref is None:
                 rec.pop("rmse")
         return f, rec
+
+
+def stream_read(buf: torch.Tensor, sink: torch.Tensor, stream=None) -> None:
+    """Read every byte of a contiguous device tensor once (eptv_stream_read), a
+    measurement aid: the read-only streaming rate of the GPU."""
+    if not buf.is_cuda or not buf.is_contiguous() or not sink.is_cuda or sink.dtype != torch.int32:
+        raise ValueError("stream_read: contiguous device tensors, sink int32")
+    _check(_lib().eptv_stream_read(buf.data_ptr(), buf.numel() * buf.element_size(), sink.data_ptr(),
+                                   _stream(stream)), "eptv_stream_read")
 
 
 def noalloc_scratch_bytes() -> int:

@@ -151,3 +151,16 @@ def test_nonfinite_status_and_params_layout(lib):
     assert src.index("int check_finite;") > src.index("double stop_rmse;")
     assert [f[0] for f in eptv._Params._fields_][-1] == "check_finite"
     assert [f[0] for f in eptv._Stats._fields_][-4:] == ["armijo_q0", "armijo_q1", "cgls_gamma", "cgls_delta"]
+
+
+def test_stream_read_rejects_bad_arguments_without_gpu(lib):
+    """The measurement aid checks its arguments before any HIP call."""
+    from paper_1009_2288_amd import eptv
+    fn = lib.eptv_stream_read
+    buf = C.c_void_p(16 * 1024)  # never dereferenced: every call below is rejected first
+    sink = C.c_void_p(64)
+    assert fn(None, 1024, sink, None) == eptv.EPTV_ERR_ARG
+    assert fn(buf, 1024, None, None) == eptv.EPTV_ERR_ARG
+    assert fn(buf, 0, sink, None) == eptv.EPTV_ERR_ARG
+    assert fn(buf, 1000, sink, None) == eptv.EPTV_ERR_ARG          # not a multiple of 16 bytes
+    assert fn(C.c_void_p(16 * 1024 + 4), 1024, sink, None) == eptv.EPTV_ERR_ARG  # misaligned
