@@ -346,6 +346,20 @@ int eptv_batch_get_launch(eptv_batch batch, int* proj_seg, int* proj_grid, int* 
  * synchronises the stream. */
 int eptv_batch_tune(eptv_batch batch, int reps, void* stream, float* proj_ms, float* backproj_ms);
 
+/* The exact P (Sec. 2.1, Eq. 1) and its transpose P^T (Sec. 2.2) of every
+ * slice in one launch each: q[i] = alpha P_i x[i] + beta q[i], and
+ * z[i] = alpha P_i^T r[i] + beta z[i] (beta == 0 never reads the output), the
+ * same arithmetic as eptv_project / eptv_backproject on each slice's plan in
+ * the batch's launch shape.  x[i], z[i] [ny_i][nx_i], q[i], r[i]
+ * [n_views_i][n_bins_i], device pointers, one per slice.  ws: workspace of
+ * eptv_batch_operator_workspace_bytes (the projector stages each image's
+ * transposed copy there).  Asynchronous on the stream. */
+int eptv_batch_operator_workspace_bytes(eptv_batch batch, size_t* bytes);
+int eptv_batch_project(eptv_batch batch, const float* const* x, float* const* q, float alpha, float beta, void* ws,
+                       size_t ws_bytes, void* stream);
+int eptv_batch_backproject(eptv_batch batch, const float* const* r, float* const* z, float alpha, float beta,
+                           void* ws, size_t ws_bytes, void* stream);
+
 /* params.outer_iters EPTV iterations on every slice: y[i] (device
  * [V_i][B_i]), f[i] (device [ny_i][nx_i], warm start unless zero_init,
  * result), f_ref (NULL, or an array of reference images for the RMSE

@@ -451,6 +451,57 @@ int eptv_batch_tune(eptv_batch b, int reps, void* stream, float* proj_ms, float*
     return EPTV_OK;
 }
 
+// The operators of every slice in one launch each (the batch's projector and
+// backprojector kernels over all slices), for callers that apply P or P^T to
+// a stack of images, such as the differentiable operators.
+static int batch_operator(eptv_batch b, bool forward, const float* const* in, float* const* out, float alpha,
+                          float beta, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!b || !in || !out) return EPTV_ERR_ARG;
+    for (int i = 0; i < b->bd.n; ++i)
+        if (!in[i] || !out[i]) return EPTV_ERR_ARG;
+    if (!ws || ((uintptr_t)ws & 255)) return EPTV_ERR_WORKSPACE;
+    std::vector<Workspace> Ws;
+    if (batch_ws_layout(*b, 1, 0, 0, (char*)ws, &Ws) > ws_bytes) return EPTV_ERR_WORKSPACE;
+    eptv_params q{};
+    q.edge_quantile = 0.9;
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lock(b->mu);
+    const BatchDev& bd = b->bd;
+    if (forward) {
+        // image -> f (transposed into the workspace for the sweep layout), sinogram -> y
+        int rc = bind_batch(*b, q, Ws, (const float* const*)out, (float* const*)in, nullptr, s);
+        if (rc != EPTV_OK) return rc;
+        EPTV_HIP(blaunch_transpose(bd, kBufF, kBufFT, s));
+        EPTV_HIP(blaunch_project(bd, kBufF, kBufFT, alpha, beta, beta != 0.0f ? kBufY : kNoBuf, kBufY, kNoBuf, s));
+    } else {
+        // sinogram -> y, image -> f
+        int rc = bind_batch(*b, q, Ws, in, out, nullptr, s);
+        if (rc != EPTV_OK) return rc;
+        EPTV_HIP(blaunch_backproject(bd, kBufY, alpha, beta, beta != 0.0f ? kBufF : kNoBuf, kBufF, kNoBuf, kNoBuf, s));
+    }
+    return EPTV_OK;
+}
+
+int eptv_batch_operator_workspace_bytes(eptv_batch b, size_t* bytes)
+{
+    if (!b || !bytes) return EPTV_ERR_ARG;
+    *bytes = batch_ws_layout(*b, 1, 0, 0, nullptr, nullptr);
+    return EPTV_OK;
+}
+
+int eptv_batch_project(eptv_batch b, const float* const* x, float* const* q, float alpha, float beta, void* ws,
+                       size_t ws_bytes, void* stream)
+{
+    return batch_operator(b, true, x, q, alpha, beta, ws, ws_bytes, stream);
+}
+
+int eptv_batch_backproject(eptv_batch b, const float* const* r, float* const* z, float alpha, float beta, void* ws,
+                           size_t ws_bytes, void* stream)
+{
+    return batch_operator(b, false, r, z, alpha, beta, ws, ws_bytes, stream);
+}
+
 int eptv_batch_reconstruct(eptv_batch b, const eptv_params* q, const float* const* y, float* const* f,
                            const float* const* f_ref, void* ws, size_t ws_bytes, eptv_stats* stats, void* stream)
 {

@@ -31,7 +31,8 @@ SYMBOLS = ["eptv_plan_create", "eptv_plan_destroy", "eptv_plan_nnz", "eptv_works
            "eptv_unet_set_params", "eptv_unet_get_params", "eptv_unet_get_grads", "eptv_unet_forward",
            "eptv_unet_backward", "eptv_unet_adam", "eptv_unet_mse", "eptv_reconstruct_weighted",
            "eptv_maps_from_eptv", "eptv_maps_to_eptv", "eptv_reconstruct_replay",
-           "eptv_reconstruct_noalloc", "eptv_noalloc_scratch_bytes", "eptv_stream_read"]
+           "eptv_reconstruct_noalloc", "eptv_noalloc_scratch_bytes", "eptv_stream_read",
+           "eptv_batch_operator_workspace_bytes", "eptv_batch_project", "eptv_batch_backproject"]
 
 
 class EptvError(RuntimeError):
@@ -177,6 +178,9 @@ def _lib() -> C.CDLL:
         L.eptv_noalloc_scratch_bytes.argtypes = []
         L.eptv_noalloc_scratch_bytes.restype = sz
         L.eptv_stream_read.argtypes = [vp, sz, vp, vp]
+        L.eptv_batch_operator_workspace_bytes.argtypes = [vp, C.POINTER(sz)]
+        L.eptv_batch_project.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.c_float, C.c_float, vp, sz, vp]
+        L.eptv_batch_backproject.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.c_float, C.c_float, vp, sz, vp]
         L.eptv_reconstruct_replay.argtypes = [vp, C.POINTER(_Params), vp, vp, vp, C.POINTER(C.c_int32), vp, sz,
                                               C.POINTER(_Stats), vp]
         L.eptv_reconstruct_weighted.argtypes = [vp, C.POINTER(_Params), vp, vp, vp, vp, vp, C.c_int, vp, sz,
@@ -604,6 +608,46 @@ class Batch:
         pm, bm = C.c_float(), C.c_float()
         _check(_lib().eptv_batch_tune(self._h, reps, _stream(stream), C.byref(pm), C.byref(bm)), "eptv_batch_tune")
         return {"project_ms": pm.value, "backproject_ms": bm.value, **self.launch()}
+
+    def _operator(self, forward: bool, xs, outs, alpha: float, beta: float, stream) -> None:
+        n = len(self)
+        if len(xs) != n or len(outs) != n:
+            raise ValueError(f"expected {n} slices")
+        if forward:
+            xs = [p._img(x, f"x[{i}]") for i, (p, x) in enumerate(zip(self.plans, xs))]
+            outs = [p._sino(o, f"q[{i}]") for i, (p, o) in enumerate(zip(self.plans, outs))]
+        else:
+            xs = [p._sino(x, f"r[{i}]") for i, (p, x) in enumerate(zip(self.plans, xs))]
+            outs = [p._img(o, f"z[{i}]") for i, (p, o) in enumerate(zip(self.plans, outs))]
+        nb = C.c_size_t()
+        _check(_lib().eptv_batch_operator_workspace_bytes(self._h, C.byref(nb)), "eptv_batch_operator_workspace_bytes")
+        if self._ws is None or self._ws.numel() < nb.value:
+            self._ws = torch.empty(int(nb.value), dtype=torch.uint8, device=self.device)
+        ip = (C.c_void_p * n)(*[x.data_ptr() for x in xs])
+        op = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+        fn = _lib().eptv_batch_project if forward else _lib().eptv_batch_backproject
+        _check(fn(self._h, ip, op, alpha, beta, self._ws.data_ptr(), self._ws.numel(), _stream(stream)),
+               "eptv_batch_project" if forward else "eptv_batch_backproject")
+
+    def project(self, xs, outs=None, alpha: float = 1.0, beta: float = 0.0, stream=None):
+        """q_i = alpha P_i x_i + beta q_i for every slice in one launch (eptv_batch_project).
+        xs: per-slice images, or a [n, ny, nx] tensor when the slices share a shape;
+        returns the outputs in the same form."""
+        stacked = isinstance(xs, torch.Tensor)
+        if outs is None:
+            outs = (torch.empty((len(self), self.plans[0].n_views, self.plans[0].n_bins), dtype=torch.float32,
+                                device=self.device) if stacked else [p.new_sinogram() for p in self.plans])
+        self._operator(True, list(xs), list(outs), alpha, beta, stream)
+        return outs
+
+    def backproject(self, rs, outs=None, alpha: float = 1.0, beta: float = 0.0, stream=None):
+        """z_i = alpha P_i^T r_i + beta z_i for every slice in one launch (eptv_batch_backproject)."""
+        stacked = isinstance(rs, torch.Tensor)
+        if outs is None:
+            outs = (torch.empty((len(self), self.plans[0].ny, self.plans[0].nx), dtype=torch.float32,
+                                device=self.device) if stacked else [p.new_image() for p in self.plans])
+        self._operator(False, list(rs), list(outs), alpha, beta, stream)
+        return outs
 
     def reconstruct(self, ys, params: Params, fs=None, f_refs=None, stats: bool = True, stream=None):
         """params.outer_iters iterations on every slice; returns (list of f, list of stats dicts or None)."""
