@@ -34,20 +34,32 @@ BF16_MFMA_PEAK = 2.5e15      # MI355X published dense bf16 matrix-core peak, FLO
 
 # HBM bytes per launch of the operator kernels on this workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
-# scaled by what the counter reads for a plain 256 MiB device copy (FETCH_SIZE
-# x 2.0, WRITE_SIZE x 1.0); see profiles/eptv_operators_512x512_40views_pmc_bytes.md.
+# scaled by what the counter reads for the read-only stream and a plain device
+# copy of known size (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0); see
+# profiles/eptv_operators_512x512_40views_pmc_bytes.md.
 # Each entry holds the hash of the kernel's source file when the counters were
 # taken: if the source has changed since, the figure is stale and reported as
 # null.
 PMC_TRAFFIC = {
-    "project": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "0984a5026983ecf3",
-                "bytes": (8330.6 * 2.0 + 115.0 * 1.0) * 1024},
-    "backproject": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "0984a5026983ecf3",
-                    "bytes": (5977.4 * 2.0 + 1024.0 * 1.0) * 1024},
+    "project": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "4232d9b9533001f9",
+                "bytes": (8343.5 * 2.0 + 125.6 * 1.0) * 1024},
+    "backproject": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "4232d9b9533001f9",
+                    "bytes": (5979.9 * 2.0 + 1304.0 * 1.0) * 1024},
     "project_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "9627430b42c3fee4",
-                       "bytes": (69835.5 * 2.0 + 116.3 * 1.0) * 1024},
+                       "bytes": (69880.5 * 2.0 + 127.7 * 1.0) * 1024},
     "backproject_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "9627430b42c3fee4",
-                           "bytes": (56062.3 * 2.0 + 1027.7 * 1.0) * 1024},
+                           "bytes": (56069.5 * 2.0 + 2293.0 * 1.0) * 1024},
+}
+
+
+# The same for the stored products on the paper's scanner at 200 views (the
+# stored_hbm leg, whose matrix streams from HBM); see
+# profiles/eptv_stored_operators_512x512_200views_paper_scanner_pmc_bytes.md.
+PMC_TRAFFIC_HBM = {
+    "project_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "9627430b42c3fee4",
+                       "bytes": (497902.8 * 2.0 + 895.4 * 1.0) * 1024},
+    "backproject_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "9627430b42c3fee4",
+                           "bytes": (459965.1 * 2.0 + 1150.0 * 1.0) * 1024},
 }
 
 
@@ -56,10 +68,10 @@ PMC_TRAFFIC = {
 # profiles/eptv_and_unet_valu_mfma_pmc.md.  Reported only while the kernel
 # source's hash matches.
 PMC_VALU = {
-    "project": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "0984a5026983ecf3",
-                "valu_busy": 0.401, "valu_wave_instructions": 8.54e6},
-    "backproject": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "0984a5026983ecf3",
-                    "valu_busy": 0.492, "valu_wave_instructions": 11.47e6},
+    "project": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "4232d9b9533001f9",
+                "valu_busy": 0.404, "valu_wave_instructions": 8.54e6},
+    "backproject": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "4232d9b9533001f9",
+                    "valu_busy": 0.491, "valu_wave_instructions": 11.47e6},
 }
 
 
@@ -67,9 +79,9 @@ PMC_VALU = {
 # rocprofv3 --pmc pass; see profiles/eptv_operators_512x512_40views_pmc_l2.md.
 # Reported only while the kernel source's hash matches.
 PMC_L2 = {
-    "project": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "0984a5026983ecf3",
+    "project": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "4232d9b9533001f9",
                 "read_requests": 1.351e6},
-    "backproject": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "0984a5026983ecf3",
+    "backproject": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "4232d9b9533001f9",
                     "read_requests": 0.460e6},
     "project_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "9627430b42c3fee4",
                        "read_requests": 1.735e6},
@@ -101,9 +113,9 @@ def pmc_valu(kernel, nnz):
     return {"valu_busy": e["valu_busy"], "valu_instructions_per_nnz": e["valu_wave_instructions"] * 64 / nnz}
 
 
-def pmc_traffic(kernel):
+def pmc_traffic(kernel, table=None):
     import hashlib
-    e = PMC_TRAFFIC.get(kernel)
+    e = (PMC_TRAFFIC if table is None else table).get(kernel)
     if e is None:
         return None
     with open(os.path.join(ROOT, e["source"]), "rb") as fh:
@@ -403,6 +415,16 @@ def stored_hbm_leg(E, synth, torch, np, reps, steps, n_views=200):
     out["achievable_read_gbps"] = rd / 1e9
     for name in ("project_stored", "backproject_stored"):
         out[name]["frac_of_achievable"] = out[name]["gbps"] * 1e9 / rd
+        out[name]["traffic"] = pmc_traffic(name, PMC_TRAFFIC_HBM)
+    # the roofline object for this workload's dominant stored kernel (4 P and
+    # 3 P^T calls per outer iteration)
+    dom = max(("project_stored", "backproject_stored"),
+              key=lambda k: (4 if k == "project_stored" else 3) * out[k]["avg_ms"])
+    d = out[dom]
+    out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": d["gbps"], "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                       "frac": d["frac"], "traffic": d["traffic"], "avg_ms": d["avg_ms"],
+                       "algorithmic_bytes_per_launch": d["algorithmic_bytes_per_launch"],
+                       "frac_of_achievable": d["frac_of_achievable"]}
     its = {}
     base = dict(cgls_iters=3, tv_iters=5, lam=1000.0, edge_quantile=0.9, tv_eps=1e-4)
     for mode in ("stored", "fly", "hybrid"):
