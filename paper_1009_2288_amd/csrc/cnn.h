@@ -29,6 +29,11 @@ struct ConvArgs {
     int cout = 0;  // GEMM output channels
     int n_pad = 0, k_pad = 0;
     int relu = 0;
+    // mask, if set: zero every output whose element of this tensor (same
+    // pixel, channel n at m_co + n, stride m_cs) is not positive -- the
+    // backward of a ReLU whose output it is, fused into the epilogue
+    const uint16_t* mask = nullptr;
+    int m_cs = 0, m_co = 0;
 };
 
 inline int pad64(int n) { return (n + 63) / 64 * 64; }
@@ -39,17 +44,21 @@ int wgrad_chunks(const ConvArgs& a, int chunk_px);
 // n_pad x kw partial tile grid (also sizes the partial buffers)
 int wgrad_chunk_px(int npix, int n_pad, int kw);
 int wgrad_max_chunks(int npix, int n_pad, int kw);
-// dW (unpacked later) into out and, if bias_out is given, the bias gradient
+// chunks of the LDS-tiled weight-gradient kernels (0 where none applies): an
+// upper bound for every batch up to n_img
+int wgrad_tiled_max_chunks(int mode, int n_img, int h, int w, int ci, int co);
+// dW into out (the parameter layout: [3][3][C_in][C_out], [C_in][C_out] or
+// [2][2][C_in][C_out]) and, if bias_out is given, the bias gradient
 // sum_p dY[p][n] into bias_out[cout]; part and bpart are partial-sum scratch
 hipError_t launch_wgrad(const ConvArgs& a, int mode, const uint16_t* dy, int dy_cs, int dy_co, int chunk_px,
                         float* part, float* out, float* bpart, float* bias_out, hipStream_t s);
 
-hipError_t launch_relu_mask(uint16_t* dy, int dcs, int dco, const uint16_t* y, int ycs, int yco, int npix, int c,
-                            hipStream_t s);
 hipError_t launch_avgpool(const uint16_t* x, int xcs, int xco, uint16_t* y, int n_img, int h, int w, int c,
                           hipStream_t s);
+// dx (+)= the adjoint of 2x2 average pooling of dy; with mask (same layout
+// as dx), elements whose mask value is not positive are set to zero
 hipError_t launch_avgpool_back(const uint16_t* dy, uint16_t* dx, int dxcs, int dxco, int n_img, int h, int w, int c,
-                               int accumulate, hipStream_t s);
+                               int accumulate, const uint16_t* mask, int mcs, int mco, hipStream_t s);
 hipError_t launch_to_bf16(const float* x, uint16_t* y, size_t n, hipStream_t s);
 hipError_t launch_eptv_to_maps(const float* f, const float* f_base, const float* wx, const float* wy, int n_img,
                                int ny, int nx, float scale, float* y, hipStream_t s);
@@ -58,10 +67,19 @@ hipError_t launch_maps_to_eptv(const float* y, const float* f_base, int n_img, i
 hipError_t launch_to_f32(const uint16_t* x, float* y, size_t n, hipStream_t s);
 hipError_t launch_add_slice(const uint16_t* src, int scs, int sco, uint16_t* dst, int dcs, int dco, int npix, int c,
                             hipStream_t s);
-hipError_t launch_pack(const float* w, int mode, int back, int ci, int co, int n_pad, int k_pad, uint16_t* out,
-                       hipStream_t s);
-hipError_t launch_unpack_grad(const float* g, int mode, int ci, int co, int n_pad, int k_pad, float* out,
-                              hipStream_t s);
+// fp32 master weights (parameter layout) -> packed bf16 GEMM operands
+//   conv3 forward: W[a][c][i][o] -> P[o][(3a+c) Ci + i]
+//   conv3 backward data: P[i][(8 - tap) Co + o] (flipped taps, in/out swapped)
+//   1x1: W[i][o] -> P[o][i];  backward data: P[i][o]
+//   up (2x2, stride 2) forward: W[a][c][i][o] -> P[q = 2a + c][o][i]
+//   up backward data: P[i][q Co + o]
+struct PackDesc {
+    const float* w;
+    uint16_t* out;
+    int mode, back, ci, co, n_pad, k_pad;
+};
+// every entry of a device-resident table, one launch
+hipError_t launch_pack(const PackDesc* tab, int entries, hipStream_t s);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, size_t n, float lr, float b1, float b2, float eps,
                        int step, hipStream_t s);
 hipError_t launch_mse(const float* y, const float* t, size_t n, float* dy, double* part, int nblocks, float* loss,

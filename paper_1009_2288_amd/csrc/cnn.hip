@@ -95,6 +95,64 @@ __device__ __forceinline__ Frag gather_a(const ConvArgs& a, int img, int y, int 
     return f;
 }
 
+// Epilogue of one 16 x 16 output tile formed as D[n][pixel] (the weights as
+// the MFMA's A operand, so that lane l holds 4 consecutive channels
+// n .. n + 3, n = 16 j + 4 (l / 16), of pixel l % 16): bias, ReLU, the fused
+// ReLU mask, then one 8-byte (bf16) or 16-byte (fp32) store.  `vec`: the
+// output and mask slices are 4-channel aligned.
+__device__ __forceinline__ uint2 epi_mask4(const ConvArgs& a, size_t pix, int n, bool ok, bool vec)
+{
+    if (!ok || !a.mask) return make_uint2(0u, 0u);
+    const uint16_t* src = a.mask + pix * a.m_cs + a.m_co + n;
+    if (vec && n + 3 < a.cout) return *reinterpret_cast<const uint2*>(src);
+    uint32_t h[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        if (n + r < a.cout) h[r] = src[r];
+    return make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+}
+
+__device__ __forceinline__ void epi_store4(const ConvArgs& a, size_t pix, int n, const floatx4& acc, uint2 m,
+                                           bool vec)
+{
+    float v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        v[r] = acc[r] + (a.bias && n + r < a.cout ? a.bias[n + r] : 0.0f);
+        if (a.relu) v[r] = fmaxf(v[r], 0.0f);
+        if (a.mask) {
+            const uint32_t w = r < 2 ? m.x : m.y;
+            if (!(bf2f((uint16_t)(w >> (16 * (r & 1)))) > 0.0f)) v[r] = 0.0f;
+        }
+    }
+    const bool full = vec && n + 3 < a.cout;
+    if (a.y32) {
+        float* dst = a.y32 + pix * a.y_cs + a.y_co + n;
+        if (full) {
+            *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (n + r < a.cout) dst[r] = v[r];
+        }
+    } else {
+        uint16_t* dst = a.y + pix * a.y_cs + a.y_co + n;
+        if (full) {
+            *reinterpret_cast<uint2*>(dst) = make_uint2((uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16),
+                                                        (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16));
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (n + r < a.cout) dst[r] = f2bf(v[r]);
+        }
+    }
+}
+
+__device__ __forceinline__ bool epi_vec(const ConvArgs& a)
+{
+    return a.y_cs % 4 == 0 && a.y_co % 4 == 0 && (!a.mask || (a.m_cs % 4 == 0 && a.m_co % 4 == 0));
+}
+
 // Block: 4 waves, each RT x 16 consecutive pixels of the flattened (image, y,
 // x) order of the GEMM grid, x 64 output channels; grid (pixel groups,
 // channel blocks, parity q for kUp).  The block's 64 weight rows are staged in
@@ -205,7 +263,7 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a)
             for (int i = 0; i < RT; ++i)
 #pragma unroll
                 for (int j = 0; j < NT; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i].v, fb[j].v, acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[j].v, fa[i].v, acc[i][j], 0, 0, 0);
 #pragma unroll
             for (int i = 0; i < RT; ++i) {
                 fa[i] = f1[i];
@@ -214,42 +272,25 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a)
         }
     }
     // epilogue: accumulator r of lane l, row tile i, column tile j is pixel
-    // p0 + 16 i + 4 (l / 16) + r, channel n0 + 16 j + l % 16
+    // p0 + 16 i + l % 16 (the lane's own pixel of the gather), channel
+    // n0 + 16 j + 4 (l / 16) + r.  A row tile's mask values are loaded before
+    // its first store (the compiler cannot move loads across stores that
+    // might alias them).
+    const bool vec = epi_vec(a);
 #pragma unroll
-    for (int i = 0; i < RT; ++i)
+    for (int i = 0; i < RT; ++i) {
+        size_t pix;
+        if (MODE == kUp)
+            pix = ((size_t)ia[i] * 2 * a.h + 2 * ya[i] + (q >> 1)) * 2 * a.w + 2 * xa[i] + (q & 1);
+        else
+            pix = (size_t)(p0 + 16 * i + mrow);
+        uint2 mk[NT];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int p = p0 + 16 * i + (lane >> 4) * 4 + r;
-            if (p >= npix) continue;
-            size_t pix;
-            if (MODE == kUp) {
-                int img, y, x;
-                if (row16) {
-                    img = ia[i];
-                    y = ya[i];
-                    x = xt[i] + (lane >> 4) * 4 + r;
-                } else {
-                    img = p / hw;
-                    const int rr = p - img * hw;
-                    y = rr / a.w;
-                    x = rr - y * a.w;
-                }
-                pix = ((size_t)img * 2 * a.h + 2 * y + (q >> 1)) * 2 * a.w + 2 * x + (q & 1);
-            } else {
-                pix = (size_t)p;
-            }
+        for (int j = 0; j < NT; ++j) mk[j] = epi_mask4(a, pix, n0 + 16 * j + kq / 2, va[i], vec);
+        if (!va[i]) continue;
 #pragma unroll
-            for (int j = 0; j < NT; ++j) {
-                const int n = n0 + 16 * j + mrow;
-                if (n >= a.cout) continue;
-                float v = acc[i][j][r] + (a.bias ? a.bias[n] : 0.0f);
-                if (a.relu) v = fmaxf(v, 0.0f);
-                if (a.y32)
-                    a.y32[pix * a.y_cs + a.y_co + n] = v;
-                else
-                    a.y[pix * a.y_cs + a.y_co + n] = f2bf(v);
-            }
-        }
+        for (int j = 0; j < NT; ++j) epi_store4(a, pix, n0 + 16 * j + kq / 2, acc[i][j], mk[j], vec);
+    }
 }
 
 template <int MODE, int NT>
@@ -285,7 +326,7 @@ constexpr int kTapLd = 9 * 32 + 8;      // bf16 per weight row (9 taps x 32 chan
 constexpr int kTileBlocksPerCu = 2;     // persistent blocks per CU
 
 template <int TH, int NT>
-__global__ __launch_bounds__(256) void k_conv3_tile(ConvArgs a, int ntiles)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv3_tile(ConvArgs a, int ntiles)
 {
     constexpr int BN = 16 * NT;       // output channels per block
     constexpr int RPW = TH / 4;       // image rows per wave
@@ -404,34 +445,29 @@ __global__ __launch_bounds__(256) void k_conv3_tile(ConvArgs a, int ntiles)
                 fa.u = *reinterpret_cast<const uint4*>(patch + lbase[i] + toff);
 #pragma unroll
                 for (int j = 0; j < NT; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa.v, fb[j].v, acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[j].v, fa.v, acc[i][j], 0, 0, 0);
             }
         }
         if (c == nch - 1) {
             // epilogue: accumulator r of lane l, row tile i, column tile j is
             // the pixel at local row wave * RPW + i / 2, column
-            // (i % 2) * 16 + 4 (l / 16) + r, channel n0 + 16 j + l % 16
+            // (i % 2) * 16 + l % 16, channel n0 + 16 j + 4 (l / 16) + r; a
+            // row tile's mask values are loaded before its first store
             int img, y0, x0;
             tile_origin(t, img, y0, x0);
+            const bool vec = epi_vec(a);
 #pragma unroll
-            for (int i = 0; i < RT; ++i)
+            for (int i = 0; i < RT; ++i) {
+                const int y = y0 + wave * RPW + (i >> 1), x = x0 + (i & 1) * 16 + mrow;
+                const bool ok = y < a.h && x < a.w;
+                const size_t pix = ((size_t)img * a.h + y) * a.w + x;
+                uint2 mk[NT];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int y = y0 + wave * RPW + (i >> 1), x = x0 + (i & 1) * 16 + (lane >> 4) * 4 + r;
-                    if (y >= a.h || x >= a.w) continue;
-                    const size_t pix = ((size_t)img * a.h + y) * a.w + x;
+                for (int j = 0; j < NT; ++j) mk[j] = epi_mask4(a, pix, n0 + 16 * j + kq / 2, ok, vec);
+                if (!ok) continue;
 #pragma unroll
-                    for (int j = 0; j < NT; ++j) {
-                        const int n = n0 + 16 * j + mrow;
-                        if (n >= a.cout) continue;
-                        float v = acc[i][j][r] + (a.bias ? a.bias[n] : 0.0f);
-                        if (a.relu) v = fmaxf(v, 0.0f);
-                        if (a.y32)
-                            a.y32[pix * a.y_cs + a.y_co + n] = v;
-                        else
-                            a.y[pix * a.y_cs + a.y_co + n] = f2bf(v);
-                    }
-                }
+                for (int j = 0; j < NT; ++j) epi_store4(a, pix, n0 + 16 * j + kq / 2, acc[i][j], mk[j], vec);
+            }
 #pragma unroll
             for (int i = 0; i < RT; ++i)
 #pragma unroll
@@ -535,7 +571,7 @@ hipError_t launch_conv(const ConvArgs& a, int mode, hipStream_t s)
 
 // ------------------------------------------------------------------ weight gradients
 // dW[n][k] = sum_p dY[p][n] A(p, k), split over chunks of pixels: block
-// (chunk, n block, k block) writes its 64 x 64 fp32 partial; k_wgrad_reduce
+// (chunk, n block, k block) writes its 64 x 64 fp32 partial; k_wgrad_finish
 // sums the chunks in order.  The reduction runs over pixels, which are not
 // contiguous in NHWC, so each 64-pixel step stages dY and A transposed in LDS
 // ([channel][pixel], four pixels per 8-byte store); then each wave (2 x 2
@@ -656,21 +692,461 @@ __global__ __launch_bounds__(256) void k_wgrad(ConvArgs a, const uint16_t* __res
     }
 }
 
-// out[i] = sum over c < chunks of part[c * stride + i], i < count, chunks in order
-__global__ void k_wgrad_reduce(const float* __restrict__ part, int chunks, size_t stride, size_t count, float* out)
+// ------------------------------------------------------------------ 3x3 weight gradients from LDS tiles
+// For C_in a multiple of 32 (and 16-byte aligned slices): block = (pixel
+// chunk, 32 output channels from n0, 32 input channels from c0), all 9 taps,
+// i.e. a 32 x 288 slice of dW held in the waves' accumulators while the
+// block walks its chunk's tiles (4 RPW rows x 32 columns of one image).  Per
+// tile it stages dY [pixel][n] and the (4 RPW + 2) x 34 input patch
+// [pixel][c] in LDS exactly as they lie in NHWC memory.  The matrix
+// instructions reduce over pixels: A = dY^T (row n, 32 pixels of one image
+// row), B = the input shifted by the tap (32 pixels x 16 channels).  gfx950's
+// transposing LDS read (ds_read_b64_tr_b16: within each 16-lane group, lane
+// j receives column j of the 4 x 16 block that the group's lanes address,
+// four rows of 4 consecutive columns each) hands a lane 4 consecutive pixels
+// of one channel, so neither tile is ever transposed in registers, and a
+// tap's shift is only a different pixel address.
+//
+// Wave w owns tile rows w RPW .. w RPW + RPW - 1.  It loads the A operands of
+// its rows once per tile and walks the RPW + 2 patch rows: each patch row's
+// three column shifts are loaded once and serve every (output row, tap) pair
+// that reads that patch row (up to three).  The bias gradient sum_p dY[p][n]
+// rides along in the blocks of the first channel chunk as a product with a
+// B operand of ones.  At the end the 4 waves' accumulators are summed in LDS
+// and the block writes its partial[chunk][n][tap C_in + c].
+constexpr int kWg3Ld = 40;  // bf16 per staged pixel (32 channels + 16 B)
+
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) bf16x4 lds_bf16x4;
+
+// the MFMA operand of 8 consecutive pixels (two transposing reads of 4)
+__device__ __forceinline__ bf16x8 tr_frag(const uint16_t* lo, const uint16_t* hi)
 {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
-        float s = 0.0f;
-        int c = 0;
-        for (; c + 8 <= chunks; c += 8) {  // 8 loads in flight, added in chunk order
-            float v[8];
+    const bf16x4 a = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf16x4*)lo);
+    const bf16x4 b = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((lds_bf16x4*)hi);
+    return __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7);
+}
+
+template <int RPW>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_wgrad3(
+    ConvArgs a, const uint16_t* __restrict__ dy, int dy_cs, int dy_co, int tiles_per_chunk, int nbn, int nbc,
+    float* part, float* bpart)
+{
+    constexpr int TH = 4 * RPW, PR = TH + 2;
+    constexpr int DN = TH * 32 * 4, DPT = (DN + 255) / 256;        // dY uint4s, per thread
+    constexpr int PN = PR * kPatchW * 4, PPT = (PN + 255) / 256;   // patch uint4s, per thread
+    __shared__ __attribute__((aligned(16))) uint16_t lds[(TH * 32 + PR * kPatchW) * kWg3Ld];
+    static_assert(sizeof(lds) >= 4 * 16 * 64 * sizeof(float), "the wave reduction reuses the tiles");
+    uint16_t* t_dy = lds;
+    uint16_t* t_x = lds + TH * 32 * kWg3Ld;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // work item: consecutive items share a chunk (and so its tiles) and land
+    // on one XCD's L2
+    const int item = xcd_band((int)blockIdx.x, (int)gridDim.x);
+    const int cb = item % nbc, nb = (item / nbc) % nbn, chunk = item / (nbc * nbn);
+    const int n0 = nb * 32, c0 = cb * 32;
+    const int tiles_x = (a.w + 31) / 32, tiles_y = (a.h + TH - 1) / TH;
+    const int ntiles = a.n_img * tiles_x * tiles_y;
+    const int t_beg = chunk * tiles_per_chunk, t_end = min(ntiles, t_beg + tiles_per_chunk);
+    const bool do_bias = bpart && cb == 0;
+    // lane roles in the transposing reads: group g = lane / 16 covers pixels
+    // 8 g .. 8 g + 7 of a 32-pixel row; lane i of the group addresses pixel
+    // 8 g + 4 h + i / 4 (h: first or second read) and channels 4 (i % 4) .. +3
+    const int px_lane = 8 * (lane >> 4) + ((lane & 15) >> 2), ch_lane = 4 * (lane & 3);
+    floatx4 acc[9][2][2];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) v[j] = part[(size_t)(c + j) * stride + i];
+    for (int t = 0; t < 9; ++t)
 #pragma unroll
-            for (int j = 0; j < 8; ++j) s += v[j];
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[t][i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    floatx4 accb[2] = {floatx4{0.0f, 0.0f, 0.0f, 0.0f}, floatx4{0.0f, 0.0f, 0.0f, 0.0f}};
+    Frag ones;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) ones.h[i] = 0x3f80;  // bf16 1.0
+    for (int t = t_beg; t < t_end; ++t) {
+        const int img = t / (tiles_x * tiles_y), r = t - img * tiles_x * tiles_y;
+        const int ty = r / tiles_x, y0 = ty * TH, x0 = (r - ty * tiles_x) * 32;
+        u32x4 dv[DPT], pv[PPT];
+#pragma unroll
+        for (int u = 0; u < DPT; ++u) {
+            const int idx = threadIdx.x + 256 * u, px = idx >> 2, part8 = (idx & 3) * 8;
+            const int y = y0 + (px >> 5), x = x0 + (px & 31);
+            dv[u] = u32x4{0u, 0u, 0u, 0u};
+            if (idx < DN && y < a.h && x < a.w && n0 + part8 < a.cout)
+                dv[u] = *reinterpret_cast<const u32x4*>(dy + (((size_t)img * a.h + y) * a.w + x) * dy_cs + dy_co + n0 +
+                                                        part8);
         }
-        for (; c < chunks; ++c) s += part[(size_t)c * stride + i];
-        out[i] = s;
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) {
+            const int idx = threadIdx.x + 256 * u, px = idx >> 2, part8 = (idx & 3) * 8;
+            const int pr = px / kPatchW, pc = px - pr * kPatchW;
+            const int y = y0 - 1 + pr, x = x0 - 1 + pc;
+            pv[u] = u32x4{0u, 0u, 0u, 0u};
+            if (idx < PN && (unsigned)y < (unsigned)a.h && (unsigned)x < (unsigned)a.w)
+                pv[u] = *reinterpret_cast<const u32x4*>(a.x + (((size_t)img * a.h + y) * a.w + x) * a.x_cs + a.x_co +
+                                                        c0 + part8);
+        }
+        __syncthreads();  // the previous tile is consumed
+#pragma unroll
+        for (int u = 0; u < DPT; ++u) {
+            const int idx = threadIdx.x + 256 * u;
+            if (idx < DN) *reinterpret_cast<u32x4*>(t_dy + (idx >> 2) * kWg3Ld + (idx & 3) * 8) = dv[u];
+        }
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) {
+            const int idx = threadIdx.x + 256 * u;
+            if (idx < PN) *reinterpret_cast<u32x4*>(t_x + (idx >> 2) * kWg3Ld + (idx & 3) * 8) = pv[u];
+        }
+        __syncthreads();
+        // A operands of the wave's rows: dY^T, channels 16 i + lane % 16
+        bf16x8 fa[RPW][2];
+#pragma unroll
+        for (int rr = 0; rr < RPW; ++rr)
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const uint16_t* p = t_dy + ((wave * RPW + rr) * 32 + px_lane) * kWg3Ld + 16 * i + ch_lane;
+                fa[rr][i] = tr_frag(p, p + 4 * kWg3Ld);
+            }
+        if (do_bias) {
+#pragma unroll
+            for (int rr = 0; rr < RPW; ++rr)
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+                    accb[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[rr][i], ones.v, accb[i], 0, 0, 0);
+        }
+        // patch row wave RPW + pr serves output row rr through tap row
+        // dy = pr - rr - 1 (dy in -1..1)
+#pragma unroll
+        for (int pr = 0; pr < RPW + 2; ++pr) {
+            bf16x8 fb[3][2];
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const uint16_t* p = t_x + ((wave * RPW + pr) * kPatchW + px_lane + dx) * kWg3Ld + 16 * j + ch_lane;
+                    fb[dx][j] = tr_frag(p, p + 4 * kWg3Ld);
+                }
+#pragma unroll
+            for (int rr = 0; rr < RPW; ++rr) {
+                const int dyi = pr - rr;  // tap row index dy + 1
+                if (dyi < 0 || dyi > 2) continue;
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+#pragma unroll
+                        for (int j = 0; j < 2; ++j)
+                            acc[dyi * 3 + dx][i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                fa[rr][i], fb[dx][j], acc[dyi * 3 + dx][i][j], 0, 0, 0);
+            }
+        }
+    }
+    // sum the 4 waves' accumulators through LDS, one tap at a time; lane l's
+    // accumulator r of (i, j) is n = n0 + 16 i + 4 (l / 16) + r,
+    // c = c0 + 16 j + l % 16
+    __syncthreads();
+    float* red = reinterpret_cast<float*>(lds);
+    const size_t kw = a.k_pad;
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) red[(wave * 16 + q) * 64 + lane] = acc[tap][q >> 3][(q >> 2) & 1][q & 3];
+        __syncthreads();
+        for (int e = threadIdx.x; e < 1024; e += 256) {
+            const int q = e >> 6, l = e & 63;
+            const float s = (red[e] + red[1024 + e]) + (red[2048 + e] + red[3072 + e]);
+            const int n = n0 + 16 * (q >> 3) + 4 * (l >> 4) + (q & 3), c = c0 + 16 * ((q >> 2) & 1) + (l & 15);
+            if (n < a.cout) part[((size_t)chunk * a.n_pad + n) * kw + tap * a.cin + c] = s;
+        }
+        __syncthreads();
+    }
+    if (do_bias) {
+        // column 0 (lanes 0, 16, 32, 48) of the ones-product holds the sums
+#pragma unroll
+        for (int q = 0; q < 8; ++q) red[(wave * 8 + q) * 64 + lane] = accb[q >> 2][q & 3];
+        __syncthreads();
+        if (threadIdx.x < 32) {
+            const int t = threadIdx.x, q = (t >> 4) * 4 + (t & 3), l = ((t & 15) >> 2) * 16;
+            const float s = (red[q * 64 + l] + red[(8 + q) * 64 + l]) + (red[(16 + q) * 64 + l] + red[(24 + q) * 64 + l]);
+            if (n0 + t < a.cout) bpart[(size_t)chunk * a.n_pad + n0 + t] = s;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ pointwise weight gradients
+// The 1x1 layer and the stride-2 2x2 transposed convolution (one GEMM per
+// output parity q): dW[q][n][c] = sum_p dY(p, q)[n] X[p][c] over the GEMM's
+// pixels p, dY(p, q) being the output pixel that p writes for parity q.
+// Block = (chunk of 256-pixel tiles, parity, 32 output channels from n0, 32
+// input channels from c0); per tile it stages dY [pixel][n] and X [pixel][c]
+// in LDS as they lie in memory (16-byte loads where the slices allow, else
+// element loads, zero past the channel counts), and wave w reduces pixels
+// 64 w .. 64 w + 63 of the tile with the transposing LDS reads, as in the
+// 3x3 kernel (without taps).  The bias gradient rides along in the blocks of
+// the first channel chunk.
+template <int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_wgrad_pt(
+    ConvArgs a, const uint16_t* __restrict__ dy, int dy_cs, int dy_co, int tiles_per_chunk, int nbn, int nbc,
+    float* part, float* bpart)
+{
+    constexpr int NQ = MODE == kUp ? 4 : 1;
+    __shared__ __attribute__((aligned(16))) uint16_t lds[2 * 256 * kWg3Ld];
+    static_assert(sizeof(lds) >= 4 * 16 * 64 * sizeof(float), "the wave reduction reuses the tiles");
+    uint16_t* t_dy = lds;
+    uint16_t* t_x = lds + 256 * kWg3Ld;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int item = xcd_band((int)blockIdx.x, (int)gridDim.x);
+    const int cb = item % nbc, nb = (item / nbc) % nbn, q = (item / (nbc * nbn)) % NQ;
+    const int chunk = item / (nbc * nbn * NQ);
+    const int n0 = nb * 32, c0 = cb * 32;
+    const int hw = a.h * a.w, npix = a.n_img * hw, ntiles = (npix + 255) / 256;
+    const int t_beg = chunk * tiles_per_chunk, t_end = min(ntiles, t_beg + tiles_per_chunk);
+    const bool do_bias = bpart && cb == 0;
+    const bool dy_vec = dy_cs % 8 == 0 && dy_co % 8 == 0;
+    const bool x_vec = a.x_cs % 8 == 0 && a.x_co % 8 == 0;
+    const int px_lane = 8 * (lane >> 4) + ((lane & 15) >> 2), ch_lane = 4 * (lane & 3);
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    floatx4 accb[2] = {floatx4{0.0f, 0.0f, 0.0f, 0.0f}, floatx4{0.0f, 0.0f, 0.0f, 0.0f}};
+    Frag ones;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) ones.h[i] = 0x3f80;  // bf16 1.0
+    for (int t = t_beg; t < t_end; ++t) {
+        u32x4 dv[4], xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int idx = threadIdx.x + 256 * u, px = idx >> 2, s8 = (idx & 3) * 8;
+            const int p = t * 256 + px;
+            Frag fd = zero_frag(), fx = zero_frag();
+            if (p < npix) {
+                size_t pd = (size_t)p;
+                if (MODE == kUp) {
+                    const int img = p / hw, r = p - img * hw, y = r / a.w, x = r - y * a.w;
+                    pd = ((size_t)img * 2 * a.h + 2 * y + (q >> 1)) * 2 * a.w + 2 * x + (q & 1);
+                }
+                const uint16_t* sd = dy + pd * dy_cs + dy_co + n0 + s8;
+                if (dy_vec && n0 + s8 + 8 <= a.cout) {
+                    fd.u = *reinterpret_cast<const uint4*>(sd);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        if (n0 + s8 + i < a.cout) fd.h[i] = sd[i];
+                }
+                const uint16_t* sx = a.x + (size_t)p * a.x_cs + a.x_co + c0 + s8;
+                if (x_vec && c0 + s8 + 8 <= a.cin) {
+                    fx.u = *reinterpret_cast<const uint4*>(sx);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 8; ++i)
+                        if (c0 + s8 + i < a.cin) fx.h[i] = sx[i];
+                }
+            }
+            dv[u] = u32x4{fd.u.x, fd.u.y, fd.u.z, fd.u.w};
+            xv[u] = u32x4{fx.u.x, fx.u.y, fx.u.z, fx.u.w};
+        }
+        __syncthreads();  // the previous tile is consumed
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int idx = threadIdx.x + 256 * u;
+            *reinterpret_cast<u32x4*>(t_dy + (idx >> 2) * kWg3Ld + (idx & 3) * 8) = dv[u];
+            *reinterpret_cast<u32x4*>(t_x + (idx >> 2) * kWg3Ld + (idx & 3) * 8) = xv[u];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int pr = 64 * wave + 32 * s + px_lane;
+            bf16x8 fa[2], fb[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const uint16_t* p = t_dy + pr * kWg3Ld + 16 * i + ch_lane;
+                fa[i] = tr_frag(p, p + 4 * kWg3Ld);
+                const uint16_t* px = t_x + pr * kWg3Ld + 16 * i + ch_lane;
+                fb[i] = tr_frag(px, px + 4 * kWg3Ld);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+                if (do_bias) accb[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], ones.v, accb[i], 0, 0, 0);
+            }
+        }
+    }
+    // the 4 waves' sums through LDS; lane l's accumulator r of (i, j) is
+    // n = n0 + 16 i + 4 (l / 16) + r, c = c0 + 16 j + l % 16
+    __syncthreads();
+    float* red = reinterpret_cast<float*>(lds);
+    const size_t kw = (size_t)NQ * a.k_pad;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) red[(wave * 16 + e) * 64 + lane] = acc[e >> 3][(e >> 2) & 1][e & 3];
+    __syncthreads();
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+        const int qq = e >> 6, l = e & 63;
+        const float s = (red[e] + red[1024 + e]) + (red[2048 + e] + red[3072 + e]);
+        const int n = n0 + 16 * (qq >> 3) + 4 * (l >> 4) + (qq & 3), c = c0 + 16 * ((qq >> 2) & 1) + (l & 15);
+        if (n < a.cout && c < a.cin) part[((size_t)chunk * a.n_pad + n) * kw + (size_t)q * a.k_pad + c] = s;
+    }
+    if (do_bias) {
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < 8; ++e) red[(wave * 8 + e) * 64 + lane] = accb[e >> 2][e & 3];
+        __syncthreads();
+        if (threadIdx.x < 32) {
+            const int t = threadIdx.x, e = (t >> 4) * 4 + (t & 3), l = ((t & 15) >> 2) * 16;
+            const float s = (red[e * 64 + l] + red[(8 + e) * 64 + l]) + (red[(16 + e) * 64 + l] + red[(24 + e) * 64 + l]);
+            if (n0 + t < a.cout) bpart[((size_t)chunk * NQ + q) * a.n_pad + n0 + t] = s;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ 3x3 weight gradients of a one-channel input
+// The first layer (C_in = 1): K = 9 taps, so per 32-pixel row a lane builds
+// its B operand itself, 8 pixels of one tap read from the staged input patch
+// (column 9 of B is all ones: the bias gradient; columns 10-15 zero), and the
+// A operand (dY^T) comes from the transposing reads as in the other kernels.
+// Block = (chunk of 8 x 32 tiles, 32 output channels from n0).
+__global__ __launch_bounds__(256) void k_wgrad3_c1(ConvArgs a, const uint16_t* __restrict__ dy, int dy_cs, int dy_co,
+                                                   int tiles_per_chunk, int nbn, float* part, float* bpart)
+{
+    constexpr int TH = 8, PR = TH + 2, DN = TH * 32 * 4;
+    __shared__ __attribute__((aligned(16))) uint16_t t_dy[TH * 32 * kWg3Ld];
+    __shared__ uint16_t t_x[PR * kPatchW];
+    static_assert(sizeof(t_dy) >= 4 * 8 * 64 * sizeof(float), "the wave reduction reuses the tile");
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int item = xcd_band((int)blockIdx.x, (int)gridDim.x);
+    const int nb = item % nbn, chunk = item / nbn, n0 = nb * 32;
+    const int tiles_x = (a.w + 31) / 32, tiles_y = (a.h + TH - 1) / TH;
+    const int ntiles = a.n_img * tiles_x * tiles_y;
+    const int t_beg = chunk * tiles_per_chunk, t_end = min(ntiles, t_beg + tiles_per_chunk);
+    const int px_lane = 8 * (lane >> 4) + ((lane & 15) >> 2), ch_lane = 4 * (lane & 3);
+    const int tap = lane & 15, g = lane >> 4;
+    const int tdy = tap / 3, tdx = tap - 3 * (tap / 3);
+    floatx4 acc[2] = {floatx4{0.0f, 0.0f, 0.0f, 0.0f}, floatx4{0.0f, 0.0f, 0.0f, 0.0f}};
+    for (int t = t_beg; t < t_end; ++t) {
+        const int img = t / (tiles_x * tiles_y), r = t - img * tiles_x * tiles_y;
+        const int ty = r / tiles_x, y0 = ty * TH, x0 = (r - ty * tiles_x) * 32;
+        u32x4 dv[DN / 256];
+#pragma unroll
+        for (int u = 0; u < DN / 256; ++u) {
+            const int idx = threadIdx.x + 256 * u, px = idx >> 2, part8 = (idx & 3) * 8;
+            const int y = y0 + (px >> 5), x = x0 + (px & 31);
+            dv[u] = u32x4{0u, 0u, 0u, 0u};
+            if (y < a.h && x < a.w && n0 + part8 < a.cout)
+                dv[u] = *reinterpret_cast<const u32x4*>(dy + (((size_t)img * a.h + y) * a.w + x) * dy_cs + dy_co + n0 +
+                                                        part8);
+        }
+        uint16_t xv[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int idx = threadIdx.x + 256 * u, pr = idx / kPatchW, pc = idx - pr * kPatchW;
+            const int y = y0 - 1 + pr, x = x0 - 1 + pc;
+            xv[u] = 0;
+            if (idx < PR * kPatchW && (unsigned)y < (unsigned)a.h && (unsigned)x < (unsigned)a.w)
+                xv[u] = a.x[(((size_t)img * a.h + y) * a.w + x) * a.x_cs + a.x_co];
+        }
+        __syncthreads();  // the previous tile is consumed
+#pragma unroll
+        for (int u = 0; u < DN / 256; ++u) {
+            const int idx = threadIdx.x + 256 * u;
+            *reinterpret_cast<u32x4*>(t_dy + (idx >> 2) * kWg3Ld + (idx & 3) * 8) = dv[u];
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int idx = threadIdx.x + 256 * u;
+            if (idx < PR * kPatchW) t_x[idx] = xv[u];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr) {
+            const int row = wave * 2 + rr;
+            Frag fb = zero_frag();
+            if (tap < 9) {
+                const uint16_t* src = t_x + (row + tdy) * kPatchW + 8 * g + tdx;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) fb.h[k] = src[k];
+            } else if (tap == 9) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) fb.h[k] = 0x3f80;  // bf16 1.0
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const uint16_t* p = t_dy + (row * 32 + px_lane) * kWg3Ld + 16 * i + ch_lane;
+                acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(tr_frag(p, p + 4 * kWg3Ld), fb.v, acc[i], 0, 0, 0);
+            }
+        }
+    }
+    // lane l's accumulator r of n-tile i: n = n0 + 16 i + 4 (l / 16) + r, tap l % 16
+    __syncthreads();
+    float* red = reinterpret_cast<float*>(t_dy);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) red[(wave * 8 + e) * 64 + lane] = acc[e >> 2][e & 3];
+    __syncthreads();
+    for (int e = threadIdx.x; e < 512; e += 256) {
+        const int qq = e >> 6, l = e & 63;
+        const float s = (red[e] + red[512 + e]) + (red[1024 + e] + red[1536 + e]);
+        const int n = n0 + 16 * (qq >> 2) + 4 * (l >> 4) + (qq & 3), k = l & 15;
+        if (n >= a.cout) continue;
+        if (k < 9) part[((size_t)chunk * a.n_pad + n) * a.k_pad + k] = s;
+        else if (k == 9 && bpart) bpart[(size_t)chunk * a.n_pad + n] = s;
+    }
+}
+
+// The weight and bias gradients from the blocks' partials, written straight
+// into the parameter layout: element i < co kw of the packed [n][kw] grid
+// (n = i / kw, k = i % kw) sums part[c stride + i] over the chunks c and goes
+// to the weight array ([3][3][C_in][C_out], [C_in][C_out] or
+// [2][2][C_in][C_out], i.e. index (k-row) C_out + n); the co elements after
+// them sum the bias partials bpart[c n_pad + n] over bchunks.  A block covers
+// 32 elements with 8 slices: slice s adds chunks s, s + 8, ... in order, then
+// the 8 slice sums are added in order of s (a fixed order, so the result does
+// not depend on the launch).
+constexpr int kRedSlices = 8;
+
+__global__ __launch_bounds__(256) void k_wgrad_finish(const float* __restrict__ part, int chunks, size_t stride,
+                                                      int kw, int mode, int ci, int co, int k_pad,
+                                                      const float* __restrict__ bpart, int bchunks, int n_pad,
+                                                      float* gw, float* gb)
+{
+    __shared__ float red[kRedSlices][32];
+    const int e = threadIdx.x & 31, sl = threadIdx.x >> 5;
+    const size_t count = (size_t)co * kw, total = count + (gb ? co : 0);
+    const size_t i = (size_t)blockIdx.x * 32 + e;
+    const float* src = i < count ? part + i : bpart + (i - count);
+    const size_t st = i < count ? stride : (size_t)n_pad;
+    const int nc = i < count ? chunks : bchunks;
+    float s = 0.0f;
+    if (i < total) {
+        int c = sl;
+        for (; c + 3 * kRedSlices < nc; c += 4 * kRedSlices) {  // 4 loads in flight
+            float v[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = src[(size_t)(c + j * kRedSlices) * st];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) s += v[j];
+        }
+        for (; c < nc; c += kRedSlices) s += src[(size_t)c * st];
+    }
+    red[sl][e] = s;
+    __syncthreads();
+    if (sl == 0 && i < total) {
+        float t = red[0][e];
+#pragma unroll
+        for (int j = 1; j < kRedSlices; ++j) t += red[j][e];
+        if (i >= count) {
+            gb[i - count] = t;
+        } else {
+            const int n = (int)(i / kw), k = (int)(i - (size_t)n * kw);
+            if (mode == kUp) {
+                const int q = k / k_pad, c = k - q * k_pad;
+                if (c < ci) gw[((size_t)q * ci + c) * co + n] = t;
+            } else if (k < (mode == kConv3 ? 9 * ci : ci)) {
+                gw[(size_t)k * co + n] = t;
+            }
+        }
     }
 }
 
@@ -696,81 +1172,93 @@ int wgrad_chunk_px(int npix, int n_pad, int kw)
     return (px + 63) / 64 * 64;  // ceil(npix / px) <= chunks
 }
 
+// k_wgrad3 applies: a 3x3 layer with C_in a multiple of 32 and 16-byte
+// aligned slices; k_wgrad3_c1: a 3x3 layer with one input channel
+static bool wgrad3_fits(const ConvArgs& a, int mode, int dy_cs, int dy_co)
+{
+    return mode == kConv3 && a.cin % 32 == 0 && a.cout % 8 == 0 && a.x_cs % 8 == 0 && a.x_co % 8 == 0 &&
+           dy_cs % 8 == 0 && dy_co % 8 == 0;
+}
+
+static bool wgrad3_c1_fits(const ConvArgs& a, int mode, int dy_cs, int dy_co)
+{
+    return mode == kConv3 && a.cin == 1 && a.cout % 8 == 0 && dy_cs % 8 == 0 && dy_co % 8 == 0;
+}
+
+constexpr int kWg3Rpw = 2;       // rows per wave: 8-row tiles
+constexpr int kWg3Blocks = 512;  // about two blocks per CU
+
+static long long wgrad3_tiles(int n_img, int h, int w)
+{
+    return (long long)n_img * ((h + 4 * kWg3Rpw - 1) / (4 * kWg3Rpw)) * ((w + 31) / 32);
+}
+
+static long long wgrad_pt_tiles(int n_img, int h, int w) { return ((long long)n_img * h * w + 255) / 256; }
+
+// chunks over nt tiles for m blocks per chunk: about kWg3Blocks blocks in
+// all, every chunk non-empty
+static int tile_chunks(long long nt, long long m, int* tiles_per_chunk)
+{
+    const long long t = std::max(1LL, (nt * m + kWg3Blocks - 1) / kWg3Blocks);
+    *tiles_per_chunk = (int)t;
+    return (int)((nt + t - 1) / t);
+}
+
+// chunks of the LDS-tiled kernels (0 where none applies); an upper bound over
+// every batch up to n_img: ceil(nt / ceil(nt m / B)) <= min(nt, ceil(B / m))
+int wgrad_tiled_max_chunks(int mode, int n_img, int h, int w, int ci, int co)
+{
+    const long long nbn = (co + 31) / 32;
+    long long nt, m;
+    if (mode == kConv3 && (ci % 32 == 0 || ci == 1)) {
+        nt = wgrad3_tiles(n_img, h, w);
+        m = nbn * std::max(1, ci / 32);
+    } else if (mode == kPoint || mode == kUp) {
+        nt = wgrad_pt_tiles(n_img, h, w);
+        m = nbn * ((ci + 31) / 32) * (mode == kUp ? 4 : 1);
+    } else {
+        return 0;
+    }
+    return (int)std::min(nt, (kWg3Blocks + m - 1) / m);
+}
+
 hipError_t launch_wgrad(const ConvArgs& a, int mode, const uint16_t* dy, int dy_cs, int dy_co, int chunk_px,
                         float* part, float* out, float* bpart, float* bias_out, hipStream_t s)
 {
-    const int chunks = wgrad_chunks(a, chunk_px);
     const int kw = mode == kUp ? 4 * a.k_pad : a.k_pad;
     float* bp = bias_out ? bpart : nullptr;
-    dim3 grid((unsigned)chunks, (unsigned)(a.n_pad / 64), (unsigned)(kw / 64));
-    switch (mode) {
-    case kConv3:
+    int chunks, tpc = 1;
+    const int nbn = (a.cout + 31) / 32;
+    if (wgrad3_fits(a, mode, dy_cs, dy_co)) {
+        const int nbc = a.cin / 32;
+        chunks = tile_chunks(wgrad3_tiles(a.n_img, a.h, a.w), (long long)nbn * nbc, &tpc);
+        hipLaunchKernelGGL(k_wgrad3<kWg3Rpw>, dim3((unsigned)(chunks * nbn * nbc)), dim3(256), 0, s, a, dy, dy_cs,
+                           dy_co, tpc, nbn, nbc, part, bp);
+    } else if (wgrad3_c1_fits(a, mode, dy_cs, dy_co)) {
+        chunks = tile_chunks(wgrad3_tiles(a.n_img, a.h, a.w), nbn, &tpc);
+        hipLaunchKernelGGL(k_wgrad3_c1, dim3((unsigned)(chunks * nbn)), dim3(256), 0, s, a, dy, dy_cs, dy_co, tpc,
+                           nbn, part, bp);
+    } else if (mode == kPoint || mode == kUp) {
+        const int nbc = (a.cin + 31) / 32, nq = mode == kUp ? 4 : 1;
+        chunks = tile_chunks(wgrad_pt_tiles(a.n_img, a.h, a.w), (long long)nbn * nbc * nq, &tpc);
+        const dim3 g((unsigned)(chunks * nbn * nbc * nq));
+        if (mode == kUp)
+            hipLaunchKernelGGL(k_wgrad_pt<kUp>, g, dim3(256), 0, s, a, dy, dy_cs, dy_co, tpc, nbn, nbc, part, bp);
+        else
+            hipLaunchKernelGGL(k_wgrad_pt<kPoint>, g, dim3(256), 0, s, a, dy, dy_cs, dy_co, tpc, nbn, nbc, part, bp);
+    } else {
+        chunks = wgrad_chunks(a, chunk_px);
+        dim3 grid((unsigned)chunks, (unsigned)(a.n_pad / 64), (unsigned)(kw / 64));
         hipLaunchKernelGGL(k_wgrad<kConv3>, grid, dim3(256), 0, s, a, dy, dy_cs, dy_co, chunk_px, part, bp);
-        break;
-    case kPoint:
-        hipLaunchKernelGGL(k_wgrad<kPoint>, grid, dim3(256), 0, s, a, dy, dy_cs, dy_co, chunk_px, part, bp);
-        break;
-    case kUp:
-        hipLaunchKernelGGL(k_wgrad<kUp>, grid, dim3(256), 0, s, a, dy, dy_cs, dy_co, chunk_px, part, bp);
-        break;
-    default:
-        hipLaunchKernelGGL(k_wgrad<kUpBack>, grid, dim3(256), 0, s, a, dy, dy_cs, dy_co, chunk_px, part, bp);
-        break;
     }
-    const size_t per = (size_t)a.n_pad * kw;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)std::min<size_t>((per + 255) / 256, 4096)), dim3(256), 0, s,
-                       part, chunks, per, per, out);
-    if (bias_out) {
-        const int nq = mode == kUp ? 4 : 1;
-        hipLaunchKernelGGL(k_wgrad_reduce, dim3(1), dim3(256), 0, s, bpart, chunks * nq, (size_t)a.n_pad,
-                           (size_t)a.cout, bias_out);
-    }
+    const size_t total = (size_t)a.cout * kw + (bias_out ? a.cout : 0);
+    hipLaunchKernelGGL(k_wgrad_finish, dim3((unsigned)((total + 31) / 32)), dim3(256), 0, s, part, chunks,
+                       (size_t)a.n_pad * kw, kw, mode, a.cin, a.cout, a.k_pad, bpart, chunks * (mode == kUp ? 4 : 1),
+                       a.n_pad, out, bias_out);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ elementwise
-// dy *= (y > 0): the ReLU's backward, in place on a channel slice
-__global__ void k_relu_mask(uint16_t* dy, int dcs, int dco, const uint16_t* y, int ycs, int yco, int npix, int c)
-{
-    const size_t n = (size_t)npix * c;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const size_t p = i / c, k = i - p * c;
-        if (!(bf2f(y[p * ycs + yco + k]) > 0.0f)) dy[p * dcs + dco + k] = 0;
-    }
-}
-
-// the same, 8 channels (16 bytes) per thread for 16-byte aligned slices
-__global__ void k_relu_mask8(uint16_t* dy, int dcs, int dco, const uint16_t* y, int ycs, int yco, int npix, int c8)
-{
-    const size_t n = (size_t)npix * c8;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const size_t p = i / c8, k = (i - p * c8) * 8;
-        Frag yv, dv;
-        yv.u = *reinterpret_cast<const uint4*>(y + p * ycs + yco + k);
-        uint4* dp = reinterpret_cast<uint4*>(dy + p * dcs + dco + k);
-        dv.u = *dp;
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-            if (!(bf2f(yv.h[j]) > 0.0f)) dv.h[j] = 0;
-        *dp = dv.u;
-    }
-}
-
-hipError_t launch_relu_mask(uint16_t* dy, int dcs, int dco, const uint16_t* y, int ycs, int yco, int npix, int c,
-                            hipStream_t s)
-{
-    if (c % 8 == 0 && dcs % 8 == 0 && dco % 8 == 0 && ycs % 8 == 0 && yco % 8 == 0) {
-        const size_t n = (size_t)npix * (c / 8);
-        hipLaunchKernelGGL(k_relu_mask8, dim3((unsigned)std::min<size_t>((n + 255) / 256, 8192)), dim3(256), 0, s,
-                           dy, dcs, dco, y, ycs, yco, npix, c / 8);
-        return hipGetLastError();
-    }
-    const size_t n = (size_t)npix * c;
-    hipLaunchKernelGGL(k_relu_mask, dim3((unsigned)std::min<size_t>((n + 255) / 256, 8192)), dim3(256), 0, s, dy, dcs,
-                       dco, y, ycs, yco, npix, c);
-    return hipGetLastError();
-}
-
 // 2x2 average pooling and its adjoint (channel slices)
 __global__ void k_avgpool(const uint16_t* x, int xcs, int xco, uint16_t* y, int n_img, int h, int w, int c)
 {
@@ -791,7 +1279,7 @@ __global__ void k_avgpool(const uint16_t* x, int xcs, int xco, uint16_t* y, int 
 }
 
 __global__ void k_avgpool_back(const uint16_t* dy, uint16_t* dx, int dxcs, int dxco, int n_img, int h, int w, int c,
-                               int accumulate)
+                               int accumulate, const uint16_t* mask, int mcs, int mco)
 {
     // dx has h x w pixels; dy has h/2 x w/2 with c channels (dense)
     const size_t n = (size_t)n_img * h * w * c;
@@ -803,8 +1291,10 @@ __global__ void k_avgpool_back(const uint16_t* dy, uint16_t* dx, int dxcs, int d
         const int y = (int)(t % h);
         const int img = (int)(t / h);
         float v = 0.25f * bf2f(dy[(((size_t)img * (h / 2) + y / 2) * (w / 2) + x / 2) * c + k]);
-        uint16_t* d = dx + (((size_t)img * h + y) * w + x) * dxcs + dxco + k;
+        const size_t px = ((size_t)img * h + y) * w + x;
+        uint16_t* d = dx + px * dxcs + dxco + k;
         if (accumulate) v += bf2f(*d);
+        if (mask && !(bf2f(mask[px * mcs + mco + k]) > 0.0f)) v = 0.0f;
         *d = f2bf(v);
     }
 }
@@ -839,7 +1329,7 @@ __global__ void k_avgpool8(const uint16_t* x, int xcs, int xco, uint16_t* y, int
 }
 
 __global__ void k_avgpool_back8(const uint16_t* dy, uint16_t* dx, int dxcs, int dxco, int n_img, int h, int w, int c8,
-                                int accumulate)
+                                int accumulate, const uint16_t* mask, int mcs, int mco)
 {
     const size_t n = (size_t)n_img * h * w * c8;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
@@ -853,10 +1343,13 @@ __global__ void k_avgpool_back8(const uint16_t* dy, uint16_t* dx, int dxcs, int 
         g.u = *reinterpret_cast<const uint4*>(dy + (((size_t)img * (h / 2) + y / 2) * (w / 2) + x / 2) * c8 * 8 + k);
         uint4* d = reinterpret_cast<uint4*>(dx + t * dxcs + dxco + k);
         if (accumulate) o.u = *d;
+        Frag m;
+        if (mask) m.u = *reinterpret_cast<const uint4*>(mask + t * mcs + mco + k);
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             float v = 0.25f * bf2f(g.h[j]);
             if (accumulate) v += bf2f(o.h[j]);
+            if (mask && !(bf2f(m.h[j]) > 0.0f)) v = 0.0f;
             o.h[j] = f2bf(v);
         }
         *d = o.u;
@@ -879,17 +1372,17 @@ hipError_t launch_avgpool(const uint16_t* x, int xcs, int xco, uint16_t* y, int 
 }
 
 hipError_t launch_avgpool_back(const uint16_t* dy, uint16_t* dx, int dxcs, int dxco, int n_img, int h, int w, int c,
-                               int accumulate, hipStream_t s)
+                               int accumulate, const uint16_t* mask, int mcs, int mco, hipStream_t s)
 {
-    if (c % 8 == 0 && dxcs % 8 == 0 && dxco % 8 == 0) {
+    if (c % 8 == 0 && dxcs % 8 == 0 && dxco % 8 == 0 && (!mask || (mcs % 8 == 0 && mco % 8 == 0))) {
         const size_t n8 = (size_t)n_img * h * w * (c / 8);
         hipLaunchKernelGGL(k_avgpool_back8, dim3((unsigned)std::min<size_t>((n8 + 255) / 256, 8192)), dim3(256), 0, s,
-                           dy, dx, dxcs, dxco, n_img, h, w, c / 8, accumulate);
+                           dy, dx, dxcs, dxco, n_img, h, w, c / 8, accumulate, mask, mcs, mco);
         return hipGetLastError();
     }
     const size_t n = (size_t)n_img * h * w * c;
     hipLaunchKernelGGL(k_avgpool_back, dim3((unsigned)std::min<size_t>((n + 255) / 256, 8192)), dim3(256), 0, s, dy, dx,
-                       dxcs, dxco, n_img, h, w, c, accumulate);
+                       dxcs, dxco, n_img, h, w, c, accumulate, mask, mcs, mco);
     return hipGetLastError();
 }
 
@@ -945,27 +1438,32 @@ hipError_t launch_add_slice(const uint16_t* src, int scs, int sco, uint16_t* dst
 //   1x1: W[i][o] -> P[o][i];  backward data: P[i][o]
 //   up (2x2, stride 2) forward: W[a][c][i][o] -> P[q = 2a + c][o][i]
 //   up backward data: P[i][q Co + o]
-__global__ void k_pack(const float* w, int mode, int back, int ci, int co, int n_pad, int k_pad, uint16_t* out)
+// One launch packs every table entry: blockIdx.y selects the entry, the
+// x blocks stride over its elements.
+__global__ __launch_bounds__(256) void k_pack(const PackDesc* __restrict__ tab)
 {
-    const int nq = (mode == kUp && !back) ? 4 : 1;
-    const size_t total = (size_t)nq * n_pad * k_pad;
+    const PackDesc d = tab[blockIdx.y];
+    const int nq = (d.mode == kUp && !d.back) ? 4 : 1;
+    const int ci = d.ci, co = d.co, k_pad = d.k_pad;
+    const size_t plane = (size_t)d.n_pad * k_pad, total = (size_t)nq * plane;
+    const float* w = d.w;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-        const int q = (int)(e / ((size_t)n_pad * k_pad));
-        const size_t r = e - (size_t)q * n_pad * k_pad;
+        const int q = (int)(e / plane);
+        const size_t r = e - (size_t)q * plane;
         const int n = (int)(r / k_pad), k = (int)(r - (size_t)n * k_pad);
         float v = 0.0f;
-        if (mode == kConv3 && !back) {
-            if (n < co && k < 9 * ci) v = w[((size_t)(k / ci) * ci + k % ci) * co + n];
-        } else if (mode == kConv3) {
+        if (d.mode == kConv3 && !d.back) {
+            if (n < co && k < 9 * ci) v = w[(size_t)k * co + n];
+        } else if (d.mode == kConv3) {
             if (n < ci && k < 9 * co) {
                 const int tap = 8 - k / co, o = k % co;
                 v = w[((size_t)tap * ci + n) * co + o];
             }
-        } else if (mode == kPoint && !back) {
+        } else if (d.mode == kPoint && !d.back) {
             if (n < co && k < ci) v = w[(size_t)k * co + n];
-        } else if (mode == kPoint) {
+        } else if (d.mode == kPoint) {
             if (n < ci && k < co) v = w[(size_t)n * co + k];
-        } else if (!back) {  // up forward, parity q
+        } else if (!d.back) {  // up forward, parity q
             if (n < co && k < ci) v = w[((size_t)q * ci + k) * co + n];
         } else {  // up backward data
             if (n < ci && k < 4 * co) {
@@ -973,40 +1471,14 @@ __global__ void k_pack(const float* w, int mode, int back, int ci, int co, int n
                 v = w[((size_t)qq * ci + n) * co + o];
             }
         }
-        out[e] = f2bf(v);
+        d.out[e] = f2bf(v);
     }
 }
 
-hipError_t launch_pack(const float* w, int mode, int back, int ci, int co, int n_pad, int k_pad, uint16_t* out,
-                       hipStream_t s)
+hipError_t launch_pack(const PackDesc* tab, int entries, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_pack, dim3(1024), dim3(256), 0, s, w, mode, back, ci, co, n_pad, k_pad, out);
-    return hipGetLastError();
-}
-
-// packed [q][n_pad][k_pad] fp32 weight gradient -> oracle layout gradient
-__global__ void k_unpack_grad(const float* g, int mode, int ci, int co, int n_pad, int k_pad, float* out)
-{
-    const size_t total = mode == kConv3 ? (size_t)9 * ci * co : (mode == kUp ? (size_t)4 * ci * co : (size_t)ci * co);
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
-        const int o = (int)(e % co);
-        const size_t t = e / co;
-        const int i = (int)(t % ci), tap = (int)(t / ci);
-        size_t src;
-        if (mode == kConv3)
-            src = (size_t)o * k_pad + (size_t)tap * ci + i;
-        else if (mode == kPoint)
-            src = (size_t)o * k_pad + i;
-        else  // gradient of the up weights laid out [n][4 k_pad] (the 4 parities side by side)
-            src = (size_t)o * 4 * k_pad + (size_t)tap * k_pad + i;
-        out[e] = g[src];
-    }
-}
-
-hipError_t launch_unpack_grad(const float* g, int mode, int ci, int co, int n_pad, int k_pad, float* out,
-                              hipStream_t s)
-{
-    hipLaunchKernelGGL(k_unpack_grad, dim3(1024), dim3(256), 0, s, g, mode, ci, co, n_pad, k_pad, out);
+    if (entries <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack, dim3(64, (unsigned)entries), dim3(256), 0, s, tab);
     return hipGetLastError();
 }
 
@@ -1053,20 +1525,27 @@ __global__ __launch_bounds__(256) void k_mse(const float* y, const float* t, siz
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-__global__ void k_sum_parts(const double* part, int n, double scale, float* out)
+// out = scale * sum of part[0 .. n): thread t adds t, t + 256, ... in order,
+// then a fixed-order tree over the 256 sums
+__global__ __launch_bounds__(256) void k_sum_parts(const double* part, int n, double scale, float* out)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < n; ++i) s += part[i];
-        out[0] = (float)(s * scale);
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) out[0] = (float)(red[0] * scale);
 }
 
 hipError_t launch_mse(const float* y, const float* t, size_t n, float* dy, double* part, int nblocks, float* loss,
                       hipStream_t s)
 {
     hipLaunchKernelGGL(k_mse, dim3((unsigned)nblocks), dim3(256), 0, s, y, t, n, dy, part);
-    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, part, nblocks, 1.0 / (double)n, loss);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, part, nblocks, 1.0 / (double)n, loss);
     return hipGetLastError();
 }
 

@@ -33,7 +33,6 @@ struct Layer {
     int nb_pad = 0, kb_pad = 0;              // backward-data GEMM
     uint16_t* wf = nullptr;                  // packed forward weights
     uint16_t* wb = nullptr;                  // packed backward-data weights
-    float* gpack = nullptr;                  // packed weight gradient
 };
 
 struct Tensor {
@@ -61,6 +60,8 @@ struct eptv_unet_s {
     size_t part_floats = 0;
     float* bpart = nullptr;                           // bias-gradient partials
     double* mse_part = nullptr;
+    eptv::PackDesc* pack_tab = nullptr;               // device: forward and backward packing of every layer
+    int pack_n = 0;
     std::vector<void*> allocs;
 };
 
@@ -93,17 +94,7 @@ static ConvArgs conv_args(const eptv_unet_s& u, const Layer& L, int n, int h, in
     return a;
 }
 
-static hipError_t repack(eptv_unet_s& u, hipStream_t s)
-{
-    hipError_t e = hipSuccess;
-    for (Layer& L : u.layers) {
-        if (e == hipSuccess) e = launch_pack(u.params + L.w_off, L.mode, 0, L.ci, L.co, L.n_pad, L.k_pad, L.wf, s);
-        if (e == hipSuccess)
-            e = launch_pack(u.params + L.w_off, L.mode == kUp ? kUp : L.mode, 1, L.ci, L.co, L.nb_pad, L.kb_pad, L.wb,
-                            s);
-    }
-    return e;
-}
+static hipError_t repack(eptv_unet_s& u, hipStream_t s) { return launch_pack(u.pack_tab, u.pack_n, s); }
 
 static hipError_t forward(eptv_unet_s& u, const float* x, int n, float* y, hipStream_t s)
 {
@@ -170,15 +161,14 @@ static hipError_t layer_grads(eptv_unet_s& u, int li, int n, int h, int w, const
     a.x_cs = xcs;
     a.x_co = xco;
     const int cpx = wgrad_chunk_px(n * h * w, Ly.n_pad, (Ly.mode == kUp ? 4 : 1) * Ly.k_pad);
-    hipError_t e = launch_wgrad(a, Ly.mode, dy, dycs, dyco, cpx, u.part, Ly.gpack, u.bpart,
-                                u.grads + Ly.b_off, s);
-    if (e != hipSuccess) return e;
-    return launch_unpack_grad(Ly.gpack, Ly.mode, Ly.ci, Ly.co, Ly.n_pad, Ly.k_pad, u.grads + Ly.w_off, s);
+    return launch_wgrad(a, Ly.mode, dy, dycs, dyco, cpx, u.part, u.grads + Ly.w_off, u.bpart, u.grads + Ly.b_off, s);
 }
 
-// backward data of layer li: gradient of its input from its output gradient
+// backward data of layer li: gradient of its input from its output gradient;
+// with mask (the input, where it is a ReLU's output), the ReLU's backward is
+// applied in the same epilogue
 static hipError_t layer_back(eptv_unet_s& u, int li, int n, int h, int w, const uint16_t* dy, int dycs, int dyco,
-                             uint16_t* dx, int dxcs, int dxco, hipStream_t s)
+                             uint16_t* dx, int dxcs, int dxco, const Tensor* mask, hipStream_t s)
 {
     const Layer& Ly = u.layers[li];
     ConvArgs a = conv_args(u, Ly, n, h, w, true);
@@ -188,9 +178,19 @@ static hipError_t layer_back(eptv_unet_s& u, int li, int n, int h, int w, const 
     a.y = dx;
     a.y_cs = dxcs;
     a.y_co = dxco;
+    if (mask) {
+        a.mask = mask->p;
+        a.m_cs = mask->c;
+        a.m_co = dxco;
+    }
     return launch_conv(a, Ly.mode == kUp ? kUpBack : Ly.mode, s);
 }
 
+// Every gradient that flows into a ReLU's output is masked where it is
+// produced: by the backward-data epilogue of the layer that consumed the
+// ReLU's output, or (the encoder outputs, which also feed the pooling) by the
+// pooling adjoint that adds the second contribution.  Masking is a product
+// with 0 / 1, so masking each contribution equals masking their sum.
 static hipError_t backward(eptv_unet_s& u, const float* dy, float* dx, hipStream_t s)
 {
     hipError_t e;
@@ -202,54 +202,57 @@ static hipError_t backward(eptv_unet_s& u, const float* dy, float* dx, hipStream
     if ((e = layer_grads(u, hl, n, u.h, u.w, last.p, last.c, 0, u.g_head.p, u.c_out, 0, s)) != hipSuccess)
         return e;
     Tensor g_last = L > 1 ? u.g_db[0] : u.g_bout;
-    if ((e = layer_back(u, hl, n, u.h, u.w, u.g_head.p, u.c_out, 0, g_last.p, g_last.c, 0, s)) != hipSuccess)
+    if ((e = layer_back(u, hl, n, u.h, u.w, u.g_head.p, u.c_out, 0, g_last.p, g_last.c, 0, &last, s)) != hipSuccess)
         return e;
     // decoder, from the top level down the U
     for (int l = 0; l <= L - 2; ++l) {
-        const int h = u.h >> l, w = u.w >> l, C = u.base << l, np = n * h * w;
+        const int h = u.h >> l, w = u.w >> l, C = u.base << l;
         const int lb = layer_index(u, 'd', l, 'b'), la = layer_index(u, 'd', l, 'a'), lu = layer_index(u, 'u', l, 0);
-        if ((e = launch_relu_mask(u.g_db[l].p, C, 0, u.db[l].p, C, 0, np, C, s)) != hipSuccess) return e;
         if ((e = layer_grads(u, lb, n, h, w, u.da[l].p, C, 0, u.g_db[l].p, C, 0, s)) != hipSuccess) return e;
-        if ((e = layer_back(u, lb, n, h, w, u.g_db[l].p, C, 0, u.g_da[l].p, C, 0, s)) != hipSuccess) return e;
-        if ((e = launch_relu_mask(u.g_da[l].p, C, 0, u.da[l].p, C, 0, np, C, s)) != hipSuccess) return e;
+        if ((e = layer_back(u, lb, n, h, w, u.g_db[l].p, C, 0, u.g_da[l].p, C, 0, &u.da[l], s)) != hipSuccess)
+            return e;
         if ((e = layer_grads(u, la, n, h, w, u.cat[l].p, 2 * C, 0, u.g_da[l].p, C, 0, s)) != hipSuccess)
             return e;
-        if ((e = layer_back(u, la, n, h, w, u.g_da[l].p, C, 0, u.g_cat[l].p, 2 * C, 0, s)) != hipSuccess) return e;
-        // the upsampled half: ReLU mask, then the transposed convolution
-        if ((e = launch_relu_mask(u.g_cat[l].p, 2 * C, C, u.cat[l].p, 2 * C, C, np, C, s)) != hipSuccess) return e;
+        // both halves of the concatenation are ReLU outputs (the skip: the
+        // encoder's; the upper half: the transposed convolution's)
+        if ((e = layer_back(u, la, n, h, w, u.g_da[l].p, C, 0, u.g_cat[l].p, 2 * C, 0, &u.cat[l], s)) != hipSuccess)
+            return e;
         const Tensor& up_in = l == L - 2 ? u.bout : u.db[l + 1];
         Tensor& g_up_in = l == L - 2 ? u.g_bout : u.g_db[l + 1];
         if ((e = layer_grads(u, lu, n, h / 2, w / 2, up_in.p, up_in.c, 0, u.g_cat[l].p, 2 * C, C, s)) !=
             hipSuccess)
             return e;
-        if ((e = layer_back(u, lu, n, h / 2, w / 2, u.g_cat[l].p, 2 * C, C, g_up_in.p, g_up_in.c, 0, s)) != hipSuccess)
+        if ((e = layer_back(u, lu, n, h / 2, w / 2, u.g_cat[l].p, 2 * C, C, g_up_in.p, g_up_in.c, 0, &up_in, s)) !=
+            hipSuccess)
             return e;
     }
     // encoder, from the bottleneck up
     for (int l = L - 1; l >= 0; --l) {
-        const int h = u.h >> l, w = u.w >> l, C = u.base << l, np = n * h * w;
+        const int h = u.h >> l, w = u.w >> l, C = u.base << l;
         const int lb = layer_index(u, 'e', l, 'b'), la = layer_index(u, 'e', l, 'a');
         // gradient of the level output: the skip half of the concatenation (or
         // the bottleneck's), plus the pooling path into level l+1
         Tensor gout = l < L - 1 ? u.g_cat[l] : u.g_bout;
         const Tensor& out = l < L - 1 ? u.cat[l] : u.bout;
         if (l < L - 1) {
-            if ((e = launch_avgpool_back(u.g_in[l + 1].p, gout.p, gout.c, 0, n, h, w, C, 1, s)) != hipSuccess)
+            if ((e = launch_avgpool_back(u.g_in[l + 1].p, gout.p, gout.c, 0, n, h, w, C, 1, out.p, out.c, 0, s)) !=
+                hipSuccess)
                 return e;
         }
-        if ((e = launch_relu_mask(gout.p, gout.c, 0, out.p, out.c, 0, np, C, s)) != hipSuccess) return e;
         if ((e = layer_grads(u, lb, n, h, w, u.a[l].p, C, 0, gout.p, gout.c, 0, s)) != hipSuccess) return e;
-        if ((e = layer_back(u, lb, n, h, w, gout.p, gout.c, 0, u.g_a[l].p, C, 0, s)) != hipSuccess) return e;
-        if ((e = launch_relu_mask(u.g_a[l].p, C, 0, u.a[l].p, C, 0, np, C, s)) != hipSuccess) return e;
+        if ((e = layer_back(u, lb, n, h, w, gout.p, gout.c, 0, u.g_a[l].p, C, 0, &u.a[l], s)) != hipSuccess)
+            return e;
         const Tensor& inp = l == 0 ? u.xin : u.in[l];
         if ((e = layer_grads(u, la, n, h, w, inp.p, inp.c, 0, u.g_a[l].p, C, 0, s)) != hipSuccess) return e;
         if (l > 0) {
-            if ((e = layer_back(u, la, n, h, w, u.g_a[l].p, C, 0, u.g_in[l].p, u.g_in[l].c, 0, s)) != hipSuccess)
+            if ((e = layer_back(u, la, n, h, w, u.g_a[l].p, C, 0, u.g_in[l].p, u.g_in[l].c, 0, nullptr, s)) !=
+                hipSuccess)
                 return e;
         } else if (dx) {
             // input gradient (bf16 through g_in[0]) to fp32: via the head-gradient buffer's width is not
             // enough in general, so g_in[0] holds it and the caller reads it converted below
-            if ((e = layer_back(u, la, n, h, w, u.g_a[l].p, C, 0, u.g_in[0].p, u.g_in[0].c, 0, s)) != hipSuccess)
+            if ((e = layer_back(u, la, n, h, w, u.g_a[l].p, C, 0, u.g_in[0].p, u.g_in[0].c, 0, nullptr, s)) !=
+                hipSuccess)
                 return e;
         }
     }
@@ -344,7 +347,6 @@ int eptv_unet_create(int c_in, int c_out, int base, int levels, int max_batch, i
         const int q = Ly.mode == kUp ? 4 : 1;
         if (e == hipSuccess) e = dalloc(*u, &Ly.wf, (size_t)q * Ly.n_pad * Ly.k_pad);
         if (e == hipSuccess) e = dalloc(*u, &Ly.wb, (size_t)Ly.nb_pad * Ly.kb_pad);
-        if (e == hipSuccess) e = dalloc(*u, &Ly.gpack, (size_t)Ly.n_pad * q * Ly.k_pad);
     }
     // activations and gradients
     const size_t B = (size_t)max_batch;
@@ -385,7 +387,9 @@ int eptv_unet_create(int c_in, int c_out, int base, int levels, int max_batch, i
     // weight-gradient partials: the largest layer
     for (const Layer& Ly : u->layers) {
         const size_t npix = B * (height >> Ly.lev) * (width >> Ly.lev);
-        const size_t chunks = wgrad_max_chunks((int)npix, Ly.n_pad, (Ly.mode == kUp ? 4 : 1) * Ly.k_pad);
+        size_t chunks = wgrad_max_chunks((int)npix, Ly.n_pad, (Ly.mode == kUp ? 4 : 1) * Ly.k_pad);
+        chunks = std::max(chunks, (size_t)wgrad_tiled_max_chunks(Ly.mode, (int)B, height >> Ly.lev, width >> Ly.lev,
+                                                                 Ly.ci, Ly.co));
         part = std::max(part, chunks * Ly.n_pad * (Ly.mode == kUp ? 4 : 1) * Ly.k_pad);
         bpart = std::max(bpart, chunks * (Ly.mode == kUp ? 4 : 1) * Ly.n_pad);  // one row per chunk and parity
     }
@@ -393,6 +397,15 @@ int eptv_unet_create(int c_in, int c_out, int base, int levels, int max_batch, i
     if (e == hipSuccess) e = dalloc(*u, &u->part, part);
     if (e == hipSuccess) e = dalloc(*u, &u->bpart, bpart);
     if (e == hipSuccess) e = dalloc(*u, &u->mse_part, (size_t)kMseBlocks);
+    // the packing table (fixed pointers from here on)
+    std::vector<PackDesc> tab;
+    for (const Layer& Ly : u->layers) {
+        tab.push_back({u->params + Ly.w_off, Ly.wf, Ly.mode, 0, Ly.ci, Ly.co, Ly.n_pad, Ly.k_pad});
+        tab.push_back({u->params + Ly.w_off, Ly.wb, Ly.mode, 1, Ly.ci, Ly.co, Ly.nb_pad, Ly.kb_pad});
+    }
+    u->pack_n = (int)tab.size();
+    if (e == hipSuccess) e = dalloc(*u, &u->pack_tab, tab.size());
+    if (e == hipSuccess) e = hipMemcpy(u->pack_tab, tab.data(), tab.size() * sizeof(PackDesc), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         const int rc = hip_fail(e, "eptv_unet_create");
         eptv_unet_destroy(u);

@@ -52,6 +52,12 @@ def unflatten(flat, shapes):
     (2, 3, 8, 3, 2, 32, 32),     # pooling, transposed convs, skip concatenation
     (1, 3, 16, 4, 1, 64, 64),    # four levels
     (1, 3, 8, 2, 3, 48, 80),     # several pixel chunks in the gradient sums, a ragged last one
+    # 3x3 weight gradients from LDS tiles (C_in a multiple of 32): ragged tile
+    # rows and columns at both levels
+    (1, 3, 32, 2, 2, 36, 72),
+    # ... 48 output channels (a half-empty channel block), three 32-channel
+    # chunks, two tiles per pixel chunk, ragged columns
+    (1, 3, 48, 2, 2, 96, 136),
 ])
 def test_unet_forward_and_gradients_match_oracle(E, c_in, c_out, base, levels, n, h, w):
     shapes = C.unet_shapes(c_in, c_out, base, levels)
