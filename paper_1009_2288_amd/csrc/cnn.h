@@ -34,6 +34,10 @@ struct ConvArgs {
     // backward of a ReLU whose output it is, fused into the epilogue
     const uint16_t* mask = nullptr;
     int m_cs = 0, m_co = 0;
+    // pool, if set (3x3 layers, even h and w): also write the 2x2 average
+    // pooling of the (bf16) output, [n_img][h/2][w/2] with channel stride p_cs
+    uint16_t* pool = nullptr;
+    int p_cs = 0;
 };
 
 inline int pad64(int n) { return (n + 63) / 64 * 64; }

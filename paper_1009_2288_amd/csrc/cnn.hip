@@ -31,12 +31,16 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint16_t f2bf(float f)
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// fp32 -> bf16, round to nearest even (gfx950's v_cvt_pk_bf16_f32)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+
+// two values in one conversion: a in the low half, b in the high half
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b)
 {
-    // round to nearest even (finite inputs)
-    uint32_t u = __float_as_uint(f);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+    const bf16x2 v = {(__bf16)a, (__bf16)b};
+    return __builtin_bit_cast(uint32_t, v);
 }
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
@@ -112,13 +116,25 @@ __device__ __forceinline__ uint2 epi_mask4(const ConvArgs& a, size_t pix, int n,
     return make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
 }
 
+// the bias of channels n .. n + 3 (zero past cout or without a bias)
+__device__ __forceinline__ floatx4 epi_bias4(const ConvArgs& a, int n)
+{
+    floatx4 b = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (a.bias) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (n + r < a.cout) b[r] = a.bias[n + r];
+    }
+    return b;
+}
+
 __device__ __forceinline__ void epi_store4(const ConvArgs& a, size_t pix, int n, const floatx4& acc, uint2 m,
-                                           bool vec)
+                                           bool vec, const floatx4& bias)
 {
     float v[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        v[r] = acc[r] + (a.bias && n + r < a.cout ? a.bias[n + r] : 0.0f);
+        v[r] = acc[r] + bias[r];
         if (a.relu) v[r] = fmaxf(v[r], 0.0f);
         if (a.mask) {
             const uint32_t w = r < 2 ? m.x : m.y;
@@ -138,8 +154,7 @@ __device__ __forceinline__ void epi_store4(const ConvArgs& a, size_t pix, int n,
     } else {
         uint16_t* dst = a.y + pix * a.y_cs + a.y_co + n;
         if (full) {
-            *reinterpret_cast<uint2*>(dst) = make_uint2((uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16),
-                                                        (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16));
+            *reinterpret_cast<uint2*>(dst) = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
         } else {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
@@ -277,6 +292,9 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a)
     // its first store (the compiler cannot move loads across stores that
     // might alias them).
     const bool vec = epi_vec(a);
+    floatx4 bias[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) bias[j] = epi_bias4(a, n0 + 16 * j + kq / 2);
 #pragma unroll
     for (int i = 0; i < RT; ++i) {
         size_t pix;
@@ -289,7 +307,7 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a)
         for (int j = 0; j < NT; ++j) mk[j] = epi_mask4(a, pix, n0 + 16 * j + kq / 2, va[i], vec);
         if (!va[i]) continue;
 #pragma unroll
-        for (int j = 0; j < NT; ++j) epi_store4(a, pix, n0 + 16 * j + kq / 2, acc[i][j], mk[j], vec);
+        for (int j = 0; j < NT; ++j) epi_store4(a, pix, n0 + 16 * j + kq / 2, acc[i][j], mk[j], vec, bias[j]);
     }
 }
 
@@ -321,16 +339,18 @@ static void conv_launch(const ConvArgs& a, int rt, int nt, dim3 grid, hipStream_
 // the 9-fold reuse of each input value comes from LDS, not from global
 // memory, and the inner loop is LDS reads and matrix instructions only.
 constexpr int kPatchW = 34;             // 32 columns + halo
-constexpr int kPatchPS = 40;            // bf16 per patch pixel (32 channels + 16 B)
-constexpr int kTapLd = 9 * 32 + 8;      // bf16 per weight row (9 taps x 32 channels + 16 B)
+// LDS pitches: 96 B per patch pixel and 608 B per weight row (measured: far
+// fewer bank conflicts than 80 B / 592 B or 112 B / 624 B)
+constexpr int kPatchPS = 48;            // bf16 per patch pixel (32 channels + 32 B)
+constexpr int kTapLd = 9 * 32 + 16;     // bf16 per weight row (9 taps x 32 channels + 32 B)
 constexpr int kTileBlocksPerCu = 2;     // persistent blocks per CU
 
 template <int TH, int NT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv3_tile(ConvArgs a, int ntiles)
 {
     constexpr int BN = 16 * NT;       // output channels per block
-    constexpr int RPW = TH / 4;       // image rows per wave
-    constexpr int RT = 2 * RPW;       // 16-pixel row tiles per wave
+    static_assert(TH == 8 || TH == 4, "8- or 4-row tiles");
+    constexpr int RT = TH / 2;        // 16-pixel row tiles per wave
     constexpr int PN = (TH + 2) * kPatchW * 4, PPT = (PN + 255) / 256;  // patch uint4s, per thread
     constexpr int WN = BN * 36, WPT = (WN + 255) / 256;                 // weight uint4s, per thread
     __shared__ __attribute__((aligned(16))) uint16_t patch[(TH + 2) * kPatchW * kPatchPS];
@@ -356,12 +376,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
     if (t_first >= t_end) return;  // whole block, before any barrier
     const int mrow = lane & 15, kq = (lane >> 4) * 8;
+    // a wave owns two image rows of the tile (so that a 2x2 pooling window
+    // stays inside it): with 8-row tiles rows 2 w, 2 w + 1, both 16-column
+    // halves (row tile i: row 2 w + i / 2, half i % 2); with 4-row tiles
+    // rows 2 (w / 2) + i of half w % 2
+    auto row_of = [&](int i) { return TH == 8 ? 2 * wave + (i >> 1) : 2 * (wave >> 1) + i; };
+    auto col_of = [&](int i) { return 16 * (TH == 8 ? (i & 1) : (wave & 1)); };
     int lbase[RT];
 #pragma unroll
-    for (int i = 0; i < RT; ++i) {
-        const int lr = wave * RPW + (i >> 1), lc = (i & 1) * 16 + mrow;
-        lbase[i] = ((lr + 1) * kPatchW + lc + 1) * kPatchPS + kq;
-    }
+    for (int i = 0; i < RT; ++i) lbase[i] = ((row_of(i) + 1) * kPatchW + col_of(i) + mrow + 1) * kPatchPS + kq;
     auto tile_origin = [&](int t, int& img, int& y0, int& x0) __attribute__((always_inline)) {
         img = t / (tiles_x * tiles_y);
         const int r = t - img * tiles_x * tiles_y;
@@ -450,15 +473,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         }
         if (c == nch - 1) {
             // epilogue: accumulator r of lane l, row tile i, column tile j is
-            // the pixel at local row wave * RPW + i / 2, column
-            // (i % 2) * 16 + l % 16, channel n0 + 16 j + 4 (l / 16) + r; a
-            // row tile's mask values are loaded before its first store
+            // the pixel at local row row_of(i), column col_of(i) + l % 16,
+            // channel n0 + 16 j + 4 (l / 16) + r; a row tile's mask values
+            // are loaded before its first store
             int img, y0, x0;
             tile_origin(t, img, y0, x0);
             const bool vec = epi_vec(a);
+            floatx4 bias[NT];
+#pragma unroll
+            for (int j = 0; j < NT; ++j) bias[j] = epi_bias4(a, n0 + 16 * j + kq / 2);
 #pragma unroll
             for (int i = 0; i < RT; ++i) {
-                const int y = y0 + wave * RPW + (i >> 1), x = x0 + (i & 1) * 16 + mrow;
+                const int y = y0 + row_of(i), x = x0 + col_of(i) + mrow;
                 const bool ok = y < a.h && x < a.w;
                 const size_t pix = ((size_t)img * a.h + y) * a.w + x;
                 uint2 mk[NT];
@@ -466,7 +492,47 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                 for (int j = 0; j < NT; ++j) mk[j] = epi_mask4(a, pix, n0 + 16 * j + kq / 2, ok, vec);
                 if (!ok) continue;
 #pragma unroll
-                for (int j = 0; j < NT; ++j) epi_store4(a, pix, n0 + 16 * j + kq / 2, acc[i][j], mk[j], vec);
+                for (int j = 0; j < NT; ++j) epi_store4(a, pix, n0 + 16 * j + kq / 2, acc[i][j], mk[j], vec, bias[j]);
+            }
+            if (a.pool) {
+                // the 2x2 average pooling of the stored (bf16) outputs: the
+                // row pair (i0, i0 + RT / 2) of one half, the column pair
+                // from the neighbouring lane; summed in the order of the
+                // pooling kernel, (0,0) + (0,1) + (1,0) + (1,1)
+#pragma unroll
+                for (int i0 = 0; i0 < RT / 2; ++i0) {
+                    const int i1 = TH == 8 ? i0 + 2 : 1;
+                    const int y = y0 + row_of(i0), x = x0 + col_of(i0) + mrow;
+                    const bool ok = (mrow & 1) == 0 && y + 1 < a.h && x + 1 < a.w;
+                    const size_t pp = ((size_t)img * (a.h / 2) + y / 2) * (a.w / 2) + x / 2;
+#pragma unroll
+                    for (int j = 0; j < NT; ++j) {
+                        const int n = n0 + 16 * j + kq / 2;
+                        float o[4];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            float v0 = acc[i0][j][r] + bias[j][r];
+                            float v1 = acc[i1][j][r] + bias[j][r];
+                            if (a.relu) {
+                                v0 = fmaxf(v0, 0.0f);
+                                v1 = fmaxf(v1, 0.0f);
+                            }
+                            v0 = bf2f(f2bf(v0));
+                            v1 = bf2f(f2bf(v1));
+                            const float w0 = __shfl_xor(v0, 1), w1 = __shfl_xor(v1, 1);
+                            o[r] = 0.25f * (((v0 + w0) + v1) + w1);
+                        }
+                        if (!ok) continue;
+                        uint16_t* dst = a.pool + pp * a.p_cs + n;
+                        if (n + 3 < a.cout && a.p_cs % 4 == 0) {
+                            *reinterpret_cast<uint2*>(dst) = make_uint2(pack_bf16x2(o[0], o[1]), pack_bf16x2(o[2], o[3]));
+                        } else {
+#pragma unroll
+                            for (int r = 0; r < 4; ++r)
+                                if (n + r < a.cout) dst[r] = f2bf(o[r]);
+                        }
+                    }
+                }
             }
 #pragma unroll
             for (int i = 0; i < RT; ++i)
@@ -520,12 +586,92 @@ __global__ __launch_bounds__(256) void k_conv3_c1(ConvArgs a)
     }
 }
 
-hipError_t launch_conv(const ConvArgs& a, int mode, hipStream_t s)
+// 1x1 layers with a thin side (the head, C_in -> 3, and its backward data,
+// 3 -> C_in): a 16 x 16 matrix tile would be mostly padding, so one thread
+// per pixel forms the outputs with fp32 products of the bf16 operands (exact)
+// and fp32 sums in input-channel order.
+constexpr int kThin = 4;        // the thin side
+constexpr int kThinWide = 256;  // the other side
+
+__global__ __launch_bounds__(256) void k_point_thin(ConvArgs a)
 {
+    __shared__ float wt[kThin * kThinWide];  // [n][k]
+    __shared__ float bs[kThinWide];
+    for (int i = threadIdx.x; i < a.cout * a.cin; i += 256)
+        wt[i] = bf2f(a.wt[(size_t)(i / a.cin) * a.k_pad + i % a.cin]);
+    for (int i = threadIdx.x; i < a.cout; i += 256) bs[i] = a.bias ? a.bias[i] : 0.0f;
+    __syncthreads();
+    const int npix = a.n_img * a.h * a.w;
+    for (int p = blockIdx.x * 256 + threadIdx.x; p < npix; p += gridDim.x * 256) {
+        const uint16_t* xp = a.x + (size_t)p * a.x_cs + a.x_co;
+        if (a.cout <= kThin) {  // thin output: the input row in 8-channel pieces
+            float sum[kThin] = {0.0f, 0.0f, 0.0f, 0.0f};
+            for (int k0 = 0; k0 < a.cin; k0 += 8) {
+                Frag f;
+                f.u = *reinterpret_cast<const uint4*>(xp + k0);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const float xv = bf2f(f.h[j]);
+#pragma unroll
+                    for (int n = 0; n < kThin; ++n)
+                        if (n < a.cout) sum[n] += xv * wt[n * a.cin + k0 + j];
+                }
+            }
+#pragma unroll
+            for (int n = 0; n < kThin; ++n) {
+                if (n >= a.cout) continue;
+                float v = sum[n] + bs[n];
+                if (a.relu) v = fmaxf(v, 0.0f);
+                if (a.mask && !(bf2f(a.mask[(size_t)p * a.m_cs + a.m_co + n]) > 0.0f)) v = 0.0f;
+                if (a.y32)
+                    a.y32[(size_t)p * a.y_cs + a.y_co + n] = v;
+                else
+                    a.y[(size_t)p * a.y_cs + a.y_co + n] = f2bf(v);
+            }
+        } else {  // thin input: the outputs in 8-channel pieces
+            float xv[kThin];
+#pragma unroll
+            for (int k = 0; k < kThin; ++k) xv[k] = k < a.cin ? bf2f(xp[k]) : 0.0f;
+            for (int n0 = 0; n0 < a.cout; n0 += 8) {
+                Frag m, o;
+                if (a.mask) m.u = *reinterpret_cast<const uint4*>(a.mask + (size_t)p * a.m_cs + a.m_co + n0);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    float v = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < kThin; ++k)
+                        if (k < a.cin) v += xv[k] * wt[(n0 + j) * a.cin + k];
+                    v += bs[n0 + j];
+                    if (a.relu) v = fmaxf(v, 0.0f);
+                    if (a.mask && !(bf2f(m.h[j]) > 0.0f)) v = 0.0f;
+                    o.h[j] = f2bf(v);
+                }
+                *reinterpret_cast<uint4*>(a.y + (size_t)p * a.y_cs + a.y_co + n0) = o.u;
+            }
+        }
+    }
+}
+
+static bool point_thin_fits(const ConvArgs& a, int mode)
+{
+    if (mode != kPoint) return false;
+    if (a.cout <= kThin && a.cin <= kThinWide && a.cin % 8 == 0 && a.x_cs % 8 == 0 && a.x_co % 8 == 0) return true;
+    return a.cin <= kThin && a.cout <= kThinWide && a.cout % 8 == 0 && !a.y32 && a.y_cs % 8 == 0 && a.y_co % 8 == 0 &&
+           (!a.mask || (a.m_cs % 8 == 0 && a.m_co % 8 == 0));
+}
+
+static hipError_t launch_conv_impl(const ConvArgs& a, int mode, hipStream_t s, bool* pooled)
+{
+    *pooled = false;
     const int npix = a.n_img * a.h * a.w;
     if (mode == kConv3 && a.cin == 1 && !a.y32 && a.cout % 8 == 0 && a.cout <= kC1MaxOut && a.y_cs % 8 == 0 &&
         a.y_co % 8 == 0) {
         hipLaunchKernelGGL(k_conv3_c1, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
+    if (point_thin_fits(a, mode)) {
+        const unsigned g = (unsigned)std::min((npix + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_point_thin, dim3(g), dim3(256), 0, s, a);
         return hipGetLastError();
     }
     // 32 output channels or fewer: a 32-wide channel tile (no padded half)
@@ -548,10 +694,13 @@ hipError_t launch_conv(const ConvArgs& a, int mode, hipStream_t s)
             const int G = (int)std::min(nt_, want);
             dim3 g((unsigned)G, (unsigned)cbn);
             const int ntl = (int)nt_;
-            if (th == 8 && tn == 4) hipLaunchKernelGGL((k_conv3_tile<8, 4>), g, dim3(256), 0, s, a, ntl);
-            else if (th == 8) hipLaunchKernelGGL((k_conv3_tile<8, 2>), g, dim3(256), 0, s, a, ntl);
-            else if (tn == 4) hipLaunchKernelGGL((k_conv3_tile<4, 4>), g, dim3(256), 0, s, a, ntl);
-            else hipLaunchKernelGGL((k_conv3_tile<4, 2>), g, dim3(256), 0, s, a, ntl);
+            ConvArgs b = a;
+            *pooled = a.pool && a.h % 2 == 0 && a.w % 2 == 0;
+            if (!*pooled) b.pool = nullptr;
+            if (th == 8 && tn == 4) hipLaunchKernelGGL((k_conv3_tile<8, 4>), g, dim3(256), 0, s, b, ntl);
+            else if (th == 8) hipLaunchKernelGGL((k_conv3_tile<8, 2>), g, dim3(256), 0, s, b, ntl);
+            else if (tn == 4) hipLaunchKernelGGL((k_conv3_tile<4, 4>), g, dim3(256), 0, s, b, ntl);
+            else hipLaunchKernelGGL((k_conv3_tile<4, 2>), g, dim3(256), 0, s, b, ntl);
             return hipGetLastError();
         }
     }
@@ -567,6 +716,17 @@ hipError_t launch_conv(const ConvArgs& a, int mode, hipStream_t s)
     default: conv_launch<kUpBack>(a, rt, nt, grid, s); break;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_conv(const ConvArgs& a, int mode, hipStream_t s)
+{
+    bool pooled = false;
+    hipError_t e = launch_conv_impl(a, mode, s, &pooled);
+    if (e == hipSuccess && a.pool && !pooled) {  // the pooling as a pass of its own (dense output)
+        if (a.p_cs != a.cout || a.y32) return hipErrorInvalidValue;
+        e = launch_avgpool(a.y, a.y_cs, a.y_co, a.pool, a.n_img, a.h, a.w, a.cout, s);
+    }
+    return e;
 }
 
 // ------------------------------------------------------------------ weight gradients

@@ -102,7 +102,7 @@ static hipError_t forward(eptv_unet_s& u, const float* x, int n, float* y, hipSt
     const int L = u.levels;
     if ((e = launch_to_bf16(x, u.xin.p, (size_t)n * u.h * u.w * u.c_in, s)) != hipSuccess) return e;
     auto conv = [&](int li, int mode, const uint16_t* xp, int xcs, int xco, int h, int w, uint16_t* yp, int ycs,
-                    int yco, float* y32, int relu) {
+                    int yco, float* y32, int relu, const Tensor* pool = nullptr) {
         const Layer& Ly = u.layers[li];
         ConvArgs a = conv_args(u, Ly, n, h, w, false);
         a.x = xp;
@@ -113,23 +113,24 @@ static hipError_t forward(eptv_unet_s& u, const float* x, int n, float* y, hipSt
         a.y_cs = ycs;
         a.y_co = yco;
         a.relu = relu;
+        if (pool) {
+            a.pool = pool->p;
+            a.p_cs = pool->c;
+        }
         return launch_conv(a, mode, s);
     };
     for (int l = 0; l < L; ++l) {
         const int h = u.h >> l, w = u.w >> l, C = u.base << l;
         const Tensor& inp = l == 0 ? u.xin : u.in[l];
-        if (l > 0) {
-            const Tensor& prev = l - 1 < L - 1 ? u.cat[l - 1] : u.bout;
-            if ((e = launch_avgpool(prev.p, prev.c, 0, u.in[l].p, n, h * 2, w * 2, u.base << (l - 1), s)) !=
-                hipSuccess)
-                return e;
-        }
         if ((e = conv(layer_index(u, 'e', l, 'a'), kConv3, inp.p, inp.c, 0, h, w, u.a[l].p, C, 0, nullptr, 1)) !=
             hipSuccess)
             return e;
+        // the level output (the skip half of the concatenation, or the
+        // bottleneck), and below the bottom level its 2x2 average pooling, the
+        // next level's input, from the same epilogue
         const Tensor& out = l < L - 1 ? u.cat[l] : u.bout;
-        if ((e = conv(layer_index(u, 'e', l, 'b'), kConv3, u.a[l].p, C, 0, h, w, out.p, out.c, 0, nullptr, 1)) !=
-            hipSuccess)
+        if ((e = conv(layer_index(u, 'e', l, 'b'), kConv3, u.a[l].p, C, 0, h, w, out.p, out.c, 0, nullptr, 1,
+                      l < L - 1 ? &u.in[l + 1] : nullptr)) != hipSuccess)
             return e;
     }
     for (int l = L - 2; l >= 0; --l) {
