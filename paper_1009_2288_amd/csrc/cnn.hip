@@ -345,7 +345,9 @@ constexpr int kPatchPS = 48;            // bf16 per patch pixel (32 channels + 3
 constexpr int kTapLd = 9 * 32 + 16;     // bf16 per weight row (9 taps x 32 channels + 32 B)
 constexpr int kTileBlocksPerCu = 2;     // persistent blocks per CU
 
-template <int TH, int NT>
+// STAGED: the epilogue goes through LDS (16-byte stores, masks, pooling);
+// otherwise each lane stores its 4 channels directly (no mask or pooling)
+template <int TH, int NT, bool STAGED>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv3_tile(ConvArgs a, int ntiles)
 {
     constexpr int BN = 16 * NT;       // output channels per block
@@ -353,8 +355,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     constexpr int RT = TH / 2;        // 16-pixel row tiles per wave
     constexpr int PN = (TH + 2) * kPatchW * 4, PPT = (PN + 255) / 256;  // patch uint4s, per thread
     constexpr int WN = BN * 36, WPT = (WN + 255) / 256;                 // weight uint4s, per thread
-    __shared__ __attribute__((aligned(16))) uint16_t patch[(TH + 2) * kPatchW * kPatchPS];
-    __shared__ __attribute__((aligned(16))) uint16_t wts[BN * kTapLd];
+    // LDS: the patch region, then the weights; a finished tile's outputs are
+    // staged in the patch region ([pixel][BN + 8] bf16, the region grown to
+    // fit) on their way to memory, so the weights stay in place
+    constexpr int PATCH = (TH + 2) * kPatchW * kPatchPS, OLD = BN + 8;
+    constexpr int STAGE = !STAGED || PATCH > TH * 32 * OLD ? PATCH : TH * 32 * OLD;
+    __shared__ __attribute__((aligned(16))) uint16_t lds[STAGE + BN * kTapLd];
+    uint16_t* patch = lds;
+    uint16_t* wts = lds + STAGE;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int tiles_x = (a.w + 31) / 32, tiles_y = (a.h + TH - 1) / TH;
     const int n0 = blockIdx.y * BN;
@@ -392,20 +400,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         y0 = ty * TH;
         x0 = (r - ty * tiles_x) * 32;
     };
+    // Staging through range-checked buffer loads: a piece outside the image
+    // (or past the patch) gets offset -1, which the hardware's range check
+    // turns into zeros, so no load sits behind a branch.  Byte offsets fit
+    // 31 bits (checked at launch).
+    const __amdgpu_buffer_rsrc_t rx =
+        __builtin_amdgcn_make_buffer_rsrc((void*)a.x, (short)0, (int)((size_t)a.n_img * a.h * a.w * a.x_cs * 2), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rw =
+        __builtin_amdgcn_make_buffer_rsrc((void*)a.wt, (short)0, (int)((size_t)a.n_pad * a.k_pad * 2), 0x00020000);
     u32x4 pr[PPT], wr[WPT];
     auto fetch_patch = [&](int t, int c0) __attribute__((always_inline)) {
         int img, y0, x0;
         tile_origin(t, img, y0, x0);
+        // element offset of patch pixel (0, 0), image pixel (y0 - 1, x0 - 1)
+        const int base = ((img * a.h + y0 - 1) * a.w + x0 - 1) * a.x_cs + a.x_co + c0;
 #pragma unroll
         for (int u = 0; u < PPT; ++u) {
             const int idx = threadIdx.x + 256 * u;
             const int px = idx >> 2, part = idx & 3;
             const int pr_ = px / kPatchW, pc = px - pr_ * kPatchW;
-            const int y = y0 - 1 + pr_, x = x0 - 1 + pc;
-            pr[u] = u32x4{0u, 0u, 0u, 0u};
-            if (idx < PN && (unsigned)y < (unsigned)a.h && (unsigned)x < (unsigned)a.w)
-                pr[u] = *reinterpret_cast<const u32x4*>(a.x + (((size_t)img * a.h + y) * a.w + x) * a.x_cs + a.x_co +
-                                                        c0 + part * 8);
+            const bool ok = idx < PN && (unsigned)(y0 - 1 + pr_) < (unsigned)a.h && (unsigned)(x0 - 1 + pc) < (unsigned)a.w;
+            const int off = ok ? 2 * (base + (pr_ * a.w + pc) * a.x_cs + part * 8) : -1;
+            pr[u] = __builtin_amdgcn_raw_buffer_load_b128(rx, off, 0, 0);
         }
     };
     auto fetch_w = [&](int c0) __attribute__((always_inline)) {
@@ -413,9 +429,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         for (int u = 0; u < WPT; ++u) {
             const int idx = threadIdx.x + 256 * u;
             const int row = idx / 36, rem = idx - row * 36, tap = rem >> 2, part = rem & 3;
-            wr[u] = idx < WN ? *reinterpret_cast<const u32x4*>(a.wt + (size_t)(n0 + row) * a.k_pad + tap * a.cin +
-                                                               c0 + part * 8)
-                             : u32x4{0u, 0u, 0u, 0u};
+            const int off = idx < WN ? 2 * ((n0 + row) * a.k_pad + tap * a.cin + c0 + part * 8) : -1;
+            wr[u] = __builtin_amdgcn_raw_buffer_load_b128(rw, off, 0, 0);
         }
     };
     floatx4 acc[RT][NT];
@@ -471,69 +486,110 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[j].v, fa.v, acc[i][j], 0, 0, 0);
             }
         }
-        if (c == nch - 1) {
-            // epilogue: accumulator r of lane l, row tile i, column tile j is
-            // the pixel at local row row_of(i), column col_of(i) + l % 16,
-            // channel n0 + 16 j + 4 (l / 16) + r; a row tile's mask values
-            // are loaded before its first store
+        if (STAGED && c == nch - 1) {
+            // epilogue through LDS: accumulator r of lane l, row tile i,
+            // column tile j is the pixel at local row row_of(i), column
+            // col_of(i) + l % 16, channel n0 + 16 j + 4 (l / 16) + r; each
+            // wave writes its bf16 outputs (bias, ReLU) to the staging
+            // region, then every thread moves whole 16-byte pieces (8
+            // channels of one pixel) to memory, applying the mask there, and
+            // forms the pooled pieces from the staged values
+            int img, y0, x0;
+            tile_origin(t, img, y0, x0);
+            __syncthreads();  // every wave is done with the patch and the weights
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const floatx4 bias = epi_bias4(a, n0 + 16 * j + kq / 2);
+#pragma unroll
+                for (int i = 0; i < RT; ++i) {
+                    float v[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        v[r] = acc[i][j][r] + bias[r];
+                        if (a.relu) v[r] = fmaxf(v[r], 0.0f);
+                    }
+                    const int px = row_of(i) * 32 + col_of(i) + mrow;
+                    *reinterpret_cast<uint2*>(lds + px * OLD + 16 * j + kq / 2) =
+                        make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+                }
+            }
+            __syncthreads();
+            constexpr int C8 = BN / 8, PIECES = TH * 32 * C8, PPT_OUT = PIECES / 256, QB = PPT_OUT < 4 ? PPT_OUT : 4;
+            static_assert(PIECES % 256 == 0 && PPT_OUT % QB == 0, "whole pieces per thread");
+#pragma unroll
+            for (int q0 = 0; q0 < PPT_OUT; q0 += QB) {
+                // QB pieces at a time, their mask values loaded before the first store
+                Frag mv[QB];
+                if (a.mask) {
+#pragma unroll
+                    for (int qq = 0; qq < QB; ++qq) {
+                        const int pc_ = threadIdx.x + 256 * (q0 + qq), px = pc_ / C8, n = n0 + (pc_ - px * C8) * 8;
+                        const int y = y0 + (px >> 5), x = x0 + (px & 31);
+                        mv[qq] = zero_frag();
+                        if (y < a.h && x < a.w && n < a.cout)
+                            mv[qq].u = *reinterpret_cast<const uint4*>(
+                                a.mask + (((size_t)img * a.h + y) * a.w + x) * a.m_cs + a.m_co + n);
+                    }
+                }
+#pragma unroll
+                for (int qq = 0; qq < QB; ++qq) {
+                    const int pc_ = threadIdx.x + 256 * (q0 + qq), px = pc_ / C8, c8 = pc_ - px * C8, n = n0 + c8 * 8;
+                    const int y = y0 + (px >> 5), x = x0 + (px & 31);
+                    if (y >= a.h || x >= a.w || n >= a.cout) continue;
+                    Frag o;
+                    o.u = *reinterpret_cast<const uint4*>(lds + px * OLD + c8 * 8);
+                    if (a.mask) {
+#pragma unroll
+                        for (int e = 0; e < 8; ++e)
+                            if (!(bf2f(mv[qq].h[e]) > 0.0f)) o.h[e] = 0;
+                    }
+                    *reinterpret_cast<uint4*>(a.y + (((size_t)img * a.h + y) * a.w + x) * a.y_cs + a.y_co + n) = o.u;
+                }
+            }
+            if (a.pool) {
+                // 2x2 average of the stored values, summed in the order of
+                // the pooling kernel: (0,0) + (0,1) + (1,0) + (1,1)
+                constexpr int PP = (TH / 2) * 16 * C8;
+                for (int pc_ = threadIdx.x; pc_ < PP; pc_ += 256) {
+                    const int pp = pc_ / C8, c8 = pc_ - pp * C8, n = n0 + c8 * 8;
+                    const int ly = 2 * (pp >> 4), lx = 2 * (pp & 15);
+                    const int y = y0 + ly, x = x0 + lx;
+                    if (y + 1 >= a.h || x + 1 >= a.w || n >= a.cout) continue;
+                    Frag f[4], o;
+#pragma unroll
+                    for (int d = 0; d < 4; ++d)
+                        f[d].u = *reinterpret_cast<const uint4*>(lds + ((ly + (d >> 1)) * 32 + lx + (d & 1)) * OLD + c8 * 8);
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        float sum = 0.0f;
+#pragma unroll
+                        for (int d = 0; d < 4; ++d) sum += bf2f(f[d].h[e]);
+                        o.h[e] = f2bf(0.25f * sum);
+                    }
+                    *reinterpret_cast<uint4*>(a.pool + (((size_t)img * (a.h / 2) + y / 2) * (a.w / 2) + x / 2) * a.p_cs +
+                                              n) = o.u;
+                }
+            }
+        } else if (!STAGED && c == nch - 1) {
+            // direct epilogue: accumulator r of lane l, row tile i, column
+            // tile j is the pixel at local row row_of(i), column
+            // col_of(i) + l % 16, channel n0 + 16 j + 4 (l / 16) + r
             int img, y0, x0;
             tile_origin(t, img, y0, x0);
             const bool vec = epi_vec(a);
-            floatx4 bias[NT];
 #pragma unroll
-            for (int j = 0; j < NT; ++j) bias[j] = epi_bias4(a, n0 + 16 * j + kq / 2);
+            for (int j = 0; j < NT; ++j) {
+                const floatx4 bias = epi_bias4(a, n0 + 16 * j + kq / 2);
 #pragma unroll
-            for (int i = 0; i < RT; ++i) {
-                const int y = y0 + row_of(i), x = x0 + col_of(i) + mrow;
-                const bool ok = y < a.h && x < a.w;
-                const size_t pix = ((size_t)img * a.h + y) * a.w + x;
-                uint2 mk[NT];
-#pragma unroll
-                for (int j = 0; j < NT; ++j) mk[j] = epi_mask4(a, pix, n0 + 16 * j + kq / 2, ok, vec);
-                if (!ok) continue;
-#pragma unroll
-                for (int j = 0; j < NT; ++j) epi_store4(a, pix, n0 + 16 * j + kq / 2, acc[i][j], mk[j], vec, bias[j]);
-            }
-            if (a.pool) {
-                // the 2x2 average pooling of the stored (bf16) outputs: the
-                // row pair (i0, i0 + RT / 2) of one half, the column pair
-                // from the neighbouring lane; summed in the order of the
-                // pooling kernel, (0,0) + (0,1) + (1,0) + (1,1)
-#pragma unroll
-                for (int i0 = 0; i0 < RT / 2; ++i0) {
-                    const int i1 = TH == 8 ? i0 + 2 : 1;
-                    const int y = y0 + row_of(i0), x = x0 + col_of(i0) + mrow;
-                    const bool ok = (mrow & 1) == 0 && y + 1 < a.h && x + 1 < a.w;
-                    const size_t pp = ((size_t)img * (a.h / 2) + y / 2) * (a.w / 2) + x / 2;
-#pragma unroll
-                    for (int j = 0; j < NT; ++j) {
-                        const int n = n0 + 16 * j + kq / 2;
-                        float o[4];
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            float v0 = acc[i0][j][r] + bias[j][r];
-                            float v1 = acc[i1][j][r] + bias[j][r];
-                            if (a.relu) {
-                                v0 = fmaxf(v0, 0.0f);
-                                v1 = fmaxf(v1, 0.0f);
-                            }
-                            v0 = bf2f(f2bf(v0));
-                            v1 = bf2f(f2bf(v1));
-                            const float w0 = __shfl_xor(v0, 1), w1 = __shfl_xor(v1, 1);
-                            o[r] = 0.25f * (((v0 + w0) + v1) + w1);
-                        }
-                        if (!ok) continue;
-                        uint16_t* dst = a.pool + pp * a.p_cs + n;
-                        if (n + 3 < a.cout && a.p_cs % 4 == 0) {
-                            *reinterpret_cast<uint2*>(dst) = make_uint2(pack_bf16x2(o[0], o[1]), pack_bf16x2(o[2], o[3]));
-                        } else {
-#pragma unroll
-                            for (int r = 0; r < 4; ++r)
-                                if (n + r < a.cout) dst[r] = f2bf(o[r]);
-                        }
-                    }
+                for (int i = 0; i < RT; ++i) {
+                    const int y = y0 + row_of(i), x = x0 + col_of(i) + mrow;
+                    if (y < a.h && x < a.w)
+                        epi_store4(a, ((size_t)img * a.h + y) * a.w + x, n0 + 16 * j + kq / 2, acc[i][j],
+                                   make_uint2(0u, 0u), vec, bias);
                 }
             }
+        }
+        if (c == nch - 1) {
 #pragma unroll
             for (int i = 0; i < RT; ++i)
 #pragma unroll
@@ -604,17 +660,23 @@ __global__ __launch_bounds__(256) void k_point_thin(ConvArgs a)
     const int npix = a.n_img * a.h * a.w;
     for (int p = blockIdx.x * 256 + threadIdx.x; p < npix; p += gridDim.x * 256) {
         const uint16_t* xp = a.x + (size_t)p * a.x_cs + a.x_co;
-        if (a.cout <= kThin) {  // thin output: the input row in 8-channel pieces
+        if (a.cout <= kThin) {  // thin output: the input row, 4 pieces of 8 channels in flight
             float sum[kThin] = {0.0f, 0.0f, 0.0f, 0.0f};
-            for (int k0 = 0; k0 < a.cin; k0 += 8) {
-                Frag f;
-                f.u = *reinterpret_cast<const uint4*>(xp + k0);
+            for (int k0 = 0; k0 < a.cin; k0 += 32) {
+                Frag f[4];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const float xv = bf2f(f.h[j]);
+                for (int q = 0; q < 4; ++q)
+                    if (k0 + 8 * q < a.cin) f[q].u = *reinterpret_cast<const uint4*>(xp + k0 + 8 * q);
 #pragma unroll
-                    for (int n = 0; n < kThin; ++n)
-                        if (n < a.cout) sum[n] += xv * wt[n * a.cin + k0 + j];
+                for (int q = 0; q < 4; ++q) {
+                    if (k0 + 8 * q >= a.cin) break;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const float xv = bf2f(f[q].h[j]);
+#pragma unroll
+                        for (int n = 0; n < kThin; ++n)
+                            if (n < a.cout) sum[n] += xv * wt[n * a.cin + k0 + 8 * q + j];
+                    }
                 }
             }
 #pragma unroll
@@ -632,21 +694,31 @@ __global__ __launch_bounds__(256) void k_point_thin(ConvArgs a)
             float xv[kThin];
 #pragma unroll
             for (int k = 0; k < kThin; ++k) xv[k] = k < a.cin ? bf2f(xp[k]) : 0.0f;
-            for (int n0 = 0; n0 < a.cout; n0 += 8) {
-                Frag m, o;
-                if (a.mask) m.u = *reinterpret_cast<const uint4*>(a.mask + (size_t)p * a.m_cs + a.m_co + n0);
+            for (int n00 = 0; n00 < a.cout; n00 += 32) {
+                // 4 pieces of 8 channels: their mask values all loaded before the first store
+                Frag m[4];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    float v = 0.0f;
+                for (int q = 0; q < 4; ++q)
+                    if (a.mask && n00 + 8 * q < a.cout)
+                        m[q].u = *reinterpret_cast<const uint4*>(a.mask + (size_t)p * a.m_cs + a.m_co + n00 + 8 * q);
 #pragma unroll
-                    for (int k = 0; k < kThin; ++k)
-                        if (k < a.cin) v += xv[k] * wt[(n0 + j) * a.cin + k];
-                    v += bs[n0 + j];
-                    if (a.relu) v = fmaxf(v, 0.0f);
-                    if (a.mask && !(bf2f(m.h[j]) > 0.0f)) v = 0.0f;
-                    o.h[j] = f2bf(v);
+                for (int q = 0; q < 4; ++q) {
+                    const int n0 = n00 + 8 * q;
+                    if (n0 >= a.cout) break;
+                    Frag o;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        float v = 0.0f;
+#pragma unroll
+                        for (int k = 0; k < kThin; ++k)
+                            if (k < a.cin) v += xv[k] * wt[(n0 + j) * a.cin + k];
+                        v += bs[n0 + j];
+                        if (a.relu) v = fmaxf(v, 0.0f);
+                        if (a.mask && !(bf2f(m[q].h[j]) > 0.0f)) v = 0.0f;
+                        o.h[j] = f2bf(v);
+                    }
+                    *reinterpret_cast<uint4*>(a.y + (size_t)p * a.y_cs + a.y_co + n0) = o.u;
                 }
-                *reinterpret_cast<uint4*>(a.y + (size_t)p * a.y_cs + a.y_co + n0) = o.u;
             }
         }
     }
@@ -676,7 +748,12 @@ static hipError_t launch_conv_impl(const ConvArgs& a, int mode, hipStream_t s, b
     }
     // 32 output channels or fewer: a 32-wide channel tile (no padded half)
     const int nt = a.cout <= 32 ? 2 : 4;
-    if (mode == kConv3 && a.cin % 32 == 0 && a.x_cs % 8 == 0 && a.x_co % 8 == 0) {
+    // the LDS-tile kernel: C_in a multiple of 32, bf16 output, every slice
+    // 16-byte aligned, byte offsets within 31 bits
+    if (mode == kConv3 && a.cin % 32 == 0 && a.x_cs % 8 == 0 && a.x_co % 8 == 0 && !a.y32 && a.cout % 8 == 0 &&
+        a.y_cs % 8 == 0 && a.y_co % 8 == 0 && (!a.mask || (a.m_cs % 8 == 0 && a.m_co % 8 == 0)) &&
+        (!a.pool || a.p_cs % 8 == 0) && (size_t)a.n_img * a.h * a.w * a.x_cs * 2 < (size_t(1) << 31) &&
+        (size_t)a.n_pad * a.k_pad * 2 < (size_t(1) << 31)) {
         // tile shape: the largest that still gives enough blocks (8 rows and
         // 64 channels preferred; smaller layers fall back to 4 rows, then to
         // 32-channel tiles)
@@ -695,12 +772,22 @@ static hipError_t launch_conv_impl(const ConvArgs& a, int mode, hipStream_t s, b
             dim3 g((unsigned)G, (unsigned)cbn);
             const int ntl = (int)nt_;
             ConvArgs b = a;
+            // the kernel pools in its epilogue (even image sides)
             *pooled = a.pool && a.h % 2 == 0 && a.w % 2 == 0;
             if (!*pooled) b.pool = nullptr;
-            if (th == 8 && tn == 4) hipLaunchKernelGGL((k_conv3_tile<8, 4>), g, dim3(256), 0, s, b, ntl);
-            else if (th == 8) hipLaunchKernelGGL((k_conv3_tile<8, 2>), g, dim3(256), 0, s, b, ntl);
-            else if (tn == 4) hipLaunchKernelGGL((k_conv3_tile<4, 4>), g, dim3(256), 0, s, b, ntl);
-            else hipLaunchKernelGGL((k_conv3_tile<4, 2>), g, dim3(256), 0, s, b, ntl);
+            // measured on MI355X: the LDS-staged epilogue pays off except for
+            // 8 x 64 tiles without a mask or pooling (many input chunks per
+            // tile, and the staging adds registers there)
+            if (th == 8 && tn == 4) {
+                if (b.mask || b.pool) hipLaunchKernelGGL((k_conv3_tile<8, 4, true>), g, dim3(256), 0, s, b, ntl);
+                else hipLaunchKernelGGL((k_conv3_tile<8, 4, false>), g, dim3(256), 0, s, b, ntl);
+            } else if (th == 8) {
+                hipLaunchKernelGGL((k_conv3_tile<8, 2, true>), g, dim3(256), 0, s, b, ntl);
+            } else if (tn == 4) {
+                hipLaunchKernelGGL((k_conv3_tile<4, 4, true>), g, dim3(256), 0, s, b, ntl);
+            } else {
+                hipLaunchKernelGGL((k_conv3_tile<4, 2, true>), g, dim3(256), 0, s, b, ntl);
+            }
             return hipGetLastError();
         }
     }
