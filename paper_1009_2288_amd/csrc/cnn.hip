@@ -211,7 +211,10 @@ template <int MODE, int RT, int NT>
 __global__ __launch_bounds__(256) void k_conv(ConvArgs a)
 {
     constexpr int BN = 16 * NT;  // output channels per block
-    __shared__ __attribute__((aligned(16))) uint16_t wlds[BN * kConvLd];
+    // LDS: the weight chunks; then (modes with contiguous output pixels) the
+    // block's outputs, [pixel][BN + 8] bf16, on their way to memory
+    constexpr int OLD = BN + 8, WL = BN * kConvLd, OL = 64 * RT * OLD;
+    __shared__ __attribute__((aligned(16))) uint16_t wlds[WL > OL ? WL : OL];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int hw = a.h * a.w, npix = a.n_img * hw;
     const int tile = xcd_band((int)blockIdx.x, (int)gridDim.x);
@@ -291,6 +294,60 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a)
     // n0 + 16 j + 4 (l / 16) + r.  A row tile's mask values are loaded before
     // its first store (the compiler cannot move loads across stores that
     // might alias them).
+    const bool staged = MODE != kUp && !a.y32 && a.cout % 8 == 0 && a.y_cs % 8 == 0 && a.y_co % 8 == 0 &&
+                        (!a.mask || (a.m_cs % 8 == 0 && a.m_co % 8 == 0));
+    if (staged) {
+        // the block's pixels are p0_block .. + 64 RT - 1: stage bf16 outputs
+        // (bias, ReLU) in LDS, then move 16-byte pieces (8 channels of one
+        // pixel) to memory with the mask applied there
+        const int pb = tile * 64 * RT;
+        __syncthreads();  // every wave is done with the weights
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            const floatx4 bias = epi_bias4(a, n0 + 16 * j + kq / 2);
+#pragma unroll
+            for (int i = 0; i < RT; ++i) {
+                float v[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    v[r] = acc[i][j][r] + bias[r];
+                    if (a.relu) v[r] = fmaxf(v[r], 0.0f);
+                }
+                *reinterpret_cast<uint2*>(wlds + (wave * 16 * RT + 16 * i + mrow) * OLD + 16 * j + kq / 2) =
+                    make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+            }
+        }
+        __syncthreads();
+        constexpr int C8 = BN / 8, PIECES = 64 * RT * C8, PPT_OUT = PIECES / 256, QB = PPT_OUT < 4 ? PPT_OUT : 4;
+        static_assert(PIECES % 256 == 0 && PPT_OUT % QB == 0, "whole pieces per thread");
+#pragma unroll
+        for (int q0 = 0; q0 < PPT_OUT; q0 += QB) {
+            Frag mv[QB];
+            if (a.mask) {
+#pragma unroll
+                for (int qq = 0; qq < QB; ++qq) {
+                    const int pc_ = threadIdx.x + 256 * (q0 + qq), px = pc_ / C8, n = n0 + (pc_ - px * C8) * 8;
+                    mv[qq] = zero_frag();
+                    if (pb + px < npix && n < a.cout)
+                        mv[qq].u = *reinterpret_cast<const uint4*>(a.mask + (size_t)(pb + px) * a.m_cs + a.m_co + n);
+                }
+            }
+#pragma unroll
+            for (int qq = 0; qq < QB; ++qq) {
+                const int pc_ = threadIdx.x + 256 * (q0 + qq), px = pc_ / C8, c8 = pc_ - px * C8, n = n0 + c8 * 8;
+                if (pb + px >= npix || n >= a.cout) continue;
+                Frag o;
+                o.u = *reinterpret_cast<const uint4*>(wlds + px * OLD + c8 * 8);
+                if (a.mask) {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e)
+                        if (!(bf2f(mv[qq].h[e]) > 0.0f)) o.h[e] = 0;
+                }
+                *reinterpret_cast<uint4*>(a.y + (size_t)(pb + px) * a.y_cs + a.y_co + n) = o.u;
+            }
+        }
+        return;
+    }
     const bool vec = epi_vec(a);
     floatx4 bias[NT];
 #pragma unroll
@@ -602,50 +659,77 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 }
 
 // A 3x3 convolution of a one-channel input (the first layer): K = 9 is too
-// thin for the matrix cores, so one thread per output pixel forms every
-// channel with fp32 products of the bf16 operands (exact) and fp32 sums.
+// thin for the matrix cores, so one thread per (output pixel, 8 channels)
+// forms them with fp32 products of the bf16 operands (exact) and fp32 sums
+// over the taps in order, then the bias.
 constexpr int kC1MaxOut = 64;
 
 __global__ __launch_bounds__(256) void k_conv3_c1(ConvArgs a)
 {
-    __shared__ float wt[kC1MaxOut * 9];
-    __shared__ float bs[kC1MaxOut];
-    for (int i = threadIdx.x; i < a.cout * 9; i += 256) wt[i] = bf2f(a.wt[(size_t)(i / 9) * a.k_pad + i % 9]);
+    // weights as fp32 [tap][n] (4 channels per LDS read), bias [n], and the
+    // three input rows the block's pixels read (zero outside the image)
+    __shared__ __attribute__((aligned(16))) float wt[9 * kC1MaxOut];
+    __shared__ __attribute__((aligned(16))) float bs[kC1MaxOut];
+    __shared__ float rows[3][256 + 2];
+    // block: blockIdx.y = image row (img h + y), pixels x0 .. x0 + pb - 1 of
+    // it, one thread per (pixel, 8 output channels)
+    const int c8n = a.cout / 8, pb = 256 / c8n;
+    const int row = blockIdx.y, img = row / a.h, y = row - img * a.h, x0 = blockIdx.x * pb;
+    for (int i = threadIdx.x; i < a.cout * 9; i += 256) {
+        const int t = i / a.cout, n = i - t * a.cout;
+        wt[i] = bf2f(a.wt[(size_t)n * a.k_pad + t]);
+    }
     for (int i = threadIdx.x; i < a.cout; i += 256) bs[i] = a.bias ? a.bias[i] : 0.0f;
+    for (int i = threadIdx.x; i < 3 * (pb + 2); i += 256) {
+        const int r = i / (pb + 2), c = i - r * (pb + 2), ys = y + r - 1, xs = x0 + c - 1;
+        rows[r][c] = ((unsigned)ys < (unsigned)a.h && (unsigned)xs < (unsigned)a.w)
+                         ? bf2f(a.x[(((size_t)img * a.h + ys) * a.w + xs) * a.x_cs + a.x_co])
+                         : 0.0f;
+    }
     __syncthreads();
-    const int hw = a.h * a.w, npix = a.n_img * hw;
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p >= npix) return;
-    const int img = p / hw, r = p - img * hw, y = r / a.w, x = r - y * a.w;
-    float v[9];
+    const int lp = threadIdx.x / c8n, n0 = (threadIdx.x - lp * c8n) * 8, x = x0 + lp;
+    if (lp >= pb || x >= a.w) return;
+    float acc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
-        const int ys = y + t / 3 - 1, xs = x + t % 3 - 1;
-        v[t] = ((unsigned)ys < (unsigned)a.h && (unsigned)xs < (unsigned)a.w)
-                   ? bf2f(a.x[(((size_t)img * a.h + ys) * a.w + xs) * a.x_cs + a.x_co])
-                   : 0.0f;
+        const float v = rows[t / 3][lp + t % 3];
+        const float4 w0 = *reinterpret_cast<const float4*>(wt + t * a.cout + n0);
+        const float4 w1 = *reinterpret_cast<const float4*>(wt + t * a.cout + n0 + 4);
+        acc[0] += v * w0.x;
+        acc[1] += v * w0.y;
+        acc[2] += v * w0.z;
+        acc[3] += v * w0.w;
+        acc[4] += v * w1.x;
+        acc[5] += v * w1.y;
+        acc[6] += v * w1.z;
+        acc[7] += v * w1.w;
     }
-    uint16_t* out = a.y + (size_t)p * a.y_cs + a.y_co;
-    for (int n0 = 0; n0 < a.cout; n0 += 8) {
-        Frag o;
+    const float4 b0 = *reinterpret_cast<const float4*>(bs + n0), b1 = *reinterpret_cast<const float4*>(bs + n0 + 4);
+    acc[0] += b0.x;
+    acc[1] += b0.y;
+    acc[2] += b0.z;
+    acc[3] += b0.w;
+    acc[4] += b1.x;
+    acc[5] += b1.y;
+    acc[6] += b1.z;
+    acc[7] += b1.w;
+    if (a.relu) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int n = n0 + j;
-            float acc = 0.0f;
-#pragma unroll
-            for (int t = 0; t < 9; ++t) acc += v[t] * wt[(n < a.cout ? n : 0) * 9 + t];
-            float val = acc + bs[n < a.cout ? n : 0];
-            if (a.relu) val = fmaxf(val, 0.0f);
-            o.h[j] = f2bf(val);
-        }
-        *reinterpret_cast<uint4*>(out + n0) = o.u;
+        for (int j = 0; j < 8; ++j) acc[j] = fmaxf(acc[j], 0.0f);
     }
+    uint4 o;
+    o.x = pack_bf16x2(acc[0], acc[1]);
+    o.y = pack_bf16x2(acc[2], acc[3]);
+    o.z = pack_bf16x2(acc[4], acc[5]);
+    o.w = pack_bf16x2(acc[6], acc[7]);
+    *reinterpret_cast<uint4*>(a.y + (((size_t)row * a.w) + x) * a.y_cs + a.y_co + n0) = o;
 }
 
 // 1x1 layers with a thin side (the head, C_in -> 3, and its backward data,
-// 3 -> C_in): a 16 x 16 matrix tile would be mostly padding, so one thread
-// per pixel forms the outputs with fp32 products of the bf16 operands (exact)
-// and fp32 sums in input-channel order.
+// 3 -> C_in): a 16 x 16 matrix tile would be mostly padding, so the vector
+// ALUs form the outputs with fp32 products of the bf16 operands (exact) and
+// fp32 sums, with lanes laid over channels so that each wave reads or
+// writes contiguous memory.
 constexpr int kThin = 4;        // the thin side
 constexpr int kThinWide = 256;  // the other side
 
@@ -658,27 +742,34 @@ __global__ __launch_bounds__(256) void k_point_thin(ConvArgs a)
     for (int i = threadIdx.x; i < a.cout; i += 256) bs[i] = a.bias ? a.bias[i] : 0.0f;
     __syncthreads();
     const int npix = a.n_img * a.h * a.w;
-    for (int p = blockIdx.x * 256 + threadIdx.x; p < npix; p += gridDim.x * 256) {
-        const uint16_t* xp = a.x + (size_t)p * a.x_cs + a.x_co;
-        if (a.cout <= kThin) {  // thin output: the input row, 4 pieces of 8 channels in flight
+    if (a.cout <= kThin) {
+        // thin output: a quad of lanes per pixel, lane j of the quad summing
+        // input channels 8 j, 8 j + 32, ... (16-byte loads, consecutive lanes
+        // contiguous); the quad's partial sums are added in lane order
+        const int sub = threadIdx.x & 3;
+        for (int p = (blockIdx.x * 256 + threadIdx.x) >> 2; p < (npix + 63) / 64 * 64; p += gridDim.x * 64) {
+            const bool ok = p < npix;
+            const uint16_t* xp = a.x + (size_t)(ok ? p : 0) * a.x_cs + a.x_co;
             float sum[kThin] = {0.0f, 0.0f, 0.0f, 0.0f};
-            for (int k0 = 0; k0 < a.cin; k0 += 32) {
-                Frag f[4];
+            for (int k0 = 8 * sub; k0 < a.cin; k0 += 32) {
+                Frag f;
+                f.u = *reinterpret_cast<const uint4*>(xp + k0);
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (k0 + 8 * q < a.cin) f[q].u = *reinterpret_cast<const uint4*>(xp + k0 + 8 * q);
+                for (int j = 0; j < 8; ++j) {
+                    const float xv = bf2f(f.h[j]);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (k0 + 8 * q >= a.cin) break;
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        const float xv = bf2f(f[q].h[j]);
-#pragma unroll
-                        for (int n = 0; n < kThin; ++n)
-                            if (n < a.cout) sum[n] += xv * wt[n * a.cin + k0 + 8 * q + j];
-                    }
+                    for (int n = 0; n < kThin; ++n)
+                        if (n < a.cout) sum[n] += xv * wt[n * a.cin + k0 + j];
                 }
             }
+            const int base = (threadIdx.x & 63) & ~3;
+#pragma unroll
+            for (int n = 0; n < kThin; ++n) {
+                const float s0 = __shfl(sum[n], base), s1 = __shfl(sum[n], base + 1);
+                const float s2 = __shfl(sum[n], base + 2), s3 = __shfl(sum[n], base + 3);
+                sum[n] = (s0 + s1) + (s2 + s3);
+            }
+            if (!ok || sub != 0) continue;
 #pragma unroll
             for (int n = 0; n < kThin; ++n) {
                 if (n >= a.cout) continue;
@@ -690,37 +781,33 @@ __global__ __launch_bounds__(256) void k_point_thin(ConvArgs a)
                 else
                     a.y[(size_t)p * a.y_cs + a.y_co + n] = f2bf(v);
             }
-        } else {  // thin input: the outputs in 8-channel pieces
-            float xv[kThin];
-#pragma unroll
-            for (int k = 0; k < kThin; ++k) xv[k] = k < a.cin ? bf2f(xp[k]) : 0.0f;
-            for (int n00 = 0; n00 < a.cout; n00 += 32) {
-                // 4 pieces of 8 channels: their mask values all loaded before the first store
-                Frag m[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (a.mask && n00 + 8 * q < a.cout)
-                        m[q].u = *reinterpret_cast<const uint4*>(a.mask + (size_t)p * a.m_cs + a.m_co + n00 + 8 * q);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int n0 = n00 + 8 * q;
-                    if (n0 >= a.cout) break;
-                    Frag o;
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        float v = 0.0f;
-#pragma unroll
-                        for (int k = 0; k < kThin; ++k)
-                            if (k < a.cin) v += xv[k] * wt[(n0 + j) * a.cin + k];
-                        v += bs[n0 + j];
-                        if (a.relu) v = fmaxf(v, 0.0f);
-                        if (a.mask && !(bf2f(m[q].h[j]) > 0.0f)) v = 0.0f;
-                        o.h[j] = f2bf(v);
-                    }
-                    *reinterpret_cast<uint4*>(a.y + (size_t)p * a.y_cs + a.y_co + n0) = o.u;
-                }
-            }
         }
+        return;
+    }
+    // thin input: one thread per (pixel, 8 output channels), consecutive
+    // threads writing consecutive 16-byte pieces
+    const int c8n = a.cout / 8;
+    const long long work = (long long)npix * c8n;
+    for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < work; idx += (long long)gridDim.x * 256) {
+        const int p = (int)(idx / c8n), n0 = (int)(idx - (long long)p * c8n) * 8;
+        const uint16_t* xp = a.x + (size_t)p * a.x_cs + a.x_co;
+        Frag m, o;
+        if (a.mask) m.u = *reinterpret_cast<const uint4*>(a.mask + (size_t)p * a.m_cs + a.m_co + n0);
+        float xv[kThin];
+#pragma unroll
+        for (int k = 0; k < kThin; ++k) xv[k] = k < a.cin ? bf2f(xp[k]) : 0.0f;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            float v = 0.0f;
+#pragma unroll
+            for (int k = 0; k < kThin; ++k)
+                if (k < a.cin) v += xv[k] * wt[(n0 + j) * a.cin + k];
+            v += bs[n0 + j];
+            if (a.relu) v = fmaxf(v, 0.0f);
+            if (a.mask && !(bf2f(m.h[j]) > 0.0f)) v = 0.0f;
+            o.h[j] = f2bf(v);
+        }
+        *reinterpret_cast<uint4*>(a.y + (size_t)p * a.y_cs + a.y_co + n0) = o.u;
     }
 }
 
@@ -732,17 +819,118 @@ static bool point_thin_fits(const ConvArgs& a, int mode)
            (!a.mask || (a.m_cs % 8 == 0 && a.m_co % 8 == 0));
 }
 
+// ------------------------------------------------------------------ stride-2 2x2 transposed convolution
+// out[2y + a][2x + c][n] = act(b[n] + sum_k X[y][x][k] W[q][n][k]), q = 2a + c.
+// Block = 32 input pixels of one row (x0 .. x0 + 31) x BN output channels;
+// wave w forms parity q = w with the weights as the MFMA's A operand
+// (D[n][pixel]), both operands read straight from memory as 16-byte rows.
+// The 2 x 64 output pixels of the block are staged in LDS and leave as whole
+// 16-byte pieces, so every output row is written contiguously.
+template <int NT>
+__global__ __launch_bounds__(256) void k_up2x2(ConvArgs a)
+{
+    constexpr int BN = 16 * NT, OLD = BN + 8;
+    __shared__ __attribute__((aligned(16))) uint16_t out[2 * 64 * OLD];
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int mrow = lane & 15, kq = (lane >> 4) * 8;
+    const int tiles_x = (a.w + 31) / 32;
+    const int t = blockIdx.x, row = t / tiles_x;  // row = img * h + y
+    const int x0 = (t - row * tiles_x) * 32, n0 = blockIdx.y * BN;
+    const int img = row / a.h, y = row - img * a.h;
+    const uint16_t* wq = a.wt + (size_t)q * a.n_pad * a.k_pad;
+    const uint16_t* xr = a.x + ((size_t)row * a.w) * a.x_cs + a.x_co;
+    floatx4 acc[2][NT];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    // operands of K-step k0 (zero past C_in; packed weight rows are zero
+    // there already, k < k_pad)
+    auto load = [&](int k0, Frag* fx, Frag* fw) __attribute__((always_inline)) {
+        const int k = k0 + kq;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int x = x0 + 16 * i + mrow;
+            fx[i] = zero_frag();
+            if (x < a.w && k < a.cin) fx[i].u = *reinterpret_cast<const uint4*>(xr + (size_t)x * a.x_cs + k);
+        }
+#pragma unroll
+        for (int j = 0; j < NT; ++j)
+            fw[j].u = *reinterpret_cast<const uint4*>(wq + (size_t)(n0 + 16 * j + mrow) * a.k_pad + min(k, a.k_pad - 8));
+    };
+    Frag fx[2], fw[NT];
+    load(0, fx, fw);
+    for (int k0 = 0; k0 < a.cin; k0 += 32) {
+        Frag gx[2], gw[NT];  // the next K-step, loaded while this one is multiplied
+        if (k0 + 32 < a.cin) load(k0 + 32, gx, gw);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fw[j].v, fx[i].v, acc[i][j], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) fx[i] = gx[i];
+#pragma unroll
+        for (int j = 0; j < NT; ++j) fw[j] = gw[j];
+    }
+    // accumulator r of lane l, pixel tile i, channel tile j: input pixel
+    // x0 + 16 i + l % 16, channel n0 + 16 j + 4 (l / 16) + r -> staged at
+    // output row q / 2, column 2 (16 i + l % 16) + q % 2
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const floatx4 bias = epi_bias4(a, n0 + 16 * j + kq / 2);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            float v[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                v[r] = acc[i][j][r] + bias[r];
+                if (a.relu) v[r] = fmaxf(v[r], 0.0f);
+            }
+            const int px = (q >> 1) * 64 + 2 * (16 * i + mrow) + (q & 1);
+            *reinterpret_cast<uint2*>(out + px * OLD + 16 * j + kq / 2) =
+                make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+        }
+    }
+    __syncthreads();
+    constexpr int C8 = BN / 8, PIECES = 128 * C8;
+    const int W2 = 2 * a.w;
+    for (int pc_ = threadIdx.x; pc_ < PIECES; pc_ += 256) {
+        const int px = pc_ / C8, c8 = pc_ - px * C8, n = n0 + c8 * 8;
+        const int fr = px >> 6, fc = 2 * x0 + (px & 63);
+        if (fc >= W2 || n >= a.cout) continue;
+        const size_t pix = ((size_t)img * 2 * a.h + 2 * y + fr) * W2 + fc;
+        *reinterpret_cast<uint4*>(a.y + pix * a.y_cs + a.y_co + n) = *reinterpret_cast<const uint4*>(out + px * OLD + c8 * 8);
+    }
+}
+
+static bool up2x2_fits(const ConvArgs& a, int mode)
+{
+    return mode == kUp && !a.y32 && !a.mask && a.cin % 8 == 0 && a.cout % 8 == 0 && a.x_cs % 8 == 0 &&
+           a.x_co % 8 == 0 && a.y_cs % 8 == 0 && a.y_co % 8 == 0;
+}
+
 static hipError_t launch_conv_impl(const ConvArgs& a, int mode, hipStream_t s, bool* pooled)
 {
     *pooled = false;
     const int npix = a.n_img * a.h * a.w;
     if (mode == kConv3 && a.cin == 1 && !a.y32 && a.cout % 8 == 0 && a.cout <= kC1MaxOut && a.y_cs % 8 == 0 &&
         a.y_co % 8 == 0) {
-        hipLaunchKernelGGL(k_conv3_c1, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, s, a);
+        const int pb = 256 / (a.cout / 8);
+        hipLaunchKernelGGL(k_conv3_c1, dim3((unsigned)((a.w + pb - 1) / pb), (unsigned)(a.n_img * a.h)), dim3(256), 0,
+                           s, a);
+        return hipGetLastError();
+    }
+    if (up2x2_fits(a, mode)) {
+        const int nt = a.cout <= 32 ? 2 : 4, bn = 16 * nt;
+        dim3 g((unsigned)(a.n_img * a.h * ((a.w + 31) / 32)), (unsigned)((a.cout + bn - 1) / bn));
+        if (nt == 2) hipLaunchKernelGGL(k_up2x2<2>, g, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL(k_up2x2<4>, g, dim3(256), 0, s, a);
         return hipGetLastError();
     }
     if (point_thin_fits(a, mode)) {
-        const unsigned g = (unsigned)std::min((npix + 255) / 256, 4096);
+        const long long work = a.cout <= kThin ? (long long)npix * 4 : (long long)npix * (a.cout / 8);
+        const unsigned g = (unsigned)std::min<long long>((work + 255) / 256, 4096);
         hipLaunchKernelGGL(k_point_thin, dim3(g), dim3(256), 0, s, a);
         return hipGetLastError();
     }
@@ -762,6 +950,8 @@ static hipError_t launch_conv_impl(const ConvArgs& a, int mode, hipStream_t s, b
         const long long c4 = (a.cout + 63) / 64, c2 = (a.cout + 31) / 32;
         int th = 0, tn = 0;
         if (t8 * (nt == 4 ? c4 : c2) >= 512) th = 8, tn = nt;
+        else if (t4 * (nt == 4 ? c4 : c2) >= 512) th = 4, tn = nt;
+        else if (t4 * c2 >= 512) th = 4, tn = 2;  // more blocks for the small layers
         else if (t4 * (nt == 4 ? c4 : c2) >= 256) th = 4, tn = nt;
         else if (t4 * c2 >= 256) th = 4, tn = 2;
         if (th) {
@@ -1152,6 +1342,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const bool do_bias = bpart && cb == 0;
     const bool dy_vec = dy_cs % 8 == 0 && dy_co % 8 == 0;
     const bool x_vec = a.x_cs % 8 == 0 && a.x_co % 8 == 0;
+    const double inv_w = 1.0 / (double)a.w;
     const int px_lane = 8 * (lane >> 4) + ((lane & 15) >> 2), ch_lane = 4 * (lane & 3);
     floatx4 acc[2][2];
 #pragma unroll
@@ -1162,8 +1353,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     Frag ones;
 #pragma unroll
     for (int i = 0; i < 8; ++i) ones.h[i] = 0x3f80;  // bf16 1.0
-    for (int t = t_beg; t < t_end; ++t) {
-        u32x4 dv[4], xv[4];
+    // a tile's 16-byte pieces (4 per thread of dY and of X) into registers;
+    // the next tile's are loaded while this one is multiplied
+    u32x4 dv[4], xv[4];
+    auto fetch = [&](int t) __attribute__((always_inline)) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int idx = threadIdx.x + 256 * u, px = idx >> 2, s8 = (idx & 3) * 8;
@@ -1172,8 +1365,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             if (p < npix) {
                 size_t pd = (size_t)p;
                 if (MODE == kUp) {
-                    const int img = p / hw, r = p - img * hw, y = r / a.w, x = r - y * a.w;
-                    pd = ((size_t)img * 2 * a.h + 2 * y + (q >> 1)) * 2 * a.w + 2 * x + (q & 1);
+                    // row R = img h + y of the GEMM grid; its output rows are
+                    // 2 R and 2 R + 1 (img 2h + 2y = 2 R).  R = p / w through
+                    // a double reciprocal, corrected to the exact quotient
+                    int R = (int)((double)p * inv_w);
+                    if (R * a.w > p) --R;
+                    if ((R + 1) * a.w <= p) ++R;
+                    const int x = p - R * a.w;
+                    pd = ((size_t)(2 * R + (q >> 1))) * 2 * a.w + 2 * x + (q & 1);
                 }
                 const uint16_t* sd = dy + pd * dy_cs + dy_co + n0 + s8;
                 if (dy_vec && n0 + s8 + 8 <= a.cout) {
@@ -1195,6 +1394,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             dv[u] = u32x4{fd.u.x, fd.u.y, fd.u.z, fd.u.w};
             xv[u] = u32x4{fx.u.x, fx.u.y, fx.u.z, fx.u.w};
         }
+    };
+    if (t_beg < t_end) fetch(t_beg);
+    for (int t = t_beg; t < t_end; ++t) {
         __syncthreads();  // the previous tile is consumed
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -1203,6 +1405,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             *reinterpret_cast<u32x4*>(t_x + (idx >> 2) * kWg3Ld + (idx & 3) * 8) = xv[u];
         }
         __syncthreads();
+        if (t + 1 < t_end) fetch(t + 1);
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             const int pr = 64 * wave + 32 * s + px_lane;
@@ -1433,7 +1636,8 @@ static bool wgrad3_c1_fits(const ConvArgs& a, int mode, int dy_cs, int dy_co)
 }
 
 constexpr int kWg3Rpw = 2;       // rows per wave: 8-row tiles
-constexpr int kWg3Blocks = 512;  // about two blocks per CU
+constexpr int kWg3Blocks = 512;   // about two blocks per CU
+constexpr int kWgPtBlocks = 1024; // the pointwise kernel: about four per CU
 
 static long long wgrad3_tiles(int n_img, int h, int w)
 {
@@ -1444,9 +1648,9 @@ static long long wgrad_pt_tiles(int n_img, int h, int w) { return ((long long)n_
 
 // chunks over nt tiles for m blocks per chunk: about kWg3Blocks blocks in
 // all, every chunk non-empty
-static int tile_chunks(long long nt, long long m, int* tiles_per_chunk)
+static int tile_chunks(long long nt, long long m, int* tiles_per_chunk, int blocks = kWg3Blocks)
 {
-    const long long t = std::max(1LL, (nt * m + kWg3Blocks - 1) / kWg3Blocks);
+    const long long t = std::max(1LL, (nt * m + blocks - 1) / blocks);
     *tiles_per_chunk = (int)t;
     return (int)((nt + t - 1) / t);
 }
@@ -1463,6 +1667,7 @@ int wgrad_tiled_max_chunks(int mode, int n_img, int h, int w, int ci, int co)
     } else if (mode == kPoint || mode == kUp) {
         nt = wgrad_pt_tiles(n_img, h, w);
         m = nbn * ((ci + 31) / 32) * (mode == kUp ? 4 : 1);
+        return (int)std::min(nt, (kWgPtBlocks + m - 1) / m);
     } else {
         return 0;
     }
@@ -1487,7 +1692,7 @@ hipError_t launch_wgrad(const ConvArgs& a, int mode, const uint16_t* dy, int dy_
                            nbn, part, bp);
     } else if (mode == kPoint || mode == kUp) {
         const int nbc = (a.cin + 31) / 32, nq = mode == kUp ? 4 : 1;
-        chunks = tile_chunks(wgrad_pt_tiles(a.n_img, a.h, a.w), (long long)nbn * nbc * nq, &tpc);
+        chunks = tile_chunks(wgrad_pt_tiles(a.n_img, a.h, a.w), (long long)nbn * nbc * nq, &tpc, kWgPtBlocks);
         const dim3 g((unsigned)(chunks * nbn * nbc * nq));
         if (mode == kUp)
             hipLaunchKernelGGL(k_wgrad_pt<kUp>, g, dim3(256), 0, s, a, dy, dy_cs, dy_co, tpc, nbn, nbc, part, bp);
