@@ -403,27 +403,32 @@ constexpr int kTapLd = 9 * 32 + 16;     // bf16 per weight row (9 taps x 32 chan
 constexpr int kTileBlocksPerCu = 2;     // persistent blocks per CU
 
 // STAGED: the epilogue goes through LDS (16-byte stores, masks, pooling);
-// otherwise each lane stores its 4 channels directly (no mask or pooling)
-template <int TH, int NT, bool STAGED>
+// otherwise each lane stores its 4 channels directly (no mask or pooling).
+// KC: input channels staged per round trip (32, or 64 for layers with many
+// chunks and few tiles: half the round trips per tile)
+template <int TH, int NT, bool STAGED, int KC = 32>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv3_tile(ConvArgs a, int ntiles)
 {
     constexpr int BN = 16 * NT;       // output channels per block
     static_assert(TH == 8 || TH == 4, "8- or 4-row tiles");
     constexpr int RT = TH / 2;        // 16-pixel row tiles per wave
-    constexpr int PN = (TH + 2) * kPatchW * 4, PPT = (PN + 255) / 256;  // patch uint4s, per thread
-    constexpr int WN = BN * 36, WPT = (WN + 255) / 256;                 // weight uint4s, per thread
+    constexpr int P8 = KC / 8;                                           // 16-byte pieces per pixel
+    constexpr int PPS = KC == 32 ? kPatchPS : KC + 16;                   // bf16 per patch pixel
+    constexpr int TLD = KC == 32 ? kTapLd : 9 * KC + 16;                 // bf16 per weight row
+    constexpr int PN = (TH + 2) * kPatchW * P8, PPT = (PN + 255) / 256;  // patch uint4s, per thread
+    constexpr int WN = BN * 9 * P8, WPT = (WN + 255) / 256;              // weight uint4s, per thread
     // LDS: the patch region, then the weights; a finished tile's outputs are
     // staged in the patch region ([pixel][BN + 8] bf16, the region grown to
     // fit) on their way to memory, so the weights stay in place
-    constexpr int PATCH = (TH + 2) * kPatchW * kPatchPS, OLD = BN + 8;
+    constexpr int PATCH = (TH + 2) * kPatchW * PPS, OLD = BN + 8;
     constexpr int STAGE = !STAGED || PATCH > TH * 32 * OLD ? PATCH : TH * 32 * OLD;
-    __shared__ __attribute__((aligned(16))) uint16_t lds[STAGE + BN * kTapLd];
+    __shared__ __attribute__((aligned(16))) uint16_t lds[STAGE + BN * TLD];
     uint16_t* patch = lds;
     uint16_t* wts = lds + STAGE;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int tiles_x = (a.w + 31) / 32, tiles_y = (a.h + TH - 1) / TH;
     const int n0 = blockIdx.y * BN;
-    const int nch = a.cin / 32;
+    const int nch = a.cin / KC;
     // persistent blocks: block b walks tiles of one contiguous band per XCD
     // (workgroups go to the 8 XCDs round robin), so neighbouring tiles share
     // an L2; without a multiple of 8 blocks, a plain stride
@@ -449,7 +454,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     auto col_of = [&](int i) { return 16 * (TH == 8 ? (i & 1) : (wave & 1)); };
     int lbase[RT];
 #pragma unroll
-    for (int i = 0; i < RT; ++i) lbase[i] = ((row_of(i) + 1) * kPatchW + col_of(i) + mrow + 1) * kPatchPS + kq;
+    for (int i = 0; i < RT; ++i) lbase[i] = ((row_of(i) + 1) * kPatchW + col_of(i) + mrow + 1) * PPS + kq;
     auto tile_origin = [&](int t, int& img, int& y0, int& x0) __attribute__((always_inline)) {
         img = t / (tiles_x * tiles_y);
         const int r = t - img * tiles_x * tiles_y;
@@ -474,7 +479,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
         for (int u = 0; u < PPT; ++u) {
             const int idx = threadIdx.x + 256 * u;
-            const int px = idx >> 2, part = idx & 3;
+            const int px = idx / P8, part = idx - px * P8;
             const int pr_ = px / kPatchW, pc = px - pr_ * kPatchW;
             const bool ok = idx < PN && (unsigned)(y0 - 1 + pr_) < (unsigned)a.h && (unsigned)(x0 - 1 + pc) < (unsigned)a.w;
             const int off = ok ? 2 * (base + (pr_ * a.w + pc) * a.x_cs + part * 8) : -1;
@@ -485,7 +490,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
         for (int u = 0; u < WPT; ++u) {
             const int idx = threadIdx.x + 256 * u;
-            const int row = idx / 36, rem = idx - row * 36, tap = rem >> 2, part = rem & 3;
+            const int row = idx / (9 * P8), rem = idx - row * (9 * P8), tap = rem / P8, part = rem - tap * P8;
             const int off = idx < WN ? 2 * ((n0 + row) * a.k_pad + tap * a.cin + c0 + part * 8) : -1;
             wr[u] = __builtin_amdgcn_raw_buffer_load_b128(rw, off, 0, 0);
         }
@@ -504,14 +509,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
         for (int u = 0; u < PPT; ++u) {
             const int idx = threadIdx.x + 256 * u;
-            if (idx < PN) *reinterpret_cast<u32x4*>(patch + (idx >> 2) * kPatchPS + (idx & 3) * 8) = pr[u];
+            if (idx < PN) *reinterpret_cast<u32x4*>(patch + (idx / P8) * PPS + (idx % P8) * 8) = pr[u];
         }
         if (nch > 1 || !w_staged) {
 #pragma unroll
             for (int u = 0; u < WPT; ++u) {
                 const int idx = threadIdx.x + 256 * u;
-                const int row = idx / 36, rem = idx - row * 36;
-                if (idx < WN) *reinterpret_cast<u32x4*>(wts + row * kTapLd + (rem >> 2) * 32 + (rem & 3) * 8) = wr[u];
+                const int row = idx / (9 * P8), rem = idx - row * (9 * P8);  // tap KC + part 8 = rem 8
+                if (idx < WN) *reinterpret_cast<u32x4*>(wts + row * TLD + rem * 8) = wr[u];
             }
             w_staged = true;
         }
@@ -524,23 +529,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         }
         const bool more = tn < t_end;
         if (more) {
-            fetch_patch(tn, cn * 32);
-            if (nch > 1) fetch_w(cn * 32);
+            fetch_patch(tn, cn * KC);
+            if (nch > 1) fetch_w(cn * KC);
         }
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
-            const int toff = ((tap / 3 - 1) * kPatchW + (tap % 3 - 1)) * kPatchPS;
-            Frag fb[NT];
 #pragma unroll
-            for (int j = 0; j < NT; ++j)
-                fb[j].u = *reinterpret_cast<const uint4*>(wts + (16 * j + mrow) * kTapLd + tap * 32 + kq);
-#pragma unroll
-            for (int i = 0; i < RT; ++i) {
-                Frag fa;
-                fa.u = *reinterpret_cast<const uint4*>(patch + lbase[i] + toff);
+            for (int ks = 0; ks < KC; ks += 32) {
+                const int toff = ((tap / 3 - 1) * kPatchW + (tap % 3 - 1)) * PPS + ks;
+                Frag fb[NT];
 #pragma unroll
                 for (int j = 0; j < NT; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[j].v, fa.v, acc[i][j], 0, 0, 0);
+                    fb[j].u = *reinterpret_cast<const uint4*>(wts + (16 * j + mrow) * TLD + tap * KC + ks + kq);
+#pragma unroll
+                for (int i = 0; i < RT; ++i) {
+                    Frag fa;
+                    fa.u = *reinterpret_cast<const uint4*>(patch + lbase[i] + toff);
+#pragma unroll
+                    for (int j = 0; j < NT; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fb[j].v, fa.v, acc[i][j], 0, 0, 0);
+                }
             }
         }
         if (STAGED && c == nch - 1) {
@@ -953,7 +961,7 @@ static hipError_t launch_conv_impl(const ConvArgs& a, int mode, hipStream_t s, b
         else if (t4 * (nt == 4 ? c4 : c2) >= 512) th = 4, tn = nt;
         else if (t4 * c2 >= 512) th = 4, tn = 2;  // more blocks for the small layers
         else if (t4 * (nt == 4 ? c4 : c2) >= 256) th = 4, tn = nt;
-        else if (t4 * c2 >= 256) th = 4, tn = 2;
+        else th = 4, tn = 2;  // small layers: the most blocks
         if (th) {
             // persistent blocks: about kTileBlocksPerCu per CU over all channel blocks
             const long long nt_ = th == 8 ? t8 : t4, cbn = tn == 4 ? c4 : c2;
@@ -975,6 +983,8 @@ static hipError_t launch_conv_impl(const ConvArgs& a, int mode, hipStream_t s, b
                 hipLaunchKernelGGL((k_conv3_tile<8, 2, true>), g, dim3(256), 0, s, b, ntl);
             } else if (tn == 4) {
                 hipLaunchKernelGGL((k_conv3_tile<4, 4, true>), g, dim3(256), 0, s, b, ntl);
+            } else if (a.cin % 64 == 0) {  // 64 input channels per round trip
+                hipLaunchKernelGGL((k_conv3_tile<4, 2, true, 64>), g, dim3(256), 0, s, b, ntl);
             } else {
                 hipLaunchKernelGGL((k_conv3_tile<4, 2, true>), g, dim3(256), 0, s, b, ntl);
             }

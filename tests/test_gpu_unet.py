@@ -58,6 +58,9 @@ def unflatten(flat, shapes):
     # ... 48 output channels (a half-empty channel block), three 32-channel
     # chunks, two tiles per pixel chunk, ragged columns
     (1, 3, 48, 2, 2, 96, 136),
+    # 8-row x 64-channel conv tiles (the forward's direct epilogue, the
+    # backward's LDS-staged one with the ReLU mask), ragged rows and columns
+    (1, 3, 64, 1, 4, 124, 250),
 ])
 def test_unet_forward_and_gradients_match_oracle(E, c_in, c_out, base, levels, n, h, w):
     shapes = C.unet_shapes(c_in, c_out, base, levels)
