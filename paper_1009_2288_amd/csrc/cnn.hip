@@ -672,65 +672,83 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // over the taps in order, then the bias.
 constexpr int kC1MaxOut = 64;
 
-__global__ __launch_bounds__(256) void k_conv3_c1(ConvArgs a)
+__global__ __launch_bounds__(256) void k_conv3_c1(ConvArgs a, int seg_per_block)
 {
     // weights as fp32 [tap][n] (4 channels per LDS read), bias [n], and the
-    // three input rows the block's pixels read (zero outside the image)
+    // three input rows around the block's pixels (zero outside the image)
     __shared__ __attribute__((aligned(16))) float wt[9 * kC1MaxOut];
     __shared__ __attribute__((aligned(16))) float bs[kC1MaxOut];
     __shared__ float rows[3][256 + 2];
-    // block: blockIdx.y = image row (img h + y), pixels x0 .. x0 + pb - 1 of
-    // it, one thread per (pixel, 8 output channels)
+    // block: segments blockIdx.y seg_per_block .. + seg_per_block - 1 (pb
+    // pixels each) of image row blockIdx.x (img h + y), one thread per
+    // (pixel, 8 output channels)
     const int c8n = a.cout / 8, pb = 256 / c8n;
-    const int row = blockIdx.y, img = row / a.h, y = row - img * a.h, x0 = blockIdx.x * pb;
+    const int row = blockIdx.x, img = row / a.h, y = row - img * a.h;
     for (int i = threadIdx.x; i < a.cout * 9; i += 256) {
         const int t = i / a.cout, n = i - t * a.cout;
         wt[i] = bf2f(a.wt[(size_t)n * a.k_pad + t]);
     }
     for (int i = threadIdx.x; i < a.cout; i += 256) bs[i] = a.bias ? a.bias[i] : 0.0f;
-    for (int i = threadIdx.x; i < 3 * (pb + 2); i += 256) {
-        const int r = i / (pb + 2), c = i - r * (pb + 2), ys = y + r - 1, xs = x0 + c - 1;
-        rows[r][c] = ((unsigned)ys < (unsigned)a.h && (unsigned)xs < (unsigned)a.w)
-                         ? bf2f(a.x[(((size_t)img * a.h + ys) * a.w + xs) * a.x_cs + a.x_co])
-                         : 0.0f;
-    }
-    __syncthreads();
-    const int lp = threadIdx.x / c8n, n0 = (threadIdx.x - lp * c8n) * 8, x = x0 + lp;
-    if (lp >= pb || x >= a.w) return;
-    float acc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    const int lp = threadIdx.x / c8n, n0 = (threadIdx.x - lp * c8n) * 8;
+    // the staged values of this thread: element i = t + 256 k (k < 4) of the
+    // 3 x (pb + 2) <= 774 rows' values, row i / (pb + 2), column i % (pb + 2)
+    int sr[4], sc[4];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-        const float v = rows[t / 3][lp + t % 3];
-        const float4 w0 = *reinterpret_cast<const float4*>(wt + t * a.cout + n0);
-        const float4 w1 = *reinterpret_cast<const float4*>(wt + t * a.cout + n0 + 4);
-        acc[0] += v * w0.x;
-        acc[1] += v * w0.y;
-        acc[2] += v * w0.z;
-        acc[3] += v * w0.w;
-        acc[4] += v * w1.x;
-        acc[5] += v * w1.y;
-        acc[6] += v * w1.z;
-        acc[7] += v * w1.w;
+    for (int k = 0; k < 4; ++k) {
+        const int i = threadIdx.x + 256 * k;
+        sr[k] = i < 3 * (pb + 2) ? i / (pb + 2) : -1;
+        sc[k] = i - (i / (pb + 2)) * (pb + 2);
     }
-    const float4 b0 = *reinterpret_cast<const float4*>(bs + n0), b1 = *reinterpret_cast<const float4*>(bs + n0 + 4);
-    acc[0] += b0.x;
-    acc[1] += b0.y;
-    acc[2] += b0.z;
-    acc[3] += b0.w;
-    acc[4] += b1.x;
-    acc[5] += b1.y;
-    acc[6] += b1.z;
-    acc[7] += b1.w;
-    if (a.relu) {
+    const uint16_t* xin = a.x + (size_t)img * a.h * a.w * a.x_cs + a.x_co;
+    const int x_beg = blockIdx.y * seg_per_block * pb, x_end = min(a.w, x_beg + seg_per_block * pb);
+    for (int x0 = x_beg; x0 < x_end; x0 += pb) {
+        __syncthreads();  // the previous segment's rows are consumed (and the weights staged)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) acc[j] = fmaxf(acc[j], 0.0f);
+        for (int k = 0; k < 4; ++k) {
+            if (sr[k] < 0) continue;
+            const int ys = y + sr[k] - 1, xs = x0 + sc[k] - 1;
+            rows[sr[k]][sc[k]] = ((unsigned)ys < (unsigned)a.h && (unsigned)xs < (unsigned)a.w)
+                                     ? bf2f(xin[((size_t)ys * a.w + xs) * a.x_cs])
+                                     : 0.0f;
+        }
+        __syncthreads();
+        const int x = x0 + lp;
+        if (lp >= pb || x >= a.w) continue;
+        float acc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const float v = rows[t / 3][lp + t % 3];
+            const float4 w0 = *reinterpret_cast<const float4*>(wt + t * a.cout + n0);
+            const float4 w1 = *reinterpret_cast<const float4*>(wt + t * a.cout + n0 + 4);
+            acc[0] += v * w0.x;
+            acc[1] += v * w0.y;
+            acc[2] += v * w0.z;
+            acc[3] += v * w0.w;
+            acc[4] += v * w1.x;
+            acc[5] += v * w1.y;
+            acc[6] += v * w1.z;
+            acc[7] += v * w1.w;
+        }
+        const float4 b0 = *reinterpret_cast<const float4*>(bs + n0), b1 = *reinterpret_cast<const float4*>(bs + n0 + 4);
+        acc[0] += b0.x;
+        acc[1] += b0.y;
+        acc[2] += b0.z;
+        acc[3] += b0.w;
+        acc[4] += b1.x;
+        acc[5] += b1.y;
+        acc[6] += b1.z;
+        acc[7] += b1.w;
+        if (a.relu) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc[j] = fmaxf(acc[j], 0.0f);
+        }
+        uint4 o;
+        o.x = pack_bf16x2(acc[0], acc[1]);
+        o.y = pack_bf16x2(acc[2], acc[3]);
+        o.z = pack_bf16x2(acc[4], acc[5]);
+        o.w = pack_bf16x2(acc[6], acc[7]);
+        *reinterpret_cast<uint4*>(a.y + (((size_t)row * a.w) + x) * a.y_cs + a.y_co + n0) = o;
     }
-    uint4 o;
-    o.x = pack_bf16x2(acc[0], acc[1]);
-    o.y = pack_bf16x2(acc[2], acc[3]);
-    o.z = pack_bf16x2(acc[4], acc[5]);
-    o.w = pack_bf16x2(acc[6], acc[7]);
-    *reinterpret_cast<uint4*>(a.y + (((size_t)row * a.w) + x) * a.y_cs + a.y_co + n0) = o;
 }
 
 // 1x1 layers with a thin side (the head, C_in -> 3, and its backward data,
@@ -924,9 +942,12 @@ static hipError_t launch_conv_impl(const ConvArgs& a, int mode, hipStream_t s, b
     const int npix = a.n_img * a.h * a.w;
     if (mode == kConv3 && a.cin == 1 && !a.y32 && a.cout % 8 == 0 && a.cout <= kC1MaxOut && a.y_cs % 8 == 0 &&
         a.y_co % 8 == 0) {
-        const int pb = 256 / (a.cout / 8);
-        hipLaunchKernelGGL(k_conv3_c1, dim3((unsigned)((a.w + pb - 1) / pb), (unsigned)(a.n_img * a.h)), dim3(256), 0,
-                           s, a);
+        // row segments per block: the per-block set-up spread over several
+        // segments, while keeping about 2048 blocks
+        const int pb = 256 / (a.cout / 8), nseg = (a.w + pb - 1) / pb;
+        const int spb = std::max(1, std::min(nseg, a.n_img * a.h * nseg / 2048));
+        hipLaunchKernelGGL(k_conv3_c1, dim3((unsigned)(a.n_img * a.h), (unsigned)((nseg + spb - 1) / spb)), dim3(256),
+                           0, s, a, spb);
         return hipGetLastError();
     }
     if (up2x2_fits(a, mode)) {
