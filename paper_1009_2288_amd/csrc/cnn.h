@@ -38,6 +38,9 @@ struct ConvArgs {
     // pooling of the (bf16) output, [n_img][h/2][w/2] with channel stride p_cs
     uint16_t* pool = nullptr;
     int p_cs = 0;
+    // x32, if set: the input as dense fp32 (channel stride cin); it is rounded
+    // to bf16, the values also written to x (dense, the layer's stored input)
+    const float* x32 = nullptr;
 };
 
 inline int pad64(int n) { return (n + 63) / 64 * 64; }

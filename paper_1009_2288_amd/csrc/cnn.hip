@@ -707,9 +707,19 @@ __global__ __launch_bounds__(256) void k_conv3_c1(ConvArgs a, int seg_per_block)
         for (int k = 0; k < 4; ++k) {
             if (sr[k] < 0) continue;
             const int ys = y + sr[k] - 1, xs = x0 + sc[k] - 1;
-            rows[sr[k]][sc[k]] = ((unsigned)ys < (unsigned)a.h && (unsigned)xs < (unsigned)a.w)
-                                     ? bf2f(xin[((size_t)ys * a.w + xs) * a.x_cs])
-                                     : 0.0f;
+            const bool in = (unsigned)ys < (unsigned)a.h && (unsigned)xs < (unsigned)a.w;
+            float v = 0.0f;
+            if (in && a.x32) {
+                // fp32 input: round to bf16 here; the centre row's own
+                // pixels are also stored (the layer's bf16 input)
+                const uint16_t hv = f2bf(a.x32[((size_t)img * a.h + ys) * a.w + xs]);
+                v = bf2f(hv);
+                if (sr[k] == 1 && sc[k] >= 1 && sc[k] <= pb)
+                    const_cast<uint16_t*>(a.x)[((size_t)img * a.h + ys) * a.w + xs] = hv;
+            } else if (in) {
+                v = bf2f(xin[((size_t)ys * a.w + xs) * a.x_cs]);
+            }
+            rows[sr[k]][sc[k]] = v;
         }
         __syncthreads();
         const int x = x0 + lp;
@@ -941,7 +951,7 @@ static hipError_t launch_conv_impl(const ConvArgs& a, int mode, hipStream_t s, b
     *pooled = false;
     const int npix = a.n_img * a.h * a.w;
     if (mode == kConv3 && a.cin == 1 && !a.y32 && a.cout % 8 == 0 && a.cout <= kC1MaxOut && a.y_cs % 8 == 0 &&
-        a.y_co % 8 == 0) {
+        a.y_co % 8 == 0 && (!a.x32 || (a.x_cs == 1 && a.x_co == 0))) {
         // row segments per block: the per-block set-up spread over several
         // segments, while keeping about 2048 blocks
         const int pb = 256 / (a.cout / 8), nseg = (a.w + pb - 1) / pb;
@@ -1026,10 +1036,25 @@ static hipError_t launch_conv_impl(const ConvArgs& a, int mode, hipStream_t s, b
     return hipGetLastError();
 }
 
+static bool conv3_c1_takes_fp32(const ConvArgs& a, int mode)
+{
+    return mode == kConv3 && a.cin == 1 && !a.y32 && a.cout % 8 == 0 && a.cout <= kC1MaxOut && a.y_cs % 8 == 0 &&
+           a.y_co % 8 == 0 && a.x_cs == 1 && a.x_co == 0;
+}
+
 hipError_t launch_conv(const ConvArgs& a, int mode, hipStream_t s)
 {
     bool pooled = false;
-    hipError_t e = launch_conv_impl(a, mode, s, &pooled);
+    hipError_t e = hipSuccess;
+    if (a.x32 && !conv3_c1_takes_fp32(a, mode)) {  // the bf16 input first, as a pass of its own
+        if (a.x_cs != a.cin || a.x_co != 0) return hipErrorInvalidValue;
+        ConvArgs b = a;
+        b.x32 = nullptr;
+        e = launch_to_bf16(a.x32, const_cast<uint16_t*>(a.x), (size_t)a.n_img * a.h * a.w * a.cin, s);
+        if (e == hipSuccess) e = launch_conv(b, mode, s);
+        return e;
+    }
+    e = launch_conv_impl(a, mode, s, &pooled);
     if (e == hipSuccess && a.pool && !pooled) {  // the pooling as a pass of its own (dense output)
         if (a.p_cs != a.cout || a.y32) return hipErrorInvalidValue;
         e = launch_avgpool(a.y, a.y_cs, a.y_co, a.pool, a.n_img, a.h, a.w, a.cout, s);

@@ -100,9 +100,8 @@ static hipError_t forward(eptv_unet_s& u, const float* x, int n, float* y, hipSt
 {
     hipError_t e;
     const int L = u.levels;
-    if ((e = launch_to_bf16(x, u.xin.p, (size_t)n * u.h * u.w * u.c_in, s)) != hipSuccess) return e;
     auto conv = [&](int li, int mode, const uint16_t* xp, int xcs, int xco, int h, int w, uint16_t* yp, int ycs,
-                    int yco, float* y32, int relu, const Tensor* pool = nullptr) {
+                    int yco, float* y32, int relu, const Tensor* pool = nullptr, const float* x32 = nullptr) {
         const Layer& Ly = u.layers[li];
         ConvArgs a = conv_args(u, Ly, n, h, w, false);
         a.x = xp;
@@ -117,13 +116,16 @@ static hipError_t forward(eptv_unet_s& u, const float* x, int n, float* y, hipSt
             a.pool = pool->p;
             a.p_cs = pool->c;
         }
+        a.x32 = x32;
         return launch_conv(a, mode, s);
     };
     for (int l = 0; l < L; ++l) {
         const int h = u.h >> l, w = u.w >> l, C = u.base << l;
         const Tensor& inp = l == 0 ? u.xin : u.in[l];
-        if ((e = conv(layer_index(u, 'e', l, 'a'), kConv3, inp.p, inp.c, 0, h, w, u.a[l].p, C, 0, nullptr, 1)) !=
-            hipSuccess)
+        // the first layer reads the fp32 input and stores its bf16 rounding
+        // (xin, kept for the backward pass) on the way
+        if ((e = conv(layer_index(u, 'e', l, 'a'), kConv3, inp.p, inp.c, 0, h, w, u.a[l].p, C, 0, nullptr, 1, nullptr,
+                      l == 0 ? x : nullptr)) != hipSuccess)
             return e;
         // the level output (the skip half of the concatenation, or the
         // bottleneck), and below the bottom level its 2x2 average pooling, the
