@@ -72,8 +72,6 @@ hipError_t launch_eptv_to_maps(const float* f, const float* f_base, const float*
 hipError_t launch_maps_to_eptv(const float* y, const float* f_base, int n_img, int ny, int nx, float scale, float* f,
                                float* wx, float* wy, hipStream_t s);
 hipError_t launch_to_f32(const uint16_t* x, float* y, size_t n, hipStream_t s);
-hipError_t launch_add_slice(const uint16_t* src, int scs, int sco, uint16_t* dst, int dcs, int dco, int npix, int c,
-                            hipStream_t s);
 // fp32 master weights (parameter layout) -> packed bf16 GEMM operands
 //   conv3 forward: W[a][c][i][o] -> P[o][(3a+c) Ci + i]
 //   conv3 backward data: P[i][(8 - tap) Co + o] (flipped taps, in/out swapped)

@@ -1062,17 +1062,17 @@ hipError_t launch_conv(const ConvArgs& a, int mode, hipStream_t s)
     return e;
 }
 
-// ------------------------------------------------------------------ weight gradients
-// dW[n][k] = sum_p dY[p][n] A(p, k), split over chunks of pixels: block
-// (chunk, n block, k block) writes its 64 x 64 fp32 partial; k_wgrad_finish
-// sums the chunks in order.  The reduction runs over pixels, which are not
-// contiguous in NHWC, so each 64-pixel step stages dY and A transposed in LDS
-// ([channel][pixel], four pixels per 8-byte store); then each wave (2 x 2
-// arrangement) forms a 32 n x 32 k tile with MFMA rows n (A' = dY^T) and
-// columns k, 32 pixels per instruction.
+// ------------------------------------------------------------------ weight gradients (3x3 fallback)
+// For 3x3 layers whose C_in is neither a multiple of 32 nor 1 (the tiled
+// kernels below take those): dW[n][k] = sum_p dY[p][n] A(p, k), split over
+// chunks of pixels: block (chunk, n block, k block) writes its 64 x 64 fp32
+// partial; k_wgrad_finish sums the chunks in order.  The reduction runs over
+// pixels, which are not contiguous in NHWC, so each 64-pixel step stages dY
+// and A transposed in LDS ([channel][pixel], four pixels per 8-byte store);
+// then each wave (2 x 2 arrangement) forms a 32 n x 32 k tile with MFMA rows
+// n (A' = dY^T) and columns k, 32 pixels per instruction.
 constexpr int kWgLd = 72;  // LDS pitch in bf16 (64 pixels + 16 B)
 
-template <int MODE>
 __global__ __launch_bounds__(256) void k_wgrad(ConvArgs a, const uint16_t* __restrict__ dy, int dy_cs, int dy_co,
                                                int chunk_px, float* part, float* bpart)
 {
@@ -1082,8 +1082,7 @@ __global__ __launch_bounds__(256) void k_wgrad(ConvArgs a, const uint16_t* __res
     const int chunk = blockIdx.x;
     const int n0 = blockIdx.y * 64;
     const int k0 = blockIdx.z * 64;
-    const int q = MODE == kUp ? (int)(k0 / a.k_pad) : 0;  // kUp: the 4 parities side by side along k
-    const int kb = MODE == kUp ? k0 - q * a.k_pad : k0;
+    const int kb = k0;
     const int hw = a.h * a.w, npix = a.n_img * hw;
     const int p_beg = chunk * chunk_px, p_end = min(npix, p_beg + chunk_px);
     // loader role: threads 0-127 stage dY, 128-255 stage A; 4 pixels x 8 channels each
@@ -1111,9 +1110,7 @@ __global__ __launch_bounds__(256) void k_wgrad(ConvArgs a, const uint16_t* __res
             if (p >= p_end) continue;
             const int img = p / hw, r = p - img * hw, yy = r / a.w, xx = r - yy * a.w;
             if (load_dy) {
-                size_t pix = (size_t)p;
-                if (MODE == kUp) pix = ((size_t)img * 2 * a.h + 2 * yy + (q >> 1)) * 2 * a.w + 2 * xx + (q & 1);
-                const uint16_t* src = dy + pix * dy_cs + dy_co + n0 + lc;
+                const uint16_t* src = dy + (size_t)p * dy_cs + dy_co + n0 + lc;
                 if (dy_vec) {
                     v[u].u = *reinterpret_cast<const uint4*>(src);
                 } else {
@@ -1122,7 +1119,7 @@ __global__ __launch_bounds__(256) void k_wgrad(ConvArgs a, const uint16_t* __res
                         if (n0 + lc + i < a.cout) v[u].h[i] = src[i];
                 }
             } else {
-                v[u] = gather_a<MODE == kConv3 ? kConv3 : kPoint>(a, img, yy, xx, kb + lc);
+                v[u] = gather_a<kConv3>(a, img, yy, xx, kb + lc);
             }
         }
         __syncthreads();  // the previous step's tiles are consumed
@@ -1160,8 +1157,8 @@ __global__ __launch_bounds__(256) void k_wgrad(ConvArgs a, const uint16_t* __res
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i].v, fb[j].v, acc[i][j], 0, 0, 0);
         }
     }
-    // partial[chunk][n][k] over the padded n x (4 or 1) k_pad grid
-    const int kw = MODE == kUp ? 4 * a.k_pad : a.k_pad;
+    // partial[chunk][n][k] over the padded n x k_pad grid
+    const int kw = a.k_pad;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -1179,8 +1176,7 @@ __global__ __launch_bounds__(256) void k_wgrad(ConvArgs a, const uint16_t* __res
         if (threadIdx.x < 64) {
             const int t = threadIdx.x;
             const float v = (red[t] + red[64 + t]) + (red[128 + t] + red[192 + t]);
-            const int nq = MODE == kUp ? 4 : 1;
-            bpart[((size_t)chunk * nq + q) * a.n_pad + n0 + t] = v;
+            bpart[(size_t)chunk * a.n_pad + n0 + t] = v;
         }
     }
 }
@@ -1757,7 +1753,7 @@ hipError_t launch_wgrad(const ConvArgs& a, int mode, const uint16_t* dy, int dy_
     } else {
         chunks = wgrad_chunks(a, chunk_px);
         dim3 grid((unsigned)chunks, (unsigned)(a.n_pad / 64), (unsigned)(kw / 64));
-        hipLaunchKernelGGL(k_wgrad<kConv3>, grid, dim3(256), 0, s, a, dy, dy_cs, dy_co, chunk_px, part, bp);
+        hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, s, a, dy, dy_cs, dy_co, chunk_px, part, bp);
     }
     const size_t total = (size_t)a.cout * kw + (bias_out ? a.cout : 0);
     hipLaunchKernelGGL(k_wgrad_finish, dim3((unsigned)((total + 31) / 32)), dim3(256), 0, s, part, chunks,
@@ -1916,26 +1912,6 @@ __global__ void k_to_f32(const uint16_t* x, float* y, size_t n)
 hipError_t launch_to_f32(const uint16_t* x, float* y, size_t n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_to_f32, dim3((unsigned)std::min<size_t>((n + 255) / 256, 8192)), dim3(256), 0, s, x, y, n);
-    return hipGetLastError();
-}
-
-// accumulate a bf16 channel slice into another (the skip gradient joins the encoder's)
-__global__ void k_add_slice(const uint16_t* src, int scs, int sco, uint16_t* dst, int dcs, int dco, int npix, int c)
-{
-    const size_t n = (size_t)npix * c;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
-        const size_t p = i / c, k = i - p * c;
-        uint16_t* d = dst + p * dcs + dco + k;
-        *d = f2bf(bf2f(*d) + bf2f(src[p * scs + sco + k]));
-    }
-}
-
-hipError_t launch_add_slice(const uint16_t* src, int scs, int sco, uint16_t* dst, int dcs, int dco, int npix, int c,
-                            hipStream_t s)
-{
-    const size_t n = (size_t)npix * c;
-    hipLaunchKernelGGL(k_add_slice, dim3((unsigned)std::min<size_t>((n + 255) / 256, 8192)), dim3(256), 0, s, src, scs,
-                       sco, dst, dcs, dco, npix, c);
     return hipGetLastError();
 }
 
