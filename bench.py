@@ -45,10 +45,10 @@ PMC_TRAFFIC = {
                 "bytes": (8343.5 * 2.0 + 125.6 * 1.0) * 1024},
     "backproject": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "4232d9b9533001f9",
                     "bytes": (5979.9 * 2.0 + 1304.0 * 1.0) * 1024},
-    "project_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "9627430b42c3fee4",
-                       "bytes": (69880.5 * 2.0 + 127.7 * 1.0) * 1024},
-    "backproject_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "9627430b42c3fee4",
-                           "bytes": (56069.5 * 2.0 + 2293.0 * 1.0) * 1024},
+    "project_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "e0fcaada13e40536",
+                       "bytes": (60873.0 * 2.0 + 129.3 * 1.0) * 1024},
+    "backproject_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "e0fcaada13e40536",
+                           "bytes": (56056.7 * 2.0 + 2292.8 * 1.0) * 1024},
 }
 
 
@@ -56,10 +56,10 @@ PMC_TRAFFIC = {
 # stored_hbm leg, whose matrix streams from HBM); see
 # profiles/eptv_stored_operators_512x512_200views_paper_scanner_pmc_bytes.md.
 PMC_TRAFFIC_HBM = {
-    "project_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "9627430b42c3fee4",
-                       "bytes": (497902.8 * 2.0 + 895.4 * 1.0) * 1024},
-    "backproject_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "9627430b42c3fee4",
-                           "bytes": (459965.1 * 2.0 + 1150.0 * 1.0) * 1024},
+    "project_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "e0fcaada13e40536",
+                       "bytes": (430343.8 * 2.0 + 902.8 * 1.0) * 1024},
+    "backproject_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "e0fcaada13e40536",
+                           "bytes": (459931.0 * 2.0 + 1193.4 * 1.0) * 1024},
 }
 
 
@@ -83,10 +83,10 @@ PMC_L2 = {
                 "read_requests": 1.351e6},
     "backproject": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "4232d9b9533001f9",
                     "read_requests": 0.460e6},
-    "project_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "9627430b42c3fee4",
-                       "read_requests": 1.735e6},
-    "backproject_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "9627430b42c3fee4",
-                           "read_requests": 1.695e6},
+    "project_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "e0fcaada13e40536",
+                       "read_requests": 1.530e6},
+    "backproject_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "e0fcaada13e40536",
+                           "read_requests": 1.683e6},
 }
 
 
@@ -122,6 +122,13 @@ def pmc_traffic(kernel, table=None):
         if hashlib.sha256(fh.read()).hexdigest()[:16] != e["sha256_16"]:
             return None
     return e["bytes"]
+
+
+def entry_bytes(P, kernel):
+    """Stored bytes per nonzero read by a stored-matrix product: a 4-byte
+    length with a 16-bit index offset in the compact CSR encoding, else a
+    4-byte length and a 4-byte index."""
+    return 6.0 if kernel == "project_stored" and P.stored_layout()["csr_compact"] else 8.0
 
 
 def log(msg):
@@ -408,7 +415,7 @@ def stored_hbm_leg(E, synth, torch, np, reps, steps, n_views=200):
             ("project_stored", lambda: P.project_stored_dual(x, xT, q), n_sino, n_img, n_sino),
             ("backproject_stored", lambda: P.backproject_stored(y, z), n_img, n_sino, n_img)):
         ms = kernel_avg_ms(fn, reps, torch)
-        nbytes = 8.0 * nnz + 4.0 * (rows + 1) + 4.0 * (n_in + n_out)
+        nbytes = entry_bytes(P, name) * nnz + 4.0 * (rows + 1) + 4.0 * (n_in + n_out)
         out[name] = {"avg_ms": ms, "algorithmic_bytes_per_launch": nbytes, "gbps": nbytes / (ms * 1e-3) / 1e9,
                      "frac": nbytes / (ms * 1e-3) / HBM_PEAK}
     rd = achievable_read(torch, E)
@@ -554,12 +561,13 @@ def main():
         kern = k_proj if dom == "project" else k_bp
         t_dom = op_ms[kern]
         if kern.endswith("_stored"):
-            # one CSR (or CSC) pass: 4-byte value and 4-byte index per nonzero
-            # (the padding to 4 entries per row is overhead, not counted), a
-            # 4-byte offset per row (column), the input vector once, the output once
+            # one CSR (or CSC) pass: each nonzero at its stored size (see
+            # entry_bytes; the padding to 4 entries per row and the CSR chunk
+            # bases are overhead, not counted), a 4-byte offset per row
+            # (column), the input vector once, the output once
             n_img, n_sino = g.nx * g.ny, g.n_views * g.n_bins
             rows, n_in, n_out = (n_sino, n_img, n_sino) if dom == "project" else (n_img, n_sino, n_img)
-            nbytes = 8.0 * nnz + 4.0 * (rows + 1) + 4.0 * (n_in + n_out)
+            nbytes = entry_bytes(P, dom + "_stored") * nnz + 4.0 * (rows + 1) + 4.0 * (n_in + n_out)
             achieved = nbytes / (t_dom * 1e-3)
             return {"bound": "hbm", "kernel": dom + "_stored", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
                     "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": pmc_traffic(dom + "_stored"),
@@ -587,6 +595,11 @@ def main():
         roof["achievable_copy_gbps"] = achievable_hbm(torch) / 1e9
         roof["note"] = ("cache-assisted: both stored copies (%.0f MB) fit the 256 MB Infinity Cache between calls"
                         % (P.store_matrix() / 1e6))
+        if roof["kernel"] == "project_stored" and P.stored_layout()["csr_compact"]:
+            roof["note"] += ("; P reads the compact CSR encoding (6 bytes per nonzero, the bytes counted here; "
+                             "the same call at 8 bytes per nonzero would be %.0f GB/s)"
+                             % (roof["achieved"] * (roof["algorithmic_bytes_per_launch"] + 2.0 * nnz)
+                                / roof["algorithmic_bytes_per_launch"]))
     log("bench: " + ", ".join(f"{k} {v * 1e3:.1f} us" for k, v in op_ms.items()) + f", nnz {nnz}")
 
     ttr = None

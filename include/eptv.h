@@ -162,14 +162,23 @@ int eptv_plan_nnz(eptv_plan plan, long long* nnz);
 int eptv_geometry_matrix(const eptv_geometry* geom, long long* nnz, long long* rowptr, int* col, float* val);
 
 /* Store that matrix on the plan's device, by ray (CSR, for P) and by pixel
- * (CSC, for P^T): 16 bytes per nonzero plus the offsets and a padding of each
- * ray and pixel to a multiple of 4 entries (219 MB at 512^2 / 40 views x 736
- * bins).  A ray swept row by row indexes the transposed image, so that its
+ * (CSC, for P^T), each ray and pixel padded to a multiple of 4 entries.  The
+ * CSC copy takes 8 bytes per entry (index, length).  The CSR copy takes 6
+ * (float32 length and a 16-bit index offset within a 128-entry chunk of the
+ * ray, plus a 4-byte base per chunk) whenever every chunk's indices span at
+ * most 65535, else 8 like the CSC copy (190 MB in all at 512^2 / 40 views x
+ * 736 bins).  A ray swept row by row indexes the transposed image, so that its
  * entries lie along the fast axis of the image it reads.  Owned by the plan;
  * built once, later calls only report the size.  Synchronous.  EPTV_ERR_ARG
  * when a copy would hold 2^31 entries or more (int32 offsets); EPTV_ERR_HIP
  * when device memory runs out (nothing is kept then). */
 int eptv_plan_store_matrix(eptv_plan plan, size_t* device_bytes);
+
+/* The stored matrix's layout (EPTV_ERR_ARG if it is not stored): *csr_compact
+ * 1 for the 6-byte CSR encoding, 0 for the 8-byte one; *csr_bytes and
+ * *csc_bytes the device bytes of each copy with its offsets.  Any pointer may
+ * be NULL. */
+int eptv_plan_stored_layout(eptv_plan plan, int* csr_compact, size_t* csr_bytes, size_t* csc_bytes);
 
 /* q = alpha P x + beta q and z = alpha P^T r + beta z from the stored matrix
  * (EPTV_ERR_ARG if it is not stored).  Same matrix as eptv_project /

@@ -107,22 +107,35 @@ struct DevState {
 };
 
 // The float32 system matrix stored on the device (optional, see spmv.hip).
-// Entries are (other index, float bits of the length) pairs; every row and
-// column is padded to a multiple of kStoredPad entries with its last index and
-// length 0, so a lane's entries are whole, aligned 16-byte loads.  The CSR
-// copy is split in chunks of kStoredChunk entries per ray (the last one
-// shorter), each stored as n/2 pairs of entries (l, n/2 + l).
+// Every row and column is padded to a multiple of kStoredPad entries with its
+// last index and length 0.  The CSR copy (by ray) is split in chunks of
+// kStoredChunk entries per ray (the last one shorter); within a chunk of n
+// entries, slot l holds entries l and n/2 + l.  It has two encodings:
+//  * compact (whenever every chunk's indices span at most 65535): a chunk is
+//    n/2 slots of three 32-bit words (the two lengths' float bits, then the
+//    two indices as 16-bit offsets from the chunk's smallest index, entry l in
+//    the low half) followed by one word holding that smallest index, so a
+//    full chunk is kChunkWords words and an entry costs 6 bytes;
+//  * wide: slots of two (index, length bits) pairs, 16 bytes, 8 per entry.
+// The CSC copy (by pixel) holds (ray index, length bits) pairs, entry order,
+// so a lane's 4 entries are two aligned 16-byte loads.
 constexpr int kStoredPad = 4;
 constexpr int kStoredChunk = 128;
+constexpr int kChunkWords = 3 * (kStoredChunk / 2) + 1;
 struct StoredMatrix {
     long long nnz = 0;          // nonzeros, padding excluded
     long long slots = 0;        // entries per copy, padding included
-    int* d_rowptr = nullptr;    // [V*B + 1] CSR by ray, offsets into d_rent
-    int2* d_rent = nullptr;     // [slots] (pixel index into x, or into x transposed for
-                                //  rays swept row by row; length)
+    bool compact = false;       // the CSR copy's encoding
+    int* d_rowptr = nullptr;    // [V*B + 1] CSR by ray: word offsets into d_rwords (compact) or
+                                //  entry offsets into d_rent (wide); bit 31 set for a ray swept
+                                //  row by row
+    int* d_rwords = nullptr;    // compact CSR chunks (pixel index into x, or into x transposed
+                                //  for rays swept row by row)
+    int2* d_rent = nullptr;     // wide CSR slots: (index as above, length bits) pairs
     int* d_colptr = nullptr;    // [nx*ny + 1] CSC by pixel, offsets into d_cent
     int2* d_cent = nullptr;     // [slots of the CSC copy] (ray index, length)
-    size_t bytes = 0;
+    size_t bytes = 0;           // both copies with their offsets
+    size_t csr_bytes = 0;       // the CSR copy with its offsets
 };
 
 struct Plan {

@@ -324,6 +324,7 @@ int eptv_plan_destroy(eptv_plan h)
     if (p.rays.d_ray) hipFree(p.rays.d_ray);
     if (p.mat.d_rowptr) hipFree(p.mat.d_rowptr);
     if (p.mat.d_rent) hipFree(p.mat.d_rent);
+    if (p.mat.d_rwords) hipFree(p.mat.d_rwords);
     if (p.mat.d_colptr) hipFree(p.mat.d_colptr);
     if (p.mat.d_cent) hipFree(p.mat.d_cent);
     if (p.rays.d_range) hipFree(p.rays.d_range);
@@ -365,31 +366,52 @@ int eptv_plan_store_matrix(eptv_plan h, size_t* device_bytes)
     if (!p.mat.d_rowptr) {
         HostStored hs;
         if (pack_stored(p, hs) != EPTV_OK) return EPTV_ERR_ARG;
-        const auto& rowptr = hs.rowptr;
+        // the CSR copy goes up in one encoding: compact when it applies, else
+        // wide; bit 31 of a ray's offset marks a ray swept row by row
+        std::vector<int> rowptr = hs.compact ? hs.rwordptr : hs.rowptr;
+        for (size_t r = 0; r < hs.rows.size(); ++r)
+            if (hs.rows[r]) rowptr[r] = (int)((unsigned)rowptr[r] | 0x80000000u);
+        const size_t rbytes = hs.compact ? hs.rwords.size() * 4 : hs.rent.size() * 8;
+        const void* rsrc = hs.compact ? (const void*)hs.rwords.data() : (const void*)hs.rent.data();
         const auto& colptr = hs.colptr;
-        const auto& rent = hs.rent;
         const auto& cent = hs.cent;
-        const long long nnz = hs.nnz;
         StoredMatrix& S = p.mat;
+        void* rdst = nullptr;
         hipError_t e = hipMalloc(&S.d_rowptr, rowptr.size() * 4);
-        if (e == hipSuccess) e = hipMalloc(&S.d_rent, rent.size() * 8);
+        if (e == hipSuccess) e = hipMalloc(&rdst, rbytes);
         if (e == hipSuccess) e = hipMalloc(&S.d_colptr, colptr.size() * 4);
         if (e == hipSuccess) e = hipMalloc(&S.d_cent, cent.size() * 8);
         if (e == hipSuccess) e = hipMemcpy(S.d_rowptr, rowptr.data(), rowptr.size() * 4, hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(S.d_rent, rent.data(), rent.size() * 8, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(rdst, rsrc, rbytes, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(S.d_colptr, colptr.data(), colptr.size() * 4, hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(S.d_cent, cent.data(), cent.size() * 8, hipMemcpyHostToDevice);
         if (e != hipSuccess) {
-            for (void* ptr : {(void*)S.d_rowptr, (void*)S.d_rent, (void*)S.d_colptr, (void*)S.d_cent})
+            for (void* ptr : {(void*)S.d_rowptr, rdst, (void*)S.d_colptr, (void*)S.d_cent})
                 if (ptr) hipFree(ptr);
             S = StoredMatrix();
             return hip_fail(e, "eptv_plan_store_matrix");
         }
-        S.slots = (long long)rent.size();
-        S.nnz = nnz;
-        S.bytes = (rowptr.size() + colptr.size()) * 4 + (rent.size() + cent.size()) * 8;
+        S.compact = hs.compact;
+        if (hs.compact)
+            S.d_rwords = (int*)rdst;
+        else
+            S.d_rent = (int2*)rdst;
+        S.slots = (long long)hs.rowptr.back();
+        S.nnz = hs.nnz;
+        S.csr_bytes = rowptr.size() * 4 + rbytes;
+        S.bytes = S.csr_bytes + colptr.size() * 4 + cent.size() * 8;
     }
     if (device_bytes) *device_bytes = p.mat.bytes;
+    return EPTV_OK;
+}
+
+int eptv_plan_stored_layout(eptv_plan h, int* csr_compact, size_t* csr_bytes, size_t* csc_bytes)
+{
+    if (!h || !h->p.mat.d_rowptr) return EPTV_ERR_ARG;
+    const StoredMatrix& S = h->p.mat;
+    if (csr_compact) *csr_compact = S.compact ? 1 : 0;
+    if (csr_bytes) *csr_bytes = S.csr_bytes;
+    if (csc_bytes) *csc_bytes = S.bytes - S.csr_bytes;
     return EPTV_OK;
 }
 

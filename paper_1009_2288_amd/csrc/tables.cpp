@@ -255,6 +255,50 @@ int pack_stored(const Plan& p, HostStored& s)
         !pack(npix, colcnt.data(), rowi.data(), cval.data(), false, s.colptr, s.cent))
         return EPTV_ERR_ARG;
     s.nnz = nnz;
+    s.rows = m.rows;
+    // the compact encoding of the CSR copy (see StoredMatrix), when every
+    // chunk's indices span at most 65535 and the words fit int32 offsets
+    s.compact = true;
+    s.rwordptr.assign((size_t)nrow + 1, 0);
+    long long words = 0;
+    for (int r = 0; r < nrow && s.compact; ++r) {
+        const int n = s.rowptr[(size_t)r + 1] - s.rowptr[r];
+        words += (long long)(n / kStoredChunk) * kChunkWords;
+        if (n % kStoredChunk) words += 3 * (n % kStoredChunk) / 2 + 1;
+        if (words >= (1LL << 31)) s.compact = false;
+        s.rwordptr[(size_t)r + 1] = (int)words;
+        for (int c0 = s.rowptr[r]; c0 < s.rowptr[(size_t)r + 1] && s.compact; c0 += kStoredChunk) {
+            const int nc = std::min(kStoredChunk, s.rowptr[(size_t)r + 1] - c0);
+            int lo = s.rent[(size_t)c0].x, hi = lo;
+            for (int e = c0; e < c0 + nc; ++e) {
+                lo = std::min(lo, s.rent[(size_t)e].x);
+                hi = std::max(hi, s.rent[(size_t)e].x);
+            }
+            if (hi - lo > 0xffff) s.compact = false;
+        }
+    }
+    if (!s.compact) {
+        s.rwordptr.clear();
+        return EPTV_OK;
+    }
+    s.rwords.assign((size_t)words, 0);
+    for (int r = 0; r < nrow; ++r) {
+        long long w = s.rwordptr[r];
+        for (int c0 = s.rowptr[r]; c0 < s.rowptr[(size_t)r + 1]; c0 += kStoredChunk) {
+            const int nc = std::min(kStoredChunk, s.rowptr[(size_t)r + 1] - c0), h = nc / 2;
+            int base = s.rent[(size_t)c0].x;
+            for (int e = c0; e < c0 + nc; ++e) base = std::min(base, s.rent[(size_t)e].x);
+            for (int l = 0; l < h; ++l) {
+                const int2 a = s.rent[(size_t)(c0 + 2 * l)], b = s.rent[(size_t)(c0 + 2 * l + 1)];
+                s.rwords[(size_t)(w + 3 * l)] = a.y;
+                s.rwords[(size_t)(w + 3 * l + 1)] = b.y;
+                s.rwords[(size_t)(w + 3 * l + 2)] = (int)((unsigned)(a.x - base) | ((unsigned)(b.x - base) << 16));
+            }
+            s.rwords[(size_t)(w + 3 * h)] = base;
+            w += 3 * h + 1;
+        }
+    }
+    std::vector<int2>().swap(s.rent);
     return EPTV_OK;
 }
 

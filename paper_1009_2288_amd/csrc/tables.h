@@ -54,8 +54,11 @@ void build_csr(const Plan& p, HostCsr& m);
 
 // The padded, interleaved copies of StoredMatrix, as uploaded.
 struct HostStored {
-    std::vector<int> rowptr, colptr;
-    std::vector<int2> rent, cent;
+    std::vector<int> rowptr, colptr;  // entry offsets (padded) of the CSR and CSC copies
+    std::vector<int2> rent, cent;     // wide CSR slots (emptied when compact), CSC pairs
+    bool compact = false;             // the CSR copy is also held in the compact encoding:
+    std::vector<int> rwordptr, rwords;  //  word offsets per ray and the chunks' words
+    std::vector<char> rows;           // per ray: swept row by row (indexes the transposed image)
     long long nnz = 0;
 };
 // EPTV_OK, or EPTV_ERR_ARG when an index or offset would not fit int32.

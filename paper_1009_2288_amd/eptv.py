@@ -24,6 +24,7 @@ EPTV_OK, EPTV_ERR_ARG, EPTV_ERR_GEOMETRY, EPTV_ERR_WORKSPACE, EPTV_ERR_HIP, EPTV
 SYMBOLS = ["eptv_plan_create", "eptv_plan_destroy", "eptv_plan_nnz", "eptv_workspace_bytes", "eptv_project",
            "eptv_project_dual", "eptv_backproject", "eptv_tv_gradient", "eptv_select_sigma", "eptv_tv_step", "eptv_reconstruct",
            "eptv_status_string", "eptv_last_error", "eptv_geometry_matrix", "eptv_plan_store_matrix",
+           "eptv_plan_stored_layout",
            "eptv_project_stored", "eptv_project_stored_dual", "eptv_backproject_stored", "eptv_backproject_interp",
            "eptv_tv_gradient_vjp", "eptv_batch_create", "eptv_batch_destroy", "eptv_batch_size", "eptv_batch_plan",
            "eptv_batch_workspace_bytes", "eptv_batch_set_launch", "eptv_batch_get_launch", "eptv_batch_tune",
@@ -187,6 +188,7 @@ def _lib() -> C.CDLL:
                                                 C.POINTER(_Stats), vp]
         L.eptv_geometry_matrix.argtypes = [C.POINTER(_Geometry), C.POINTER(C.c_longlong), vp, vp, vp]
         L.eptv_plan_store_matrix.argtypes = [vp, C.POINTER(sz)]
+        L.eptv_plan_stored_layout.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(sz), C.POINTER(sz)]
         L.eptv_project_stored.argtypes = [vp, vp, vp, C.c_float, C.c_float, vp, sz, vp]
         L.eptv_project_stored_dual.argtypes = [vp, vp, vp, vp, C.c_float, C.c_float, vp]
         L.eptv_backproject_stored.argtypes = [vp, vp, vp, C.c_float, C.c_float, vp]
@@ -348,6 +350,14 @@ class Plan:
         with torch.cuda.device(self.device):
             _check(_lib().eptv_plan_store_matrix(self._h, C.byref(n)), "eptv_plan_store_matrix")
         return int(n.value)
+
+    def stored_layout(self) -> dict:
+        """The stored matrix's CSR encoding (compact: 6 bytes per entry, else 8)
+        and each copy's device bytes."""
+        cp, rb, cb = C.c_int(), C.c_size_t(), C.c_size_t()
+        _check(_lib().eptv_plan_stored_layout(self._h, C.byref(cp), C.byref(rb), C.byref(cb)),
+               "eptv_plan_stored_layout")
+        return {"csr_compact": bool(cp.value), "csr_bytes": int(rb.value), "csc_bytes": int(cb.value)}
 
     def project_stored(self, x: torch.Tensor, out: Optional[torch.Tensor] = None, alpha: float = 1.0,
                        beta: float = 0.0, stream=None) -> torch.Tensor:

@@ -52,7 +52,7 @@ static eptv_geometry geom(int nx, int ny, double pix, int V, int B, double sad, 
     return g;
 }
 
-static void check_geometry(const eptv_geometry& g, const char* name)
+static void check_geometry(const eptv_geometry& g, const char* name, int want_compact = -1)
 {
     CHECK(validate_geometry(&g) == EPTV_OK, "%s: geometry rejected", name);
     const Plan p = host_plan(&g);
@@ -98,21 +98,36 @@ static void check_geometry(const eptv_geometry& g, const char* name)
     HostStored s;
     CHECK(pack_stored(p, s) == EPTV_OK, "%s: pack_stored", name);
     CHECK(s.nnz == t.nnz, "%s: stored nnz", name);
+    CHECK(s.rows == m.rows, "%s: stored row-sweep flags", name);
+    CHECK(want_compact < 0 || (int)s.compact == want_compact, "%s: CSR encoding compact = %d", name, (int)s.compact);
+    CHECK(s.compact ? s.rent.empty() && (int)s.rwordptr.size() == nrow + 1 : s.rwords.empty(), "%s: one CSR encoding",
+          name);
     CHECK((int)s.rowptr.size() == nrow + 1 && (int)s.colptr.size() == npix + 1, "%s: stored offsets", name);
     for (int r = 0; r < nrow; ++r) {
         const int a = s.rowptr[r], b = s.rowptr[r + 1];
         const long long len = m.rowptr[r + 1] - m.rowptr[r];
         CHECK(a % kStoredPad == 0 && b % kStoredPad == 0, "%s: row %d not padded", name, r);
         CHECK(b - a == (len + kStoredPad - 1) / kStoredPad * kStoredPad, "%s: row %d padded length", name, r);
-        // un-interleave the chunks: slot l of a chunk of n holds entries l and n/2 + l
+        // un-interleave the chunks: slot l of a chunk of n holds entries l and n/2 + l;
+        // compact slots are (length bits, length bits, 16-bit offsets) and the chunk's base
         std::vector<int2> flat((size_t)(b - a));
+        long long wpos = s.compact ? s.rwordptr[(size_t)r] : 0;
         for (int c0 = a; c0 < b; c0 += kStoredChunk) {
             const int nc = std::min(kStoredChunk, b - c0), h = nc / 2;
             for (int l = 0; l < h; ++l) {
-                flat[(size_t)(c0 - a + l)] = s.rent[(size_t)(c0 + 2 * l)];
-                flat[(size_t)(c0 - a + h + l)] = s.rent[(size_t)(c0 + 2 * l + 1)];
+                if (s.compact) {
+                    const int base = s.rwords[(size_t)(wpos + 3 * h)];
+                    const unsigned off = (unsigned)s.rwords[(size_t)(wpos + 3 * l + 2)];
+                    flat[(size_t)(c0 - a + l)] = int2{base + (int)(off & 0xffffu), s.rwords[(size_t)(wpos + 3 * l)]};
+                    flat[(size_t)(c0 - a + h + l)] = int2{base + (int)(off >> 16), s.rwords[(size_t)(wpos + 3 * l + 1)]};
+                } else {
+                    flat[(size_t)(c0 - a + l)] = s.rent[(size_t)(c0 + 2 * l)];
+                    flat[(size_t)(c0 - a + h + l)] = s.rent[(size_t)(c0 + 2 * l + 1)];
+                }
             }
+            wpos += 3 * h + 1;
         }
+        if (s.compact) CHECK(wpos == s.rwordptr[(size_t)r + 1], "%s: row %d compact words", name, r);
         for (long long e = 0; e < len; ++e) {
             const int col = m.col[m.rowptr[r] + e];
             const int want = m.rows[r] ? (col % p.nx) * p.ny + col / p.nx : col;
@@ -143,8 +158,9 @@ static void check_geometry(const eptv_geometry& g, const char* name)
         }
     }
     CHECK(seen == t.nnz, "%s: CSC holds %lld of %lld entries", name, seen, t.nnz);
-    std::printf("%s: %d x %d, %d x %d, nnz %lld, list %zu ids, stored %zu + %zu slots\n", name, p.nx, p.ny, p.V,
-                p.B, t.nnz, t.list.size(), s.rent.size(), s.cent.size());
+    std::printf("%s: %d x %d, %d x %d, nnz %lld, list %zu ids, stored %s CSR (%zu slots / %zu words) + %zu CSC\n",
+                name, p.nx, p.ny, p.V, p.B, t.nnz, t.list.size(), s.compact ? "compact" : "wide", s.rent.size(),
+                s.rwords.size(), s.cent.size());
 }
 
 static void check_rejections()
@@ -234,7 +250,11 @@ int main()
     check_geometry(geom(77, 53, 1.1, 13, 101, 300.0, 600.0, 0.3), "77x53 offset");
     check_geometry(geom(33, 18, 0.9, 5, 64, 80.0, 160.0, -0.45, ang), "33x18 given angles");
     check_geometry(geom(65, 65, 1.0, 7, 129, 400.0, 800.0, 0.0), "65x65 isocentre ray");
-    check_geometry(geom(128, 128, 1.0, 30, 256, 500.0, 1000.0, 0.0), "128x128 30 views");
+    check_geometry(geom(128, 128, 1.0, 30, 256, 500.0, 1000.0, 0.0), "128x128 30 views", 1);
+    // a 1100-pixel-wide image seen at 45 degrees: a 128-entry chunk of a
+    // diagonal ray spans ~64 image rows (> 65535 indices), so the CSR copy
+    // keeps the wide encoding
+    check_geometry(geom(1100, 1100, 0.5, 2, 64, 2000.0, 4000.0, 0.0, ang), "1100x1100 wide CSR", 0);
     if (g_fail) {
         std::fprintf(stderr, "%d checks failed\n", g_fail);
         return 1;

@@ -52,11 +52,20 @@ def odd_geom():
     return Geometry(65, 65, 1.0, 7, 129, fan_dbeta(65, 65, 1.0, 120.0, 129), 120.0, 240.0)
 
 
+def wide_geom():
+    # 1100 pixels wide, two views 45 degrees apart: a 128-entry chunk of a
+    # diagonal ray spans more than 65535 image indices, so the stored CSR copy
+    # keeps its wide (16-byte slot) encoding
+    return Geometry(1100, 1100, 0.5, 2, 64, fan_dbeta(1100, 1100, 0.5, 2000.0, 64), 2000.0, 4000.0,
+                    view_angles_rad=np.array([0.0, np.pi / 4]))
+
+
 GEOMS = {
     "small": synth.geometry_small,
     "paper": synth.geometry_paper,
     "ragged": ragged_geom,
     "odd": odd_geom,
+    "wide": wide_geom,
 }
 
 _mat_cache = {}
@@ -382,12 +391,16 @@ def test_zero_iterations_and_empty_steps(E):
 
 # ------------------------------------------------------------------ the stored matrix (Sec. 2.3 look-up tables)
 
-@pytest.mark.parametrize("name", ["small", "paper", "ragged", "odd"])
+@pytest.mark.parametrize("name", ["small", "paper", "ragged", "odd", "wide"])
 def test_stored_matrix_parity(E, oracle, name):
     g = GEOMS[name]()
     M, P = matrix(oracle, name), plan(E, name)
     nbytes = P.store_matrix()
-    assert nbytes >= 16 * P.nnz
+    # compact CSR (6 bytes per entry) + CSC (8), or the wide CSR (8) + CSC (8)
+    lay = P.stored_layout()
+    assert lay["csr_compact"] == (name != "wide")
+    assert lay["csr_bytes"] + lay["csc_bytes"] == nbytes
+    assert lay["csc_bytes"] >= 8 * P.nnz and lay["csr_bytes"] >= (6 if lay["csr_compact"] else 8) * P.nnz
     x = synth.random_image(g.nx, g.ny, 41)
     r = synth.random_sinogram(g.n_views, g.n_bins, 42)
     qs = P.project_stored(dev(x)).cpu().numpy()
