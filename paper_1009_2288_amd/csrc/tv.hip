@@ -74,6 +74,57 @@ __device__ __forceinline__ float tv_down(const Nbhd& N, float e2)
     return tv_edge(N.n[1][0], N.n[1][1], N.n[2][0], N.n[2][1], N.n[0][0], N.n[0][1], e2);
 }
 
+// tv_edge's three differences (across the half-edge, and of the pair means on
+// either side along it) are linear in the image, so for a trial point
+// f - t g they are f's minus t times g's: one FMA each per candidate instead
+// of forming the trial neighbourhood.
+struct EdgeLin {
+    float d, t1, t2;
+};
+
+__device__ __forceinline__ EdgeLin edge_lin(float a, float b, float au, float bu, float ad, float bd)
+{
+    const float m0 = 0.5f * (a + b), mu = 0.5f * (au + bu), md = 0.5f * (ad + bd);
+    return {b - a, mu - m0, m0 - md};
+}
+
+// The owned half-edges of a pixel: right and up, and left / down on the
+// image's first column / row.
+struct EdgeSet {
+    EdgeLin R, U, L, D;
+};
+
+__device__ __forceinline__ EdgeSet edge_set(const Nbhd& N, bool left, bool down)
+{
+    EdgeSet E;
+    E.R = edge_lin(N.n[1][1], N.n[2][1], N.n[1][2], N.n[2][2], N.n[1][0], N.n[2][0]);
+    E.U = edge_lin(N.n[1][1], N.n[1][2], N.n[2][1], N.n[2][2], N.n[0][1], N.n[0][2]);
+    E.L = left ? edge_lin(N.n[0][1], N.n[1][1], N.n[0][2], N.n[1][2], N.n[0][0], N.n[1][0]) : EdgeLin{0.f, 0.f, 0.f};
+    E.D = down ? edge_lin(N.n[1][0], N.n[1][1], N.n[2][0], N.n[2][1], N.n[0][0], N.n[0][1]) : EdgeLin{0.f, 0.f, 0.f};
+    return E;
+}
+
+// Magnitude of a half-edge at f - t g from its terms in f (F) and g (G).
+__device__ __forceinline__ float edge_at(const EdgeLin& F, const EdgeLin& G, float t, float e2)
+{
+    const float d = fmaf(-t, G.d, F.d), t1 = fmaf(-t, G.t1, F.t1), t2 = fmaf(-t, G.t2, F.t2);
+    return hw_sqrt(d * d + 0.5f * (t1 * t1) + 0.5f * (t2 * t2) + e2);
+}
+
+// A pixel's share of Q(f - t g) (Eq. 8 with Eq. A3's magnitudes): its owned
+// half-edges' weighted magnitudes (weights frozen) plus lambda/2 (f - t g - v)^2
+// at the pixel; dv0 = f - v and g11 = g at the pixel.
+__device__ __forceinline__ double trial_energy(const EdgeSet& F, const EdgeSet& G, float wR, float wU, float wL,
+                                               float wD, bool left, bool down, float dv0, float g11, float t,
+                                               float lambda, float e2)
+{
+    float s = wR * edge_at(F.R, G.R, t, e2) + wU * edge_at(F.U, G.U, t, e2);
+    if (left) s += wL * edge_at(F.L, G.L, t, e2);
+    if (down) s += wD * edge_at(F.D, G.D, t, e2);
+    const float d = fmaf(-t, g11, dv0);
+    return (double)s + 0.5 * (double)lambda * (double)d * (double)d;
+}
+
 
 // ------------------------------------------------------------------ sigma (radix select)
 // sigma is the order statistic of rank `rank` of all half-edge magnitudes.
@@ -434,20 +485,12 @@ __device__ __forceinline__ void candidate_energies(const float* f, const float* 
         if (i == 0) wL = weight(tv_left(F, eps2), inv_s2);
         if (j == 0) wD = weight(tv_down(F, eps2), inv_s2);
     }
-    const float vv = v[(size_t)j * nx + i];
+    const float dv0 = F.n[1][1] - v[(size_t)j * nx + i];
+    const EdgeSet EF = edge_set(F, i == 0, j == 0), EG = edge_set(G, i == 0, j == 0);
     float t = cand_t(t0, shrink, k0);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        Nbhd H;
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-            for (int bb = 0; bb < 3; ++bb) H.n[a][bb] = fmaf(-t, G.n[a][bb], F.n[a][bb]);
-        float s = wR * tv_right(H, eps2) + wU * tv_up(H, eps2);
-        if (i == 0) s += wL * tv_left(H, eps2);
-        if (j == 0) s += wD * tv_down(H, eps2);
-        const float d = H.n[1][1] - vv;
-        e[c] += (double)s + 0.5 * (double)lambda * (double)d * (double)d;
+        e[c] += trial_energy(EF, EG, wR, wU, wL, wD, i == 0, j == 0, dv0, G.n[1][1], t, lambda, eps2);
         t *= shrink;
     }
 }
@@ -514,28 +557,24 @@ struct DecShared {
     int verdict;
 };
 
-// Block sums of the kP2Slots values of every thread of a kP2Threads block in a
-// fixed order: the values go to LDS by slot, lane l of wave c sums slot c's
-// entries l, l + 64, ... in order, and wave c's butterfly closes slot c.
-// Results in L.tot for every thread.  Starts and ends with __syncthreads(), so
-// the LDS may alias data the block has finished with.
+// Block sums of kP2Slots values per thread of a kP2Threads block in a fixed
+// order: each thread stores its values in v[c][tid] (threads past the first
+// 64 nw store nothing and count as zeros), then lane l of wave c sums slot
+// c's entries l, l + 64, ... in order and wave c's butterfly closes slot c.
 struct SlotSums {
     double v[kP2Slots][kP2Threads];
     double tot[kP2Slots];
 };
 
-__device__ __forceinline__ void slot_sums(const double* val, SlotSums& L)
+// The sums of the values stored in L.v by the first 64 nw threads, in L.tot
+// for every thread.  Contains __syncthreads() before and after.
+__device__ __forceinline__ void slot_sums_stored(SlotSums& L, int nw = kP2Threads / 64)
 {
-    const int tid = threadIdx.x;
     __syncthreads();
-#pragma unroll
-    for (int c = 0; c < kP2Slots; ++c) L.v[c][tid] = val[c];
-    __syncthreads();
-    const int w = tid >> 6, l = tid & 63;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     if (w < kP2Slots) {
         double a = 0.0;
-#pragma unroll
-        for (int q = 0; q < kP2Threads / 64; ++q) a += L.v[w][l + 64 * q];
+        for (int q = 0; q < nw; ++q) a += L.v[w][l + 64 * q];
         a = wave_sum(a);
         if (l == 0) L.tot[w] = a;
     }
@@ -543,13 +582,9 @@ __device__ __forceinline__ void slot_sums(const double* val, SlotSums& L)
 }
 
 struct P2Shared {
-    union {
-        struct {
-            float f[kP2Win][kP2Win];  // the iterate, tile + 2-pixel halo (the final kernel: the transposition tile)
-            float g[kP2Dir][kP2Dir];  // the direction, tile + 1-pixel halo
-        };
-        SlotSums sums;                // the step's partials (the decision's first, before the window is stored)
-    };
+    float f[kP2Win][kP2Win];  // the iterate, tile + 2-pixel halo (the final kernel: the transposition tile)
+    float g[kP2Dir][kP2Dir];  // the direction, tile + 1-pixel halo
+    SlotSums sums;            // the decision's sums, then the step's partials (written as they are formed)
     DecShared dec;
     SelShared sel;
 };
@@ -581,7 +616,14 @@ __device__ __forceinline__ void p2_decide(const P2Decide& D, int nb, const DevSt
     }
     const double* tot;
     if constexpr (NT == kP2Threads) {
-        slot_sums(a, *L);
+        // only the first ceil(nb / 64) waves hold partials: the others' zeros
+        // are left out of the sums (adding them would not change a bit)
+        const int nw = (nb < NT ? nb + 63 : NT) / 64;
+        if ((int)threadIdx.x < 64 * nw) {
+#pragma unroll
+            for (int c = 0; c < kP2Slots; ++c) L->v[c][threadIdx.x] = a[c];
+        }
+        slot_sums_stored(*L, nw);
         tot = L->tot;
     } else {
         block_sums<NT, kP2Slots>(a, S.R);
@@ -650,14 +692,14 @@ __device__ __forceinline__ void p2_decide(const P2Decide& D, int nb, const DevSt
 // The direction g at window position (li, lj) of the 1-pixel-halo window
 // (pixel (i0 - 1 + li, j0 - 1 + lj)), from the iterate window in LDS: Eq. A3's
 // magnitudes of the pixel's four half-edges, Eq. 5's weights (or the given
-// ones), the A2 fluxes and lambda (f - v).
+// ones), the A2 fluxes and lambda (f - v); vpix is v at the pixel.
 struct DirOut {
     float g, wR, wL, wU, wD, tR, tL, tU, tD, dv;
 };
 
 __device__ __forceinline__ DirOut p2_direction_at(const P2Shared& S, int li, int lj, int gi, int gj, int nx,
-                                                  const float* __restrict__ v, float lambda, float eps2,
-                                                  float inv_s2, const float* wx_in, const float* wy_in)
+                                                  float vpix, float lambda, float eps2, float inv_s2,
+                                                  const float* wx_in, const float* wy_in)
 {
     Nbhd N;
 #pragma unroll
@@ -679,7 +721,7 @@ __device__ __forceinline__ DirOut p2_direction_at(const P2Shared& S, int li, int
     const float FL = o.wL * (c - N.n[0][1]) * hw_rcp(o.tL);
     const float FU = o.wU * (N.n[1][2] - c) * hw_rcp(o.tU);
     const float FD = o.wD * (c - N.n[1][0]) * hw_rcp(o.tD);
-    o.dv = c - v[(size_t)gj * nx + gi];
+    o.dv = c - vpix;
     o.g = lambda * o.dv - (FR - FL) - (FU - FD);
     return o;
 }
@@ -702,7 +744,25 @@ __device__ __forceinline__ void p2_step_block(const float* __restrict__ f, const
     const int i0 = bx * kP2T, j0 = by * kP2T;
     constexpr int kWin = kP2Win * kP2Win;
     constexpr int kWinPer = (kWin + kP2Threads - 1) / kP2Threads;
-    // the window's loads first, so they overlap sigma's digit and the decision
+    const int ti = tid & (kP2T - 1), tj = tid / kP2T;
+    const int i = i0 + ti, j = j0 + tj;
+    const bool own = i < nx && j < ny;
+    // this thread's position on the direction window's halo ring (tid < kP2Halo)
+    int li = 0, lj = 0;
+    if (tid < kP2Dir) {
+        li = tid;
+    } else if (tid < 2 * kP2Dir) {
+        li = tid - kP2Dir;
+        lj = kP2Dir - 1;
+    } else if (tid < 2 * kP2Dir + kP2T) {
+        lj = tid - 2 * kP2Dir + 1;
+    } else {
+        li = kP2Dir - 1;
+        lj = tid - 2 * kP2Dir - kP2T + 1;
+    }
+    const int hi = i0 - 1 + li, hj = j0 - 1 + lj;
+    const bool ring = tid < kP2Halo && (unsigned)hi < (unsigned)nx && (unsigned)hj < (unsigned)ny;
+    // the window's and v's loads first, so they overlap sigma's digit and the decision
     float fv[kWinPer], gv[kWinPer];
 #pragma unroll
     for (int u = 0; u < kWinPer; ++u) {
@@ -751,52 +811,33 @@ __device__ __forceinline__ void p2_step_block(const float* __restrict__ f, const
         if (idx < kWin) S.f[idx / kP2Win][idx % kP2Win] = g_prev ? stepped(fv[u], gv[u], kp, tp) : fv[u];
     }
     __syncthreads();
-    const int ti = tid & (kP2T - 1), tj = tid / kP2T;
-    const int i = i0 + ti, j = j0 + tj;
-    const bool own = i < nx && j < ny;
     // the own pixel's direction (its weights and terms kept for the trials)
     DirOut o{};
     if (own) {
-        o = p2_direction_at(S, ti + 1, tj + 1, i, j, nx, v, lambda, eps2, inv_s2, wx_in, wy_in);
+        o = p2_direction_at(S, ti + 1, tj + 1, i, j, nx, v[(size_t)j * nx + i], lambda, eps2, inv_s2, wx_in, wy_in);
         const size_t id = (size_t)j * nx + i;
         g[id] = o.g;
         if (g_prev) f_out[id] = S.f[tj + 2][ti + 2];
     }
     S.g[tj + 1][ti + 1] = own ? o.g : 0.0f;
     // the halo ring of the direction window
-    if (tid < kP2Halo) {
-        int li, lj;
-        if (tid < kP2Dir) {
-            li = tid;
-            lj = 0;
-        } else if (tid < 2 * kP2Dir) {
-            li = tid - kP2Dir;
-            lj = kP2Dir - 1;
-        } else if (tid < 2 * kP2Dir + kP2T) {
-            li = 0;
-            lj = tid - 2 * kP2Dir + 1;
-        } else {
-            li = kP2Dir - 1;
-            lj = tid - 2 * kP2Dir - kP2T + 1;
-        }
-        const int gi = i0 - 1 + li, gj = j0 - 1 + lj;
-        float gh = 0.0f;
-        if ((unsigned)gi < (unsigned)nx && (unsigned)gj < (unsigned)ny)
-            gh = p2_direction_at(S, li, lj, gi, gj, nx, v, lambda, eps2, inv_s2, wx_in, wy_in).g;
-        S.g[lj][li] = gh;
-    }
+    if (tid < kP2Halo)
+        S.g[lj][li] = ring ? p2_direction_at(S, li, lj, hi, hj, nx, v[(size_t)hj * nx + hi], lambda, eps2, inv_s2, wx_in, wy_in).g
+                           : 0.0f;
     __syncthreads();
     // this step's partials: Q(f_s), ||g_s||^2 and the trial energies, the
-    // trials as candidate_energies with the weights frozen at f_s
-    double val[kP2Slots];
+    // trials as candidate_energies with the weights frozen at f_s, each
+    // stored to LDS as it is formed
+    double (*val)[kP2Threads] = S.sums.v;
+    if (!own) {
 #pragma unroll
-    for (int c = 0; c < kP2Slots; ++c) val[c] = 0.0;
-    if (own) {
+        for (int c = 0; c < kP2Slots; ++c) val[c][tid] = 0.0;
+    } else {
         float e = o.wR * o.tR + o.wU * o.tU;
         if (i == 0) e += o.wL * o.tL;
         if (j == 0) e += o.wD * o.tD;
-        val[0] = (double)e + 0.5 * (double)lambda * (double)o.dv * (double)o.dv;
-        val[1] = (double)o.g * (double)o.g;
+        val[0][tid] = (double)e + 0.5 * (double)lambda * (double)o.dv * (double)o.dv;
+        val[1][tid] = (double)o.g * (double)o.g;
         Nbhd F, G;
 #pragma unroll
         for (int a = 0; a < 3; ++a)
@@ -805,25 +846,16 @@ __device__ __forceinline__ void p2_step_block(const float* __restrict__ f, const
                 F.n[a][bb] = S.f[tj + 1 + bb][ti + 1 + a];
                 G.n[a][bb] = S.g[tj + bb][ti + a];
             }
-        const float wL = i == 0 ? o.wL : 0.0f, wD = j == 0 ? o.wD : 0.0f;
-        const float vpix = v[(size_t)j * nx + i];
+        const EdgeSet EF = edge_set(F, i == 0, j == 0), EG = edge_set(G, i == 0, j == 0);
+        const float g11 = G.n[1][1];
         float t = t0;
 #pragma unroll
         for (int c = 0; c < kArmijoFirst; ++c) {
-            Nbhd H;
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int bb = 0; bb < 3; ++bb) H.n[a][bb] = fmaf(-t, G.n[a][bb], F.n[a][bb]);
-            float sm = o.wR * tv_right(H, eps2) + o.wU * tv_up(H, eps2);
-            if (i == 0) sm += wL * tv_left(H, eps2);
-            if (j == 0) sm += wD * tv_down(H, eps2);
-            const float d = H.n[1][1] - vpix;
-            val[2 + c] = (double)sm + 0.5 * (double)lambda * (double)d * (double)d;
+            val[2 + c][tid] = trial_energy(EF, EG, o.wR, o.wU, o.wL, o.wD, i == 0, j == 0, o.dv, g11, t, lambda, eps2);
             t *= shrink;
         }
     }
-    slot_sums(val, S.sums);
+    slot_sums_stored(S.sums);
     if (tid < kP2Slots) part[(size_t)tid * nb + b] = S.sums.tot[tid];
 }
 
