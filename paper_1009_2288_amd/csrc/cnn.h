@@ -41,11 +41,22 @@ struct ConvArgs {
     // x32, if set: the input as dense fp32 (channel stride cin); it is rounded
     // to bf16, the values also written to x (dense, the layer's stored input)
     const float* x32 = nullptr;
+    // head_y32, if set (3x3 layers that conv3_head_fits): also the 1x1
+    // convolution of the layer's bf16 output with head_wt (packed
+    // [head_n][head_kpad]) plus head_bias, written to head_y32 as dense fp32
+    // [pixel][head_n] (head_n <= 4), summed in the thin pointwise kernel's order
+    const uint16_t* head_wt = nullptr;
+    const float* head_bias = nullptr;
+    float* head_y32 = nullptr;
+    int head_n = 0, head_kpad = 0;
 };
 
 inline int pad64(int n) { return (n + 63) / 64 * 64; }
 
 hipError_t launch_conv(const ConvArgs& a, int mode, hipStream_t s);
+// whether a 3x3 layer's launch can also form a thin 1x1 head of head_n
+// outputs from its output (one block holds every channel of its pixels)
+bool conv3_head_fits(const ConvArgs& a, int head_n);
 int wgrad_chunks(const ConvArgs& a, int chunk_px);
 // pixels per weight-gradient chunk for a layer with npix GEMM pixels and an
 // n_pad x kw partial tile grid (also sizes the partial buffers)

@@ -401,15 +401,18 @@ constexpr int kPatchW = 34;             // 32 columns + halo
 constexpr int kPatchPS = 48;            // bf16 per patch pixel (32 channels + 32 B)
 constexpr int kTapLd = 9 * 32 + 16;     // bf16 per weight row (9 taps x 32 channels + 32 B)
 constexpr int kTileBlocksPerCu = 2;     // persistent blocks per CU
+constexpr int kThin = 4;                // the thin side of a 1x1 layer done on the vector ALUs (the head)
 
 // STAGED: the epilogue goes through LDS (16-byte stores, masks, pooling);
 // otherwise each lane stores its 4 channels directly (no mask or pooling).
 // KC: input channels staged per round trip (32, or 64 for layers with many
-// chunks and few tiles: half the round trips per tile)
-template <int TH, int NT, bool STAGED, int KC = 32>
+// chunks and few tiles: half the round trips per tile).  HEAD (STAGED, one
+// 32-channel block): the thin 1x1 head of a.head_* from the staged outputs.
+template <int TH, int NT, bool STAGED, int KC = 32, bool HEAD = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv3_tile(ConvArgs a, int ntiles)
 {
     constexpr int BN = 16 * NT;       // output channels per block
+    static_assert(!HEAD || STAGED, "the head reads the staged outputs");
     static_assert(TH == 8 || TH == 4, "8- or 4-row tiles");
     constexpr int RT = TH / 2;        // 16-pixel row tiles per wave
     constexpr int P8 = KC / 8;                                           // 16-byte pieces per pixel
@@ -423,6 +426,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     constexpr int PATCH = (TH + 2) * kPatchW * PPS, OLD = BN + 8;
     constexpr int STAGE = !STAGED || PATCH > TH * 32 * OLD ? PATCH : TH * 32 * OLD;
     __shared__ __attribute__((aligned(16))) uint16_t lds[STAGE + BN * TLD];
+    __shared__ float hwt[HEAD ? kThin * BN + kThin : 1];  // the head's weights [n][k], then its bias
     uint16_t* patch = lds;
     uint16_t* wts = lds + STAGE;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -504,6 +508,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     bool w_staged = false;
     fetch_patch(t, 0);
     fetch_w(0);
+    if constexpr (HEAD) {
+        // behind the first item's loads; read after the main loop's first barrier
+        for (int i = threadIdx.x; i < kThin * BN; i += 256) {
+            const int n = i / BN, k = i - n * BN;
+            hwt[i] = n < a.head_n && k < a.cout ? bf2f(a.head_wt[(size_t)n * a.head_kpad + k]) : 0.0f;
+        }
+        if (threadIdx.x < kThin)
+            hwt[kThin * BN + threadIdx.x] = (int)threadIdx.x < a.head_n && a.head_bias ? a.head_bias[threadIdx.x] : 0.0f;
+    }
     while (true) {
         __syncthreads();  // the previous item is consumed
 #pragma unroll
@@ -635,6 +648,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                                               n) = o.u;
                 }
             }
+            if constexpr (HEAD) {
+                // the head, one thread per pixel, in k_point_thin's order:
+                // partial sum q over channels 8 q + 32 k + j (k, then j
+                // ascending), then (s0 + s1) + (s2 + s3), then the bias; one
+                // output at a time, so that few registers are added to those
+                // the next tile's prefetch holds
+                for (int px = threadIdx.x; px < TH * 32; px += 256) {
+                    const int y = y0 + (px >> 5), x = x0 + (px & 31);
+                    if (y >= a.h || x >= a.w) continue;
+                    Frag xr[BN / 8];
+#pragma unroll
+                    for (int i = 0; i < BN / 8; ++i) xr[i].u = *reinterpret_cast<const uint4*>(lds + px * OLD + 8 * i);
+                    float* yo = a.head_y32 + (((size_t)img * a.h + y) * a.w + x) * a.head_n;
+#pragma unroll 1
+                    for (int n = 0; n < a.head_n; ++n) {
+                        const float* wn = hwt + n * BN;
+                        float sq[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            sq[q] = 0.0f;
+#pragma unroll
+                            for (int i = q; i < BN / 8; i += 4)
+#pragma unroll
+                                for (int j = 0; j < 8; ++j) sq[q] += bf2f(xr[i].h[j]) * wn[8 * i + j];
+                        }
+                        yo[n] = ((sq[0] + sq[1]) + (sq[2] + sq[3])) + hwt[kThin * BN + n];
+                    }
+                }
+            }
         } else if (!STAGED && c == nch - 1) {
             // direct epilogue: accumulator r of lane l, row tile i, column
             // tile j is the pixel at local row row_of(i), column
@@ -680,8 +722,8 @@ __global__ __launch_bounds__(256) void k_conv3_c1(ConvArgs a, int seg_per_block)
     __shared__ __attribute__((aligned(16))) float bs[kC1MaxOut];
     __shared__ float rows[3][256 + 2];
     // block: segments blockIdx.y seg_per_block .. + seg_per_block - 1 (pb
-    // pixels each) of image row blockIdx.x (img h + y), one thread per
-    // (pixel, 8 output channels)
+    // pixels each, seg_per_block pb <= 256) of image row blockIdx.x
+    // (img h + y), one thread per (pixel, 8 output channels)
     const int c8n = a.cout / 8, pb = 256 / c8n;
     const int row = blockIdx.x, img = row / a.h, y = row - img * a.h;
     for (int i = threadIdx.x; i < a.cout * 9; i += 256) {
@@ -690,44 +732,39 @@ __global__ __launch_bounds__(256) void k_conv3_c1(ConvArgs a, int seg_per_block)
     }
     for (int i = threadIdx.x; i < a.cout; i += 256) bs[i] = a.bias ? a.bias[i] : 0.0f;
     const int lp = threadIdx.x / c8n, n0 = (threadIdx.x - lp * c8n) * 8;
-    // the staged values of this thread: element i = t + 256 k (k < 4) of the
-    // 3 x (pb + 2) <= 774 rows' values, row i / (pb + 2), column i % (pb + 2)
-    int sr[4], sc[4];
+    // the block's columns [x_beg, x_end) (at most 256) and one on each side
+    // are staged once: element i = t + 256 k (k < 4) of the 3 x (W + 2) <= 774
+    // values, row i / (W + 2), column i % (W + 2)
+    const uint16_t* xin = a.x + (size_t)img * a.h * a.w * a.x_cs + a.x_co;
+    const int x_beg = blockIdx.y * seg_per_block * pb, x_end = min(a.w, x_beg + seg_per_block * pb);
+    const int W2 = x_end - x_beg + 2;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int i = threadIdx.x + 256 * k;
-        sr[k] = i < 3 * (pb + 2) ? i / (pb + 2) : -1;
-        sc[k] = i - (i / (pb + 2)) * (pb + 2);
-    }
-    const uint16_t* xin = a.x + (size_t)img * a.h * a.w * a.x_cs + a.x_co;
-    const int x_beg = blockIdx.y * seg_per_block * pb, x_end = min(a.w, x_beg + seg_per_block * pb);
-    for (int x0 = x_beg; x0 < x_end; x0 += pb) {
-        __syncthreads();  // the previous segment's rows are consumed (and the weights staged)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (sr[k] < 0) continue;
-            const int ys = y + sr[k] - 1, xs = x0 + sc[k] - 1;
-            const bool in = (unsigned)ys < (unsigned)a.h && (unsigned)xs < (unsigned)a.w;
-            float v = 0.0f;
-            if (in && a.x32) {
-                // fp32 input: round to bf16 here; the centre row's own
-                // pixels are also stored (the layer's bf16 input)
-                const uint16_t hv = f2bf(a.x32[((size_t)img * a.h + ys) * a.w + xs]);
-                v = bf2f(hv);
-                if (sr[k] == 1 && sc[k] >= 1 && sc[k] <= pb)
-                    const_cast<uint16_t*>(a.x)[((size_t)img * a.h + ys) * a.w + xs] = hv;
-            } else if (in) {
-                v = bf2f(xin[((size_t)ys * a.w + xs) * a.x_cs]);
-            }
-            rows[sr[k]][sc[k]] = v;
+        if (i >= 3 * W2) continue;
+        const int sr = i / W2, sc = i - sr * W2;
+        const int ys = y + sr - 1, xs = x_beg + sc - 1;
+        const bool in = (unsigned)ys < (unsigned)a.h && (unsigned)xs < (unsigned)a.w;
+        float v = 0.0f;
+        if (in && a.x32) {
+            // fp32 input: round to bf16 here; the centre row's own pixels
+            // are also stored (the layer's bf16 input)
+            const uint16_t hv = f2bf(a.x32[((size_t)img * a.h + ys) * a.w + xs]);
+            v = bf2f(hv);
+            if (sr == 1 && sc >= 1 && sc < W2 - 1) const_cast<uint16_t*>(a.x)[((size_t)img * a.h + ys) * a.w + xs] = hv;
+        } else if (in) {
+            v = bf2f(xin[((size_t)ys * a.w + xs) * a.x_cs]);
         }
-        __syncthreads();
-        const int x = x0 + lp;
-        if (lp >= pb || x >= a.w) continue;
+        rows[sr][sc] = v;
+    }
+    __syncthreads();  // the rows and the weights are staged
+    for (int x0 = x_beg; x0 < x_end; x0 += pb) {
+        const int x = x0 + lp, lx = x - x_beg;  // rows' column lx + 1 is pixel x
+        if (lp >= pb || x >= x_end) continue;
         float acc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
-            const float v = rows[t / 3][lp + t % 3];
+            const float v = rows[t / 3][lx + t % 3];
             const float4 w0 = *reinterpret_cast<const float4*>(wt + t * a.cout + n0);
             const float4 w1 = *reinterpret_cast<const float4*>(wt + t * a.cout + n0 + 4);
             acc[0] += v * w0.x;
@@ -766,8 +803,7 @@ __global__ __launch_bounds__(256) void k_conv3_c1(ConvArgs a, int seg_per_block)
 // ALUs form the outputs with fp32 products of the bf16 operands (exact) and
 // fp32 sums, with lanes laid over channels so that each wave reads or
 // writes contiguous memory.
-constexpr int kThin = 4;        // the thin side
-constexpr int kThinWide = 256;  // the other side
+constexpr int kThinWide = 256;  // the other side (kThin: the thin side)
 
 __global__ __launch_bounds__(256) void k_point_thin(ConvArgs a)
 {
@@ -946,6 +982,39 @@ static bool up2x2_fits(const ConvArgs& a, int mode)
            a.x_co % 8 == 0 && a.y_cs % 8 == 0 && a.y_co % 8 == 0;
 }
 
+// The LDS-tile kernel's shape for a layer (false where it does not apply:
+// C_in a multiple of 32, bf16 output, every slice 16-byte aligned, byte
+// offsets within 31 bits): the largest tile that still gives enough blocks
+// (8 rows and 64 channels preferred; smaller layers fall back to 4 rows, then
+// to 32-channel tiles; 32 output channels or fewer: a 32-wide channel tile).
+static bool conv3_tile_shape(const ConvArgs& a, int mode, int& th, int& tn)
+{
+    if (!(mode == kConv3 && a.cin % 32 == 0 && a.x_cs % 8 == 0 && a.x_co % 8 == 0 && !a.y32 && a.cout % 8 == 0 &&
+          a.y_cs % 8 == 0 && a.y_co % 8 == 0 && (!a.mask || (a.m_cs % 8 == 0 && a.m_co % 8 == 0)) &&
+          (!a.pool || a.p_cs % 8 == 0) && (size_t)a.n_img * a.h * a.w * a.x_cs * 2 < (size_t(1) << 31) &&
+          (size_t)a.n_pad * a.k_pad * 2 < (size_t(1) << 31)))
+        return false;
+    const int nt = a.cout <= 32 ? 2 : 4;
+    const long long t8 = (long long)a.n_img * ((a.h + 7) / 8) * ((a.w + 31) / 32);
+    const long long t4 = (long long)a.n_img * ((a.h + 3) / 4) * ((a.w + 31) / 32);
+    const long long c4 = (a.cout + 63) / 64, c2 = (a.cout + 31) / 32;
+    if (t8 * (nt == 4 ? c4 : c2) >= 512) th = 8, tn = nt;
+    else if (t4 * (nt == 4 ? c4 : c2) >= 512) th = 4, tn = nt;
+    else if (t4 * c2 >= 512) th = 4, tn = 2;  // more blocks for the small layers
+    else if (t4 * (nt == 4 ? c4 : c2) >= 256) th = 4, tn = nt;
+    else th = 4, tn = 2;  // small layers: the most blocks
+    return true;
+}
+
+bool conv3_head_fits(const ConvArgs& a, int head_n)
+{
+    ConvArgs b = a;
+    b.head_y32 = nullptr;
+    int th = 0, tn = 0;
+    return head_n >= 1 && head_n <= kThin && !a.mask && !a.x32 && conv3_tile_shape(b, kConv3, th, tn) && th == 8 &&
+           tn == 2 && a.cout <= 32;
+}
+
 static hipError_t launch_conv_impl(const ConvArgs& a, int mode, hipStream_t s, bool* pooled)
 {
     *pooled = false;
@@ -955,7 +1024,8 @@ static hipError_t launch_conv_impl(const ConvArgs& a, int mode, hipStream_t s, b
         // row segments per block: the per-block set-up spread over several
         // segments, while keeping about 2048 blocks
         const int pb = 256 / (a.cout / 8), nseg = (a.w + pb - 1) / pb;
-        const int spb = std::max(1, std::min(nseg, a.n_img * a.h * nseg / 2048));
+        // (a block stages at most 256 columns of its row)
+        const int spb = std::max(1, std::min({nseg, a.n_img * a.h * nseg / 2048, 256 / pb}));
         hipLaunchKernelGGL(k_conv3_c1, dim3((unsigned)(a.n_img * a.h), (unsigned)((nseg + spb - 1) / spb)), dim3(256),
                            0, s, a, spb);
         return hipGetLastError();
@@ -973,27 +1043,13 @@ static hipError_t launch_conv_impl(const ConvArgs& a, int mode, hipStream_t s, b
         hipLaunchKernelGGL(k_point_thin, dim3(g), dim3(256), 0, s, a);
         return hipGetLastError();
     }
-    // 32 output channels or fewer: a 32-wide channel tile (no padded half)
     const int nt = a.cout <= 32 ? 2 : 4;
-    // the LDS-tile kernel: C_in a multiple of 32, bf16 output, every slice
-    // 16-byte aligned, byte offsets within 31 bits
-    if (mode == kConv3 && a.cin % 32 == 0 && a.x_cs % 8 == 0 && a.x_co % 8 == 0 && !a.y32 && a.cout % 8 == 0 &&
-        a.y_cs % 8 == 0 && a.y_co % 8 == 0 && (!a.mask || (a.m_cs % 8 == 0 && a.m_co % 8 == 0)) &&
-        (!a.pool || a.p_cs % 8 == 0) && (size_t)a.n_img * a.h * a.w * a.x_cs * 2 < (size_t(1) << 31) &&
-        (size_t)a.n_pad * a.k_pad * 2 < (size_t(1) << 31)) {
-        // tile shape: the largest that still gives enough blocks (8 rows and
-        // 64 channels preferred; smaller layers fall back to 4 rows, then to
-        // 32-channel tiles)
+    int th = 0, tn = 0;
+    if (conv3_tile_shape(a, mode, th, tn)) {
         const long long t8 = (long long)a.n_img * ((a.h + 7) / 8) * ((a.w + 31) / 32);
         const long long t4 = (long long)a.n_img * ((a.h + 3) / 4) * ((a.w + 31) / 32);
         const long long c4 = (a.cout + 63) / 64, c2 = (a.cout + 31) / 32;
-        int th = 0, tn = 0;
-        if (t8 * (nt == 4 ? c4 : c2) >= 512) th = 8, tn = nt;
-        else if (t4 * (nt == 4 ? c4 : c2) >= 512) th = 4, tn = nt;
-        else if (t4 * c2 >= 512) th = 4, tn = 2;  // more blocks for the small layers
-        else if (t4 * (nt == 4 ? c4 : c2) >= 256) th = 4, tn = nt;
-        else th = 4, tn = 2;  // small layers: the most blocks
-        if (th) {
+        {
             // persistent blocks: about kTileBlocksPerCu per CU over all channel blocks
             const long long nt_ = th == 8 ? t8 : t4, cbn = tn == 4 ? c4 : c2;
             const long long want = std::max(8LL, (long long)kTileBlocksPerCu * 256 / cbn / 8 * 8);
@@ -1004,6 +1060,10 @@ static hipError_t launch_conv_impl(const ConvArgs& a, int mode, hipStream_t s, b
             // the kernel pools in its epilogue (even image sides)
             *pooled = a.pool && a.h % 2 == 0 && a.w % 2 == 0;
             if (!*pooled) b.pool = nullptr;
+            if (a.head_y32) {  // conv3_head_fits: 8 x 32 tiles, one channel block
+                hipLaunchKernelGGL((k_conv3_tile<8, 2, true, 32, true>), g, dim3(256), 0, s, b, ntl);
+                return hipGetLastError();
+            }
             // measured on MI355X: the LDS-staged epilogue pays off except for
             // 8 x 64 tiles without a mask or pooling (many input chunks per
             // tile, and the staging adds registers there)
@@ -1046,6 +1106,8 @@ hipError_t launch_conv(const ConvArgs& a, int mode, hipStream_t s)
 {
     bool pooled = false;
     hipError_t e = hipSuccess;
+    if (a.head_y32 && (mode != kConv3 || !conv3_head_fits(a, a.head_n) || !a.head_wt || a.head_kpad < a.cout))
+        return hipErrorInvalidValue;
     if (a.x32 && !conv3_c1_takes_fp32(a, mode)) {  // the bf16 input first, as a pass of its own
         if (a.x_cs != a.cin || a.x_co != 0) return hipErrorInvalidValue;
         ConvArgs b = a;

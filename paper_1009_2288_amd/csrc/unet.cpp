@@ -100,8 +100,14 @@ static hipError_t forward(eptv_unet_s& u, const float* x, int n, float* y, hipSt
 {
     hipError_t e;
     const int L = u.levels;
+    // the head (1x1, c_out outputs in fp32) is formed by the last decoder
+    // layer's epilogue where its launch allows (one block holds all of a
+    // pixel's channels), else by a launch of its own
+    const int hl = layer_index(u, 'h', 0, 0);
+    bool head_fused = false;
     auto conv = [&](int li, int mode, const uint16_t* xp, int xcs, int xco, int h, int w, uint16_t* yp, int ycs,
-                    int yco, float* y32, int relu, const Tensor* pool = nullptr, const float* x32 = nullptr) {
+                    int yco, float* y32, int relu, const Tensor* pool = nullptr, const float* x32 = nullptr,
+                    bool try_head = false) {
         const Layer& Ly = u.layers[li];
         ConvArgs a = conv_args(u, Ly, n, h, w, false);
         a.x = xp;
@@ -117,6 +123,15 @@ static hipError_t forward(eptv_unet_s& u, const float* x, int n, float* y, hipSt
             a.p_cs = pool->c;
         }
         a.x32 = x32;
+        if (try_head && conv3_head_fits(a, u.c_out)) {
+            const ConvArgs hd = conv_args(u, u.layers[hl], n, h, w, false);
+            a.head_wt = hd.wt;
+            a.head_bias = hd.bias;
+            a.head_kpad = hd.k_pad;
+            a.head_n = u.c_out;
+            a.head_y32 = y;
+            head_fused = true;
+        }
         return launch_conv(a, mode, s);
     };
     for (int l = 0; l < L; ++l) {
@@ -145,12 +160,13 @@ static hipError_t forward(eptv_unet_s& u, const float* x, int n, float* y, hipSt
         if ((e = conv(layer_index(u, 'd', l, 'a'), kConv3, u.cat[l].p, 2 * C, 0, h, w, u.da[l].p, C, 0, nullptr, 1)) !=
             hipSuccess)
             return e;
-        if ((e = conv(layer_index(u, 'd', l, 'b'), kConv3, u.da[l].p, C, 0, h, w, u.db[l].p, C, 0, nullptr, 1)) !=
-            hipSuccess)
+        if ((e = conv(layer_index(u, 'd', l, 'b'), kConv3, u.da[l].p, C, 0, h, w, u.db[l].p, C, 0, nullptr, 1,
+                      nullptr, nullptr, l == 0)) != hipSuccess)
             return e;
     }
+    if (head_fused) return hipSuccess;
     const Tensor& last = L > 1 ? u.db[0] : u.bout;
-    return conv(layer_index(u, 'h', 0, 0), kPoint, last.p, last.c, 0, u.h, u.w, nullptr, u.c_out, 0, y, 0);
+    return conv(hl, kPoint, last.p, last.c, 0, u.h, u.w, nullptr, u.c_out, 0, y, 0);
 }
 
 // weight and bias gradients of layer li from its input x (slice) and its
