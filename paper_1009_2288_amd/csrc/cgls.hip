@@ -213,53 +213,40 @@ hipError_t launch_rmse_part(const Plan& p, const float* f, const float* ref, dou
     return hipGetLastError();
 }
 
-__device__ __forceinline__ void iter_end_block(DevState* st, const double* part_res, int n_res, int with_resid,
-                                               const double* part_rmse, int n_rmse, int with_rmse, double npix,
-                                               float* st_sigma, int32_t* st_steps, double* st_resid, double* st_rmse,
-                                               int M, double* st_gamma, double* st_delta, uint32_t* hist,
-                                               float sigma_fixed, double* lds)
+IterEnd iter_end_args(const Plan& p, DevState* st, const double* part_res, int with_resid, const double* part_rmse,
+                      int n_rmse, int with_rmse, float* st_sigma, int32_t* st_steps, double* st_resid, double* st_rmse,
+                      int M, double* st_gamma, double* st_delta, uint32_t* hist, float sigma_fixed)
 {
-    const double res = with_resid ? block_sum_partials<256>(part_res, n_res, 1, lds) : 0.0;
-    const double e = with_rmse ? block_sum_partials<256>(part_rmse, n_rmse, 1, lds) : 0.0;
-    const int it = st->iter;
-    // the CGLS scalars of the steps reached (gamma_m is recorded for every
-    // step that the previous ones left active, including one it stopped)
-    for (int m = threadIdx.x; m < M; m += blockDim.x) {
-        const int reached = m == 0 || st->active[m - 1];
-        if (st_gamma) st_gamma[(size_t)it * M + m] = reached ? st->gamma[m] : 0.0;
-        if (st_delta) st_delta[(size_t)it * M + m] = reached ? st->delta[m] : 0.0;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        if (st_sigma) st_sigma[it] = st->sigma;
-        if (st_steps) st_steps[it] = st->cg_steps;
-        if (st_resid) st_resid[it] = res;
-        if (with_rmse && st_rmse) st_rmse[it] = sqrt(e / npix);
-        st->iter = it + 1;
-    }
-    __syncthreads();
-    reset_iteration_state(st, hist, sigma_fixed);
+    IterEnd e;
+    e.st = st;
+    e.part_res = part_res;
+    e.n_res = sino_blocks(p);
+    e.with_resid = with_resid;
+    e.part_rmse = part_rmse;
+    e.n_rmse = n_rmse;
+    e.with_rmse = with_rmse;
+    e.npix = (double)p.nx * p.ny;
+    e.st_sigma = st_sigma;
+    e.st_steps = st_steps;
+    e.st_resid = st_resid;
+    e.st_rmse = st_rmse;
+    e.M = M;
+    e.st_gamma = st_gamma;
+    e.st_delta = st_delta;
+    e.hist = hist;
+    e.sigma_fixed = sigma_fixed;
+    return e;
 }
 
-__global__ __launch_bounds__(256) void k_iter_end(DevState* st, const double* part_res, int n_res, int with_resid,
-                                                  const double* part_rmse, int n_rmse, int with_rmse, double npix,
-                                                  float* st_sigma, int32_t* st_steps, double* st_resid,
-                                                  double* st_rmse, int M, double* st_gamma, double* st_delta,
-                                                  uint32_t* hist, float sigma_fixed)
+__global__ __launch_bounds__(256) void k_iter_end(IterEnd e)
 {
     __shared__ double lds[4];
-    iter_end_block(st, part_res, n_res, with_resid, part_rmse, n_rmse, with_rmse, npix, st_sigma, st_steps, st_resid,
-                   st_rmse, M, st_gamma, st_delta, hist, sigma_fixed, lds);
+    iter_end_run<256>(e, lds);
 }
 
-hipError_t launch_iter_end(const Plan& p, DevState* st, const double* part_res, int with_resid,
-                           const double* part_rmse, int n_rmse, int with_rmse, float* st_sigma, int32_t* st_steps,
-                           double* st_resid, double* st_rmse, int M, double* st_gamma, double* st_delta,
-                           uint32_t* hist, float sigma_fixed, hipStream_t s)
+hipError_t launch_iter_end(const IterEnd& e, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_iter_end, dim3(1), dim3(256), 0, s, st, part_res, sino_blocks(p), with_resid, part_rmse,
-                       n_rmse, with_rmse, (double)p.nx * p.ny, st_sigma, st_steps, st_resid, st_rmse, M, st_gamma,
-                       st_delta, hist, sigma_fixed);
+    hipLaunchKernelGGL(k_iter_end, dim3(1), dim3(256), 0, s, e);
     return hipGetLastError();
 }
 
@@ -384,10 +371,25 @@ __global__ __launch_bounds__(256) void kb_iter_end(const SliceDev* __restrict__ 
 {
     __shared__ double lds[4];
     const SliceDev& d = sl[blockIdx.x];
-    const int rm = with_rmse && d.buf[kBufFRef] != nullptr;
-    iter_end_block(d.st, d.part[kPartRes], d.axpy_sino, with_resid, d.part[kPartRmse],
-                   rmse_tiles ? d.t32x * d.t32y : kRmseBlocks, rm, (double)d.nx * d.ny, d.st_sigma, d.st_steps,
-                   d.st_resid, d.st_rmse, d.cgls_iters, d.st_gamma, d.st_delta, d.hist, sigma_fixed, lds);
+    IterEnd e;
+    e.st = d.st;
+    e.part_res = d.part[kPartRes];
+    e.n_res = d.axpy_sino;
+    e.with_resid = with_resid;
+    e.part_rmse = d.part[kPartRmse];
+    e.n_rmse = rmse_tiles ? d.t32x * d.t32y : kRmseBlocks;
+    e.with_rmse = with_rmse && d.buf[kBufFRef] != nullptr;
+    e.npix = (double)d.nx * d.ny;
+    e.st_sigma = d.st_sigma;
+    e.st_steps = d.st_steps;
+    e.st_resid = d.st_resid;
+    e.st_rmse = d.st_rmse;
+    e.M = d.cgls_iters;
+    e.st_gamma = d.st_gamma;
+    e.st_delta = d.st_delta;
+    e.hist = d.hist;
+    e.sigma_fixed = sigma_fixed;
+    iter_end_run<256>(e, lds);
 }
 
 hipError_t blaunch_iter_end(const BatchDev& b, bool with_resid, bool with_rmse, bool rmse_tiles, float sigma_fixed,

@@ -106,6 +106,26 @@ struct DevState {
     int nonfinite;               // the input scan found NaN or inf
 };
 
+// What closes an outer iteration (records, counter, reset of the
+// per-iteration state); run by k_iter_end, or by one extra block of the next
+// iteration's first projector launch (st non-null there).
+struct IterEnd {
+    DevState* st = nullptr;
+    const double* part_res = nullptr;   // ||r||^2 partials (with_resid)
+    const double* part_rmse = nullptr;  // squared-error partials (with_rmse)
+    int n_res = 0, with_resid = 0, n_rmse = 0, with_rmse = 0;
+    double npix = 0.0;
+    float* st_sigma = nullptr;
+    int32_t* st_steps = nullptr;
+    double *st_resid = nullptr, *st_rmse = nullptr, *st_gamma = nullptr, *st_delta = nullptr;
+    int M = 0;  // CGLS steps per P1, whose gamma_m / delta_m go to st_gamma / st_delta ([K*M])
+    uint32_t* hist = nullptr;
+    float sigma_fixed = -1.0f;
+};
+struct Plan;
+IterEnd iter_end_args(const Plan& p, DevState* st, const double* part_res, int with_resid, const double* part_rmse,
+                      int n_rmse, int with_rmse, float* st_sigma, int32_t* st_steps, double* st_resid, double* st_rmse,
+                      int M, double* st_gamma, double* st_delta, uint32_t* hist, float sigma_fixed);
 // The float32 system matrix stored on the device (optional, see spmv.hip).
 // Every row and column is padded to a multiple of kStoredPad entries with its
 // last index and length 0.  The CSR copy (by ray) is split in chunks of
@@ -225,8 +245,10 @@ hipError_t launch_backproject(const Plan& p, const float* r, float alpha, float 
 hipError_t launch_backproject_interp(const Plan& p, const float* r, float alpha, float beta, const float* c,
                                      float* z, float* zT, double* partial, hipStream_t s);
 
+// fold: the previous outer iteration's closing, run by one extra block of
+// this launch (null: none)
 hipError_t launch_project_stored(const Plan& p, const float* x, const float* xT, float alpha, float beta, const float* c, float* q,
-                                 double* partial, hipStream_t s);
+                                 double* partial, hipStream_t s, const IterEnd* fold = nullptr);
 hipError_t launch_backproject_stored(const Plan& p, const float* r, float alpha, float beta, const float* c, float* z,
                                      float* zT, double* partial, hipStream_t s);
 
@@ -280,11 +302,7 @@ hipError_t launch_copy_clamp(const Plan& p, const float* src, float* dst, float*
 // bookkeeping
 hipError_t launch_rmse_part(const Plan& p, const float* f, const float* ref, double* part,
                             hipStream_t s);
-// M: CGLS steps per P1, whose gamma_m / delta_m go to st_gamma / st_delta ([K*M])
-hipError_t launch_iter_end(const Plan& p, DevState* st, const double* part_res, int with_resid,
-                           const double* part_rmse, int n_rmse, int with_rmse, float* st_sigma, int32_t* st_steps,
-                           double* st_resid, double* st_rmse, int M, double* st_gamma, double* st_delta,
-                           uint32_t* hist, float sigma_fixed, hipStream_t s);
+hipError_t launch_iter_end(const IterEnd& e, hipStream_t s);
 // st->nonfinite = whether a[0..n) holds NaN or inf (accumulate: or-ed into the
 // flag of an earlier scan); one block, no other state touched
 hipError_t launch_scan_finite(const float* a, size_t n, DevState* st, int accumulate, hipStream_t s);

@@ -164,7 +164,25 @@ static hipError_t enqueue_p2(const Plan& p, Workspace& W, const eptv_params& q, 
 }
 
 // One outer iteration of the EPTV algorithm (Sec. 2.2), entirely on `s`.
-static hipError_t enqueue_iteration(const Ctx& c, hipStream_t s)
+// What closes an outer iteration of c (records, counter, state reset).
+static IterEnd iteration_end(const Ctx& c)
+{
+    const Plan& p = c.p;
+    Workspace& W = c.W;
+    const int M = c.q.cgls_iters, T = c.q.tv_iters;
+    return iter_end_args(p, W.st, W.part_res, M > 0, W.part_rmse, T > 0 ? update_tiles(p) : kRmseBlocks,
+                         c.f_ref != nullptr, W.st_sigma, W.st_steps, W.st_resid, W.st_rmse, M, W.st_gamma,
+                         W.st_delta, W.hist, sigma_init(c.q));
+}
+
+// Whether an iteration can leave its close to the next iteration's first
+// kernel: only the stored projector takes it (one extra block of its launch).
+static bool can_defer_end(const Ctx& c) { return c.q.stored_matrix == 1; }
+
+// One outer iteration.  fold_prev: the previous iteration's close, still
+// pending, run by this iteration's first projector launch (can_defer_end);
+// defer_end: leave this iteration's close pending instead of launching it.
+static hipError_t enqueue_iteration(const Ctx& c, hipStream_t s, bool fold_prev = false, bool defer_end = false)
 {
     const Plan& p = c.p;
     Workspace& W = c.W;
@@ -172,7 +190,9 @@ static hipError_t enqueue_iteration(const Ctx& c, hipStream_t s)
     const int M = q.cgls_iters, T = q.tv_iters;
     const bool adaptive = q.sigma_fixed < 0;
     hipError_t e;
-    // (the per-iteration state was reset by the previous iteration's last kernel, or by the caller)
+    // (the per-iteration state was reset by the previous iteration's close,
+    // by this iteration's first kernel, or by the caller)
+    const IterEnd close = iteration_end(c);
     // Step 1: P1.  r = y - P f
     // P and P^T: on the fly, or from the stored matrix (the paper's two strategies,
     // Sec. 2.3), or P on the fly and P^T stored (stored_matrix = 2); both are the
@@ -187,7 +207,13 @@ static hipError_t enqueue_iteration(const Ctx& c, hipStream_t s)
         return q.stored_matrix ? launch_backproject_stored(p, rr, al, be, cc, zz, zzT, part, s)
                                : launch_backproject(p, rr, al, be, cc, zz, zzT, part, s);
     };
-    if ((e = proj(c.f, W.fT, -1.0f, 1.0f, c.y, W.r, nullptr)) != hipSuccess) return e;
+    if (fold_prev) {
+        if (!can_defer_end(c)) return hipErrorInvalidValue;
+        if ((e = launch_project_stored(p, c.f, W.fT, -1.0f, 1.0f, c.y, W.r, nullptr, s, &close)) != hipSuccess)
+            return e;
+    } else if ((e = proj(c.f, W.fT, -1.0f, 1.0f, c.y, W.r, nullptr)) != hipSuccess) {
+        return e;
+    }
     if (M > 0) {
         // s = P^T r (gamma_0 partials)
         if ((e = bproj(W.r, 1.0f, 0.0f, nullptr, W.s, W.sT, W.part_bp)) != hipSuccess) return e;
@@ -224,9 +250,8 @@ static hipError_t enqueue_iteration(const Ctx& c, hipStream_t s)
     if (c.f_ref && T == 0) {
         if ((e = launch_rmse_part(p, c.f, c.f_ref, W.part_rmse, s)) != hipSuccess) return e;
     }
-    return launch_iter_end(p, W.st, W.part_res, M > 0, W.part_rmse, T > 0 ? update_tiles(p) : kRmseBlocks,
-                           c.f_ref != nullptr, W.st_sigma, W.st_steps, W.st_resid, W.st_rmse, M, W.st_gamma,
-                           W.st_delta, W.hist, sigma_init(q), s);
+    if (defer_end) return can_defer_end(c) ? hipSuccess : hipErrorInvalidValue;
+    return launch_iter_end(close, s);
 }
 
 // Kernels are launched on the stream one by one unless EPTV_GRAPH is set to a
@@ -657,6 +682,7 @@ int reconstruct_impl(eptv_plan h, const eptv_params* q, const float* y, float* f
     Ctx cw{p, W, *q, y, f, f_ref, wx_in, wy_in};
     int done = 0;          // iterations run so far
     bool stopped = false;  // the RMSE reached stop_rmse at a check
+    bool pending = false;  // the last iteration's close is left to the next one's first kernel
     // after each iteration: every check_every-th one, read its RMSE record back
     auto check = [&]() -> int {
         ++done;
@@ -673,7 +699,11 @@ int reconstruct_impl(eptv_plan h, const eptv_params* q, const float* y, float* f
         if (count <= 0 || stopped) return EPTV_OK;
         if (noalloc || no_graph()) {
             for (int k = 0; k < count && !stopped; ++k) {
-                EPTV_HIP(enqueue_iteration(cc, s));
+                // the close of each iteration goes into the next one's first
+                // launch, except where its records are read right after
+                const bool defer = can_defer_end(cc) && !(stop && (done + 1) % every == 0);
+                EPTV_HIP(enqueue_iteration(cc, s, pending, defer));
+                pending = defer;
                 const int rc_ = check();
                 if (rc_ != EPTV_OK) return rc_;
             }
@@ -730,6 +760,7 @@ int reconstruct_impl(eptv_plan h, const eptv_params* q, const float* y, float* f
         if (rc == EPTV_OK) rc = run(c, K - (wx_in ? frozen : 0), p.gexec, p.gkey);
     }
     if (rc != EPTV_OK) return rc;
+    if (pending) EPTV_HIP(launch_iter_end(iteration_end(c), s));
     if (stats) {
         const size_t kk = (size_t)done;  // the records of the iterations that ran
         if (stats->iters_run) *stats->iters_run = done;

@@ -33,6 +33,7 @@
 // Sums are per lane then a fixed lane pattern: deterministic.
 #include "eptv_internal.h"
 #include "reduce.h"
+#include "state.h"
 
 namespace eptv {
 
@@ -167,15 +168,21 @@ struct __attribute__((aligned(4))) Slot3 {
 
 // P from the compact encoding: per chunk of n entries, n/2 12-byte slots then
 // the base word; a lane takes one slot (entries l and n/2 + l).
+// With fold.st set, block nblk (one past the projector's blocks) closes the
+// previous outer iteration instead (see IterEnd).
 __global__ __launch_bounds__(1024) void k_csr_compact(const int* __restrict__ wordptr, const int* __restrict__ words,
                                                       const float* __restrict__ x, const float* __restrict__ xT,
                                                       int nrows, float alpha, float beta, const float* c, float* q,
-                                                      double* partial)
+                                                      double* partial, IterEnd fold, int nblk)
 {
     __shared__ double lds[16];
+    if (fold.st && (int)blockIdx.x == nblk) {
+        iter_end_run<1024>(fold, lds);
+        return;
+    }
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     double s2 = 0.0;
-    for (int row = blockIdx.x * 16 + w; row < nrows; row += gridDim.x * 16) {
+    for (int row = blockIdx.x * 16 + w; row < nrows; row += nblk * 16) {
         const int r0 = wordptr[row], r1 = wordptr[row + 1];
         const float cv = beta != 0.0f ? c[row] : 0.0f;  // issued ahead of the entries
         const float* img = r0 < 0 ? xT : x;  // the layout the entries index
@@ -200,12 +207,16 @@ __global__ __launch_bounds__(1024) void k_csr_compact(const int* __restrict__ wo
 __global__ __launch_bounds__(1024) void k_csr_rows(const int* __restrict__ rowptr, const i32x4* __restrict__ ent,
                                                    const float* __restrict__ x, const float* __restrict__ xT,
                                                    int nrows, float alpha, float beta, const float* c, float* q,
-                                                   double* partial)
+                                                   double* partial, IterEnd fold, int nblk)
 {
     __shared__ double lds[16];
+    if (fold.st && (int)blockIdx.x == nblk) {
+        iter_end_run<1024>(fold, lds);
+        return;
+    }
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     double s2 = 0.0;
-    for (int row = blockIdx.x * 16 + w; row < nrows; row += gridDim.x * 16) {
+    for (int row = blockIdx.x * 16 + w; row < nrows; row += nblk * 16) {
         const int r0 = rowptr[row], r1 = rowptr[row + 1];
         const float cv = beta != 0.0f ? c[row] : 0.0f;
         const float* img = r0 < 0 ? xT : x;
@@ -258,14 +269,17 @@ __global__ __launch_bounds__(kCscThreads) void k_csc_cols(const int* __restrict_
 }
 
 hipError_t launch_project_stored(const Plan& p, const float* x, const float* xT, float alpha, float beta,
-                                 const float* c, float* q, double* partial, hipStream_t s)
+                                 const float* c, float* q, double* partial, hipStream_t s, const IterEnd* fold)
 {
+    const int nblk = project_blocks(p);
+    const IterEnd fe = fold ? *fold : IterEnd();
+    const dim3 grid((unsigned)(nblk + (fold ? 1 : 0)));
     if (p.mat.compact)
-        hipLaunchKernelGGL(k_csr_compact, dim3(project_blocks(p)), dim3(1024), 0, s, p.mat.d_rowptr,
-                           p.mat.d_rwords, x, xT, p.V * p.B, alpha, beta, c, q, partial);
+        hipLaunchKernelGGL(k_csr_compact, grid, dim3(1024), 0, s, p.mat.d_rowptr, p.mat.d_rwords, x, xT, p.V * p.B,
+                           alpha, beta, c, q, partial, fe, nblk);
     else
-        hipLaunchKernelGGL(k_csr_rows, dim3(project_blocks(p)), dim3(1024), 0, s, p.mat.d_rowptr,
-                           (const i32x4*)p.mat.d_rent, x, xT, p.V * p.B, alpha, beta, c, q, partial);
+        hipLaunchKernelGGL(k_csr_rows, grid, dim3(1024), 0, s, p.mat.d_rowptr, (const i32x4*)p.mat.d_rent, x, xT,
+                           p.V * p.B, alpha, beta, c, q, partial, fe, nblk);
     return hipGetLastError();
 }
 
