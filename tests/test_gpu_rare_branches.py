@@ -58,11 +58,13 @@ def small(E, oracle):
     return _cache["small"]
 
 
-def run_both(E, oracle, K, **kw):
+def run_both(E, oracle, K, stored=0, **kw):
     g, P, M, c = small(E, oracle)
     y = c.y.astype(np.float32)
     fo, so = M.reconstruct(y, oracle.Params(outer_iters=K, **kw), f_ref=c.phantom)
-    f, sg = P.reconstruct(dev(y), E.Params(outer_iters=K, **kw), f_ref=dev(c.phantom))
+    if stored:
+        P.store_matrix()
+    f, sg = P.reconstruct(dev(y), E.Params(outer_iters=K, stored_matrix=stored, **kw), f_ref=dev(c.phantom))
     return f.cpu().numpy(), sg, fo, so
 
 
@@ -126,15 +128,20 @@ def one_ray_geometry():
     return Geometry(2, 2, 1.0, 1, 1, 0.1, 10.0, 20.0, 0.0, np.array([0.0]))
 
 
-def test_cgls_breakdown_after_the_exact_step(E, oracle):
+# stored_matrix 1: the iteration's operators from the stored matrix (and its
+# close folded into the next projector launch), a launch sequence of its own
+@pytest.mark.parametrize("stored", [0, 1], ids=["fly", "stored"])
+def test_cgls_breakdown_after_the_exact_step(E, oracle, stored):
     """gamma_1 = 0 after the first step stops CGLS (App. I): one step per outer
     iteration on both sides, the records of the stopped step equal."""
     g = one_ray_geometry()
     P, M = E.Plan(g), oracle.Matrix(g)
+    if stored:
+        P.store_matrix()
     y = np.array([[0.75]], np.float32)
     kw = dict(outer_iters=4, lam=10.0, edge_quantile=0.5)
     fo, so = M.reconstruct(y, oracle.Params(**kw))
-    f, sg = P.reconstruct(dev(y), E.Params(**kw))
+    f, sg = P.reconstruct(dev(y), E.Params(stored_matrix=stored, **kw))
     print("oracle steps", so["cgls_steps"], "gamma", so["cgls_gamma"], "delta", so["cgls_delta"])
     assert np.all(so["cgls_steps"] == 1)
     assert np.array_equal(sg["cgls_steps"], so["cgls_steps"])
@@ -146,14 +153,17 @@ def test_cgls_breakdown_after_the_exact_step(E, oracle):
     assert rel(f.cpu().numpy(), fo) <= 1e-5
 
 
-def test_cgls_breakdown_at_the_start(E, oracle):
+@pytest.mark.parametrize("stored", [0, 1], ids=["fly", "stored"])
+def test_cgls_breakdown_at_the_start(E, oracle, stored):
     """y = 0 from f = 0: gamma_0 = 0, so CGLS takes no step (App. I); P2 then
     sees a zero direction and the image stays zero."""
     g, P, M, c = small(E, oracle)
+    if stored:
+        P.store_matrix()
     y = np.zeros((g.n_views, g.n_bins), np.float32)
     kw = dict(outer_iters=2)
     fo, so = M.reconstruct(y, oracle.Params(**kw))
-    f, sg = P.reconstruct(dev(y), E.Params(**kw))
+    f, sg = P.reconstruct(dev(y), E.Params(stored_matrix=stored, **kw))
     assert np.all(so["cgls_steps"] == 0)
     assert np.array_equal(sg["cgls_steps"], so["cgls_steps"])
     assert np.all(sg["cgls_gamma"] == 0.0) and np.all(sg["cgls_delta"] == 0.0)
@@ -161,11 +171,12 @@ def test_cgls_breakdown_at_the_start(E, oracle):
     assert float(torch.abs(f).max()) == 0.0 and np.abs(fo).max() == 0.0
 
 
-def test_records_match_the_oracle(E, oracle):
+@pytest.mark.parametrize("stored", [0, 1], ids=["fly", "stored"])
+def test_records_match_the_oracle(E, oracle, stored):
     """The Armijo energies before / after each descent step and the CGLS
     scalars of each step agree with the oracle's while the trajectories agree
     closely (first iterations)."""
-    f, sg, fo, so = run_both(E, oracle, 6)
+    f, sg, fo, so = run_both(E, oracle, 6, stored=stored)
     assert np.array_equal(sg["armijo_k"], so["armijo_k"])
     for key in ("armijo_q0", "armijo_q1", "cgls_gamma", "cgls_delta"):
         r = np.abs(sg[key] - so[key]).max() / np.abs(so[key]).max()
