@@ -45,10 +45,10 @@ PMC_TRAFFIC = {
                 "bytes": (8343.5 * 2.0 + 125.6 * 1.0) * 1024},
     "backproject": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "4232d9b9533001f9",
                     "bytes": (5979.9 * 2.0 + 1304.0 * 1.0) * 1024},
-    "project_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "e0fcaada13e40536",
-                       "bytes": (60873.0 * 2.0 + 129.3 * 1.0) * 1024},
-    "backproject_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "e0fcaada13e40536",
-                           "bytes": (56056.7 * 2.0 + 2292.8 * 1.0) * 1024},
+    "project_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "fd7c499ef7f7fce8",
+                       "bytes": (60465.1 * 2.0 + 129.4 * 1.0) * 1024},
+    "backproject_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "fd7c499ef7f7fce8",
+                           "bytes": (56058.5 * 2.0 + 2293.3 * 1.0) * 1024},
 }
 
 
@@ -56,10 +56,10 @@ PMC_TRAFFIC = {
 # stored_hbm leg, whose matrix streams from HBM); see
 # profiles/eptv_stored_operators_512x512_200views_paper_scanner_pmc_bytes.md.
 PMC_TRAFFIC_HBM = {
-    "project_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "e0fcaada13e40536",
-                       "bytes": (430343.8 * 2.0 + 902.8 * 1.0) * 1024},
-    "backproject_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "e0fcaada13e40536",
-                           "bytes": (459931.0 * 2.0 + 1193.4 * 1.0) * 1024},
+    "project_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "fd7c499ef7f7fce8",
+                       "bytes": (426012.5 * 2.0 + 868.4 * 1.0) * 1024},
+    "backproject_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "fd7c499ef7f7fce8",
+                           "bytes": (459869.6 * 2.0 + 1193.8 * 1.0) * 1024},
 }
 
 
@@ -83,10 +83,10 @@ PMC_L2 = {
                 "read_requests": 1.351e6},
     "backproject": {"source": "paper_1009_2288_amd/csrc/proj.hip", "sha256_16": "4232d9b9533001f9",
                     "read_requests": 0.460e6},
-    "project_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "e0fcaada13e40536",
-                       "read_requests": 1.530e6},
-    "backproject_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "e0fcaada13e40536",
-                           "read_requests": 1.683e6},
+    "project_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "fd7c499ef7f7fce8",
+                       "read_requests": 1.517e6},
+    "backproject_stored": {"source": "paper_1009_2288_amd/csrc/spmv.hip", "sha256_16": "fd7c499ef7f7fce8",
+                           "read_requests": 1.682e6},
 }
 
 
