@@ -560,11 +560,37 @@ struct DecShared {
 // Block sums of kP2Slots values per thread of a kP2Threads block in a fixed
 // order: each thread stores its values in v[c][tid] (threads past the first
 // 64 nw store nothing and count as zeros), then lane l of wave c sums slot
-// c's entries l, l + 64, ... in order and wave c's butterfly closes slot c.
+// c's entries l, l + 64, ... in order and wave c closes slot c by DPP lane
+// patterns (wave_sum_dpp).
 struct SlotSums {
     double v[kP2Slots][kP2Threads];
     double tot[kP2Slots];
 };
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_add_d(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, false);
+    return v + __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double lane_value_d(double v, int l)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// Sum over the 64 lanes by DPP lane patterns within each 16-lane row, then
+// the four rows in a fixed order (every lane gets the same bits).
+__device__ __forceinline__ double wave_sum_dpp(double v)
+{
+    v = dpp_add_d<0xb1>(v);
+    v = dpp_add_d<0x4e>(v);
+    v = dpp_add_d<0x141>(v);
+    v = dpp_add_d<0x140>(v);
+    return (lane_value_d(v, 0) + lane_value_d(v, 16)) + (lane_value_d(v, 32) + lane_value_d(v, 48));
+}
 
 // The sums of the values stored in L.v by the first 64 nw threads, in L.tot
 // for every thread.  Contains __syncthreads() before and after.
@@ -575,7 +601,7 @@ __device__ __forceinline__ void slot_sums_stored(SlotSums& L, int nw = kP2Thread
     if (w < kP2Slots) {
         double a = 0.0;
         for (int q = 0; q < nw; ++q) a += L.v[w][l + 64 * q];
-        a = wave_sum(a);
+        a = wave_sum_dpp(a);
         if (l == 0) L.tot[w] = a;
     }
     __syncthreads();
