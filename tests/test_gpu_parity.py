@@ -341,6 +341,34 @@ def test_reconstruct_is_deterministic_and_graph_equals_direct(E, monkeypatch, st
     assert torch.equal(f1, f2) and torch.equal(f1, f3) and torch.equal(f1, f4)
 
 
+@pytest.mark.parametrize("every", [0, 2], ids=["no_checks", "checks_every_2"])
+def test_stored_iteration_close_folded_equals_own_launch(E, monkeypatch, every):
+    """With the stored matrix and direct launches, each outer iteration's close
+    (records, counter, state reset) runs in one extra block of the next
+    iteration's first projector launch; with a captured graph it is a launch
+    of its own.  Both give the same image and the same records bit for bit,
+    also when RMSE checks (stop_rmse, never reached here) make the checked
+    iterations close in their own launch."""
+    c = synth.make_case("small", 1)
+    P = plan(E, "small")
+    P.store_matrix()
+    kw = dict(outer_iters=7, stored_matrix=1)
+    if every:
+        kw.update(stop_rmse=1e-12, check_every=every)
+    prm = E.Params(**kw)
+    y, ref = dev(c.y), dev(c.phantom)
+    monkeypatch.delenv("EPTV_GRAPH", raising=False)
+    f1, s1 = P.reconstruct(y, prm, f_ref=ref)
+    monkeypatch.setenv("EPTV_GRAPH", "1")
+    f2, s2 = P.reconstruct(y, prm, f_ref=ref)
+    torch.cuda.synchronize()
+    assert torch.equal(f1, f2)
+    assert set(s1) == set(s2)
+    for k in s1:
+        assert np.array_equal(np.asarray(s1[k]), np.asarray(s2[k])), k
+    assert len(s1["rmse"]) == 7 and np.all(np.asarray(s1["rmse"]) > 0)
+
+
 def test_warm_start_split_equals_straight_run(E):
     """Resume: K1 iterations then K2 more from the result equals K1 + K2 in one call."""
     c = synth.make_case("small", 2)
