@@ -15,6 +15,7 @@
 // the remaining steps.
 #include "batch.h"
 #include "eptv_internal.h"
+#include "cgls_step.h"
 #include "reduce.h"
 #include "state.h"
 
@@ -38,62 +39,7 @@ hipError_t launch_state_init(DevState* st, uint32_t* hist, uint32_t rank, float 
 
 int sino_blocks(const Plan& p) { return (int)(((size_t)p.V * p.B + 1023) / 1024); }
 
-// u = u_in + a_m s (image part) and r = r - a_m q (sinogram part), one launch.
-// Every block first forms a_m from gamma_m (the backprojector's partials for
-// m = 0, else the value recorded by the previous s-update) and delta_m (the
-// projector's partials).  When part_res is given the sinogram blocks also
-// emit ||r||^2.
-constexpr int kAxpyBlock = 256;
-constexpr int kAxpyPer = 4;
-
-__device__ __forceinline__ void cgls_axpy_block(DevState* st, int m, const double* part_bp, int n_bp,
-                                                const double* part_proj, int n_proj, size_t n_img, size_t n_sino,
-                                                int img_blocks, const float* u_in, float* u, const float* sdir,
-                                                float* r, const float* q, double* part_res, int blk, double* lds)
-{
-    const double g = m == 0 ? block_sum_partials<kAxpyBlock>(part_bp, n_bp, 1, lds) : st->gamma[m];
-    const double d = block_sum_partials<kAxpyBlock>(part_proj, n_proj, 1, lds);
-    const double g0 = m == 0 ? g : st->gamma0;
-    const int was = m == 0 ? 1 : st->active[m - 1];
-    const bool g_ok = g > 1e-30 * g0;
-    const int active = was && g_ok && (d > 0.0);
-    const float a = active ? (float)(g / d) : 0.0f;
-    if (blk == 0 && threadIdx.x == 0) {
-        if (m == 0) {
-            st->gamma[0] = g;
-            st->gamma0 = g;
-        }
-        st->delta[m] = was && g_ok ? d : 0.0;  // a step stopped by gamma_m forms no delta_m
-        st->a[m] = a;
-        st->active[m] = active;
-        if (active) st->cg_steps = m + 1;
-    }
-    if (blk < img_blocks) {
-        const size_t base = (size_t)blk * kAxpyBlock * kAxpyPer + threadIdx.x;
-#pragma unroll
-        for (int e = 0; e < kAxpyPer; ++e) {
-            const size_t i = base + (size_t)e * kAxpyBlock;
-            if (i < n_img) u[i] = fmaf(a, sdir[i], u_in[i]);
-        }
-    } else {
-        const size_t base = (size_t)(blk - img_blocks) * kAxpyBlock * kAxpyPer + threadIdx.x;
-        double r2 = 0.0;
-#pragma unroll
-        for (int e = 0; e < kAxpyPer; ++e) {
-            const size_t i = base + (size_t)e * kAxpyBlock;
-            if (i < n_sino) {
-                const float rv = fmaf(-a, q[i], r[i]);
-                r[i] = rv;
-                r2 += (double)rv * (double)rv;
-            }
-        }
-        if (part_res) {
-            r2 = block_sum<kAxpyBlock>(r2, lds);
-            if (threadIdx.x == 0) part_res[blk - img_blocks] = r2;
-        }
-    }
-}
-
+// One CGLS step's update, u = u_in + a_m s and r -= a_m q (cgls_axpy_block).
 __global__ __launch_bounds__(kAxpyBlock) void k_cgls_axpy(DevState* st, int m, const double* part_bp, int n_bp,
                                                           const double* part_proj, int n_proj, size_t n_img,
                                                           size_t n_sino, int img_blocks, const float* u_in,

@@ -267,6 +267,12 @@ hipError_t launch_gd_p1(const Plan& p, const float* f, const float* z, float ste
 // sigma: three histogram passes, each closed by a one-block kernel
 hipError_t launch_edges_hist(const Plan& p, const float* f, float eps2, uint32_t* keys,
                              uint32_t* hist0, hipStream_t s);
+// a CGLS step's update (as launch_cgls_axpy, u distinct from u_in) with the
+// histogram of the resulting u's half-edges (as launch_edges_hist), one launch
+hipError_t launch_cgls_axpy_edges(const Plan& p, DevState* st, int m, const double* part_bp,
+                                  const double* part_proj, const float* u_in, float* u, const float* sdir, float* r,
+                                  const float* q, double* part_res, float eps2, uint32_t* keys, uint32_t* hist0,
+                                  hipStream_t s);
 // pass 1 and 2 (each first closing the previous digit), then the last digit and sigma
 hipError_t launch_select_pass(const Plan& p, int pass, const uint32_t* keys, DevState* st, uint32_t* hist,
                               hipStream_t s);

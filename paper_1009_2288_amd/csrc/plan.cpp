@@ -95,11 +95,13 @@ struct Ctx {
 // sigma from the half-edge magnitudes of `img` (radix select, three digits).
 // The selection of sigma (three digit passes); with last_digit false the
 // last digit is left to the first P2 kernel (enqueue_p2's close_sigma).
+// With edges false the first digit's histogram is already there (formed by
+// the launch that produced img).
 static hipError_t enqueue_select(const Plan& p, Workspace& W, const float* img, float eps2, float floor_,
-                                 hipStream_t s, bool last_digit = true)
+                                 hipStream_t s, bool last_digit = true, bool edges = true)
 {
     hipError_t e;
-    if ((e = launch_edges_hist(p, img, eps2, W.keys, W.hist, s)) != hipSuccess) return e;
+    if (edges && (e = launch_edges_hist(p, img, eps2, W.keys, W.hist, s)) != hipSuccess) return e;
     for (int pass = 1; pass <= 2; ++pass)
         if ((e = launch_select_pass(p, pass, W.keys, W.st, W.hist, s)) != hipSuccess) return e;
     return last_digit ? launch_select_sigma(W.st, W.hist, floor_, s) : hipSuccess;
@@ -214,6 +216,14 @@ static hipError_t enqueue_iteration(const Ctx& c, hipStream_t s, bool fold_prev 
     } else if ((e = proj(c.f, W.fT, -1.0f, 1.0f, c.y, W.r, nullptr)) != hipSuccess) {
         return e;
     }
+    // sigma is chosen from P2's start image when it is not given; when that is
+    // v, the last CGLS step's launch also forms the first digit's histogram of
+    // its half-edges, and writes v to z (free by then) so that the histogram
+    // blocks read the step's unchanged inputs
+    const bool select = adaptive && T > 0 && !c.wx_in;
+    const bool fused_edges = select && M > 0 && !q.p2_start;
+    const float eps2 = (float)(q.tv_eps * q.tv_eps);
+    float* const v_out = fused_edges ? W.z : W.u;
     if (M > 0) {
         // s = P^T r (gamma_0 partials)
         if ((e = bproj(W.r, 1.0f, 0.0f, nullptr, W.s, W.sT, W.part_bp)) != hipSuccess) return e;
@@ -221,9 +231,14 @@ static hipError_t enqueue_iteration(const Ctx& c, hipStream_t s, bool fold_prev 
             const bool last = m == M - 1;
             // q = P s (delta_m partials); u += a_m s, r -= a_m q
             if ((e = proj(W.s, W.sT, 1.0f, 0.0f, nullptr, W.q, W.part_proj)) != hipSuccess) return e;
-            if ((e = launch_cgls_axpy(p, W.st, m, W.part_bp, W.part_proj, m == 0 ? c.f : W.u, W.u, W.s, W.r, W.q,
-                                      last ? W.part_res : nullptr, s)) != hipSuccess)
-                return e;
+            const float* u_in = m == 0 ? c.f : W.u;
+            if (last && fused_edges)
+                e = launch_cgls_axpy_edges(p, W.st, m, W.part_bp, W.part_proj, u_in, v_out, W.s, W.r, W.q,
+                                           W.part_res, eps2, W.keys, W.hist, s);
+            else
+                e = launch_cgls_axpy(p, W.st, m, W.part_bp, W.part_proj, u_in, W.u, W.s, W.r, W.q,
+                                     last ? W.part_res : nullptr, s);
+            if (e != hipSuccess) return e;
             if (last) break;  // P^T r of the final residual is not needed
             // z = P^T r (gamma_{m+1} partials); s = z + b_m s
             if ((e = bproj(W.r, 1.0f, 0.0f, nullptr, W.z, nullptr, W.part_bp)) != hipSuccess) return e;
@@ -235,16 +250,14 @@ static hipError_t enqueue_iteration(const Ctx& c, hipStream_t s, bool fold_prev 
         if ((e = launch_gd_p1(p, c.f, W.z, (float)(q.mu / q.lambda), W.u, s)) != hipSuccess) return e;
     }
     // Step 2: P2 from v (or f^(k)), sigma chosen once from the start image.
-    const float* start = q.p2_start ? c.f : W.u;
-    const bool select = adaptive && T > 0 && !c.wx_in;
+    const float* start = q.p2_start ? c.f : v_out;
     if (select) {  // the last digit is closed by the first descent step's kernel
-        if ((e = enqueue_select(p, W, start, (float)(q.tv_eps * q.tv_eps), (float)q.sigma_floor, s, false)) !=
-            hipSuccess)
+        if ((e = enqueue_select(p, W, start, eps2, (float)q.sigma_floor, s, false, !fused_edges)) != hipSuccess)
             return e;
     }
     // Step 3 (positivity) is fused into the last descent update.
     // With a reference, the last update also forms the squared errors per tile.
-    if ((e = enqueue_p2(p, W, q, start, W.u, T, c.f, W.fT, q.positivity, W.st_k, s, c.wx_in, c.wy_in, c.replay,
+    if ((e = enqueue_p2(p, W, q, start, v_out, T, c.f, W.fT, q.positivity, W.st_k, s, c.wx_in, c.wy_in, c.replay,
                         c.f_ref, select)) != hipSuccess)
         return e;
     if (c.f_ref && T == 0) {

@@ -13,6 +13,7 @@
 // exactly one pixel (its left / lower pixel, or the border pixel for the
 // edges on the left and bottom image border) for the energy sums.
 #include "batch.h"
+#include "cgls_step.h"
 #include "eptv_internal.h"
 #include "tables.h"
 #include "reduce.h"
@@ -147,34 +148,137 @@ __device__ __forceinline__ void hist_add(uint32_t* h, uint32_t bin)
     }
 }
 
+// The image a half-edge pass reads: pixels in memory, or the pixels that the
+// same launch's CGLS update is writing, u_in + a s, formed here again with the
+// same FMA (so the same bits) from the step's unchanged inputs.  A pixel is
+// loaded as it is stored (Raw) and turned into its value afterwards, so that
+// loads can be in flight while a is still being formed.
+struct StoredImage {
+    const float* f;
+    typedef float Raw;
+    __device__ Raw load(size_t id) const { return f[id]; }
+    __device__ float value(Raw r) const { return r; }
+};
+struct AxpyImage {
+    const float* u_in;
+    const float* s;
+    float a;
+    typedef float2 Raw;
+    __device__ Raw load(size_t id) const { return make_float2(u_in[id], s[id]); }
+    __device__ float value(Raw r) const { return fmaf(a, r.y, r.x); }
+};
+
+template <class Img>
+using RawNbhd = typename Img::Raw[3][3];
+
+__device__ __forceinline__ bool in_image(int nx, int ny, int i, int j)
+{
+    return i >= 0 && i < nx && j >= 0 && j < ny;
+}
+
+// Every load is made, at a position clamped into the image (nbhd_of zeroes
+// what lies outside): conditional loads into zeroed registers make the
+// compiler wait for all loads in flight before each one.
+template <class Img>
+__device__ __forceinline__ void load_raw(const Img& img, int nx, int ny, int i, int j, RawNbhd<Img>& R)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const int ii = min(max(i + a - 1, 0), nx - 1), jj = min(max(j + b - 1, 0), ny - 1);
+            R[a][b] = img.load((size_t)jj * nx + ii);
+        }
+}
+
+// Pixels outside the image are zero.
+template <class Img>
+__device__ __forceinline__ void nbhd_of(const Img& img, int nx, int ny, int i, int j, const RawNbhd<Img>& R, Nbhd& N)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) N.n[a][b] = in_image(nx, ny, i + a - 1, j + b - 1) ? img.value(R[a][b]) : 0.0f;
+}
+
 // Edge index: x-edge (i+1/2, j) -> j*(nx+1) + i+1; y-edge (i, j+1/2) -> ny*(nx+1) + (j+1)*nx + i.
-// One 16x16 tile's half-edge magnitudes into keys and the block's LDS
+// Pixel (i, j)'s owned half-edge magnitudes into keys and the block's LDS
 // histogram of their top 11 bits.
-__device__ __forceinline__ void edges_tile(const float* __restrict__ f, int nx, int ny, float eps2, uint32_t* keys,
-                                           int bx, int by, uint32_t* h)
+__device__ __forceinline__ void edges_pixel(const Nbhd& N, int nx, int ny, int i, int j, float eps2, uint32_t* keys,
+                                            uint32_t* h)
+{
+    const size_t xo = (size_t)j * (nx + 1), yo = (size_t)ny * (nx + 1);
+    uint32_t k = __float_as_uint(tv_right(N, eps2));
+    keys[xo + i + 1] = k;
+    hist_add(h, k >> 21);
+    k = __float_as_uint(tv_up(N, eps2));
+    keys[yo + (size_t)(j + 1) * nx + i] = k;
+    hist_add(h, k >> 21);
+    if (i == 0) {
+        k = __float_as_uint(tv_left(N, eps2));
+        keys[xo] = k;
+        hist_add(h, k >> 21);
+    }
+    if (j == 0) {
+        k = __float_as_uint(tv_down(N, eps2));
+        keys[yo + i] = k;
+        hist_add(h, k >> 21);
+    }
+}
+
+// One 16x16 tile's half-edges, one pixel per thread.
+template <class Img>
+__device__ __forceinline__ void edges_tile(const Img& img, int nx, int ny, float eps2, uint32_t* keys, int bx, int by,
+                                           uint32_t* h)
 {
     const int i = bx * kT + (threadIdx.x & (kT - 1)), j = by * kT + threadIdx.x / kT;
     if (i < nx && j < ny) {
+        RawNbhd<Img> R;
+        load_raw(img, nx, ny, i, j, R);
         Nbhd N;
-        load_nbhd(f, nx, ny, i, j, N);
-        const size_t xo = (size_t)j * (nx + 1), yo = (size_t)ny * (nx + 1);
-        uint32_t k = __float_as_uint(tv_right(N, eps2));
-        keys[xo + i + 1] = k;
-        hist_add(h, k >> 21);
-        k = __float_as_uint(tv_up(N, eps2));
-        keys[yo + (size_t)(j + 1) * nx + i] = k;
-        hist_add(h, k >> 21);
-        if (i == 0) {
-            k = __float_as_uint(tv_left(N, eps2));
-            keys[xo] = k;
-            hist_add(h, k >> 21);
+        nbhd_of(img, nx, ny, i, j, R, N);
+        edges_pixel(N, nx, ny, i, j, eps2, keys, h);
+    }
+}
+
+// A block's tiles first, first + stride, ... of the image, kEdgeGroup at a
+// time: the group's neighbourhoods are all loaded before any is used (a
+// block per CU would otherwise wait out one load round trip per tile).
+// `ready` runs once, after the first group's loads are issued, by every
+// thread of the block (it may hold barriers; AxpyImage forms a there).
+constexpr int kEdgeGroup = 4;
+
+template <class Img, class Ready>
+__device__ __forceinline__ void edges_walk(Img& img, int nx, int ny, float eps2, uint32_t* keys, int first, int stride,
+                                           uint32_t* h, Ready&& ready)
+{
+    const int tx = (nx + kT - 1) / kT, nt = tx * ((ny + kT - 1) / kT);
+    const int li = threadIdx.x & (kT - 1), lj = threadIdx.x / kT;
+    bool pending = true;
+    for (int t0 = first; t0 < nt; t0 += kEdgeGroup * stride) {
+        RawNbhd<Img> R[kEdgeGroup];
+#pragma unroll
+        for (int g = 0; g < kEdgeGroup; ++g) {  // (past the last tile or the image: a clamped position)
+            const int t = min(t0 + g * stride, nt - 1);
+            const int i = min((t % tx) * kT + li, nx - 1), j = min((t / tx) * kT + lj, ny - 1);
+            load_raw(img, nx, ny, i, j, R[g]);
         }
-        if (j == 0) {
-            k = __float_as_uint(tv_down(N, eps2));
-            keys[yo + i] = k;
-            hist_add(h, k >> 21);
+        if (pending) {
+            ready();
+            pending = false;
+        }
+#pragma unroll
+        for (int g = 0; g < kEdgeGroup; ++g) {
+            const int t = t0 + g * stride;
+            const int i = (t % tx) * kT + li, j = (t / tx) * kT + lj;
+            if (t < nt && i < nx && j < ny) {
+                Nbhd N;
+                nbhd_of(img, nx, ny, i, j, R[g], N);
+                edges_pixel(N, nx, ny, i, j, eps2, keys, h);
+            }
         }
     }
+    if (pending) ready();
 }
 
 __device__ __forceinline__ void hist_clear(uint32_t* h)
@@ -197,20 +301,65 @@ __global__ __launch_bounds__(256) void k_edges_hist(const float* __restrict__ f,
                                                     uint32_t* keys, uint32_t* hist0)
 {
     __shared__ uint32_t h[kSelectBins];
-    const int tx = (nx + kT - 1) / kT, nt = tx * ((ny + kT - 1) / kT);
     hist_clear(h);
-    for (int t = blockIdx.x; t < nt; t += gridDim.x) edges_tile(f, nx, ny, eps2, keys, t % tx, t / tx, h);
+    StoredImage img{f};
+    edges_walk(img, nx, ny, eps2, keys, blockIdx.x, gridDim.x, h, [] {});
     hist_flush(h, hist0);
 }
 
 constexpr int kEdgesHistBlocks = 256;
 
+static int edges_hist_blocks(const Plan& p)
+{
+    const int nt = ((p.nx + kT - 1) / kT) * ((p.ny + kT - 1) / kT);
+    return std::min(nt, kEdgesHistBlocks);
+}
+
 hipError_t launch_edges_hist(const Plan& p, const float* f, float eps2, uint32_t* keys, uint32_t* hist0,
                              hipStream_t s)
 {
-    const int nt = ((p.nx + kT - 1) / kT) * ((p.ny + kT - 1) / kT);
-    hipLaunchKernelGGL(k_edges_hist, dim3((unsigned)std::min(nt, kEdgesHistBlocks)), dim3(256), 0, s, f, p.nx, p.ny,
-                       eps2, keys, hist0);
+    hipLaunchKernelGGL(k_edges_hist, dim3((unsigned)edges_hist_blocks(p)), dim3(256), 0, s, f, p.nx, p.ny, eps2,
+                       keys, hist0);
+    return hipGetLastError();
+}
+
+// The last CGLS step's update (u = u_in + a s written to u, r -= a q) and the
+// half-edge histogram of that u, one launch: the first blocks are the
+// histogram's (k_edges_hist's walk over the tiles), forming the pixels they
+// read from u_in and s with the update's own FMA, so they never read what
+// the update blocks are writing; u must not alias u_in.
+__global__ __launch_bounds__(kAxpyBlock) void k_cgls_axpy_edges(
+    DevState* st, int m, const double* part_bp, int n_bp, const double* part_proj, int n_proj, size_t n_img,
+    size_t n_sino, int img_blocks, const float* __restrict__ u_in, float* __restrict__ u,
+    const float* __restrict__ sdir, float* r, const float* q, double* part_res, int edge_blocks, int nx, int ny,
+    float eps2, uint32_t* keys, uint32_t* hist0)
+{
+    __shared__ double lds[4];
+    __shared__ uint32_t h[kSelectBins];
+    const int blk = (int)blockIdx.x - edge_blocks;
+    if (blk >= 0) {
+        cgls_axpy_block(st, m, part_bp, n_bp, part_proj, n_proj, n_img, n_sino, img_blocks, u_in, u, sdir, r, q,
+                        part_res, blk, lds);
+        return;
+    }
+    AxpyImage img{u_in, sdir, 0.0f};
+    hist_clear(h);
+    edges_walk(img, nx, ny, eps2, keys, blockIdx.x, edge_blocks, h,
+               [&] { img.a = cgls_step_a(st, m, part_bp, n_bp, part_proj, n_proj, false, lds); });
+    hist_flush(h, hist0);
+}
+
+hipError_t launch_cgls_axpy_edges(const Plan& p, DevState* st, int m, const double* part_bp,
+                                  const double* part_proj, const float* u_in, float* u, const float* sdir, float* r,
+                                  const float* q, double* part_res, float eps2, uint32_t* keys, uint32_t* hist0,
+                                  hipStream_t s)
+{
+    if (u == u_in) return hipErrorInvalidValue;
+    const size_t ni = (size_t)p.nx * p.ny, ns = (size_t)p.V * p.B;
+    const int bi = axpy_blocks(ni), bs = axpy_blocks(ns), be = edges_hist_blocks(p);
+    hipLaunchKernelGGL(k_cgls_axpy_edges, dim3(be + bi + bs), dim3(kAxpyBlock), 0, s, st, m, part_bp,
+                       image_tile_blocks(p), part_proj, project_blocks(p), ni, ns, bi, u_in, u, sdir, r, q, part_res,
+                       be, p.nx, p.ny, eps2, keys, hist0);
     return hipGetLastError();
 }
 
@@ -1142,7 +1291,7 @@ __global__ __launch_bounds__(256) void kb_edges_hist(const SliceDev* __restrict_
             cur = w.x;
         }
         const SliceDev& d = sl[w.x];
-        edges_tile(d.buf[imgs], d.nx, d.ny, eps2, d.keys, w.y % d.t16x, w.y / d.t16x, h);
+        edges_tile(StoredImage{d.buf[imgs]}, d.nx, d.ny, eps2, d.keys, w.y % d.t16x, w.y / d.t16x, h);
     }
     hist_flush(h, sl[cur].hist);
 }

@@ -369,6 +369,28 @@ def test_stored_iteration_close_folded_equals_own_launch(E, monkeypatch, every):
     assert len(s1["rmse"]) == 7 and np.all(np.asarray(s1["rmse"]) > 0)
 
 
+@pytest.mark.parametrize("name,stored", [("small", 0), ("small", 1), ("ragged", 0), ("odd", 1)])
+def test_sigma_from_last_cgls_launch_equals_selection_entry(E, name, stored):
+    """The last CGLS step's launch also forms the half-edge histogram of v
+    (sigma's first digit, Eq. 5 with sigma as an order statistic of the
+    magnitudes): the sigma an outer iteration records equals, bit for bit,
+    the selection entry point run on that iteration's v (the same iteration
+    with no P2 step and positivity off, whose CGLS launches leave the
+    histogram to the selection)."""
+    g = GEOMS[name]()
+    P = plan(E, name)
+    if stored:
+        P.store_matrix()
+    y = dev(synth.make_case("small", 4).y) if name == "small" else dev(synth.random_image(g.n_bins, g.n_views, 4))
+    base = dict(outer_iters=1, stored_matrix=stored)
+    v, _ = P.reconstruct(y, E.Params(tv_iters=0, positivity=0, **base), stats=False)
+    prm = E.Params(**base)
+    _, rec = P.reconstruct(y, prm)
+    s_ref = P.select_sigma(v, prm.edge_quantile, prm.tv_eps, prm.sigma_floor)
+    torch.cuda.synchronize()
+    assert np.float32(rec["sigma"][0]).tobytes() == s_ref.cpu().numpy().astype(np.float32)[0].tobytes()
+
+
 def test_warm_start_split_equals_straight_run(E):
     """Resume: K1 iterations then K2 more from the result equals K1 + K2 in one call."""
     c = synth.make_case("small", 2)
