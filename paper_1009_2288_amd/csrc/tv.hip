@@ -456,11 +456,26 @@ __device__ __forceinline__ void select_finalize_block(DevState* st, int pass, ui
 // block), so the digit needs no kernel of its own; block 0 records the
 // prefix and rank after it for the next pass (in entries no block of this
 // launch reads).  hist: the three passes' histograms.
+// The keys a thread takes in a grid-stride walk are loaded kSelGroup at a
+// time, unconditionally (past the end: the last key, not counted), so that
+// they are all in flight together; the first group is loaded before the
+// block closes the previous digit.
+constexpr int kSelGroup = 8;
+
 __global__ __launch_bounds__(256) void k_select_pass(const uint32_t* __restrict__ keys, size_t n, int pass,
                                                      DevState* st, uint32_t* hist)
 {
     __shared__ uint32_t h[kSelectBins];
     __shared__ SelShared S;
+    for (int b = threadIdx.x; b < kSelectBins; b += 256) h[b] = 0u;  // ordered by select_digit's barriers
+    const size_t stride = (size_t)gridDim.x * 256;
+    uint32_t k[kSelGroup];
+    auto load = [&](size_t e0) {
+#pragma unroll
+        for (int g = 0; g < kSelGroup; ++g) k[g] = keys[min(e0 + g * stride, n - 1)];
+    };
+    size_t e0 = (size_t)blockIdx.x * 256 + threadIdx.x;
+    load(e0);
     const uint32_t pin = pass == 1 ? st->prefix : st->sel_prefix[0];
     const uint32_t rin = pass == 1 ? st->rank : st->sel_rank[0];
     select_digit(hist + (pass - 1) * kSelectBins, pass - 1, rin, S);
@@ -469,7 +484,24 @@ __global__ __launch_bounds__(256) void k_select_pass(const uint32_t* __restrict_
         st->sel_prefix[pass - 1] = pout;
         st->sel_rank[pass - 1] = rin - S.found_before;
     }
-    select_hist_block(keys, n, pass, pout, hist + pass * kSelectBins, blockIdx.x, gridDim.x, h);
+    // pass 1: digit = bits 20..10 among keys whose bits 31..21 equal the
+    // prefix; pass 2: digit = bits 9..0 among keys whose bits 31..10 do
+    const int hshift = pass == 1 ? 21 : 10;
+    const int dshift = pass == 1 ? 10 : 0;
+    const uint32_t dmask = pass == 1 ? 2047u : 1023u;
+    const uint32_t want = pout >> hshift;
+    for (;;) {
+#pragma unroll
+        for (int g = 0; g < kSelGroup; ++g)
+            if (e0 + g * stride < n && (k[g] >> hshift) == want) hist_add(h, (k[g] >> dshift) & dmask);
+        e0 += kSelGroup * stride;
+        if (e0 >= n) break;
+        load(e0);
+    }
+    __syncthreads();
+    uint32_t* hp = hist + pass * kSelectBins;
+    for (int b = threadIdx.x; b < kSelectBins; b += 256)
+        if (h[b]) atomicAdd(&hp[b], h[b]);
 }
 
 int select_blocks(const Plan& p)
