@@ -71,21 +71,31 @@ __device__ __forceinline__ void cgls_supdate_block(DevState* st, int m, const do
                                                    const float* __restrict__ z, float* sdir, float* sdirT, int nx,
                                                    int ny, int tbx, int tby, float (*t)[33], double* lds)
 {
+    // the tile's s and z are loaded (at positions clamped into the image)
+    // before b_m is formed, so the two memory round trips overlap
+    const int bx = tbx * 32, by = tby * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    float sv[4], zv[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const size_t id = (size_t)min(by + ty + 8 * c, ny - 1) * nx + min(bx + tx, nx - 1);
+        sv[c] = sdir[id];
+        zv[c] = z[id];
+    }
     const double gn = block_sum_partials<256>(part_bp, n_bp, 1, lds);
     const float bm = st->active[m] ? (float)(gn / st->gamma[m]) : 0.0f;
     if (tbx == 0 && tby == 0 && threadIdx.x == 0) {
         st->gamma[m + 1] = gn;
         st->b[m] = bm;
     }
-    const int bx = tbx * 32, by = tby * 32;
-    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    for (int k = ty; k < 32; k += 8) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int k = ty + 8 * c;
         const int i = bx + tx, j = by + k;
         float v = 0.0f;
         if (i < nx && j < ny) {
-            const size_t id = (size_t)j * nx + i;
-            v = fmaf(bm, sdir[id], z[id]);
-            sdir[id] = v;
+            v = fmaf(bm, sv[c], zv[c]);
+            sdir[(size_t)j * nx + i] = v;
         }
         t[k][tx] = v;
     }

@@ -46,28 +46,40 @@ __device__ __forceinline__ float cgls_step_a(DevState* st, int m, const double* 
 
 // u = u_in + a_m s (image part, blocks below img_blocks) and r = r - a_m q
 // (sinogram part, the blocks after them), one launch.  When part_res is given
-// the sinogram blocks also emit ||r||^2.
+// the sinogram blocks also emit ||r||^2.  A block's operands are loaded
+// (unconditionally, at indices clamped into the vector) before a_m is formed,
+// so the two memory round trips overlap.
 __device__ __forceinline__ void cgls_axpy_block(DevState* st, int m, const double* part_bp, int n_bp,
                                                 const double* part_proj, int n_proj, size_t n_img, size_t n_sino,
                                                 int img_blocks, const float* u_in, float* u, const float* sdir,
                                                 float* r, const float* q, double* part_res, int blk, double* lds)
 {
+    const bool img = blk < img_blocks;
+    const size_t n = img ? n_img : n_sino;
+    const float* xs = img ? sdir : q;  // the direction the step moves along
+    const float* ys = img ? u_in : r;  // the vector it moves
+    const size_t base = (size_t)(img ? blk : blk - img_blocks) * kAxpyBlock * kAxpyPer + threadIdx.x;
+    float x[kAxpyPer], y[kAxpyPer];
+#pragma unroll
+    for (int e = 0; e < kAxpyPer; ++e) {
+        const size_t i = min(base + (size_t)e * kAxpyBlock, n - 1);
+        x[e] = xs[i];
+        y[e] = ys[i];
+    }
     const float a = cgls_step_a(st, m, part_bp, n_bp, part_proj, n_proj, blk == 0, lds);
-    if (blk < img_blocks) {
-        const size_t base = (size_t)blk * kAxpyBlock * kAxpyPer + threadIdx.x;
+    if (img) {
 #pragma unroll
         for (int e = 0; e < kAxpyPer; ++e) {
             const size_t i = base + (size_t)e * kAxpyBlock;
-            if (i < n_img) u[i] = fmaf(a, sdir[i], u_in[i]);
+            if (i < n_img) u[i] = fmaf(a, x[e], y[e]);
         }
     } else {
-        const size_t base = (size_t)(blk - img_blocks) * kAxpyBlock * kAxpyPer + threadIdx.x;
         double r2 = 0.0;
 #pragma unroll
         for (int e = 0; e < kAxpyPer; ++e) {
             const size_t i = base + (size_t)e * kAxpyBlock;
             if (i < n_sino) {
-                const float rv = fmaf(-a, q[i], r[i]);
+                const float rv = fmaf(-a, x[e], y[e]);
                 r[i] = rv;
                 r2 += (double)rv * (double)rv;
             }
