@@ -363,6 +363,11 @@ hipError_t launch_cgls_axpy_edges(const Plan& p, DevState* st, int m, const doub
     return hipGetLastError();
 }
 
+// The keys a thread takes in a grid-stride walk are loaded kSelGroup at a
+// time, unconditionally (past the end: the last key, not counted), so that
+// they are all in flight together.
+constexpr int kSelGroup = 8;
+
 // pass 1: digit = bits 20..10 among keys whose bits 31..21 equal the prefix;
 // pass 2: digit = bits 9..0 among keys whose bits 31..10 equal the prefix.
 __device__ __forceinline__ void select_hist_block(const uint32_t* __restrict__ keys, size_t n, int pass,
@@ -374,9 +379,14 @@ __device__ __forceinline__ void select_hist_block(const uint32_t* __restrict__ k
     const int dshift = pass == 1 ? 10 : 0;
     const uint32_t dmask = pass == 1 ? 2047u : 1023u;
     const uint32_t want = prefix >> hshift;
-    for (size_t e = (size_t)blk * 256 + threadIdx.x; e < n; e += (size_t)nblk * 256) {
-        const uint32_t k = keys[e];
-        if ((k >> hshift) == want) hist_add(h, (k >> dshift) & dmask);
+    const size_t stride = (size_t)nblk * 256;
+    for (size_t e0 = (size_t)blk * 256 + threadIdx.x; e0 < n; e0 += kSelGroup * stride) {
+        uint32_t k[kSelGroup];
+#pragma unroll
+        for (int g = 0; g < kSelGroup; ++g) k[g] = keys[min(e0 + g * stride, n - 1)];
+#pragma unroll
+        for (int g = 0; g < kSelGroup; ++g)
+            if (e0 + g * stride < n && (k[g] >> hshift) == want) hist_add(h, (k[g] >> dshift) & dmask);
     }
     __syncthreads();
     for (int b = threadIdx.x; b < kSelectBins; b += 256)
@@ -456,11 +466,7 @@ __device__ __forceinline__ void select_finalize_block(DevState* st, int pass, ui
 // block), so the digit needs no kernel of its own; block 0 records the
 // prefix and rank after it for the next pass (in entries no block of this
 // launch reads).  hist: the three passes' histograms.
-// The keys a thread takes in a grid-stride walk are loaded kSelGroup at a
-// time, unconditionally (past the end: the last key, not counted), so that
-// they are all in flight together; the first group is loaded before the
-// block closes the previous digit.
-constexpr int kSelGroup = 8;
+// (the first group of keys is loaded before the block closes the previous digit)
 
 __global__ __launch_bounds__(256) void k_select_pass(const uint32_t* __restrict__ keys, size_t n, int pass,
                                                      DevState* st, uint32_t* hist)
